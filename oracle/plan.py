@@ -1,0 +1,165 @@
+"""Oracle plan rule for Ozaki scheme II (test infrastructure, not the product).
+
+This module is part of the CPU oracle.  Only ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py`` may import it.
+
+It restates, in plain Python, how the paper chooses the slice count S, the slice
+width w, the fixed-point width Q = w*S and the number of moduli N_mod
+(Sec. 3.2, paragraph "Determining w and N"; slack from the paragraph after
+Prop. 2), and the CRT constants of Eq. (crt): P = prod m_l, M_l = P/m_l,
+y_l = M_l^{-1} mod m_l.
+
+Readings taken where the paper is terse (each is listed in the design doc):
+  * modulus set: the 54 largest prime powers not exceeding 256, in descending
+    order (Sec. 3.2 says 54 moduli and 362.8 bits; only the set containing 256
+    gives both, and it reproduces every printed GEMM/moduli count);
+  * ``need`` uses real-valued log2 and the first prefix whose cumulative log2
+    is strictly larger than ``need``;
+  * S is the smallest slice count for which ``need`` fits the capacity and the
+    accumulator bound holds (INT8: K*S*128^2 < 2^31, residues lie in
+    [-128, 127]); FP8 base-17 additionally needs K*S*64 < 2^24 per sub-GEMM;
+  * the binary64-moduli back-end uses the largest primes m with
+    K*S*(m/2)^2 < 2^53, so every digit group accumulates exactly in one FP64
+    GEMM.  The paper prints counts for this back-end that do not follow one
+    rule, so this set is "parity unpinned" against the paper (self-consistent
+    only).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+BACKEND_INT8 = 1
+BACKEND_FP8_B17 = 2
+BACKEND_F64MOD = 3
+
+
+def _is_prime(n: int) -> bool:
+    if n < 2:
+        return False
+    i = 2
+    while i * i <= n:
+        if n % i == 0:
+            return False
+        i += 1
+    return True
+
+
+def int8_moduli() -> List[int]:
+    """Largest power of every prime not exceeding 256, descending (Sec. 3.2)."""
+    out = []
+    for p in range(2, 257):
+        if _is_prime(p):
+            q = p
+            while q * p <= 256:
+                q *= p
+            out.append(q)
+    return sorted(out, reverse=True)
+
+
+def f64_moduli(K: int, S: int, count: int = 64) -> List[int]:
+    """Largest primes m with K*S*(m/2)^2 < 2^53 (Eq. fp64mod with the inner
+    dimension of one digit-group GEMM, K*npairs <= K*S), descending."""
+    lim = math.isqrt((1 << 55) // (K * S)) + 2
+    out = []
+    m = lim
+    while len(out) < count and m > 2:
+        if K * S * m * m < (1 << 55) and _is_prime(m):
+            out.append(m)
+        m -= 1
+    return out
+
+
+@dataclass
+class Plan:
+    p: int
+    K: int
+    backend: int
+    S: int
+    w: int
+    Q: int
+    nmod: int
+    moduli: List[int]
+    extra_groups: int = 0
+    guard_ex: int = 0
+    need: float = 0.0
+    P: int = 0
+    M: List[int] = field(default_factory=list)
+    y: List[int] = field(default_factory=list)
+
+    @property
+    def g0(self) -> int:
+        """Lowest retained digit group (Sec. 3.2: groups S-1..2S-2, widened by
+        the extra-groups option)."""
+        return max(0, self.S - 1 - self.extra_groups)
+
+    @property
+    def groups(self) -> List[int]:
+        return list(range(self.g0, 2 * self.S - 1))
+
+    def pairs(self, g: int):
+        return [(ta, g - ta) for ta in range(self.S) if 0 <= g - ta < self.S]
+
+    @property
+    def gemm_count(self) -> int:
+        """Eq. (gemmcount) generalised to the retained groups: one GEMM per
+        slice pair and modulus."""
+        return sum(len(self.pairs(g)) for g in self.groups) * self.nmod
+
+
+def _accum_ok(backend: int, K: int, S: int) -> bool:
+    if backend == BACKEND_INT8:
+        return K * S * 128 * 128 < (1 << 31)
+    if backend == BACKEND_FP8_B17:
+        return K * S * 128 * 128 < (1 << 31) and K * S * 64 < (1 << 24)
+    return True
+
+
+def make_plan(p: int, K: int, backend: int = BACKEND_INT8, nslice: int = 0,
+              extra_groups: int = 0, guard_ex: int = 0) -> Plan:
+    """Plan rule of Sec. 3.2 ("Determining w and N").
+
+    slack = ceil(log2 2K) + 16 + g_ex;  for S = 1, 2, ...:
+    w = ceil((p + slack)/S), need = 2w + log2 K + log2 S + 5, N = fewest
+    leading moduli whose cumulative log2 exceeds need; accept the first S that
+    fits the capacity and the accumulator bound.  ``nslice`` forces S.
+    Raises ValueError when no S fits (or the forced one does not).
+    """
+    if p <= 0 or K <= 0:
+        raise ValueError("p and K must be positive")
+    slack = math.ceil(math.log2(2 * K)) + 16 + guard_ex
+    s_range = [nslice] if nslice > 0 else range(1, 4097)
+    for S in s_range:
+        if not _accum_ok(backend, K, S):
+            continue
+        mods = f64_moduli(K, S) if backend == BACKEND_F64MOD else int8_moduli()
+        w = -(-(p + slack) // S)
+        need = 2 * w + math.log2(K) + math.log2(S) + 5
+        cum = 0.0
+        N = None
+        for i, m in enumerate(mods, 1):
+            cum += math.log2(m)
+            if cum > need:
+                N = i
+                break
+        if N is None:
+            continue
+        used = mods[:N]
+        P = 1
+        for m in used:
+            P *= m
+        M = [P // m for m in used]
+        y = [pow(Mi % m, -1, m) for Mi, m in zip(M, used)]
+        return Plan(p=p, K=K, backend=backend, S=S, w=w, Q=w * S, nmod=N,
+                    moduli=used, extra_groups=extra_groups, guard_ex=guard_ex,
+                    need=need, P=P, M=M, y=y)
+    raise ValueError(f"no slice count fits p={p} K={K} backend={backend} nslice={nslice}")
+
+
+def lhint(r: float, t: int, M: int, N: int) -> int:
+    """Eq. (Lhint): S* = sqrt(r n_d (M+N)/(MN)), n_d = ceil(t/16), rounded to
+    nearest (the paper's ceiling disagrees with its own Table phase; reading
+    documented)."""
+    nd = -(-t // 16)
+    return max(1, int(math.floor(math.sqrt(r * nd * (M + N) / (M * N)) + 0.5)))
