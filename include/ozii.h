@@ -1,0 +1,135 @@
+/*
+ * ozii -- Ozaki-scheme-II multiple-precision LU for AMD MI355X (gfx950).
+ *
+ * C ABI of the library libozii.so.  Every matrix is column-major and every
+ * element is a non-overlapping expansion of nc binary64 components (nc = 2:
+ * double-double, 3: triple-double, 4: quad-double; Sec. 2 of Kouya,
+ * "Accelerating Multiple-Precision LU Decomposition with Ozaki Scheme II"):
+ * component c of element (i, j) of a matrix X with leading dimension ld sits
+ * at X[(i + j*ld)*nc + c].  All matrix, pivot and info pointers are DEVICE
+ * pointers owned by the caller; the library never frees caller memory.  The
+ * handle owns its plan tables and workspace.
+ *
+ * Asynchrony: every call is enqueued on the handle's HIP stream and returns
+ * without waiting.  Host-detectable problems (bad sizes, null pointers, plans
+ * that do not fit) are reported synchronously before anything is enqueued.
+ * Data-dependent conditions (an exactly zero pivot) are reported through the
+ * device `info` word, LAPACK style.
+ *
+ * Threads: one handle per host thread.
+ */
+#ifndef OZII_H
+#define OZII_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  OZII_OK = 0,
+  OZII_EINVAL = 1,       /* bad argument (size, pointer, leading dimension) */
+  OZII_ECAPACITY = 2,    /* the requested plan exceeds the CRT capacity      */
+  OZII_EOVERFLOW = 3,    /* a forced plan breaks an accumulator bound        */
+  OZII_ENOMEM = 4,       /* workspace allocation failed                      */
+  OZII_EHIP = 5,         /* a HIP runtime call failed                        */
+  OZII_EUNSUPPORTED = 6, /* format or option not built into this library     */
+  OZII_EDEVICE = 7       /* a kernel reported an internal error (see text)   */
+} ozII_status;
+
+typedef enum {
+  OZII_BE_AUTO = 0,
+  OZII_BE_INT8 = 1,      /* int8 residues, exact int32 MFMA accumulation      */
+  OZII_BE_FP8_B17 = 2,   /* balanced base-17 digits in FP8 E4M3, FP32 accum.  */
+  OZII_BE_F64MOD = 3     /* binary64 residues of ~23-bit primes, FP64 MFMA    */
+} ozII_backend;
+
+typedef enum {
+  OZII_METHOD_OZAKI = 0, /* Schur update by the Ozaki-II product              */
+  OZII_METHOD_NAIVE = 1  /* Schur update by expansion multiply-subtracts       */
+} ozII_method;
+
+/* Options.  A null pointer means all defaults (zero). */
+typedef struct {
+  int32_t backend;      /* ozII_backend                                        */
+  int32_t nslice;       /* force the slice count S; 0 = plan rule (Sec. 3.2)   */
+  int32_t extra_groups; /* keep this many digit groups below S-1 (Sec. 3.2)    */
+  int32_t guard_ex;     /* extra guard bits g_ex added to the slack (Sec. 3.2) */
+  int32_t block;        /* getrf panel width b; 0 = 256                        */
+  int32_t method;       /* getrf Schur update: ozII_method                     */
+  int32_t flags;        /* reserved, must be 0                                 */
+} ozII_opts;
+
+typedef struct ozII_ctx *ozII_handle;
+
+/* Create a handle on HIP device `device`, enqueueing on `stream` (a
+ * hipStream_t; null = the default stream). */
+ozII_status ozII_create(ozII_handle *h, int device, void *stream);
+ozII_status ozII_destroy(ozII_handle h);
+ozII_status ozII_set_stream(ozII_handle h, void *stream);
+
+/* Plan of Sec. 3.2 ("Determining w and N") for precision p bits and inner
+ * dimension K: slice count S, slice width w, fixed-point width Q = w S,
+ * number of moduli nmod and the moduli themselves (up to 64 entries written).
+ * Host only; returns OZII_ECAPACITY when no slice count fits. */
+ozII_status ozII_plan_query(int32_t p, int64_t K, const ozII_opts *o, int32_t *S, int32_t *w,
+                            int32_t *Q, int32_t *nmod, int32_t *moduli);
+
+/* Grow the workspace so that products up to M x N x K and LUs up to order n
+ * (panel width b) run without allocation (needed before graph capture). */
+ozII_status ozII_reserve(ozII_handle h, int32_t nc, int64_t M, int64_t N, int64_t K, int64_t n,
+                         const ozII_opts *o);
+
+/* Ozaki-II product, steps (S1)-(S6) of Sec. 3.1 with the slices of Sec. 3.2:
+ *   mode 0: C = A B,   mode 1: C = C - A B,
+ * A is M x K (lda >= M), B is K x N (ldb >= K), C is M x N (ldc >= M).  The
+ * product is rounded once (greedy round-to-nearest expansion of the exact
+ * integer result); mode 1 then subtracts with expansion addition. */
+ozII_status ozII_gemm(ozII_handle h, int32_t mode, int32_t nc, int64_t M, int64_t N, int64_t K,
+                      const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
+                      int64_t ldc, const ozII_opts *o);
+
+/* Same product with the intermediate stages copied out (parity hooks); any
+ * output pointer may be null.  Sizes follow ozII_gemm_stage_dims:
+ *   ea[M], eb[N]     (S1) row / column exponents (INT32_MIN for zero);
+ *   planesA          (S3) int8 residues, S*nmod planes of Mp x Kp in
+ *                    fragment order, planesB likewise Np x Kp;
+ *   tpl              (S4) uint8 t-planes [ng][nmod][Np][Mp];
+ *   sbar             (S5) group sums, nlimb 64-bit two's-complement limbs per
+ *                    element, layout [ng][N][M][nlimb]. */
+ozII_status ozII_gemm_stages(ozII_handle h, int32_t mode, int32_t nc, int64_t M, int64_t N,
+                             int64_t K, const double *A, int64_t lda, const double *B,
+                             int64_t ldb, double *C, int64_t ldc, const ozII_opts *o,
+                             int32_t *ea, int32_t *eb, int8_t *planesA, int8_t *planesB,
+                             uint8_t *tpl, uint64_t *sbar, int32_t nlimb);
+ozII_status ozII_gemm_stage_dims(int32_t nc, int64_t M, int64_t N, int64_t K, const ozII_opts *o,
+                                 int64_t *Mp, int64_t *Np, int64_t *Kp, int32_t *S,
+                                 int32_t *nmod, int32_t *ng);
+
+/* Blocked right-looking LU with partial pivoting (Sec. 3.4), in place on the
+ * n x n matrix A.  ipiv[j] (0-based, device int64) = row interchanged with row
+ * j (LAPACK semantics); *info (device int32) = first j+1 with an exactly zero
+ * pivot, else 0.  o->method selects the Schur update (Ozaki-II or native). */
+ozII_status ozII_getrf(ozII_handle h, int32_t nc, int64_t n, double *A, int64_t lda,
+                       int64_t *ipiv, int32_t *info, const ozII_opts *o);
+
+/* Solve A X = B from getrf's factors: interchanges in ipiv order, forward
+ * substitution with unit L (ascending order per element), backward
+ * substitution with U (descending order, then division by u_ii).  B is
+ * n x nrhs (ldb >= n), overwritten by X. */
+ozII_status ozII_getrs(ozII_handle h, int32_t nc, int64_t n, int64_t nrhs, const double *LU,
+                       int64_t lda, const int64_t *ipiv, double *B, int64_t ldb);
+
+/* Wait for the handle's stream and report a device-side error flag raised by
+ * a kernel (a grid barrier that did not complete). */
+ozII_status ozII_sync_check(ozII_handle h);
+
+const char *ozII_status_string(ozII_status s);
+const char *ozII_last_error(ozII_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OZII_H */

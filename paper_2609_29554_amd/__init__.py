@@ -1,0 +1,236 @@
+"""Python binding of libozii (Ozaki-scheme-II multiple-precision LU on gfx950).
+
+Argument marshalling only: every step runs in the HIP kernels of libozii.so.
+PyTorch supplies device memory and the stream.  There is no CPU fallback: if
+the library is not built, importing works but every call raises.
+
+Matrices are float64 CUDA tensors of shape (cols, rows, nc), contiguous: the
+column-major array of nc-component expansions that the C ABI expects
+(element (i, j) component c at flat index (i + j*rows)*nc + c).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Tuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libozii.so")
+
+OK, EINVAL, ECAPACITY, EOVERFLOW, ENOMEM, EHIP, EUNSUPPORTED, EDEVICE = range(8)
+BE_AUTO, BE_INT8, BE_FP8_B17, BE_F64MOD = range(4)
+METHOD_OZAKI, METHOD_NAIVE = 0, 1
+
+
+class OziiError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"ozii status {status}: {msg}")
+        self.status = status
+
+
+class Opts(C.Structure):
+    _fields_ = [("backend", C.c_int32), ("nslice", C.c_int32), ("extra_groups", C.c_int32),
+                ("guard_ex", C.c_int32), ("block", C.c_int32), ("method", C.c_int32),
+                ("flags", C.c_int32)]
+
+
+_lib = None
+_p = C.c_void_p
+_i64 = C.c_int64
+_i32 = C.c_int32
+
+EXPORTED = ["ozII_create", "ozII_destroy", "ozII_set_stream", "ozII_plan_query", "ozII_reserve",
+            "ozII_gemm", "ozII_gemm_stages", "ozII_gemm_stage_dims", "ozII_getrf", "ozII_getrs",
+            "ozII_sync_check", "ozII_status_string", "ozII_last_error"]
+
+
+def lib():
+    """Load libozii.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        OP = C.POINTER(Opts)
+        L.ozII_create.argtypes = [C.POINTER(_p), C.c_int, _p]
+        L.ozII_destroy.argtypes = [_p]
+        L.ozII_set_stream.argtypes = [_p, _p]
+        L.ozII_plan_query.argtypes = [_i32, _i64, OP, C.POINTER(_i32), C.POINTER(_i32),
+                                      C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]
+        L.ozII_reserve.argtypes = [_p, _i32, _i64, _i64, _i64, _i64, OP]
+        L.ozII_gemm.argtypes = [_p, _i32, _i32, _i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, OP]
+        L.ozII_gemm_stages.argtypes = [_p, _i32, _i32, _i64, _i64, _i64, _p, _i64, _p, _i64, _p,
+                                       _i64, OP, _p, _p, _p, _p, _p, _p, _i32]
+        L.ozII_gemm_stage_dims.argtypes = [_i32, _i64, _i64, _i64, OP, C.POINTER(_i64),
+                                           C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i32),
+                                           C.POINTER(_i32), C.POINTER(_i32)]
+        L.ozII_getrf.argtypes = [_p, _i32, _i64, _p, _i64, _p, _p, OP]
+        L.ozII_getrs.argtypes = [_p, _i32, _i64, _i64, _p, _i64, _p, _p, _i64]
+        L.ozII_sync_check.argtypes = [_p]
+        L.ozII_status_string.argtypes = [C.c_int]
+        L.ozII_status_string.restype = C.c_char_p
+        L.ozII_last_error.argtypes = [_p]
+        L.ozII_last_error.restype = C.c_char_p
+        for name in EXPORTED:
+            if name not in ("ozII_status_string", "ozII_last_error"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def make_opts(backend: int = 0, nslice: int = 0, extra_groups: int = 0, guard_ex: int = 0,
+              block: int = 0, method: int = 0) -> Opts:
+    return Opts(backend, nslice, extra_groups, guard_ex, block, method, 0)
+
+
+def plan_query(p: int, K: int, opts: Optional[Opts] = None):
+    """Plan of Sec. 3.2 as the library computes it: (S, w, Q, nmod, moduli)."""
+    S, w, Q, n = _i32(), _i32(), _i32(), _i32()
+    mods = (_i32 * 64)()
+    st = lib().ozII_plan_query(p, K, C.byref(opts) if opts else None, C.byref(S), C.byref(w),
+                               C.byref(Q), C.byref(n), mods)
+    if st != OK:
+        raise OziiError(st, lib().ozII_status_string(st).decode())
+    return S.value, w.value, Q.value, n.value, list(mods[: n.value])
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def _check_mat(t, nc: Optional[int] = None):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.dim() == 3):
+        raise ValueError("expected a contiguous float64 CUDA tensor of shape (cols, rows, nc)")
+    if nc is not None and t.shape[2] != nc:
+        raise ValueError("component count mismatch")
+
+
+class Context:
+    """A libozii handle bound to one device and (by default) torch's current
+    stream on it."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.device = device
+        torch.cuda.set_device(device)
+        self._h = _p()
+        st = lib().ozII_create(C.byref(self._h), device, self._stream())
+        if st != OK:
+            raise OziiError(st, "ozII_create failed")
+
+    @staticmethod
+    def _stream():
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def _call(self, st: int):
+        if st != OK:
+            msg = lib().ozII_last_error(self._h).decode()
+            raise OziiError(st, f"{lib().ozII_status_string(st).decode()}: {msg}")
+
+    def _bind(self):
+        lib().ozII_set_stream(self._h, self._stream())
+
+    def close(self):
+        if self._h:
+            lib().ozII_destroy(self._h)
+            self._h = _p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reserve(self, nc: int, M: int, N: int, K: int, n: int = 0, opts: Optional[Opts] = None):
+        self._call(lib().ozII_reserve(self._h, nc, M, N, K, n, C.byref(opts) if opts else None))
+
+    def gemm(self, mode: int, A, B, Cm, opts: Optional[Opts] = None):
+        """mode 0: C = A B; mode 1: C = C - A B.  A: (K, M, nc), B: (N, K, nc),
+        C: (N, M, nc)."""
+        nc = A.shape[2]
+        for t in (A, B, Cm):
+            _check_mat(t, nc)
+        K, M = A.shape[0], A.shape[1]
+        N = B.shape[0]
+        if B.shape[1] != K or Cm.shape[0] != N or Cm.shape[1] != M:
+            raise ValueError("shape mismatch")
+        self._bind()
+        self._call(lib().ozII_gemm(self._h, mode, nc, M, N, K, _ptr(A), max(M, 1), _ptr(B),
+                                   max(K, 1), _ptr(Cm), max(M, 1), C.byref(opts) if opts else None))
+        return Cm
+
+    def gemm_stages(self, mode: int, A, B, Cm, opts: Optional[Opts] = None, nlimb: int = 6):
+        """Product with every intermediate stage returned (parity hooks):
+        dict(ea, eb, planesA, planesB, tpl, sbar, dims)."""
+        import torch
+        nc = A.shape[2]
+        K, M = A.shape[0], A.shape[1]
+        N = B.shape[0]
+        Mp, Np, Kp = _i64(), _i64(), _i64()
+        S, nmod, ng = _i32(), _i32(), _i32()
+        st = lib().ozII_gemm_stage_dims(nc, M, N, K, C.byref(opts) if opts else None,
+                                        C.byref(Mp), C.byref(Np), C.byref(Kp), C.byref(S),
+                                        C.byref(nmod), C.byref(ng))
+        if st != OK:
+            raise OziiError(st, "stage dims")
+        dev = A.device
+        ea = torch.empty(M, dtype=torch.int32, device=dev)
+        eb = torch.empty(N, dtype=torch.int32, device=dev)
+        pa = torch.empty(S.value * nmod.value * Mp.value * Kp.value, dtype=torch.int8, device=dev)
+        pb = torch.empty(S.value * nmod.value * Np.value * Kp.value, dtype=torch.int8, device=dev)
+        tpl = torch.empty(ng.value * nmod.value * Np.value * Mp.value, dtype=torch.uint8, device=dev)
+        sbar = torch.empty(ng.value * N * M * nlimb, dtype=torch.int64, device=dev)
+        self._bind()
+        self._call(lib().ozII_gemm_stages(self._h, mode, nc, M, N, K, _ptr(A), M, _ptr(B), K,
+                                          _ptr(Cm), M, C.byref(opts) if opts else None, _ptr(ea),
+                                          _ptr(eb), _ptr(pa), _ptr(pb), _ptr(tpl), _ptr(sbar),
+                                          nlimb))
+        dims = dict(Mp=Mp.value, Np=Np.value, Kp=Kp.value, S=S.value, nmod=nmod.value,
+                    ng=ng.value, M=M, N=N, K=K)
+        return dict(ea=ea, eb=eb, planesA=pa, planesB=pb, tpl=tpl, sbar=sbar, dims=dims)
+
+    def getrf(self, A, block: int = 256, method: int = METHOD_OZAKI, opts: Optional[Opts] = None):
+        """In-place LU of the n x n matrix A (shape (n, n, nc)); returns
+        (ipiv int64[n] 0-based LAPACK semantics, info int32[1]) on the device."""
+        import torch
+        _check_mat(A)
+        n, nc = A.shape[0], A.shape[2]
+        if A.shape[1] != n:
+            raise ValueError("A must be square")
+        o = opts if opts is not None else Opts()
+        o.block = block
+        o.method = method
+        ipiv = torch.empty(max(n, 1), dtype=torch.int64, device=A.device)
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+        self._bind()
+        self._call(lib().ozII_getrf(self._h, nc, n, _ptr(A), max(n, 1), _ptr(ipiv), _ptr(info),
+                                    C.byref(o)))
+        return ipiv, info
+
+    def getrs(self, LU, ipiv, B):
+        """Solve in place: B (shape (nrhs, n, nc)) <- A^{-1} B."""
+        _check_mat(LU)
+        _check_mat(B, LU.shape[2])
+        n, nc = LU.shape[0], LU.shape[2]
+        nrhs = B.shape[0]
+        if B.shape[1] != n:
+            raise ValueError("shape mismatch")
+        self._bind()
+        self._call(lib().ozII_getrs(self._h, nc, n, nrhs, _ptr(LU), max(n, 1), _ptr(ipiv),
+                                    _ptr(B), max(n, 1)))
+        return B
+
+    def sync_check(self):
+        self._call(lib().ozII_sync_check(self._h))
+
+
+def unfragment(planes, n_planes: int, noutp: int, Kp: int):
+    """Residue planes from fragment order to [plane][row][k] (numpy, for
+    tests): block (ob, kb) = 1024 bytes, lane l holds row l%16 and inner
+    indices 16*(l/16)..+15."""
+    import numpy as np
+    a = np.asarray(planes).reshape(n_planes, noutp // 16, Kp // 64, 4, 16, 16)
+    # axes: plane, ob, kb, kgroup, row, byte -> plane, ob, row, kb, kgroup, byte
+    return a.transpose(0, 1, 4, 2, 3, 5).reshape(n_planes, noutp, Kp)

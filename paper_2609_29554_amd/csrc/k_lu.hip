@@ -1,0 +1,682 @@
+// LU kernels for gfx950 around the Ozaki-II update (Sec. 3.4 of the paper):
+//   (P1) panel factorisation with partial pivoting,
+//   (P2) row interchanges (laswp),
+//   (P3) U12 = L11^{-1} A12,
+//   the native expansion product C -= A B (blocked-naive comparator and the
+//   triangular-solve updates), and the pieces of the solve (getrs).
+// All multiple-precision arithmetic here is the expansion arithmetic of
+// expansion.hpp; every element sees its multiply-subtracts in the order the
+// specification fixes (ascending inner index, descending in the backward
+// substitution).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "expansion.hpp"
+#include "ozii_kernels.hpp"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Grid-wide barrier for the cooperative panel kernel.  Every workgroup is
+// co-resident (cooperative launch); the wait is still bounded so that a
+// broken invariant ends in an error flag, never in a hang.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void grid_barrier(uint32_t *bar, uint32_t nblocks, int *err) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t *count = bar, *gen = bar + 1;
+    const uint32_t g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t arrived =
+        __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      // bounded wait; once any barrier has timed out every later one returns
+      // at once, so a broken invariant costs one timeout, not one per column
+      uint64_t spins = 0;
+      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > (1ull << 24)) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// ---------------------------------------------------------------------------
+// (P1) panel.  Panel rows [k, n), columns [k, k+kb).  Workgroup w owns the
+// physical rows k + w*R .. k + w*R + R - 1 and keeps them in LDS for the
+// whole panel.  Rows are never moved during the panel: the row permutation
+// is tracked in LDS (position -> physical row and back, every workgroup
+// keeping an identical copy) and applied once afterwards.  Per column:
+//   1. every workgroup publishes its best candidate (key, position, row data)
+//      in a double-buffered table; grid barrier;
+//   2. every workgroup reduces the table identically (largest |value|, ties
+//      to the lowest position, i.e. LAPACK's i?amax on the permuted column);
+//   3. owners of active rows divide by the pivot and apply the rank-1 update
+//      to the rest of the panel row; the next column's candidate is formed.
+// ---------------------------------------------------------------------------
+template <int NC>
+__global__ __launch_bounds__(256) void k_panel(double *A, int64_t lda, int64_t n, int64_t k,
+                                               int kb, int R, int64_t *ipiv, int32_t *info,
+                                               uint32_t *bar, int *err, double *ckey, int *cpos,
+                                               int *cphys, double *crow, int *perm_out,
+                                               int *moved, int *nmoved) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  const int nr = (int)(n - k);
+  const int G = gridDim.x, wg = blockIdx.x, tid = threadIdx.x;
+  double *rows = (double *)smem_raw;                 // R * kb * NC
+  double *piv = rows + (size_t)R * kb * NC;          // kb * NC
+  int *sperm = (int *)(piv + (size_t)kb * NC);       // nr
+  int *sinv = sperm + nr;                            // nr
+  __shared__ double rkey[256][NC];
+  __shared__ int rpos[256], ridx[256];
+  __shared__ uint32_t active;
+  __shared__ int s_info, s_wi, s_ppos, s_pphys, s_zero;
+
+  const int r0 = wg * R;
+  const int cnt = r0 < nr ? (nr - r0 < R ? nr - r0 : R) : 0;
+
+  for (int idx = tid; idx < cnt * kb; idx += 256) {
+    const int r = idx % cnt, c = idx / cnt;
+    const double *src = A + ((k + r0 + r) + (k + c) * lda) * NC;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) rows[((size_t)r * kb + c) * NC + q] = src[q];
+  }
+  for (int p = tid; p < nr; p += 256) {
+    sperm[p] = p;
+    sinv[p] = p;
+  }
+  if (tid == 0) {
+    active = cnt >= 32 ? 0xffffffffu : ((1u << cnt) - 1u);
+    s_info = 0;
+  }
+  __syncthreads();
+
+  // publish the local candidate for column c into buffer buf
+  auto publish = [&](int c, int buf) {
+    if (tid == 0) {
+      int best = -1;
+      double bk[NC];
+      for (int r = 0; r < cnt; ++r) {
+        if (!((active >> r) & 1u)) continue;
+        double x[NC];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) x[q] = rows[((size_t)r * kb + c) * NC + q];
+        bool take = best < 0;
+        if (!take) {
+          if (ozx::abs_greater<NC>(x, bk)) take = true;
+          else if (!ozx::abs_greater<NC>(bk, x) && sinv[r0 + r] < sinv[r0 + best]) take = true;
+        }
+        if (take) {
+          best = r;
+#pragma unroll
+          for (int q = 0; q < NC; ++q) bk[q] = x[q];
+        }
+      }
+      if (best >= 0) {
+#pragma unroll
+        for (int q = 0; q < NC; ++q) ckey[((size_t)buf * G + wg) * NC + q] = bk[q];
+        cpos[buf * G + wg] = sinv[r0 + best];
+        cphys[buf * G + wg] = r0 + best;
+      } else {
+        cphys[buf * G + wg] = -1;
+        cpos[buf * G + wg] = 0x7fffffff;
+      }
+      ridx[0] = best;
+    }
+    __syncthreads();
+    const int best = ridx[0];
+    if (best >= 0) {
+      for (int idx = tid; idx < (kb - c) * NC; idx += 256)
+        crow[((size_t)buf * G + wg) * kb * NC + (size_t)c * NC + idx] =
+            rows[((size_t)best * kb + c) * NC + idx];
+    }
+    __syncthreads();
+  };
+
+  publish(0, 0);
+
+  for (int j = 0; j < kb; ++j) {
+    const int buf = j & 1;
+    grid_barrier(bar, (uint32_t)G, err);
+    // reduce the candidate table (identically in every workgroup)
+    {
+      int gi = tid;
+      if (gi < G && cphys[buf * G + gi] >= 0) {
+#pragma unroll
+        for (int q = 0; q < NC; ++q) rkey[tid][q] = ckey[((size_t)buf * G + gi) * NC + q];
+        rpos[tid] = cpos[buf * G + gi];
+        ridx[tid] = gi;
+      } else {
+#pragma unroll
+        for (int q = 0; q < NC; ++q) rkey[tid][q] = 0.0;
+        rpos[tid] = 0x7fffffff;
+        ridx[tid] = -1;
+      }
+      __syncthreads();
+      for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+          const int a = tid, b = tid + s;
+          bool takeb = false;
+          if (ridx[b] >= 0) {
+            if (ridx[a] < 0) takeb = true;
+            else {
+              double ka[NC], kbv[NC];
+#pragma unroll
+              for (int q = 0; q < NC; ++q) {
+                ka[q] = rkey[a][q];
+                kbv[q] = rkey[b][q];
+              }
+              if (ozx::abs_greater<NC>(kbv, ka)) takeb = true;
+              else if (!ozx::abs_greater<NC>(ka, kbv) && rpos[b] < rpos[a]) takeb = true;
+            }
+          }
+          if (takeb) {
+#pragma unroll
+            for (int q = 0; q < NC; ++q) rkey[a][q] = rkey[b][q];
+            rpos[a] = rpos[b];
+            ridx[a] = ridx[b];
+          }
+        }
+        __syncthreads();
+      }
+      if (tid == 0) {
+        const int wi = ridx[0];
+        s_wi = wi;
+        s_ppos = rpos[0];
+        s_pphys = cphys[buf * G + wi];
+        bool z = true;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) z = z && (rkey[0][q] == 0.0);
+        s_zero = z ? 1 : 0;
+      }
+      __syncthreads();
+    }
+    const int wi = s_wi, ppos = s_ppos, pphys = s_pphys, zero = s_zero;
+    // pivot row (columns j .. kb-1) into LDS
+    for (int idx = tid; idx < (kb - j) * NC; idx += 256)
+      piv[(size_t)j * NC + idx] = crow[((size_t)buf * G + wi) * kb * NC + (size_t)j * NC + idx];
+    if (tid == 0) {
+      const int q = sperm[j];
+      sperm[j] = pphys;
+      sperm[ppos] = q;
+      sinv[pphys] = j;
+      sinv[q] = ppos;
+      if (pphys >= r0 && pphys < r0 + cnt) active &= ~(1u << (pphys - r0));
+      if (zero && s_info == 0) s_info = (int)(k + j + 1);
+      if (wg == 0) ipiv[k + j] = k + ppos;
+    }
+    __syncthreads();
+    if (!zero) {
+      const double *pv = piv + (size_t)j * NC;
+      for (int r = tid; r < cnt; r += 256) {
+        if ((active >> r) & 1u) {
+          double a[NC], d[NC], l[NC];
+          ozx::load<NC>(rows + ((size_t)r * kb + j) * NC, a);
+          ozx::load<NC>(pv, d);
+          ozx::div<NC>(a, d, l);
+          ozx::store<NC>(rows + ((size_t)r * kb + j) * NC, l);
+        }
+      }
+      __syncthreads();
+      const int width = kb - j - 1;
+      for (int idx = tid; idx < cnt * width; idx += 256) {
+        const int r = idx % cnt, c = j + 1 + idx / cnt;
+        if ((active >> r) & 1u) {
+          double a[NC], l[NC], u[NC], o[NC];
+          ozx::load<NC>(rows + ((size_t)r * kb + c) * NC, a);
+          ozx::load<NC>(rows + ((size_t)r * kb + j) * NC, l);
+          ozx::load<NC>(piv + (size_t)c * NC, u);
+          ozx::fms<NC>(a, l, u, o);
+          ozx::store<NC>(rows + ((size_t)r * kb + c) * NC, o);
+        }
+      }
+      __syncthreads();
+    }
+    if (j + 1 < kb) publish(j + 1, (j + 1) & 1);
+  }
+  // write the rows back to their physical places
+  for (int idx = tid; idx < cnt * kb; idx += 256) {
+    const int r = idx % cnt, c = idx / cnt;
+    double *dst = A + ((k + r0 + r) + (k + c) * lda) * NC;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) dst[q] = rows[((size_t)r * kb + c) * NC + q];
+  }
+  if (wg == 0) {
+    __shared__ int s_nm;
+    if (tid == 0) s_nm = 0;
+    __syncthreads();
+    for (int p = tid; p < nr; p += 256) {
+      perm_out[p] = sperm[p];
+      if (sperm[p] != p) {
+        const int slot = atomicAdd(&s_nm, 1);
+        moved[slot] = p;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      *nmoved = s_nm;
+      if (s_info != 0 && *info == 0) *info = s_info;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// (P2) apply the panel's row permutation to columns [c0, c1):
+// new row k+p = old row k+perm[p] for every moved position p.
+// ---------------------------------------------------------------------------
+template <int NC>
+__global__ __launch_bounds__(256) void k_laswp(double *A, int64_t lda, int64_t k, int64_t c0,
+                                               int64_t c1, const int *perm, const int *moved,
+                                               const int *nmoved) {
+  const int64_t c = c0 + blockIdx.x;
+  if (c >= c1) return;
+  const int nm = *nmoved;
+  constexpr int PER = 4;  // up to 1024 moved positions per column
+  double v[PER][NC];
+  int pos[PER];
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    const int e = threadIdx.x + 256 * t;
+    pos[t] = -1;
+    if (e < nm) {
+      const int p = moved[e];
+      pos[t] = p;
+      ozx::load<NC>(A + ((k + perm[p]) + c * lda) * NC, v[t]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < PER; ++t)
+    if (pos[t] >= 0) ozx::store<NC>(A + ((k + pos[t]) + c * lda) * NC, v[t]);
+}
+
+// ---------------------------------------------------------------------------
+// (P3) X <- L^{-1} X for a unit lower-triangular kb x kb block L (at Lp, ld
+// lda) and kb x ncols right-hand sides X (at Xp, ld ldx): element i is
+// updated for h = 0 .. i-1 in ascending order.  One workgroup per CPB
+// columns; thread t owns rows t, t+256, ...
+// ---------------------------------------------------------------------------
+template <int NC, int CPB, int RPT>
+__global__ __launch_bounds__(256) void k_trsm_lower_unit(const double *Lp, int64_t lda, double *Xp,
+                                                         int64_t ldx, int kb, int64_t ncols) {
+  __shared__ double xs[2][CPB][NC];
+  const int tid = threadIdx.x;
+  const int64_t cbase = (int64_t)blockIdx.x * CPB;
+  double x[RPT][CPB][NC];
+#pragma unroll
+  for (int rr = 0; rr < RPT; ++rr) {
+    const int i = tid + 256 * rr;
+#pragma unroll
+    for (int cc = 0; cc < CPB; ++cc) {
+      const int64_t c = cbase + cc;
+      if (i < kb && c < ncols) ozx::load<NC>(Xp + (i + c * ldx) * NC, x[rr][cc]);
+      else
+#pragma unroll
+        for (int q = 0; q < NC; ++q) x[rr][cc][q] = 0.0;
+    }
+  }
+  for (int h = 0; h < kb; ++h) {
+    const int b = h & 1;
+    if (tid == (h & 255)) {
+#pragma unroll
+      for (int rr = 0; rr < RPT; ++rr)
+        if (rr == h / 256)
+#pragma unroll
+          for (int cc = 0; cc < CPB; ++cc)
+#pragma unroll
+            for (int q = 0; q < NC; ++q) xs[b][cc][q] = x[rr][cc][q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < RPT; ++rr) {
+      const int i = tid + 256 * rr;
+      if (i > h && i < kb) {
+        double l[NC];
+        ozx::load<NC>(Lp + (i + (int64_t)h * lda) * NC, l);
+#pragma unroll
+        for (int cc = 0; cc < CPB; ++cc) {
+          double u[NC], o[NC];
+#pragma unroll
+          for (int q = 0; q < NC; ++q) u[q] = xs[b][cc][q];
+          ozx::fms<NC>(x[rr][cc], l, u, o);
+#pragma unroll
+          for (int q = 0; q < NC; ++q) x[rr][cc][q] = o[q];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int rr = 0; rr < RPT; ++rr) {
+    const int i = tid + 256 * rr;
+#pragma unroll
+    for (int cc = 0; cc < CPB; ++cc) {
+      const int64_t c = cbase + cc;
+      if (i < kb && c < ncols) ozx::store<NC>(Xp + (i + c * ldx) * NC, x[rr][cc]);
+    }
+  }
+}
+
+// X <- U^{-1} X for an upper-triangular kb x kb block: for h = kb-1 .. 0,
+// x_h <- x_h / u_hh, then x_i -= u_ih x_h for i < h (descending order).
+template <int NC, int CPB, int RPT>
+__global__ __launch_bounds__(256) void k_trsm_upper(const double *Up, int64_t lda, double *Xp,
+                                                    int64_t ldx, int kb, int64_t ncols) {
+  __shared__ double xs[2][CPB][NC];
+  const int tid = threadIdx.x;
+  const int64_t cbase = (int64_t)blockIdx.x * CPB;
+  double x[RPT][CPB][NC];
+#pragma unroll
+  for (int rr = 0; rr < RPT; ++rr) {
+    const int i = tid + 256 * rr;
+#pragma unroll
+    for (int cc = 0; cc < CPB; ++cc) {
+      const int64_t c = cbase + cc;
+      if (i < kb && c < ncols) ozx::load<NC>(Xp + (i + c * ldx) * NC, x[rr][cc]);
+      else
+#pragma unroll
+        for (int q = 0; q < NC; ++q) x[rr][cc][q] = 0.0;
+    }
+  }
+  for (int h = kb - 1; h >= 0; --h) {
+    const int b = h & 1;
+    if (tid == (h & 255)) {
+#pragma unroll
+      for (int rr = 0; rr < RPT; ++rr)
+        if (rr == h / 256) {
+          double d[NC];
+          ozx::load<NC>(Up + (h + (int64_t)h * lda) * NC, d);
+#pragma unroll
+          for (int cc = 0; cc < CPB; ++cc) {
+            double o[NC];
+            ozx::div<NC>(x[rr][cc], d, o);
+#pragma unroll
+            for (int q = 0; q < NC; ++q) {
+              x[rr][cc][q] = o[q];
+              xs[b][cc][q] = o[q];
+            }
+          }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < RPT; ++rr) {
+      const int i = tid + 256 * rr;
+      if (i < h) {
+        double u[NC];
+        ozx::load<NC>(Up + (i + (int64_t)h * lda) * NC, u);
+#pragma unroll
+        for (int cc = 0; cc < CPB; ++cc) {
+          double xh[NC], o[NC];
+#pragma unroll
+          for (int q = 0; q < NC; ++q) xh[q] = xs[b][cc][q];
+          ozx::fms<NC>(x[rr][cc], u, xh, o);
+#pragma unroll
+          for (int q = 0; q < NC; ++q) x[rr][cc][q] = o[q];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int rr = 0; rr < RPT; ++rr) {
+    const int i = tid + 256 * rr;
+#pragma unroll
+    for (int cc = 0; cc < CPB; ++cc) {
+      const int64_t c = cbase + cc;
+      if (i < kb && c < ncols) ozx::store<NC>(Xp + (i + c * ldx) * NC, x[rr][cc]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Native expansion product: C <- C - A B with one rounded multiply-subtract
+// per inner index, h ascending (desc = 0) or descending (desc = 1).
+// A is M x K (lda), B is K x N (ldb).  Tile TM x TN outputs per workgroup.
+// ---------------------------------------------------------------------------
+template <int NC, int TM, int TN>
+__global__ __launch_bounds__(256) void k_naive_gemm(const double *A, int64_t lda, const double *B,
+                                                    int64_t ldb, double *C, int64_t ldc, int64_t M,
+                                                    int64_t N, int64_t K, int desc) {
+  static_assert(TM * TN == 256, "tile");
+  constexpr int KC = TM >= 128 ? 4 : 16;
+  __shared__ double As[KC][TM][NC];
+  __shared__ double Bs[TN][KC][NC];
+  const int tid = threadIdx.x;
+  const int ti = tid % TM, tj = tid / TM;
+  const int64_t i = (int64_t)blockIdx.x * TM + ti, j = (int64_t)blockIdx.y * TN + tj;
+  double acc[NC];
+  const bool in = i < M && j < N;
+  if (in) ozx::load<NC>(C + (i + j * ldc) * NC, acc);
+  else
+#pragma unroll
+    for (int q = 0; q < NC; ++q) acc[q] = 0.0;
+  const int64_t nch = (K + KC - 1) / KC;
+  for (int64_t cc = 0; cc < nch; ++cc) {
+    const int64_t ch = desc ? nch - 1 - cc : cc;
+    const int64_t h0 = ch * KC;
+    for (int e = tid; e < KC * TM; e += 256) {
+      const int r = e % TM, hh = e / TM;
+      const int64_t gi = (int64_t)blockIdx.x * TM + r, gh = h0 + hh;
+#pragma unroll
+      for (int q = 0; q < NC; ++q)
+        As[hh][r][q] = (gi < M && gh < K) ? A[(gi + gh * lda) * NC + q] : 0.0;
+    }
+    for (int e = tid; e < KC * TN; e += 256) {
+      const int hh = e % KC, cj = e / KC;
+      const int64_t gj = (int64_t)blockIdx.y * TN + cj, gh = h0 + hh;
+#pragma unroll
+      for (int q = 0; q < NC; ++q)
+        Bs[cj][hh][q] = (gj < N && gh < K) ? B[(gh + gj * ldb) * NC + q] : 0.0;
+    }
+    __syncthreads();
+    if (in) {
+      const int hmax = (int)((K - h0) < KC ? (K - h0) : KC);
+      for (int t = 0; t < hmax; ++t) {
+        const int hh = desc ? hmax - 1 - t : t;
+        double a[NC], b[NC], o[NC];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+          a[q] = As[hh][ti][q];
+          b[q] = Bs[tj][hh][q];
+        }
+        ozx::fms<NC>(acc, a, b, o);
+#pragma unroll
+        for (int q = 0; q < NC; ++q) acc[q] = o[q];
+      }
+    }
+    __syncthreads();
+  }
+  if (in) ozx::store<NC>(C + (i + j * ldc) * NC, acc);
+}
+
+// getrs: apply the interchanges ipiv[0..n) in order to one column of B.
+template <int NC>
+__global__ __launch_bounds__(256) void k_apply_ipiv(double *B, int64_t ldb, int64_t n,
+                                                    const int64_t *ipiv, int use_lds) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  double *col = B + (int64_t)blockIdx.x * ldb * NC;
+  if (use_lds) {
+    double *s = (double *)smem_raw;
+    for (int64_t e = threadIdx.x; e < n * NC; e += 256) s[e] = col[e];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int64_t j = 0; j < n; ++j) {
+        const int64_t p = ipiv[j];
+        if (p != j) {
+#pragma unroll
+          for (int q = 0; q < NC; ++q) {
+            double t = s[j * NC + q];
+            s[j * NC + q] = s[p * NC + q];
+            s[p * NC + q] = t;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    for (int64_t e = threadIdx.x; e < n * NC; e += 256) col[e] = s[e];
+  } else if (threadIdx.x == 0) {
+    for (int64_t j = 0; j < n; ++j) {
+      const int64_t p = ipiv[j];
+      if (p != j) {
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+          double t = col[j * NC + q];
+          col[j * NC + q] = col[p * NC + q];
+          col[p * NC + q] = t;
+        }
+      }
+    }
+  }
+}
+
+__global__ void k_fill_int(int *p, int v, int64_t cnt) {
+  int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < cnt) p[e] = v;
+}
+
+}  // namespace
+
+namespace ozl {
+
+size_t panel_lds_bytes(int nc, int kb, int R, int64_t nr) {
+  return (size_t)R * kb * nc * 8 + (size_t)kb * nc * 8 + (size_t)nr * 8;
+}
+
+const void *panel_kernel_ptr(int nc) {
+  if (nc == 2) return (const void *)k_panel<2>;
+  if (nc == 3) return (const void *)k_panel<3>;
+  return (const void *)k_panel<4>;
+}
+
+hipError_t launch_panel(int nc, double *A, int64_t lda, int64_t n, int64_t k, int kb, int R, int G,
+                        int64_t *ipiv, int32_t *info, uint32_t *bar, int *err, double *ckey,
+                        int *cpos, int *cphys, double *crow, int *perm, int *moved, int *nmoved,
+                        hipStream_t s) {
+  const size_t lds = panel_lds_bytes(nc, kb, R, n - k);
+  const void *fn = panel_kernel_ptr(nc);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  void *args[] = {&A, &lda, &n, &k, &kb, &R, &ipiv, &info, &bar, &err,
+                  &ckey, &cpos, &cphys, &crow, &perm, &moved, &nmoved};
+  return hipLaunchCooperativeKernel(fn, dim3(G), dim3(256), args, (unsigned)lds, s);
+}
+
+hipError_t panel_max_blocks(int nc, int kb, int R, int64_t nr, int *maxblocks) {
+  const size_t lds = panel_lds_bytes(nc, kb, R, nr);
+  const void *fn = panel_kernel_ptr(nc);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int per = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, lds);
+  if (e != hipSuccess) return e;
+  int dev = 0, ncu = 0;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  *maxblocks = per * ncu;
+  return hipSuccess;
+}
+
+hipError_t launch_laswp(int nc, double *A, int64_t lda, int64_t k, int64_t c0, int64_t c1,
+                        const int *perm, const int *moved, const int *nmoved, hipStream_t s) {
+  if (c1 <= c0) return hipSuccess;
+  dim3 g((unsigned)(c1 - c0));
+  if (nc == 2) hipLaunchKernelGGL(k_laswp<2>, g, dim3(256), 0, s, A, lda, k, c0, c1, perm, moved, nmoved);
+  else if (nc == 3) hipLaunchKernelGGL(k_laswp<3>, g, dim3(256), 0, s, A, lda, k, c0, c1, perm, moved, nmoved);
+  else hipLaunchKernelGGL(k_laswp<4>, g, dim3(256), 0, s, A, lda, k, c0, c1, perm, moved, nmoved);
+  return hipGetLastError();
+}
+
+template <int NC>
+static void trsm_l(int kb, dim3 g, hipStream_t s, const double *L, int64_t lda, double *X,
+                   int64_t ldx, int64_t ncols) {
+  if (kb <= 256) hipLaunchKernelGGL((k_trsm_lower_unit<NC, 4, 1>), g, dim3(256), 0, s, L, lda, X, ldx, kb, ncols);
+  else hipLaunchKernelGGL((k_trsm_lower_unit<NC, 2, 2>), g, dim3(256), 0, s, L, lda, X, ldx, kb, ncols);
+}
+
+hipError_t launch_trsm_lower_unit(int nc, const double *L, int64_t lda, double *X, int64_t ldx,
+                                  int kb, int64_t ncols, hipStream_t s) {
+  if (ncols <= 0 || kb <= 0) return hipSuccess;
+  if (kb > 512) return hipErrorInvalidValue;
+  const int cpb = kb <= 256 ? 4 : 2;
+  dim3 g((unsigned)((ncols + cpb - 1) / cpb));
+  if (nc == 2) trsm_l<2>(kb, g, s, L, lda, X, ldx, ncols);
+  else if (nc == 3) trsm_l<3>(kb, g, s, L, lda, X, ldx, ncols);
+  else trsm_l<4>(kb, g, s, L, lda, X, ldx, ncols);
+  return hipGetLastError();
+}
+
+template <int NC>
+static void trsm_u(int kb, dim3 g, hipStream_t s, const double *U, int64_t lda, double *X,
+                   int64_t ldx, int64_t ncols) {
+  if (kb <= 256) hipLaunchKernelGGL((k_trsm_upper<NC, 4, 1>), g, dim3(256), 0, s, U, lda, X, ldx, kb, ncols);
+  else hipLaunchKernelGGL((k_trsm_upper<NC, 2, 2>), g, dim3(256), 0, s, U, lda, X, ldx, kb, ncols);
+}
+
+hipError_t launch_trsm_upper(int nc, const double *U, int64_t lda, double *X, int64_t ldx, int kb,
+                             int64_t ncols, hipStream_t s) {
+  if (ncols <= 0 || kb <= 0) return hipSuccess;
+  if (kb > 512) return hipErrorInvalidValue;
+  const int cpb = kb <= 256 ? 4 : 2;
+  dim3 g((unsigned)((ncols + cpb - 1) / cpb));
+  if (nc == 2) trsm_u<2>(kb, g, s, U, lda, X, ldx, ncols);
+  else if (nc == 3) trsm_u<3>(kb, g, s, U, lda, X, ldx, ncols);
+  else trsm_u<4>(kb, g, s, U, lda, X, ldx, ncols);
+  return hipGetLastError();
+}
+
+template <int NC>
+static void naive_nc(int64_t M, int64_t N, hipStream_t s, const double *A, int64_t lda,
+                     const double *B, int64_t ldb, double *C, int64_t ldc, int64_t K, int desc) {
+  if (N >= 16) {
+    dim3 g((unsigned)((M + 15) / 16), (unsigned)((N + 15) / 16));
+    hipLaunchKernelGGL((k_naive_gemm<NC, 16, 16>), g, dim3(256), 0, s, A, lda, B, ldb, C, ldc, M, N, K, desc);
+  } else {
+    dim3 g((unsigned)((M + 255) / 256), (unsigned)N);
+    hipLaunchKernelGGL((k_naive_gemm<NC, 256, 1>), g, dim3(256), 0, s, A, lda, B, ldb, C, ldc, M, N, K, desc);
+  }
+}
+
+hipError_t launch_naive_gemm(int nc, const double *A, int64_t lda, const double *B, int64_t ldb,
+                             double *C, int64_t ldc, int64_t M, int64_t N, int64_t K, int desc,
+                             hipStream_t s) {
+  if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+  if (nc == 2) naive_nc<2>(M, N, s, A, lda, B, ldb, C, ldc, K, desc);
+  else if (nc == 3) naive_nc<3>(M, N, s, A, lda, B, ldb, C, ldc, K, desc);
+  else naive_nc<4>(M, N, s, A, lda, B, ldb, C, ldc, K, desc);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_ipiv(int nc, double *B, int64_t ldb, int64_t n, int64_t nrhs,
+                             const int64_t *ipiv, hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return hipSuccess;
+  const size_t lds = (size_t)n * nc * 8;
+  const int use_lds = lds <= 160 * 1024 ? 1 : 0;
+  const void *fn = nc == 2 ? (const void *)k_apply_ipiv<2>
+                           : (nc == 3 ? (const void *)k_apply_ipiv<3> : (const void *)k_apply_ipiv<4>);
+  if (use_lds) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  dim3 g((unsigned)nrhs);
+  const unsigned shm = use_lds ? (unsigned)lds : 0u;
+  if (nc == 2) hipLaunchKernelGGL(k_apply_ipiv<2>, g, dim3(256), shm, s, B, ldb, n, ipiv, use_lds);
+  else if (nc == 3) hipLaunchKernelGGL(k_apply_ipiv<3>, g, dim3(256), shm, s, B, ldb, n, ipiv, use_lds);
+  else hipLaunchKernelGGL(k_apply_ipiv<4>, g, dim3(256), shm, s, B, ldb, n, ipiv, use_lds);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int *p, int v, int64_t cnt, hipStream_t s) {
+  if (cnt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, p, v, cnt);
+  return hipGetLastError();
+}
+
+}  // namespace ozl

@@ -1,0 +1,642 @@
+// Host side of libozii: the plan rule, the device plan tables, workspace
+// management and the orchestration of the product, the LU and the solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/ozii.h"
+#include "ozii_elem.hpp"
+#include "ozii_kernels.hpp"
+
+namespace {
+
+using ozk::DevPlan;
+
+// ---------------------------------------------------------------------------
+// Plan rule (Sec. 3.2, paragraph "Determining w and N"):
+//   slack = ceil(log2 2K) + 16 + g_ex; for S = 1, 2, ...:
+//   w = ceil((p + slack)/S), need = 2w + log2 K + log2 S + 5,
+//   N = fewest leading moduli whose cumulative log2 exceeds need;
+//   accept the first S whose need fits and whose accumulator bound holds.
+// Moduli: the 54 largest prime powers <= 256, descending (54 moduli and
+// 362.8 bits in Sec. 3.2).
+// ---------------------------------------------------------------------------
+std::vector<int> int8_moduli() {
+  std::vector<int> out;
+  for (int p = 2; p <= 256; ++p) {
+    bool prime = true;
+    for (int d = 2; d * d <= p; ++d)
+      if (p % d == 0) {
+        prime = false;
+        break;
+      }
+    if (!prime) continue;
+    int q = p;
+    while (q * p <= 256) q *= p;
+    out.push_back(q);
+  }
+  std::sort(out.begin(), out.end(), std::greater<int>());
+  return out;
+}
+
+struct HostPlan {
+  int p = 0;
+  int64_t K = 0;
+  int backend = OZII_BE_INT8;
+  int S = 0, w = 0, Q = 0, nmod = 0, g0 = 0, ng = 0;
+  int nwx = 0, nh = 0, nwc = 0;
+  double need = 0;
+  std::vector<int> mods;
+};
+
+bool accum_ok(int backend, int64_t K, int S) {
+  const double ks = (double)K * S;
+  if (backend == OZII_BE_INT8) return ks * 128.0 * 128.0 < 2147483648.0;
+  if (backend == OZII_BE_FP8_B17) return ks * 128.0 * 128.0 < 2147483648.0 && ks * 64.0 < 16777216.0;
+  return true;
+}
+
+ozII_status make_plan(int p, int64_t K, const ozII_opts *o, HostPlan &pl, std::string *why,
+                      bool check_sizes = true) {
+  const int backend = (o && o->backend) ? o->backend : OZII_BE_INT8;
+  const int nslice = o ? o->nslice : 0;
+  const int extra = o ? o->extra_groups : 0;
+  const int gex = o ? o->guard_ex : 0;
+  if (p <= 0 || K <= 0 || nslice < 0 || extra < 0 || gex < 0) return OZII_EINVAL;
+  if (backend != OZII_BE_INT8) {
+    if (why) *why = "only the INT8 back-end is built";
+    return OZII_EUNSUPPORTED;
+  }
+  const std::vector<int> mods = int8_moduli();
+  const int slack = (int)std::ceil(std::log2(2.0 * (double)K)) + 16 + gex;
+  const int s_lo = nslice > 0 ? nslice : 1, s_hi = nslice > 0 ? nslice : 4096;
+  bool any_acc = false;
+  for (int S = s_lo; S <= s_hi; ++S) {
+    if (!accum_ok(backend, K, S)) continue;
+    any_acc = true;
+    const int w = (p + slack + S - 1) / S;
+    const double need = 2.0 * w + std::log2((double)K) + std::log2((double)S) + 5.0;
+    double cum = 0.0;
+    int N = 0;
+    for (size_t i = 0; i < mods.size(); ++i) {
+      cum += std::log2((double)mods[i]);
+      if (cum > need) {
+        N = (int)i + 1;
+        break;
+      }
+    }
+    if (N == 0) continue;
+    pl.p = p;
+    pl.K = K;
+    pl.backend = backend;
+    pl.S = S;
+    pl.w = w;
+    pl.Q = w * S;
+    pl.nmod = N;
+    pl.g0 = std::max(0, S - 1 - extra);
+    pl.ng = 2 * S - 1 - pl.g0;
+    pl.need = need;
+    pl.mods.assign(mods.begin(), mods.begin() + N);
+    pl.nwx = (pl.Q + 2 + 31) / 32;
+    pl.nh = (w + 2 + 15) / 16;
+    const int sbits = 2 * w + (int)std::ceil(std::log2((double)K * S)) + 2;
+    pl.nwc = (sbits + w * (pl.ng - 1) + 1 + 31) / 32;
+    if (check_sizes && (pl.nwx > 12 || pl.nh > ozk::NHMAX || pl.nwc > 16 || w > 300)) {
+      if (why) *why = "plan exceeds the compiled word sizes";
+      return OZII_EUNSUPPORTED;
+    }
+    return OZII_OK;
+  }
+  if (why) *why = any_acc ? "need exceeds the 362.8-bit CRT capacity" : "accumulator bound";
+  return any_acc ? OZII_ECAPACITY : OZII_EOVERFLOW;
+}
+
+// ---------------------------------------------------------------------------
+// Small unsigned big integers (little-endian 32-bit limbs) for the CRT
+// constants P and M_l.
+// ---------------------------------------------------------------------------
+typedef std::vector<uint32_t> Big;
+void big_mul_small(Big &a, uint32_t m) {
+  uint64_t carry = 0;
+  for (auto &x : a) {
+    uint64_t t = (uint64_t)x * m + carry;
+    x = (uint32_t)t;
+    carry = t >> 32;
+  }
+  if (carry) a.push_back((uint32_t)carry);
+}
+uint32_t big_mod_small(const Big &a, uint32_t m) {
+  uint64_t r = 0;
+  for (size_t i = a.size(); i-- > 0;) r = ((r << 32) | a[i]) % m;
+  return (uint32_t)r;
+}
+uint16_t big_digit16(const Big &a, int k) {
+  size_t wi = (size_t)k / 2;
+  if (wi >= a.size()) return 0;
+  return (uint16_t)(a[wi] >> (16 * (k & 1)));
+}
+
+void build_devplan(const HostPlan &hp, DevPlan &dp) {
+  std::memset(&dp, 0, sizeof(dp));
+  dp.S = hp.S;
+  dp.w = hp.w;
+  dp.Q = hp.Q;
+  dp.nmod = hp.nmod;
+  dp.g0 = hp.g0;
+  dp.ng = hp.ng;
+  dp.nwx = hp.nwx;
+  dp.nh = hp.nh;
+  Big P{1};
+  for (int m : hp.mods) big_mul_small(P, (uint32_t)m);
+  for (int l = 0; l < hp.nmod; ++l) {
+    const uint32_t m = (uint32_t)hp.mods[l];
+    dp.m[l] = (int32_t)m;
+    dp.inv_m[l] = 1.0 / (double)m;
+    Big Ml{1};
+    for (int k = 0; k < hp.nmod; ++k)
+      if (k != l) big_mul_small(Ml, (uint32_t)hp.mods[k]);
+    const uint32_t r = big_mod_small(Ml, m);
+    uint32_t y = 0;
+    for (uint32_t c = 1; c < m; ++c)
+      if ((uint64_t)r * c % m == 1) {
+        y = c;
+        break;
+      }
+    dp.y[l] = (int32_t)y;
+    for (int k = 0; k < ozk::NDCRT; ++k) dp.Mdig[l][k] = big_digit16(Ml, k);
+    uint64_t pw = 1 % m;
+    for (int k = 0; k < ozk::NHMAX; ++k) {
+      dp.pw16[l][k] = (uint32_t)pw;
+      pw = (pw << 16) % m;
+    }
+    uint64_t p2 = 1 % m;
+    for (int b = 0; b < hp.w; ++b) p2 = (p2 * 2) % m;
+    dp.p2w[l] = (uint32_t)p2;
+  }
+  for (int k = 0; k < ozk::NDCRT; ++k) dp.Pdig[k] = big_digit16(P, k);
+  dp.nd = ozk::NDCRT;
+}
+
+int64_t roundup(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// handle
+// ---------------------------------------------------------------------------
+struct ozII_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  // Ozaki workspace
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  // panel scratch
+  uint32_t *bar = nullptr;
+  int *err = nullptr;
+  double *ckey = nullptr;
+  int *cpos = nullptr, *cphys = nullptr;
+  double *crow = nullptr;
+  int *perm = nullptr, *moved = nullptr, *nmoved = nullptr;
+  int64_t panel_n = 0;
+  int panel_kb = 0;
+  std::map<std::tuple<int, int64_t, int, int, int, int>, std::pair<HostPlan, DevPlan *>> plans;
+};
+
+namespace {
+
+ozII_status fail(ozII_ctx *h, ozII_status s, const std::string &msg) {
+  if (h) h->last_error = msg;
+  return s;
+}
+
+ozII_status hip_fail(ozII_ctx *h, hipError_t e, const char *where) {
+  return fail(h, OZII_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+ozII_status get_plan(ozII_ctx *h, int p, int64_t K, const ozII_opts *o, const HostPlan **hp,
+                     const DevPlan **dp) {
+  const int backend = (o && o->backend) ? o->backend : OZII_BE_INT8;
+  auto key = std::make_tuple(p, K, backend, o ? o->nslice : 0, o ? o->extra_groups : 0,
+                             o ? o->guard_ex : 0);
+  auto it = h->plans.find(key);
+  if (it == h->plans.end()) {
+    HostPlan pl;
+    std::string why;
+    ozII_status st = make_plan(p, K, o, pl, &why);
+    if (st != OZII_OK) return fail(h, st, "plan: " + why);
+    DevPlan host_dp;
+    build_devplan(pl, host_dp);
+    DevPlan *d = nullptr;
+    hipError_t e = hipMalloc((void **)&d, sizeof(DevPlan));
+    if (e != hipSuccess) return hip_fail(h, e, "hipMalloc(plan)");
+    e = hipMemcpy(d, &host_dp, sizeof(DevPlan), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(h, e, "hipMemcpy(plan)");
+    it = h->plans.emplace(key, std::make_pair(pl, d)).first;
+  }
+  *hp = &it->second.first;
+  *dp = it->second.second;
+  return OZII_OK;
+}
+
+struct GemmLayout {
+  int64_t Mp, Np, Kp, planeA, planeB, tplBytes;
+  size_t off_ea, off_eb, off_pa, off_pb, off_tpl, total;
+};
+
+GemmLayout gemm_layout(const HostPlan &hp, int64_t M, int64_t N, int64_t K) {
+  GemmLayout L;
+  L.Mp = roundup(std::max<int64_t>(M, 1), 128);
+  L.Np = roundup(std::max<int64_t>(N, 1), 128);
+  L.Kp = roundup(std::max<int64_t>(K, 1), 64);
+  L.planeA = L.Mp * L.Kp;
+  L.planeB = L.Np * L.Kp;
+  L.tplBytes = (int64_t)hp.ng * hp.nmod * L.Mp * L.Np;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o += (bytes + 255) / 256 * 256;
+    return r;
+  };
+  L.off_ea = take(sizeof(int32_t) * L.Mp);
+  L.off_eb = take(sizeof(int32_t) * L.Np);
+  L.off_pa = take((size_t)hp.S * hp.nmod * L.planeA);
+  L.off_pb = take((size_t)hp.S * hp.nmod * L.planeB);
+  L.off_tpl = take((size_t)L.tplBytes);
+  L.total = o;
+  return L;
+}
+
+ozII_status ensure_ws(ozII_ctx *h, size_t bytes) {
+  if (bytes <= h->ws_bytes) return OZII_OK;
+  if (h->ws) {
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+    hipFree(h->ws);
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+  }
+  hipError_t e = hipMalloc((void **)&h->ws, bytes);
+  if (e != hipSuccess) {
+    h->ws = nullptr;
+    return fail(h, OZII_ENOMEM, "workspace allocation failed");
+  }
+  h->ws_bytes = bytes;
+  return OZII_OK;
+}
+
+ozII_status ensure_panel(ozII_ctx *h, int64_t n, int kb) {
+  if (n <= h->panel_n && kb <= h->panel_kb) return OZII_OK;
+  if (h->bar) {
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+    hipFree(h->ckey);
+    hipFree(h->cpos);
+    hipFree(h->cphys);
+    hipFree(h->crow);
+    hipFree(h->perm);
+    hipFree(h->moved);
+  }
+  const int64_t nn = std::max<int64_t>(n, h->panel_n);
+  const int kk = std::max(kb, h->panel_kb);
+  const int G = 256;
+  hipError_t e = hipSuccess;
+  if (!h->bar) {
+    e = hipMalloc((void **)&h->bar, 64);
+    if (e == hipSuccess) e = hipMemset(h->bar, 0, 64);
+    if (e == hipSuccess) {
+      h->err = (int *)(h->bar + 4);
+      h->nmoved = (int *)(h->bar + 8);
+    }
+  }
+  if (e == hipSuccess) e = hipMalloc((void **)&h->ckey, sizeof(double) * 2 * G * 4);
+  if (e == hipSuccess) e = hipMalloc((void **)&h->cpos, sizeof(int) * 2 * G);
+  if (e == hipSuccess) e = hipMalloc((void **)&h->cphys, sizeof(int) * 2 * G);
+  if (e == hipSuccess) e = hipMalloc((void **)&h->crow, sizeof(double) * 2 * G * kk * 4);
+  if (e == hipSuccess) e = hipMalloc((void **)&h->perm, sizeof(int) * nn);
+  if (e == hipSuccess) e = hipMalloc((void **)&h->moved, sizeof(int) * nn);
+  if (e != hipSuccess) return fail(h, OZII_ENOMEM, "panel scratch allocation failed");
+  h->panel_n = nn;
+  h->panel_kb = kk;
+  return OZII_OK;
+}
+
+bool valid_nc(int nc) { return nc >= 2 && nc <= 4; }
+
+ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64_t K,
+                      const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
+                      int64_t ldc, const ozII_opts *o, int32_t *ea_out, int32_t *eb_out,
+                      int8_t *pa_out, int8_t *pb_out, uint8_t *tpl_out, uint64_t *sbar_out,
+                      int nlimb) {
+  if (!h) return OZII_EINVAL;
+  if (!valid_nc(nc)) return fail(h, OZII_EUNSUPPORTED, "nc must be 2, 3 or 4");
+  if (mode != 0 && mode != 1) return fail(h, OZII_EINVAL, "mode must be 0 or 1");
+  if (M < 0 || N < 0 || K < 0) return fail(h, OZII_EINVAL, "negative size");
+  if (M == 0 || N == 0) return OZII_OK;
+  if (lda < std::max<int64_t>(M, 1) || ldb < std::max<int64_t>(K, 1) || ldc < M)
+    return fail(h, OZII_EINVAL, "leading dimension too small");
+  if (!C || (K > 0 && (!A || !B))) return fail(h, OZII_EINVAL, "null matrix pointer");
+  if (K == 0) {
+    if (mode == 1) return OZII_OK;
+    // C = 0
+    hipError_t e = hipMemset2DAsync(C, ldc * nc * 8, 0, M * nc * 8, N, h->stream);
+    return e == hipSuccess ? OZII_OK : hip_fail(h, e, "hipMemset2DAsync");
+  }
+  const HostPlan *hp;
+  const DevPlan *dp;
+  ozII_status st = get_plan(h, 53 * nc, K, o, &hp, &dp);
+  if (st != OZII_OK) return st;
+  GemmLayout L = gemm_layout(*hp, M, N, K);
+  st = ensure_ws(h, L.total);
+  if (st != OZII_OK) return st;
+  int32_t *ea = (int32_t *)(h->ws + L.off_ea);
+  int32_t *eb = (int32_t *)(h->ws + L.off_eb);
+  int8_t *pa = (int8_t *)(h->ws + L.off_pa);
+  int8_t *pb = (int8_t *)(h->ws + L.off_pb);
+  uint8_t *tpl = (uint8_t *)(h->ws + L.off_tpl);
+  hipStream_t s = h->stream;
+  hipError_t e;
+  if ((e = ozl::launch_exponents(nc, A, lda, M, K, 1, ea, s)) != hipSuccess) return hip_fail(h, e, "exponents(A)");
+  if ((e = ozl::launch_exponents(nc, B, ldb, K, N, 0, eb, s)) != hipSuccess) return hip_fail(h, e, "exponents(B)");
+  if ((e = ozl::launch_producer(nc, hp->nwx, hp->nh, A, lda, 1, M, L.Mp, K, L.Kp, ea, dp, pa, L.planeA, s)) != hipSuccess)
+    return hip_fail(h, e, "producer(A)");
+  if ((e = ozl::launch_producer(nc, hp->nwx, hp->nh, B, ldb, 0, N, L.Np, K, L.Kp, eb, dp, pb, L.planeB, s)) != hipSuccess)
+    return hip_fail(h, e, "producer(B)");
+  if ((e = ozl::launch_gemm_i8(pa, pb, tpl, dp, hp->ng, hp->nmod, L.Mp, L.Np, L.Kp, L.planeA, L.planeB, s)) != hipSuccess)
+    return hip_fail(h, e, "gemm_i8");
+  if (ea_out && (e = hipMemcpyAsync(ea_out, ea, 4 * M, hipMemcpyDeviceToDevice, s)) != hipSuccess) return hip_fail(h, e, "copy ea");
+  if (eb_out && (e = hipMemcpyAsync(eb_out, eb, 4 * N, hipMemcpyDeviceToDevice, s)) != hipSuccess) return hip_fail(h, e, "copy eb");
+  if (pa_out && (e = hipMemcpyAsync(pa_out, pa, (size_t)hp->S * hp->nmod * L.planeA, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+    return hip_fail(h, e, "copy planesA");
+  if (pb_out && (e = hipMemcpyAsync(pb_out, pb, (size_t)hp->S * hp->nmod * L.planeB, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+    return hip_fail(h, e, "copy planesB");
+  if (tpl_out && (e = hipMemcpyAsync(tpl_out, tpl, (size_t)L.tplBytes, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+    return hip_fail(h, e, "copy tpl");
+  if (sbar_out && (e = ozl::launch_crt_export(tpl, L.Mp, L.Np, M, N, dp, sbar_out, nlimb, s)) != hipSuccess)
+    return hip_fail(h, e, "crt_export");
+  if ((e = ozl::launch_consumer(nc, hp->nwc, tpl, L.Mp, L.Np, C, ldc, M, N, ea, eb, dp, mode, s)) != hipSuccess)
+    return hip_fail(h, e, "consumer");
+  return OZII_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ozII_status ozII_create(ozII_handle *out, int device, void *stream) {
+  if (!out) return OZII_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return OZII_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return OZII_EHIP;
+  ozII_ctx *h = new ozII_ctx();
+  h->device = device;
+  h->stream = (hipStream_t)stream;
+  *out = h;
+  return OZII_OK;
+}
+
+ozII_status ozII_destroy(ozII_handle h) {
+  if (!h) return OZII_EINVAL;
+  hipStreamSynchronize(h->stream);
+  if (h->ws) hipFree(h->ws);
+  for (auto &kv : h->plans) hipFree(kv.second.second);
+  if (h->bar) {
+    hipFree(h->bar);
+    hipFree(h->ckey);
+    hipFree(h->cpos);
+    hipFree(h->cphys);
+    hipFree(h->crow);
+    hipFree(h->perm);
+    hipFree(h->moved);
+  }
+  delete h;
+  return OZII_OK;
+}
+
+ozII_status ozII_set_stream(ozII_handle h, void *stream) {
+  if (!h) return OZII_EINVAL;
+  h->stream = (hipStream_t)stream;
+  return OZII_OK;
+}
+
+ozII_status ozII_plan_query(int32_t p, int64_t K, const ozII_opts *o, int32_t *S, int32_t *w,
+                            int32_t *Q, int32_t *nmod, int32_t *moduli) {
+  HostPlan pl;
+  ozII_status st = make_plan(p, K, o, pl, nullptr, false);
+  if (st != OZII_OK) return st;
+  if (S) *S = pl.S;
+  if (w) *w = pl.w;
+  if (Q) *Q = pl.Q;
+  if (nmod) *nmod = pl.nmod;
+  if (moduli)
+    for (int i = 0; i < pl.nmod && i < 64; ++i) moduli[i] = pl.mods[i];
+  return OZII_OK;
+}
+
+ozII_status ozII_reserve(ozII_handle h, int32_t nc, int64_t M, int64_t N, int64_t K, int64_t n,
+                         const ozII_opts *o) {
+  if (!h || !valid_nc(nc) || M < 0 || N < 0 || K < 0 || n < 0) return OZII_EINVAL;
+  if (K > 0 && M > 0 && N > 0) {
+    const HostPlan *hp;
+    const DevPlan *dp;
+    ozII_status st = get_plan(h, 53 * nc, K, o, &hp, &dp);
+    if (st != OZII_OK) return st;
+    st = ensure_ws(h, gemm_layout(*hp, M, N, K).total);
+    if (st != OZII_OK) return st;
+  }
+  if (n > 0) {
+    const int b = (o && o->block > 0) ? o->block : 256;
+    ozII_status st = ensure_panel(h, n, b);
+    if (st != OZII_OK) return st;
+    if (!(o && o->method == OZII_METHOD_NAIVE) && n > b) {
+      const HostPlan *hp;
+      const DevPlan *dp;
+      st = get_plan(h, 53 * nc, b, o, &hp, &dp);
+      if (st != OZII_OK) return st;
+      st = ensure_ws(h, gemm_layout(*hp, n - b, n - b, b).total);
+      if (st != OZII_OK) return st;
+    }
+  }
+  return OZII_OK;
+}
+
+ozII_status ozII_gemm(ozII_handle h, int32_t mode, int32_t nc, int64_t M, int64_t N, int64_t K,
+                      const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
+                      int64_t ldc, const ozII_opts *o) {
+  return gemm_impl(h, mode, nc, M, N, K, A, lda, B, ldb, C, ldc, o, nullptr, nullptr, nullptr,
+                   nullptr, nullptr, nullptr, 0);
+}
+
+ozII_status ozII_gemm_stages(ozII_handle h, int32_t mode, int32_t nc, int64_t M, int64_t N,
+                             int64_t K, const double *A, int64_t lda, const double *B,
+                             int64_t ldb, double *C, int64_t ldc, const ozII_opts *o,
+                             int32_t *ea, int32_t *eb, int8_t *planesA, int8_t *planesB,
+                             uint8_t *tpl, uint64_t *sbar, int32_t nlimb) {
+  if (sbar && (nlimb < 1 || nlimb > 6)) return fail(h, OZII_EINVAL, "nlimb must be 1..6");
+  return gemm_impl(h, mode, nc, M, N, K, A, lda, B, ldb, C, ldc, o, ea, eb, planesA, planesB, tpl,
+                   sbar, nlimb);
+}
+
+ozII_status ozII_gemm_stage_dims(int32_t nc, int64_t M, int64_t N, int64_t K, const ozII_opts *o,
+                                 int64_t *Mp, int64_t *Np, int64_t *Kp, int32_t *S,
+                                 int32_t *nmod, int32_t *ng) {
+  if (!valid_nc(nc) || M <= 0 || N <= 0 || K <= 0) return OZII_EINVAL;
+  HostPlan pl;
+  ozII_status st = make_plan(53 * nc, K, o, pl, nullptr);
+  if (st != OZII_OK) return st;
+  GemmLayout L = gemm_layout(pl, M, N, K);
+  if (Mp) *Mp = L.Mp;
+  if (Np) *Np = L.Np;
+  if (Kp) *Kp = L.Kp;
+  if (S) *S = pl.S;
+  if (nmod) *nmod = pl.nmod;
+  if (ng) *ng = pl.ng;
+  return OZII_OK;
+}
+
+ozII_status ozII_getrf(ozII_handle h, int32_t nc, int64_t n, double *A, int64_t lda,
+                       int64_t *ipiv, int32_t *info, const ozII_opts *o) {
+  if (!h) return OZII_EINVAL;
+  if (!valid_nc(nc)) return fail(h, OZII_EUNSUPPORTED, "nc must be 2, 3 or 4");
+  if (n < 0 || lda < std::max<int64_t>(n, 1)) return fail(h, OZII_EINVAL, "bad n or lda");
+  if (n == 0) return OZII_OK;
+  if (!A || !ipiv || !info) return fail(h, OZII_EINVAL, "null pointer");
+  const int b = (o && o->block > 0) ? o->block : 256;
+  const int method = o ? o->method : OZII_METHOD_OZAKI;
+  if (b > 512) return fail(h, OZII_EUNSUPPORTED, "panel width above 512");
+  if (method != OZII_METHOD_OZAKI && method != OZII_METHOD_NAIVE) return fail(h, OZII_EINVAL, "bad method");
+  if (n > (int64_t)1 << 20) return fail(h, OZII_EUNSUPPORTED, "n too large");
+  ozII_status st = ensure_panel(h, n, b);
+  if (st != OZII_OK) return st;
+  if (method == OZII_METHOD_OZAKI && n > b) {
+    const HostPlan *hp;
+    const DevPlan *dp;
+    st = get_plan(h, 53 * nc, b, o, &hp, &dp);
+    if (st != OZII_OK) return st;
+    st = ensure_ws(h, gemm_layout(*hp, n - b, n - b, b).total);
+    if (st != OZII_OK) return st;
+  }
+  hipStream_t s = h->stream;
+  hipError_t e;
+  if ((e = ozl::launch_fill_int(info, 0, 1, s)) != hipSuccess) return hip_fail(h, e, "fill info");
+  for (int64_t k = 0; k < n; k += b) {
+    const int kb = (int)std::min<int64_t>(b, n - k);
+    const int64_t nr = n - k;
+    // panel geometry: G co-resident workgroups of R rows each
+    int G = 256, R = 0, maxb = 0;
+    for (;;) {
+      R = (int)((nr + G - 1) / G);
+      if (R > 32) return fail(h, OZII_EUNSUPPORTED, "panel too tall for the resident kernel");
+      if (ozl::panel_lds_bytes(nc, kb, R, nr) + 16384 > 160 * 1024) {
+        return fail(h, OZII_EUNSUPPORTED, "panel does not fit in LDS");
+      }
+      e = ozl::panel_max_blocks(nc, kb, R, nr, &maxb);
+      if (e != hipSuccess) return hip_fail(h, e, "panel occupancy");
+      if (maxb >= G) break;
+      G = maxb;
+      if (G <= 0) return fail(h, OZII_EUNSUPPORTED, "panel kernel cannot be resident");
+    }
+    G = (int)std::min<int64_t>(G, (nr + R - 1) / R);
+    if ((e = ozl::launch_fill_int((int *)h->bar, 0, 2, s)) != hipSuccess) return hip_fail(h, e, "fill bar");
+    if ((e = ozl::launch_panel(nc, A, lda, n, k, kb, R, G, ipiv, info, h->bar, h->err, h->ckey,
+                               h->cpos, h->cphys, h->crow, h->perm, h->moved, h->nmoved, s)) != hipSuccess)
+      return hip_fail(h, e, "panel");
+    if ((e = ozl::launch_laswp(nc, A, lda, k, 0, n, h->perm, h->moved, h->nmoved, s)) != hipSuccess)
+      return hip_fail(h, e, "laswp");
+    if (k + kb < n) {
+      const int64_t m2 = n - k - kb;
+      const double *L11 = A + (k + k * lda) * nc;
+      double *A12 = A + (k + (k + kb) * lda) * nc;
+      if ((e = ozl::launch_trsm_lower_unit(nc, L11, lda, A12, lda, kb, m2, s)) != hipSuccess)
+        return hip_fail(h, e, "trsm");
+      const double *L21 = A + ((k + kb) + k * lda) * nc;
+      double *A22 = A + ((k + kb) + (k + kb) * lda) * nc;
+      if (method == OZII_METHOD_OZAKI) {
+        st = gemm_impl(h, 1, nc, m2, m2, kb, L21, lda, A12, lda, A22, lda, o, nullptr, nullptr,
+                       nullptr, nullptr, nullptr, nullptr, 0);
+        if (st != OZII_OK) return st;
+      } else {
+        if ((e = ozl::launch_naive_gemm(nc, L21, lda, A12, lda, A22, lda, m2, m2, kb, 0, s)) != hipSuccess)
+          return hip_fail(h, e, "naive update");
+      }
+    }
+  }
+  return OZII_OK;
+}
+
+ozII_status ozII_getrs(ozII_handle h, int32_t nc, int64_t n, int64_t nrhs, const double *LU,
+                       int64_t lda, const int64_t *ipiv, double *B, int64_t ldb) {
+  if (!h) return OZII_EINVAL;
+  if (!valid_nc(nc)) return fail(h, OZII_EUNSUPPORTED, "nc must be 2, 3 or 4");
+  if (n < 0 || nrhs < 0 || lda < std::max<int64_t>(n, 1) || ldb < std::max<int64_t>(n, 1))
+    return fail(h, OZII_EINVAL, "bad size or leading dimension");
+  if (n == 0 || nrhs == 0) return OZII_OK;
+  if (!LU || !ipiv || !B) return fail(h, OZII_EINVAL, "null pointer");
+  hipStream_t s = h->stream;
+  hipError_t e;
+  if ((e = ozl::launch_apply_ipiv(nc, B, ldb, n, nrhs, ipiv, s)) != hipSuccess) return hip_fail(h, e, "apply ipiv");
+  const int bs = 256;
+  for (int64_t i0 = 0; i0 < n; i0 += bs) {
+    const int ib = (int)std::min<int64_t>(bs, n - i0);
+    if ((e = ozl::launch_trsm_lower_unit(nc, LU + (i0 + i0 * lda) * nc, lda, B + i0 * nc, ldb, ib, nrhs, s)) != hipSuccess)
+      return hip_fail(h, e, "forward block");
+    if (i0 + ib < n) {
+      if ((e = ozl::launch_naive_gemm(nc, LU + ((i0 + ib) + i0 * lda) * nc, lda, B + i0 * nc, ldb,
+                                      B + (i0 + ib) * nc, ldb, n - i0 - ib, nrhs, ib, 0, s)) != hipSuccess)
+        return hip_fail(h, e, "forward update");
+    }
+  }
+  const int64_t nblk = (n + bs - 1) / bs;
+  for (int64_t bi = nblk - 1; bi >= 0; --bi) {
+    const int64_t j0 = bi * bs;
+    const int ib = (int)std::min<int64_t>(bs, n - j0);
+    if ((e = ozl::launch_trsm_upper(nc, LU + (j0 + j0 * lda) * nc, lda, B + j0 * nc, ldb, ib, nrhs, s)) != hipSuccess)
+      return hip_fail(h, e, "backward block");
+    if (j0 > 0) {
+      if ((e = ozl::launch_naive_gemm(nc, LU + (j0 * lda) * nc, lda, B + j0 * nc, ldb, B, ldb, j0,
+                                      nrhs, ib, 1, s)) != hipSuccess)
+        return hip_fail(h, e, "backward update");
+    }
+  }
+  return OZII_OK;
+}
+
+ozII_status ozII_sync_check(ozII_handle h) {
+  if (!h) return OZII_EINVAL;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+  if (h->err) {
+    int v = 0;
+    e = hipMemcpy(&v, h->err, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(h, e, "read error flag");
+    if (v) return fail(h, OZII_EDEVICE, "a panel grid barrier timed out");
+  }
+  return OZII_OK;
+}
+
+const char *ozII_status_string(ozII_status s) {
+  switch (s) {
+    case OZII_OK: return "ok";
+    case OZII_EINVAL: return "invalid argument";
+    case OZII_ECAPACITY: return "plan exceeds the CRT capacity";
+    case OZII_EOVERFLOW: return "accumulator bound violated";
+    case OZII_ENOMEM: return "out of device memory";
+    case OZII_EHIP: return "HIP runtime error";
+    case OZII_EUNSUPPORTED: return "unsupported format or option";
+    case OZII_EDEVICE: return "device-side error";
+  }
+  return "unknown status";
+}
+
+const char *ozII_last_error(ozII_handle h) { return h ? h->last_error.c_str() : ""; }
+
+}  // extern "C"

@@ -1,0 +1,392 @@
+// Per-element building blocks of the Ozaki-II product (Sec. 3.1-3.3 of the
+// paper): fixed-point conversion of an expansion (Eq. direct), balanced
+// slicing, centred residues, CRT of one digit group (Eq. crt) and the final
+// greedy round-to-nearest.  Everything is exact integer arithmetic on 32-bit
+// words or 16-bit digits held in fixed-size arrays with compile-time sizes.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define OZ_HD __host__ __device__ __forceinline__
+
+namespace ozk {
+
+constexpr int MAXMOD = 64;   // moduli a plan may use
+constexpr int NHMAX = 20;    // 16-bit digits of one slice (w <= 300)
+constexpr int NDCRT = 24;    // 16-bit digits of sum_l t_l M_l (log2 P <= 363)
+constexpr int32_t EXP_ZERO = INT32_MIN;
+
+// Tables of one plan, resident in device memory (read with uniform indices).
+struct DevPlan {
+  int32_t S, w, Q, nmod, g0, ng, nwx, nh;
+  int32_t m[MAXMOD];
+  int32_t y[MAXMOD];
+  double inv_m[MAXMOD];
+  uint32_t pw16[MAXMOD][NHMAX];   // 2^(16k) mod m
+  uint32_t p2w[MAXMOD];           // 2^w mod m
+  uint16_t Mdig[MAXMOD][NDCRT];   // M_l = P/m_l in 16-bit digits
+  uint16_t Pdig[NDCRT];           // P in 16-bit digits
+  int32_t nd;                     // digits used for the CRT sums
+};
+
+// Bits [32k, 32k+32) of mag * 2^s (mag < 2^54, s may be negative: the bits
+// below 2^0 are dropped, i.e. the value is truncated toward zero).
+OZ_HD uint32_t word_of_shifted(uint64_t mag, int s, int k) {
+  int d = s - 32 * k;
+  if (d >= 0) return d < 32 ? (uint32_t)(mag << d) : 0u;
+  int r = -d;
+  return r < 64 ? (uint32_t)(mag >> r) : 0u;
+}
+
+// Decompose a non-zero finite double: |x| = mag * 2^(e - 53), e = frexp
+// exponent for normal numbers.
+OZ_HD void split_double(double x, uint64_t &mag, int &e) {
+  uint64_t bits;
+  __builtin_memcpy(&bits, &x, 8);
+  int be = (int)((bits >> 52) & 0x7ff);
+  uint64_t f = bits & ((1ull << 52) - 1);
+  if (be == 0) {  // subnormal: |x| = f * 2^-1074
+    mag = f;
+    e = -1074 + 53;
+  } else {
+    mag = f | (1ull << 52);
+    e = be - 1022;
+  }
+}
+
+// frexp exponent of the leading non-zero component, EXP_ZERO for zero.
+template <int NC>
+OZ_HD int32_t exponent_of(const double *x) {
+  int32_t r = EXP_ZERO;
+  bool found = false;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    double v = x[c];
+    if (!found && v != 0.0) {
+      found = true;
+      uint64_t bits;
+      __builtin_memcpy(&bits, &v, 8);
+      int be = (int)((bits >> 52) & 0x7ff);
+      if (be != 0) {
+        r = be - 1022;
+      } else {
+        uint64_t f = bits & ((1ull << 52) - 1);
+        r = -1074 + (64 - __builtin_clzll(f));
+      }
+    }
+  }
+  return r;
+}
+
+// X = sum_c sgn(x_c) floor(|x_c| 2^mu) in NWX-word two's complement.
+template <int NC, int NWX>
+OZ_HD void to_fixed(const double *x, int mu, uint32_t (&X)[NWX]) {
+#pragma unroll
+  for (int k = 0; k < NWX; ++k) X[k] = 0u;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    double v = x[c];
+    if (v != 0.0) {
+      uint64_t mag;
+      int e;
+      split_double(v, mag, e);
+      int s = e - 53 + mu;
+      uint32_t carry = 0;
+      if (v > 0.0) {
+#pragma unroll
+        for (int k = 0; k < NWX; ++k) {
+          uint64_t t = (uint64_t)X[k] + word_of_shifted(mag, s, k) + carry;
+          X[k] = (uint32_t)t;
+          carry = (uint32_t)(t >> 32);
+        }
+      } else {
+        uint32_t borrow = 0;
+#pragma unroll
+        for (int k = 0; k < NWX; ++k) {
+          uint64_t sub = (uint64_t)word_of_shifted(mag, s, k) + borrow;
+          uint64_t t = (uint64_t)X[k] - sub;
+          X[k] = (uint32_t)t;
+          borrow = (uint32_t)((t >> 63) & 1u);
+        }
+      }
+      (void)carry;
+    }
+  }
+}
+
+// residue in [0, m) of x < 2^53 given as a double-exact integer
+OZ_HD uint32_t mod_small(double x, int32_t m, double inv_m) {
+  double q = __builtin_floor(x * inv_m);
+  double r = __builtin_fma(-q, (double)m, x);
+  if (r < 0.0) r += (double)m;
+  if (r >= (double)m) r -= (double)m;
+  return (uint32_t)r;
+}
+
+// Residues mod every modulus of the NH 16-bit digits dig (an unsigned value):
+// r_l = (sum_k dig_k (2^16k mod m_l)) mod m_l
+template <int NH>
+OZ_HD uint32_t digits_mod(const uint32_t (&dig)[NH], const DevPlan *pl, int l) {
+  uint32_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < NH; ++k) acc += dig[k] * pl->pw16[l][k];
+  return mod_small((double)acc, pl->m[l], pl->inv_m[l]);
+}
+
+// centred residue in [-floor(m/2), ceil(m/2)-1] of r in [0, m)
+OZ_HD int32_t centre(uint32_t r, int32_t m) {
+  return (int32_t)r >= (m + 1) / 2 ? (int32_t)r - m : (int32_t)r;
+}
+
+// ---------------------------------------------------------------------------
+// CRT of one digit group (Eq. crt, GPU encoding): Sbar = sum t_l M_l -
+// round(F) P with F = sum t_l / m_l.  Output as two's-complement 16-bit digits
+// held in int32 (after carry propagation every digit is in [0, 2^16) except
+// the top one, which carries the sign).
+// ---------------------------------------------------------------------------
+OZ_HD void crt_digits(const uint8_t *t, int64_t stride, const DevPlan *pl, int32_t (&d)[NDCRT]) {
+#pragma unroll
+  for (int k = 0; k < NDCRT; ++k) d[k] = 0;
+  double F = 0.0;
+  for (int l = 0; l < pl->nmod; ++l) {
+    uint32_t tl = t[l * stride];
+    F += (double)tl * pl->inv_m[l];
+#pragma unroll
+    for (int k = 0; k < NDCRT; ++k) d[k] += (int32_t)(tl * (uint32_t)pl->Mdig[l][k]);
+  }
+  int32_t q = (int32_t)__builtin_floor(F + 0.5);
+#pragma unroll
+  for (int k = 0; k < NDCRT; ++k) d[k] -= q * (int32_t)pl->Pdig[k];
+  int32_t carry = 0;
+#pragma unroll
+  for (int k = 0; k < NDCRT; ++k) {
+    int32_t v = d[k] + carry;
+    d[k] = v & 0xffff;
+    carry = v >> 16;  // arithmetic
+  }
+  // |Sbar| < 2^383, so the digits are the two's complement of Sbar and the top
+  // digit carries the sign; the final carry holds no further information.
+  (void)carry;
+  d[NDCRT - 1] = (int32_t)(int16_t)(uint16_t)d[NDCRT - 1];
+}
+
+// ---------------------------------------------------------------------------
+// Greedy round-to-nearest (ties to even) of an NW-word two's-complement
+// integer times 2^eps into NC doubles; a component below 2^-1022 is flushed
+// and ends the expansion.
+// ---------------------------------------------------------------------------
+template <int NW>
+OZ_HD bool is_zero_words(const uint32_t (&a)[NW]) {
+  uint32_t o = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) o |= a[k];
+  return o == 0;
+}
+
+template <int NW>
+OZ_HD void negate_words(uint32_t (&a)[NW]) {
+  uint32_t carry = 1;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    uint64_t t = (uint64_t)(~a[k]) + carry;
+    a[k] = (uint32_t)t;
+    carry = (uint32_t)(t >> 32);
+  }
+}
+
+template <int NW, int NC>
+OZ_HD void round_out(uint32_t (&cb)[NW], int eps, double (&x)[NC]) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c) x[c] = 0.0;
+  bool done = false;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    if (!done && is_zero_words<NW>(cb)) done = true;
+    if (!done) {
+      const bool neg = (cb[NW - 1] >> 31) != 0;
+      uint32_t mag[NW];
+#pragma unroll
+      for (int k = 0; k < NW; ++k) mag[k] = cb[k];
+      if (neg) negate_words<NW>(mag);
+      // top non-zero word and the two below it
+      int tw = 0;
+#pragma unroll
+      for (int k = 0; k < NW; ++k)
+        if (mag[k] != 0u) tw = k;
+      uint32_t w0 = 0, w1 = 0, w2 = 0, below = 0;
+#pragma unroll
+      for (int k = 0; k < NW; ++k) {
+        if (k == tw) w0 = mag[k];
+        if (k == tw - 1) w1 = mag[k];
+        if (k == tw - 2) w2 = mag[k];
+        if (k < tw - 2) below |= mag[k];
+      }
+      const int lz = __builtin_clz(w0);
+      const int L = 32 * tw + 32 - lz;  // bit length
+      // 96-bit window normalised so that the leading one is bit 95
+      uint64_t hi = ((uint64_t)w0 << 32) | w1;
+      uint64_t lo = (uint64_t)w2 << 32;
+      if (lz) {
+        hi = (hi << lz) | (lo >> (64 - lz));
+        lo <<= lz;
+      }
+      uint64_t m = hi >> 11;                       // 53 bits
+      const uint32_t rb = (uint32_t)((hi >> 10) & 1u);
+      const bool sticky = ((hi & 0x3ffull) != 0) || (lo != 0) || (below != 0);
+      if (rb && (sticky || (m & 1ull))) m += 1;
+      const int ex = L - 53;                       // value = m * 2^ex
+      const int top = (63 - __builtin_clzll(m)) + ex + eps;
+      if (top < -1022) {
+        done = true;
+      } else {
+        double v = __builtin_ldexp((double)m, ex + eps);
+        x[c] = neg ? -v : v;
+        // cb -= sign * m * 2^ex  (for ex < 0 the bits below 2^0 are zero)
+        uint32_t borrow = 0, carry = 0;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+          uint32_t part = word_of_shifted(m, ex, k);
+          if (!neg) {
+            uint64_t t = (uint64_t)cb[k] - part - borrow;
+            cb[k] = (uint32_t)t;
+            borrow = (uint32_t)((t >> 63) & 1u);
+          } else {
+            uint64_t t = (uint64_t)cb[k] + part + carry;
+            cb[k] = (uint32_t)t;
+            carry = (uint32_t)(t >> 32);
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Producer, one element: fixed point (Eq. direct), balanced slices
+// v_0 .. v_{S-1} of width w (Sec. 3.2), centred residues of every slice for
+// every modulus, handed to store(t, l, r).  st: STG words of scratch
+// (thread-private) used for the arithmetic right shift by w.
+// ---------------------------------------------------------------------------
+constexpr int STG = 29;
+
+template <int NC, int NWX, int NH, class Store>
+OZ_HD void produce_element(const double *src, int mu, const DevPlan *pl, uint32_t *st, Store store) {
+  static_assert(NWX + 16 <= STG, "staging too small");
+  const int S = pl->S, w = pl->w, nmod = pl->nmod;
+  const int q0 = w >> 5, b0 = w & 31;
+  uint32_t Xw[NWX];
+#pragma unroll
+  for (int k = 0; k < NWX; ++k) Xw[k] = 0u;
+  if (src) to_fixed<NC, NWX>(src, mu, Xw);
+  for (int t = 0; t < S; ++t) {
+    uint32_t dig[NH];
+    bool neg = false;
+    uint32_t flag = 0;
+    if (t < S - 1) {
+      // the low w bits as 16-bit digits
+#pragma unroll
+      for (int k = 0; k < NH; ++k) {
+        uint32_t word = (k / 2 < NWX) ? Xw[k / 2] : 0u;
+        uint32_t d = (word >> (16 * (k & 1))) & 0xffffu;
+        int nb = w - 16 * k;
+        d = nb >= 16 ? d : (nb <= 0 ? 0u : (d & ((1u << nb) - 1u)));
+        dig[k] = d;
+      }
+      // the slice is centred (v = field - 2^w) when bit w-1 is set
+#pragma unroll
+      for (int k = 0; k < NWX; ++k)
+        if (k == ((w - 1) >> 5)) flag = (Xw[k] >> ((w - 1) & 31)) & 1u;
+    } else {
+      uint32_t mag[NWX];
+#pragma unroll
+      for (int k = 0; k < NWX; ++k) mag[k] = Xw[k];
+      neg = (mag[NWX - 1] >> 31) != 0;
+      if (neg) negate_words<NWX>(mag);
+#pragma unroll
+      for (int k = 0; k < NH; ++k) {
+        uint32_t word = (k / 2 < NWX) ? mag[k / 2] : 0u;
+        dig[k] = (word >> (16 * (k & 1))) & 0xffffu;
+      }
+    }
+    for (int l = 0; l < nmod; ++l) {
+      const int32_t m = pl->m[l];
+      uint32_t r = digits_mod<NH>(dig, pl, l);
+      if (t < S - 1) {
+        if (flag) {
+          r += (uint32_t)m - pl->p2w[l];  // r - 2^w (mod m)
+          r = r >= (uint32_t)m ? r - (uint32_t)m : r;
+        }
+      } else if (neg) {
+        r = r == 0 ? 0u : (uint32_t)m - r;
+      }
+      store(t, l, (int8_t)centre(r, m));
+    }
+    if (t < S - 1) {
+      // X <- (X >> w) + flag, an exact division since the slice was removed
+      const uint32_t fill = (Xw[NWX - 1] >> 31) ? 0xffffffffu : 0u;
+#pragma unroll
+      for (int k = 0; k < NWX; ++k) st[k] = Xw[k];
+#pragma unroll
+      for (int k = NWX; k < STG; ++k) st[k] = fill;
+      uint32_t carry = flag;
+#pragma unroll
+      for (int k = 0; k < NWX; ++k) {
+        int s = k + q0;
+        uint32_t lo = st[s < STG ? s : STG - 1];
+        uint32_t hi = st[s + 1 < STG ? s + 1 : STG - 1];
+        uint32_t v = b0 ? ((lo >> b0) | (hi << (32 - b0))) : lo;
+        uint64_t tt = (uint64_t)v + carry;
+        Xw[k] = (uint32_t)tt;
+        carry = (uint32_t)(tt >> 32);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Consumer, one element: CRT of every retained digit group, exact sum
+// cbar = sum_gi Sbar_{g0+gi} 2^(w gi), greedy rounding to NC components of
+// cbar 2^eps.  tptr(gi) points at t_0 of group gi; consecutive moduli are
+// pstride bytes apart.  st: CST words of thread-private scratch.
+// ---------------------------------------------------------------------------
+constexpr int CST = 33;
+
+template <int NC, int NWC, class TPtr>
+OZ_HD void consume_element(TPtr tptr, int64_t pstride, const DevPlan *pl, uint32_t *st, bool zero,
+                           int eps, double (&c)[NC]) {
+  static_assert(NDCRT / 2 + NWC + 1 <= CST, "staging too small");
+  const int w = pl->w, ng = pl->ng;
+  uint32_t cb[NWC];
+#pragma unroll
+  for (int k = 0; k < NWC; ++k) cb[k] = 0u;
+  for (int gi = 0; gi < ng; ++gi) {
+    int32_t d[NDCRT];
+    crt_digits(tptr(gi), pstride, pl, d);
+    const uint32_t fill = d[NDCRT - 1] < 0 ? 0xffffffffu : 0u;
+#pragma unroll
+    for (int k = 0; k < NDCRT / 2; ++k)
+      st[k] = ((uint32_t)d[2 * k] & 0xffffu) | ((uint32_t)d[2 * k + 1] << 16);
+#pragma unroll
+    for (int k = NDCRT / 2; k < CST; ++k) st[k] = fill;
+    const int off = w * gi, q0 = off >> 5, b0 = off & 31;
+    uint32_t carry = 0;
+#pragma unroll
+    for (int k = 0; k < NWC; ++k) {
+      const int s = k - q0;
+      uint32_t cur = s >= 0 ? st[s < CST ? s : CST - 1] : 0u;
+      uint32_t prv = s - 1 >= 0 ? st[s - 1 < CST ? s - 1 : CST - 1] : 0u;
+      uint32_t v = b0 ? ((cur << b0) | (prv >> (32 - b0))) : cur;
+      uint64_t tt = (uint64_t)cb[k] + v + carry;
+      cb[k] = (uint32_t)tt;
+      carry = (uint32_t)(tt >> 32);
+    }
+  }
+  if (zero) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) c[q] = 0.0;
+  } else {
+    round_out<NWC, NC>(cb, eps, c);
+  }
+}
+
+}  // namespace ozk

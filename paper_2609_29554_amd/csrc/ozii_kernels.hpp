@@ -1,0 +1,50 @@
+// Host-side launchers of the HIP kernels (internal to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ozk {
+struct DevPlan;
+}
+
+namespace ozl {
+using ozk::DevPlan;
+
+// Ozaki-II product stages
+hipError_t launch_exponents(int nc, const double *X, int64_t ld, int64_t rows, int64_t cols,
+                            int rowwise, int32_t *e, hipStream_t s);
+hipError_t launch_producer(int nc, int nwx, int nh, const double *X, int64_t ld, int rowwise,
+                           int64_t nout, int64_t noutp, int64_t K, int64_t Kp,
+                           const int32_t *exps, const DevPlan *pl, int8_t *planes,
+                           int64_t plane_bytes, hipStream_t s);
+hipError_t launch_gemm_i8(const int8_t *pa, const int8_t *pb, uint8_t *tpl, const DevPlan *pl,
+                          int ng, int nmod, int64_t Mp, int64_t Np, int64_t Kp, int64_t planeA,
+                          int64_t planeB, hipStream_t s);
+hipError_t launch_consumer(int nc, int nwc, const uint8_t *tpl, int64_t Mp, int64_t Np, double *C,
+                           int64_t ldc, int64_t M, int64_t N, const int32_t *ea,
+                           const int32_t *eb, const DevPlan *pl, int mode, hipStream_t s);
+hipError_t launch_crt_export(const uint8_t *tpl, int64_t Mp, int64_t Np, int64_t M, int64_t N,
+                             const DevPlan *pl, uint64_t *out, int nlimb, hipStream_t s);
+
+// LU pieces
+size_t panel_lds_bytes(int nc, int kb, int R, int64_t nr);
+hipError_t panel_max_blocks(int nc, int kb, int R, int64_t nr, int *maxblocks);
+hipError_t launch_panel(int nc, double *A, int64_t lda, int64_t n, int64_t k, int kb, int R, int G,
+                        int64_t *ipiv, int32_t *info, uint32_t *bar, int *err, double *ckey,
+                        int *cpos, int *cphys, double *crow, int *perm, int *moved, int *nmoved,
+                        hipStream_t s);
+hipError_t launch_laswp(int nc, double *A, int64_t lda, int64_t k, int64_t c0, int64_t c1,
+                        const int *perm, const int *moved, const int *nmoved, hipStream_t s);
+hipError_t launch_trsm_lower_unit(int nc, const double *L, int64_t lda, double *X, int64_t ldx,
+                                  int kb, int64_t ncols, hipStream_t s);
+hipError_t launch_trsm_upper(int nc, const double *U, int64_t lda, double *X, int64_t ldx, int kb,
+                             int64_t ncols, hipStream_t s);
+hipError_t launch_naive_gemm(int nc, const double *A, int64_t lda, const double *B, int64_t ldb,
+                             double *C, int64_t ldc, int64_t M, int64_t N, int64_t K, int desc,
+                             hipStream_t s);
+hipError_t launch_apply_ipiv(int nc, double *B, int64_t ldb, int64_t n, int64_t nrhs,
+                             const int64_t *ipiv, hipStream_t s);
+hipError_t launch_fill_int(int *p, int v, int64_t cnt, hipStream_t s);
+
+}  // namespace ozl
