@@ -1,0 +1,251 @@
+#!/usr/bin/env python
+"""Benchmark of the Ozaki-II multiple-precision LU on one MI355X.
+
+Workload: quad-double (4 x binary64 expansion, ~212 bits) LU with partial
+pivoting of the Lotkin matrix of order n = 2048 (row 0 all ones, a_ij =
+1/(i+j+1) below, each entry rounded greedily to QD), panel width b = 256,
+Schur updates by the Ozaki-II INT8 path, followed by the solve with
+b = A * ones.  One step = copy the resident input to the work buffer,
+getrf, getrs.  Inputs are generated on the host and uploaded before the
+timed region.
+
+Also measured in the same run (not part of `value`):
+  * the native QD LU on the same GPU -- the same panel and solve with the
+    Schur update done by expansion multiply-subtracts (blocked naive, same b)
+    and the unblocked b = 1 LU; the faster of the two is the comparator;
+  * per-kernel times from HIP events on the library's stream, their
+    algorithmic bytes / operations, and roofline fractions;
+  * the CPU oracle on a bounded sample (rank 0 only).
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+from fractions import Fraction
+
+METRIC = "QD LU n=2048 time vs native-QD GPU LU; Ozaki-II GEMM GOPS & % INT8 MFMA peak"
+PEAK_HBM_GBS = 8000.0
+PEAK_INT8_TOPS = 5000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def correct_bits(x_np):
+    """min_i -log2 |x_i - 1| computed exactly (no binary64 underflow)."""
+    worst = None
+    for row in x_np.reshape(-1, x_np.shape[-1]):
+        v = sum((Fraction(float(c)) for c in row), Fraction(0)) - 1
+        if v == 0:
+            continue
+        v = abs(v)
+        bits = v.denominator.bit_length() - v.numerator.bit_length()
+        worst = bits if worst is None else min(worst, bits)
+    return worst if worst is not None else 9999
+
+
+def schur_shapes(n, b):
+    out = []
+    for k in range(0, n, b):
+        kb = min(b, n - k)
+        if k + kb < n:
+            out.append((n - k - kb, kb))
+    return out
+
+
+def op_counts(n, b):
+    """Counts used to scale the oracle sample: panel + U12-solve multiply-
+    subtracts, and Schur-update element x inner-index products."""
+    P = 0.0
+    U = 0.0
+    for k in range(0, n, b):
+        kb = min(b, n - k)
+        nr = n - k
+        m2 = n - k - kb
+        P += nr * kb * kb / 2.0 + m2 * kb * kb / 2.0
+        U += float(m2) * m2 * kb
+    return P, U
+
+
+def cpu_baseline(n_target, nc, b, n_sample):
+    import oracle as O
+    import workloads as W
+    A = W.lotkin(n_sample, nc)
+    rhs = W.rhs_ones(A)
+    t0 = time.perf_counter()
+    LU, ipiv, info, (tp, tu) = O.getrf(A, b, O.METHOD_OZAKI)
+    t1 = time.perf_counter()
+    O.getrs(LU, ipiv, rhs)
+    t2 = time.perf_counter()
+    Ps, Us = op_counts(n_sample, b)
+    Pt, Ut = op_counts(n_target, b)
+    scale_s = (n_target / n_sample) ** 2
+    est = tp * Pt / Ps + tu * (Ut / Us if Us else 0.0) + (t2 - t1) * scale_s
+    return {
+        "value": est, "unit": "s", "cores": os.cpu_count(), "kind": "oracle",
+        "sample": (f"full oracle getrf+getrs of the QD Lotkin matrix at n={n_sample}, b={b} "
+                   f"({t2 - t0:.1f} s: panel+solve {tp:.1f} s, update {tu:.1f} s, getrs "
+                   f"{t2 - t1:.1f} s), scaled to n={n_target} by panel op counts "
+                   f"({Pt / Ps:.1f}x), Schur op counts ({Ut / max(Us, 1):.1f}x) and n^2 for getrs"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--nc", type=int, default=4)
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--native-steps", type=int, default=1)
+    ap.add_argument("--no-native", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-n", type=int, default=1024)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the LU would shard 2D block-cyclic; see DESIGN.md). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2609_29554_amd as Z
+    import workloads as W
+
+    n, nc, b = args.n, args.nc, args.block
+    log(f"generating Lotkin n={n} nc={nc}")
+    A0 = W.lotkin(n, nc)
+    rhs0 = W.rhs_ones(A0)
+    ctx = Z.Context(0)
+    dev = torch.device("cuda", 0)
+    dA0 = torch.from_numpy(A0).to(dev)
+    db0 = torch.from_numpy(rhs0).to(dev)
+    dA = torch.empty_like(dA0)
+    dx = torch.empty_like(db0)
+    ctx.reserve(nc, 0, 0, 0, n, Z.make_opts(block=b))
+
+    def step(method, blk):
+        dA.copy_(dA0)
+        dx.copy_(db0)
+        ipiv, info = ctx.getrf(dA, block=blk, method=method)
+        ctx.getrs(dA, ipiv, dx)
+        return ipiv, info
+
+    log("warmup")
+    for _ in range(args.warmup):
+        step(Z.METHOD_OZAKI, b)
+    ctx.sync_check()
+    ctx.set_profiling(True)
+    ctx.profile_read()
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ipiv, info = step(Z.METHOD_OZAKI, b)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.set_profiling(False)
+    ctx.sync_check()
+    sec = (t1 - t0) / args.steps
+    info_v = int(info.cpu()[0])
+    bits = correct_bits(dx.cpu().numpy())
+    log(f"ozaki step {sec * 1e3:.2f} ms, info={info_v}, correct bits={bits}")
+
+    K = args.steps
+    stages = {k: {"ms_per_step": v[0] / K, "launches_per_step": v[1] / K} for k, v in prof.items()
+              if v[1]}
+
+    def roof(name, bound):
+        ms, launches, by, ops = prof[name]
+        if not launches or ms <= 0:
+            return None
+        per_launch_ms = ms / launches
+        if bound == "mfma":
+            achieved = ops / launches / (per_launch_ms * 1e-3) / 1e12
+            return {"bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_TOPS,
+                    "unit": "TOP/s", "frac": achieved / PEAK_INT8_TOPS, "traffic": None,
+                    "kernel": name, "avg_launch_ms": per_launch_ms, "launches": launches / K}
+        achieved = by / launches / (per_launch_ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": name,
+                "avg_launch_ms": per_launch_ms, "launches": launches / K}
+
+    rooflines = {"gemm": roof("gemm", "mfma"), "producer": roof("producer", "hbm"),
+                 "consumer": roof("consumer", "hbm")}
+    ozk_ms = {k: prof[k][0] for k in ("producer", "gemm", "consumer")}
+    dominant = max(ozk_ms, key=lambda k: ozk_ms[k])
+    schur_ms = sum(prof[k][0] for k in ("exponents", "producer", "gemm", "consumer")) / K
+    gemm_ms, gemm_ops = prof["gemm"][0], prof["gemm"][3]
+    gops = gemm_ops / (gemm_ms * 1e-3) / 1e9 if gemm_ms > 0 else None
+
+    native = None
+    if not args.no_native:
+        nat = {}
+        for label, blk in (("blocked_naive", b), ("unblocked", 1)):
+            log(f"native {label}")
+            step(Z.METHOD_NAIVE, blk)          # warm
+            torch.cuda.synchronize()
+            ctx.set_profiling(True)
+            ctx.profile_read()
+            tt0 = time.perf_counter()
+            for _ in range(args.native_steps):
+                step(Z.METHOD_NAIVE, blk)
+            torch.cuda.synchronize()
+            tt1 = time.perf_counter()
+            p2 = ctx.profile_read()
+            ctx.set_profiling(False)
+            nat[label] = {"s": (tt1 - tt0) / args.native_steps,
+                          "update_ms": p2["naive_update"][0] / args.native_steps,
+                          "panel_ms": p2["panel"][0] / args.native_steps}
+            log(f"native {label}: {nat[label]['s'] * 1e3:.1f} ms")
+        best = min(nat.values(), key=lambda v: v["s"])["s"]
+        native = {**nat, "best_s": best, "speedup_vs_native": best / sec}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(n, nc, b, args.cpu_sample_n)
+
+    out = {
+        "metric": METRIC,
+        "value": sec,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64x4+i8",
+        "data": "synthetic",
+        "config": {"workload": f"Lotkin quad-double LU n={n} b={b} (getrf+getrs), Ozaki-II INT8",
+                   "n": n, "nc": nc, "block": b, "backend": "int8"},
+        "roofline": rooflines[dominant],
+        "rooflines": rooflines,
+        "cpu_baseline": cpu,
+        "native_qd_lu": native,
+        "schur_update_ms": schur_ms,
+        "gemm_gops": gops,
+        "gemm_frac_int8_peak": (gops / 1e3 / PEAK_INT8_TOPS) if gops else None,
+        "stages": stages,
+        "info": info_v,
+        "correct_bits": bits,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -125,6 +125,19 @@ ozII_status ozII_getrs(ozII_handle h, int32_t nc, int64_t n, int64_t nrhs, const
  * a kernel (a grid barrier that did not complete). */
 ozII_status ozII_sync_check(ozII_handle h);
 
+/* Per-stage timing.  When on, every kernel launch of the library is
+ * bracketed by HIP events recorded on the handle's stream; ozII_profile_read
+ * waits for the stream and returns, per stage, the summed event time [ms],
+ * the number of launches, and the algorithmic bytes and operations of those
+ * launches (what the method itself must move / compute), then clears the
+ * record.  Stages: 0 exponents, 1 residue producer, 2 modular GEMM,
+ * 3 CRT + rounding + update, 4 panel, 5 row interchanges, 6 U12 solve,
+ * 7 native expansion update, 8 getrs.  Arrays have nstages entries (any may
+ * be null). */
+ozII_status ozII_set_profiling(ozII_handle h, int32_t on);
+ozII_status ozII_profile_read(ozII_handle h, int32_t nstages, double *ms, int64_t *launches,
+                              double *bytes, double *ops);
+
 const char *ozII_status_string(ozII_status s);
 const char *ozII_last_error(ozII_handle h);
 

@@ -41,7 +41,11 @@ _i32 = C.c_int32
 
 EXPORTED = ["ozII_create", "ozII_destroy", "ozII_set_stream", "ozII_plan_query", "ozII_reserve",
             "ozII_gemm", "ozII_gemm_stages", "ozII_gemm_stage_dims", "ozII_getrf", "ozII_getrs",
-            "ozII_sync_check", "ozII_status_string", "ozII_last_error"]
+            "ozII_sync_check", "ozII_set_profiling", "ozII_profile_read", "ozII_status_string",
+            "ozII_last_error"]
+
+STAGES = ["exponents", "producer", "gemm", "consumer", "panel", "laswp", "trsm", "naive_update",
+          "getrs"]
 
 
 def lib():
@@ -67,6 +71,8 @@ def lib():
         L.ozII_getrf.argtypes = [_p, _i32, _i64, _p, _i64, _p, _p, OP]
         L.ozII_getrs.argtypes = [_p, _i32, _i64, _i64, _p, _i64, _p, _p, _i64]
         L.ozII_sync_check.argtypes = [_p]
+        L.ozII_set_profiling.argtypes = [_p, _i32]
+        L.ozII_profile_read.argtypes = [_p, _i32, _p, _p, _p, _p]
         L.ozII_status_string.argtypes = [C.c_int]
         L.ozII_status_string.restype = C.c_char_p
         L.ozII_last_error.argtypes = [_p]
@@ -224,6 +230,20 @@ class Context:
 
     def sync_check(self):
         self._call(lib().ozII_sync_check(self._h))
+
+    def set_profiling(self, on: bool):
+        self._call(lib().ozII_set_profiling(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        """Per-stage {name: (ms, launches, algorithmic bytes, algorithmic ops)}
+        since the last read (waits for the stream)."""
+        n = len(STAGES)
+        ms = (C.c_double * n)()
+        la = (C.c_int64 * n)()
+        by = (C.c_double * n)()
+        op = (C.c_double * n)()
+        self._call(lib().ozII_profile_read(self._h, n, ms, la, by, op))
+        return {STAGES[i]: (ms[i], la[i], by[i], op[i]) for i in range(n)}
 
 
 def unfragment(planes, n_planes: int, noutp: int, Kp: int):

@@ -17,37 +17,56 @@
 namespace {
 
 // ---------------------------------------------------------------------------
-// Grid-wide barrier for the cooperative panel kernel.  Every workgroup is
-// co-resident (cooperative launch); the wait is still bounded so that a
-// broken invariant ends in an error flag, never in a hang.
+// Split-phase grid barrier for the cooperative panel kernel.  Every
+// workgroup owns one arrival flag on its own 128-byte line; arrive() makes the
+// workgroup's global writes visible (agent-scope release) and stores the
+// epoch in its flag; wait() polls every flag (one per thread) and acquires.
+// Between the two calls a workgroup may keep working on data nobody else
+// reads.  Waits are bounded: a timeout raises the sticky error flag, after
+// which every later wait returns at once, so a broken invariant ends the
+// kernel quickly instead of hanging it.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void grid_barrier(uint32_t *bar, uint32_t nblocks, int *err) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+constexpr int FLAG_STRIDE = 32;  // uint32 per 128-byte line
+
+__device__ __forceinline__ void bar_arrive(uint32_t *flags, uint32_t epoch) {
+  // every wave waits for its own global stores (s_waitcnt vmcnt(0)): the
+  // workgroup barrier alone does not, and the release below only covers the
+  // L2, so the data must have reached it before the flag is written
+  __builtin_amdgcn_s_waitcnt(0x0F70);
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t *count = bar, *gen = bar + 1;
-    const uint32_t g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t arrived =
-        __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == nblocks - 1) {
-      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      // bounded wait; once any barrier has timed out every later one returns
-      // at once, so a broken invariant costs one timeout, not one per column
-      uint64_t spins = 0;
-      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > (1ull << 24)) {
-          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(flags + blockIdx.x * FLAG_STRIDE, epoch, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Returns false when the wait failed (timeout now or earlier); the caller
+// must then stop using data published by other workgroups.
+__device__ __forceinline__ bool bar_wait(uint32_t *flags, uint32_t nblocks, uint32_t epoch,
+                                         int *err) {
+  __shared__ int s_fail;
+  if (threadIdx.x < nblocks) {
+    // bounded by the 100 MHz real-time counter: about one second
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    uint32_t spins = 0;
+    // flags only grow: a workgroup that already arrived for a later epoch
+    // has also arrived for this one
+    while ((int32_t)(__hip_atomic_load(flags + threadIdx.x * FLAG_STRIDE, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT) - epoch) < 0) {
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+      if ((++spins & 63u) == 0 && __builtin_amdgcn_s_memrealtime() - t0 > 100000000ull) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
       }
     }
   }
   __syncthreads();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (threadIdx.x == 0)
+    s_fail = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+  __syncthreads();
+  return !s_fail;
 }
 
 // ---------------------------------------------------------------------------
@@ -55,18 +74,22 @@ __device__ __forceinline__ void grid_barrier(uint32_t *bar, uint32_t nblocks, in
 // physical rows k + w*R .. k + w*R + R - 1 and keeps them in LDS for the
 // whole panel.  Rows are never moved during the panel: the row permutation
 // is tracked in LDS (position -> physical row and back, every workgroup
-// keeping an identical copy) and applied once afterwards.  Per column:
-//   1. every workgroup publishes its best candidate (key, position, row data)
-//      in a double-buffered table; grid barrier;
-//   2. every workgroup reduces the table identically (largest |value|, ties
-//      to the lowest position, i.e. LAPACK's i?amax on the permuted column);
-//   3. owners of active rows divide by the pivot and apply the rank-1 update
-//      to the rest of the panel row; the next column's candidate is formed.
+// keeping an identical copy) and applied once afterwards.  Per column j:
+//   1. wait for every workgroup's candidate for column j (largest |value| in
+//      its active rows, ties to the lowest position) and reduce the table
+//      identically everywhere: the winner is LAPACK's i?amax on the permuted
+//      column;
+//   2. divide the active rows by the pivot, update column j+1, pick the local
+//      candidate for column j+1, finish that row's update and publish it
+//      (the critical path), then arrive;
+//   3. update the remaining columns of the other active rows while the other
+//      workgroups arrive.
+// Every element still receives its multiply-subtracts in column order.
 // ---------------------------------------------------------------------------
 template <int NC>
 __global__ __launch_bounds__(256) void k_panel(double *A, int64_t lda, int64_t n, int64_t k,
                                                int kb, int R, int64_t *ipiv, int32_t *info,
-                                               uint32_t *bar, int *err, double *ckey, int *cpos,
+                                               uint32_t *flags, int *err, double *ckey, int *cpos,
                                                int *cphys, double *crow, int *perm_out,
                                                int *moved, int *nmoved) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -79,16 +102,17 @@ __global__ __launch_bounds__(256) void k_panel(double *A, int64_t lda, int64_t n
   __shared__ double rkey[256][NC];
   __shared__ int rpos[256], ridx[256];
   __shared__ uint32_t active;
-  __shared__ int s_info, s_wi, s_ppos, s_pphys, s_zero;
+  __shared__ int s_info, s_wi, s_ppos, s_pphys, s_zero, s_best;
 
   const int r0 = wg * R;
   const int cnt = r0 < nr ? (nr - r0 < R ? nr - r0 : R) : 0;
+  auto RW = [&](int r, int c) { return rows + ((size_t)r * kb + c) * NC; };
 
   for (int idx = tid; idx < cnt * kb; idx += 256) {
     const int r = idx % cnt, c = idx / cnt;
     const double *src = A + ((k + r0 + r) + (k + c) * lda) * NC;
 #pragma unroll
-    for (int q = 0; q < NC; ++q) rows[((size_t)r * kb + c) * NC + q] = src[q];
+    for (int q = 0; q < NC; ++q) RW(r, c)[q] = src[q];
   }
   for (int p = tid; p < nr; p += 256) {
     sperm[p] = p;
@@ -100,16 +124,16 @@ __global__ __launch_bounds__(256) void k_panel(double *A, int64_t lda, int64_t n
   }
   __syncthreads();
 
-  // publish the local candidate for column c into buffer buf
-  auto publish = [&](int c, int buf) {
+  // local candidate for column c among the active rows (thread 0), result in
+  // s_best (local row or -1)
+  auto pick = [&](int c) {
     if (tid == 0) {
       int best = -1;
       double bk[NC];
       for (int r = 0; r < cnt; ++r) {
         if (!((active >> r) & 1u)) continue;
         double x[NC];
-#pragma unroll
-        for (int q = 0; q < NC; ++q) x[q] = rows[((size_t)r * kb + c) * NC + q];
+        ozx::load<NC>(RW(r, c), x);
         bool take = best < 0;
         if (!take) {
           if (ozx::abs_greater<NC>(x, bk)) take = true;
@@ -121,35 +145,40 @@ __global__ __launch_bounds__(256) void k_panel(double *A, int64_t lda, int64_t n
           for (int q = 0; q < NC; ++q) bk[q] = x[q];
         }
       }
+      s_best = best;
+    }
+    __syncthreads();
+  };
+  // publish the candidate of column c (row s_best, columns c..kb-1) into buffer
+  auto publish = [&](int c, int buf) {
+    const int best = s_best;
+    if (tid == 0) {
       if (best >= 0) {
 #pragma unroll
-        for (int q = 0; q < NC; ++q) ckey[((size_t)buf * G + wg) * NC + q] = bk[q];
+        for (int q = 0; q < NC; ++q) ckey[((size_t)buf * G + wg) * NC + q] = RW(best, c)[q];
         cpos[buf * G + wg] = sinv[r0 + best];
         cphys[buf * G + wg] = r0 + best;
       } else {
         cphys[buf * G + wg] = -1;
         cpos[buf * G + wg] = 0x7fffffff;
       }
-      ridx[0] = best;
     }
-    __syncthreads();
-    const int best = ridx[0];
     if (best >= 0) {
       for (int idx = tid; idx < (kb - c) * NC; idx += 256)
-        crow[((size_t)buf * G + wg) * kb * NC + (size_t)c * NC + idx] =
-            rows[((size_t)best * kb + c) * NC + idx];
+        crow[((size_t)buf * G + wg) * kb * NC + (size_t)c * NC + idx] = RW(best, c)[idx];
     }
-    __syncthreads();
   };
 
+  pick(0);
   publish(0, 0);
+  bar_arrive(flags, 1u);
 
   for (int j = 0; j < kb; ++j) {
     const int buf = j & 1;
-    grid_barrier(bar, (uint32_t)G, err);
+    if (!bar_wait(flags, (uint32_t)G, (uint32_t)(j + 1), err)) return;
     // reduce the candidate table (identically in every workgroup)
     {
-      int gi = tid;
+      const int gi = tid;
       if (gi < G && cphys[buf * G + gi] >= 0) {
 #pragma unroll
         for (int q = 0; q < NC; ++q) rkey[tid][q] = ckey[((size_t)buf * G + gi) * NC + q];
@@ -192,7 +221,7 @@ __global__ __launch_bounds__(256) void k_panel(double *A, int64_t lda, int64_t n
         const int wi = ridx[0];
         s_wi = wi;
         s_ppos = rpos[0];
-        s_pphys = cphys[buf * G + wi];
+        s_pphys = wi >= 0 ? cphys[buf * G + wi] : -1;
         bool z = true;
 #pragma unroll
         for (int q = 0; q < NC; ++q) z = z && (rkey[0][q] == 0.0);
@@ -201,7 +230,11 @@ __global__ __launch_bounds__(256) void k_panel(double *A, int64_t lda, int64_t n
       __syncthreads();
     }
     const int wi = s_wi, ppos = s_ppos, pphys = s_pphys, zero = s_zero;
-    // pivot row (columns j .. kb-1) into LDS
+    // an empty or inconsistent table can only follow a failed barrier
+    if (wi < 0 || ppos < j || ppos >= nr || pphys < 0 || pphys >= nr) {
+      if (tid == 0) __hip_atomic_store(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
     for (int idx = tid; idx < (kb - j) * NC; idx += 256)
       piv[(size_t)j * NC + idx] = crow[((size_t)buf * G + wi) * kb * NC + (size_t)j * NC + idx];
     if (tid == 0) {
@@ -215,40 +248,66 @@ __global__ __launch_bounds__(256) void k_panel(double *A, int64_t lda, int64_t n
       if (wg == 0) ipiv[k + j] = k + ppos;
     }
     __syncthreads();
+    const bool last = j + 1 >= kb;
     if (!zero) {
-      const double *pv = piv + (size_t)j * NC;
       for (int r = tid; r < cnt; r += 256) {
         if ((active >> r) & 1u) {
           double a[NC], d[NC], l[NC];
-          ozx::load<NC>(rows + ((size_t)r * kb + j) * NC, a);
-          ozx::load<NC>(pv, d);
+          ozx::load<NC>(RW(r, j), a);
+          ozx::load<NC>(piv + (size_t)j * NC, d);
           ozx::div<NC>(a, d, l);
-          ozx::store<NC>(rows + ((size_t)r * kb + j) * NC, l);
-        }
-      }
-      __syncthreads();
-      const int width = kb - j - 1;
-      for (int idx = tid; idx < cnt * width; idx += 256) {
-        const int r = idx % cnt, c = j + 1 + idx / cnt;
-        if ((active >> r) & 1u) {
-          double a[NC], l[NC], u[NC], o[NC];
-          ozx::load<NC>(rows + ((size_t)r * kb + c) * NC, a);
-          ozx::load<NC>(rows + ((size_t)r * kb + j) * NC, l);
-          ozx::load<NC>(piv + (size_t)c * NC, u);
-          ozx::fms<NC>(a, l, u, o);
-          ozx::store<NC>(rows + ((size_t)r * kb + c) * NC, o);
+          ozx::store<NC>(RW(r, j), l);
+          if (!last) {
+            double x[NC], u[NC], o[NC];
+            ozx::load<NC>(RW(r, j + 1), x);
+            ozx::load<NC>(piv + (size_t)(j + 1) * NC, u);
+            ozx::fms<NC>(x, l, u, o);
+            ozx::store<NC>(RW(r, j + 1), o);
+          }
         }
       }
       __syncthreads();
     }
-    if (j + 1 < kb) publish(j + 1, (j + 1) & 1);
+    if (last) break;
+    // candidate for column j+1: finish its row first, publish, arrive
+    pick(j + 1);
+    const int best = s_best;
+    const int width = kb - j - 2;
+    if (!zero && best >= 0) {
+      for (int c = j + 2 + tid; c < kb; c += 256) {
+        double x[NC], l[NC], u[NC], o[NC];
+        ozx::load<NC>(RW(best, c), x);
+        ozx::load<NC>(RW(best, j), l);
+        ozx::load<NC>(piv + (size_t)c * NC, u);
+        ozx::fms<NC>(x, l, u, o);
+        ozx::store<NC>(RW(best, c), o);
+      }
+      __syncthreads();
+    }
+    publish(j + 1, (j + 1) & 1);
+    bar_arrive(flags, (uint32_t)(j + 2));
+    // the rest of the rank-1 update, overlapped with the other arrivals
+    if (!zero && width > 0) {
+      for (int idx = tid; idx < cnt * width; idx += 256) {
+        const int r = idx % cnt, c = j + 2 + idx / cnt;
+        if (((active >> r) & 1u) && r != best) {
+          double a[NC], l[NC], u[NC], o[NC];
+          ozx::load<NC>(RW(r, c), a);
+          ozx::load<NC>(RW(r, j), l);
+          ozx::load<NC>(piv + (size_t)c * NC, u);
+          ozx::fms<NC>(a, l, u, o);
+          ozx::store<NC>(RW(r, c), o);
+        }
+      }
+    }
+    __syncthreads();
   }
   // write the rows back to their physical places
   for (int idx = tid; idx < cnt * kb; idx += 256) {
     const int r = idx % cnt, c = idx / cnt;
     double *dst = A + ((k + r0 + r) + (k + c) * lda) * NC;
 #pragma unroll
-    for (int q = 0; q < NC; ++q) dst[q] = rows[((size_t)r * kb + c) * NC + q];
+    for (int q = 0; q < NC; ++q) dst[q] = RW(r, c)[q];
   }
   if (wg == 0) {
     __shared__ int s_nm;
@@ -365,11 +424,27 @@ __global__ __launch_bounds__(256) void k_trsm_lower_unit(const double *Lp, int64
   }
 }
 
+// rinv[k] = 1 / u_kk (expansion division), one thread per diagonal entry.
+template <int NC>
+__global__ __launch_bounds__(256) void k_recip_diag(const double *LU, int64_t lda, int64_t n,
+                                                    double *rinv) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  double one[NC], d[NC], r[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) one[q] = q == 0 ? 1.0 : 0.0;
+  ozx::load<NC>(LU + (k + k * lda) * NC, d);
+  ozx::div<NC>(one, d, r);
+  ozx::store<NC>(rinv + k * NC, r);
+}
+
 // X <- U^{-1} X for an upper-triangular kb x kb block: for h = kb-1 .. 0,
-// x_h <- x_h / u_hh, then x_i -= u_ih x_h for i < h (descending order).
+// x_h <- x_h * rinv_h (rinv_h = 1/u_hh), then x_i -= u_ih x_h for i < h
+// (descending order).
 template <int NC, int CPB, int RPT>
 __global__ __launch_bounds__(256) void k_trsm_upper(const double *Up, int64_t lda, double *Xp,
-                                                    int64_t ldx, int kb, int64_t ncols) {
+                                                    int64_t ldx, int kb, int64_t ncols,
+                                                    const double *rinv) {
   __shared__ double xs[2][CPB][NC];
   const int tid = threadIdx.x;
   const int64_t cbase = (int64_t)blockIdx.x * CPB;
@@ -393,11 +468,11 @@ __global__ __launch_bounds__(256) void k_trsm_upper(const double *Up, int64_t ld
       for (int rr = 0; rr < RPT; ++rr)
         if (rr == h / 256) {
           double d[NC];
-          ozx::load<NC>(Up + (h + (int64_t)h * lda) * NC, d);
+          ozx::load<NC>(rinv + (int64_t)h * NC, d);
 #pragma unroll
           for (int cc = 0; cc < CPB; ++cc) {
             double o[NC];
-            ozx::div<NC>(x[rr][cc], d, o);
+            ozx::mul<NC>(x[rr][cc], d, o);
 #pragma unroll
             for (int q = 0; q < NC; ++q) {
               x[rr][cc][q] = o[q];
@@ -557,14 +632,14 @@ const void *panel_kernel_ptr(int nc) {
 }
 
 hipError_t launch_panel(int nc, double *A, int64_t lda, int64_t n, int64_t k, int kb, int R, int G,
-                        int64_t *ipiv, int32_t *info, uint32_t *bar, int *err, double *ckey,
+                        int64_t *ipiv, int32_t *info, uint32_t *flags, int *err, double *ckey,
                         int *cpos, int *cphys, double *crow, int *perm, int *moved, int *nmoved,
                         hipStream_t s) {
   const size_t lds = panel_lds_bytes(nc, kb, R, n - k);
   const void *fn = panel_kernel_ptr(nc);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  void *args[] = {&A, &lda, &n, &k, &kb, &R, &ipiv, &info, &bar, &err,
+  void *args[] = {&A, &lda, &n, &k, &kb, &R, &ipiv, &info, &flags, &err,
                   &ckey, &cpos, &cphys, &crow, &perm, &moved, &nmoved};
   return hipLaunchCooperativeKernel(fn, dim3(G), dim3(256), args, (unsigned)lds, s);
 }
@@ -597,15 +672,15 @@ hipError_t launch_laswp(int nc, double *A, int64_t lda, int64_t k, int64_t c0, i
 template <int NC>
 static void trsm_l(int kb, dim3 g, hipStream_t s, const double *L, int64_t lda, double *X,
                    int64_t ldx, int64_t ncols) {
-  if (kb <= 256) hipLaunchKernelGGL((k_trsm_lower_unit<NC, 4, 1>), g, dim3(256), 0, s, L, lda, X, ldx, kb, ncols);
-  else hipLaunchKernelGGL((k_trsm_lower_unit<NC, 2, 2>), g, dim3(256), 0, s, L, lda, X, ldx, kb, ncols);
+  if (kb <= 256) hipLaunchKernelGGL((k_trsm_lower_unit<NC, 2, 1>), g, dim3(256), 0, s, L, lda, X, ldx, kb, ncols);
+  else hipLaunchKernelGGL((k_trsm_lower_unit<NC, 1, 2>), g, dim3(256), 0, s, L, lda, X, ldx, kb, ncols);
 }
 
 hipError_t launch_trsm_lower_unit(int nc, const double *L, int64_t lda, double *X, int64_t ldx,
                                   int kb, int64_t ncols, hipStream_t s) {
   if (ncols <= 0 || kb <= 0) return hipSuccess;
   if (kb > 512) return hipErrorInvalidValue;
-  const int cpb = kb <= 256 ? 4 : 2;
+  const int cpb = kb <= 256 ? 2 : 1;
   dim3 g((unsigned)((ncols + cpb - 1) / cpb));
   if (nc == 2) trsm_l<2>(kb, g, s, L, lda, X, ldx, ncols);
   else if (nc == 3) trsm_l<3>(kb, g, s, L, lda, X, ldx, ncols);
@@ -615,20 +690,29 @@ hipError_t launch_trsm_lower_unit(int nc, const double *L, int64_t lda, double *
 
 template <int NC>
 static void trsm_u(int kb, dim3 g, hipStream_t s, const double *U, int64_t lda, double *X,
-                   int64_t ldx, int64_t ncols) {
-  if (kb <= 256) hipLaunchKernelGGL((k_trsm_upper<NC, 4, 1>), g, dim3(256), 0, s, U, lda, X, ldx, kb, ncols);
-  else hipLaunchKernelGGL((k_trsm_upper<NC, 2, 2>), g, dim3(256), 0, s, U, lda, X, ldx, kb, ncols);
+                   int64_t ldx, int64_t ncols, const double *rinv) {
+  if (kb <= 256) hipLaunchKernelGGL((k_trsm_upper<NC, 1, 1>), g, dim3(256), 0, s, U, lda, X, ldx, kb, ncols, rinv);
+  else hipLaunchKernelGGL((k_trsm_upper<NC, 1, 2>), g, dim3(256), 0, s, U, lda, X, ldx, kb, ncols, rinv);
 }
 
 hipError_t launch_trsm_upper(int nc, const double *U, int64_t lda, double *X, int64_t ldx, int kb,
-                             int64_t ncols, hipStream_t s) {
+                             int64_t ncols, const double *rinv, hipStream_t s) {
   if (ncols <= 0 || kb <= 0) return hipSuccess;
   if (kb > 512) return hipErrorInvalidValue;
-  const int cpb = kb <= 256 ? 4 : 2;
-  dim3 g((unsigned)((ncols + cpb - 1) / cpb));
-  if (nc == 2) trsm_u<2>(kb, g, s, U, lda, X, ldx, ncols);
-  else if (nc == 3) trsm_u<3>(kb, g, s, U, lda, X, ldx, ncols);
-  else trsm_u<4>(kb, g, s, U, lda, X, ldx, ncols);
+  dim3 g((unsigned)ncols);
+  if (nc == 2) trsm_u<2>(kb, g, s, U, lda, X, ldx, ncols, rinv);
+  else if (nc == 3) trsm_u<3>(kb, g, s, U, lda, X, ldx, ncols, rinv);
+  else trsm_u<4>(kb, g, s, U, lda, X, ldx, ncols, rinv);
+  return hipGetLastError();
+}
+
+hipError_t launch_recip_diag(int nc, const double *LU, int64_t lda, int64_t n, double *rinv,
+                             hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  dim3 g((unsigned)((n + 255) / 256));
+  if (nc == 2) hipLaunchKernelGGL(k_recip_diag<2>, g, dim3(256), 0, s, LU, lda, n, rinv);
+  else if (nc == 3) hipLaunchKernelGGL(k_recip_diag<3>, g, dim3(256), 0, s, LU, lda, n, rinv);
+  else hipLaunchKernelGGL(k_recip_diag<4>, g, dim3(256), 0, s, LU, lda, n, rinv);
   return hipGetLastError();
 }
 

@@ -20,6 +20,19 @@ namespace {
 
 using ozk::DevPlan;
 
+enum {
+  OZ_STAGE_EXP = 0,
+  OZ_STAGE_PRODUCER = 1,
+  OZ_STAGE_GEMM = 2,
+  OZ_STAGE_CONSUMER = 3,
+  OZ_STAGE_PANEL = 4,
+  OZ_STAGE_LASWP = 5,
+  OZ_STAGE_TRSM = 6,
+  OZ_STAGE_NAIVE = 7,
+  OZ_STAGE_GETRS = 8,
+  OZ_NSTAGES = 9
+};
+
 // ---------------------------------------------------------------------------
 // Plan rule (Sec. 3.2, paragraph "Determining w and N"):
 //   slack = ceil(log2 2K) + 16 + g_ex; for S = 1, 2, ...:
@@ -201,6 +214,7 @@ struct ozII_ctx {
   size_t ws_bytes = 0;
   // panel scratch
   uint32_t *bar = nullptr;
+  uint32_t *flags = nullptr;  // panel arrival flags, one 128-byte line per workgroup
   int *err = nullptr;
   double *ckey = nullptr;
   int *cpos = nullptr, *cphys = nullptr;
@@ -208,7 +222,20 @@ struct ozII_ctx {
   int *perm = nullptr, *moved = nullptr, *nmoved = nullptr;
   int64_t panel_n = 0;
   int panel_kb = 0;
+  // getrs: reciprocals of the diagonal of U
+  double *rinv = nullptr;
+  int64_t rinv_cap = 0;
   std::map<std::tuple<int, int64_t, int, int, int, int>, std::pair<HostPlan, DevPlan *>> plans;
+  // per-stage profiling (HIP events on the handle's stream)
+  struct ProfRec {
+    int stage;
+    hipEvent_t a, b;
+    double bytes, ops;
+  };
+  bool profiling = false;
+  std::vector<ProfRec> prof;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
 };
 
 namespace {
@@ -221,6 +248,32 @@ ozII_status fail(ozII_ctx *h, ozII_status s, const std::string &msg) {
 ozII_status hip_fail(ozII_ctx *h, hipError_t e, const char *where) {
   return fail(h, OZII_EHIP, std::string(where) + ": " + hipGetErrorString(e));
 }
+
+hipEvent_t prof_event(ozII_ctx *h) {
+  if (h->pool_used == h->pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->pool.push_back(e);
+  }
+  return h->pool[h->pool_used++];
+}
+
+// Bracket one launch with events when profiling is on.
+struct ProfScope {
+  ozII_ctx *h;
+  int idx = -1;
+  ProfScope(ozII_ctx *hh, int stage, double bytes, double ops) : h(hh) {
+    if (!h->profiling) return;
+    hipEvent_t a = prof_event(h), b = prof_event(h);
+    if (!a || !b) return;
+    hipEventRecord(a, h->stream);
+    h->prof.push_back({stage, a, b, bytes, ops});
+    idx = (int)h->prof.size() - 1;
+  }
+  ~ProfScope() {
+    if (idx >= 0) hipEventRecord(h->prof[idx].b, h->stream);
+  }
+};
 
 ozII_status get_plan(ozII_ctx *h, int p, int64_t K, const ozII_opts *o, const HostPlan **hp,
                      const DevPlan **dp) {
@@ -317,6 +370,7 @@ ozII_status ensure_panel(ozII_ctx *h, int64_t n, int kb) {
       h->nmoved = (int *)(h->bar + 8);
     }
   }
+  if (e == hipSuccess && !h->flags) e = hipMalloc((void **)&h->flags, 128 * G);
   if (e == hipSuccess) e = hipMalloc((void **)&h->ckey, sizeof(double) * 2 * G * 4);
   if (e == hipSuccess) e = hipMalloc((void **)&h->cpos, sizeof(int) * 2 * G);
   if (e == hipSuccess) e = hipMalloc((void **)&h->cphys, sizeof(int) * 2 * G);
@@ -364,14 +418,31 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
   uint8_t *tpl = (uint8_t *)(h->ws + L.off_tpl);
   hipStream_t s = h->stream;
   hipError_t e;
-  if ((e = ozl::launch_exponents(nc, A, lda, M, K, 1, ea, s)) != hipSuccess) return hip_fail(h, e, "exponents(A)");
-  if ((e = ozl::launch_exponents(nc, B, ldb, K, N, 0, eb, s)) != hipSuccess) return hip_fail(h, e, "exponents(B)");
-  if ((e = ozl::launch_producer(nc, hp->nwx, hp->nh, A, lda, 1, M, L.Mp, K, L.Kp, ea, dp, pa, L.planeA, s)) != hipSuccess)
-    return hip_fail(h, e, "producer(A)");
-  if ((e = ozl::launch_producer(nc, hp->nwx, hp->nh, B, ldb, 0, N, L.Np, K, L.Kp, eb, dp, pb, L.planeB, s)) != hipSuccess)
-    return hip_fail(h, e, "producer(B)");
-  if ((e = ozl::launch_gemm_i8(pa, pb, tpl, dp, hp->ng, hp->nmod, L.Mp, L.Np, L.Kp, L.planeA, L.planeB, s)) != hipSuccess)
-    return hip_fail(h, e, "gemm_i8");
+  const double pairs = (double)hp->nmod * [&] {
+    int np = 0;
+    for (int g = hp->g0; g <= 2 * hp->S - 2; ++g)
+      for (int ta = 0; ta < hp->S; ++ta)
+        if (g - ta >= 0 && g - ta < hp->S) ++np;
+    return np;
+  }();
+  {
+    ProfScope ps(h, OZ_STAGE_EXP, 8.0 * nc * (double)(M * K + K * N), 0);
+    if ((e = ozl::launch_exponents(nc, A, lda, M, K, 1, ea, s)) != hipSuccess) return hip_fail(h, e, "exponents(A)");
+    if ((e = ozl::launch_exponents(nc, B, ldb, K, N, 0, eb, s)) != hipSuccess) return hip_fail(h, e, "exponents(B)");
+  }
+  {
+    ProfScope ps(h, OZ_STAGE_PRODUCER, (double)(M + N) * K * (8.0 * nc + (double)hp->S * hp->nmod), 0);
+    if ((e = ozl::launch_producer(nc, hp->nwx, hp->nh, A, lda, 1, M, L.Mp, K, L.Kp, ea, dp, pa, L.planeA, s)) != hipSuccess)
+      return hip_fail(h, e, "producer(A)");
+    if ((e = ozl::launch_producer(nc, hp->nwx, hp->nh, B, ldb, 0, N, L.Np, K, L.Kp, eb, dp, pb, L.planeB, s)) != hipSuccess)
+      return hip_fail(h, e, "producer(B)");
+  }
+  {
+    ProfScope ps(h, OZ_STAGE_GEMM, (double)hp->S * hp->nmod * (double)(M + N) * K + (double)hp->ng * hp->nmod * M * N,
+                 2.0 * (double)M * N * K * pairs);
+    if ((e = ozl::launch_gemm_i8(pa, pb, tpl, dp, hp->ng, hp->nmod, L.Mp, L.Np, L.Kp, L.planeA, L.planeB, s)) != hipSuccess)
+      return hip_fail(h, e, "gemm_i8");
+  }
   if (ea_out && (e = hipMemcpyAsync(ea_out, ea, 4 * M, hipMemcpyDeviceToDevice, s)) != hipSuccess) return hip_fail(h, e, "copy ea");
   if (eb_out && (e = hipMemcpyAsync(eb_out, eb, 4 * N, hipMemcpyDeviceToDevice, s)) != hipSuccess) return hip_fail(h, e, "copy eb");
   if (pa_out && (e = hipMemcpyAsync(pa_out, pa, (size_t)hp->S * hp->nmod * L.planeA, hipMemcpyDeviceToDevice, s)) != hipSuccess)
@@ -382,8 +453,11 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
     return hip_fail(h, e, "copy tpl");
   if (sbar_out && (e = ozl::launch_crt_export(tpl, L.Mp, L.Np, M, N, dp, sbar_out, nlimb, s)) != hipSuccess)
     return hip_fail(h, e, "crt_export");
-  if ((e = ozl::launch_consumer(nc, hp->nwc, tpl, L.Mp, L.Np, C, ldc, M, N, ea, eb, dp, mode, s)) != hipSuccess)
-    return hip_fail(h, e, "consumer");
+  {
+    ProfScope ps(h, OZ_STAGE_CONSUMER, (double)M * N * ((double)hp->ng * hp->nmod + 8.0 * nc * (mode ? 2 : 1)), 0);
+    if ((e = ozl::launch_consumer(nc, hp->nwc, tpl, L.Mp, L.Np, C, ldc, M, N, ea, eb, dp, mode, s)) != hipSuccess)
+      return hip_fail(h, e, "consumer");
+  }
   return OZII_OK;
 }
 
@@ -409,8 +483,11 @@ ozII_status ozII_destroy(ozII_handle h) {
   hipStreamSynchronize(h->stream);
   if (h->ws) hipFree(h->ws);
   for (auto &kv : h->plans) hipFree(kv.second.second);
+  for (auto ev : h->pool) hipEventDestroy(ev);
+  if (h->rinv) hipFree(h->rinv);
   if (h->bar) {
     hipFree(h->bar);
+    hipFree(h->flags);
     hipFree(h->ckey);
     hipFree(h->cpos);
     hipFree(h->cphys);
@@ -546,18 +623,30 @@ ozII_status ozII_getrf(ozII_handle h, int32_t nc, int64_t n, double *A, int64_t 
       if (G <= 0) return fail(h, OZII_EUNSUPPORTED, "panel kernel cannot be resident");
     }
     G = (int)std::min<int64_t>(G, (nr + R - 1) / R);
-    if ((e = ozl::launch_fill_int((int *)h->bar, 0, 2, s)) != hipSuccess) return hip_fail(h, e, "fill bar");
-    if ((e = ozl::launch_panel(nc, A, lda, n, k, kb, R, G, ipiv, info, h->bar, h->err, h->ckey,
-                               h->cpos, h->cphys, h->crow, h->perm, h->moved, h->nmoved, s)) != hipSuccess)
-      return hip_fail(h, e, "panel");
-    if ((e = ozl::launch_laswp(nc, A, lda, k, 0, n, h->perm, h->moved, h->nmoved, s)) != hipSuccess)
-      return hip_fail(h, e, "laswp");
+    if ((e = ozl::launch_fill_int((int *)h->flags, 0, 32 * 256, s)) != hipSuccess) return hip_fail(h, e, "fill flags");
+    // a panel that stops early leaves no moved rows behind for laswp
+    if ((e = ozl::launch_fill_int(h->nmoved, 0, 1, s)) != hipSuccess) return hip_fail(h, e, "fill nmoved");
+    {
+      ProfScope ps(h, OZ_STAGE_PANEL, 16.0 * nc * (double)nr * kb, (double)nr * kb * kb / 2.0);
+      if ((e = ozl::launch_panel(nc, A, lda, n, k, kb, R, G, ipiv, info, h->flags, h->err, h->ckey,
+                                 h->cpos, h->cphys, h->crow, h->perm, h->moved, h->nmoved, s)) != hipSuccess)
+        return hip_fail(h, e, "panel");
+    }
+    {
+      ProfScope ps(h, OZ_STAGE_LASWP, 32.0 * nc * (double)kb * n, 0);
+      if ((e = ozl::launch_laswp(nc, A, lda, k, 0, n, h->perm, h->moved, h->nmoved, s)) != hipSuccess)
+        return hip_fail(h, e, "laswp");
+    }
     if (k + kb < n) {
       const int64_t m2 = n - k - kb;
       const double *L11 = A + (k + k * lda) * nc;
       double *A12 = A + (k + (k + kb) * lda) * nc;
-      if ((e = ozl::launch_trsm_lower_unit(nc, L11, lda, A12, lda, kb, m2, s)) != hipSuccess)
-        return hip_fail(h, e, "trsm");
+      {
+        ProfScope ps(h, OZ_STAGE_TRSM, 16.0 * nc * (double)kb * m2 + 8.0 * nc * kb * kb / 2.0,
+                     (double)m2 * kb * kb / 2.0);
+        if ((e = ozl::launch_trsm_lower_unit(nc, L11, lda, A12, lda, kb, m2, s)) != hipSuccess)
+          return hip_fail(h, e, "trsm");
+      }
       const double *L21 = A + ((k + kb) + k * lda) * nc;
       double *A22 = A + ((k + kb) + (k + kb) * lda) * nc;
       if (method == OZII_METHOD_OZAKI) {
@@ -565,6 +654,8 @@ ozII_status ozII_getrf(ozII_handle h, int32_t nc, int64_t n, double *A, int64_t 
                        nullptr, nullptr, nullptr, nullptr, 0);
         if (st != OZII_OK) return st;
       } else {
+        ProfScope ps(h, OZ_STAGE_NAIVE, 16.0 * nc * (double)m2 * m2 + 16.0 * nc * (double)m2 * kb,
+                     (double)m2 * m2 * kb);
         if ((e = ozl::launch_naive_gemm(nc, L21, lda, A12, lda, A22, lda, m2, m2, kb, 0, s)) != hipSuccess)
           return hip_fail(h, e, "naive update");
       }
@@ -583,6 +674,20 @@ ozII_status ozII_getrs(ozII_handle h, int32_t nc, int64_t n, int64_t nrhs, const
   if (!LU || !ipiv || !B) return fail(h, OZII_EINVAL, "null pointer");
   hipStream_t s = h->stream;
   hipError_t e;
+  ProfScope ps(h, OZ_STAGE_GETRS, 8.0 * nc * (double)n * n + 16.0 * nc * (double)n * nrhs,
+               (double)n * n * nrhs);
+  if (h->rinv_cap < n * nc) {
+    if (h->rinv) {
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+      hipFree(h->rinv);
+      h->rinv = nullptr;
+      h->rinv_cap = 0;
+    }
+    if (hipMalloc((void **)&h->rinv, sizeof(double) * n * nc) != hipSuccess)
+      return fail(h, OZII_ENOMEM, "getrs scratch allocation failed");
+    h->rinv_cap = n * nc;
+  }
+  if ((e = ozl::launch_recip_diag(nc, LU, lda, n, h->rinv, s)) != hipSuccess) return hip_fail(h, e, "recip diag");
   if ((e = ozl::launch_apply_ipiv(nc, B, ldb, n, nrhs, ipiv, s)) != hipSuccess) return hip_fail(h, e, "apply ipiv");
   const int bs = 256;
   for (int64_t i0 = 0; i0 < n; i0 += bs) {
@@ -599,7 +704,8 @@ ozII_status ozII_getrs(ozII_handle h, int32_t nc, int64_t n, int64_t nrhs, const
   for (int64_t bi = nblk - 1; bi >= 0; --bi) {
     const int64_t j0 = bi * bs;
     const int ib = (int)std::min<int64_t>(bs, n - j0);
-    if ((e = ozl::launch_trsm_upper(nc, LU + (j0 + j0 * lda) * nc, lda, B + j0 * nc, ldb, ib, nrhs, s)) != hipSuccess)
+    if ((e = ozl::launch_trsm_upper(nc, LU + (j0 + j0 * lda) * nc, lda, B + j0 * nc, ldb, ib, nrhs,
+                                    h->rinv + j0 * nc, s)) != hipSuccess)
       return hip_fail(h, e, "backward block");
     if (j0 > 0) {
       if ((e = ozl::launch_naive_gemm(nc, LU + (j0 * lda) * nc, lda, B + j0 * nc, ldb, B, ldb, j0,
@@ -620,6 +726,38 @@ ozII_status ozII_sync_check(ozII_handle h) {
     if (e != hipSuccess) return hip_fail(h, e, "read error flag");
     if (v) return fail(h, OZII_EDEVICE, "a panel grid barrier timed out");
   }
+  return OZII_OK;
+}
+
+ozII_status ozII_set_profiling(ozII_handle h, int32_t on) {
+  if (!h) return OZII_EINVAL;
+  h->profiling = on != 0;
+  return OZII_OK;
+}
+
+ozII_status ozII_profile_read(ozII_handle h, int32_t nstages, double *ms, int64_t *launches,
+                              double *bytes, double *ops) {
+  if (!h || nstages < 0) return OZII_EINVAL;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+  for (int i = 0; i < nstages; ++i) {
+    if (ms) ms[i] = 0;
+    if (launches) launches[i] = 0;
+    if (bytes) bytes[i] = 0;
+    if (ops) ops[i] = 0;
+  }
+  for (auto &r : h->prof) {
+    if (r.stage < 0 || r.stage >= nstages) continue;
+    float t = 0.f;
+    e = hipEventElapsedTime(&t, r.a, r.b);
+    if (e != hipSuccess) return hip_fail(h, e, "hipEventElapsedTime");
+    if (ms) ms[r.stage] += t;
+    if (launches) launches[r.stage] += 1;
+    if (bytes) bytes[r.stage] += r.bytes;
+    if (ops) ops[r.stage] += r.ops;
+  }
+  h->prof.clear();
+  h->pool_used = 0;
   return OZII_OK;
 }
 

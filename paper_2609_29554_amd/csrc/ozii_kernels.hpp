@@ -39,7 +39,9 @@ hipError_t launch_laswp(int nc, double *A, int64_t lda, int64_t k, int64_t c0, i
 hipError_t launch_trsm_lower_unit(int nc, const double *L, int64_t lda, double *X, int64_t ldx,
                                   int kb, int64_t ncols, hipStream_t s);
 hipError_t launch_trsm_upper(int nc, const double *U, int64_t lda, double *X, int64_t ldx, int kb,
-                             int64_t ncols, hipStream_t s);
+                             int64_t ncols, const double *rinv, hipStream_t s);
+hipError_t launch_recip_diag(int nc, const double *LU, int64_t lda, int64_t n, double *rinv,
+                             hipStream_t s);
 hipError_t launch_naive_gemm(int nc, const double *A, int64_t lda, const double *B, int64_t ldb,
                              double *C, int64_t ldc, int64_t M, int64_t N, int64_t K, int desc,
                              hipStream_t s);

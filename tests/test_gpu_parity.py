@@ -84,6 +84,7 @@ LU_CASES = [
     (3, 64, 32, "graded"),
     (4, 129, 64, "graded"),
     (2, 128, 32, "lotkin"),          # the DD Lotkin configuration, n = 128, b = 32
+    (4, 520, 256, "lotkin"),         # wide panel, 174 workgroups, ragged last panel
 ]
 
 

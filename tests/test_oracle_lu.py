@@ -99,10 +99,12 @@ def test_wellconditioned_correct_bits():
 
 
 def test_getrs_solves_triangular_systems_exactly_on_integers():
-    # A = L U with small integer factors: every operation is exact
+    # A = L U with small integer factors and powers of two on the diagonal of
+    # U (exact reciprocals): every operation is exact
     n, nc = 6, 2
     L = np.eye(n)
     U = np.triu(np.arange(1, n * n + 1).reshape(n, n) % 5 + 1.0)
+    U[np.diag_indices(n)] = [1.0, 2.0, 4.0, 0.5, 8.0, 0.25]
     L[np.tril_indices(n, -1)] = [(k % 3) - 1 for k in range(n * (n - 1) // 2)]
     LU = np.zeros((n, n, nc))
     LU[..., 0] = (np.tril(L, -1) + U).T
