@@ -28,17 +28,27 @@ namespace {
 // ---------------------------------------------------------------------------
 // (S1) exponents
 // ---------------------------------------------------------------------------
+// Row maxima: a 2-D grid, each thread scans a chunk of one row and the chunk
+// maxima meet in e[i] through an atomic max (e pre-filled with EXP_ZERO).
+constexpr int ROWEXP_CHUNK = 16;
 template <int NC>
 __global__ __launch_bounds__(256) void k_row_exponents(const double *A, int64_t lda, int64_t rows,
                                                        int64_t cols, int32_t *e) {
-  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= rows) return;
+  const int64_t h0 = (int64_t)blockIdx.y * ROWEXP_CHUNK;
+  const int64_t h1 = h0 + ROWEXP_CHUNK < cols ? h0 + ROWEXP_CHUNK : cols;
   int32_t best = EXP_ZERO;
-  for (int64_t h = 0; h < cols; ++h) {
+  for (int64_t h = h0; h < h1; ++h) {
     int32_t v = exponent_of<NC>(A + (i + h * lda) * NC);
     best = v > best ? v : best;
   }
-  e[i] = best;
+  if (best != EXP_ZERO) atomicMax(e + i, best);
+}
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t cnt) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < cnt) p[t] = v;
 }
 
 template <int NC>
@@ -199,7 +209,7 @@ __global__ __launch_bounds__(256) void k_gemm_i8(const int8_t *__restrict__ pa,
 // ---------------------------------------------------------------------------
 // (S5)+(S6) consumer
 // ---------------------------------------------------------------------------
-template <int NC, int NWC>
+template <int NC, int NWC, int ND>
 __global__ __launch_bounds__(256) void k_consumer(const uint8_t *__restrict__ tpl, int64_t Mp,
                                                   int64_t Np, double *C, int64_t ldc, int64_t M,
                                                   int64_t N, const int32_t *ea, const int32_t *eb,
@@ -214,7 +224,7 @@ __global__ __launch_bounds__(256) void k_consumer(const uint8_t *__restrict__ tp
   const bool zero = ei == EXP_ZERO || ej == EXP_ZERO;
   const int eps = zero ? 0 : pl->w * pl->g0 - (Q - 1 - ei) - (Q - 1 - ej);
   double c[NC];
-  consume_element<NC, NWC>(
+  consume_element<NC, NWC, ND>(
       [&](int gi) { return tpl + ((int64_t)gi * nmod * Np + j) * Mp + i; }, Np * Mp, pl, st, zero,
       eps, c);
   double *dst = C + (i + j * ldc) * NC;
@@ -241,7 +251,7 @@ __global__ __launch_bounds__(256) void k_crt_export(const uint8_t *__restrict__ 
   const int nmod = pl->nmod;
   for (int gi = 0; gi < pl->ng; ++gi) {
     int32_t d[NDCRT];
-    crt_digits(tpl + ((int64_t)gi * nmod * Np + j) * Mp + i, Np * Mp, pl, d);
+    crt_digits<NDCRT>(tpl + ((int64_t)gi * nmod * Np + j) * Mp + i, Np * Mp, pl, d);
     uint64_t *o = out + (((int64_t)gi * N + j) * M + i) * nlimb;
     const uint64_t fill = d[NDCRT - 1] < 0 ? ~0ull : 0ull;
     for (int q = 0; q < nlimb; ++q) {
@@ -267,7 +277,10 @@ hipError_t launch_exponents(int nc, const double *X, int64_t ld, int64_t rows, i
                             int rowwise, int32_t *e, hipStream_t s) {
   if (rowwise) {
     if (rows <= 0) return hipSuccess;
-    dim3 g((unsigned)((rows + 255) / 256));
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, e,
+                       EXP_ZERO, rows);
+    if (cols <= 0) return hipGetLastError();
+    dim3 g((unsigned)((rows + 255) / 256), (unsigned)((cols + ROWEXP_CHUNK - 1) / ROWEXP_CHUNK));
     if (nc == 2) hipLaunchKernelGGL(k_row_exponents<2>, g, dim3(256), 0, s, X, ld, rows, cols, e);
     else if (nc == 3) hipLaunchKernelGGL(k_row_exponents<3>, g, dim3(256), 0, s, X, ld, rows, cols, e);
     else hipLaunchKernelGGL(k_row_exponents<4>, g, dim3(256), 0, s, X, ld, rows, cols, e);
@@ -322,17 +335,20 @@ hipError_t launch_gemm_i8(const int8_t *pa, const int8_t *pb, uint8_t *tpl, cons
   return hipGetLastError();
 }
 
-hipError_t launch_consumer(int nc, int nwc, const uint8_t *tpl, int64_t Mp, int64_t Np, double *C,
-                           int64_t ldc, int64_t M, int64_t N, const int32_t *ea,
+hipError_t launch_consumer(int nc, int nwc, int nd, const uint8_t *tpl, int64_t Mp, int64_t Np,
+                           double *C, int64_t ldc, int64_t M, int64_t N, const int32_t *ea,
                            const int32_t *eb, const DevPlan *pl, int mode, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
   dim3 g((unsigned)((M + 255) / 256), (unsigned)N);
-#define OZ_CONS(NC_, NWC_)                                                                   \
-  hipLaunchKernelGGL((k_consumer<NC_, NWC_>), g, dim3(256), 0, s, tpl, Mp, Np, C, ldc, M, N, \
-                     ea, eb, pl, mode)
-  if (nc == 2) { if (nwc <= 12) OZ_CONS(2, 12); else OZ_CONS(2, 16); }
-  else if (nc == 3) { if (nwc <= 12) OZ_CONS(3, 12); else OZ_CONS(3, 16); }
-  else { if (nwc <= 12) OZ_CONS(4, 12); else OZ_CONS(4, 16); }
+#define OZ_CONS(NC_, NWC_, ND_)                                                             \
+  hipLaunchKernelGGL((k_consumer<NC_, NWC_, ND_>), g, dim3(256), 0, s, tpl, Mp, Np, C, ldc, M, \
+                     N, ea, eb, pl, mode)
+#define OZ_CONS_ND(NC_, NWC_) \
+  do { if (nd <= 18) OZ_CONS(NC_, NWC_, 18); else OZ_CONS(NC_, NWC_, 24); } while (0)
+  if (nc == 2) { if (nwc <= 12) OZ_CONS_ND(2, 12); else OZ_CONS_ND(2, 16); }
+  else if (nc == 3) { if (nwc <= 12) OZ_CONS_ND(3, 12); else OZ_CONS_ND(3, 16); }
+  else { if (nwc <= 12) OZ_CONS_ND(4, 12); else OZ_CONS_ND(4, 16); }
+#undef OZ_CONS_ND
 #undef OZ_CONS
   return hipGetLastError();
 }

@@ -65,7 +65,7 @@ struct HostPlan {
   int64_t K = 0;
   int backend = OZII_BE_INT8;
   int S = 0, w = 0, Q = 0, nmod = 0, g0 = 0, ng = 0;
-  int nwx = 0, nh = 0, nwc = 0;
+  int nwx = 0, nh = 0, nwc = 0, nd = 0;
   double need = 0;
   std::vector<int> mods;
 };
@@ -122,6 +122,13 @@ ozII_status make_plan(int p, int64_t K, const ozII_opts *o, HostPlan &pl, std::s
     pl.nh = (w + 2 + 15) / 16;
     const int sbits = 2 * w + (int)std::ceil(std::log2((double)K * S)) + 2;
     pl.nwc = (sbits + w * (pl.ng - 1) + 1 + 31) / 32;
+    {
+      // 16-bit digits of sum_l t_l M_l < nmod P (one sign bit to spare)
+      double lp = 0.0;
+      for (int i = 0; i < N; ++i) lp += std::log2((double)mods[i]);
+      const int bits = (int)std::ceil(lp + std::log2((double)N)) + 2;
+      pl.nd = ((bits + 15) / 16 + 1) & ~1;
+    }
     if (check_sizes && (pl.nwx > 12 || pl.nh > ozk::NHMAX || pl.nwc > 16 || w > 300)) {
       if (why) *why = "plan exceeds the compiled word sizes";
       return OZII_EUNSUPPORTED;
@@ -455,7 +462,7 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
     return hip_fail(h, e, "crt_export");
   {
     ProfScope ps(h, OZ_STAGE_CONSUMER, (double)M * N * ((double)hp->ng * hp->nmod + 8.0 * nc * (mode ? 2 : 1)), 0);
-    if ((e = ozl::launch_consumer(nc, hp->nwc, tpl, L.Mp, L.Np, C, ldc, M, N, ea, eb, dp, mode, s)) != hipSuccess)
+    if ((e = ozl::launch_consumer(nc, hp->nwc, hp->nd, tpl, L.Mp, L.Np, C, ldc, M, N, ea, eb, dp, mode, s)) != hipSuccess)
       return hip_fail(h, e, "consumer");
   }
   return OZII_OK;

@@ -144,30 +144,32 @@ OZ_HD int32_t centre(uint32_t r, int32_t m) {
 // held in int32 (after carry propagation every digit is in [0, 2^16) except
 // the top one, which carries the sign).
 // ---------------------------------------------------------------------------
-OZ_HD void crt_digits(const uint8_t *t, int64_t stride, const DevPlan *pl, int32_t (&d)[NDCRT]) {
+// ND digits (ND*16 bits) must hold sum_l t_l M_l < nmod P; the plan checks.
+template <int ND = NDCRT>
+OZ_HD void crt_digits(const uint8_t *t, int64_t stride, const DevPlan *pl, int32_t (&d)[ND]) {
 #pragma unroll
-  for (int k = 0; k < NDCRT; ++k) d[k] = 0;
+  for (int k = 0; k < ND; ++k) d[k] = 0;
   double F = 0.0;
   for (int l = 0; l < pl->nmod; ++l) {
     uint32_t tl = t[l * stride];
     F += (double)tl * pl->inv_m[l];
 #pragma unroll
-    for (int k = 0; k < NDCRT; ++k) d[k] += (int32_t)(tl * (uint32_t)pl->Mdig[l][k]);
+    for (int k = 0; k < ND; ++k) d[k] += (int32_t)(tl * (uint32_t)pl->Mdig[l][k]);
   }
   int32_t q = (int32_t)__builtin_floor(F + 0.5);
 #pragma unroll
-  for (int k = 0; k < NDCRT; ++k) d[k] -= q * (int32_t)pl->Pdig[k];
+  for (int k = 0; k < ND; ++k) d[k] -= q * (int32_t)pl->Pdig[k];
   int32_t carry = 0;
 #pragma unroll
-  for (int k = 0; k < NDCRT; ++k) {
+  for (int k = 0; k < ND; ++k) {
     int32_t v = d[k] + carry;
     d[k] = v & 0xffff;
     carry = v >> 16;  // arithmetic
   }
-  // |Sbar| < 2^383, so the digits are the two's complement of Sbar and the top
-  // digit carries the sign; the final carry holds no further information.
+  // |Sbar| < P/2 fits the ND digits, so they are the two's complement of Sbar
+  // and the top digit carries the sign; the final carry holds nothing more.
   (void)carry;
-  d[NDCRT - 1] = (int32_t)(int16_t)(uint16_t)d[NDCRT - 1];
+  d[ND - 1] = (int32_t)(int16_t)(uint16_t)d[ND - 1];
 }
 
 // ---------------------------------------------------------------------------
@@ -351,23 +353,24 @@ OZ_HD void produce_element(const double *src, int mu, const DevPlan *pl, uint32_
 // ---------------------------------------------------------------------------
 constexpr int CST = 33;
 
-template <int NC, int NWC, class TPtr>
+template <int NC, int NWC, int ND, class TPtr>
 OZ_HD void consume_element(TPtr tptr, int64_t pstride, const DevPlan *pl, uint32_t *st, bool zero,
                            int eps, double (&c)[NC]) {
-  static_assert(NDCRT / 2 + NWC + 1 <= CST, "staging too small");
+  static_assert(ND % 2 == 0 && ND <= NDCRT, "digits");
+  static_assert(ND / 2 + NWC + 1 <= CST, "staging too small");
   const int w = pl->w, ng = pl->ng;
   uint32_t cb[NWC];
 #pragma unroll
   for (int k = 0; k < NWC; ++k) cb[k] = 0u;
   for (int gi = 0; gi < ng; ++gi) {
-    int32_t d[NDCRT];
-    crt_digits(tptr(gi), pstride, pl, d);
-    const uint32_t fill = d[NDCRT - 1] < 0 ? 0xffffffffu : 0u;
+    int32_t d[ND];
+    crt_digits<ND>(tptr(gi), pstride, pl, d);
+    const uint32_t fill = d[ND - 1] < 0 ? 0xffffffffu : 0u;
 #pragma unroll
-    for (int k = 0; k < NDCRT / 2; ++k)
+    for (int k = 0; k < ND / 2; ++k)
       st[k] = ((uint32_t)d[2 * k] & 0xffffu) | ((uint32_t)d[2 * k + 1] << 16);
 #pragma unroll
-    for (int k = NDCRT / 2; k < CST; ++k) st[k] = fill;
+    for (int k = ND / 2; k < CST; ++k) st[k] = fill;
     const int off = w * gi, q0 = off >> 5, b0 = off & 31;
     uint32_t carry = 0;
 #pragma unroll

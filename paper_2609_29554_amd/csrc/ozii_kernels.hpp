@@ -21,8 +21,8 @@ hipError_t launch_producer(int nc, int nwx, int nh, const double *X, int64_t ld,
 hipError_t launch_gemm_i8(const int8_t *pa, const int8_t *pb, uint8_t *tpl, const DevPlan *pl,
                           int ng, int nmod, int64_t Mp, int64_t Np, int64_t Kp, int64_t planeA,
                           int64_t planeB, hipStream_t s);
-hipError_t launch_consumer(int nc, int nwc, const uint8_t *tpl, int64_t Mp, int64_t Np, double *C,
-                           int64_t ldc, int64_t M, int64_t N, const int32_t *ea,
+hipError_t launch_consumer(int nc, int nwc, int nd, const uint8_t *tpl, int64_t Mp, int64_t Np,
+                           double *C, int64_t ldc, int64_t M, int64_t N, const int32_t *ea,
                            const int32_t *eb, const DevPlan *pl, int mode, hipStream_t s);
 hipError_t launch_crt_export(const uint8_t *tpl, int64_t Mp, int64_t Np, int64_t M, int64_t N,
                              const DevPlan *pl, uint64_t *out, int nlimb, hipStream_t s);
