@@ -109,6 +109,9 @@ def main():
     ap.add_argument("--no-native", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=1024)
+    ap.add_argument("--workload", choices=["lu", "gemm"], default="lu",
+                    help="lu: QD Lotkin LU (default); gemm: standalone TD product m=n=k=4096")
+    ap.add_argument("--gemm-n", type=int, default=4096)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -122,6 +125,9 @@ def main():
 
     import paper_2609_29554_amd as Z
     import workloads as W
+
+    if args.workload == "gemm":
+        return bench_gemm(args)
 
     n, nc, b = args.n, args.nc, args.block
     log(f"generating Lotkin n={n} nc={nc}")
@@ -243,6 +249,66 @@ def main():
         "stages": stages,
         "info": info_v,
         "correct_bits": bits,
+    }
+    print(json.dumps(out))
+
+
+def bench_gemm(args):
+    """Standalone Ozaki-II product C = A B, triple-double, m = n = k = N,
+    entries with uniform mantissas and exponents round(N(0, 16))."""
+    import numpy as np
+    import torch
+
+    import paper_2609_29554_amd as Z
+    import workloads as W
+
+    n, nc = args.gemm_n, 3
+    log(f"generating TD operands n={n}")
+    rng = np.random.default_rng(20260932)
+    A = W.random_expansions(n, n, nc, rng, exp_sigma=4.0)
+    B = W.random_expansions(n, n, nc, rng, exp_sigma=4.0)
+    ctx = Z.Context(0)
+    dA = torch.from_numpy(A).cuda()
+    dB = torch.from_numpy(B).cuda()
+    dC = torch.zeros_like(dA)
+    S, w, Q, nmod, _ = Z.plan_query(53 * nc, n)
+    ctx.reserve(nc, n, n, n)
+    for _ in range(args.warmup):
+        ctx.gemm(0, dA, dB, dC)
+    ctx.sync_check()
+    ctx.set_profiling(True)
+    ctx.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.gemm(0, dA, dB, dC)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.set_profiling(False)
+    sec = (t1 - t0) / args.steps
+    K = args.steps
+    ms, launches, by, ops = prof["gemm"]
+    ach = ops / launches / (ms / launches * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
+            "frac": ach / PEAK_INT8_TOPS, "traffic": None, "kernel": "gemm",
+            "avg_launch_ms": ms / launches}
+    rooflines = {"gemm": roof}
+    for k in ("producer", "consumer"):
+        m2, l2, b2, _ = prof[k]
+        a2 = b2 / l2 / (m2 / l2 * 1e-3) / 1e9
+        rooflines[k] = {"bound": "hbm", "achieved": a2, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": a2 / PEAK_HBM_GBS, "traffic": None, "kernel": k,
+                        "avg_launch_ms": m2 / l2}
+    out = {
+        "metric": METRIC, "value": sec, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64x3+i8", "data": "synthetic",
+        "config": {"workload": f"Ozaki-II product C=AB, triple-double, m=n=k={n}",
+                   "S": S, "w": w, "nmod": nmod},
+        "roofline": roof, "rooflines": rooflines,
+        "effective_gflops_td": 2.0 * n ** 3 / sec / 1e9,
+        "stages": {k: {"ms_per_step": v[0] / K} for k, v in prof.items() if v[1]},
     }
     print(json.dumps(out))
 
