@@ -50,6 +50,13 @@ typedef enum {
   OZII_METHOD_NAIVE = 1  /* Schur update by expansion multiply-subtracts       */
 } ozII_method;
 
+typedef enum {
+  OZII_TILE_AUTO = 0,    /* chosen from the product shape                     */
+  OZII_TILE_128x128 = 1, /* 4 wavefronts of 64x64, operands straight from L2  */
+  OZII_TILE_256x128 = 2, /* 4 wavefronts of 128x64, operands staged in LDS    */
+  OZII_TILE_256x256 = 3  /* 8 wavefronts of 128x64, operands staged in LDS    */
+} ozII_gemm_tile;
+
 /* Options.  A null pointer means all defaults (zero). */
 typedef struct {
   int32_t backend;      /* ozII_backend                                        */
@@ -59,6 +66,9 @@ typedef struct {
   int32_t block;        /* getrf panel width b; 0 = 256                        */
   int32_t method;       /* getrf Schur update: ozII_method                     */
   int32_t flags;        /* reserved, must be 0                                 */
+  int32_t gemm_tile;    /* (S4) workgroup tile: ozII_gemm_tile; the residue   */
+                        /* planes are padded to it.  Results do not depend on */
+                        /* it (exact integer products).                       */
 } ozII_opts;
 
 typedef struct ozII_ctx *ozII_handle;

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libozii.so")
 OK, EINVAL, ECAPACITY, EOVERFLOW, ENOMEM, EHIP, EUNSUPPORTED, EDEVICE = range(8)
 BE_AUTO, BE_INT8, BE_FP8_B17, BE_F64MOD = range(4)
 METHOD_OZAKI, METHOD_NAIVE = 0, 1
+TILE_AUTO, TILE_128x128, TILE_256x128, TILE_256x256 = range(4)
 
 
 class OziiError(RuntimeError):
@@ -31,7 +32,7 @@ class OziiError(RuntimeError):
 class Opts(C.Structure):
     _fields_ = [("backend", C.c_int32), ("nslice", C.c_int32), ("extra_groups", C.c_int32),
                 ("guard_ex", C.c_int32), ("block", C.c_int32), ("method", C.c_int32),
-                ("flags", C.c_int32)]
+                ("flags", C.c_int32), ("gemm_tile", C.c_int32)]
 
 
 _lib = None
@@ -85,8 +86,8 @@ def lib():
 
 
 def make_opts(backend: int = 0, nslice: int = 0, extra_groups: int = 0, guard_ex: int = 0,
-              block: int = 0, method: int = 0) -> Opts:
-    return Opts(backend, nslice, extra_groups, guard_ex, block, method, 0)
+              block: int = 0, method: int = 0, gemm_tile: int = 0) -> Opts:
+    return Opts(backend, nslice, extra_groups, guard_ex, block, method, 0, gemm_tile)
 
 
 def plan_query(p: int, K: int, opts: Optional[Opts] = None):

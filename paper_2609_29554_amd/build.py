@@ -14,6 +14,11 @@ SOURCES = ["k_ozaki.hip", "k_lu.hip", "ozii.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]
+# Per-source additions.  The MFMA kernels keep their int32 accumulators in
+# ordinary VGPRs: with the default AGPR form the register allocator splits
+# the accumulator tiles and copies them between register files around every
+# MFMA of the pipelined loops.
+EXTRA = {"k_ozaki.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _obj(src: str) -> str:
@@ -24,7 +29,7 @@ def _compile(src: str) -> str:
     obj = _obj(src)
     os.makedirs(os.path.dirname(obj), exist_ok=True)
     lang = ["-x", "hip"]
-    cmd = [HIPCC] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + FLAGS + EXTRA.get(src, []) + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")

@@ -103,6 +103,21 @@ __global__ __launch_bounds__(256) void k_producer(const double *X, int64_t ld, i
 }
 
 // ---------------------------------------------------------------------------
+// (S4) epilogue: t = ((C mod m) y) mod m for |C| < 2^31, y < m <= 256.  x = C y is exact
+// in binary64 (< 2^39); floor(x * RN(1/m)) is floor(x/m) unless x/m is an
+// integer, when it may be one less (the rounding error, < 2^-17, is far
+// below the 1/m distance of any other quotient to an integer), so the
+// remainder is in [0, m] and the single wrap m -> 0 is an unsigned min.
+__device__ __forceinline__ uint32_t mod_times_y(int32_t c, double md, double yd, double im,
+                                                uint32_t m) {
+  const double x = (double)c * yd;
+  const double q = __builtin_floor(x * im);
+  const uint32_t r = (uint32_t)__builtin_fma(-q, md, x);
+  const uint32_t rm = r - m;
+  return r < rm ? r : rm;
+}
+
+// ---------------------------------------------------------------------------
 // (S4) batched INT8 GEMM: one workgroup = one 128x128 tile of one
 // (group, modulus) product; four wavefronts in 2x2, each 64x64 = 4x4 MFMA
 // 16x16x64 fragments.
@@ -174,7 +189,7 @@ __global__ __launch_bounds__(256) void k_gemm_i8(const int8_t *__restrict__ pa,
   }
   // epilogue: t = ((C mod m) y) mod m, one byte, staged through LDS so that
   // the column-major t-plane is written with contiguous 64-byte runs
-  const int32_t m = pl->m[l];
+  const uint32_t m = (uint32_t)pl->m[l];
   const double md = (double)m, yd = (double)pl->y[l], im = pl->inv_m[l];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
@@ -182,14 +197,7 @@ __global__ __launch_bounds__(256) void k_gemm_i8(const int8_t *__restrict__ pa,
     for (int b = 0; b < 4; ++b) {
       uint32_t packed = 0;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        double x = (double)acc[a][b][r] * yd;
-        double qq = __builtin_floor(x * im);
-        double rr = __builtin_fma(-qq, md, x);
-        rr = rr < 0.0 ? rr + md : rr;
-        rr = rr >= md ? rr - md : rr;
-        packed |= ((uint32_t)rr & 0xffu) << (8 * r);
-      }
+      for (int r = 0; r < 4; ++r) packed |= mod_times_y(acc[a][b][r], md, yd, im, m) << (8 * r);
       const int row = wm * 64 + 16 * a + 4 * (lane >> 4);
       const int col = wn * 64 + 16 * b + (lane & 15);
       *(uint32_t *)(tile + col * LDT + row) = packed;
@@ -203,6 +211,210 @@ __global__ __launch_bounds__(256) void k_gemm_i8(const int8_t *__restrict__ pa,
                            (int64_t)tm * 128 + half * 64);
 #pragma unroll
     for (int k = 0; k < 4; ++k) dst[k] = src[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// (S4), pipelined large tiles: one workgroup = one (128 WMW) x (64 WNW)
+// tile of one (group, modulus) product, WMW x WNW wavefronts of 128x64
+// (8x4 MFMA 16x16x64 fragments each).  Operand blocks move from global
+// memory straight into LDS (global_load_lds, 16 bytes per lane: a 1 KiB
+// fragment block lands as one wavefront instruction, in the order the MFMA
+// reads it), NS stages deep, so up to NS-1 inner steps of loads are in flight
+// without holding registers.  Each wavefront reads its 12 fragments of the
+// next step from LDS while its MFMAs run on the current ones.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int GL_LDT = 272;  // output staging column stride (256 rows + pad)
+constexpr int GL_GM = 4;     // tile rows per raster group
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ __forceinline__ void gl_to_lds(const int8_t *g, uint8_t *l) {
+  __builtin_amdgcn_global_load_lds((const void *)g, (lds_void *)l, 16, 0, 0);
+}
+
+// wait until at most n*LPW of this wavefront's global->LDS loads are pending
+template <int LPW>
+__device__ __forceinline__ void gl_wait_pending(int n) {
+  // s_waitcnt immediate: vmcnt[3:0] | expcnt 7 << 4 | lgkmcnt 15 << 8 | vmcnt[5:4] << 14
+#define OZ_VMCNT(N) ((((N) & 15) | (7 << 4) | (15 << 8) | (((N) >> 4) << 14)))
+  switch (n) {
+    case 0: __builtin_amdgcn_s_waitcnt(OZ_VMCNT(0)); break;
+    case 1: __builtin_amdgcn_s_waitcnt(OZ_VMCNT(1 * LPW)); break;
+    case 2: __builtin_amdgcn_s_waitcnt(OZ_VMCNT(2 * LPW)); break;
+    case 3: __builtin_amdgcn_s_waitcnt(OZ_VMCNT(3 * LPW)); break;
+    default: __builtin_amdgcn_s_waitcnt(OZ_VMCNT(4 * LPW)); break;
+  }
+#undef OZ_VMCNT
+}
+
+// Workgroup barrier for the operand pipeline: this wavefront's LDS reads have
+// returned (a wait the compiler sees, so it adds none of its own before the
+// next MFMAs), then s_barrier.  The memory clobber keeps the compiler from
+// moving LDS accesses across it; the global->LDS loads are waited for
+// explicitly (gl_wait_pending), not by a blanket vmcnt(0) at every barrier.
+__device__ __forceinline__ void gl_barrier() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), vmcnt and expcnt unconstrained
+  asm volatile("s_barrier" ::: "memory");
+}
+
+}  // namespace
+
+template <int WMW, int WNW, int NS>
+__global__ __launch_bounds__(64 * WMW * WNW) void k_gemm_i8_p(
+    const int8_t *__restrict__ pa, const int8_t *__restrict__ pb, uint8_t *__restrict__ tpl,
+    const DevPlan *pl, int64_t Mp, int64_t Np, int64_t KB, int64_t planeA, int64_t planeB,
+    int tilesM, int tilesN) {
+  constexpr int NW = WMW * WNW, NT = 64 * NW;
+  constexpr int NAB = 8 * WMW, NBB = 4 * WNW;  // 1 KiB blocks of A, B per stage
+  constexpr int STAGE = (NAB + NBB) * 1024;
+  constexpr int LPW = (NAB + NBB) / NW;        // global->LDS loads per wavefront per stage
+  constexpr int LPA = NAB / NW;                // of which A blocks
+  constexpr int TR = 128 * WMW, TC = 64 * WNW; // tile rows, columns
+  static_assert(NAB % NW == 0 && NBB % NW == 0, "blocks must split evenly over wavefronts");
+  static_assert(TR + 16 <= GL_LDT, "staging column stride");
+  static_assert(NS * STAGE >= TC * GL_LDT, "output staging must fit the operand buffers");
+  static_assert(NS >= 3 && NS <= 6, "wait table covers 0..4 stages in flight");
+  static_assert(NT == 2 * TC, "output copy: two threads per tile column");
+  __shared__ __attribute__((aligned(1024))) uint8_t lds[NS * STAGE];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv / WNW, wn = wv % WNW;
+  // XCD-aware remap (as in k_gemm_i8), then a grouped raster inside each
+  // product: consecutive logical tiles sweep GL_GM tile rows before moving to
+  // the next tile column, so the tiles running together on one XCD share
+  // few A and B panels in its L2.
+  const int nb = gridDim.x, pid = blockIdx.x;
+  const int xcd = pid & 7, loc = pid >> 3;
+  const int qd = nb >> 3, rm = nb & 7;
+  const int lt = (xcd < rm ? xcd * (qd + 1) : rm * (qd + 1) + (xcd - rm) * qd) + loc;
+  const int per = tilesM * tilesN;
+  const int gl = lt / per, r = lt - gl * per;
+  const int grp = r / (GL_GM * tilesN), r2 = r - grp * (GL_GM * tilesN);
+  const int tm0 = grp * GL_GM;
+  const int gh = tilesM - tm0 < GL_GM ? tilesM - tm0 : GL_GM;
+  const int tm = tm0 + r2 % gh, tn = r2 / gh;
+  const int nmod = pl->nmod;
+  const int l = gl % nmod, gi = gl / nmod;
+  const int S = pl->S, g = pl->g0 + gi;
+  const int ta0 = g - (S - 1) > 0 ? g - (S - 1) : 0;
+  const int ta1 = g < S - 1 ? g : S - 1;
+  const int nst = (ta1 - ta0 + 1) * (int)KB;
+
+  // Wavefront wv loads blocks c NW + wv (c < LPW) of a stage: A blocks first,
+  // then B blocks; lane l moves bytes [16 l, 16 l + 16) of each.
+  const int64_t lo16 = (int64_t)lane * 16;
+  int64_t off[LPW];
+#pragma unroll
+  for (int c = 0; c < LPW; ++c) {
+    const int bi = c * NW + wv;
+    off[c] = c < LPA ? (int64_t)(tm * NAB + bi) * KB * 1024 + lo16
+                     : (int64_t)(tn * NBB + bi - NAB) * KB * 1024 + lo16;
+  }
+
+  v4i acc[8][4];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = v4i{0, 0, 0, 0};
+
+  const int KBi = (int)KB;
+  int f_ta = ta0, f_kb = 0;  // position of the next stage to load
+#define OZ_ISSUE(BUF)                                                                          \
+  do {                                                                                         \
+    const int8_t *A0_ = pa + (int64_t)(f_ta * nmod + l) * planeA + (int64_t)f_kb * 1024;       \
+    const int8_t *B0_ = pb + (int64_t)((g - f_ta) * nmod + l) * planeB + (int64_t)f_kb * 1024; \
+    uint8_t *D_ = lds + (BUF) * STAGE + wv * 1024;                                             \
+    _Pragma("unroll") for (int c_ = 0; c_ < LPW; ++c_)                                         \
+      gl_to_lds((c_ < LPA ? A0_ : B0_) + off[c_], D_ + c_ * NW * 1024);                        \
+    if (++f_kb == KBi) {                                                                       \
+      f_kb = 0;                                                                                \
+      ++f_ta;                                                                                  \
+    }                                                                                          \
+  } while (0)
+#define OZ_READ(BUF, AF, BF)                                                                   \
+  do {                                                                                         \
+    const uint8_t *S_ = lds + (BUF) * STAGE + lo16;                                            \
+    _Pragma("unroll") for (int b_ = 0; b_ < 4; ++b_)                                           \
+      BF[b_] = *(const v4i *)(S_ + (NAB + wn * 4 + b_) * 1024);                                \
+    _Pragma("unroll") for (int a_ = 0; a_ < 8; ++a_)                                           \
+      AF[a_] = *(const v4i *)(S_ + (wm * 8 + a_) * 1024);                                      \
+  } while (0)
+  // Step st computes from CA/CB (stage st, read during step st-1).  First it
+  // waits for its own loads of stage st+1 and meets the other wavefronts at
+  // the barrier: stage st+1 has then landed, and every wavefront has read
+  // stage st out of LDS, so stage st+NS can go into that buffer.
+#define OZ_STEP(ST, CA, CB, NA, NB)                                                            \
+  do {                                                                                         \
+    const int nxt_ = (ST) + 1;                                                                 \
+    if (nxt_ < nst) {                                                                          \
+      const int ahead_ = nst - 1 - nxt_;                                                       \
+      gl_wait_pending<LPW>(ahead_ < NS - 2 ? ahead_ : NS - 2);                                 \
+    }                                                                                          \
+    gl_barrier();                                                                              \
+    if ((ST) + NS < nst) OZ_ISSUE(buf);                                                        \
+    buf = buf == NS - 1 ? 0 : buf + 1;                                                         \
+    if (nxt_ < nst) OZ_READ(buf, NA, NB);                                                      \
+    _Pragma("unroll") for (int a = 0; a < 8; ++a)                                              \
+      _Pragma("unroll") for (int b = 0; b < 4; ++b)                                            \
+        acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(CA[a], CB[b], acc[a][b], 0, 0, 0);   \
+  } while (0)
+
+  const int pro = nst < NS ? nst : NS;
+  for (int s = 0; s < pro; ++s) OZ_ISSUE(s);
+  gl_wait_pending<LPW>(pro - 1);
+  gl_barrier();
+  int buf = 0;  // buffer of the stage being computed
+  v4i xa[8], xb[4], ya[8], yb[4];
+  OZ_READ(0, xa, xb);
+  // pairs of steps that both have a following stage, then one or two steps
+  // with the fragments of the last one in xa/xb
+  int st = 0;
+  for (; st + 2 < nst; st += 2) {
+    OZ_STEP(st, xa, xb, ya, yb);
+    OZ_STEP(st + 1, ya, yb, xa, xb);
+  }
+  if (st + 1 < nst) {
+    OZ_STEP(st, xa, xb, ya, yb);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) xa[a] = ya[a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) xb[b] = yb[b];
+  }
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(xa[a], xb[b], acc[a][b], 0, 0, 0);
+#undef OZ_STEP
+#undef OZ_ISSUE
+#undef OZ_READ
+  gl_barrier();  // operand buffers are reused for the output staging tile
+  // epilogue: t = ((C mod m) y) mod m staged through LDS as a TC-column x
+  // TR-row byte tile, then written as 128-byte runs of the t-plane
+  const uint32_t m = (uint32_t)pl->m[l];
+  const double md = (double)m, yd = (double)pl->y[l], im = pl->inv_m[l];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      uint32_t packed = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) packed |= mod_times_y(acc[a][b][r], md, yd, im, m) << (8 * r);
+      const int row = wm * 128 + 16 * a + 4 * (lane >> 4);
+      const int col = wn * 64 + 16 * b + (lane & 15);
+      *(uint32_t *)(lds + col * GL_LDT + row) = packed;
+    }
+  }
+  __syncthreads();
+  {
+    constexpr int RUNS = TR / 2 / 16;  // uint4 per thread: half a column
+    const int col = tid >> 1, half = tid & 1;
+    const uint4 *src = (const uint4 *)(lds + col * GL_LDT + half * (TR / 2));
+    uint4 *dst = (uint4 *)(tpl + ((int64_t)gl * Np + (int64_t)tn * TC + col) * Mp +
+                           (int64_t)tm * TR + half * (TR / 2));
+#pragma unroll
+    for (int k = 0; k < RUNS; ++k) dst[k] = src[k];
   }
 }
 
@@ -326,12 +538,28 @@ hipError_t launch_producer(int nc, int nwx, int nh, const double *X, int64_t ld,
 
 hipError_t launch_gemm_i8(const int8_t *pa, const int8_t *pb, uint8_t *tpl, const DevPlan *pl,
                           int ng, int nmod, int64_t Mp, int64_t Np, int64_t Kp, int64_t planeA,
-                          int64_t planeB, hipStream_t s) {
-  const int tilesM = (int)(Mp / 128), tilesN = (int)(Np / 128);
-  const int64_t nblk = (int64_t)ng * nmod * tilesM * tilesN;
-  if (nblk <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gemm_i8, dim3((unsigned)nblk), dim3(256), 0, s, pa, pb, tpl, pl, Mp, Np,
-                     Kp / 64, planeA, planeB, tilesM, tilesN);
+                          int64_t planeB, int tile, hipStream_t s) {
+  const int64_t prods = (int64_t)ng * nmod;
+  if (prods <= 0 || Mp <= 0 || Np <= 0) return hipSuccess;
+  if (tile == GEMM_TILE_AUTO) tile = gemm_tile_auto(prods, Mp, Np);
+  if (tile < GEMM_TILE_AUTO || tile > GEMM_TILE_256x256 || !gemm_tile_fits(tile, Mp, Np))
+    return hipErrorInvalidValue;
+  const int64_t KB = Kp / 64;
+  if (tile == GEMM_TILE_256x256) {
+    const int tilesM = (int)(Mp / 256), tilesN = (int)(Np / 256);
+    hipLaunchKernelGGL((k_gemm_i8_p<2, 4, 4>), dim3((unsigned)(prods * tilesM * tilesN)),
+                       dim3(512), 0, s, pa, pb, tpl, pl, Mp, Np, KB, planeA, planeB, tilesM,
+                       tilesN);
+  } else if (tile == GEMM_TILE_256x128) {
+    const int tilesM = (int)(Mp / 256), tilesN = (int)(Np / 128);
+    hipLaunchKernelGGL((k_gemm_i8_p<2, 2, 5>), dim3((unsigned)(prods * tilesM * tilesN)),
+                       dim3(256), 0, s, pa, pb, tpl, pl, Mp, Np, KB, planeA, planeB, tilesM,
+                       tilesN);
+  } else {
+    const int tilesM = (int)(Mp / 128), tilesN = (int)(Np / 128);
+    hipLaunchKernelGGL(k_gemm_i8, dim3((unsigned)(prods * tilesM * tilesN)), dim3(256), 0, s, pa,
+                       pb, tpl, pl, Mp, Np, KB, planeA, planeB, tilesM, tilesN);
+  }
   return hipGetLastError();
 }
 

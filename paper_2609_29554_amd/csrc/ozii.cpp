@@ -84,6 +84,10 @@ ozII_status make_plan(int p, int64_t K, const ozII_opts *o, HostPlan &pl, std::s
   const int extra = o ? o->extra_groups : 0;
   const int gex = o ? o->guard_ex : 0;
   if (p <= 0 || K <= 0 || nslice < 0 || extra < 0 || gex < 0) return OZII_EINVAL;
+  if (o && (o->gemm_tile < OZII_TILE_AUTO || o->gemm_tile > OZII_TILE_256x256)) {
+    if (why) *why = "gemm_tile must be 0..3";
+    return OZII_EINVAL;
+  }
   if (backend != OZII_BE_INT8) {
     if (why) *why = "only the INT8 back-end is built";
     return OZII_EUNSUPPORTED;
@@ -312,10 +316,12 @@ struct GemmLayout {
   size_t off_ea, off_eb, off_pa, off_pb, off_tpl, total;
 };
 
-GemmLayout gemm_layout(const HostPlan &hp, int64_t M, int64_t N, int64_t K) {
+GemmLayout gemm_layout(const HostPlan &hp, int64_t M, int64_t N, int64_t K, int tile) {
   GemmLayout L;
-  L.Mp = roundup(std::max<int64_t>(M, 1), 128);
-  L.Np = roundup(std::max<int64_t>(N, 1), 128);
+  // rows and columns padded to the 256-wide tiles of the large GEMM kernels
+  // once they exceed one 128-wide tile (or when such a tile is forced)
+  L.Mp = roundup(std::max<int64_t>(M, 1), (M > 128 || tile >= ozl::GEMM_TILE_256x128) ? 256 : 128);
+  L.Np = roundup(std::max<int64_t>(N, 1), (N > 128 || tile == ozl::GEMM_TILE_256x256) ? 256 : 128);
   L.Kp = roundup(std::max<int64_t>(K, 1), 64);
   L.planeA = L.Mp * L.Kp;
   L.planeB = L.Np * L.Kp;
@@ -415,7 +421,7 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
   const DevPlan *dp;
   ozII_status st = get_plan(h, 53 * nc, K, o, &hp, &dp);
   if (st != OZII_OK) return st;
-  GemmLayout L = gemm_layout(*hp, M, N, K);
+  GemmLayout L = gemm_layout(*hp, M, N, K, o ? o->gemm_tile : 0);
   st = ensure_ws(h, L.total);
   if (st != OZII_OK) return st;
   int32_t *ea = (int32_t *)(h->ws + L.off_ea);
@@ -447,7 +453,8 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
   {
     ProfScope ps(h, OZ_STAGE_GEMM, (double)hp->S * hp->nmod * (double)(M + N) * K + (double)hp->ng * hp->nmod * M * N,
                  2.0 * (double)M * N * K * pairs);
-    if ((e = ozl::launch_gemm_i8(pa, pb, tpl, dp, hp->ng, hp->nmod, L.Mp, L.Np, L.Kp, L.planeA, L.planeB, s)) != hipSuccess)
+    if ((e = ozl::launch_gemm_i8(pa, pb, tpl, dp, hp->ng, hp->nmod, L.Mp, L.Np, L.Kp, L.planeA, L.planeB,
+                                  o ? o->gemm_tile : 0, s)) != hipSuccess)
       return hip_fail(h, e, "gemm_i8");
   }
   if (ea_out && (e = hipMemcpyAsync(ea_out, ea, 4 * M, hipMemcpyDeviceToDevice, s)) != hipSuccess) return hip_fail(h, e, "copy ea");
@@ -534,7 +541,7 @@ ozII_status ozII_reserve(ozII_handle h, int32_t nc, int64_t M, int64_t N, int64_
     const DevPlan *dp;
     ozII_status st = get_plan(h, 53 * nc, K, o, &hp, &dp);
     if (st != OZII_OK) return st;
-    st = ensure_ws(h, gemm_layout(*hp, M, N, K).total);
+    st = ensure_ws(h, gemm_layout(*hp, M, N, K, o ? o->gemm_tile : 0).total);
     if (st != OZII_OK) return st;
   }
   if (n > 0) {
@@ -546,7 +553,7 @@ ozII_status ozII_reserve(ozII_handle h, int32_t nc, int64_t M, int64_t N, int64_
       const DevPlan *dp;
       st = get_plan(h, 53 * nc, b, o, &hp, &dp);
       if (st != OZII_OK) return st;
-      st = ensure_ws(h, gemm_layout(*hp, n - b, n - b, b).total);
+      st = ensure_ws(h, gemm_layout(*hp, n - b, n - b, b, o ? o->gemm_tile : 0).total);
       if (st != OZII_OK) return st;
     }
   }
@@ -577,7 +584,7 @@ ozII_status ozII_gemm_stage_dims(int32_t nc, int64_t M, int64_t N, int64_t K, co
   HostPlan pl;
   ozII_status st = make_plan(53 * nc, K, o, pl, nullptr);
   if (st != OZII_OK) return st;
-  GemmLayout L = gemm_layout(pl, M, N, K);
+  GemmLayout L = gemm_layout(pl, M, N, K, o ? o->gemm_tile : 0);
   if (Mp) *Mp = L.Mp;
   if (Np) *Np = L.Np;
   if (Kp) *Kp = L.Kp;
@@ -606,7 +613,7 @@ ozII_status ozII_getrf(ozII_handle h, int32_t nc, int64_t n, double *A, int64_t 
     const DevPlan *dp;
     st = get_plan(h, 53 * nc, b, o, &hp, &dp);
     if (st != OZII_OK) return st;
-    st = ensure_ws(h, gemm_layout(*hp, n - b, n - b, b).total);
+    st = ensure_ws(h, gemm_layout(*hp, n - b, n - b, b, o ? o->gemm_tile : 0).total);
     if (st != OZII_OK) return st;
   }
   hipStream_t s = h->stream;

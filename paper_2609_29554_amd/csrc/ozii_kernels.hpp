@@ -11,6 +11,28 @@ struct DevPlan;
 namespace ozl {
 using ozk::DevPlan;
 
+// (S4) GEMM workgroup tiles (values of ozII_opts.gemm_tile)
+enum { GEMM_TILE_AUTO = 0, GEMM_TILE_128x128 = 1, GEMM_TILE_256x128 = 2, GEMM_TILE_256x256 = 3 };
+
+inline bool gemm_tile_fits(int tile, int64_t Mp, int64_t Np) {
+  switch (tile) {
+    case GEMM_TILE_128x128: return Mp % 128 == 0 && Np % 128 == 0;
+    case GEMM_TILE_256x128: return Mp % 256 == 0 && Np % 128 == 0;
+    case GEMM_TILE_256x256: return Mp % 256 == 0 && Np % 256 == 0;
+    default: return false;
+  }
+}
+
+// Largest tile that fits the padded shape and still gives every CU two
+// workgroups (prods = batched (group, modulus) products).
+inline int gemm_tile_auto(int64_t prods, int64_t Mp, int64_t Np) {
+  if (gemm_tile_fits(GEMM_TILE_256x256, Mp, Np) && prods * (Mp / 256) * (Np / 256) >= 512)
+    return GEMM_TILE_256x256;
+  if (gemm_tile_fits(GEMM_TILE_256x128, Mp, Np) && prods * (Mp / 256) * (Np / 128) >= 512)
+    return GEMM_TILE_256x128;
+  return GEMM_TILE_128x128;
+}
+
 // Ozaki-II product stages
 hipError_t launch_exponents(int nc, const double *X, int64_t ld, int64_t rows, int64_t cols,
                             int rowwise, int32_t *e, hipStream_t s);
@@ -20,7 +42,7 @@ hipError_t launch_producer(int nc, int nwx, int nh, const double *X, int64_t ld,
                            int64_t plane_bytes, hipStream_t s);
 hipError_t launch_gemm_i8(const int8_t *pa, const int8_t *pb, uint8_t *tpl, const DevPlan *pl,
                           int ng, int nmod, int64_t Mp, int64_t Np, int64_t Kp, int64_t planeA,
-                          int64_t planeB, hipStream_t s);
+                          int64_t planeB, int tile, hipStream_t s);
 hipError_t launch_consumer(int nc, int nwc, int nd, const uint8_t *tpl, int64_t Mp, int64_t Np,
                            double *C, int64_t ldc, int64_t M, int64_t N, const int32_t *ea,
                            const int32_t *eb, const DevPlan *pl, int mode, hipStream_t s);

@@ -49,6 +49,11 @@ def test_plan_options_and_errors():
     with pytest.raises(Z.OziiError) as e:
         Z.plan_query(0, 256)
     assert e.value.status == Z.EINVAL
+    Z.plan_query(212, 256, Z.make_opts(gemm_tile=Z.TILE_256x256))  # a valid tile is accepted
+    for bad in (-1, 4):
+        with pytest.raises(Z.OziiError) as e:
+            Z.plan_query(212, 256, Z.make_opts(gemm_tile=bad))
+        assert e.value.status == Z.EINVAL
     with pytest.raises(Z.OziiError) as e:
         Z.plan_query(212, 256, Z.make_opts(backend=Z.BE_F64MOD))
     assert e.value.status == Z.EUNSUPPORTED

@@ -4,6 +4,8 @@ Bar: bit-exact for every integer stage (exponents, residue planes, t-planes,
 group sums) and, since the HIP path and the oracle follow the same rounding
 specification, bit-exact for the rounded outputs and the factors as well.
 """
+import functools
+
 import numpy as np
 import pytest
 
@@ -23,6 +25,8 @@ STAGE_CASES = [
     (4, 1, 1, 1, 0, 0),
     (2, 130, 3, 7, 0, 0),
     (4, 129, 257, 65, 2, 1),
+    (2, 260, 140, 192, 1, 0),   # 3 inner steps per product (odd, below the stage count)
+    (2, 300, 130, 448, 1, 0),   # 7 inner steps: loads issued inside the loop
 ]
 
 
@@ -39,19 +43,29 @@ def _operands(nc, M, N, K, seed):
     return A, B, C0
 
 
-@pytest.mark.parametrize("case", STAGE_CASES, ids=lambda c: "nc{}-{}x{}x{}-S{}-E{}".format(*c))
-def test_gemm_stages_bit_exact(case):
-    import paper_2609_29554_amd as Z
+@functools.lru_cache(maxsize=16)
+def _stage_reference(case):
+    """Oracle stages of one case (cached across the tile parametrisation)."""
     nc, M, N, K, S_f, E = case
-    note(f"gemm stages {case}")
     A, B, C0 = _operands(nc, M, N, K, 100 + M + N + K)
     pl = O.make_plan(53 * nc, K, nslice=S_f, extra_groups=E)
-    opts = Z.make_opts(nslice=S_f, extra_groups=E)
     ea, eb = O.exponents(A, True), O.exponents(B, False)
     ra, rb = O.residues(A, True, ea, pl), O.residues(B, False, eb, pl)
     tpl = O.modgemm(ra, rb, pl)
     Cref, sb = O.ozgemm(0, A, B, np.zeros((N, M, nc)), pl, want_sbar=True, nw_out=6)
     C1ref, _ = O.ozgemm(1, A, B, C0, pl)
+    return A, B, C0, pl, ea, eb, ra, rb, tpl, Cref, sb, C1ref
+
+
+# every (S4) workgroup tile: 0 = automatic, 1 = 128x128, 2 = 256x128, 3 = 256x256
+@pytest.mark.parametrize("tile", [0, 1, 2, 3], ids=["auto", "t128x128", "t256x128", "t256x256"])
+@pytest.mark.parametrize("case", STAGE_CASES, ids=lambda c: "nc{}-{}x{}x{}-S{}-E{}".format(*c))
+def test_gemm_stages_bit_exact(case, tile):
+    import paper_2609_29554_amd as Z
+    nc, M, N, K, S_f, E = case
+    note(f"gemm stages {case} tile {tile}")
+    A, B, C0, pl, ea, eb, ra, rb, tpl, Cref, sb, C1ref = _stage_reference(case)
+    opts = Z.make_opts(nslice=S_f, extra_groups=E, gemm_tile=tile)
 
     dA, dB = to_dev(A), to_dev(B)
     dC = to_dev(np.zeros((N, M, nc)))
