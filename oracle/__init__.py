@@ -54,6 +54,7 @@ def lib():
 _dp = C.POINTER(C.c_double)
 _i8p = C.POINTER(C.c_int8)
 _u8p = C.POINTER(C.c_uint8)
+_u32p = C.POINTER(C.c_uint32)
 _i32p = C.POINTER(C.c_int32)
 _i64p = C.POINTER(C.c_int64)
 _u64p = C.POINTER(C.c_uint64)
@@ -67,10 +68,13 @@ def _declare(L):
     L.orc_abs_greater.restype = _int
     L.orc_exponents.argtypes = [_int, _i64, _i64, _dp, _i64, _int, _i32p]
     L.orc_residues.argtypes = [_int, _i64, _i64, _dp, _i64, _int, _i32p, _int, _int, _int,
-                               _i32p, _i8p]
-    L.orc_modgemm.argtypes = [_i64, _i64, _i64, _i8p, _i8p, _int, _int, _i32p, _i32p, _int,
-                              _u8p]
-    L.orc_crt.argtypes = [_i64, _i64, _u8p, _int, _int, _i32p, _int, _u64p]
+                               _i32p, _i32p]
+    L.orc_modgemm.argtypes = [_i64, _i64, _i64, _i32p, _i32p, _int, _int, _i32p, _i32p, _int,
+                              _u32p, _i64p]
+    L.orc_crt.argtypes = [_i64, _i64, _u32p, _int, _int, _i32p, _int, _u64p]
+    L.orc_fp8_digits.argtypes = [_i64, _i32p, _i32p, _i32p]
+    L.orc_e4m3_int.argtypes = [C.c_int32]
+    L.orc_e4m3_int.restype = C.c_uint8
     L.orc_round_out.argtypes = [_int, _u64p, _int, _int, _dp]
     L.orc_ozgemm.argtypes = [_int, _int, _i64, _i64, _i64, _dp, _i64, _dp, _i64, _dp, _i64,
                              _int, _int, _int, _int, _u64p]
@@ -140,42 +144,58 @@ def exponents(X, rowwise: bool) -> np.ndarray:
 def residues(X, rowwise: bool, exps, plan: Plan) -> np.ndarray:
     """(S2)+(S3): centred residues of the balanced slices.
 
-    rowwise (A operand, rows x K): returns int8 [S, nmod, rows, K];
-    otherwise (B operand, K x cols): int8 [S, nmod, cols, K]."""
+    rowwise (A operand, rows x K): returns int32 [S, nmod, rows, K];
+    otherwise (B operand, K x cols): int32 [S, nmod, cols, K]."""
     X = _f64(X)
     cols, rows, nc = X.shape
     exps = np.ascontiguousarray(exps, dtype=np.int32)
     mods = np.array(plan.moduli, dtype=np.int32)
     nout, K = (rows, cols) if rowwise else (cols, rows)
-    out = np.empty((plan.S, plan.nmod, nout, K), dtype=np.int8)
+    out = np.empty((plan.S, plan.nmod, nout, K), dtype=np.int32)
     lib().orc_residues(nc, rows, cols, _p(X, _dp), rows, int(rowwise), _p(exps, _i32p),
-                       plan.S, plan.w, plan.nmod, _p(mods, _i32p), _p(out, _i8p))
+                       plan.S, plan.w, plan.nmod, _p(mods, _i32p), _p(out, _i32p))
     return out
 
 
-def modgemm(pa, pb, plan: Plan) -> np.ndarray:
-    """(S4) + t_l of Eq. (crt): uint8 t-planes [ngroups, nmod, N, M]."""
+def modgemm(pa, pb, plan: Plan, want_cmax: bool = False):
+    """(S4) + t_l of Eq. (crt): uint32 t-planes [ngroups, nmod, N, M] (values
+    below the modulus).  With want_cmax, also max |C| over every product."""
     S, nmod, M, K = pa.shape
     N = pb.shape[2]
-    pa = np.ascontiguousarray(pa)
-    pb = np.ascontiguousarray(pb)
+    pa = np.ascontiguousarray(pa, dtype=np.int32)
+    pb = np.ascontiguousarray(pb, dtype=np.int32)
     mods = np.array(plan.moduli, dtype=np.int32)
     y = np.array(plan.y, dtype=np.int32)
     ng = len(plan.groups)
-    out = np.empty((ng, nmod, N, M), dtype=np.uint8)
-    lib().orc_modgemm(M, N, K, _p(pa, _i8p), _p(pb, _i8p), S, nmod, _p(mods, _i32p),
-                      _p(y, _i32p), plan.g0, _p(out, _u8p))
-    return out
+    out = np.empty((ng, nmod, N, M), dtype=np.uint32)
+    cmax = np.zeros(1, dtype=np.int64)
+    lib().orc_modgemm(M, N, K, _p(pa, _i32p), _p(pb, _i32p), S, nmod, _p(mods, _i32p),
+                      _p(y, _i32p), plan.g0, _p(out, _u32p), _p(cmax, _i64p))
+    return (out, int(cmax[0])) if want_cmax else out
+
+
+def fp8_digits(r):
+    """Balanced base-17 digits (d0, d1) of residues r (Eq. fp8digits)."""
+    r = np.ascontiguousarray(r, dtype=np.int32)
+    d0 = np.empty_like(r)
+    d1 = np.empty_like(r)
+    lib().orc_fp8_digits(r.size, _p(r, _i32p), _p(d0, _i32p), _p(d1, _i32p))
+    return d0, d1
+
+
+def e4m3_int(d: int) -> int:
+    """OCP FP8 E4M3 byte of a small integer (|d| <= 16)."""
+    return int(lib().orc_e4m3_int(int(d)))
 
 
 def crt(tpl, plan: Plan, nw: int = 8) -> np.ndarray:
     """(S5), CPU encoding: signed group sums as nw-limb two's complement,
     uint64 [ngroups, N, M, nw]."""
     ng, nmod, N, M = tpl.shape
-    tpl = np.ascontiguousarray(tpl)
+    tpl = np.ascontiguousarray(tpl, dtype=np.uint32)
     mods = np.array(plan.moduli, dtype=np.int32)
     out = np.empty((ng, N, M, nw), dtype=np.uint64)
-    lib().orc_crt(M, N, _p(tpl, _u8p), ng, nmod, _p(mods, _i32p), nw, _p(out, _u64p))
+    lib().orc_crt(M, N, _p(tpl, _u32p), ng, nmod, _p(mods, _i32p), nw, _p(out, _u64p))
     return out
 
 

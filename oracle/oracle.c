@@ -441,10 +441,11 @@ static int mu_of(int Q, int e) { return e == EXP_ZERO ? 0 : Q - 1 - e; }
  *   out[((t*nmod + l)*rows + i)*K + h]  (K contiguous)
  * rowwise=0: operand B (K x cols), element (h,j); output planes
  *   out[((t*nmod + l)*cols + j)*K + h]  (K contiguous)
- * Residues are centred: r in [-floor(m/2), ceil(m/2)-1]. */
+ * Residues are centred: r in [-floor(m/2), ceil(m/2)-1] (int8 range for the
+ * moduli <= 256, about +-2^22 for the binary64 back-end's primes). */
 void orc_residues(int nc, int64_t rows, int64_t cols, const double *A, int64_t ld,
                   int rowwise, const int32_t *exps, int S, int w, int nmod,
-                  const int32_t *moduli, int8_t *out) {
+                  const int32_t *moduli, int32_t *out) {
     int Q = S * w;
     int nw = fixed_limbs(Q), nv = chunk_limbs(w);
     int64_t K = rowwise ? cols : rows, nout = rowwise ? rows : cols;
@@ -463,7 +464,7 @@ void orc_residues(int nc, int64_t rows, int64_t cols, const double *A, int64_t l
                     uint32_t r = bi_mod_small(nv, v + t * nv, m);
                     int32_t c = (int32_t)r;
                     if (r >= (m + 1) / 2) c -= (int32_t)m;
-                    out[((t * nmod + l) * nout + o) * K + h] = (int8_t)c;
+                    out[((t * nmod + l) * nout + o) * K + h] = c;
                 }
             }
         }
@@ -473,12 +474,14 @@ void orc_residues(int nc, int64_t rows, int64_t cols, const double *A, int64_t l
 /* Modular GEMM per (group, modulus) with the t_l epilogue of Eq. (crt):
  * C = sum over pairs (ta,tb) with ta+tb=g of A_ta * B_tb^T (exact int64),
  * t = ((C mod m) y) mod m.  Output tpl[((gi*nmod + l)*N + j)*M + i]
- * (column major per plane), gi = g - g0. */
-void orc_modgemm(int64_t M, int64_t N, int64_t K, const int8_t *pa, const int8_t *pb,
+ * (column major per plane), gi = g - g0.  *cmax receives max |C| over all
+ * products, so callers can check the accumulator bound of a back-end. */
+void orc_modgemm(int64_t M, int64_t N, int64_t K, const int32_t *pa, const int32_t *pb,
                  int S, int nmod, const int32_t *moduli, const int32_t *y, int g0,
-                 uint8_t *tpl) {
+                 uint32_t *tpl, int64_t *cmax) {
     int ng = 2 * S - 1 - g0;
-#pragma omp parallel for collapse(2) schedule(static)
+    int64_t big = 0;
+#pragma omp parallel for collapse(2) schedule(static) reduction(max : big)
     for (int gi = 0; gi < ng; ++gi) {
         for (int l = 0; l < nmod; ++l) {
             int g = g0 + gi;
@@ -489,23 +492,48 @@ void orc_modgemm(int64_t M, int64_t N, int64_t K, const int8_t *pa, const int8_t
                     for (int ta = 0; ta < S; ++ta) {
                         int tb = g - ta;
                         if (tb < 0 || tb >= S) continue;
-                        const int8_t *ar = pa + ((int64_t)(ta * nmod + l) * M + i) * K;
-                        const int8_t *br = pb + ((int64_t)(tb * nmod + l) * N + j) * K;
+                        const int32_t *ar = pa + ((int64_t)(ta * nmod + l) * M + i) * K;
+                        const int32_t *br = pb + ((int64_t)(tb * nmod + l) * N + j) * K;
                         for (int64_t h = 0; h < K; ++h) C += (int64_t)ar[h] * br[h];
                     }
+                    int64_t ac = C < 0 ? -C : C;
+                    if (ac > big) big = ac;
                     int64_t cm = C % m;
                     if (cm < 0) cm += m;
-                    tpl[((int64_t)(gi * nmod + l) * N + j) * M + i] = (uint8_t)((cm * y[l]) % m);
+                    tpl[((int64_t)(gi * nmod + l) * N + j) * M + i] = (uint32_t)((cm * y[l]) % m);
                 }
             }
         }
     }
+    if (cmax) *cmax = big;
+}
+
+/* Balanced base-17 digits of the FP8 back-end (Eq. fp8digits):
+ * d1 = round(r/17) (17 is odd, so r/17 is never halfway), d0 = r - 17 d1. */
+void orc_fp8_digits(int64_t count, const int32_t *r, int32_t *d0, int32_t *d1) {
+    for (int64_t i = 0; i < count; ++i) {
+        int32_t v = r[i];
+        int32_t q = v >= 0 ? (2 * v + 17) / 34 : -((-2 * v + 17) / 34);
+        d1[i] = q;
+        d0[i] = v - 17 * q;
+    }
+}
+
+/* OCP FP8 E4M3 encoding (1 sign bit, 4 exponent bits with bias 7, 3 fraction
+ * bits) of a small integer |d| <= 16, every one of which is exact in it. */
+uint8_t orc_e4m3_int(int32_t d) {
+    uint8_t sign = d < 0 ? 0x80 : 0;
+    uint32_t a = (uint32_t)(d < 0 ? -d : d);
+    if (a == 0) return sign;
+    int e = 31 - __builtin_clz(a);             /* a = 2^e (1 + f/8) */
+    uint32_t f = ((a << 3) >> e) & 7u;         /* exact for a <= 16 */
+    return (uint8_t)(sign | ((uint32_t)(e + 7) << 3) | f);
 }
 
 /* CRT by the CPU encoding (Sec. 3.5.1): X = (sum_l t_l M_l) mod P in [0,P),
  * then X -= P when X > floor(P/2).  Output nw-limb two's complement per
  * element: out[((gi*N + j)*M + i)*nw + k]. */
-void orc_crt(int64_t M, int64_t N, const uint8_t *tpl, int ngroups, int nmod,
+void orc_crt(int64_t M, int64_t N, const uint32_t *tpl, int ngroups, int nmod,
              const int32_t *moduli, int nw, uint64_t *out) {
     /* P and M_l as big integers */
     uint64_t P[64], halfP[64], Ml[64][64];

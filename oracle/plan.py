@@ -18,11 +18,13 @@ Readings taken where the paper is terse (each is listed in the design doc):
   * S is the smallest slice count for which ``need`` fits the capacity and the
     accumulator bound holds (INT8: K*S*128^2 < 2^31, residues lie in
     [-128, 127]); FP8 base-17 additionally needs K*S*64 < 2^24 per sub-GEMM;
-  * the binary64-moduli back-end uses the largest primes m with
-    K*S*(m/2)^2 < 2^53, so every digit group accumulates exactly in one FP64
-    GEMM.  The paper prints counts for this back-end that do not follow one
-    rule, so this set is "parity unpinned" against the paper (self-consistent
-    only).
+  * the binary64-moduli back-end (Sec. "binary64 back-end", Eq. fp64mod)
+    uses, per slice count S, the F64_MAXMOD largest primes m with
+    K*S*m^2 < 2^53, descending: every digit group (inner dimension K*npairs
+    <= K*S) then accumulates exactly in one FP64 GEMM even without the
+    factor 4 that centred residues would allow.  With at most 20 moduli this
+    reproduces the printed DD/TD/QD GEMM counts 13/18/36 at K=512 (any cap
+    from 18 to 21 does; the bound with the factor 4 gives 17 for TD).
 """
 from __future__ import annotations
 
@@ -58,14 +60,17 @@ def int8_moduli() -> List[int]:
     return sorted(out, reverse=True)
 
 
-def f64_moduli(K: int, S: int, count: int = 64) -> List[int]:
-    """Largest primes m with K*S*(m/2)^2 < 2^53 (Eq. fp64mod with the inner
-    dimension of one digit-group GEMM, K*npairs <= K*S), descending."""
-    lim = math.isqrt((1 << 55) // (K * S)) + 2
+F64_MAXMOD = 20
+
+
+def f64_moduli(K: int, S: int, count: int = F64_MAXMOD) -> List[int]:
+    """The `count` largest primes m with K*S*m^2 < 2^53 (Eq. fp64mod for the
+    inner dimension of one digit-group GEMM, K*npairs <= K*S), descending."""
+    lim = math.isqrt((1 << 53) // (K * S)) + 2
     out = []
     m = lim
     while len(out) < count and m > 2:
-        if K * S * m * m < (1 << 55) and _is_prime(m):
+        if K * S * m * m < (1 << 53) and _is_prime(m):
             out.append(m)
         m -= 1
     return out

@@ -21,7 +21,8 @@ def _rows():
 @pytest.mark.parametrize("row", list(_rows()), ids=lambda r: f"{r[0]}-p{r[1]}-K{r[2]}")
 def test_printed_counts(row):
     src, p, K, cnt, nmod = row
-    pl = P.make_plan(p, K)
+    backend = P.BACKEND_F64MOD if src.endswith(":f64") else P.BACKEND_INT8
+    pl = P.make_plan(p, K, backend=backend)
     if cnt is not None:
         assert pl.gemm_count == cnt
         assert pl.S * (pl.S + 1) // 2 * pl.nmod == cnt  # Eq. (gemmcount)
@@ -68,10 +69,17 @@ def test_fp8_and_f64_plans():
     p8 = P.make_plan(212, 256, backend=P.BACKEND_FP8_B17)
     p1 = P.make_plan(212, 256)
     assert (p8.S, p8.w, p8.nmod) == (p1.S, p1.w, p1.nmod)   # same capacity as INT8
+    # FP8: the three FP32 accumulators (weights 1, 17, 289) stay exact
+    assert 2 * p8.K * p8.S * 64 < 2 ** 24
     pf = P.make_plan(212, 256, backend=P.BACKEND_F64MOD)
     for m in pf.moduli:
-        assert pf.K * pf.S * m * m < 2 ** 55                   # Eq. (fp64mod)
-    assert pf.gemm_count * 3 <= p1.gemm_count                # a third or fewer GEMMs
+        assert pf.K * pf.S * m * m < 2 ** 53                   # Eq. (fp64mod), no factor 4
+        assert all(m % q for q in range(2, math.isqrt(m) + 1))  # prime
+    assert pf.moduli == sorted(pf.moduli, reverse=True) and pf.nmod <= P.F64_MAXMOD
+    # "a third or less" of the INT8 GEMM count (Sec. binary64 back-end)
+    assert pf.gemm_count * 2.9 <= p1.gemm_count
+    # uniqueness of the CRT with the binary64 set, as for INT8
+    assert pf.S * pf.K * 2 ** (2 * pf.w) < pf.P // 2
 
 
 def test_lhint_table_phase():

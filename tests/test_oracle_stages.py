@@ -55,14 +55,16 @@ def test_exponents_match_frexp():
     assert np.all(O.exponents(Z, True) == O.EXP_ZERO)
 
 
-@pytest.mark.parametrize("nc,S", [(2, 1), (3, 2), (4, 2), (4, 3)])
-def test_residues_rebuild_fixed_point(nc, S):
+@pytest.mark.parametrize("nc,S,be", [(2, 1, O.BACKEND_INT8), (3, 2, O.BACKEND_INT8),
+                                     (4, 2, O.BACKEND_INT8), (4, 3, O.BACKEND_INT8),
+                                     (2, 1, O.BACKEND_F64MOD), (4, 2, O.BACKEND_F64MOD)])
+def test_residues_rebuild_fixed_point(nc, S, be):
     K = 16
-    pl = O.make_plan(53 * nc, K, nslice=S)
+    pl = O.make_plan(53 * nc, K, backend=be, nslice=S)
     A, _ = _operands(nc, 6, 3, K, 2 + S)
     ea = O.exponents(A, True)
     r = O.residues(A, True, ea, pl)          # [S, nmod, M, K]
-    assert r.dtype == np.int8
+    assert r.dtype == np.int32
     for l, m in enumerate(pl.moduli):
         assert r[:, l].min() >= -(m // 2) and r[:, l].max() <= (m + 1) // 2 - 1
     for i in range(6):
@@ -93,7 +95,7 @@ def test_modgemm_matches_numpy_matmul():
                 C += ra[ta, l].astype(np.int64) @ rb[tb, l].astype(np.int64).T
             y = pow((pl.P // m) % m, -1, m)
             want = ((C % m) * y) % m
-            assert np.array_equal(tpl[gi, l].T, want.astype(np.uint8))
+            assert np.array_equal(tpl[gi, l].T, want)
 
 
 def test_crt_round_trip():
@@ -102,7 +104,7 @@ def test_crt_round_trip():
     vals = [0, 1, -1, pl.P // 2, -(pl.P // 2) + 1]
     vals += [int.from_bytes(rng.bytes(40), "little") % pl.P - pl.P // 2 for _ in range(40)]
     M = len(vals)
-    tpl = np.zeros((1, pl.nmod, 1, M), dtype=np.uint8)
+    tpl = np.zeros((1, pl.nmod, 1, M), dtype=np.uint32)
     for i, X in enumerate(vals):
         for l, m in enumerate(pl.moduli):
             tpl[0, l, 0, i] = ((X % m) * pl.y[l]) % m
@@ -214,3 +216,93 @@ def test_naive_gemm_error():
             exact = sum(F(A[h, i]) * F(B[j, h]) for h in range(K))
             mag = sum(abs(F(A[h, i]) * F(B[j, h])) for h in range(K))
             assert abs(F(C[j, i]) - exact) <= mag * K * Fraction(1, 2 ** (53 * nc - 4))
+
+
+def test_crt_round_trip_binary64_moduli():
+    # the ~22-bit primes of the binary64 back-end: 12 moduli, P of 262 bits
+    pl = O.make_plan(212, 256, backend=O.BACKEND_F64MOD)
+    rng = np.random.default_rng(14)
+    vals = [0, 1, -1, pl.P // 2, -(pl.P // 2) + 1]
+    vals += [int.from_bytes(rng.bytes(40), "little") % pl.P - pl.P // 2 for _ in range(40)]
+    tpl = np.zeros((1, pl.nmod, 1, len(vals)), dtype=np.uint32)
+    for i, X in enumerate(vals):
+        for l, m in enumerate(pl.moduli):
+            tpl[0, l, 0, i] = ((X % m) * pl.y[l]) % m
+    out = O.crt(tpl, pl, nw=8)
+    for i, X in enumerate(vals):
+        assert O.limbs_to_int(out[0, 0, i]) == X
+
+
+def test_modgemm_binary64_moduli_exact_and_bounded():
+    nc, K = 4, 40
+    pl = O.make_plan(212, K, backend=O.BACKEND_F64MOD)
+    A, B = _operands(nc, 6, 5, K, 9)
+    ra = O.residues(A, True, O.exponents(A, True), pl)
+    rb = O.residues(B, False, O.exponents(B, False), pl)
+    assert np.abs(ra).max() > 2 ** 20             # large residues really occur
+    tpl, cmax = O.modgemm(ra, rb, pl, want_cmax=True)
+    assert cmax < 2 ** 53                         # every group product exact in FP64
+    for gi, g in enumerate(pl.groups):
+        for l, m in enumerate(pl.moduli):
+            C = [[sum(int(ra[ta, l, i, h]) * int(rb[tb, l, j, h])
+                      for ta, tb in pl.pairs(g) for h in range(K)) for j in range(5)]
+                 for i in range(6)]
+            want = np.array([[((c % m) * pl.y[l]) % m for c in row] for row in C])
+            assert np.array_equal(tpl[gi, l].T, want)
+    # the same digit-group sums as the INT8 back-end would give at this (S, w)
+    _, sb = O.ozgemm(0, A, B, np.zeros((5, 6, nc)), pl, want_sbar=True, nw_out=10)
+    assert np.array_equal(O.crt(tpl, pl, nw=10), sb)
+
+
+def test_fp8_digits_exhaustive():
+    # Eq. (fp8digits) over every centred residue of the moduli <= 256
+    r = np.arange(-128, 128, dtype=np.int32)
+    d0, d1 = O.fp8_digits(r)
+    assert np.array_equal(17 * d1 + d0, r)
+    assert np.abs(d0).max() == 8 and np.abs(d1).max() == 8   # -128 gives d1 = -8
+    assert np.abs(d1[1:]).max() == 7          # |r| <= 127 gives |d1| <= 7, as the paper says
+    # d1 is the nearest integer to r/17 (never a tie: 17 is odd)
+    for v, a in zip(r, d1):
+        assert abs(Fraction(int(v), 17) - int(a)) < Fraction(1, 2)
+
+
+def _decode_e4m3(b):
+    """Value of an OCP E4M3 byte from the format definition (no NaN here)."""
+    sign = -1 if b & 0x80 else 1
+    e, f = (b >> 3) & 15, b & 7
+    if e == 0:
+        return sign * Fraction(f, 8) * Fraction(2) ** -6
+    return sign * (1 + Fraction(f, 8)) * Fraction(2) ** (e - 7)
+
+
+def test_e4m3_encoding_of_digits():
+    for d in range(-16, 17):
+        b = O.e4m3_int(d)
+        assert _decode_e4m3(b) == d
+    assert O.e4m3_int(1) == 0x38 and O.e4m3_int(-8) == 0xD0
+
+
+def test_fp8_subproducts_rebuild_modgemm():
+    # rr' = d0 d0' + 17 (d0 d1' + d1 d0') + 289 d1 d1'; the three partial
+    # products stay below 2^24 (exact FP32 accumulation) at the plan's K*S
+    nc, K = 3, 64
+    pl = O.make_plan(159, K, backend=O.BACKEND_FP8_B17)
+    A, B = _operands(nc, 5, 4, K, 10)
+    ra = O.residues(A, True, O.exponents(A, True), pl)
+    rb = O.residues(B, False, O.exponents(B, False), pl)
+    a0, a1 = O.fp8_digits(ra)
+    b0, b1 = O.fp8_digits(rb)
+    tpl = O.modgemm(ra, rb, pl)
+    for gi, g in enumerate(pl.groups):
+        for l, m in enumerate(pl.moduli):
+            P = [np.zeros((5, 4), dtype=np.int64) for _ in range(3)]
+            for ta, tb in pl.pairs(g):
+                P[0] += a0[ta, l].astype(np.int64) @ b0[tb, l].astype(np.int64).T
+                P[1] += (a0[ta, l].astype(np.int64) @ b1[tb, l].astype(np.int64).T
+                         + a1[ta, l].astype(np.int64) @ b0[tb, l].astype(np.int64).T)
+                P[2] += a1[ta, l].astype(np.int64) @ b1[tb, l].astype(np.int64).T
+            for q in P:
+                assert np.abs(q).max() < 2 ** 24
+            C = P[0] + 17 * P[1] + 289 * P[2]
+            want = ((C % m) * pl.y[l]) % m
+            assert np.array_equal(tpl[gi, l].T, want)
