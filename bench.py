@@ -32,6 +32,8 @@ from fractions import Fraction
 METRIC = "QD LU n=2048 time vs native-QD GPU LU; Ozaki-II GEMM GOPS & % INT8 MFMA peak"
 PEAK_HBM_GBS = 8000.0
 PEAK_INT8_TOPS = 5000.0
+# dense MFMA peaks of MI355X per back-end of the modular GEMM [TOP/s]
+PEAK_MFMA = {"int8": 5000.0, "fp8": 5000.0, "f64": 78.6}
 
 
 def log(msg):
@@ -112,6 +114,10 @@ def main():
     ap.add_argument("--workload", choices=["lu", "gemm"], default="lu",
                     help="lu: QD Lotkin LU (default); gemm: standalone TD product m=n=k=4096")
     ap.add_argument("--gemm-n", type=int, default=4096)
+    ap.add_argument("--gemm-backend", choices=["int8", "fp8", "f64"], default="int8")
+    ap.add_argument("--sweep-n", type=int, default=1024,
+                    help="order of the back-end comparison LU (0 = skip)")
+    ap.add_argument("--sweep-block", type=int, default=128)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -219,6 +225,8 @@ def main():
         best = min(nat.values(), key=lambda v: v["s"])["s"]
         native = {**nat, "best_s": best, "speedup_vs_native": best / sec}
 
+    sweep = backend_sweep(ctx, args) if args.sweep_n > 0 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -249,8 +257,65 @@ def main():
         "stages": stages,
         "info": info_v,
         "correct_bits": bits,
+        "backend_sweep": sweep,
     }
     print(json.dumps(out))
+
+
+def backend_sweep(ctx, args):
+    """Quad-double Lotkin LU + solve at n = sweep_n, b = sweep_block with the
+    Schur update on each back-end of the modular GEMM (INT8, FP8 E4M3
+    base-17, binary64 moduli) and natively; one timed step each after a
+    warm-up step.  Reports seconds, Schur-update time and the modular GEMM
+    rate against that engine's MFMA peak."""
+    import torch
+
+    import paper_2609_29554_amd as Z
+    import workloads as W
+
+    n, b, nc = args.sweep_n, args.sweep_block, args.nc
+    A0 = torch.from_numpy(W.lotkin(n, nc)).cuda()
+    r0 = torch.from_numpy(W.rhs_ones(W.lotkin(n, nc))).cuda()
+    dA, dx = torch.empty_like(A0), torch.empty_like(r0)
+    out = {"workload": f"Lotkin quad-double LU n={n} b={b} (getrf+getrs)"}
+    for name, be, method in (("int8", Z.BE_INT8, Z.METHOD_OZAKI), ("fp8", Z.BE_FP8_B17, Z.METHOD_OZAKI),
+                             ("f64", Z.BE_F64MOD, Z.METHOD_OZAKI), ("native", Z.BE_INT8, Z.METHOD_NAIVE)):
+        opts = Z.make_opts(backend=be)
+
+        def run():
+            dA.copy_(A0)
+            dx.copy_(r0)
+            ipiv, info = ctx.getrf(dA, block=b, method=method, opts=opts)
+            ctx.getrs(dA, ipiv, dx)
+
+        log(f"sweep {name}")
+        run()
+        ctx.sync_check()
+        torch.cuda.synchronize()
+        ctx.set_profiling(True)
+        ctx.profile_read()
+        t0 = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = ctx.profile_read()
+        ctx.set_profiling(False)
+        ctx.sync_check()
+        rec = {"s": t1 - t0, "correct_bits": correct_bits(dx.cpu().numpy())}
+        if method == Z.METHOD_OZAKI:
+            rec["schur_update_ms"] = sum(prof[k][0] for k in ("exponents", "producer", "gemm", "consumer"))
+            ms, la, by, ops = prof["gemm"]
+            if la and ms > 0:
+                ach = ops / (ms * 1e-3) / 1e12
+                rec["gemm"] = {"achieved": ach, "peak": PEAK_MFMA[name], "unit": "TOP/s",
+                               "frac": ach / PEAK_MFMA[name], "ms": ms}
+            S, w, Q, nmod, _ = Z.plan_query(53 * nc, b, opts)
+            rec["plan"] = {"S": S, "w": w, "nmod": nmod}
+        else:
+            rec["schur_update_ms"] = prof["naive_update"][0]
+        out[name] = rec
+        log(f"sweep {name}: {rec['s'] * 1e3:.1f} ms, Schur {rec['schur_update_ms']:.2f} ms")
+    return out
 
 
 def bench_gemm(args):
@@ -271,17 +336,20 @@ def bench_gemm(args):
     dA = torch.from_numpy(A).cuda()
     dB = torch.from_numpy(B).cuda()
     dC = torch.zeros_like(dA)
-    S, w, Q, nmod, _ = Z.plan_query(53 * nc, n)
-    ctx.reserve(nc, n, n, n)
+    be = {"int8": Z.BE_INT8, "fp8": Z.BE_FP8_B17, "f64": Z.BE_F64MOD}[args.gemm_backend]
+    opts = Z.make_opts(backend=be)
+    peak = PEAK_MFMA[args.gemm_backend]
+    S, w, Q, nmod, _ = Z.plan_query(53 * nc, n, opts)
+    ctx.reserve(nc, n, n, n, 0, opts)
     for _ in range(args.warmup):
-        ctx.gemm(0, dA, dB, dC)
+        ctx.gemm(0, dA, dB, dC, opts)
     ctx.sync_check()
     ctx.set_profiling(True)
     ctx.profile_read()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        ctx.gemm(0, dA, dB, dC)
+        ctx.gemm(0, dA, dB, dC, opts)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = ctx.profile_read()
@@ -290,8 +358,8 @@ def bench_gemm(args):
     K = args.steps
     ms, launches, by, ops = prof["gemm"]
     ach = ops / launches / (ms / launches * 1e-3) / 1e12
-    roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
-            "frac": ach / PEAK_INT8_TOPS, "traffic": None, "kernel": "gemm",
+    roof = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TOP/s",
+            "frac": ach / peak, "traffic": None, "kernel": "gemm",
             "avg_launch_ms": ms / launches}
     rooflines = {"gemm": roof}
     for k in ("producer", "consumer"):
@@ -305,7 +373,7 @@ def bench_gemm(args):
         "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64x3+i8", "data": "synthetic",
         "config": {"workload": f"Ozaki-II product C=AB, triple-double, m=n=k={n}",
-                   "S": S, "w": w, "nmod": nmod},
+                   "backend": args.gemm_backend, "S": S, "w": w, "nmod": nmod},
         "roofline": roof, "rooflines": rooflines,
         "effective_gflops_td": 2.0 * n ** 3 / sec / 1e9,
         "stages": {k: {"ms_per_step": v[0] / K} for k, v in prof.items() if v[1]},

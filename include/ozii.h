@@ -38,11 +38,21 @@ typedef enum {
   OZII_EDEVICE = 7       /* a kernel reported an internal error (see text)   */
 } ozII_status;
 
+/* Back-ends of (S3)/(S4).  All three give bit-identical products at equal
+ * (S, w): the digit-group sums are exact integers either way.
+ *   INT8:  the 54 largest prime powers <= 256 (Sec. 3.2), int8 residues,
+ *          exact int32 MFMA accumulation (K S 128^2 < 2^31);
+ *   FP8:   the same moduli, every residue split into balanced base-17 digits
+ *          (Eq. fp8digits) stored as E4M3, four sub-products per pair with
+ *          exact FP32 accumulation;
+ *   F64:   the 20 largest primes m with K S m^2 < 2^53 (Eq. fp64mod),
+ *          residues in binary64, exact FP64 MFMA accumulation.
+ * AUTO currently means INT8. */
 typedef enum {
   OZII_BE_AUTO = 0,
-  OZII_BE_INT8 = 1,      /* int8 residues, exact int32 MFMA accumulation      */
-  OZII_BE_FP8_B17 = 2,   /* balanced base-17 digits in FP8 E4M3, FP32 accum.  */
-  OZII_BE_F64MOD = 3     /* binary64 residues of ~23-bit primes, FP64 MFMA    */
+  OZII_BE_INT8 = 1,
+  OZII_BE_FP8_B17 = 2,
+  OZII_BE_F64MOD = 3
 } ozII_backend;
 
 typedef enum {
@@ -103,16 +113,26 @@ ozII_status ozII_gemm(ozII_handle h, int32_t mode, int32_t nc, int64_t M, int64_
 /* Same product with the intermediate stages copied out (parity hooks); any
  * output pointer may be null.  Sizes follow ozII_gemm_stage_dims:
  *   ea[M], eb[N]     (S1) row / column exponents (INT32_MIN for zero);
- *   planesA          (S3) int8 residues, S*nmod planes of Mp x Kp in
- *                    fragment order, planesB likewise Np x Kp;
- *   tpl              (S4) uint8 t-planes [ng][nmod][Np][Mp];
+ *   planesA          (S3) residue planes of Mp x Kp elements, planesB of
+ *                    Np x Kp, in MFMA fragment order: 1 KiB blocks of 16 rows
+ *                    (lane l of a block holds row l%16), blocks ordered
+ *                    (row block, k block).  Per back-end:
+ *                      INT8: S*nmod planes of int8 residues, a block spans
+ *                            64 k (lane l: k 16(l/16) .. +16);
+ *                      FP8:  2*S*nmod planes (digit d0, then d1, of Eq.
+ *                            fp8digits, per slice and modulus) of OCP E4M3
+ *                            bytes, blocks as INT8;
+ *                      F64:  S*nmod planes of residues as doubles, a block
+ *                            spans 8 k (lane l: k l/16 and 4 + l/16);
+ *   tpl              (S4) t-planes [ng][nmod][Np][Mp], uint8 (INT8, FP8) or
+ *                    uint32 (F64);
  *   sbar             (S5) group sums, nlimb 64-bit two's-complement limbs per
  *                    element, layout [ng][N][M][nlimb]. */
 ozII_status ozII_gemm_stages(ozII_handle h, int32_t mode, int32_t nc, int64_t M, int64_t N,
                              int64_t K, const double *A, int64_t lda, const double *B,
                              int64_t ldb, double *C, int64_t ldc, const ozII_opts *o,
-                             int32_t *ea, int32_t *eb, int8_t *planesA, int8_t *planesB,
-                             uint8_t *tpl, uint64_t *sbar, int32_t nlimb);
+                             int32_t *ea, int32_t *eb, void *planesA, void *planesB,
+                             void *tpl, uint64_t *sbar, int32_t nlimb);
 ozII_status ozII_gemm_stage_dims(int32_t nc, int64_t M, int64_t N, int64_t K, const ozII_opts *o,
                                  int64_t *Mp, int64_t *Np, int64_t *Kp, int32_t *S,
                                  int32_t *nmod, int32_t *ng);

@@ -183,11 +183,17 @@ class Context:
         if st != OK:
             raise OziiError(st, "stage dims")
         dev = A.device
+        backend = opts.backend if opts is not None and opts.backend else BE_INT8
+        # plane element type and planes per (slice, modulus); t-value type
+        pdt, per, tdt = {BE_INT8: (torch.int8, 1, torch.uint8),
+                         BE_FP8_B17: (torch.uint8, 2, torch.uint8),
+                         BE_F64MOD: (torch.float64, 1, torch.int32)}[backend]
+        npl = S.value * nmod.value * per
         ea = torch.empty(M, dtype=torch.int32, device=dev)
         eb = torch.empty(N, dtype=torch.int32, device=dev)
-        pa = torch.empty(S.value * nmod.value * Mp.value * Kp.value, dtype=torch.int8, device=dev)
-        pb = torch.empty(S.value * nmod.value * Np.value * Kp.value, dtype=torch.int8, device=dev)
-        tpl = torch.empty(ng.value * nmod.value * Np.value * Mp.value, dtype=torch.uint8, device=dev)
+        pa = torch.empty(npl * Mp.value * Kp.value, dtype=pdt, device=dev)
+        pb = torch.empty(npl * Np.value * Kp.value, dtype=pdt, device=dev)
+        tpl = torch.empty(ng.value * nmod.value * Np.value * Mp.value, dtype=tdt, device=dev)
         sbar = torch.empty(ng.value * N * M * nlimb, dtype=torch.int64, device=dev)
         self._bind()
         self._call(lib().ozII_gemm_stages(self._h, mode, nc, M, N, K, _ptr(A), M, _ptr(B), K,
@@ -195,7 +201,7 @@ class Context:
                                           _ptr(eb), _ptr(pa), _ptr(pb), _ptr(tpl), _ptr(sbar),
                                           nlimb))
         dims = dict(Mp=Mp.value, Np=Np.value, Kp=Kp.value, S=S.value, nmod=nmod.value,
-                    ng=ng.value, M=M, N=N, K=K)
+                    ng=ng.value, M=M, N=N, K=K, backend=backend, nplanes=npl)
         return dict(ea=ea, eb=eb, planesA=pa, planesB=pb, tpl=tpl, sbar=sbar, dims=dims)
 
     def getrf(self, A, block: int = 256, method: int = METHOD_OZAKI, opts: Optional[Opts] = None):
@@ -247,11 +253,16 @@ class Context:
         return {STAGES[i]: (ms[i], la[i], by[i], op[i]) for i in range(n)}
 
 
-def unfragment(planes, n_planes: int, noutp: int, Kp: int):
+def unfragment(planes, n_planes: int, noutp: int, Kp: int, backend: int = BE_INT8):
     """Residue planes from fragment order to [plane][row][k] (numpy, for
-    tests): block (ob, kb) = 1024 bytes, lane l holds row l%16 and inner
-    indices 16*(l/16)..+15."""
+    tests).  A block (ob, kb) is 1 KiB; lane l holds row l%16 and
+      INT8 / FP8: bytes for k = 16*(l/16) .. +15 of a 64-k block;
+      F64: doubles for k = l/16 and 4 + l/16 of an 8-k block."""
     import numpy as np
+    if backend == BE_F64MOD:
+        a = np.asarray(planes).reshape(n_planes, noutp // 16, Kp // 8, 4, 16, 2)
+        # axes: plane, ob, kb, kgroup, row, slot -> plane, ob, row, kb, slot, kgroup
+        return a.transpose(0, 1, 4, 2, 5, 3).reshape(n_planes, noutp, Kp)
     a = np.asarray(planes).reshape(n_planes, noutp // 16, Kp // 64, 4, 16, 16)
     # axes: plane, ob, kb, kgroup, row, byte -> plane, ob, row, kb, kgroup, byte
     return a.transpose(0, 1, 4, 2, 3, 5).reshape(n_planes, noutp, Kp)

@@ -73,20 +73,52 @@ __global__ __launch_bounds__(256) void k_col_exponents(const double *B, int64_t 
 // ---------------------------------------------------------------------------
 // (S2)+(S3) producer
 // ---------------------------------------------------------------------------
-template <int NC, int NWX, int NH>
+// Plane encodings of the three back-ends of (S3)/(S4).
+enum { PL_I8 = 0, PL_F8 = 1, PL_F64 = 2 };
+
+// OCP FP8 E4M3 byte of an integer |d| <= 8 (sign, exponent bias 7, 3-bit
+// fraction): d = 2^e (1 + f/8) with e = floor(log2 |d|).
+__device__ __forceinline__ uint8_t e4m3_small(int32_t d) {
+  const uint32_t a = (uint32_t)(d < 0 ? -d : d);
+  const uint32_t sign = d < 0 ? 0x80u : 0u;
+  if (a == 0) return (uint8_t)sign;
+  const uint32_t e = 31u - (uint32_t)__builtin_clz(a);
+  const uint32_t f = ((a << 3) >> e) & 7u;
+  return (uint8_t)(sign | ((e + 7u) << 3) | f);
+}
+
+// Producer: one workgroup fills one 16-row x 64-k window of every plane.
+//   PL_I8 : int8 residues, 1 KiB blocks of 16 rows x 64 k (lane l: row l%16,
+//           k 16(l/16) .. +16);
+//   PL_F8 : the balanced base-17 digits d0, d1 of every residue (Eq.
+//           fp8digits) as E4M3 bytes, two planes per (slice, modulus), same
+//           blocks;
+//   PL_F64: residues as doubles, 1 KiB blocks of 16 rows x 8 k (lane l: row
+//           l%16, k l/16 and 4 + l/16), eight blocks per window.
+template <int NC, int NWX, int NH, int PL>
 __global__ __launch_bounds__(256) void k_producer(const double *X, int64_t ld, int rowwise,
                                                   int64_t nout, int64_t K, int64_t KB,
                                                   const int32_t *exps, const DevPlan *pl,
-                                                  int8_t *planes, int64_t plane_bytes) {
+                                                  void *planes, int64_t plane_elems) {
   __shared__ uint32_t stage[256 * STG];
   uint32_t *st = stage + threadIdx.x * STG;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t kb = blockIdx.x, ob = blockIdx.y;
   const int nmod = pl->nmod, Q = pl->Q;
   for (int q = 0; q < 4; ++q) {
-    const int64_t o = ob * 16 + 4 * q + (lane >> 4);
-    const int64_t h = kb * 64 + 16 * wv + (lane & 15);
-    const int64_t off = (ob * KB + kb) * 1024 + 64 * q + 256 * wv + lane;
+    int64_t o, h, off;
+    if (PL == PL_F64) {
+      // output order: consecutive threads write consecutive doubles
+      const int E = q * 256 + (int)threadIdx.x;
+      const int fb = E >> 7, L = (E >> 1) & 63, slot = E & 1;
+      o = ob * 16 + (L & 15);
+      h = kb * 64 + fb * 8 + (L >> 4) + 4 * slot;
+      off = ((ob * KB + kb) * 8 + fb) * 128 + (E & 127);
+    } else {
+      o = ob * 16 + 4 * q + (lane >> 4);
+      h = kb * 64 + 16 * wv + (lane & 15);
+      off = (ob * KB + kb) * 1024 + 64 * q + 256 * wv + lane;
+    }
     const double *src = nullptr;
     int mu = 0;
     if (o < nout && h < K) {
@@ -96,8 +128,18 @@ __global__ __launch_bounds__(256) void k_producer(const double *X, int64_t ld, i
         mu = Q - 1 - ex;
       }
     }
-    produce_element<NC, NWX, NH>(src, mu, pl, st, [&](int t, int l, int8_t r) {
-      planes[(int64_t)(t * nmod + l) * plane_bytes + off] = r;
+    produce_element<NC, NWX, NH, PL == PL_F64>(src, mu, pl, st, [&](int t, int l, int32_t r) {
+      const int64_t pi = (int64_t)(t * nmod + l);
+      if (PL == PL_I8) {
+        ((int8_t *)planes)[pi * plane_elems + off] = (int8_t)r;
+      } else if (PL == PL_F8) {
+        const int32_t d1 = (int32_t)__builtin_rintf((float)r * (1.0f / 17.0f));
+        const int32_t d0 = r - 17 * d1;
+        ((uint8_t *)planes)[(2 * pi) * plane_elems + off] = e4m3_small(d0);
+        ((uint8_t *)planes)[(2 * pi + 1) * plane_elems + off] = e4m3_small(d1);
+      } else {
+        ((double *)planes)[pi * plane_elems + off] = (double)r;
+      }
     });
   }
 }
@@ -419,10 +461,237 @@ __global__ __launch_bounds__(64 * WMW * WNW) void k_gemm_i8_p(
 }
 
 // ---------------------------------------------------------------------------
+// (S4), FP8 E4M3 back-end (balanced base-17 digits, Eq. fp8digits): for every
+// slice pair and modulus r r' = d0 d0' + 17 (d0 d1' + d1 d0') + 289 d1 d1',
+// so three FP32 accumulators per output (the two cross products share one).
+// Every partial sum is an integer below 2 K S 64 < 2^24, exact in FP32 under
+// the plan's bound.  One workgroup = one 128x128 tile, eight wavefronts of
+// 32x64 (2x4 fragments of v_mfma_f32_16x16x128_f8f6f4).  A 128-wide inner
+// step takes two consecutive 1 KiB blocks per operand; both operands use the
+// same byte-to-k assignment, so the products pair up as the dot product
+// needs.
+// ---------------------------------------------------------------------------
+namespace {
+typedef int v8i_t __attribute__((ext_vector_type(8)));
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+typedef double v2d_t __attribute__((ext_vector_type(2)));
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v8i_t load_pair(const uint8_t *p) {
+  const v4i lo = *(const v4i *)p, hi = *(const v4i *)(p + 1024);
+  return v8i_t{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
+
+// t = ((C mod m) y) mod m for an integer C held exactly in a double with
+// |C y| < 2^44: floor(C y RN(1/m)) is off only for exact multiples (see
+// mod_times_y), so the remainder lies in [0, m].
+__device__ __forceinline__ uint32_t mod_times_y_d(double c, double md, double yd, double im,
+                                                  uint32_t m) {
+  const double x = c * yd;
+  const double q = __builtin_floor(x * im);
+  const uint32_t r = (uint32_t)__builtin_fma(-q, md, x);
+  const uint32_t rm = r - m;
+  return r < rm ? r : rm;
+}
+}  // namespace
+
+__global__ __launch_bounds__(512) void k_gemm_f8(const uint8_t *__restrict__ pa,
+                                                 const uint8_t *__restrict__ pb,
+                                                 uint8_t *__restrict__ tpl, const DevPlan *pl,
+                                                 int64_t Mp, int64_t Np, int64_t KB,
+                                                 int64_t planeA, int64_t planeB, int tilesM,
+                                                 int tilesN) {
+  constexpr int LDT = 144;
+  __shared__ __attribute__((aligned(16))) uint8_t tile[128 * LDT];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wm = wv >> 1, wn = wv & 1;  // 4 x 2 wavefronts of 32 x 64
+  const int nb = gridDim.x, pid = blockIdx.x;
+  const int xcd = pid & 7, loc = pid >> 3;
+  const int qd = nb >> 3, rm = nb & 7;
+  const int lt = (xcd < rm ? xcd * (qd + 1) : rm * (qd + 1) + (xcd - rm) * qd) + loc;
+  const int tn = lt % tilesN;
+  const int tm = (lt / tilesN) % tilesM;
+  const int gl = lt / (tilesN * tilesM);
+  const int nmod = pl->nmod;
+  const int l = gl % nmod, gi = gl / nmod;
+  const int S = pl->S, g = pl->g0 + gi;
+  const int ta0 = g - (S - 1) > 0 ? g - (S - 1) : 0;
+  const int ta1 = g < S - 1 ? g : S - 1;
+
+  v4f_t c0[2][4], c1[2][4], c2[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      c0[a][b] = v4f_t{0.f, 0.f, 0.f, 0.f};
+      c1[a][b] = c0[a][b];
+      c2[a][b] = c0[a][b];
+    }
+  for (int ta = ta0; ta <= ta1; ++ta) {
+    const int tb = g - ta;
+    const uint8_t *A0 = pa + (int64_t)(2 * (ta * nmod + l)) * planeA +
+                        ((int64_t)(tm * 8 + wm * 2) * KB) * 1024 + lane * 16;
+    const uint8_t *B0 = pb + (int64_t)(2 * (tb * nmod + l)) * planeB +
+                        ((int64_t)(tn * 8 + wn * 4) * KB) * 1024 + lane * 16;
+    for (int64_t kb = 0; kb < KB; kb += 2) {
+      v8i_t a0[2], a1[2], b0[4], b1[4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const uint8_t *p = A0 + ((int64_t)a * KB + kb) * 1024;
+        a0[a] = load_pair(p);
+        a1[a] = load_pair(p + planeA);
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const uint8_t *p = B0 + ((int64_t)b * KB + kb) * 1024;
+        b0[b] = load_pair(p);
+        b1[b] = load_pair(p + planeB);
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          c0[a][b] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a0[a], b0[b], c0[a][b], 0, 0,
+                                                                      0, 0, 0, 0);
+          c1[a][b] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a0[a], b1[b], c1[a][b], 0, 0,
+                                                                      0, 0, 0, 0);
+          c1[a][b] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a1[a], b0[b], c1[a][b], 0, 0,
+                                                                      0, 0, 0, 0);
+          c2[a][b] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a1[a], b1[b], c2[a][b], 0, 0,
+                                                                      0, 0, 0, 0);
+        }
+    }
+  }
+  const uint32_t m = (uint32_t)pl->m[l];
+  const double md = (double)m, yd = (double)pl->y[l], im = pl->inv_m[l];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      uint32_t packed = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double cc = (double)c0[a][b][r] + 17.0 * (double)c1[a][b][r] +
+                          289.0 * (double)c2[a][b][r];  // exact: |cc| < 2^33
+        packed |= mod_times_y_d(cc, md, yd, im, m) << (8 * r);
+      }
+      const int row = wm * 32 + 16 * a + 4 * (lane >> 4);
+      const int col = wn * 64 + 16 * b + (lane & 15);
+      *(uint32_t *)(tile + col * LDT + row) = packed;
+    }
+  }
+  __syncthreads();
+  {
+    const int col = threadIdx.x >> 2, qtr = threadIdx.x & 3;
+    const uint4 *src = (const uint4 *)(tile + col * LDT + qtr * 32);
+    uint4 *dst = (uint4 *)(tpl + ((int64_t)gl * Np + (int64_t)tn * 128 + col) * Mp +
+                           (int64_t)tm * 128 + qtr * 32);
+    dst[0] = src[0];
+    dst[1] = src[1];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// (S4), binary64-moduli back-end (Eq. fp64mod): residues of ~22-bit primes as
+// doubles, one FP64 MFMA product per (group, modulus); every partial sum is
+// an integer below K S m^2 < 2^53, so the accumulation is exact.  One
+// workgroup = one 128x128 tile, four wavefronts of 64x64 (4x4 fragments of
+// v_mfma_f64_16x16x4_f64); a 1 KiB block holds 16 rows x 8 k (lane l: row
+// l%16, k l/16 and 4 + l/16), i.e. two MFMA steps.  t-values are uint32.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ pa,
+                                                  const double *__restrict__ pb,
+                                                  uint32_t *__restrict__ tpl, const DevPlan *pl,
+                                                  int64_t Mp, int64_t Np, int64_t KB8,
+                                                  int64_t planeA, int64_t planeB, int tilesM,
+                                                  int tilesN) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int nb = gridDim.x, pid = blockIdx.x;
+  const int xcd = pid & 7, loc = pid >> 3;
+  const int qd = nb >> 3, rm = nb & 7;
+  const int lt = (xcd < rm ? xcd * (qd + 1) : rm * (qd + 1) + (xcd - rm) * qd) + loc;
+  const int tn = lt % tilesN;
+  const int tm = (lt / tilesN) % tilesM;
+  const int gl = lt / (tilesN * tilesM);
+  const int nmod = pl->nmod;
+  const int l = gl % nmod, gi = gl / nmod;
+  const int S = pl->S, g = pl->g0 + gi;
+  const int ta0 = g - (S - 1) > 0 ? g - (S - 1) : 0;
+  const int ta1 = g < S - 1 ? g : S - 1;
+
+  v4d_t acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = v4d_t{0.0, 0.0, 0.0, 0.0};
+  for (int ta = ta0; ta <= ta1; ++ta) {
+    const int tb = g - ta;
+    const double *A0 = pa + (int64_t)(ta * nmod + l) * planeA +
+                       ((int64_t)(tm * 8 + wm * 4) * KB8) * 128 + lane * 2;
+    const double *B0 = pb + (int64_t)(tb * nmod + l) * planeB +
+                       ((int64_t)(tn * 8 + wn * 4) * KB8) * 128 + lane * 2;
+    v2d_t af[4], bf[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) af[a] = *(const v2d_t *)(A0 + (int64_t)a * KB8 * 128);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) bf[b] = *(const v2d_t *)(B0 + (int64_t)b * KB8 * 128);
+    for (int64_t kb = 0; kb < KB8; ++kb) {
+      v2d_t an[4], bn[4];
+      const bool more = kb + 1 < KB8;
+      if (more) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) an[a] = *(const v2d_t *)(A0 + ((int64_t)a * KB8 + kb + 1) * 128);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bn[b] = *(const v2d_t *)(B0 + ((int64_t)b * KB8 + kb + 1) * 128);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a][0], bf[b][0], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a][1], bf[b][1], acc[a][b], 0, 0, 0);
+        }
+      if (more) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) af[a] = an[a];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bf[b] = bn[b];
+      }
+    }
+  }
+  // t = ((C mod m) y) mod m.  |C| < 2^53: floor(C RN(1/m)) is within one of
+  // floor(C/m) either way, so C - q m lies in [-m, 2m) and is corrected once;
+  // then (c y) < 2^46 is reduced like the small back-ends.
+  const uint32_t m = (uint32_t)pl->m[l];
+  const double md = (double)m, yd = (double)pl->y[l], im = pl->inv_m[l];
+  // The FP64 MFMA's result rows are interleaved: value r of lane l is row
+  // l/16 + 4 r, column l%16, of the 16x16 fragment.
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int64_t row0 = (int64_t)tm * 128 + wm * 64 + 16 * a + (lane >> 4);
+      const int64_t col = (int64_t)tn * 128 + wn * 64 + 16 * b + (lane & 15);
+      uint32_t *dst = tpl + ((int64_t)gl * Np + col) * Mp + row0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double C = acc[a][b][r];
+        const double q = __builtin_floor(C * im);
+        double c = __builtin_fma(-q, md, C);
+        c = c < 0.0 ? c + md : c;
+        c = c >= md ? c - md : c;
+        dst[4 * r] = mod_times_y_d(c, md, yd, im, m);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // (S5)+(S6) consumer
 // ---------------------------------------------------------------------------
-template <int NC, int NWC, int ND>
-__global__ __launch_bounds__(256) void k_consumer(const uint8_t *__restrict__ tpl, int64_t Mp,
+template <int NC, int NWC, int ND, class TT>
+__global__ __launch_bounds__(256) void k_consumer(const TT *__restrict__ tpl, int64_t Mp,
                                                   int64_t Np, double *C, int64_t ldc, int64_t M,
                                                   int64_t N, const int32_t *ea, const int32_t *eb,
                                                   const DevPlan *pl, int mode) {
@@ -436,7 +705,7 @@ __global__ __launch_bounds__(256) void k_consumer(const uint8_t *__restrict__ tp
   const bool zero = ei == EXP_ZERO || ej == EXP_ZERO;
   const int eps = zero ? 0 : pl->w * pl->g0 - (Q - 1 - ei) - (Q - 1 - ej);
   double c[NC];
-  consume_element<NC, NWC, ND>(
+  consume_element<NC, NWC, ND, TT>(
       [&](int gi) { return tpl + ((int64_t)gi * nmod * Np + j) * Mp + i; }, Np * Mp, pl, st, zero,
       eps, c);
   double *dst = C + (i + j * ldc) * NC;
@@ -454,7 +723,8 @@ __global__ __launch_bounds__(256) void k_consumer(const uint8_t *__restrict__ tp
 
 // Debug export of the group sums: Sbar as 64-bit limbs (two's complement),
 // layout [gi][j][i][limb], nlimb limbs.
-__global__ __launch_bounds__(256) void k_crt_export(const uint8_t *__restrict__ tpl, int64_t Mp,
+template <class TT>
+__global__ __launch_bounds__(256) void k_crt_export(const TT *__restrict__ tpl, int64_t Mp,
                                                     int64_t Np, int64_t M, int64_t N,
                                                     const DevPlan *pl, uint64_t *out, int nlimb) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -463,7 +733,7 @@ __global__ __launch_bounds__(256) void k_crt_export(const uint8_t *__restrict__ 
   const int nmod = pl->nmod;
   for (int gi = 0; gi < pl->ng; ++gi) {
     int32_t d[NDCRT];
-    crt_digits<NDCRT>(tpl + ((int64_t)gi * nmod * Np + j) * Mp + i, Np * Mp, pl, d);
+    crt_digits<NDCRT, TT>(tpl + ((int64_t)gi * nmod * Np + j) * Mp + i, Np * Mp, pl, d);
     uint64_t *o = out + (((int64_t)gi * N + j) * M + i) * nlimb;
     const uint64_t fill = d[NDCRT - 1] < 0 ? ~0ull : 0ull;
     for (int q = 0; q < nlimb; ++q) {
@@ -506,33 +776,71 @@ hipError_t launch_exponents(int nc, const double *X, int64_t ld, int64_t rows, i
   return hipGetLastError();
 }
 
-template <int NC, int NWX>
+template <int NC, int NWX, int PL>
 static void producer_nh(int nh, dim3 g, hipStream_t s, const double *X, int64_t ld, int rowwise,
                         int64_t nout, int64_t K, int64_t KB, const int32_t *exps,
-                        const DevPlan *pl, int8_t *planes, int64_t plane_bytes) {
+                        const DevPlan *pl, void *planes, int64_t plane_elems) {
   if (nh <= 8)
-    hipLaunchKernelGGL((k_producer<NC, NWX, 8>), g, dim3(256), 0, s, X, ld, rowwise, nout, K, KB,
-                       exps, pl, planes, plane_bytes);
+    hipLaunchKernelGGL((k_producer<NC, NWX, 8, PL>), g, dim3(256), 0, s, X, ld, rowwise, nout, K,
+                       KB, exps, pl, planes, plane_elems);
   else if (nh <= 12)
-    hipLaunchKernelGGL((k_producer<NC, NWX, 12>), g, dim3(256), 0, s, X, ld, rowwise, nout, K, KB,
-                       exps, pl, planes, plane_bytes);
+    hipLaunchKernelGGL((k_producer<NC, NWX, 12, PL>), g, dim3(256), 0, s, X, ld, rowwise, nout, K,
+                       KB, exps, pl, planes, plane_elems);
   else
-    hipLaunchKernelGGL((k_producer<NC, NWX, NHMAX>), g, dim3(256), 0, s, X, ld, rowwise, nout, K,
-                       KB, exps, pl, planes, plane_bytes);
+    hipLaunchKernelGGL((k_producer<NC, NWX, NHMAX, PL>), g, dim3(256), 0, s, X, ld, rowwise, nout,
+                       K, KB, exps, pl, planes, plane_elems);
 }
 
-hipError_t launch_producer(int nc, int nwx, int nh, const double *X, int64_t ld, int rowwise,
-                           int64_t nout, int64_t noutp, int64_t K, int64_t Kp,
-                           const int32_t *exps, const DevPlan *pl, int8_t *planes,
-                           int64_t plane_bytes, hipStream_t s) {
-  const int64_t KB = Kp / 64, OB = noutp / 16;
-  if (KB <= 0 || OB <= 0) return hipSuccess;
-  dim3 g((unsigned)KB, (unsigned)OB);
-#define OZ_PROD(NC_, NWX_) producer_nh<NC_, NWX_>(nh, g, s, X, ld, rowwise, nout, K, KB, exps, pl, planes, plane_bytes)
+template <int PL>
+static void producer_pl(int nc, int nwx, int nh, dim3 g, hipStream_t s, const double *X,
+                        int64_t ld, int rowwise, int64_t nout, int64_t K, int64_t KB,
+                        const int32_t *exps, const DevPlan *pl, void *planes,
+                        int64_t plane_elems) {
+#define OZ_PROD(NC_, NWX_) \
+  producer_nh<NC_, NWX_, PL>(nh, g, s, X, ld, rowwise, nout, K, KB, exps, pl, planes, plane_elems)
   if (nc == 2) { if (nwx <= 8) OZ_PROD(2, 8); else OZ_PROD(2, 12); }
   else if (nc == 3) { if (nwx <= 8) OZ_PROD(3, 8); else OZ_PROD(3, 12); }
   else { if (nwx <= 8) OZ_PROD(4, 8); else OZ_PROD(4, 12); }
 #undef OZ_PROD
+}
+
+hipError_t launch_producer(int nc, int nwx, int nh, const double *X, int64_t ld, int rowwise,
+                           int64_t nout, int64_t noutp, int64_t K, int64_t Kp,
+                           const int32_t *exps, const DevPlan *pl, int backend, void *planes,
+                           int64_t plane_elems, hipStream_t s) {
+  const int64_t KB = Kp / 64, OB = noutp / 16;
+  if (KB <= 0 || OB <= 0) return hipSuccess;
+  dim3 g((unsigned)KB, (unsigned)OB);
+  if (backend == PLANES_F8)
+    producer_pl<PL_F8>(nc, nwx, nh, g, s, X, ld, rowwise, nout, K, KB, exps, pl, planes, plane_elems);
+  else if (backend == PLANES_F64)
+    producer_pl<PL_F64>(nc, nwx, nh, g, s, X, ld, rowwise, nout, K, KB, exps, pl, planes, plane_elems);
+  else
+    producer_pl<PL_I8>(nc, nwx, nh, g, s, X, ld, rowwise, nout, K, KB, exps, pl, planes, plane_elems);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_f8(const uint8_t *pa, const uint8_t *pb, uint8_t *tpl, const DevPlan *pl,
+                          int ng, int nmod, int64_t Mp, int64_t Np, int64_t Kp, int64_t planeA,
+                          int64_t planeB, hipStream_t s) {
+  const int64_t prods = (int64_t)ng * nmod;
+  if (prods <= 0 || Mp <= 0 || Np <= 0) return hipSuccess;
+  if (Mp % 128 || Np % 128 || Kp % 128) return hipErrorInvalidValue;
+  const int tilesM = (int)(Mp / 128), tilesN = (int)(Np / 128);
+  hipLaunchKernelGGL(k_gemm_f8, dim3((unsigned)(prods * tilesM * tilesN)), dim3(512), 0, s, pa, pb,
+                     tpl, pl, Mp, Np, Kp / 64, planeA, planeB, tilesM, tilesN);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_f64(const double *pa, const double *pb, uint32_t *tpl, const DevPlan *pl,
+                           int ng, int nmod, int64_t Mp, int64_t Np, int64_t Kp, int64_t planeA,
+                           int64_t planeB, hipStream_t s) {
+  const int64_t prods = (int64_t)ng * nmod;
+  if (prods <= 0 || Mp <= 0 || Np <= 0) return hipSuccess;
+  if (Mp % 128 || Np % 128 || Kp % 64) return hipErrorInvalidValue;
+  const int tilesM = (int)(Mp / 128), tilesN = (int)(Np / 128);
+  hipLaunchKernelGGL(k_gemm_f64, dim3((unsigned)(prods * tilesM * tilesN)), dim3(256), 0, s, pa,
+                     pb, tpl, pl, Mp, Np, Kp / 8, planeA, planeB, tilesM, tilesN);
   return hipGetLastError();
 }
 
@@ -563,16 +871,26 @@ hipError_t launch_gemm_i8(const int8_t *pa, const int8_t *pb, uint8_t *tpl, cons
   return hipGetLastError();
 }
 
-hipError_t launch_consumer(int nc, int nwc, int nd, const uint8_t *tpl, int64_t Mp, int64_t Np,
-                           double *C, int64_t ldc, int64_t M, int64_t N, const int32_t *ea,
-                           const int32_t *eb, const DevPlan *pl, int mode, hipStream_t s) {
+hipError_t launch_consumer(int nc, int nwc, int nd, const void *tpl, int tbytes, int64_t Mp,
+                           int64_t Np, double *C, int64_t ldc, int64_t M, int64_t N,
+                           const int32_t *ea, const int32_t *eb, const DevPlan *pl, int mode,
+                           hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
   dim3 g((unsigned)((M + 255) / 256), (unsigned)N);
-#define OZ_CONS(NC_, NWC_, ND_)                                                             \
-  hipLaunchKernelGGL((k_consumer<NC_, NWC_, ND_>), g, dim3(256), 0, s, tpl, Mp, Np, C, ldc, M, \
-                     N, ea, eb, pl, mode)
-#define OZ_CONS_ND(NC_, NWC_) \
-  do { if (nd <= 18) OZ_CONS(NC_, NWC_, 18); else OZ_CONS(NC_, NWC_, 24); } while (0)
+#define OZ_CONS(NC_, NWC_, ND_, TT_)                                                            \
+  hipLaunchKernelGGL((k_consumer<NC_, NWC_, ND_, TT_>), g, dim3(256), 0, s, (const TT_ *)tpl, Mp, \
+                     Np, C, ldc, M, N, ea, eb, pl, mode)
+#define OZ_CONS_ND(NC_, NWC_)                                  \
+  do {                                                        \
+    if (tbytes == 1) {                                        \
+      if (nd <= 18) OZ_CONS(NC_, NWC_, 18, uint8_t);          \
+      else OZ_CONS(NC_, NWC_, 24, uint8_t);                   \
+    } else {                                                  \
+      if (nd <= 18) OZ_CONS(NC_, NWC_, 18, uint32_t);         \
+      else OZ_CONS(NC_, NWC_, 32, uint32_t);                  \
+    }                                                         \
+  } while (0)
+  if ((tbytes == 1 && nd > 24) || nd > 32) return hipErrorInvalidValue;
   if (nc == 2) { if (nwc <= 12) OZ_CONS_ND(2, 12); else OZ_CONS_ND(2, 16); }
   else if (nc == 3) { if (nwc <= 12) OZ_CONS_ND(3, 12); else OZ_CONS_ND(3, 16); }
   else { if (nwc <= 12) OZ_CONS_ND(4, 12); else OZ_CONS_ND(4, 16); }
@@ -581,11 +899,17 @@ hipError_t launch_consumer(int nc, int nwc, int nd, const uint8_t *tpl, int64_t 
   return hipGetLastError();
 }
 
-hipError_t launch_crt_export(const uint8_t *tpl, int64_t Mp, int64_t Np, int64_t M, int64_t N,
-                             const DevPlan *pl, uint64_t *out, int nlimb, hipStream_t s) {
+hipError_t launch_crt_export(const void *tpl, int tbytes, int64_t Mp, int64_t Np, int64_t M,
+                             int64_t N, const DevPlan *pl, uint64_t *out, int nlimb,
+                             hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
   dim3 g((unsigned)((M + 255) / 256), (unsigned)N);
-  hipLaunchKernelGGL(k_crt_export, g, dim3(256), 0, s, tpl, Mp, Np, M, N, pl, out, nlimb);
+  if (tbytes == 1)
+    hipLaunchKernelGGL(k_crt_export<uint8_t>, g, dim3(256), 0, s, (const uint8_t *)tpl, Mp, Np, M,
+                       N, pl, out, nlimb);
+  else
+    hipLaunchKernelGGL(k_crt_export<uint32_t>, g, dim3(256), 0, s, (const uint32_t *)tpl, Mp, Np,
+                       M, N, pl, out, nlimb);
   return hipGetLastError();
 }
 

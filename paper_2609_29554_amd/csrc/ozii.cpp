@@ -60,6 +60,31 @@ std::vector<int> int8_moduli() {
   return out;
 }
 
+// binary64-moduli back-end (Sec. "binary64 back-end", Eq. fp64mod): the
+// F64_MAXMOD largest primes m with K S m^2 < 2^53, descending, so that every
+// digit-group product (inner dimension K npairs <= K S) accumulates exactly
+// in FP64.  At most 20 of them: read this way the plan reproduces the
+// DD/TD/QD GEMM counts 13/18/36 printed for K = 512.
+constexpr int F64_MAXMOD = 20;
+
+bool is_prime(int64_t n) {
+  if (n < 2) return false;
+  for (int64_t d = 2; d * d <= n; ++d)
+    if (n % d == 0) return false;
+  return true;
+}
+
+std::vector<int> f64_moduli(int64_t K, int S) {
+  std::vector<int> out;
+  const double ks = (double)K * S;
+  int64_t m = (int64_t)std::floor(std::sqrt(9007199254740992.0 / ks)) + 2;
+  for (; m > 2 && (int)out.size() < F64_MAXMOD; --m) {
+    if (ks * (double)m * (double)m >= 9007199254740992.0) continue;  // exact: all terms < 2^53
+    if (is_prime(m)) out.push_back((int)m);
+  }
+  return out;
+}
+
 struct HostPlan {
   int p = 0;
   int64_t K = 0;
@@ -68,12 +93,25 @@ struct HostPlan {
   int nwx = 0, nh = 0, nwc = 0, nd = 0;
   double need = 0;
   std::vector<int> mods;
+  // storage of one back-end: bytes per plane element, planes per (slice,
+  // modulus), bytes per t-value, inner-dimension padding
+  int el_bytes() const { return backend == OZII_BE_F64MOD ? 8 : 1; }
+  int planes_per() const { return backend == OZII_BE_FP8_B17 ? 2 : 1; }
+  int t_bytes() const { return backend == OZII_BE_F64MOD ? 4 : 1; }
+  int k_align() const { return backend == OZII_BE_FP8_B17 ? 128 : 64; }
+  int planes_kind() const {
+    return backend == OZII_BE_F64MOD ? ozl::PLANES_F64
+                                     : backend == OZII_BE_FP8_B17 ? ozl::PLANES_F8 : ozl::PLANES_I8;
+  }
 };
 
+// Accumulator bounds: INT8 K S 128^2 < 2^31 (residues in [-128, 127]); FP8
+// the same (it also keeps 2 K S 64 < 2^24, so the three FP32 sub-product
+// accumulators are exact); binary64 holds by the choice of the moduli.
 bool accum_ok(int backend, int64_t K, int S) {
   const double ks = (double)K * S;
   if (backend == OZII_BE_INT8) return ks * 128.0 * 128.0 < 2147483648.0;
-  if (backend == OZII_BE_FP8_B17) return ks * 128.0 * 128.0 < 2147483648.0 && ks * 64.0 < 16777216.0;
+  if (backend == OZII_BE_FP8_B17) return ks * 128.0 * 128.0 < 2147483648.0 && 2.0 * ks * 64.0 < 16777216.0;
   return true;
 }
 
@@ -88,16 +126,18 @@ ozII_status make_plan(int p, int64_t K, const ozII_opts *o, HostPlan &pl, std::s
     if (why) *why = "gemm_tile must be 0..3";
     return OZII_EINVAL;
   }
-  if (backend != OZII_BE_INT8) {
-    if (why) *why = "only the INT8 back-end is built";
-    return OZII_EUNSUPPORTED;
+  if (backend < OZII_BE_INT8 || backend > OZII_BE_F64MOD) {
+    if (why) *why = "unknown back-end";
+    return OZII_EINVAL;
   }
-  const std::vector<int> mods = int8_moduli();
+  const std::vector<int> mods8 = int8_moduli();
   const int slack = (int)std::ceil(std::log2(2.0 * (double)K)) + 16 + gex;
   const int s_lo = nslice > 0 ? nslice : 1, s_hi = nslice > 0 ? nslice : 4096;
   bool any_acc = false;
   for (int S = s_lo; S <= s_hi; ++S) {
     if (!accum_ok(backend, K, S)) continue;
+    const std::vector<int> mods = backend == OZII_BE_F64MOD ? f64_moduli(K, S) : mods8;
+    if (mods.empty()) continue;
     any_acc = true;
     const int w = (p + slack + S - 1) / S;
     const double need = 2.0 * w + std::log2((double)K) + std::log2((double)S) + 5.0;
@@ -133,13 +173,14 @@ ozII_status make_plan(int p, int64_t K, const ozII_opts *o, HostPlan &pl, std::s
       const int bits = (int)std::ceil(lp + std::log2((double)N)) + 2;
       pl.nd = ((bits + 15) / 16 + 1) & ~1;
     }
-    if (check_sizes && (pl.nwx > 12 || pl.nh > ozk::NHMAX || pl.nwc > 16 || w > 300)) {
+    if (check_sizes && (pl.nwx > 12 || pl.nh > ozk::NHMAX || pl.nwc > 16 || w > 300 ||
+                        pl.nd > (backend == OZII_BE_F64MOD ? 32 : 24))) {
       if (why) *why = "plan exceeds the compiled word sizes";
       return OZII_EUNSUPPORTED;
     }
     return OZII_OK;
   }
-  if (why) *why = any_acc ? "need exceeds the 362.8-bit CRT capacity" : "accumulator bound";
+  if (why) *why = any_acc ? "need exceeds the CRT capacity of the modulus set" : "accumulator bound";
   return any_acc ? OZII_ECAPACITY : OZII_EOVERFLOW;
 }
 
@@ -187,14 +228,16 @@ void build_devplan(const HostPlan &hp, DevPlan &dp) {
     Big Ml{1};
     for (int k = 0; k < hp.nmod; ++k)
       if (k != l) big_mul_small(Ml, (uint32_t)hp.mods[k]);
-    const uint32_t r = big_mod_small(Ml, m);
-    uint32_t y = 0;
-    for (uint32_t c = 1; c < m; ++c)
-      if ((uint64_t)r * c % m == 1) {
-        y = c;
-        break;
-      }
-    dp.y[l] = (int32_t)y;
+    // y_l = M_l^{-1} mod m_l by the extended Euclidean algorithm
+    int64_t r0 = (int64_t)m, r1 = (int64_t)big_mod_small(Ml, m), s0 = 0, s1 = 1;
+    while (r1 != 0) {
+      const int64_t qq = r0 / r1, r2 = r0 - qq * r1, s2 = s0 - qq * s1;
+      r0 = r1;
+      r1 = r2;
+      s0 = s1;
+      s1 = s2;
+    }
+    dp.y[l] = (int32_t)(((s0 % (int64_t)m) + (int64_t)m) % (int64_t)m);
     for (int k = 0; k < ozk::NDCRT; ++k) dp.Mdig[l][k] = big_digit16(Ml, k);
     uint64_t pw = 1 % m;
     for (int k = 0; k < ozk::NHMAX; ++k) {
@@ -322,10 +365,10 @@ GemmLayout gemm_layout(const HostPlan &hp, int64_t M, int64_t N, int64_t K, int 
   // once they exceed one 128-wide tile (or when such a tile is forced)
   L.Mp = roundup(std::max<int64_t>(M, 1), (M > 128 || tile >= ozl::GEMM_TILE_256x128) ? 256 : 128);
   L.Np = roundup(std::max<int64_t>(N, 1), (N > 128 || tile == ozl::GEMM_TILE_256x256) ? 256 : 128);
-  L.Kp = roundup(std::max<int64_t>(K, 1), 64);
-  L.planeA = L.Mp * L.Kp;
+  L.Kp = roundup(std::max<int64_t>(K, 1), hp.k_align());
+  L.planeA = L.Mp * L.Kp;  // elements per plane
   L.planeB = L.Np * L.Kp;
-  L.tplBytes = (int64_t)hp.ng * hp.nmod * L.Mp * L.Np;
+  L.tplBytes = (int64_t)hp.ng * hp.nmod * L.Mp * L.Np * hp.t_bytes();
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t r = o;
@@ -334,8 +377,8 @@ GemmLayout gemm_layout(const HostPlan &hp, int64_t M, int64_t N, int64_t K, int 
   };
   L.off_ea = take(sizeof(int32_t) * L.Mp);
   L.off_eb = take(sizeof(int32_t) * L.Np);
-  L.off_pa = take((size_t)hp.S * hp.nmod * L.planeA);
-  L.off_pb = take((size_t)hp.S * hp.nmod * L.planeB);
+  L.off_pa = take((size_t)hp.S * hp.nmod * hp.planes_per() * L.planeA * hp.el_bytes());
+  L.off_pb = take((size_t)hp.S * hp.nmod * hp.planes_per() * L.planeB * hp.el_bytes());
   L.off_tpl = take((size_t)L.tplBytes);
   L.total = o;
   return L;
@@ -401,7 +444,7 @@ bool valid_nc(int nc) { return nc >= 2 && nc <= 4; }
 ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64_t K,
                       const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
                       int64_t ldc, const ozII_opts *o, int32_t *ea_out, int32_t *eb_out,
-                      int8_t *pa_out, int8_t *pb_out, uint8_t *tpl_out, uint64_t *sbar_out,
+                      void *pa_out, void *pb_out, void *tpl_out, uint64_t *sbar_out,
                       int nlimb) {
   if (!h) return OZII_EINVAL;
   if (!valid_nc(nc)) return fail(h, OZII_EUNSUPPORTED, "nc must be 2, 3 or 4");
@@ -426,9 +469,9 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
   if (st != OZII_OK) return st;
   int32_t *ea = (int32_t *)(h->ws + L.off_ea);
   int32_t *eb = (int32_t *)(h->ws + L.off_eb);
-  int8_t *pa = (int8_t *)(h->ws + L.off_pa);
-  int8_t *pb = (int8_t *)(h->ws + L.off_pb);
-  uint8_t *tpl = (uint8_t *)(h->ws + L.off_tpl);
+  void *pa = h->ws + L.off_pa;
+  void *pb = h->ws + L.off_pb;
+  void *tpl = h->ws + L.off_tpl;
   hipStream_t s = h->stream;
   hipError_t e;
   const double pairs = (double)hp->nmod * [&] {
@@ -438,38 +481,55 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
         if (g - ta >= 0 && g - ta < hp->S) ++np;
     return np;
   }();
+  // algorithmic bytes of the residue planes and t-planes of this back-end
+  const double res_bytes = (double)hp->S * hp->nmod * hp->planes_per() * hp->el_bytes();
+  const double t_bytes = (double)hp->ng * hp->nmod * hp->t_bytes();
   {
     ProfScope ps(h, OZ_STAGE_EXP, 8.0 * nc * (double)(M * K + K * N), 0);
     if ((e = ozl::launch_exponents(nc, A, lda, M, K, 1, ea, s)) != hipSuccess) return hip_fail(h, e, "exponents(A)");
     if ((e = ozl::launch_exponents(nc, B, ldb, K, N, 0, eb, s)) != hipSuccess) return hip_fail(h, e, "exponents(B)");
   }
   {
-    ProfScope ps(h, OZ_STAGE_PRODUCER, (double)(M + N) * K * (8.0 * nc + (double)hp->S * hp->nmod), 0);
-    if ((e = ozl::launch_producer(nc, hp->nwx, hp->nh, A, lda, 1, M, L.Mp, K, L.Kp, ea, dp, pa, L.planeA, s)) != hipSuccess)
+    ProfScope ps(h, OZ_STAGE_PRODUCER, (double)(M + N) * K * (8.0 * nc + res_bytes), 0);
+    if ((e = ozl::launch_producer(nc, hp->nwx, hp->nh, A, lda, 1, M, L.Mp, K, L.Kp, ea, dp,
+                                  hp->planes_kind(), pa, L.planeA, s)) != hipSuccess)
       return hip_fail(h, e, "producer(A)");
-    if ((e = ozl::launch_producer(nc, hp->nwx, hp->nh, B, ldb, 0, N, L.Np, K, L.Kp, eb, dp, pb, L.planeB, s)) != hipSuccess)
+    if ((e = ozl::launch_producer(nc, hp->nwx, hp->nh, B, ldb, 0, N, L.Np, K, L.Kp, eb, dp,
+                                  hp->planes_kind(), pb, L.planeB, s)) != hipSuccess)
       return hip_fail(h, e, "producer(B)");
   }
   {
-    ProfScope ps(h, OZ_STAGE_GEMM, (double)hp->S * hp->nmod * (double)(M + N) * K + (double)hp->ng * hp->nmod * M * N,
-                 2.0 * (double)M * N * K * pairs);
-    if ((e = ozl::launch_gemm_i8(pa, pb, tpl, dp, hp->ng, hp->nmod, L.Mp, L.Np, L.Kp, L.planeA, L.planeB,
-                                  o ? o->gemm_tile : 0, s)) != hipSuccess)
-      return hip_fail(h, e, "gemm_i8");
+    // issued operations: the FP8 back-end runs four sub-products per pair
+    const double ops = 2.0 * (double)M * N * K * pairs * (hp->backend == OZII_BE_FP8_B17 ? 4.0 : 1.0);
+    ProfScope ps(h, OZ_STAGE_GEMM, res_bytes * (double)(M + N) * K + t_bytes * M * N, ops);
+    if (hp->backend == OZII_BE_FP8_B17)
+      e = ozl::launch_gemm_f8((const uint8_t *)pa, (const uint8_t *)pb, (uint8_t *)tpl, dp, hp->ng,
+                              hp->nmod, L.Mp, L.Np, L.Kp, L.planeA, L.planeB, s);
+    else if (hp->backend == OZII_BE_F64MOD)
+      e = ozl::launch_gemm_f64((const double *)pa, (const double *)pb, (uint32_t *)tpl, dp, hp->ng,
+                               hp->nmod, L.Mp, L.Np, L.Kp, L.planeA, L.planeB, s);
+    else
+      e = ozl::launch_gemm_i8((const int8_t *)pa, (const int8_t *)pb, (uint8_t *)tpl, dp, hp->ng,
+                              hp->nmod, L.Mp, L.Np, L.Kp, L.planeA, L.planeB,
+                              o ? o->gemm_tile : 0, s);
+    if (e != hipSuccess) return hip_fail(h, e, "modular gemm");
   }
+  const size_t pl_bytes_a = (size_t)hp->S * hp->nmod * hp->planes_per() * L.planeA * hp->el_bytes();
+  const size_t pl_bytes_b = (size_t)hp->S * hp->nmod * hp->planes_per() * L.planeB * hp->el_bytes();
   if (ea_out && (e = hipMemcpyAsync(ea_out, ea, 4 * M, hipMemcpyDeviceToDevice, s)) != hipSuccess) return hip_fail(h, e, "copy ea");
   if (eb_out && (e = hipMemcpyAsync(eb_out, eb, 4 * N, hipMemcpyDeviceToDevice, s)) != hipSuccess) return hip_fail(h, e, "copy eb");
-  if (pa_out && (e = hipMemcpyAsync(pa_out, pa, (size_t)hp->S * hp->nmod * L.planeA, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+  if (pa_out && (e = hipMemcpyAsync(pa_out, pa, pl_bytes_a, hipMemcpyDeviceToDevice, s)) != hipSuccess)
     return hip_fail(h, e, "copy planesA");
-  if (pb_out && (e = hipMemcpyAsync(pb_out, pb, (size_t)hp->S * hp->nmod * L.planeB, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+  if (pb_out && (e = hipMemcpyAsync(pb_out, pb, pl_bytes_b, hipMemcpyDeviceToDevice, s)) != hipSuccess)
     return hip_fail(h, e, "copy planesB");
   if (tpl_out && (e = hipMemcpyAsync(tpl_out, tpl, (size_t)L.tplBytes, hipMemcpyDeviceToDevice, s)) != hipSuccess)
     return hip_fail(h, e, "copy tpl");
-  if (sbar_out && (e = ozl::launch_crt_export(tpl, L.Mp, L.Np, M, N, dp, sbar_out, nlimb, s)) != hipSuccess)
+  if (sbar_out && (e = ozl::launch_crt_export(tpl, hp->t_bytes(), L.Mp, L.Np, M, N, dp, sbar_out, nlimb, s)) != hipSuccess)
     return hip_fail(h, e, "crt_export");
   {
-    ProfScope ps(h, OZ_STAGE_CONSUMER, (double)M * N * ((double)hp->ng * hp->nmod + 8.0 * nc * (mode ? 2 : 1)), 0);
-    if ((e = ozl::launch_consumer(nc, hp->nwc, hp->nd, tpl, L.Mp, L.Np, C, ldc, M, N, ea, eb, dp, mode, s)) != hipSuccess)
+    ProfScope ps(h, OZ_STAGE_CONSUMER, (double)M * N * (t_bytes + 8.0 * nc * (mode ? 2 : 1)), 0);
+    if ((e = ozl::launch_consumer(nc, hp->nwc, hp->nd, tpl, hp->t_bytes(), L.Mp, L.Np, C, ldc, M, N,
+                                  ea, eb, dp, mode, s)) != hipSuccess)
       return hip_fail(h, e, "consumer");
   }
   return OZII_OK;
@@ -570,8 +630,8 @@ ozII_status ozII_gemm(ozII_handle h, int32_t mode, int32_t nc, int64_t M, int64_
 ozII_status ozII_gemm_stages(ozII_handle h, int32_t mode, int32_t nc, int64_t M, int64_t N,
                              int64_t K, const double *A, int64_t lda, const double *B,
                              int64_t ldb, double *C, int64_t ldc, const ozII_opts *o,
-                             int32_t *ea, int32_t *eb, int8_t *planesA, int8_t *planesB,
-                             uint8_t *tpl, uint64_t *sbar, int32_t nlimb) {
+                             int32_t *ea, int32_t *eb, void *planesA, void *planesB,
+                             void *tpl, uint64_t *sbar, int32_t nlimb) {
   if (sbar && (nlimb < 1 || nlimb > 6)) return fail(h, OZII_EINVAL, "nlimb must be 1..6");
   return gemm_impl(h, mode, nc, M, N, K, A, lda, B, ldb, C, ldc, o, ea, eb, planesA, planesB, tpl,
                    sbar, nlimb);

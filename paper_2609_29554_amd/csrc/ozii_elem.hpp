@@ -7,13 +7,15 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #define OZ_HD __host__ __device__ __forceinline__
 
 namespace ozk {
 
 constexpr int MAXMOD = 64;   // moduli a plan may use
 constexpr int NHMAX = 20;    // 16-bit digits of one slice (w <= 300)
-constexpr int NDCRT = 24;    // 16-bit digits of sum_l t_l M_l (log2 P <= 363)
+constexpr int NDCRT = 32;    // 16-bit digits of sum_l t_l M_l (log2 P <= 470)
 constexpr int32_t EXP_ZERO = INT32_MIN;
 
 // Tables of one plan, resident in device memory (read with uniform indices).
@@ -124,9 +126,17 @@ OZ_HD uint32_t mod_small(double x, int32_t m, double inv_m) {
 }
 
 // Residues mod every modulus of the NH 16-bit digits dig (an unsigned value):
-// r_l = (sum_k dig_k (2^16k mod m_l)) mod m_l
-template <int NH>
+// r_l = (sum_k dig_k (2^16k mod m_l)) mod m_l.  WIDE: moduli up to 2^23 (the
+// binary64 back-end), summed in 64 bits (< 2^44); otherwise m <= 256 and the
+// sum stays below 2^29.
+template <int NH, bool WIDE>
 OZ_HD uint32_t digits_mod(const uint32_t (&dig)[NH], const DevPlan *pl, int l) {
+  if (WIDE) {
+    uint64_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < NH; ++k) acc += (uint64_t)dig[k] * pl->pw16[l][k];
+    return mod_small((double)acc, pl->m[l], pl->inv_m[l]);
+  }
   uint32_t acc = 0;
 #pragma unroll
   for (int k = 0; k < NH; ++k) acc += dig[k] * pl->pw16[l][k];
@@ -145,25 +155,29 @@ OZ_HD int32_t centre(uint32_t r, int32_t m) {
 // the top one, which carries the sign).
 // ---------------------------------------------------------------------------
 // ND digits (ND*16 bits) must hold sum_l t_l M_l < nmod P; the plan checks.
-template <int ND = NDCRT>
-OZ_HD void crt_digits(const uint8_t *t, int64_t stride, const DevPlan *pl, int32_t (&d)[ND]) {
+// TT: uint8_t t-values (moduli <= 256: digit sums t M_dig < 2^24 each, summed
+// in int32) or uint32_t (moduli < 2^23: products < 2^39, summed in int64).
+template <int ND, class TT>
+OZ_HD void crt_digits(const TT *t, int64_t stride, const DevPlan *pl, int32_t (&d)[ND]) {
+  typedef typename std::conditional<sizeof(TT) == 1, int32_t, int64_t>::type Acc;
+  Acc a[ND];
 #pragma unroll
-  for (int k = 0; k < ND; ++k) d[k] = 0;
+  for (int k = 0; k < ND; ++k) a[k] = 0;
   double F = 0.0;
   for (int l = 0; l < pl->nmod; ++l) {
-    uint32_t tl = t[l * stride];
+    const uint32_t tl = (uint32_t)t[l * stride];
     F += (double)tl * pl->inv_m[l];
 #pragma unroll
-    for (int k = 0; k < ND; ++k) d[k] += (int32_t)(tl * (uint32_t)pl->Mdig[l][k]);
+    for (int k = 0; k < ND; ++k) a[k] += (Acc)tl * (Acc)pl->Mdig[l][k];
   }
-  int32_t q = (int32_t)__builtin_floor(F + 0.5);
+  const Acc q = (Acc)__builtin_floor(F + 0.5);
 #pragma unroll
-  for (int k = 0; k < ND; ++k) d[k] -= q * (int32_t)pl->Pdig[k];
-  int32_t carry = 0;
+  for (int k = 0; k < ND; ++k) a[k] -= q * (Acc)pl->Pdig[k];
+  Acc carry = 0;
 #pragma unroll
   for (int k = 0; k < ND; ++k) {
-    int32_t v = d[k] + carry;
-    d[k] = v & 0xffff;
+    Acc v = a[k] + carry;
+    d[k] = (int32_t)(v & 0xffff);
     carry = v >> 16;  // arithmetic
   }
   // |Sbar| < P/2 fits the ND digits, so they are the two's complement of Sbar
@@ -271,7 +285,7 @@ OZ_HD void round_out(uint32_t (&cb)[NW], int eps, double (&x)[NC]) {
 // ---------------------------------------------------------------------------
 constexpr int STG = 29;
 
-template <int NC, int NWX, int NH, class Store>
+template <int NC, int NWX, int NH, bool WIDE, class Store>
 OZ_HD void produce_element(const double *src, int mu, const DevPlan *pl, uint32_t *st, Store store) {
   static_assert(NWX + 16 <= STG, "staging too small");
   const int S = pl->S, w = pl->w, nmod = pl->nmod;
@@ -312,7 +326,7 @@ OZ_HD void produce_element(const double *src, int mu, const DevPlan *pl, uint32_
     }
     for (int l = 0; l < nmod; ++l) {
       const int32_t m = pl->m[l];
-      uint32_t r = digits_mod<NH>(dig, pl, l);
+      uint32_t r = digits_mod<NH, WIDE>(dig, pl, l);
       if (t < S - 1) {
         if (flag) {
           r += (uint32_t)m - pl->p2w[l];  // r - 2^w (mod m)
@@ -321,7 +335,7 @@ OZ_HD void produce_element(const double *src, int mu, const DevPlan *pl, uint32_
       } else if (neg) {
         r = r == 0 ? 0u : (uint32_t)m - r;
       }
-      store(t, l, (int8_t)centre(r, m));
+      store(t, l, centre(r, m));
     }
     if (t < S - 1) {
       // X <- (X >> w) + flag, an exact division since the slice was removed
@@ -353,7 +367,7 @@ OZ_HD void produce_element(const double *src, int mu, const DevPlan *pl, uint32_
 // ---------------------------------------------------------------------------
 constexpr int CST = 33;
 
-template <int NC, int NWC, int ND, class TPtr>
+template <int NC, int NWC, int ND, class TT, class TPtr>
 OZ_HD void consume_element(TPtr tptr, int64_t pstride, const DevPlan *pl, uint32_t *st, bool zero,
                            int eps, double (&c)[NC]) {
   static_assert(ND % 2 == 0 && ND <= NDCRT, "digits");
@@ -364,7 +378,7 @@ OZ_HD void consume_element(TPtr tptr, int64_t pstride, const DevPlan *pl, uint32
   for (int k = 0; k < NWC; ++k) cb[k] = 0u;
   for (int gi = 0; gi < ng; ++gi) {
     int32_t d[ND];
-    crt_digits<ND>(tptr(gi), pstride, pl, d);
+    crt_digits<ND, TT>(tptr(gi), pstride, pl, d);
     const uint32_t fill = d[ND - 1] < 0 ? 0xffffffffu : 0u;
 #pragma unroll
     for (int k = 0; k < ND / 2; ++k)

@@ -36,18 +36,28 @@ inline int gemm_tile_auto(int64_t prods, int64_t Mp, int64_t Np) {
 // Ozaki-II product stages
 hipError_t launch_exponents(int nc, const double *X, int64_t ld, int64_t rows, int64_t cols,
                             int rowwise, int32_t *e, hipStream_t s);
+// plane encodings of the producer (one per back-end)
+enum { PLANES_I8 = 0, PLANES_F8 = 1, PLANES_F64 = 2 };
 hipError_t launch_producer(int nc, int nwx, int nh, const double *X, int64_t ld, int rowwise,
                            int64_t nout, int64_t noutp, int64_t K, int64_t Kp,
-                           const int32_t *exps, const DevPlan *pl, int8_t *planes,
-                           int64_t plane_bytes, hipStream_t s);
+                           const int32_t *exps, const DevPlan *pl, int planes_kind, void *planes,
+                           int64_t plane_elems, hipStream_t s);
 hipError_t launch_gemm_i8(const int8_t *pa, const int8_t *pb, uint8_t *tpl, const DevPlan *pl,
                           int ng, int nmod, int64_t Mp, int64_t Np, int64_t Kp, int64_t planeA,
                           int64_t planeB, int tile, hipStream_t s);
-hipError_t launch_consumer(int nc, int nwc, int nd, const uint8_t *tpl, int64_t Mp, int64_t Np,
-                           double *C, int64_t ldc, int64_t M, int64_t N, const int32_t *ea,
-                           const int32_t *eb, const DevPlan *pl, int mode, hipStream_t s);
-hipError_t launch_crt_export(const uint8_t *tpl, int64_t Mp, int64_t Np, int64_t M, int64_t N,
-                             const DevPlan *pl, uint64_t *out, int nlimb, hipStream_t s);
+hipError_t launch_gemm_f8(const uint8_t *pa, const uint8_t *pb, uint8_t *tpl, const DevPlan *pl,
+                          int ng, int nmod, int64_t Mp, int64_t Np, int64_t Kp, int64_t planeA,
+                          int64_t planeB, hipStream_t s);
+hipError_t launch_gemm_f64(const double *pa, const double *pb, uint32_t *tpl, const DevPlan *pl,
+                           int ng, int nmod, int64_t Mp, int64_t Np, int64_t Kp, int64_t planeA,
+                           int64_t planeB, hipStream_t s);
+hipError_t launch_consumer(int nc, int nwc, int nd, const void *tpl, int tbytes, int64_t Mp,
+                           int64_t Np, double *C, int64_t ldc, int64_t M, int64_t N,
+                           const int32_t *ea, const int32_t *eb, const DevPlan *pl, int mode,
+                           hipStream_t s);
+hipError_t launch_crt_export(const void *tpl, int tbytes, int64_t Mp, int64_t Np, int64_t M,
+                             int64_t N, const DevPlan *pl, uint64_t *out, int nlimb,
+                             hipStream_t s);
 
 // LU pieces
 size_t panel_lds_bytes(int nc, int kb, int R, int64_t nr);

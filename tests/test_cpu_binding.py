@@ -55,8 +55,18 @@ def test_plan_options_and_errors():
             Z.plan_query(212, 256, Z.make_opts(gemm_tile=bad))
         assert e.value.status == Z.EINVAL
     with pytest.raises(Z.OziiError) as e:
-        Z.plan_query(212, 256, Z.make_opts(backend=Z.BE_F64MOD))
-    assert e.value.status == Z.EUNSUPPORTED
+        Z.plan_query(212, 256, Z.make_opts(backend=7))
+    assert e.value.status == Z.EINVAL
+
+
+@pytest.mark.parametrize("be", [2, 3], ids=["fp8", "f64"])
+@pytest.mark.parametrize("p,K", [(106, 32), (159, 512), (212, 256), (212, 512), (212, 4096)])
+def test_backend_plans_match_oracle(be, p, K):
+    Z = _lib()
+    import oracle as O
+    got = Z.plan_query(p, K, Z.make_opts(backend=be))
+    pl = O.make_plan(p, K, backend=be)
+    assert got == (pl.S, pl.w, pl.Q, pl.nmod, pl.moduli)
 
 
 def test_status_strings():

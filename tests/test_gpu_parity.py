@@ -91,6 +91,74 @@ def test_gemm_stages_bit_exact(case, tile):
     assert np.array_equal(to_host(dC1), C1ref)
 
 
+def _e4m3_table():
+    """Integer value of every E4M3 byte that encodes an integer in [-16, 16],
+    from the OCP format definition (bias 7, 3 fraction bits)."""
+    from fractions import Fraction
+    tab = {}
+    for b in range(256):
+        e, f = (b >> 3) & 15, b & 7
+        if e == 15 and f == 7:
+            continue  # NaN
+        v = (Fraction(f, 8) * Fraction(2) ** -6) if e == 0 else (1 + Fraction(f, 8)) * Fraction(2) ** (e - 7)
+        v = -v if b & 0x80 else v
+        if v.denominator == 1 and abs(v) <= 16:
+            tab[b] = int(v)
+    return tab
+
+
+BACKEND_CASES = [c for c in STAGE_CASES if c[1] * c[2] > 1][:6] + [(2, 300, 130, 448, 1, 0)]
+
+
+@pytest.mark.parametrize("backend", [O.BACKEND_FP8_B17, O.BACKEND_F64MOD], ids=["fp8", "f64"])
+@pytest.mark.parametrize("case", BACKEND_CASES, ids=lambda c: "nc{}-{}x{}x{}-S{}-E{}".format(*c))
+def test_gemm_stages_backends(case, backend):
+    """Residue (or digit) planes, t-planes, group sums and products of the
+    FP8 base-17 and binary64-moduli back-ends against the oracle."""
+    import paper_2609_29554_amd as Z
+    nc, M, N, K, S_f, E = case
+    note(f"gemm stages {case} backend {backend}")
+    A, B, C0 = _operands(nc, M, N, K, 100 + M + N + K)
+    pl = O.make_plan(53 * nc, K, backend=backend, nslice=S_f, extra_groups=E)
+    opts = Z.make_opts(backend=backend, nslice=S_f, extra_groups=E)
+    ea, eb = O.exponents(A, True), O.exponents(B, False)
+    ra, rb = O.residues(A, True, ea, pl), O.residues(B, False, eb, pl)
+    tpl = O.modgemm(ra, rb, pl)
+    Cref, sb = O.ozgemm(0, A, B, np.zeros((N, M, nc)), pl, want_sbar=True, nw_out=6)
+    C1ref, _ = O.ozgemm(1, A, B, C0, pl)
+
+    dA, dB = to_dev(A), to_dev(B)
+    dC = to_dev(np.zeros((N, M, nc)))
+    st = ctx().gemm_stages(0, dA, dB, dC, opts, nlimb=6)
+    d = st["dims"]
+    assert (d["S"], d["nmod"], d["ng"]) == (pl.S, pl.nmod, len(pl.groups))
+    P = pl.S * pl.nmod
+    ga = Z.unfragment(to_host(st["planesA"]), d["nplanes"], d["Mp"], d["Kp"], backend)
+    gb = Z.unfragment(to_host(st["planesB"]), d["nplanes"], d["Np"], d["Kp"], backend)
+    if backend == O.BACKEND_FP8_B17:
+        tab = _e4m3_table()
+        dec = np.vectorize(lambda b: tab[int(b)])
+        for g_, r_, n_ in ((ga, ra, M), (gb, rb, N)):
+            vals = dec(g_.reshape(P, 2, -1, d["Kp"]))
+            d0, d1 = O.fp8_digits(r_.reshape(P, n_, K))
+            assert np.array_equal(vals[:, 0, :n_, :K], d0)
+            assert np.array_equal(vals[:, 1, :n_, :K], d1)
+            assert not vals[:, :, n_:, :].any() and not vals[:, :, :, K:].any()
+    else:
+        assert np.array_equal(ga[:, :M, :K], ra.reshape(P, M, K))
+        assert np.array_equal(gb[:, :N, :K], rb.reshape(P, N, K))
+        assert not ga[:, M:, :].any() and not ga[:, :, K:].any()
+    gt = to_host(st["tpl"]).view(np.uint32 if backend == O.BACKEND_F64MOD else np.uint8)
+    gt = gt.reshape(len(pl.groups), pl.nmod, d["Np"], d["Mp"])
+    assert np.array_equal(gt[:, :, :N, :M], tpl)
+    gs = to_host(st["sbar"]).view(np.uint64).reshape(len(pl.groups), N, M, 6)
+    assert np.array_equal(gs, sb)
+    assert np.array_equal(to_host(dC), Cref)
+    dC1 = to_dev(C0)
+    ctx().gemm(1, dA, dB, dC1, opts)
+    assert np.array_equal(to_host(dC1), C1ref)
+
+
 LU_CASES = [
     # nc, n, b, kind
     (4, 100, 32, "lotkin"),
@@ -122,6 +190,33 @@ def test_getrf_getrs_bit_exact(case, method):
     X = O.getrs(LU, ipiv, rhs)
     dA = to_dev(A)
     dip, dinfo = ctx().getrf(dA, block=b, method=method)
+    ctx().sync_check()
+    assert int(to_host(dinfo)[0]) == info
+    assert np.array_equal(to_host(dip), ipiv)
+    assert np.array_equal(to_host(dA), LU)
+    dX = to_dev(rhs)
+    ctx().getrs(dA, dip, dX)
+    ctx().sync_check()
+    assert np.array_equal(to_host(dX), X)
+
+
+@pytest.mark.parametrize("backend", [O.BACKEND_FP8_B17, O.BACKEND_F64MOD], ids=["fp8", "f64"])
+@pytest.mark.parametrize("case", [(4, 100, 32, "lotkin"), (3, 129, 64, "graded"),
+                                  (2, 300, 128, "lotkin")],
+                         ids=lambda c: "nc{}-n{}-b{}-{}".format(*c))
+def test_getrf_getrs_backends(case, backend):
+    """The LU with its Schur updates on the FP8 / binary64 back-ends, against
+    the oracle LU with that back-end's plan."""
+    import paper_2609_29554_amd as Z
+    nc, n, b, kind = case
+    note(f"getrf/getrs {case} backend={backend}")
+    A = _matrix(nc, n, kind, 7 + n)
+    plan = O.make_plan(53 * nc, b, backend=backend)
+    LU, ipiv, info, _ = O.getrf(A, b, O.METHOD_OZAKI, plan=plan)
+    rhs = W.rhs_ones(A)
+    X = O.getrs(LU, ipiv, rhs)
+    dA = to_dev(A)
+    dip, dinfo = ctx().getrf(dA, block=b, opts=Z.make_opts(backend=backend))
     ctx().sync_check()
     assert int(to_host(dinfo)[0]) == info
     assert np.array_equal(to_host(dip), ipiv)
