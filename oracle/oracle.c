@@ -20,12 +20,12 @@
  * the residue / modular-GEMM / CRT mirror so that each stage can be compared.
  *
  * Expansion arithmetic (the panel, the triangular solves, the native update)
- * follows the written specification in DESIGN.md, section "Expansion
- * arithmetic": error-free TwoSum (Knuth) and TwoProd (FMA), a two-pass
- * renormalisation (bottom-up VecSum, then top-down error-branch compression,
- * after Joldes-Muller-Popescu) of terms first sorted by magnitude with
- * Batcher's merge-exchange network, partial products by order for
- * multiplication, long division.
+ * follows one written specification: error-free TwoSum (Knuth) and TwoProd
+ * (FMA); a two-pass renormalisation (bottom-up VecSum, then top-down
+ * error-branch compression, after Joldes-Muller-Popescu); addition merges the
+ * two operands by magnitude with Batcher's odd-even merge network before
+ * renormalising; multiplication sums partial products by order (Hida, Li,
+ * Bailey); division is long division.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -77,6 +77,8 @@ static void renorm(double *x, int k, int n, double *y) {
     if (j < n) y[j] = eps;
 }
 
+/* compare-exchange: the larger magnitude moves to the lower index; equal
+ * magnitudes stay where they are */
 static inline void ce(double *x, int i, int j) {
     if (fabs(x[j]) > fabs(x[i])) {
         double t = x[i];
@@ -85,65 +87,80 @@ static inline void ce(double *x, int i, int j) {
     }
 }
 
-/* Sort k terms by decreasing magnitude with Batcher's merge-exchange network
- * (Knuth, TAOCP vol. 3, Sec. 5.2.2, Algorithm M).  The network is a fixed
- * sequence of compare-exchanges, so the outcome (ties included) is fully
- * determined by the input. */
-static void sort_terms(double *x, int k) {
-    if (k < 2) return;
-    int t = 0;
-    while ((1 << t) < k) ++t;
-    for (int p = 1 << (t - 1); p > 0; p >>= 1) {
-        int q = 1 << (t - 1), r = 0, d = p;
-        for (;;) {
-            for (int i = 0; i + d < k; ++i)
-                if ((i & p) == r) ce(x, i, i + d);
-            if (q == p) break;
-            d = q - p;
-            q >>= 1;
-            r = p;
-        }
+/* Batcher's odd-even merge network (Knuth, TAOCP vol. 3, Sec. 5.3.4) on
+ * x[lo..hi] with comparator stride r, in the order of its recursive
+ * definition: merge the even and the odd subsequences, then compare
+ * neighbours.  Called as oe_merge(x, 0, 2m-1, 1) it merges two runs of m (a
+ * power of two) terms sorted by decreasing magnitude, x[0..m-1] and
+ * x[m..2m-1].  A fixed comparator sequence: the outcome, ties included, is a
+ * function of the input alone. */
+static void oe_merge(double *x, int lo, int hi, int r) {
+    int step = 2 * r;
+    if (step < hi - lo) {
+        oe_merge(x, lo, hi, step);
+        oe_merge(x, lo + r, hi, step);
+        for (int i = lo + r; i < hi - r; i += step) ce(x, i, i + r);
+    } else {
+        ce(x, lo, lo + r);
     }
 }
 
-/* r = a + b: all 2n components sorted by magnitude, then renormalised */
+/* r = a + b: the components of a and b (each a non-overlapping expansion,
+ * largest first) merged by magnitude -- triple-double operands padded with a
+ * zero to four -- then all 2m terms renormalised. */
 void orc_add(int n, const double *a, const double *b, double *r) {
     double x[2 * MAXNC];
-    for (int i = 0; i < n; ++i) {
-        x[i] = a[i];
-        x[n + i] = b[i];
+    int m = n == 3 ? 4 : n;
+    for (int i = 0; i < m; ++i) {
+        x[i] = i < n ? a[i] : 0.0;
+        x[m + i] = i < n ? b[i] : 0.0;
     }
-    sort_terms(x, 2 * n);
-    renorm(x, 2 * n, n, r);
+    oe_merge(x, 0, 2 * m - 1, 1);
+    renorm(x, 2 * m, n, r);
 }
 
-/* r = a * b: partial products grouped by order i+j; orders <= n-2 exact via
- * TwoProd (their errors move to the next order), order n-1 plain products,
- * orders >= n dropped. */
+/* r = a * b, partial products summed by order o = i + j (Hida, Li, Bailey's
+ * quad-double product, for any n):
+ *   orders o <= n-2: products by TwoProd, a_0 b_o first; their errors and
+ *   the terms carried into this order are added to the running sum by
+ *   TwoSum, each TwoSum error carried to order o+1 after the product errors;
+ *   order n-1: the plain products and everything carried, summed left to
+ *   right; orders >= n are dropped.
+ * The n order sums are then renormalised. */
 void orc_mul(int n, const double *a, const double *b, double *r) {
-    double terms[16];
-    double err[MAXNC + 1][MAXNC + 1];
-    int k = 0;
+    double s[MAXNC], carry[32], next[32], t[40];
+    int nc = 0;
     for (int o = 0; o < n; ++o) {
+        int nt = 0, nn = 0;
         for (int i = 0; i <= o; ++i) {
-            int j = o - i;
             if (o <= n - 2) {
                 double p, e;
-                two_prod(a[i], b[j], &p, &e);
-                terms[k++] = p;
-                err[o + 1][i] = e;
+                two_prod(a[i], b[o - i], &p, &e);
+                t[nt++] = p;
+                next[nn++] = e;
             } else {
-                terms[k++] = a[i] * b[j];
+                t[nt++] = a[i] * b[o - i];
             }
         }
-        if (o >= 1)
-            for (int i = 0; i < o; ++i) terms[k++] = err[o][i];
+        for (int q = 0; q < nc; ++q) t[nt++] = carry[q];
+        double sum = t[0];
+        for (int q = 1; q < nt; ++q) {
+            if (o <= n - 2) {
+                double c;
+                two_sum(sum, t[q], &sum, &c);
+                next[nn++] = c;
+            } else {
+                sum = sum + t[q];
+            }
+        }
+        s[o] = sum;
+        for (int q = 0; q < nn; ++q) carry[q] = next[q];
+        nc = nn;
     }
-    sort_terms(terms, k);
-    renorm(terms, k, n, r);
+    renorm(s, n, n, r);
 }
 
-/* r = c - a*b */
+/* r = c - a*b: the rounded product, negated, added to c */
 void orc_fms(int n, const double *c, const double *a, const double *b, double *r) {
     double p[MAXNC];
     orc_mul(n, a, b, p);
@@ -151,28 +168,41 @@ void orc_fms(int n, const double *c, const double *a, const double *b, double *r
     orc_add(n, c, p, r);
 }
 
-/* r = b * q for a double q */
+/* r = b * q for a double q, by order as in orc_mul: b_o q by TwoProd for
+ * o <= n-2 plus the carried errors (TwoSum), plain at order n-1. */
 static void mul_d(int n, const double *b, double q, double *r) {
-    double terms[8];
-    int k = 0;
-    double e_prev = 0.0;
-    for (int i = 0; i < n; ++i) {
-        if (i <= n - 2) {
+    double s[MAXNC], carry[8], next[8], t[8];
+    int nc = 0;
+    for (int o = 0; o < n; ++o) {
+        int nt = 0, nn = 0;
+        if (o <= n - 2) {
             double p, e;
-            two_prod(b[i], q, &p, &e);
-            terms[k++] = p;
-            if (i >= 1) terms[k++] = e_prev;
-            e_prev = e;
+            two_prod(b[o], q, &p, &e);
+            t[nt++] = p;
+            next[nn++] = e;
         } else {
-            terms[k++] = b[i] * q;
-            if (i >= 1) terms[k++] = e_prev;
+            t[nt++] = b[o] * q;
         }
+        for (int k = 0; k < nc; ++k) t[nt++] = carry[k];
+        double sum = t[0];
+        for (int k = 1; k < nt; ++k) {
+            if (o <= n - 2) {
+                double c;
+                two_sum(sum, t[k], &sum, &c);
+                next[nn++] = c;
+            } else {
+                sum = sum + t[k];
+            }
+        }
+        s[o] = sum;
+        for (int k = 0; k < nn; ++k) carry[k] = next[k];
+        nc = nn;
     }
-    sort_terms(terms, k);
-    renorm(terms, k, n, r);
+    renorm(s, n, n, r);
 }
 
-/* r = a / b by long division with n+1 quotient digits */
+/* r = a / b by long division: n+1 quotient digits q_k = rem_0 / b_0 with
+ * rem <- rem - q_k b, then the digits renormalised. */
 void orc_div(int n, const double *a, const double *b, double *r) {
     double q[MAXNC + 1], rem[MAXNC], t[MAXNC];
     for (int i = 0; i < n; ++i) rem[i] = a[i];
@@ -186,7 +216,6 @@ void orc_div(int n, const double *a, const double *b, double *r) {
             for (int i = 0; i < n; ++i) rem[i] = nr[i];
         }
     }
-    sort_terms(q, n + 1);
     renorm(q, n + 1, n, r);
 }
 

@@ -6,15 +6,19 @@
 // solve, plus the native comparator).  They follow one fixed specification so
 // that every result is reproducible bit for bit:
 //   * TwoSum (Knuth) and TwoProd (exact error from one FMA);
-//   * terms are sorted by decreasing magnitude with Batcher's merge-exchange
-//     network (Knuth, TAOCP 3, 5.2.2, Algorithm M), then renormalised by a
-//     bottom-up VecSum followed by a top-down error-branch compression that
-//     keeps the first NC non-zero partial sums (Joldes, Muller, Popescu);
-//   * a*b: partial products of order i+j <= NC-2 exact (TwoProd; the error
-//     joins the next order), order NC-1 plain products, higher orders
-//     dropped;
+//   * renormalisation of K terms into NC components: a bottom-up VecSum, then
+//     a top-down error-branch compression that keeps the first NC non-zero
+//     partial sums (Joldes, Muller, Popescu);
+//   * a+b: the components of a and b (each largest first) merged by
+//     magnitude with Batcher's odd-even merge network (triple-double padded
+//     with a zero to four), then renormalised;
+//   * a*b: partial products summed by order i+j (Hida, Li, Bailey): orders
+//     <= NC-2 by TwoProd, with the product errors and the TwoSum errors of
+//     each order's sum carried to the next order; order NC-1 plain products
+//     and carries summed left to right; higher orders dropped; the NC order
+//     sums renormalised;
 //   * c - a*b: the rounded product subtracted with the addition above;
-//   * a/b: long division producing NC+1 quotient digits.
+//   * a/b: long division producing NC+1 quotient digits, renormalised.
 // All loops have compile-time trip counts and are unrolled, so the terms live
 // in registers; the code must be built with -ffp-contract=off.
 #pragma once
@@ -40,54 +44,58 @@ OZX_HD void two_prod(double a, double b, double &p, double &e) {
 }
 
 // ---------------------------------------------------------------------------
-// Batcher merge-exchange network, generated at compile time.
+// Batcher's odd-even merge network for two runs of M terms (M a power of
+// two), generated at compile time in the order of its recursive definition:
+// merge the even and the odd subsequences, then compare neighbours.
 // ---------------------------------------------------------------------------
-template <int K>
-struct SortNet {
+template <int M>
+struct MergeNet {
   int n;
-  unsigned char a[128];
-  unsigned char b[128];
+  unsigned char a[32];
+  unsigned char b[32];
 };
 
-template <int K>
-constexpr SortNet<K> make_sortnet() {
-  SortNet<K> net{};
-  net.n = 0;
-  if (K < 2) return net;
-  int t = 0;
-  while ((1 << t) < K) ++t;
-  for (int p = 1 << (t - 1); p > 0; p >>= 1) {
-    int q = 1 << (t - 1), r = 0, d = p;
-    for (;;) {
-      for (int i = 0; i + d < K; ++i) {
-        if ((i & p) == r) {
-          net.a[net.n] = (unsigned char)i;
-          net.b[net.n] = (unsigned char)(i + d);
-          ++net.n;
-        }
-      }
-      if (q == p) break;
-      d = q - p;
-      q >>= 1;
-      r = p;
+template <int M>
+constexpr void merge_rec(MergeNet<M> &net, int lo, int hi, int r) {
+  const int step = 2 * r;
+  if (step < hi - lo) {
+    merge_rec<M>(net, lo, hi, step);
+    merge_rec<M>(net, lo + r, hi, step);
+    for (int i = lo + r; i < hi - r; i += step) {
+      net.a[net.n] = (unsigned char)i;
+      net.b[net.n] = (unsigned char)(i + r);
+      ++net.n;
     }
+  } else {
+    net.a[net.n] = (unsigned char)lo;
+    net.b[net.n] = (unsigned char)(lo + r);
+    ++net.n;
   }
+}
+
+template <int M>
+constexpr MergeNet<M> make_mergenet() {
+  MergeNet<M> net{};
+  net.n = 0;
+  merge_rec<M>(net, 0, 2 * M - 1, 1);
   return net;
 }
 
-template <int K>
-OZX_HD void sort_desc(double (&x)[K]) {
-  constexpr SortNet<K> net = make_sortnet<K>();
+// merge x[0..M-1] and x[M..2M-1] by decreasing magnitude; a compare-exchange
+// moves the larger magnitude to the lower index, equal magnitudes stay
+template <int M>
+OZX_HD void merge_desc(double (&x)[2 * M]) {
+  constexpr MergeNet<M> net = make_mergenet<M>();
 #pragma unroll
   for (int c = 0; c < net.n; ++c) {
-    double u = x[net.a[c]], v = x[net.b[c]];
-    bool sw = __builtin_fabs(v) > __builtin_fabs(u);
+    const double u = x[net.a[c]], v = x[net.b[c]];
+    const bool sw = __builtin_fabs(v) > __builtin_fabs(u);
     x[net.a[c]] = sw ? v : u;
     x[net.b[c]] = sw ? u : v;
   }
 }
 
-// Renormalise K sorted terms into NC components.
+// Renormalise K terms into NC components.
 template <int K, int NC>
 OZX_HD void renorm(double (&x)[K], double (&y)[NC]) {
   double s = x[K - 1];
@@ -108,9 +116,11 @@ OZX_HD void renorm(double (&x)[K], double (&y)[NC]) {
     two_sum(eps, x[i], r, e);
     const bool live = j < NC;
     const bool emit = live && (e != 0.0);
+    // before step i at most i-1 components are out, so only y[0..i-1] can
+    // receive this one (q < i is decided at compile time)
 #pragma unroll
     for (int q = 0; q < NC; ++q)
-      if (emit && j == q) y[q] = r;
+      if (q < i && emit && j == q) y[q] = r;
     eps = live ? (e != 0.0 ? e : r) : eps;
     j += emit ? 1 : 0;
   }
@@ -121,42 +131,56 @@ OZX_HD void renorm(double (&x)[K], double (&y)[NC]) {
 
 template <int NC>
 OZX_HD void add(const double (&a)[NC], const double (&b)[NC], double (&r)[NC]) {
-  double x[2 * NC];
+  constexpr int M = NC == 3 ? 4 : NC;
+  double x[2 * M];
 #pragma unroll
-  for (int i = 0; i < NC; ++i) {
-    x[i] = a[i];
-    x[NC + i] = b[i];
+  for (int i = 0; i < M; ++i) {
+    x[i] = i < NC ? a[i < NC ? i : 0] : 0.0;
+    x[M + i] = i < NC ? b[i < NC ? i : 0] : 0.0;
   }
-  sort_desc<2 * NC>(x);
-  renorm<2 * NC, NC>(x, r);
+  merge_desc<M>(x);
+  renorm<2 * M, NC>(x, r);
 }
 
 template <int NC>
 OZX_HD void mul(const double (&a)[NC], const double (&b)[NC], double (&r)[NC]) {
-  double terms[NC * NC];
-  double err[NC + 1][NC + 1];
-  int k = 0;
+  double s[NC];
+  double carry[16];
+  int nc = 0;
 #pragma unroll
   for (int o = 0; o < NC; ++o) {
+    double t[24], nx[16];
+    int nt = 0, nn = 0;
 #pragma unroll
     for (int i = 0; i <= o; ++i) {
-      const int j = o - i;
       if (o <= NC - 2) {
         double p, e;
-        two_prod(a[i], b[j], p, e);
-        terms[k++] = p;
-        err[o + 1][i] = e;
+        two_prod(a[i], b[o - i], p, e);
+        t[nt++] = p;
+        nx[nn++] = e;
       } else {
-        terms[k++] = a[i] * b[j];
+        t[nt++] = a[i] * b[o - i];
       }
     }
-    if (o >= 1) {
 #pragma unroll
-      for (int i = 0; i < o; ++i) terms[k++] = err[o][i];
+    for (int q = 0; q < nc; ++q) t[nt++] = carry[q];
+    double sum = t[0];
+#pragma unroll
+    for (int q = 1; q < nt; ++q) {
+      if (o <= NC - 2) {
+        double c;
+        two_sum(sum, t[q], sum, c);
+        nx[nn++] = c;
+      } else {
+        sum = sum + t[q];
+      }
     }
+    s[o] = sum;
+#pragma unroll
+    for (int q = 0; q < nn; ++q) carry[q] = nx[q];
+    nc = nn;
   }
-  sort_desc<NC * NC>(terms);
-  renorm<NC * NC, NC>(terms, r);
+  renorm<NC, NC>(s, r);
 }
 
 // r = c - a*b
@@ -170,27 +194,43 @@ OZX_HD void fms(const double (&c)[NC], const double (&a)[NC], const double (&b)[
   add<NC>(c, p, r);
 }
 
-// r = b * q, q a double
+// r = b * q, q a double: by order as in mul
 template <int NC>
 OZX_HD void mul_d(const double (&b)[NC], double q, double (&r)[NC]) {
-  double terms[2 * NC - 1];
-  int k = 0;
-  double e_prev = 0.0;
+  double s[NC];
+  double carry[NC];
+  int nc = 0;
 #pragma unroll
-  for (int i = 0; i < NC; ++i) {
-    if (i <= NC - 2) {
+  for (int o = 0; o < NC; ++o) {
+    double t[NC + 1], nx[NC];
+    int nt = 0, nn = 0;
+    if (o <= NC - 2) {
       double p, e;
-      two_prod(b[i], q, p, e);
-      terms[k++] = p;
-      if (i >= 1) terms[k++] = e_prev;
-      e_prev = e;
+      two_prod(b[o], q, p, e);
+      t[nt++] = p;
+      nx[nn++] = e;
     } else {
-      terms[k++] = b[i] * q;
-      if (i >= 1) terms[k++] = e_prev;
+      t[nt++] = b[o] * q;
     }
+#pragma unroll
+    for (int k = 0; k < nc; ++k) t[nt++] = carry[k];
+    double sum = t[0];
+#pragma unroll
+    for (int k = 1; k < nt; ++k) {
+      if (o <= NC - 2) {
+        double c;
+        two_sum(sum, t[k], sum, c);
+        nx[nn++] = c;
+      } else {
+        sum = sum + t[k];
+      }
+    }
+    s[o] = sum;
+#pragma unroll
+    for (int k = 0; k < nn; ++k) carry[k] = nx[k];
+    nc = nn;
   }
-  sort_desc<2 * NC - 1>(terms);
-  renorm<2 * NC - 1, NC>(terms, r);
+  renorm<NC, NC>(s, r);
 }
 
 template <int NC>
@@ -212,7 +252,6 @@ OZX_HD void div(const double (&a)[NC], const double (&b)[NC], double (&r)[NC]) {
       for (int i = 0; i < NC; ++i) rem[i] = nr[i];
     }
   }
-  sort_desc<NC + 1>(q);
   renorm<NC + 1, NC>(q, r);
 }
 
