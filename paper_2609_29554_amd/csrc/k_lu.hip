@@ -17,43 +17,62 @@
 namespace {
 
 // ---------------------------------------------------------------------------
-// Split-phase grid barrier for the cooperative panel kernel.  Every
-// workgroup owns one arrival flag on its own 128-byte line; arrive() makes the
-// workgroup's global writes visible (agent-scope release) and stores the
-// epoch in its flag; wait() polls every flag (one per thread) and acquires.
-// Between the two calls a workgroup may keep working on data nobody else
-// reads.  Waits are bounded: a timeout raises the sticky error flag, after
-// which every later wait returns at once, so a broken invariant ends the
-// kernel quickly instead of hanging it.
+// Exchange between the workgroups of the cooperative panel kernel.
+//
+// Each workgroup owns two 128-byte candidate lines (one per parity of the
+// pivot column): word 0 holds an arrival epoch, the rest the workgroup's
+// pivot candidate for that column -- its row position and physical row, its
+// value in the pivot column and in the next column -- and a buffer crow holds
+// the rest of that row.  A workgroup writes the payload, makes it visible at
+// device scope (agent release: the dirty L2 lines are written back) and then
+// stores the epoch.  Readers poll the epochs and read every payload and crow
+// with device-coherent loads, which go past the non-coherent caches, so no
+// cache invalidation is needed on the reading side; they are issued only
+// after the epochs were seen (the wait ends in a workgroup barrier).  Waits
+// are bounded: a timeout raises the sticky error flag, after which every
+// later wait returns at once, so a broken invariant ends the kernel quickly.
 // ---------------------------------------------------------------------------
-constexpr int FLAG_STRIDE = 32;  // uint32 per 128-byte line
+constexpr int CAND_WORDS = 32;  // uint32 per candidate line
+constexpr int CAND_KEY = 4;     // first payload word of the key doubles
 
-__device__ __forceinline__ void bar_arrive(uint32_t *flags, uint32_t epoch) {
+__device__ __forceinline__ uint32_t ld_dev_u32(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev_f64(const double *p) {
+  const uint64_t v = __hip_atomic_load((const uint64_t *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  double d;
+  __builtin_memcpy(&d, &v, 8);
+  return d;
+}
+
+// Make this workgroup's global writes visible at device scope, then store
+// the epoch in its candidate line.
+__device__ __forceinline__ void cand_arrive(uint32_t *line, uint32_t epoch) {
   // every wave waits for its own global stores (s_waitcnt vmcnt(0)): the
   // workgroup barrier alone does not, and the release below only covers the
-  // L2, so the data must have reached it before the flag is written
+  // L2, so the data must have reached it before the epoch is written
   __builtin_amdgcn_s_waitcnt(0x0F70);
   __syncthreads();
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_store(flags + blockIdx.x * FLAG_STRIDE, epoch, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(line, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
-// Returns false when the wait failed (timeout now or earlier); the caller
-// must then stop using data published by other workgroups.
-__device__ __forceinline__ bool bar_wait(uint32_t *flags, uint32_t nblocks, uint32_t epoch,
-                                         int *err) {
+// Wait until the lines of all G workgroups (buffer b) carry an epoch of at
+// least `epoch`.  Returns false when the wait failed (timeout now or
+// earlier); the caller must then stop using data published by others.
+__device__ __forceinline__ bool cand_wait(const uint32_t *lines, int G, int b, uint32_t epoch,
+                                          int *err) {
   __shared__ int s_fail;
-  if (threadIdx.x < nblocks) {
+  if ((int)threadIdx.x < G) {
     // bounded by the 100 MHz real-time counter: about one second
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
     uint32_t spins = 0;
-    // flags only grow: a workgroup that already arrived for a later epoch
+    const uint32_t *f = lines + ((size_t)b * G + threadIdx.x) * CAND_WORDS;
+    // epochs only grow: a workgroup that already arrived for a later epoch
     // has also arrived for this one
-    while ((int32_t)(__hip_atomic_load(flags + threadIdx.x * FLAG_STRIDE, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT) - epoch) < 0) {
+    while ((int32_t)(ld_dev_u32(f) - epoch) < 0) {
       if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
       if ((++spins & 63u) == 0 && __builtin_amdgcn_s_memrealtime() - t0 > 100000000ull) {
         __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -62,12 +81,26 @@ __device__ __forceinline__ bool bar_wait(uint32_t *flags, uint32_t nblocks, uint
     }
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   if (threadIdx.x == 0)
     s_fail = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
   __syncthreads();
   return !s_fail;
 }
+
+// Candidate order of the pivot search: larger |value| first, then the lower
+// row position.  A total order on (key, position) pairs, so any reduction
+// tree picks the same winner.
+template <int NC>
+__device__ __forceinline__ bool cand_better(const double (&kb_)[NC], int pb, int ib,
+                                            const double (&ka)[NC], int pa, int ia) {
+  if (ib < 0) return false;
+  if (ia < 0) return true;
+  if (ozx::abs_greater<NC>(kb_, ka)) return true;
+  if (ozx::abs_greater<NC>(ka, kb_)) return false;
+  return pb < pa;
+}
+
+constexpr int PANEL_NT = 256;  // threads per panel workgroup
 
 // ---------------------------------------------------------------------------
 // (P1) panel.  Panel rows [k, n), columns [k, k+kb).  Workgroup w owns the
@@ -79,19 +112,20 @@ __device__ __forceinline__ bool bar_wait(uint32_t *flags, uint32_t nblocks, uint
 //      its active rows, ties to the lowest position) and reduce the table
 //      identically everywhere: the winner is LAPACK's i?amax on the permuted
 //      column;
-//   2. divide the active rows by the pivot, update column j+1, pick the local
-//      candidate for column j+1, finish that row's update and publish it
-//      (the critical path), then arrive;
-//   3. update the remaining columns of the other active rows while the other
+//   2. wavefront 0 divides the active rows by the pivot and updates column
+//      j+1 (the candidate line carries the pivot row's value there) while
+//      the other wavefronts fetch the rest of the pivot row;
+//   3. pick the local candidate for column j+1, finish that row's update and
+//      publish it (the critical path), then arrive;
+//   4. update the remaining columns of the other active rows while the other
 //      workgroups arrive.
 // Every element still receives its multiply-subtracts in column order.
 // ---------------------------------------------------------------------------
 template <int NC>
-__global__ __launch_bounds__(256) void k_panel(double *A, int64_t lda, int64_t n, int64_t k,
-                                               int kb, int R, int64_t *ipiv, int32_t *info,
-                                               uint32_t *flags, int *err, double *ckey, int *cpos,
-                                               int *cphys, double *crow, int *perm_out,
-                                               int *moved, int *nmoved) {
+__global__ __launch_bounds__(PANEL_NT) void k_panel(double *A, int64_t lda, int64_t n, int64_t k,
+                                                    int kb, int R, int64_t *ipiv, int32_t *info,
+                                                    uint32_t *lines, int *err, double *crow,
+                                                    int *perm_out, int *moved, int *nmoved) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int nr = (int)(n - k);
   const int G = gridDim.x, wg = blockIdx.x, tid = threadIdx.x;
@@ -99,22 +133,24 @@ __global__ __launch_bounds__(256) void k_panel(double *A, int64_t lda, int64_t n
   double *piv = rows + (size_t)R * kb * NC;          // kb * NC
   int *sperm = (int *)(piv + (size_t)kb * NC);       // nr
   int *sinv = sperm + nr;                            // nr
-  __shared__ double rkey[256][NC];
-  __shared__ int rpos[256], ridx[256];
+  __shared__ double tkey[256][NC], tnxt[256][NC];
+  __shared__ int tpos[256], tidx[256], tphys[256];
   __shared__ uint32_t active;
   __shared__ int s_info, s_wi, s_ppos, s_pphys, s_zero, s_best;
 
   const int r0 = wg * R;
   const int cnt = r0 < nr ? (nr - r0 < R ? nr - r0 : R) : 0;
   auto RW = [&](int r, int c) { return rows + ((size_t)r * kb + c) * NC; };
+  auto LINE = [&](int b, int w) { return lines + ((size_t)b * G + w) * CAND_WORDS; };
+  auto CROW = [&](int b, int w) { return crow + ((size_t)b * G + w) * kb * NC; };
 
-  for (int idx = tid; idx < cnt * kb; idx += 256) {
+  for (int idx = tid; idx < cnt * kb; idx += PANEL_NT) {
     const int r = idx % cnt, c = idx / cnt;
     const double *src = A + ((k + r0 + r) + (k + c) * lda) * NC;
 #pragma unroll
     for (int q = 0; q < NC; ++q) RW(r, c)[q] = src[q];
   }
-  for (int p = tid; p < nr; p += 256) {
+  for (int p = tid; p < nr; p += PANEL_NT) {
     sperm[p] = p;
     sinv[p] = p;
   }
@@ -149,95 +185,110 @@ __global__ __launch_bounds__(256) void k_panel(double *A, int64_t lda, int64_t n
     }
     __syncthreads();
   };
-  // publish the candidate of column c (row s_best, columns c..kb-1) into buffer
-  auto publish = [&](int c, int buf) {
+  // publish the candidate of column c (row s_best) into buffer b: the line
+  // payload (position, physical row, values in columns c and c+1) and the
+  // row's columns c+2 .. kb-1 in crow
+  auto publish = [&](int c, int b) {
     const int best = s_best;
+    uint32_t *ln = LINE(b, wg);
     if (tid == 0) {
+      double *kv = (double *)(ln + CAND_KEY);
       if (best >= 0) {
+        ln[1] = (uint32_t)sinv[r0 + best];
+        ln[2] = (uint32_t)(r0 + best);
 #pragma unroll
-        for (int q = 0; q < NC; ++q) ckey[((size_t)buf * G + wg) * NC + q] = RW(best, c)[q];
-        cpos[buf * G + wg] = sinv[r0 + best];
-        cphys[buf * G + wg] = r0 + best;
+        for (int q = 0; q < NC; ++q) {
+          kv[q] = RW(best, c)[q];
+          kv[NC + q] = c + 1 < kb ? RW(best, c + 1)[q] : 0.0;
+        }
       } else {
-        cphys[buf * G + wg] = -1;
-        cpos[buf * G + wg] = 0x7fffffff;
+        ln[1] = 0x7fffffffu;
+        ln[2] = 0xffffffffu;
       }
     }
     if (best >= 0) {
-      for (int idx = tid; idx < (kb - c) * NC; idx += 256)
-        crow[((size_t)buf * G + wg) * kb * NC + (size_t)c * NC + idx] = RW(best, c)[idx];
+      double *cr = CROW(b, wg);
+      for (int idx = tid; idx < (kb - c - 2) * NC; idx += PANEL_NT)
+        cr[(size_t)(c + 2) * NC + idx] = RW(best, c + 2)[idx];
     }
   };
 
   pick(0);
   publish(0, 0);
-  bar_arrive(flags, 1u);
+  cand_arrive(LINE(0, wg), 1u);
 
   for (int j = 0; j < kb; ++j) {
     const int buf = j & 1;
-    if (!bar_wait(flags, (uint32_t)G, (uint32_t)(j + 1), err)) return;
-    // reduce the candidate table (identically in every workgroup)
-    {
-      const int gi = tid;
-      if (gi < G && cphys[buf * G + gi] >= 0) {
+    if (!cand_wait(lines, G, buf, (uint32_t)(j + 1), err)) return;
+    // read the candidate table (one line per thread, device-coherent) and
+    // reduce it identically in every workgroup: four entries per lane of the
+    // first wavefront, then a butterfly
+    if (tid < G) {
+      const uint32_t *ln = LINE(buf, tid);
+      const int ph = (int)ld_dev_u32(ln + 2);
+      tpos[tid] = (int)ld_dev_u32(ln + 1);
+      tphys[tid] = ph;
+      tidx[tid] = ph >= 0 ? tid : -1;
+      const double *kv = (const double *)(ln + CAND_KEY);
 #pragma unroll
-        for (int q = 0; q < NC; ++q) rkey[tid][q] = ckey[((size_t)buf * G + gi) * NC + q];
-        rpos[tid] = cpos[buf * G + gi];
-        ridx[tid] = gi;
-      } else {
-#pragma unroll
-        for (int q = 0; q < NC; ++q) rkey[tid][q] = 0.0;
-        rpos[tid] = 0x7fffffff;
-        ridx[tid] = -1;
+      for (int q = 0; q < NC; ++q) {
+        tkey[tid][q] = ld_dev_f64(kv + q);
+        tnxt[tid][q] = ld_dev_f64(kv + NC + q);
       }
-      __syncthreads();
-      for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s) {
-          const int a = tid, b = tid + s;
-          bool takeb = false;
-          if (ridx[b] >= 0) {
-            if (ridx[a] < 0) takeb = true;
-            else {
-              double ka[NC], kbv[NC];
+    }
+    __syncthreads();
+    if (tid < 64) {
+      double bk[NC];
+      int bp = 0x7fffffff, bi = -1;
 #pragma unroll
-              for (int q = 0; q < NC; ++q) {
-                ka[q] = rkey[a][q];
-                kbv[q] = rkey[b][q];
-              }
-              if (ozx::abs_greater<NC>(kbv, ka)) takeb = true;
-              else if (!ozx::abs_greater<NC>(ka, kbv) && rpos[b] < rpos[a]) takeb = true;
-            }
-          }
-          if (takeb) {
+      for (int q = 0; q < NC; ++q) bk[q] = 0.0;
+      for (int gi = tid; gi < G; gi += 64) {
+        double kk[NC];
 #pragma unroll
-            for (int q = 0; q < NC; ++q) rkey[a][q] = rkey[b][q];
-            rpos[a] = rpos[b];
-            ridx[a] = ridx[b];
-          }
+        for (int q = 0; q < NC; ++q) kk[q] = tkey[gi][q];
+        if (cand_better<NC>(kk, tpos[gi], tidx[gi], bk, bp, bi)) {
+#pragma unroll
+          for (int q = 0; q < NC; ++q) bk[q] = kk[q];
+          bp = tpos[gi];
+          bi = tidx[gi];
         }
-        __syncthreads();
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        double ok[NC];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) ok[q] = __shfl_xor(bk[q], off, 64);
+        const int op = __shfl_xor(bp, off, 64), oi = __shfl_xor(bi, off, 64);
+        if (cand_better<NC>(ok, op, oi, bk, bp, bi)) {
+#pragma unroll
+          for (int q = 0; q < NC; ++q) bk[q] = ok[q];
+          bp = op;
+          bi = oi;
+        }
       }
       if (tid == 0) {
-        const int wi = ridx[0];
-        s_wi = wi;
-        s_ppos = rpos[0];
-        s_pphys = wi >= 0 ? cphys[buf * G + wi] : -1;
+        s_wi = bi;
+        s_ppos = bp;
+        s_pphys = bi >= 0 ? tphys[bi] : -1;
         bool z = true;
 #pragma unroll
-        for (int q = 0; q < NC; ++q) z = z && (rkey[0][q] == 0.0);
+        for (int q = 0; q < NC; ++q) z = z && (bk[q] == 0.0);
         s_zero = z ? 1 : 0;
       }
-      __syncthreads();
     }
+    __syncthreads();
     const int wi = s_wi, ppos = s_ppos, pphys = s_pphys, zero = s_zero;
-    // an empty or inconsistent table can only follow a failed barrier
+    // an empty or inconsistent table can only follow a failed wait
     if (wi < 0 || ppos < j || ppos >= nr || pphys < 0 || pphys >= nr) {
       if (tid == 0) __hip_atomic_store(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
-    for (int idx = tid; idx < (kb - j) * NC; idx += 256)
-      piv[(size_t)j * NC + idx] = crow[((size_t)buf * G + wi) * kb * NC + (size_t)j * NC + idx];
     if (tid == 0) {
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        piv[(size_t)j * NC + q] = tkey[wi][q];
+        if (j + 1 < kb) piv[(size_t)(j + 1) * NC + q] = tnxt[wi][q];
+      }
       const int q = sperm[j];
       sperm[j] = pphys;
       sperm[ppos] = q;
@@ -249,32 +300,40 @@ __global__ __launch_bounds__(256) void k_panel(double *A, int64_t lda, int64_t n
     }
     __syncthreads();
     const bool last = j + 1 >= kb;
-    if (!zero) {
-      for (int r = tid; r < cnt; r += 256) {
-        if ((active >> r) & 1u) {
-          double a[NC], d[NC], l[NC];
-          ozx::load<NC>(RW(r, j), a);
-          ozx::load<NC>(piv + (size_t)j * NC, d);
-          ozx::div<NC>(a, d, l);
-          ozx::store<NC>(RW(r, j), l);
-          if (!last) {
-            double x[NC], u[NC], o[NC];
-            ozx::load<NC>(RW(r, j + 1), x);
-            ozx::load<NC>(piv + (size_t)(j + 1) * NC, u);
-            ozx::fms<NC>(x, l, u, o);
-            ozx::store<NC>(RW(r, j + 1), o);
+    if (tid < 64) {
+      // wavefront 0: l = a / pivot for the active rows, then column j+1
+      if (!zero) {
+        for (int r = tid; r < cnt; r += 64) {
+          if ((active >> r) & 1u) {
+            double a[NC], d[NC], l[NC];
+            ozx::load<NC>(RW(r, j), a);
+            ozx::load<NC>(piv + (size_t)j * NC, d);
+            ozx::div<NC>(a, d, l);
+            ozx::store<NC>(RW(r, j), l);
+            if (!last) {
+              double x[NC], u[NC], o[NC];
+              ozx::load<NC>(RW(r, j + 1), x);
+              ozx::load<NC>(piv + (size_t)(j + 1) * NC, u);
+              ozx::fms<NC>(x, l, u, o);
+              ozx::store<NC>(RW(r, j + 1), o);
+            }
           }
         }
       }
-      __syncthreads();
+    } else {
+      // the other wavefronts: columns j+2 .. kb-1 of the pivot row
+      const double *cr = CROW(buf, wi);
+      for (int idx = tid - 64; idx < (kb - j - 2) * NC; idx += PANEL_NT - 64)
+        piv[(size_t)(j + 2) * NC + idx] = ld_dev_f64(cr + (size_t)(j + 2) * NC + idx);
     }
+    __syncthreads();
     if (last) break;
     // candidate for column j+1: finish its row first, publish, arrive
     pick(j + 1);
     const int best = s_best;
     const int width = kb - j - 2;
     if (!zero && best >= 0) {
-      for (int c = j + 2 + tid; c < kb; c += 256) {
+      for (int c = j + 2 + tid; c < kb; c += PANEL_NT) {
         double x[NC], l[NC], u[NC], o[NC];
         ozx::load<NC>(RW(best, c), x);
         ozx::load<NC>(RW(best, j), l);
@@ -285,10 +344,10 @@ __global__ __launch_bounds__(256) void k_panel(double *A, int64_t lda, int64_t n
       __syncthreads();
     }
     publish(j + 1, (j + 1) & 1);
-    bar_arrive(flags, (uint32_t)(j + 2));
+    cand_arrive(LINE((j + 1) & 1, wg), (uint32_t)(j + 2));
     // the rest of the rank-1 update, overlapped with the other arrivals
     if (!zero && width > 0) {
-      for (int idx = tid; idx < cnt * width; idx += 256) {
+      for (int idx = tid; idx < cnt * width; idx += PANEL_NT) {
         const int r = idx % cnt, c = j + 2 + idx / cnt;
         if (((active >> r) & 1u) && r != best) {
           double a[NC], l[NC], u[NC], o[NC];
@@ -303,7 +362,7 @@ __global__ __launch_bounds__(256) void k_panel(double *A, int64_t lda, int64_t n
     __syncthreads();
   }
   // write the rows back to their physical places
-  for (int idx = tid; idx < cnt * kb; idx += 256) {
+  for (int idx = tid; idx < cnt * kb; idx += PANEL_NT) {
     const int r = idx % cnt, c = idx / cnt;
     double *dst = A + ((k + r0 + r) + (k + c) * lda) * NC;
 #pragma unroll
@@ -313,7 +372,7 @@ __global__ __launch_bounds__(256) void k_panel(double *A, int64_t lda, int64_t n
     __shared__ int s_nm;
     if (tid == 0) s_nm = 0;
     __syncthreads();
-    for (int p = tid; p < nr; p += 256) {
+    for (int p = tid; p < nr; p += PANEL_NT) {
       perm_out[p] = sperm[p];
       if (sperm[p] != p) {
         const int slot = atomicAdd(&s_nm, 1);
@@ -632,16 +691,15 @@ const void *panel_kernel_ptr(int nc) {
 }
 
 hipError_t launch_panel(int nc, double *A, int64_t lda, int64_t n, int64_t k, int kb, int R, int G,
-                        int64_t *ipiv, int32_t *info, uint32_t *flags, int *err, double *ckey,
-                        int *cpos, int *cphys, double *crow, int *perm, int *moved, int *nmoved,
-                        hipStream_t s) {
+                        int64_t *ipiv, int32_t *info, uint32_t *lines, int *err, double *crow,
+                        int *perm, int *moved, int *nmoved, hipStream_t s) {
   const size_t lds = panel_lds_bytes(nc, kb, R, n - k);
   const void *fn = panel_kernel_ptr(nc);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  void *args[] = {&A, &lda, &n, &k, &kb, &R, &ipiv, &info, &flags, &err,
-                  &ckey, &cpos, &cphys, &crow, &perm, &moved, &nmoved};
-  return hipLaunchCooperativeKernel(fn, dim3(G), dim3(256), args, (unsigned)lds, s);
+  void *args[] = {&A, &lda, &n, &k, &kb, &R, &ipiv, &info, &lines, &err,
+                  &crow, &perm, &moved, &nmoved};
+  return hipLaunchCooperativeKernel(fn, dim3(G), dim3(PANEL_NT), args, (unsigned)lds, s);
 }
 
 hipError_t panel_max_blocks(int nc, int kb, int R, int64_t nr, int *maxblocks) {
@@ -650,7 +708,7 @@ hipError_t panel_max_blocks(int nc, int kb, int R, int64_t nr, int *maxblocks) {
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int per = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, PANEL_NT, lds);
   if (e != hipSuccess) return e;
   int dev = 0, ncu = 0;
   hipGetDevice(&dev);

@@ -268,10 +268,8 @@ struct ozII_ctx {
   size_t ws_bytes = 0;
   // panel scratch
   uint32_t *bar = nullptr;
-  uint32_t *flags = nullptr;  // panel arrival flags, one 128-byte line per workgroup
+  uint32_t *flags = nullptr;  // panel candidate lines, two 128-byte lines per workgroup
   int *err = nullptr;
-  double *ckey = nullptr;
-  int *cpos = nullptr, *cphys = nullptr;
   double *crow = nullptr;
   int *perm = nullptr, *moved = nullptr, *nmoved = nullptr;
   int64_t panel_n = 0;
@@ -407,9 +405,6 @@ ozII_status ensure_panel(ozII_ctx *h, int64_t n, int kb) {
   if (h->bar) {
     hipError_t e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
-    hipFree(h->ckey);
-    hipFree(h->cpos);
-    hipFree(h->cphys);
     hipFree(h->crow);
     hipFree(h->perm);
     hipFree(h->moved);
@@ -426,10 +421,7 @@ ozII_status ensure_panel(ozII_ctx *h, int64_t n, int kb) {
       h->nmoved = (int *)(h->bar + 8);
     }
   }
-  if (e == hipSuccess && !h->flags) e = hipMalloc((void **)&h->flags, 128 * G);
-  if (e == hipSuccess) e = hipMalloc((void **)&h->ckey, sizeof(double) * 2 * G * 4);
-  if (e == hipSuccess) e = hipMalloc((void **)&h->cpos, sizeof(int) * 2 * G);
-  if (e == hipSuccess) e = hipMalloc((void **)&h->cphys, sizeof(int) * 2 * G);
+  if (e == hipSuccess && !h->flags) e = hipMalloc((void **)&h->flags, 2 * 128 * G);
   if (e == hipSuccess) e = hipMalloc((void **)&h->crow, sizeof(double) * 2 * G * kk * 4);
   if (e == hipSuccess) e = hipMalloc((void **)&h->perm, sizeof(int) * nn);
   if (e == hipSuccess) e = hipMalloc((void **)&h->moved, sizeof(int) * nn);
@@ -562,9 +554,6 @@ ozII_status ozII_destroy(ozII_handle h) {
   if (h->bar) {
     hipFree(h->bar);
     hipFree(h->flags);
-    hipFree(h->ckey);
-    hipFree(h->cpos);
-    hipFree(h->cphys);
     hipFree(h->crow);
     hipFree(h->perm);
     hipFree(h->moved);
@@ -697,13 +686,13 @@ ozII_status ozII_getrf(ozII_handle h, int32_t nc, int64_t n, double *A, int64_t 
       if (G <= 0) return fail(h, OZII_EUNSUPPORTED, "panel kernel cannot be resident");
     }
     G = (int)std::min<int64_t>(G, (nr + R - 1) / R);
-    if ((e = ozl::launch_fill_int((int *)h->flags, 0, 32 * 256, s)) != hipSuccess) return hip_fail(h, e, "fill flags");
+    if ((e = ozl::launch_fill_int((int *)h->flags, 0, 2 * 32 * 256, s)) != hipSuccess) return hip_fail(h, e, "fill lines");
     // a panel that stops early leaves no moved rows behind for laswp
     if ((e = ozl::launch_fill_int(h->nmoved, 0, 1, s)) != hipSuccess) return hip_fail(h, e, "fill nmoved");
     {
       ProfScope ps(h, OZ_STAGE_PANEL, 16.0 * nc * (double)nr * kb, (double)nr * kb * kb / 2.0);
-      if ((e = ozl::launch_panel(nc, A, lda, n, k, kb, R, G, ipiv, info, h->flags, h->err, h->ckey,
-                                 h->cpos, h->cphys, h->crow, h->perm, h->moved, h->nmoved, s)) != hipSuccess)
+      if ((e = ozl::launch_panel(nc, A, lda, n, k, kb, R, G, ipiv, info, h->flags, h->err, h->crow,
+                                 h->perm, h->moved, h->nmoved, s)) != hipSuccess)
         return hip_fail(h, e, "panel");
     }
     {

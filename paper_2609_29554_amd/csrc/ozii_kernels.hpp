@@ -62,10 +62,11 @@ hipError_t launch_crt_export(const void *tpl, int tbytes, int64_t Mp, int64_t Np
 // LU pieces
 size_t panel_lds_bytes(int nc, int kb, int R, int64_t nr);
 hipError_t panel_max_blocks(int nc, int kb, int R, int64_t nr, int *maxblocks);
+// lines: 2 * G candidate lines of 128 bytes (zeroed before each panel);
+// crow: 2 * G rows of kb expansions
 hipError_t launch_panel(int nc, double *A, int64_t lda, int64_t n, int64_t k, int kb, int R, int G,
-                        int64_t *ipiv, int32_t *info, uint32_t *bar, int *err, double *ckey,
-                        int *cpos, int *cphys, double *crow, int *perm, int *moved, int *nmoved,
-                        hipStream_t s);
+                        int64_t *ipiv, int32_t *info, uint32_t *lines, int *err, double *crow,
+                        int *perm, int *moved, int *nmoved, hipStream_t s);
 hipError_t launch_laswp(int nc, double *A, int64_t lda, int64_t k, int64_t c0, int64_t c1,
                         const int *perm, const int *moved, const int *nmoved, hipStream_t s);
 hipError_t launch_trsm_lower_unit(int nc, const double *L, int64_t lda, double *X, int64_t ldx,
