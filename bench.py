@@ -76,6 +76,23 @@ def op_counts(n, b):
     return P, U
 
 
+PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
+KERNEL_FAMILY = {"producer": "k_producer", "consumer": "k_consumer"}
+
+
+def traffic_of(stage, profile_md, gemm_family="k_gemm_i8_p"):
+    """HBM bytes per launch of a stage's kernel from a committed rocprofv3
+    counter summary, or None when there is none or the kernel source has
+    changed since it was measured."""
+    from paper_2609_29554_amd import pmc
+    s = pmc.load(os.path.join(PROFILES, profile_md))
+    if not s or s.get("kernel_source_sha256") != pmc.source_sha():
+        return None
+    fam = gemm_family if stage == "gemm" else KERNEL_FAMILY.get(stage)
+    rec = s["kernels"].get(fam)
+    return rec.get("hbm_bytes_per_launch") if rec else None
+
+
 def cpu_baseline(n_target, nc, b, n_sample):
     import oracle as O
     import workloads as W
@@ -90,13 +107,18 @@ def cpu_baseline(n_target, nc, b, n_sample):
     Pt, Ut = op_counts(n_target, b)
     scale_s = (n_target / n_sample) ** 2
     est = tp * Pt / Ps + tu * (Ut / Us if Us else 0.0) + (t2 - t1) * scale_s
-    return {
-        "value": est, "unit": "s", "cores": os.cpu_count(), "kind": "oracle",
-        "sample": (f"full oracle getrf+getrs of the QD Lotkin matrix at n={n_sample}, b={b} "
-                   f"({t2 - t0:.1f} s: panel+solve {tp:.1f} s, update {tu:.1f} s, getrs "
-                   f"{t2 - t1:.1f} s), scaled to n={n_target} by panel op counts "
-                   f"({Pt / Ps:.1f}x), Schur op counts ({Ut / max(Us, 1):.1f}x) and n^2 for getrs"),
-    }
+    if n_sample == n_target:
+        sample = (f"the whole workload: oracle getrf+getrs of the QD Lotkin matrix n={n_sample}, "
+                  f"b={b} ({t2 - t0:.1f} s: panel+solve {tp:.1f} s, update {tu:.1f} s, getrs "
+                  f"{t2 - t1:.1f} s)")
+    else:
+        sample = (f"full oracle getrf+getrs of the QD Lotkin matrix at n={n_sample}, b={b} "
+                  f"({t2 - t0:.1f} s: panel+solve {tp:.1f} s, update {tu:.1f} s, getrs "
+                  f"{t2 - t1:.1f} s), scaled to n={n_target} by panel op counts "
+                  f"({Pt / Ps:.1f}x), Schur op counts ({Ut / max(Us, 1):.1f}x) and n^2 for getrs")
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": est, "unit": "s", "cores": min(threads, os.cpu_count() or threads),
+            "kind": "oracle", "sample": sample}
 
 
 def main():
@@ -110,14 +132,17 @@ def main():
     ap.add_argument("--native-steps", type=int, default=1)
     ap.add_argument("--no-native", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-n", type=int, default=1024)
-    ap.add_argument("--workload", choices=["lu", "gemm"], default="lu",
-                    help="lu: QD Lotkin LU (default); gemm: standalone TD product m=n=k=4096")
+    ap.add_argument("--cpu-sample-n", type=int, default=2048)
+    ap.add_argument("--workload", choices=["lu", "gemm", "schur"], default="lu",
+                    help="lu: QD Lotkin LU (default); gemm: standalone TD product m=n=k=4096; "
+                         "schur: only the LU's Ozaki-II Schur-update products (for profiling)")
     ap.add_argument("--gemm-n", type=int, default=4096)
     ap.add_argument("--gemm-backend", choices=["int8", "fp8", "f64"], default="int8")
     ap.add_argument("--sweep-n", type=int, default=1024,
                     help="order of the back-end comparison LU (0 = skip)")
     ap.add_argument("--sweep-block", type=int, default=128)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -132,8 +157,18 @@ def main():
     import paper_2609_29554_amd as Z
     import workloads as W
 
+    if args.copy_calibration_mib > 0:
+        src = torch.ones(args.copy_calibration_mib * (1 << 20) // 8, dtype=torch.float64,
+                         device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     if args.workload == "gemm":
         return bench_gemm(args)
+    if args.workload == "schur":
+        return bench_schur(args)
 
     n, nc, b = args.n, args.nc, args.block
     log(f"generating Lotkin n={n} nc={nc}")
@@ -184,15 +219,18 @@ def main():
         if not launches or ms <= 0:
             return None
         per_launch_ms = ms / launches
+        traffic = traffic_of(name, "pmc_traffic_lu_qd2048_lotkin.md")
         if bound == "mfma":
             achieved = ops / launches / (per_launch_ms * 1e-3) / 1e12
             return {"bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_TOPS,
-                    "unit": "TOP/s", "frac": achieved / PEAK_INT8_TOPS, "traffic": None,
-                    "kernel": name, "avg_launch_ms": per_launch_ms, "launches": launches / K}
+                    "unit": "TOP/s", "frac": achieved / PEAK_INT8_TOPS, "traffic": traffic,
+                    "kernel": name, "avg_launch_ms": per_launch_ms, "launches": launches / K,
+                    "algorithmic_bytes_per_launch": by / launches}
         achieved = by / launches / (per_launch_ms * 1e-3) / 1e9
         return {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": name,
-                "avg_launch_ms": per_launch_ms, "launches": launches / K}
+                "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": name,
+                "avg_launch_ms": per_launch_ms, "launches": launches / K,
+                "algorithmic_bytes_per_launch": by / launches}
 
     rooflines = {"gemm": roof("gemm", "mfma"), "producer": roof("producer", "hbm"),
                  "consumer": roof("consumer", "hbm")}
@@ -318,6 +356,49 @@ def backend_sweep(ctx, args):
     return out
 
 
+def bench_schur(args):
+    """The Ozaki-II Schur updates of the QD Lotkin LU (n, b) alone: for every
+    step, C = C - A B with the update's shape (M = N = n-k-b, K = b) on blocks
+    of the Lotkin matrix.  Same kernels, shapes and plan as inside the LU, no
+    panel; used to take hardware counters of the update kernels."""
+    import torch
+
+    import paper_2609_29554_amd as Z
+    import workloads as W
+
+    n, nc, b = args.n, args.nc, args.block
+    A0 = torch.from_numpy(W.lotkin(n, nc)).cuda()
+    ctx = Z.Context(0)
+    shapes = schur_shapes(n, b)
+    work = [(A0[:kb, b:b + m].clone(), A0[b:b + m, :kb].clone(), A0[b:b + m, b:b + m].clone())
+            for m, kb in shapes]   # (K x M), (N x K), (N x M) blocks in (cols, rows, nc) layout
+    ctx.reserve(nc, shapes[0][0], shapes[0][0], b, 0, None)
+    for _ in range(max(args.warmup, 1)):
+        for L21, U12, A22 in work:
+            ctx.gemm(1, L21, U12, A22)
+    ctx.sync_check()
+    ctx.set_profiling(True)
+    ctx.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for L21, U12, A22 in work:
+            ctx.gemm(1, L21, U12, A22)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.set_profiling(False)
+    sec = (t1 - t0) / args.steps
+    out = {"metric": METRIC, "value": sec, "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64x4+i8", "data": "synthetic",
+           "config": {"workload": f"Ozaki-II Schur updates of the QD Lotkin LU n={n} b={b}",
+                      "shapes": shapes},
+           "stages": {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps}
+                      for k, v in prof.items() if v[1]}}
+    print(json.dumps(out))
+
+
 def bench_gemm(args):
     """Standalone Ozaki-II product C = A B, triple-double, m = n = k = N,
     entries with uniform mantissas and exponents round(N(0, 16))."""
@@ -358,16 +439,18 @@ def bench_gemm(args):
     K = args.steps
     ms, launches, by, ops = prof["gemm"]
     ach = ops / launches / (ms / launches * 1e-3) / 1e12
+    fam = {"int8": "k_gemm_i8_p", "fp8": "k_gemm_f8", "f64": "k_gemm_f64"}[args.gemm_backend]
+    prof_md = f"pmc_traffic_gemm_td{n}_{args.gemm_backend}.md"
     roof = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TOP/s",
-            "frac": ach / peak, "traffic": None, "kernel": "gemm",
-            "avg_launch_ms": ms / launches}
+            "frac": ach / peak, "traffic": traffic_of("gemm", prof_md, fam), "kernel": "gemm",
+            "avg_launch_ms": ms / launches, "algorithmic_bytes_per_launch": by / launches}
     rooflines = {"gemm": roof}
     for k in ("producer", "consumer"):
         m2, l2, b2, _ = prof[k]
         a2 = b2 / l2 / (m2 / l2 * 1e-3) / 1e9
         rooflines[k] = {"bound": "hbm", "achieved": a2, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                        "frac": a2 / PEAK_HBM_GBS, "traffic": None, "kernel": k,
-                        "avg_launch_ms": m2 / l2}
+                        "frac": a2 / PEAK_HBM_GBS, "traffic": traffic_of(k, prof_md), "kernel": k,
+                        "avg_launch_ms": m2 / l2, "algorithmic_bytes_per_launch": b2 / l2}
     out = {
         "metric": METRIC, "value": sec, "unit": "s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": False,

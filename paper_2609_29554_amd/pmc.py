@@ -1,0 +1,115 @@
+"""HBM traffic of the Ozaki-II kernels from rocprofv3 counter runs.
+
+Two runs of the same command, one with ``--pmc FETCH_SIZE`` and one with
+``--pmc WRITE_SIZE`` (the counters read KiB per dispatch), each also timing a
+plain device copy of known size (``bench.py --copy-calibration-mib N``).
+Per kernel family the mean counter value per dispatch is scaled by
+(known copy bytes) / (counter value of the copy) -- one factor for reads,
+one for writes -- and reported as bytes per launch, next to the sha256 of
+the kernel sources it was measured on.  bench.py uses the figures only while
+that source is unchanged.
+
+    python -m paper_2609_29554_amd.pmc FETCH.csv WRITE.csv COPY_MIB OUT.md "command"
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import os
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+# everything that decides what the Ozaki-II kernels read and write
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in
+                  ("k_ozaki.hip", "ozii_elem.hpp", "expansion.hpp", "ozii.cpp")]
+FAMILIES = ("k_producer", "k_gemm_i8_p", "k_gemm_i8", "k_gemm_f8", "k_gemm_f64", "k_consumer")
+
+
+def source_sha() -> str:
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _family(name: str):
+    for fam in FAMILIES:  # longer names first where one is a prefix of another
+        if fam + "<" in name or fam + "(" in name:
+            return fam
+    return None
+
+
+def _read(path: str, counter: str):
+    per = defaultdict(list)
+    copies = []
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        v = float(r["Counter_Value"])
+        fam = _family(r["Kernel_Name"])
+        if fam:
+            per[fam].append(v)
+        elif "copy" in r["Kernel_Name"].lower() or "elementwise" in r["Kernel_Name"]:
+            copies.append(v)
+    return per, copies
+
+
+def summarize(fetch_csv: str, write_csv: str, copy_mib: float):
+    f_per, f_copy = _read(fetch_csv, "FETCH_SIZE")
+    w_per, w_copy = _read(write_csv, "WRITE_SIZE")
+    want_kib = copy_mib * 1024.0
+    # the calibration copy is the largest copy-like dispatch of each run
+    ff = want_kib / max(f_copy) if f_copy else None
+    fw = want_kib / max(w_copy) if w_copy else None
+    out = {}
+    for fam in sorted(set(f_per) | set(w_per)):
+        fk = sum(f_per[fam]) / len(f_per[fam]) if f_per.get(fam) else None
+        wk = sum(w_per[fam]) / len(w_per[fam]) if w_per.get(fam) else None
+        rec = {"dispatches": max(len(f_per.get(fam, [])), len(w_per.get(fam, []))),
+               "fetch_kib_per_launch": fk, "write_kib_per_launch": wk}
+        if fk is not None and wk is not None and ff and fw:
+            rec["hbm_bytes_per_launch"] = (fk * ff + wk * fw) * 1024.0
+        out[fam] = rec
+    return {"copy_mib": copy_mib, "fetch_factor": ff, "write_factor": fw,
+            "kernel_source_sha256": source_sha(), "kernels": out}
+
+
+def write_md(summary, path: str, command: str, title: str):
+    lines = [f"# {title}", "", "Commands (run from /tmp on the MI355X box, repository at $R):", "```",
+             command, "```", "",
+             f"Calibration: a device copy of {summary['copy_mib']} MiB in the same runs; "
+             f"FETCH_SIZE factor {summary['fetch_factor']:.4f}, WRITE_SIZE factor "
+             f"{summary['write_factor']:.4f} (known bytes / counter bytes).", "",
+             "| kernel | dispatches | FETCH KiB / launch | WRITE KiB / launch | HBM bytes / launch (scaled) |",
+             "|---|---:|---:|---:|---:|"]
+    for fam, r in summary["kernels"].items():
+        hb = r.get("hbm_bytes_per_launch")
+        lines.append(f"| `{fam}` | {r['dispatches']} | {r['fetch_kib_per_launch'] or 0:.1f} | "
+                     f"{r['write_kib_per_launch'] or 0:.1f} | {hb if hb is None else f'{hb:.4g}'} |")
+    lines += ["", "Machine-readable (bench.py reads this block):", "```json",
+              json.dumps(summary), "```", ""]
+    with open(path, "w") as f:
+        f.write("\n".join(lines))
+
+
+def load(path: str):
+    """The summary stored in a profiles/*.md file, or None."""
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    i = text.find("```json")
+    if i < 0:
+        return None
+    j = text.find("```", i + 7)
+    return json.loads(text[i + 7:j])
+
+
+if __name__ == "__main__":
+    fetch_csv, write_csv, mib, out_md, cmd = sys.argv[1:6]
+    title = sys.argv[6] if len(sys.argv) > 6 else "HBM traffic per kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE)"
+    s = summarize(fetch_csv, write_csv, float(mib))
+    write_md(s, out_md, cmd, title)
+    print(json.dumps(s, indent=1))
