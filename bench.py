@@ -141,6 +141,8 @@ def main():
     ap.add_argument("--sweep-n", type=int, default=1024,
                     help="order of the back-end comparison LU (0 = skip)")
     ap.add_argument("--sweep-block", type=int, default=128)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use --block and the INT8 back-end instead of the autotuner's choice")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -180,18 +182,30 @@ def main():
     db0 = torch.from_numpy(rhs0).to(dev)
     dA = torch.empty_like(dA0)
     dx = torch.empty_like(db0)
-    ctx.reserve(nc, 0, 0, 0, n, Z.make_opts(block=b))
+    names = {Z.BE_INT8: "int8", Z.BE_FP8_B17: "fp8", Z.BE_F64MOD: "f64"}
+    tuning = None
+    if args.no_autotune:
+        run_opts = Z.make_opts(block=b, backend=Z.BE_INT8)
+    else:
+        log("autotune")
+        import tempfile
+        run_opts, tuning = ctx.tune(nc, n, os.path.join(tempfile.gettempdir(), "ozii_tune.json"))
+        b = run_opts.block
+        log(f"autotuner: b={b} update={'native' if run_opts.method == Z.METHOD_NAIVE else names[run_opts.backend]}")
+    run_method = run_opts.method
+    update_name = "native" if run_method == Z.METHOD_NAIVE else names[run_opts.backend or Z.BE_INT8]
+    ctx.reserve(nc, 0, 0, 0, n, run_opts)
 
-    def step(method, blk):
+    def step(method, blk, opts=None):
         dA.copy_(dA0)
         dx.copy_(db0)
-        ipiv, info = ctx.getrf(dA, block=blk, method=method)
+        ipiv, info = ctx.getrf(dA, block=blk, method=method, opts=opts)
         ctx.getrs(dA, ipiv, dx)
         return ipiv, info
 
     log("warmup")
     for _ in range(args.warmup):
-        step(Z.METHOD_OZAKI, b)
+        step(run_method, b, run_opts)
     ctx.sync_check()
     ctx.set_profiling(True)
     ctx.profile_read()
@@ -199,7 +213,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        ipiv, info = step(Z.METHOD_OZAKI, b)
+        ipiv, info = step(run_method, b, run_opts)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = ctx.profile_read()
@@ -219,11 +233,13 @@ def main():
         if not launches or ms <= 0:
             return None
         per_launch_ms = ms / launches
-        traffic = traffic_of(name, "pmc_traffic_lu_qd2048_lotkin.md")
+        traffic = (traffic_of(name, "pmc_traffic_lu_qd2048_lotkin.md")
+                   if update_name == "int8" and b == 256 else None)
         if bound == "mfma":
+            peak = PEAK_MFMA[update_name]
             achieved = ops / launches / (per_launch_ms * 1e-3) / 1e12
-            return {"bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_TOPS,
-                    "unit": "TOP/s", "frac": achieved / PEAK_INT8_TOPS, "traffic": traffic,
+            return {"bound": "mfma", "achieved": achieved, "peak": peak,
+                    "unit": "TOP/s", "frac": achieved / peak, "traffic": traffic,
                     "kernel": name, "avg_launch_ms": per_launch_ms, "launches": launches / K,
                     "algorithmic_bytes_per_launch": by / launches}
         achieved = by / launches / (per_launch_ms * 1e-3) / 1e9
@@ -232,10 +248,14 @@ def main():
                 "avg_launch_ms": per_launch_ms, "launches": launches / K,
                 "algorithmic_bytes_per_launch": by / launches}
 
-    rooflines = {"gemm": roof("gemm", "mfma"), "producer": roof("producer", "hbm"),
-                 "consumer": roof("consumer", "hbm")}
-    ozk_ms = {k: prof[k][0] for k in ("producer", "gemm", "consumer")}
-    dominant = max(ozk_ms, key=lambda k: ozk_ms[k])
+    if run_method == Z.METHOD_NAIVE:
+        rooflines = {}
+        dominant = None
+    else:
+        rooflines = {"gemm": roof("gemm", "mfma"), "producer": roof("producer", "hbm"),
+                     "consumer": roof("consumer", "hbm")}
+        ozk_ms = {k: prof[k][0] for k in ("producer", "gemm", "consumer")}
+        dominant = max(ozk_ms, key=lambda k: ozk_ms[k])
     schur_ms = sum(prof[k][0] for k in ("exponents", "producer", "gemm", "consumer")) / K
     gemm_ms, gemm_ops = prof["gemm"][0], prof["gemm"][3]
     gops = gemm_ops / (gemm_ms * 1e-3) / 1e9 if gemm_ms > 0 else None
@@ -281,17 +301,20 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64x4+i8",
+        "dtype": {"int8": "f64x4+i8", "fp8": "f64x4+fp8", "f64": "f64x4", "native": "f64x4"}[update_name],
         "data": "synthetic",
-        "config": {"workload": f"Lotkin quad-double LU n={n} b={b} (getrf+getrs), Ozaki-II INT8",
-                   "n": n, "nc": nc, "block": b, "backend": "int8"},
-        "roofline": rooflines[dominant],
+        "config": {"workload": f"Lotkin quad-double LU n={n} (getrf+getrs), b={b}, Schur update "
+                               f"{'Ozaki-II ' + update_name if update_name != 'native' else 'native'}"
+                               f"{' (autotuned)' if tuning else ''}",
+                   "n": n, "nc": nc, "block": b, "update": update_name},
+        "autotune": tuning,
+        "roofline": rooflines[dominant] if dominant else None,
         "rooflines": rooflines,
         "cpu_baseline": cpu,
         "native_qd_lu": native,
         "schur_update_ms": schur_ms,
         "gemm_gops": gops,
-        "gemm_frac_int8_peak": (gops / 1e3 / PEAK_INT8_TOPS) if gops else None,
+        "gemm_frac_peak": (gops / 1e3 / PEAK_MFMA.get(update_name, PEAK_INT8_TOPS)) if gops else None,
         "stages": stages,
         "info": info_v,
         "correct_bits": bits,

@@ -151,6 +151,40 @@ ozII_status ozII_getrf(ozII_handle h, int32_t nc, int64_t n, double *A, int64_t 
 ozII_status ozII_getrs(ozII_handle h, int32_t nc, int64_t n, int64_t nrhs, const double *LU,
                        int64_t lda, const int64_t *ipiv, double *B, int64_t ldb);
 
+/* Autotuner (the tuning step of Sec. 4.1, "only timing at the actual size is
+ * trustworthy"): chooses the panel width b (64, 128, 256, 512 below n) and
+ * the Schur update -- one of the three back-ends or the native expansion
+ * update -- for nc-component expansions and order n.  Candidates are ordered
+ * by a cost model (engine throughput x bits per modulus, plane and t-plane
+ * traffic) and every one is timed with HIP events around ozII_getrf of a
+ * synthetic diagonally dominant n x n matrix on the handle's stream; the
+ * fastest is returned in *best (block, backend, method; other fields 0).
+ * Candidates the library cannot run at this size (OZII_EUNSUPPORTED: a panel
+ * that does not fit in LDS, a plan beyond the compiled word sizes) are
+ * skipped; the report lists the timed ones.
+ * With a cache path (host file, JSON array with one object per line, keyed by
+ * the device's architecture name, nc and n) a cached choice is returned
+ * without timing unless OZII_TUNE_RETUNE is set, and a new choice is stored.
+ * Allocates a scratch matrix of n*n*nc doubles for the duration of the call
+ * and synchronises the stream; rep may be null. */
+#define OZII_TUNE_RETUNE 1
+#define OZII_TUNE_MAXCAND 16
+typedef struct {
+  int32_t ncand;                         /* candidates timed (1 when cached)     */
+  int32_t best;                          /* index of the choice                  */
+  int32_t from_cache;                    /* 1: taken from the cache file          */
+  int32_t reserved;
+  ozII_opts cand[OZII_TUNE_MAXCAND];     /* the candidates, in model order       */
+  double ms[OZII_TUNE_MAXCAND];          /* measured getrf time [ms]             */
+  double model_ms[OZII_TUNE_MAXCAND];    /* the model's estimate [ms]            */
+} ozII_tune_report;
+
+ozII_status ozII_tune(ozII_handle h, int32_t nc, int64_t n, const char *cache_path,
+                      int32_t flags, ozII_opts *best, ozII_tune_report *rep);
+
+/* The HIP stream the handle enqueues on (as a void*). */
+ozII_status ozII_stream_of(ozII_handle h, void **stream);
+
 /* Wait for the handle's stream and report a device-side error flag raised by
  * a kernel (a grid barrier that did not complete). */
 ozII_status ozII_sync_check(ozII_handle h);

@@ -42,8 +42,17 @@ _i32 = C.c_int32
 
 EXPORTED = ["ozII_create", "ozII_destroy", "ozII_set_stream", "ozII_plan_query", "ozII_reserve",
             "ozII_gemm", "ozII_gemm_stages", "ozII_gemm_stage_dims", "ozII_getrf", "ozII_getrs",
-            "ozII_sync_check", "ozII_set_profiling", "ozII_profile_read", "ozII_status_string",
-            "ozII_last_error"]
+            "ozII_tune", "ozII_stream_of", "ozII_sync_check", "ozII_set_profiling",
+            "ozII_profile_read", "ozII_status_string", "ozII_last_error"]
+
+TUNE_RETUNE = 1
+TUNE_MAXCAND = 16
+
+
+class TuneReport(C.Structure):
+    _fields_ = [("ncand", C.c_int32), ("best", C.c_int32), ("from_cache", C.c_int32),
+                ("reserved", C.c_int32), ("cand", Opts * TUNE_MAXCAND),
+                ("ms", C.c_double * TUNE_MAXCAND), ("model_ms", C.c_double * TUNE_MAXCAND)]
 
 STAGES = ["exponents", "producer", "gemm", "consumer", "panel", "laswp", "trsm", "naive_update",
           "getrs"]
@@ -71,6 +80,8 @@ def lib():
                                            C.POINTER(_i32), C.POINTER(_i32)]
         L.ozII_getrf.argtypes = [_p, _i32, _i64, _p, _i64, _p, _p, OP]
         L.ozII_getrs.argtypes = [_p, _i32, _i64, _i64, _p, _i64, _p, _p, _i64]
+        L.ozII_tune.argtypes = [_p, _i32, _i64, C.c_char_p, _i32, OP, C.POINTER(TuneReport)]
+        L.ozII_stream_of.argtypes = [_p, C.POINTER(_p)]
         L.ozII_sync_check.argtypes = [_p]
         L.ozII_set_profiling.argtypes = [_p, _i32]
         L.ozII_profile_read.argtypes = [_p, _i32, _p, _p, _p, _p]
@@ -234,6 +245,23 @@ class Context:
         self._call(lib().ozII_getrs(self._h, nc, n, nrhs, _ptr(LU), max(n, 1), _ptr(ipiv),
                                     _ptr(B), max(n, 1)))
         return B
+
+    def tune(self, nc: int, n: int, cache_path: Optional[str] = None, retune: bool = False):
+        """Autotune (block, back-end or native update) for order n; returns
+        (Opts, report dict with the timed candidates)."""
+        best = Opts()
+        rep = TuneReport()
+        self._bind()
+        self._call(lib().ozII_tune(self._h, nc, n, cache_path.encode() if cache_path else None,
+                                   TUNE_RETUNE if retune else 0, C.byref(best), C.byref(rep)))
+        names = {BE_INT8: "int8", BE_FP8_B17: "fp8", BE_F64MOD: "f64"}
+        cands = []
+        for i in range(rep.ncand):
+            o = rep.cand[i]
+            cands.append({"block": o.block,
+                          "update": "native" if o.method == METHOD_NAIVE else names.get(o.backend, "?"),
+                          "ms": rep.ms[i], "model_ms": rep.model_ms[i]})
+        return best, {"from_cache": bool(rep.from_cache), "best": rep.best, "candidates": cands}
 
     def sync_check(self):
         self._call(lib().ozII_sync_check(self._h))

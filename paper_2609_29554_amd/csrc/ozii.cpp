@@ -779,6 +779,12 @@ ozII_status ozII_getrs(ozII_handle h, int32_t nc, int64_t n, int64_t nrhs, const
   return OZII_OK;
 }
 
+ozII_status ozII_stream_of(ozII_handle h, void **stream) {
+  if (!h || !stream) return OZII_EINVAL;
+  *stream = (void *)h->stream;
+  return OZII_OK;
+}
+
 ozII_status ozII_sync_check(ozII_handle h) {
   if (!h) return OZII_EINVAL;
   hipError_t e = hipStreamSynchronize(h->stream);
