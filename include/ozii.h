@@ -151,6 +151,38 @@ ozII_status ozII_getrf(ozII_handle h, int32_t nc, int64_t n, double *A, int64_t 
 ozII_status ozII_getrs(ozII_handle h, int32_t nc, int64_t n, int64_t nrhs, const double *LU,
                        int64_t lda, const int64_t *ipiv, double *B, int64_t ldb);
 
+/* Batched LU + solve of many independent small systems in one persistent
+ * launch.  Each item is an n x n matrix of nc-component expansions
+ * (column-major, lda = n, device memory, factored in place), an optional
+ * right-hand side b of n expansions (device; overwritten by the solution),
+ * ipiv (device, n entries, 0-based LAPACK semantics) and info (device, one
+ * int32).  Items may mix DD / TD / QD and orders.  Every item is factored by
+ * one workgroup with the unblocked right-looking LU (partial pivoting) and
+ * the native expansion update -- per element the operations of ozII_getrf
+ * with block = 1, method = native -- then solved as ozII_getrs does.
+ *
+ * ozII_batch_prepare (host, synchronous) validates the items, orders them by
+ * decreasing cost nc n^3 (longest first) and uploads the table into
+ * handle-owned device memory, replacing any previous batch; ozII_batch_run
+ * enqueues the queue reset and the persistent kernel on the handle's stream,
+ * allocates nothing and may be captured in a hipGraph.  times (device, may be
+ * null) receives 2 per item in the caller's item order: the 100 MHz
+ * real-time counter when its workgroup started and when it finished.
+ * Errors: OZII_EINVAL for a bad item (nc outside 2..4, n < 1 or > 4096, null
+ * A/ipiv/info). */
+typedef struct {
+  int32_t nc;
+  int32_t reserved;
+  int64_t n;
+  double *A;
+  double *b;
+  int64_t *ipiv;
+  int32_t *info;
+} ozII_batch_item;
+
+ozII_status ozII_batch_prepare(ozII_handle h, int32_t count, const ozII_batch_item *items);
+ozII_status ozII_batch_run(ozII_handle h, uint64_t *times);
+
 /* Autotuner (the tuning step of Sec. 4.1, "only timing at the actual size is
  * trustworthy"): chooses the panel width b (64, 128, 256, 512 below n) and
  * the Schur update -- one of the three back-ends or the native expansion

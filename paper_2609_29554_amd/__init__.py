@@ -42,8 +42,14 @@ _i32 = C.c_int32
 
 EXPORTED = ["ozII_create", "ozII_destroy", "ozII_set_stream", "ozII_plan_query", "ozII_reserve",
             "ozII_gemm", "ozII_gemm_stages", "ozII_gemm_stage_dims", "ozII_getrf", "ozII_getrs",
-            "ozII_tune", "ozII_stream_of", "ozII_sync_check", "ozII_set_profiling",
+            "ozII_batch_prepare", "ozII_batch_run", "ozII_tune", "ozII_stream_of",
+            "ozII_sync_check", "ozII_set_profiling",
             "ozII_profile_read", "ozII_status_string", "ozII_last_error"]
+
+class BatchItem(C.Structure):
+    _fields_ = [("nc", C.c_int32), ("reserved", C.c_int32), ("n", C.c_int64), ("A", C.c_void_p),
+                ("b", C.c_void_p), ("ipiv", C.c_void_p), ("info", C.c_void_p)]
+
 
 TUNE_RETUNE = 1
 TUNE_MAXCAND = 16
@@ -81,6 +87,8 @@ def lib():
         L.ozII_getrf.argtypes = [_p, _i32, _i64, _p, _i64, _p, _p, OP]
         L.ozII_getrs.argtypes = [_p, _i32, _i64, _i64, _p, _i64, _p, _p, _i64]
         L.ozII_tune.argtypes = [_p, _i32, _i64, C.c_char_p, _i32, OP, C.POINTER(TuneReport)]
+        L.ozII_batch_prepare.argtypes = [_p, _i32, C.POINTER(BatchItem)]
+        L.ozII_batch_run.argtypes = [_p, _p]
         L.ozII_stream_of.argtypes = [_p, C.POINTER(_p)]
         L.ozII_sync_check.argtypes = [_p]
         L.ozII_set_profiling.argtypes = [_p, _i32]
@@ -245,6 +253,27 @@ class Context:
         self._call(lib().ozII_getrs(self._h, nc, n, nrhs, _ptr(LU), max(n, 1), _ptr(ipiv),
                                     _ptr(B), max(n, 1)))
         return B
+
+    def batch_prepare(self, systems):
+        """Upload a batch: systems = [(A, b or None, ipiv, info), ...] of CUDA
+        tensors, A (n, n, nc) float64, b (1, n, nc) float64, ipiv int64[n],
+        info int32[1]; the tensors must stay alive while the batch is used."""
+        arr = (BatchItem * max(len(systems), 1))()
+        for i, (A, b, ipiv, info) in enumerate(systems):
+            _check_mat(A)
+            if b is not None:
+                _check_mat(b, A.shape[2])
+            arr[i] = BatchItem(A.shape[2], 0, A.shape[0], _ptr(A), _ptr(b) if b is not None else None,
+                               _ptr(ipiv), _ptr(info))
+        self._batch_refs = list(systems)
+        self._bind()
+        self._call(lib().ozII_batch_prepare(self._h, len(systems), arr))
+
+    def batch_run(self, times=None):
+        """Factor and solve the prepared batch (graph-capturable); times: CUDA
+        int64 tensor of 2 * count, start/end stamps of the 100 MHz counter."""
+        self._bind()
+        self._call(lib().ozII_batch_run(self._h, _ptr(times) if times is not None else None))
 
     def tune(self, nc: int, n: int, cache_path: Optional[str] = None, retune: bool = False):
         """Autotune (block, back-end or native update) for order n; returns

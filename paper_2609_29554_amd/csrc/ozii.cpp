@@ -277,6 +277,10 @@ struct ozII_ctx {
   // getrs: reciprocals of the diagonal of U
   double *rinv = nullptr;
   int64_t rinv_cap = 0;
+  // batched LU: the uploaded item table (processing order) and its queue
+  ozII_batch_item *batch = nullptr;
+  int batch_cap = 0, batch_count = 0, batch_grid = 1;
+  int *batch_queue = nullptr;
   std::map<std::tuple<int, int64_t, int, int, int, int>, std::pair<HostPlan, DevPlan *>> plans;
   // per-stage profiling (HIP events on the handle's stream)
   struct ProfRec {
@@ -551,6 +555,8 @@ ozII_status ozII_destroy(ozII_handle h) {
   for (auto &kv : h->plans) hipFree(kv.second.second);
   for (auto ev : h->pool) hipEventDestroy(ev);
   if (h->rinv) hipFree(h->rinv);
+  if (h->batch) hipFree(h->batch);
+  if (h->batch_queue) hipFree(h->batch_queue);
   if (h->bar) {
     hipFree(h->bar);
     hipFree(h->flags);
@@ -776,6 +782,55 @@ ozII_status ozII_getrs(ozII_handle h, int32_t nc, int64_t n, int64_t nrhs, const
         return hip_fail(h, e, "backward update");
     }
   }
+  return OZII_OK;
+}
+
+ozII_status ozII_batch_prepare(ozII_handle h, int32_t count, const ozII_batch_item *items) {
+  if (!h || count < 0 || (count > 0 && !items)) return OZII_EINVAL;
+  std::vector<ozII_batch_item> v(items, items + count);
+  for (int i = 0; i < count; ++i) {
+    const ozII_batch_item &it = v[i];
+    if (it.nc < 2 || it.nc > 4 || it.n < 1 || it.n > 4096 || !it.A || !it.ipiv || !it.info)
+      return fail(h, OZII_EINVAL, "batch item " + std::to_string(i) + " is invalid");
+    v[i].reserved = i;
+  }
+  // longest processing time first: cost ~ nc n^3, ties in caller order
+  std::stable_sort(v.begin(), v.end(), [](const ozII_batch_item &a, const ozII_batch_item &b) {
+    return (double)a.nc * a.n * a.n * a.n > (double)b.nc * b.n * b.n * b.n;
+  });
+  hipError_t e;
+  if (count > h->batch_cap) {
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+    if (h->batch) hipFree(h->batch);
+    h->batch = nullptr;
+    h->batch_cap = 0;
+    if ((e = hipMalloc((void **)&h->batch, sizeof(ozII_batch_item) * count)) != hipSuccess)
+      return fail(h, OZII_ENOMEM, "batch table allocation failed");
+    h->batch_cap = count;
+  }
+  if (!h->batch_queue && (e = hipMalloc((void **)&h->batch_queue, 256)) != hipSuccess)
+    return fail(h, OZII_ENOMEM, "batch queue allocation failed");
+  if (count > 0 &&
+      (e = hipMemcpyAsync(h->batch, v.data(), sizeof(ozII_batch_item) * count, hipMemcpyHostToDevice,
+                          h->stream)) != hipSuccess)
+    return hip_fail(h, e, "batch upload");
+  if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+  // persistent grid: one 1024-thread workgroup per CU, at most one per item
+  int dev = 0, ncu = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess ||
+      (e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return hip_fail(h, e, "device query");
+  h->batch_count = count;
+  h->batch_grid = std::max(1, std::min(count, ncu));
+  return OZII_OK;
+}
+
+ozII_status ozII_batch_run(ozII_handle h, uint64_t *times) {
+  if (!h) return OZII_EINVAL;
+  if (h->batch_count == 0) return OZII_OK;
+  hipError_t e = ozl::launch_batch(h->batch, h->batch_count, h->batch_queue, times, h->batch_grid,
+                                   h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "batched LU");
   return OZII_OK;
 }
 

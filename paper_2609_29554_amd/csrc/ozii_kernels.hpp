@@ -4,6 +4,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/ozii.h"
+
 namespace ozk {
 struct DevPlan;
 }
@@ -81,5 +83,10 @@ hipError_t launch_naive_gemm(int nc, const double *A, int64_t lda, const double 
 hipError_t launch_apply_ipiv(int nc, double *B, int64_t ldb, int64_t n, int64_t nrhs,
                              const int64_t *ipiv, hipStream_t s);
 hipError_t launch_fill_int(int *p, int v, int64_t cnt, hipStream_t s);
+
+// batched LU + solve (k_batch.hip); items in processing order, each with its
+// caller-order index in `reserved`
+hipError_t launch_batch(const ozII_batch_item *items, int count, int *queue, uint64_t *times,
+                        int grid, hipStream_t s);
 
 }  // namespace ozl

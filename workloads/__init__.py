@@ -130,3 +130,20 @@ def to_dense_fraction(X):
     cols, rows, nc = X.shape
     return [[sum((Fraction(float(X[j, i, c])) for c in range(nc)), Fraction(0))
              for j in range(cols)] for i in range(rows)]
+
+
+def batch_systems(count: int, rng: np.random.Generator, n_lo: int = 64, n_hi: int = 512):
+    """The batched configuration: `count` independent systems, orders uniform
+    in [n_lo, n_hi], even items double-double and odd items quad-double,
+    A = D R D with R ~ N(0, 1) and D = diag(10^(c/2 * i/(n-1))), c uniform in
+    [20, 60] -- D rounded to powers of two so the scaled entries stay exact
+    expansions (the same grading as `graded`) -- and b = A * ones.  Returns a
+    list of (nc, A, b) with A of shape (n, n, nc) and b of shape (1, n, nc)."""
+    out = []
+    for k in range(count):
+        n = int(rng.integers(n_lo, n_hi + 1))
+        nc = 2 if k % 2 == 0 else 4
+        c = float(rng.uniform(20.0, 60.0))
+        A = graded(n, nc, c, rng)
+        out.append((nc, A, rhs_ones(A)))
+    return out
