@@ -632,30 +632,36 @@ __global__ __launch_bounds__(256) void k_naive_gemm(const double *A, int64_t lda
 }
 
 // getrs: apply the interchanges ipiv[0..n) in order to one column of B.
+// Row interchanges of the solve, b <- P b with P the product of the
+// transpositions (j, ipiv[j]), j ascending (LAPACK's i?laswp).  One
+// workgroup per right-hand side.  use_lds: the pivots are staged in LDS,
+// thread 0 composes the transpositions on row indices (src[j] = row that
+// ends at position j), and the expansions are then gathered in parallel.
 template <int NC>
 __global__ __launch_bounds__(256) void k_apply_ipiv(double *B, int64_t ldb, int64_t n,
                                                     const int64_t *ipiv, int use_lds) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   double *col = B + (int64_t)blockIdx.x * ldb * NC;
   if (use_lds) {
-    double *s = (double *)smem_raw;
-    for (int64_t e = threadIdx.x; e < n * NC; e += 256) s[e] = col[e];
+    double *xs = (double *)smem_raw;               // n * NC
+    int *pv = (int *)(xs + n * NC);                // n
+    int *src = pv + n;                             // n
+    for (int64_t e = threadIdx.x; e < n * NC; e += 256) xs[e] = col[e];
+    for (int64_t j = threadIdx.x; j < n; j += 256) {
+      pv[j] = (int)ipiv[j];
+      src[j] = (int)j;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-      for (int64_t j = 0; j < n; ++j) {
-        const int64_t p = ipiv[j];
-        if (p != j) {
-#pragma unroll
-          for (int q = 0; q < NC; ++q) {
-            double t = s[j * NC + q];
-            s[j * NC + q] = s[p * NC + q];
-            s[p * NC + q] = t;
-          }
-        }
+      for (int j = 0; j < (int)n; ++j) {
+        const int p = pv[j];
+        const int t = src[j];
+        src[j] = src[p];
+        src[p] = t;
       }
     }
     __syncthreads();
-    for (int64_t e = threadIdx.x; e < n * NC; e += 256) col[e] = s[e];
+    for (int64_t e = threadIdx.x; e < n * NC; e += 256) col[e] = xs[(int64_t)src[e / NC] * NC + e % NC];
   } else if (threadIdx.x == 0) {
     for (int64_t j = 0; j < n; ++j) {
       const int64_t p = ipiv[j];
@@ -668,6 +674,129 @@ __global__ __launch_bounds__(256) void k_apply_ipiv(double *B, int64_t ldb, int6
         }
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Triangular solves of getrs for one right-hand side, pipelined over the
+// whole grid (one cooperative launch per direction).  Workgroup w owns the
+// rows at processing positions [w R, w R + R): rows 0.. in the forward
+// solve with the unit lower factor, rows n-1.. in the backward solve with
+// the upper factor.  While earlier blocks are being finished it applies
+// their published solution values to its own rows -- the products l_ik x_k
+// in parallel, then the subtractions in the order the specification fixes
+// (ascending k forward, descending backward), so every element sees exactly
+// fms(x_i, l_ik, x_k) = x_i (+) (-(l_ik (x) x_k)) in that order -- then solves
+// its diagonal block, stores its R values and publishes the count of
+// finished positions (agent release, then the counter).  Waits are bounded
+// like the panel's.
+// ---------------------------------------------------------------------------
+constexpr int TRSV_R = 16;  // rows per workgroup
+constexpr int TRSV_B = 32;  // solution values applied per batch
+
+template <int NC, bool FWD>
+__global__ __launch_bounds__(256) void k_trsv(const double *LU, int64_t lda, double *x,
+                                              const double *rinv, int64_t n, uint32_t *ready,
+                                              int *err) {
+  __shared__ double xs[TRSV_R][NC];
+  __shared__ double ys[TRSV_B][NC];
+  __shared__ double pr[TRSV_R][TRSV_B][NC];
+  __shared__ int s_avail, s_fail;
+  const int tid = threadIdx.x;
+  const int64_t p0 = (int64_t)blockIdx.x * TRSV_R;
+  const int cnt = (int)(n - p0 < TRSV_R ? n - p0 : TRSV_R);
+  auto row = [&](int64_t p) { return FWD ? p : n - 1 - p; };
+  auto L = [&](int64_t i, int64_t k) { return LU + (i + k * lda) * NC; };
+  if (tid < cnt * NC) (&xs[0][0])[tid] = x[row(p0 + tid / NC) * NC + tid % NC];
+  if (tid == 0) s_fail = 0;
+  __syncthreads();
+  int64_t applied = 0;
+  while (applied < p0) {
+    if (tid == 0) {
+      const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+      uint32_t spins = 0, v;
+      while ((int64_t)(v = ld_dev_u32(ready)) <= applied) {
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { s_fail = 1; break; }
+        if ((++spins & 63u) == 0 && __builtin_amdgcn_s_memrealtime() - t0 > 100000000ull) {
+          __hip_atomic_store(err, 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          s_fail = 1;
+          break;
+        }
+      }
+      s_avail = (int)((int64_t)v < p0 ? (int64_t)v : p0);
+    }
+    __syncthreads();
+    if (s_fail) return;
+    const int64_t avail = s_avail;
+    for (int64_t c0 = applied; c0 < avail; c0 += TRSV_B) {
+      const int nb = (int)(avail - c0 < TRSV_B ? avail - c0 : TRSV_B);
+      // published values: device-coherent loads, issued after the count was seen
+      if (tid < nb * NC) (&ys[0][0])[tid] = ld_dev_f64(x + row(c0 + tid / NC) * NC + tid % NC);
+      __syncthreads();
+      for (int idx = tid; idx < cnt * nb; idx += 256) {
+        const int q = idx % cnt, t = idx / cnt;
+        double a[NC], y[NC], o[NC];
+        ozx::load<NC>(L(row(p0 + q), row(c0 + t)), a);
+#pragma unroll
+        for (int e = 0; e < NC; ++e) y[e] = ys[t][e];
+        ozx::mul<NC>(a, y, o);
+#pragma unroll
+        for (int e = 0; e < NC; ++e) pr[q][t][e] = -o[e];
+      }
+      __syncthreads();
+      if (tid < cnt) {
+        double v[NC], pv[NC], o[NC];
+#pragma unroll
+        for (int e = 0; e < NC; ++e) v[e] = xs[tid][e];
+        for (int t = 0; t < nb; ++t) {
+#pragma unroll
+          for (int e = 0; e < NC; ++e) pv[e] = pr[tid][t][e];
+          ozx::add<NC>(v, pv, o);
+#pragma unroll
+          for (int e = 0; e < NC; ++e) v[e] = o[e];
+        }
+#pragma unroll
+        for (int e = 0; e < NC; ++e) xs[tid][e] = v[e];
+      }
+      __syncthreads();
+    }
+    applied = avail;
+  }
+  // the diagonal block
+  for (int q = 0; q < cnt; ++q) {
+    if (!FWD) {
+      if (tid == 0) {
+        double v[NC], r[NC], o[NC];
+#pragma unroll
+        for (int e = 0; e < NC; ++e) v[e] = xs[q][e];
+        ozx::load<NC>(rinv + row(p0 + q) * NC, r);
+        ozx::mul<NC>(v, r, o);
+#pragma unroll
+        for (int e = 0; e < NC; ++e) xs[q][e] = o[e];
+      }
+      __syncthreads();
+    }
+    const int r = q + 1 + tid;
+    if (r < cnt) {
+      double v[NC], a[NC], y[NC], o[NC];
+#pragma unroll
+      for (int e = 0; e < NC; ++e) {
+        v[e] = xs[r][e];
+        y[e] = xs[q][e];
+      }
+      ozx::load<NC>(L(row(p0 + r), row(p0 + q)), a);
+      ozx::fms<NC>(v, a, y, o);
+#pragma unroll
+      for (int e = 0; e < NC; ++e) xs[r][e] = o[e];
+    }
+    __syncthreads();
+  }
+  if (tid < cnt * NC) x[row(p0 + tid / NC) * NC + tid % NC] = (&xs[0][0])[tid];
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  __syncthreads();
+  if (tid == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(ready, (uint32_t)(p0 + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -799,7 +928,7 @@ hipError_t launch_naive_gemm(int nc, const double *A, int64_t lda, const double 
 hipError_t launch_apply_ipiv(int nc, double *B, int64_t ldb, int64_t n, int64_t nrhs,
                              const int64_t *ipiv, hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return hipSuccess;
-  const size_t lds = (size_t)n * nc * 8;
+  const size_t lds = (size_t)n * nc * 8 + (size_t)n * 8;  // expansions + pivots + sources
   const int use_lds = lds <= 160 * 1024 ? 1 : 0;
   const void *fn = nc == 2 ? (const void *)k_apply_ipiv<2>
                            : (nc == 3 ? (const void *)k_apply_ipiv<3> : (const void *)k_apply_ipiv<4>);
@@ -812,6 +941,22 @@ hipError_t launch_apply_ipiv(int nc, double *B, int64_t ldb, int64_t n, int64_t 
   if (nc == 2) hipLaunchKernelGGL(k_apply_ipiv<2>, g, dim3(256), shm, s, B, ldb, n, ipiv, use_lds);
   else if (nc == 3) hipLaunchKernelGGL(k_apply_ipiv<3>, g, dim3(256), shm, s, B, ldb, n, ipiv, use_lds);
   else hipLaunchKernelGGL(k_apply_ipiv<4>, g, dim3(256), shm, s, B, ldb, n, ipiv, use_lds);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsv(int nc, int fwd, const double *LU, int64_t lda, double *x, const double *rinv,
+                       int64_t n, uint32_t *ready, int *err, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int G = (int)((n + TRSV_R - 1) / TRSV_R);
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(256), 0, s, (int *)ready, 0, (int64_t)1);
+#define OZ_TRSV(NC_, F_) \
+  hipLaunchKernelGGL((k_trsv<NC_, F_>), dim3((unsigned)G), dim3(256), 0, s, LU, lda, x, rinv, n, ready, err)
+  if (fwd) {
+    if (nc == 2) OZ_TRSV(2, true); else if (nc == 3) OZ_TRSV(3, true); else OZ_TRSV(4, true);
+  } else {
+    if (nc == 2) OZ_TRSV(2, false); else if (nc == 3) OZ_TRSV(3, false); else OZ_TRSV(4, false);
+  }
+#undef OZ_TRSV
   return hipGetLastError();
 }
 

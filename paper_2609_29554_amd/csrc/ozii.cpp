@@ -758,6 +758,19 @@ ozII_status ozII_getrs(ozII_handle h, int32_t nc, int64_t n, int64_t nrhs, const
   }
   if ((e = ozl::launch_recip_diag(nc, LU, lda, n, h->rinv, s)) != hipSuccess) return hip_fail(h, e, "recip diag");
   if ((e = ozl::launch_apply_ipiv(nc, B, ldb, n, nrhs, ipiv, s)) != hipSuccess) return hip_fail(h, e, "apply ipiv");
+  if (nrhs == 1) {
+    // one right-hand side: the pipelined solves (same operations per element)
+    if (!h->bar) {
+      const ozII_status st = ensure_panel(h, 1, 1);
+      if (st != OZII_OK) return st;
+    }
+    uint32_t *ready = h->bar + 12;
+    if ((e = ozl::launch_trsv(nc, 1, LU, lda, B, nullptr, n, ready, h->err, s)) != hipSuccess)
+      return hip_fail(h, e, "forward solve");
+    if ((e = ozl::launch_trsv(nc, 0, LU, lda, B, h->rinv, n, ready, h->err, s)) != hipSuccess)
+      return hip_fail(h, e, "backward solve");
+    return OZII_OK;
+  }
   const int bs = 256;
   for (int64_t i0 = 0; i0 < n; i0 += bs) {
     const int ib = (int)std::min<int64_t>(bs, n - i0);
@@ -848,7 +861,7 @@ ozII_status ozII_sync_check(ozII_handle h) {
     int v = 0;
     e = hipMemcpy(&v, h->err, sizeof(int), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(h, e, "read error flag");
-    if (v) return fail(h, OZII_EDEVICE, "a panel grid barrier timed out");
+    if (v) return fail(h, OZII_EDEVICE, "a grid-wide wait timed out (panel exchange or pipelined solve)");
   }
   return OZII_OK;
 }

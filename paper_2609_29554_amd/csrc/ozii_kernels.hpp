@@ -83,6 +83,11 @@ hipError_t launch_naive_gemm(int nc, const double *A, int64_t lda, const double 
 hipError_t launch_apply_ipiv(int nc, double *B, int64_t ldb, int64_t n, int64_t nrhs,
                              const int64_t *ipiv, hipStream_t s);
 hipError_t launch_fill_int(int *p, int v, int64_t cnt, hipStream_t s);
+// pipelined triangular solve of one right-hand side (fwd: unit lower,
+// ascending; else upper with the reciprocals rinv, descending); ready: one
+// device counter owned by the caller, reset by the launcher
+hipError_t launch_trsv(int nc, int fwd, const double *LU, int64_t lda, double *x, const double *rinv,
+                       int64_t n, uint32_t *ready, int *err, hipStream_t s);
 
 // batched LU + solve (k_batch.hip); items in processing order, each with its
 // caller-order index in `reserved`

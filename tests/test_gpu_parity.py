@@ -227,6 +227,27 @@ def test_getrf_getrs_backends(case, backend):
     assert np.array_equal(to_host(dX), X)
 
 
+def test_getrs_several_rhs():
+    """Three right-hand sides take the blocked solve (one takes the pipelined
+    one); both against the oracle."""
+    nc, n, b = 4, 300, 64
+    note("getrs nrhs=3")
+    A = _matrix(nc, n, "graded", 17)
+    LU, ipiv, info, _ = O.getrf(A, b, O.METHOD_NAIVE)
+    rng = np.random.default_rng(5)
+    R = W.random_expansions(n, 3, nc, rng, exp_sigma=2)          # (3, n, nc)
+    X = O.getrs(LU, ipiv, R)
+    dLU, dX = to_dev(LU), to_dev(R)
+    import torch
+    ctx().getrs(dLU, torch.from_numpy(ipiv).cuda(), dX)
+    ctx().sync_check()
+    assert np.array_equal(to_host(dX), X)
+    dX1 = to_dev(np.ascontiguousarray(R[1:2]))
+    ctx().getrs(dLU, torch.from_numpy(ipiv).cuda(), dX1)
+    ctx().sync_check()
+    assert np.array_equal(to_host(dX1), X[1:2])
+
+
 def test_unblocked_equals_blocked_naive_on_gpu():
     nc, n = 4, 80
     note("unblocked vs blocked naive")
