@@ -87,6 +87,168 @@ __device__ __forceinline__ uint8_t e4m3_small(int32_t d) {
   return (uint8_t)(sign | ((e + 7u) << 3) | f);
 }
 
+// ---------------------------------------------------------------------------
+// Producer of the byte back-ends (INT8 residues, FP8 base-17 digits).  One
+// workgroup fills one 1 KiB block (16 rows x 64 k) of every plane; thread T
+// owns the four consecutive bytes 4T .. 4T+3 of the block, i.e. row
+// (T/4)%16 and inner indices 16(T/64) + 4(T%4) + e, e = 0..3, so each
+// residue plane receives one dword store per thread.
+//
+// Per element: X = sum_c sgn(x_c) floor(|x_c| 2^mu) (Eq. direct) in NWX
+// words; slice t of the balanced split (Sec. 3.2) is read straight from X as
+// the w-bit field at bit t w plus the incoming carry c_t:
+//   s = field + c_t;  carry = s >> w;  s mod= 2^w;  f = bit w-1 of s;
+//   v_t = s - f 2^w;  c_{t+1} = carry + f,
+// and the top slice is v = (X >> (S-1) w) + c_{S-1}, taken as a two's
+// complement number of nwt words.  Its residue for modulus m is
+//   (sum_b byte_b (2^(8b) mod m) + [f or sign] ((-2^W) mod m)) mod m,
+// W = w or 32 nwt, where the byte sum is v_dot4_u32_u8 of the slice words
+// with the table words (operands in scalar registers).  With h = floor(m/2)
+// added first, the centred residue is acc - floor(acc/m) m - h, and
+// floor(acc/m) is exact as the high word of (acc << k) * ceil(2^(32-k)/m):
+// acc < 2^(32-k)/m and (acc << k) < 2^24 hold for w <= 300.
+// ---------------------------------------------------------------------------
+// v_mul_u32_u24 (full rate; the compiler selects the quarter-rate 32-bit
+// multiply for operands it cannot prove to be 24-bit)
+__device__ __forceinline__ uint32_t mul_u24(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+template <int NWX>
+__device__ __forceinline__ uint32_t word_or_fill(const uint32_t (&X)[NWX], int k, uint32_t fill) {
+  uint32_t r = fill;
+#pragma unroll
+  for (int i = 0; i < NWX; ++i) r = k == i ? X[i] : r;
+  return r;
+}
+
+template <int NC, int NWX, int NWM, int PL>
+__global__ __launch_bounds__(256) void k_producer_b(const double *__restrict__ X, int64_t ld,
+                                                    int rowwise, int64_t nout, int64_t K,
+                                                    int64_t KB, const int32_t *__restrict__ exps,
+                                                    const DevPlan *__restrict__ pl,
+                                                    uint8_t *__restrict__ planes,
+                                                    int64_t plane_elems) {
+  const int T = threadIdx.x;
+  const int64_t kb = blockIdx.x, ob = blockIdx.y;
+  const int64_t o = ob * 16 + ((T >> 2) & 15);
+  const int64_t h0 = kb * 64 + 16 * (T >> 6) + 4 * (T & 3);
+  // dword index of this thread's four bytes in every plane (planes hold
+  // fewer than 2^31 elements)
+  const uint32_t offb = (uint32_t)((ob * KB + kb) * 1024 + 4 * T);  // < 2^31
+  const int S = pl->S, w = pl->w, nmod = pl->nmod, Q = pl->Q, nwt = pl->nwt;
+
+  uint32_t Xw[4][NWX];
+  int32_t ex = EXP_ZERO;
+  if (o < nout) ex = exps[o];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t h = h0 + e;
+    const double *src = nullptr;
+    if (ex != EXP_ZERO && h < K) src = rowwise ? X + (o + h * ld) * NC : X + (h + o * ld) * NC;
+    if (src) {
+      to_fixed<NC, NWX>(src, Q - 1 - ex, Xw[e]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < NWX; ++k) Xw[e][k] = 0u;
+    }
+  }
+  uint32_t cin[4] = {0u, 0u, 0u, 0u};
+  for (int t = 0; t < S; ++t) {
+    const bool top = t == S - 1;
+    const int bo = t * w, q = bo >> 5, b = bo & 31;
+    const int wq = w >> 5, wb = w & 31;
+    uint32_t F[4][NWM];
+    uint32_t sel[4];  // 1: add the (-2^W) mod m term (flag or sign)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t fill = (Xw[e][NWX - 1] >> 31) ? 0xffffffffu : 0u;
+      uint32_t prev = word_or_fill<NWX>(Xw[e], q, fill);
+#pragma unroll
+      for (int j = 0; j < NWM; ++j) {
+        const uint32_t nxt = word_or_fill<NWX>(Xw[e], q + j + 1, fill);
+        F[e][j] = __builtin_amdgcn_alignbit(nxt, prev, b);
+        prev = nxt;
+      }
+      if (!top) {
+        // keep the w-bit field
+#pragma unroll
+        for (int j = 0; j < NWM; ++j)
+          F[e][j] = j < wq ? F[e][j] : (j == wq ? F[e][j] & ((1u << wb) - 1u) : 0u);
+      }
+      // add the incoming carry
+      uint32_t c = cin[e];
+#pragma unroll
+      for (int j = 0; j < NWM; ++j) {
+        const uint32_t sum = F[e][j] + c;
+        c = sum < c ? 1u : 0u;
+        F[e][j] = sum;
+      }
+      if (!top) {
+        // carry out of the field (bit w, inside the window since 32 nwt > w)
+        // and the centring flag (bit w-1)
+        uint32_t co = 0, fl = 0;
+        const int fq = (w - 1) >> 5, fb = (w - 1) & 31;
+#pragma unroll
+        for (int j = 0; j < NWM; ++j) {
+          if (j == wq) {
+            co = (F[e][j] >> wb) & 1u;
+            F[e][j] &= ~(1u << wb);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < NWM; ++j)
+          if (j == fq) fl = (F[e][j] >> fb) & 1u;
+        sel[e] = fl;
+        cin[e] = co + fl;
+      } else {
+        uint32_t sg = 0;
+#pragma unroll
+        for (int j = 0; j < NWM; ++j)
+          if (j == nwt - 1) sg = F[e][j] >> 31;
+        sel[e] = sg;
+      }
+    }
+    const int base = top ? REC_HT : REC_HW;
+    uint8_t *pp = planes + (int64_t)t * nmod * (PL == PL_F8 ? 2 : 1) * plane_elems;
+    for (int l = 0; l < nmod; ++l, pp += (PL == PL_F8 ? 2 : 1) * plane_elems) {
+      const uint32_t *R = pl->rec[l];
+      const uint32_t m = R[REC_M], h = R[REC_H], magic = R[REC_MAGIC], ks = R[REC_K];
+      const uint32_t hs = R[base];
+      int32_t c[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        uint32_t acc = sel[e] ? hs : h;
+#pragma unroll
+        for (int j = 0; j < NWM; ++j) acc = __builtin_amdgcn_udot4(F[e][j], R[j], acc, false);
+        const uint32_t qq =
+            (uint32_t)(((uint64_t)((acc << ks) & 0xffffffu) * (uint64_t)(magic & 0xffffffu)) >> 32);
+        c[e] = (int32_t)(acc - mul_u24(qq, m) - h);
+      }
+      if (PL == PL_I8) {
+        const uint32_t word = (uint32_t)(c[0] & 0xff) | ((uint32_t)(c[1] & 0xff) << 8) |
+                              ((uint32_t)(c[2] & 0xff) << 16) | ((uint32_t)c[3] << 24);
+        *(uint32_t *)(pp + offb) = word;
+      } else {
+        // balanced base-17 digits (Eq. fp8digits): d1 = round(c/17) (never a
+        // tie), d0 = c - 17 d1; floor((c+144)/17) as a multiply-high
+        uint32_t w0 = 0, w1 = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int32_t d1 = (int32_t)(((uint32_t)(c[e] + 144) * 3856u) >> 16) - 8;
+          const int32_t d0 = c[e] - 17 * d1;
+          w0 |= (uint32_t)e4m3_small(d0) << (8 * e);
+          w1 |= (uint32_t)e4m3_small(d1) << (8 * e);
+        }
+        *(uint32_t *)(pp + offb) = w0;
+        *(uint32_t *)(pp + plane_elems + offb) = w1;
+      }
+    }
+  }
+}
+
 // Producer: one workgroup fills one 16-row x 64-k window of every plane.
 //   PL_I8 : int8 residues, 1 KiB blocks of 16 rows x 64 k (lane l: row l%16,
 //           k 16(l/16) .. +16);
@@ -791,6 +953,35 @@ static void producer_nh(int nh, dim3 g, hipStream_t s, const double *X, int64_t 
                        K, KB, exps, pl, planes, plane_elems);
 }
 
+template <int NC, int NWX, int PL>
+static void producer_b_nw(int nwt, dim3 g, hipStream_t s, const double *X, int64_t ld,
+                          int rowwise, int64_t nout, int64_t K, int64_t KB, const int32_t *exps,
+                          const DevPlan *pl, void *planes, int64_t plane_elems) {
+  uint8_t *P = (uint8_t *)planes;
+  if (nwt <= 4)
+    hipLaunchKernelGGL((k_producer_b<NC, NWX, 4, PL>), g, dim3(256), 0, s, X, ld, rowwise, nout,
+                       K, KB, exps, pl, P, plane_elems);
+  else if (nwt <= 6)
+    hipLaunchKernelGGL((k_producer_b<NC, NWX, 6, PL>), g, dim3(256), 0, s, X, ld, rowwise, nout,
+                       K, KB, exps, pl, P, plane_elems);
+  else
+    hipLaunchKernelGGL((k_producer_b<NC, NWX, REC_PWMAX, PL>), g, dim3(256), 0, s, X, ld, rowwise,
+                       nout, K, KB, exps, pl, P, plane_elems);
+}
+
+template <int PL>
+static void producer_b(int nc, int nwx, int nwt, dim3 g, hipStream_t s, const double *X,
+                       int64_t ld, int rowwise, int64_t nout, int64_t K, int64_t KB,
+                       const int32_t *exps, const DevPlan *pl, void *planes,
+                       int64_t plane_elems) {
+#define OZ_PRODB(NC_, NWX_) \
+  producer_b_nw<NC_, NWX_, PL>(nwt, g, s, X, ld, rowwise, nout, K, KB, exps, pl, planes, plane_elems)
+  if (nc == 2) { if (nwx <= 8) OZ_PRODB(2, 8); else OZ_PRODB(2, 12); }
+  else if (nc == 3) { if (nwx <= 8) OZ_PRODB(3, 8); else OZ_PRODB(3, 12); }
+  else { if (nwx <= 8) OZ_PRODB(4, 8); else OZ_PRODB(4, 12); }
+#undef OZ_PRODB
+}
+
 template <int PL>
 static void producer_pl(int nc, int nwx, int nh, dim3 g, hipStream_t s, const double *X,
                         int64_t ld, int rowwise, int64_t nout, int64_t K, int64_t KB,
@@ -804,19 +995,21 @@ static void producer_pl(int nc, int nwx, int nh, dim3 g, hipStream_t s, const do
 #undef OZ_PROD
 }
 
-hipError_t launch_producer(int nc, int nwx, int nh, const double *X, int64_t ld, int rowwise,
+hipError_t launch_producer(int nc, int nwx, int nh, int nwt, const double *X, int64_t ld, int rowwise,
                            int64_t nout, int64_t noutp, int64_t K, int64_t Kp,
                            const int32_t *exps, const DevPlan *pl, int backend, void *planes,
                            int64_t plane_elems, hipStream_t s) {
   const int64_t KB = Kp / 64, OB = noutp / 16;
   if (KB <= 0 || OB <= 0) return hipSuccess;
+  // the byte producer addresses a plane with 32-bit offsets
+  if (backend != PLANES_F64 && plane_elems >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
   dim3 g((unsigned)KB, (unsigned)OB);
   if (backend == PLANES_F8)
-    producer_pl<PL_F8>(nc, nwx, nh, g, s, X, ld, rowwise, nout, K, KB, exps, pl, planes, plane_elems);
+    producer_b<PL_F8>(nc, nwx, nwt, g, s, X, ld, rowwise, nout, K, KB, exps, pl, planes, plane_elems);
   else if (backend == PLANES_F64)
     producer_pl<PL_F64>(nc, nwx, nh, g, s, X, ld, rowwise, nout, K, KB, exps, pl, planes, plane_elems);
   else
-    producer_pl<PL_I8>(nc, nwx, nh, g, s, X, ld, rowwise, nout, K, KB, exps, pl, planes, plane_elems);
+    producer_b<PL_I8>(nc, nwx, nwt, g, s, X, ld, rowwise, nout, K, KB, exps, pl, planes, plane_elems);
   return hipGetLastError();
 }
 

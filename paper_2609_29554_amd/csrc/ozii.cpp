@@ -250,6 +250,35 @@ void build_devplan(const HostPlan &hp, DevPlan &dp) {
   }
   for (int k = 0; k < ozk::NDCRT; ++k) dp.Pdig[k] = big_digit16(P, k);
   dp.nd = ozk::NDCRT;
+  // records of the byte back-ends (see DevPlan::rec)
+  dp.nwt = (hp.w + 2 + 31) / 32;
+  if (hp.backend != OZII_BE_F64MOD) {
+    for (int l = 0; l < hp.nmod; ++l) {
+      const uint64_t m = (uint64_t)hp.mods[l];
+      uint32_t *r = dp.rec[l];
+      uint64_t pw = 1 % m;
+      for (int j = 0; j < ozk::REC_PWMAX; ++j) {
+        uint32_t word = 0;
+        for (int i = 0; i < 4; ++i) {
+          if (j < dp.nwt) word |= (uint32_t)pw << (8 * i);
+          pw = (pw << 8) % m;
+        }
+        r[j] = word;
+      }
+      uint64_t p2w = 1 % m, p2t = 1 % m;
+      for (int b = 0; b < hp.w; ++b) p2w = (p2w * 2) % m;
+      for (int b = 0; b < 32 * dp.nwt; ++b) p2t = (p2t * 2) % m;
+      const uint32_t h = (uint32_t)(m / 2);
+      r[ozk::REC_H] = h;
+      r[ozk::REC_HW] = h + (uint32_t)((m - p2w) % m);
+      r[ozk::REC_HT] = h + (uint32_t)((m - p2t) % m);
+      int k = 1;
+      while (((1ull << (32 - k)) + m - 1) / m >= (1ull << 24)) ++k;
+      r[ozk::REC_MAGIC] = (uint32_t)(((1ull << (32 - k)) + m - 1) / m);
+      r[ozk::REC_M] = (uint32_t)m;
+      r[ozk::REC_K] = (uint32_t)k;
+    }
+  }
 }
 
 int64_t roundup(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
@@ -487,10 +516,10 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
   }
   {
     ProfScope ps(h, OZ_STAGE_PRODUCER, (double)(M + N) * K * (8.0 * nc + res_bytes), 0);
-    if ((e = ozl::launch_producer(nc, hp->nwx, hp->nh, A, lda, 1, M, L.Mp, K, L.Kp, ea, dp,
+    if ((e = ozl::launch_producer(nc, hp->nwx, hp->nh, (hp->w + 2 + 31) / 32, A, lda, 1, M, L.Mp, K, L.Kp, ea, dp,
                                   hp->planes_kind(), pa, L.planeA, s)) != hipSuccess)
       return hip_fail(h, e, "producer(A)");
-    if ((e = ozl::launch_producer(nc, hp->nwx, hp->nh, B, ldb, 0, N, L.Np, K, L.Kp, eb, dp,
+    if ((e = ozl::launch_producer(nc, hp->nwx, hp->nh, (hp->w + 2 + 31) / 32, B, ldb, 0, N, L.Np, K, L.Kp, eb, dp,
                                   hp->planes_kind(), pb, L.planeB, s)) != hipSuccess)
       return hip_fail(h, e, "producer(B)");
   }

@@ -29,7 +29,16 @@ struct DevPlan {
   uint16_t Mdig[MAXMOD][NDCRT];   // M_l = P/m_l in 16-bit digits
   uint16_t Pdig[NDCRT];           // P in 16-bit digits
   int32_t nd;                     // digits used for the CRT sums
+  // Byte back-ends (moduli <= 256): one 16-word record per modulus, read by
+  // the producer with scalar loads.  Words 0..9: the bytes 2^(8b) mod m,
+  // four per word (b = 4j .. 4j+3), zero beyond the nwt words of a slice
+  // window; then h = floor(m/2), h + ((-2^w) mod m), h + ((-2^(32 nwt)) mod m),
+  // magic = ceil(2^(32-k) / m) < 2^24, m and the pre-shift k.
+  int32_t nwt;                    // 32-bit words of a slice window: ceil((w+2)/32)
+  uint32_t rec[MAXMOD][16];
 };
+constexpr int REC_H = 10, REC_HW = 11, REC_HT = 12, REC_MAGIC = 13, REC_M = 14, REC_K = 15;
+constexpr int REC_PWMAX = 10;
 
 // Bits [32k, 32k+32) of mag * 2^s (mag < 2^54, s may be negative: the bits
 // below 2^0 are dropped, i.e. the value is truncated toward zero).

@@ -40,7 +40,7 @@ hipError_t launch_exponents(int nc, const double *X, int64_t ld, int64_t rows, i
                             int rowwise, int32_t *e, hipStream_t s);
 // plane encodings of the producer (one per back-end)
 enum { PLANES_I8 = 0, PLANES_F8 = 1, PLANES_F64 = 2 };
-hipError_t launch_producer(int nc, int nwx, int nh, const double *X, int64_t ld, int rowwise,
+hipError_t launch_producer(int nc, int nwx, int nh, int nwt, const double *X, int64_t ld, int rowwise,
                            int64_t nout, int64_t noutp, int64_t K, int64_t Kp,
                            const int32_t *exps, const DevPlan *pl, int planes_kind, void *planes,
                            int64_t plane_elems, hipStream_t s);
