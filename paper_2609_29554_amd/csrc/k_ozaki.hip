@@ -883,6 +883,102 @@ __global__ __launch_bounds__(256) void k_consumer(const TT *__restrict__ tpl, in
   }
 }
 
+// ---------------------------------------------------------------------------
+// (S5)+(S6) consumer of the byte back-ends (t-values < 256).  Per element and
+// digit group the CRT sum sum_l t_l M_l is formed in NB byte columns with
+// v_dot4_u32_u8, four moduli per instruction: the t-bytes of moduli
+// 4c .. 4c+3 packed into one word against the packed bytes of their M_l
+// (table words in scalar registers); each column stays below 2^22.  F =
+// sum_l t_l / m_l comes from the same instruction with f_l = round(2^16 /
+// m_l): its error is below 54 * 255 / 2^17 < 0.11, and F lies within 2^-7 of
+// an integer (the plan keeps |Sbar| < P 2^-7), so round(F) is exact.  Then
+// Sbar = sum_k (col_k - round(F) P_k) 2^(8k) is carried into 16-bit digits
+// and added at bit w gi to the group sum, as in consume_element.
+// ---------------------------------------------------------------------------
+template <int NC, int NWC, int NB>
+__global__ __launch_bounds__(256) void k_consumer_b(const uint8_t *__restrict__ tpl, int64_t Mp,
+                                                    int64_t Np, double *__restrict__ C,
+                                                    int64_t ldc, int64_t M, int64_t N,
+                                                    const int32_t *__restrict__ ea,
+                                                    const int32_t *__restrict__ eb,
+                                                    const DevPlan *__restrict__ pl, int mode) {
+  static_assert(NB % 4 == 0 && NB <= CRT4_NB, "byte columns");
+  constexpr int ND = NB / 2;
+  __shared__ uint32_t stage[256 * CST];
+  uint32_t *st = stage + threadIdx.x * CST;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (i >= M || j >= N) return;
+  const int nmod = pl->nmod, Q = pl->Q, w = pl->w, ng = pl->ng;
+  const int nch = (nmod + 3) >> 2;
+  const int32_t ei = ea[i], ej = eb[j];
+  const bool zero = ei == EXP_ZERO || ej == EXP_ZERO;
+  const int eps = zero ? 0 : w * pl->g0 - (Q - 1 - ei) - (Q - 1 - ej);
+  const int64_t ps = Np * Mp;  // bytes between consecutive moduli
+  uint32_t cb[NWC];
+#pragma unroll
+  for (int k = 0; k < NWC; ++k) cb[k] = 0u;
+  for (int gi = 0; gi < ng; ++gi) {
+    const uint8_t *tp = tpl + ((int64_t)gi * nmod * Np + j) * Mp + i;
+    // moduli past nmod read the last plane again: their table bytes are zero.
+    // The bytes of the next four moduli are loaded one chunk ahead and packed
+    // only when used.
+    uint32_t bt[4];
+    auto load4 = [&](int c) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int l = 4 * c + e < nmod ? 4 * c + e : nmod - 1;
+        bt[e] = tp[(int64_t)l * ps];
+      }
+    };
+    uint32_t col[NB], F0 = 0, F1 = 0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) col[k] = 0u;
+    load4(0);
+    for (int c = 0; c < nch; ++c) {
+      const uint32_t tw = bt[0] | (bt[1] << 8) | (bt[2] << 16) | (bt[3] << 24);
+      if (c + 1 < nch) load4(c + 1);
+      const uint32_t *T = pl->crt4[c];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) col[k] = __builtin_amdgcn_udot4(tw, T[k], col[k], false);
+      F0 = __builtin_amdgcn_udot4(tw, T[CRT4_NB], F0, false);
+      F1 = __builtin_amdgcn_udot4(tw, T[CRT4_NB + 1], F1, false);
+    }
+    const int32_t q = (int32_t)((F0 + (F1 << 8) + 32768u) >> 16);
+    int32_t d[ND];
+    int32_t carry = 0;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+      const int32_t lo = (int32_t)col[2 * k] - q * (pl->pbyte[2 * k] & 0xff);
+      const int32_t hi = (int32_t)col[2 * k + 1] - q * (pl->pbyte[2 * k + 1] & 0xff);
+      const int32_t v = lo + (int32_t)((uint32_t)hi << 8) + carry;
+      d[k] = v & 0xffff;
+      carry = v >> 16;  // arithmetic
+    }
+    // |Sbar| < P/2 fits the ND digits: the top one carries the sign
+    d[ND - 1] = (int32_t)(int16_t)(uint16_t)d[ND - 1];
+    add_shifted_digits<NWC, ND>(cb, d, w * gi, st);
+  }
+  double c[NC];
+  if (zero) {
+#pragma unroll
+    for (int qq = 0; qq < NC; ++qq) c[qq] = 0.0;
+  } else {
+    round_out<NWC, NC>(cb, eps, c);
+  }
+  double *dst = C + (i + j * ldc) * NC;
+  if (mode == 0) {
+    ozx::store<NC>(dst, c);
+  } else {
+    double a[NC], nc_[NC], r[NC];
+    ozx::load<NC>(dst, a);
+#pragma unroll
+    for (int qq = 0; qq < NC; ++qq) nc_[qq] = -c[qq];
+    ozx::add<NC>(a, nc_, r);
+    ozx::store<NC>(dst, r);
+  }
+}
+
 // Debug export of the group sums: Sbar as 64-bit limbs (two's complement),
 // layout [gi][j][i][limb], nlimb limbs.
 template <class TT>
@@ -1073,11 +1169,14 @@ hipError_t launch_consumer(int nc, int nwc, int nd, const void *tpl, int tbytes,
 #define OZ_CONS(NC_, NWC_, ND_, TT_)                                                            \
   hipLaunchKernelGGL((k_consumer<NC_, NWC_, ND_, TT_>), g, dim3(256), 0, s, (const TT_ *)tpl, Mp, \
                      Np, C, ldc, M, N, ea, eb, pl, mode)
+#define OZ_CONSB(NC_, NWC_, NB_)                                                        \
+  hipLaunchKernelGGL((k_consumer_b<NC_, NWC_, NB_>), g, dim3(256), 0, s, (const uint8_t *)tpl, \
+                     Mp, Np, C, ldc, M, N, ea, eb, pl, mode)
 #define OZ_CONS_ND(NC_, NWC_)                                  \
   do {                                                        \
     if (tbytes == 1) {                                        \
-      if (nd <= 18) OZ_CONS(NC_, NWC_, 18, uint8_t);          \
-      else OZ_CONS(NC_, NWC_, 24, uint8_t);                   \
+      if (nd <= 18) OZ_CONSB(NC_, NWC_, 36);                  \
+      else OZ_CONSB(NC_, NWC_, 48);                           \
     } else {                                                  \
       if (nd <= 18) OZ_CONS(NC_, NWC_, 18, uint32_t);         \
       else OZ_CONS(NC_, NWC_, 32, uint32_t);                  \
@@ -1088,6 +1187,7 @@ hipError_t launch_consumer(int nc, int nwc, int nd, const void *tpl, int tbytes,
   else if (nc == 3) { if (nwc <= 12) OZ_CONS_ND(3, 12); else OZ_CONS_ND(3, 16); }
   else { if (nwc <= 12) OZ_CONS_ND(4, 12); else OZ_CONS_ND(4, 16); }
 #undef OZ_CONS_ND
+#undef OZ_CONSB
 #undef OZ_CONS
   return hipGetLastError();
 }

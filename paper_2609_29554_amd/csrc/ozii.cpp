@@ -278,6 +278,21 @@ void build_devplan(const HostPlan &hp, DevPlan &dp) {
       r[ozk::REC_M] = (uint32_t)m;
       r[ozk::REC_K] = (uint32_t)k;
     }
+    for (int l = 0; l < hp.nmod; ++l) {
+      const uint32_t m = (uint32_t)hp.mods[l];
+      Big Ml{1};
+      for (int k = 0; k < hp.nmod; ++k)
+        if (k != l) big_mul_small(Ml, (uint32_t)hp.mods[k]);
+      uint32_t *c4 = dp.crt4[l / 4];
+      const int sh = 8 * (l % 4);
+      for (int b = 0; b < ozk::CRT4_NB; ++b)
+        c4[b] |= ((big_digit16(Ml, b / 2) >> (8 * (b % 2))) & 0xffu) << sh;
+      const uint32_t f = (65536u + m / 2) / m;
+      c4[ozk::CRT4_NB] |= (f & 0xffu) << sh;
+      c4[ozk::CRT4_NB + 1] |= (f >> 8) << sh;
+    }
+    for (int b = 0; b < ozk::CRT4_NB; ++b)
+      dp.pbyte[b] = (int32_t)((big_digit16(P, b / 2) >> (8 * (b % 2))) & 0xffu);
   }
 }
 

@@ -36,7 +36,14 @@ struct DevPlan {
   // magic = ceil(2^(32-k) / m) < 2^24, m and the pre-shift k.
   int32_t nwt;                    // 32-bit words of a slice window: ceil((w+2)/32)
   uint32_t rec[MAXMOD][16];
+  // CRT of the byte back-ends, four moduli per table word: for moduli
+  // 4c .. 4c+3, word k < CRT4_NB packs byte k of each M_l, word CRT4_NB the
+  // low and word CRT4_NB + 1 the high byte of f_l = round(2^16 / m_l)
+  // (zero for moduli beyond nmod).  pbyte: the bytes of P.
+  uint32_t crt4[MAXMOD / 4][50];
+  int32_t pbyte[48];
 };
+constexpr int CRT4_NB = 48, CRT4_W = 50;
 constexpr int REC_H = 10, REC_HW = 11, REC_HT = 12, REC_MAGIC = 13, REC_M = 14, REC_K = 15;
 constexpr int REC_PWMAX = 10;
 
@@ -368,19 +375,43 @@ OZ_HD void produce_element(const double *src, int mu, const DevPlan *pl, uint32_
   }
 }
 
+// cb += Sbar 2^off (mod 2^(32 NWC)), Sbar given as ND two's-complement 16-bit
+// digits (the top one signed); st: CST words of thread-private scratch.
+constexpr int CST = 33;
+
+template <int NWC, int ND>
+OZ_HD void add_shifted_digits(uint32_t (&cb)[NWC], const int32_t (&d)[ND], int off, uint32_t *st) {
+  static_assert(ND % 2 == 0 && ND / 2 + NWC + 1 <= CST, "staging too small");
+  const uint32_t fill = d[ND - 1] < 0 ? 0xffffffffu : 0u;
+#pragma unroll
+  for (int k = 0; k < ND / 2; ++k)
+    st[k] = ((uint32_t)d[2 * k] & 0xffffu) | ((uint32_t)d[2 * k + 1] << 16);
+#pragma unroll
+  for (int k = ND / 2; k < CST; ++k) st[k] = fill;
+  const int q0 = off >> 5, b0 = off & 31;
+  uint32_t carry = 0;
+#pragma unroll
+  for (int k = 0; k < NWC; ++k) {
+    const int s = k - q0;
+    uint32_t cur = s >= 0 ? st[s < CST ? s : CST - 1] : 0u;
+    uint32_t prv = s - 1 >= 0 ? st[s - 1 < CST ? s - 1 : CST - 1] : 0u;
+    uint32_t v = b0 ? ((cur << b0) | (prv >> (32 - b0))) : cur;
+    uint64_t tt = (uint64_t)cb[k] + v + carry;
+    cb[k] = (uint32_t)tt;
+    carry = (uint32_t)(tt >> 32);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Consumer, one element: CRT of every retained digit group, exact sum
 // cbar = sum_gi Sbar_{g0+gi} 2^(w gi), greedy rounding to NC components of
 // cbar 2^eps.  tptr(gi) points at t_0 of group gi; consecutive moduli are
 // pstride bytes apart.  st: CST words of thread-private scratch.
 // ---------------------------------------------------------------------------
-constexpr int CST = 33;
-
 template <int NC, int NWC, int ND, class TT, class TPtr>
 OZ_HD void consume_element(TPtr tptr, int64_t pstride, const DevPlan *pl, uint32_t *st, bool zero,
                            int eps, double (&c)[NC]) {
   static_assert(ND % 2 == 0 && ND <= NDCRT, "digits");
-  static_assert(ND / 2 + NWC + 1 <= CST, "staging too small");
   const int w = pl->w, ng = pl->ng;
   uint32_t cb[NWC];
 #pragma unroll
@@ -388,24 +419,7 @@ OZ_HD void consume_element(TPtr tptr, int64_t pstride, const DevPlan *pl, uint32
   for (int gi = 0; gi < ng; ++gi) {
     int32_t d[ND];
     crt_digits<ND, TT>(tptr(gi), pstride, pl, d);
-    const uint32_t fill = d[ND - 1] < 0 ? 0xffffffffu : 0u;
-#pragma unroll
-    for (int k = 0; k < ND / 2; ++k)
-      st[k] = ((uint32_t)d[2 * k] & 0xffffu) | ((uint32_t)d[2 * k + 1] << 16);
-#pragma unroll
-    for (int k = ND / 2; k < CST; ++k) st[k] = fill;
-    const int off = w * gi, q0 = off >> 5, b0 = off & 31;
-    uint32_t carry = 0;
-#pragma unroll
-    for (int k = 0; k < NWC; ++k) {
-      const int s = k - q0;
-      uint32_t cur = s >= 0 ? st[s < CST ? s : CST - 1] : 0u;
-      uint32_t prv = s - 1 >= 0 ? st[s - 1 < CST ? s - 1 : CST - 1] : 0u;
-      uint32_t v = b0 ? ((cur << b0) | (prv >> (32 - b0))) : cur;
-      uint64_t tt = (uint64_t)cb[k] + v + carry;
-      cb[k] = (uint32_t)tt;
-      carry = (uint32_t)(tt >> 32);
-    }
+    add_shifted_digits<NWC, ND>(cb, d, w * gi, st);
   }
   if (zero) {
 #pragma unroll
