@@ -22,6 +22,16 @@ Recipes (seed = 20260929 + config number unless a test says otherwise):
     uniform in [0.5, 1), random sign, exponent round(N(0, exp_sigma^2)), then
     nc - 1 further components each at most half an ulp of the previous one
     (a canonical expansion), as in the standalone TD product workload.
+
+Limb matrices (p = 64 nlimb bits; value (-1)^sign * mantissa * 2^(exp - p),
+mantissa normalised to [2^(p-1), 2^p); zero = all limbs 0, exp INT32_MIN):
+tuples (limb (nlimb, cols, rows) uint64, exp (cols, rows) int32, sign
+(cols, rows) uint8).
+  * random_limbs(rows, cols, nlimb, rng, exp_sigma, zero_frac): uniformly
+    random normalised mantissas, random signs, exp round(N(0, exp_sigma^2)),
+    a fraction of exact zeros.
+  * lotkin_limbs(n, nlimb): the Lotkin matrix with every entry rounded to
+    nearest (ties to even) at p bits.
 """
 from __future__ import annotations
 
@@ -147,3 +157,58 @@ def batch_systems(count: int, rng: np.random.Generator, n_lo: int = 64, n_hi: in
         A = graded(n, nc, c, rng)
         out.append((nc, A, rhs_ones(A)))
     return out
+
+
+LIMB_EXP_ZERO = -(2 ** 31)
+
+
+def random_limbs(rows: int, cols: int, nlimb: int, rng: np.random.Generator,
+                 exp_sigma: float = 0.0, zero_frac: float = 0.0):
+    limb = rng.integers(0, 2 ** 63, size=(nlimb, cols, rows), dtype=np.uint64) * np.uint64(2) \
+        + rng.integers(0, 2, size=(nlimb, cols, rows), dtype=np.uint64)
+    limb[nlimb - 1] |= np.uint64(1 << 63)
+    e = np.rint(rng.normal(0.0, exp_sigma, size=(cols, rows))).astype(np.int32) if exp_sigma else \
+        np.zeros((cols, rows), dtype=np.int32)
+    sign = rng.integers(0, 2, size=(cols, rows), dtype=np.uint8)
+    if zero_frac > 0:
+        z = rng.random(size=(cols, rows)) < zero_frac
+        limb[:, z] = 0
+        e[z] = LIMB_EXP_ZERO
+        sign[z] = 0
+    return limb, e, sign
+
+
+def _limb_of_fraction(x: Fraction, p: int):
+    """(sign, mantissa, exp) of the p-bit round-to-nearest-even of x > 0."""
+    k = p - (x.numerator.bit_length() - x.denominator.bit_length())
+    while x * Fraction(2) ** k >= 2 ** p:
+        k -= 1
+    while x * Fraction(2) ** k < 2 ** (p - 1):
+        k += 1
+    t = x * Fraction(2) ** k
+    m = t.numerator // t.denominator
+    r = t - m
+    if r > Fraction(1, 2) or (r == Fraction(1, 2) and m % 2 == 1):
+        m += 1
+    if m == 2 ** p:
+        m //= 2
+        k -= 1
+    return 0, m, p - k
+
+
+def lotkin_limbs(n: int, nlimb: int):
+    p = 64 * nlimb
+    limb = np.zeros((nlimb, n, n), dtype=np.uint64)
+    e = np.zeros((n, n), dtype=np.int32)
+    sign = np.zeros((n, n), dtype=np.uint8)
+    cache = {}
+    for j in range(n):
+        for i in range(n):
+            d = 1 if i == 0 else i + j + 1
+            if d not in cache:
+                cache[d] = _limb_of_fraction(Fraction(1, d), p)
+            _, m, ex = cache[d]
+            for q in range(nlimb):
+                limb[q, j, i] = (m >> (64 * q)) & ((1 << 64) - 1)
+            e[j, i] = ex
+    return limb, e, sign
