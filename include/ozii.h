@@ -110,6 +110,41 @@ ozII_status ozII_gemm(ozII_handle h, int32_t mode, int32_t nc, int64_t M, int64_
                       const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
                       int64_t ldc, const ozII_opts *o);
 
+/* Arbitrary-precision limb matrices (the MPFR-like input of Sec. 3.3 and
+ * the p-bit results of (S6)), p = 64 nlimb bits, 1 <= nlimb <= 64:
+ *   x = (-1)^sign * (sum_q limb_q 2^(64 q)) * 2^(exp - p),
+ * mantissa normalised (bit 63 of limb nlimb-1 set, i.e. x = 0.m 2^exp as
+ * mpfr_get_exp reports it); zero has every limb 0 (on input exp and sign are
+ * then ignored; outputs write exp = INT32_MIN, sign = 0).  Non-zero
+ * exponents must lie in [-2^30, 2^30] (MPFR's default range); inputs that
+ * are not normalised give undefined results.  All arrays are device memory
+ * owned by the caller; element (i, j) of an M-row matrix:
+ *   limb q at limb[q * plane + i + j * ld]   (one plane per limb: SoA)
+ *   exp[i + j * ld], sign[i + j * ld] (0 positive, 1 negative),
+ * with ld >= rows and plane >= ld * cols. */
+typedef struct {
+  uint64_t *limb;
+  int32_t *exp;
+  uint8_t *sign;
+  int64_t ld;
+  int64_t plane;
+} ozII_limbs;
+
+/* Ozaki-II product on limb matrices, steps (S1)-(S6) of Sec. 3.1 with the
+ * slices of Sec. 3.2 (the INT8 back-end only):
+ *   mode 0: C = RN_p(A B),   mode 1: C = RN_p(C - RN_p(A B)),
+ * RN_p: round to nearest, ties to even (MPFR's RNDN), applied once to the
+ * exact integer result of (S5) and once to the update.  (S2) truncates:
+ * X = sgn(x) trunc(|x| 2^mu) (mpfr_mul_2si then mpfr_get_z toward zero).
+ * A is M x K, B is K x N, C is M x N; C must not overlap A or B.
+ * Errors: OZII_EINVAL (bad sizes, null pointers, nlimb outside 1..64, ld or
+ * plane too small), OZII_EUNSUPPORTED (a back-end other than INT8, or a plan
+ * beyond the compiled sizes), OZII_ENOMEM.  Uses handle workspace of about
+ * (M + N) K S N_mod + M N (ng N_mod + 4 * words) bytes. */
+ozII_status ozII_gemm_limbs(ozII_handle h, int32_t mode, int32_t nlimb, int64_t M, int64_t N,
+                            int64_t K, const ozII_limbs *A, const ozII_limbs *B, ozII_limbs *C,
+                            const ozII_opts *o);
+
 /* Same product with the intermediate stages copied out (parity hooks); any
  * output pointer may be null.  Sizes follow ozII_gemm_stage_dims:
  *   ea[M], eb[N]     (S1) row / column exponents (INT32_MIN for zero);

@@ -41,10 +41,17 @@ _i64 = C.c_int64
 _i32 = C.c_int32
 
 EXPORTED = ["ozII_create", "ozII_destroy", "ozII_set_stream", "ozII_plan_query", "ozII_reserve",
-            "ozII_gemm", "ozII_gemm_stages", "ozII_gemm_stage_dims", "ozII_getrf", "ozII_getrs",
+            "ozII_gemm", "ozII_gemm_limbs", "ozII_gemm_stages", "ozII_gemm_stage_dims",
+            "ozII_getrf", "ozII_getrs",
             "ozII_batch_prepare", "ozII_batch_run", "ozII_tune", "ozII_stream_of",
             "ozII_sync_check", "ozII_set_profiling",
             "ozII_profile_read", "ozII_status_string", "ozII_last_error"]
+
+class Limbs(C.Structure):
+    """ozII_limbs: limb planes, exponents, signs, ld, plane (device pointers)."""
+    _fields_ = [("limb", C.c_void_p), ("exp", C.c_void_p), ("sign", C.c_void_p),
+                ("ld", C.c_int64), ("plane", C.c_int64)]
+
 
 class BatchItem(C.Structure):
     _fields_ = [("nc", C.c_int32), ("reserved", C.c_int32), ("n", C.c_int64), ("A", C.c_void_p),
@@ -61,7 +68,7 @@ class TuneReport(C.Structure):
                 ("ms", C.c_double * TUNE_MAXCAND), ("model_ms", C.c_double * TUNE_MAXCAND)]
 
 STAGES = ["exponents", "producer", "gemm", "consumer", "panel", "laswp", "trsm", "naive_update",
-          "getrs"]
+          "getrs", "round"]
 
 
 def lib():
@@ -79,6 +86,8 @@ def lib():
                                       C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]
         L.ozII_reserve.argtypes = [_p, _i32, _i64, _i64, _i64, _i64, OP]
         L.ozII_gemm.argtypes = [_p, _i32, _i32, _i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, OP]
+        LP = C.POINTER(Limbs)
+        L.ozII_gemm_limbs.argtypes = [_p, _i32, _i32, _i64, _i64, _i64, LP, LP, LP, OP]
         L.ozII_gemm_stages.argtypes = [_p, _i32, _i32, _i64, _i64, _i64, _p, _i64, _p, _i64, _p,
                                        _i64, OP, _p, _p, _p, _p, _p, _p, _i32]
         L.ozII_gemm_stage_dims.argtypes = [_i32, _i64, _i64, _i64, OP, C.POINTER(_i64),
@@ -185,6 +194,38 @@ class Context:
         self._bind()
         self._call(lib().ozII_gemm(self._h, mode, nc, M, N, K, _ptr(A), max(M, 1), _ptr(B),
                                    max(K, 1), _ptr(Cm), max(M, 1), C.byref(opts) if opts else None))
+        return Cm
+
+    def gemm_limbs(self, mode: int, A, B, Cm, opts: Optional[Opts] = None):
+        """Limb-format product, mode 0: C = RN_p(A B); mode 1: C = RN_p(C - RN_p(A B)).
+        Each matrix is a tuple (limb, exp, sign) of contiguous CUDA tensors of
+        shapes (nlimb, cols, rows) int64 (the uint64 limbs), (cols, rows) int32
+        and (cols, rows) uint8."""
+        import torch
+        nl = A[0].shape[0]
+        for X in (A, B, Cm):
+            lb, ex, sg = X
+            if not (lb.is_cuda and lb.dtype == torch.int64 and lb.is_contiguous() and lb.dim() == 3
+                    and lb.shape[0] == nl):
+                raise ValueError("limbs: contiguous int64 CUDA tensor (nlimb, cols, rows)")
+            if ex.dtype != torch.int32 or sg.dtype != torch.uint8 or \
+                    tuple(ex.shape) != tuple(lb.shape[1:]) or tuple(sg.shape) != tuple(lb.shape[1:]) \
+                    or not (ex.is_contiguous() and sg.is_contiguous()):
+                raise ValueError("exp int32 / sign uint8 of shape (cols, rows)")
+        K, M = A[0].shape[1], A[0].shape[2]
+        N = B[0].shape[1]
+        if B[0].shape[2] != K or Cm[0].shape[1] != N or Cm[0].shape[2] != M:
+            raise ValueError("shape mismatch")
+
+        def desc(X):
+            lb, ex, sg = X
+            rows, cols = lb.shape[2], lb.shape[1]
+            return Limbs(_ptr(lb), _ptr(ex), _ptr(sg), max(rows, 1), max(rows, 1) * cols)
+
+        dA, dB, dC = desc(A), desc(B), desc(Cm)
+        self._bind()
+        self._call(lib().ozII_gemm_limbs(self._h, mode, nl, M, N, K, C.byref(dA), C.byref(dB),
+                                         C.byref(dC), C.byref(opts) if opts else None))
         return Cm
 
     def gemm_stages(self, mode: int, A, B, Cm, opts: Optional[Opts] = None, nlimb: int = 6):

@@ -17,6 +17,7 @@
 
 #include "expansion.hpp"
 #include "ozii_elem.hpp"
+#include "ozii_bytes.hpp"
 #include "ozii_kernels.hpp"
 
 using namespace ozk;
@@ -76,17 +77,6 @@ __global__ __launch_bounds__(256) void k_col_exponents(const double *B, int64_t 
 // Plane encodings of the three back-ends of (S3)/(S4).
 enum { PL_I8 = 0, PL_F8 = 1, PL_F64 = 2 };
 
-// OCP FP8 E4M3 byte of an integer |d| <= 8 (sign, exponent bias 7, 3-bit
-// fraction): d = 2^e (1 + f/8) with e = floor(log2 |d|).
-__device__ __forceinline__ uint8_t e4m3_small(int32_t d) {
-  const uint32_t a = (uint32_t)(d < 0 ? -d : d);
-  const uint32_t sign = d < 0 ? 0x80u : 0u;
-  if (a == 0) return (uint8_t)sign;
-  const uint32_t e = 31u - (uint32_t)__builtin_clz(a);
-  const uint32_t f = ((a << 3) >> e) & 7u;
-  return (uint8_t)(sign | ((e + 7u) << 3) | f);
-}
-
 // ---------------------------------------------------------------------------
 // Producer of the byte back-ends (INT8 residues, FP8 base-17 digits).  One
 // workgroup fills one 1 KiB block (16 rows x 64 k) of every plane; thread T
@@ -108,14 +98,6 @@ __device__ __forceinline__ uint8_t e4m3_small(int32_t d) {
 // floor(acc/m) is exact as the high word of (acc << k) * ceil(2^(32-k)/m):
 // acc < 2^(32-k)/m and (acc << k) < 2^24 hold for w <= 300.
 // ---------------------------------------------------------------------------
-// v_mul_u32_u24 (full rate; the compiler selects the quarter-rate 32-bit
-// multiply for operands it cannot prove to be 24-bit)
-__device__ __forceinline__ uint32_t mul_u24(uint32_t a, uint32_t b) {
-  uint32_t r;
-  asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-  return r;
-}
-
 template <int NWX>
 __device__ __forceinline__ uint32_t word_or_fill(const uint32_t (&X)[NWX], int k, uint32_t fill) {
   uint32_t r = fill;
@@ -211,41 +193,10 @@ __global__ __launch_bounds__(256) void k_producer_b(const double *__restrict__ X
         sel[e] = sg;
       }
     }
-    const int base = top ? REC_HT : REC_HW;
-    uint8_t *pp = planes + (int64_t)t * nmod * (PL == PL_F8 ? 2 : 1) * plane_elems;
-    for (int l = 0; l < nmod; ++l, pp += (PL == PL_F8 ? 2 : 1) * plane_elems) {
-      const uint32_t *R = pl->rec[l];
-      const uint32_t m = R[REC_M], h = R[REC_H], magic = R[REC_MAGIC], ks = R[REC_K];
-      const uint32_t hs = R[base];
-      int32_t c[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        uint32_t acc = sel[e] ? hs : h;
-#pragma unroll
-        for (int j = 0; j < NWM; ++j) acc = __builtin_amdgcn_udot4(F[e][j], R[j], acc, false);
-        const uint32_t qq =
-            (uint32_t)(((uint64_t)((acc << ks) & 0xffffffu) * (uint64_t)(magic & 0xffffffu)) >> 32);
-        c[e] = (int32_t)(acc - mul_u24(qq, m) - h);
-      }
-      if (PL == PL_I8) {
-        const uint32_t word = (uint32_t)(c[0] & 0xff) | ((uint32_t)(c[1] & 0xff) << 8) |
-                              ((uint32_t)(c[2] & 0xff) << 16) | ((uint32_t)c[3] << 24);
-        *(uint32_t *)(pp + offb) = word;
-      } else {
-        // balanced base-17 digits (Eq. fp8digits): d1 = round(c/17) (never a
-        // tie), d0 = c - 17 d1; floor((c+144)/17) as a multiply-high
-        uint32_t w0 = 0, w1 = 0;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int32_t d1 = (int32_t)(((uint32_t)(c[e] + 144) * 3856u) >> 16) - 8;
-          const int32_t d0 = c[e] - 17 * d1;
-          w0 |= (uint32_t)e4m3_small(d0) << (8 * e);
-          w1 |= (uint32_t)e4m3_small(d1) << (8 * e);
-        }
-        *(uint32_t *)(pp + offb) = w0;
-        *(uint32_t *)(pp + plane_elems + offb) = w1;
-      }
-    }
+    const int pstep = PL == PL_F8 ? 2 : 1;
+    emit_byte_residues<NWM, PL == PL_F8>(F, sel, top ? REC_HT : REC_HW, pl, nmod,
+                                         planes + (int64_t)t * nmod * pstep * plane_elems,
+                                         plane_elems, offb);
   }
 }
 
@@ -884,16 +835,9 @@ __global__ __launch_bounds__(256) void k_consumer(const TT *__restrict__ tpl, in
 }
 
 // ---------------------------------------------------------------------------
-// (S5)+(S6) consumer of the byte back-ends (t-values < 256).  Per element and
-// digit group the CRT sum sum_l t_l M_l is formed in NB byte columns with
-// v_dot4_u32_u8, four moduli per instruction: the t-bytes of moduli
-// 4c .. 4c+3 packed into one word against the packed bytes of their M_l
-// (table words in scalar registers); each column stays below 2^22.  F =
-// sum_l t_l / m_l comes from the same instruction with f_l = round(2^16 /
-// m_l): its error is below 54 * 255 / 2^17 < 0.11, and F lies within 2^-7 of
-// an integer (the plan keeps |Sbar| < P 2^-7), so round(F) is exact.  Then
-// Sbar = sum_k (col_k - round(F) P_k) 2^(8k) is carried into 16-bit digits
-// and added at bit w gi to the group sum, as in consume_element.
+// (S5)+(S6) consumer of the byte back-ends (t-values < 256): per element
+// and digit group the CRT of crt_group_bytes, then the group is added at bit
+// w gi to the group sum, which is rounded once as in consume_element.
 // ---------------------------------------------------------------------------
 template <int NC, int NWC, int NB>
 __global__ __launch_bounds__(256) void k_consumer_b(const uint8_t *__restrict__ tpl, int64_t Mp,
@@ -910,7 +854,6 @@ __global__ __launch_bounds__(256) void k_consumer_b(const uint8_t *__restrict__ 
   const int64_t j = blockIdx.y;
   if (i >= M || j >= N) return;
   const int nmod = pl->nmod, Q = pl->Q, w = pl->w, ng = pl->ng;
-  const int nch = (nmod + 3) >> 2;
   const int32_t ei = ea[i], ej = eb[j];
   const bool zero = ei == EXP_ZERO || ej == EXP_ZERO;
   const int eps = zero ? 0 : w * pl->g0 - (Q - 1 - ei) - (Q - 1 - ej);
@@ -920,43 +863,8 @@ __global__ __launch_bounds__(256) void k_consumer_b(const uint8_t *__restrict__ 
   for (int k = 0; k < NWC; ++k) cb[k] = 0u;
   for (int gi = 0; gi < ng; ++gi) {
     const uint8_t *tp = tpl + ((int64_t)gi * nmod * Np + j) * Mp + i;
-    // moduli past nmod read the last plane again: their table bytes are zero.
-    // The bytes of the next four moduli are loaded one chunk ahead and packed
-    // only when used.
-    uint32_t bt[4];
-    auto load4 = [&](int c) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int l = 4 * c + e < nmod ? 4 * c + e : nmod - 1;
-        bt[e] = tp[(int64_t)l * ps];
-      }
-    };
-    uint32_t col[NB], F0 = 0, F1 = 0;
-#pragma unroll
-    for (int k = 0; k < NB; ++k) col[k] = 0u;
-    load4(0);
-    for (int c = 0; c < nch; ++c) {
-      const uint32_t tw = bt[0] | (bt[1] << 8) | (bt[2] << 16) | (bt[3] << 24);
-      if (c + 1 < nch) load4(c + 1);
-      const uint32_t *T = pl->crt4[c];
-#pragma unroll
-      for (int k = 0; k < NB; ++k) col[k] = __builtin_amdgcn_udot4(tw, T[k], col[k], false);
-      F0 = __builtin_amdgcn_udot4(tw, T[CRT4_NB], F0, false);
-      F1 = __builtin_amdgcn_udot4(tw, T[CRT4_NB + 1], F1, false);
-    }
-    const int32_t q = (int32_t)((F0 + (F1 << 8) + 32768u) >> 16);
     int32_t d[ND];
-    int32_t carry = 0;
-#pragma unroll
-    for (int k = 0; k < ND; ++k) {
-      const int32_t lo = (int32_t)col[2 * k] - q * (pl->pbyte[2 * k] & 0xff);
-      const int32_t hi = (int32_t)col[2 * k + 1] - q * (pl->pbyte[2 * k + 1] & 0xff);
-      const int32_t v = lo + (int32_t)((uint32_t)hi << 8) + carry;
-      d[k] = v & 0xffff;
-      carry = v >> 16;  // arithmetic
-    }
-    // |Sbar| < P/2 fits the ND digits: the top one carries the sign
-    d[ND - 1] = (int32_t)(int16_t)(uint16_t)d[ND - 1];
+    crt_group_bytes<NB>(tp, ps, nmod, pl, d);
     add_shifted_digits<NWC, ND>(cb, d, w * gi, st);
   }
   double c[NC];

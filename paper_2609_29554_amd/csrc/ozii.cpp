@@ -30,7 +30,8 @@ enum {
   OZ_STAGE_TRSM = 6,
   OZ_STAGE_NAIVE = 7,
   OZ_STAGE_GETRS = 8,
-  OZ_NSTAGES = 9
+  OZ_STAGE_ROUND = 9,  // limb format: rounding of the group sums and the update
+  OZ_NSTAGES = 10
 };
 
 // ---------------------------------------------------------------------------
@@ -375,17 +376,22 @@ struct ProfScope {
   }
 };
 
+// limbs: plans for the limb format, whose fixed point and group sums live in
+// memory rather than registers; only the slice window (w <= 300) and the
+// byte CRT (at most 24 16-bit digits) bound them.
 ozII_status get_plan(ozII_ctx *h, int p, int64_t K, const ozII_opts *o, const HostPlan **hp,
-                     const DevPlan **dp) {
+                     const DevPlan **dp, bool limbs = false) {
   const int backend = (o && o->backend) ? o->backend : OZII_BE_INT8;
   auto key = std::make_tuple(p, K, backend, o ? o->nslice : 0, o ? o->extra_groups : 0,
-                             o ? o->guard_ex : 0);
+                             (o ? o->guard_ex : 0) * 2 + (limbs ? 1 : 0));
   auto it = h->plans.find(key);
   if (it == h->plans.end()) {
     HostPlan pl;
     std::string why;
-    ozII_status st = make_plan(p, K, o, pl, &why);
+    ozII_status st = make_plan(p, K, o, pl, &why, !limbs);
     if (st != OZII_OK) return fail(h, st, "plan: " + why);
+    if (limbs && (pl.w > 300 || pl.nd > 24))
+      return fail(h, OZII_EUNSUPPORTED, "plan: limb plan exceeds the compiled sizes");
     DevPlan host_dp;
     build_devplan(pl, host_dp);
     DevPlan *d = nullptr;
@@ -575,9 +581,142 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
   return OZII_OK;
 }
 
+// Words of the exact group-sum column kept per element by the limb consumer
+// (the same walk as the kernel's), and the words per shifted group sum.
+void limb_words(const HostPlan &hp, int *nvw, int *nwords) {
+  const int sbits = 2 * hp.w + (int)std::ceil(std::log2((double)hp.K * hp.S)) + 2;
+  *nvw = (sbits + 31) / 32 + 1;
+  int hw = 0;
+  for (int gi = 0; gi < hp.ng; ++gi) {
+    const int q0 = (hp.w * gi) >> 5;
+    if (q0 > hw) hw = q0;
+    hw = std::max(q0 + *nvw, hw + 1);
+  }
+  *nwords = hw + 1;
+}
+
+bool limbs_ok(const ozII_limbs *X, int64_t rows, int64_t cols) {
+  if (!X || !X->limb || !X->exp || !X->sign) return false;
+  if (X->ld < std::max<int64_t>(rows, 1)) return false;
+  return X->plane >= X->ld * cols;
+}
+
+ozII_status gemm_limbs_impl(ozII_ctx *h, int mode, int nlimb, int64_t M, int64_t N, int64_t K,
+                            const ozII_limbs *A, const ozII_limbs *B, ozII_limbs *C,
+                            const ozII_opts *o) {
+  if (!h) return OZII_EINVAL;
+  if (mode != 0 && mode != 1) return fail(h, OZII_EINVAL, "mode must be 0 or 1");
+  if (nlimb < 1 || nlimb > 64) return fail(h, OZII_EINVAL, "nlimb must be 1..64");
+  if (M < 0 || N < 0 || K < 0) return fail(h, OZII_EINVAL, "negative size");
+  if (o && o->backend && o->backend != OZII_BE_INT8)
+    return fail(h, OZII_EUNSUPPORTED, "the limb format runs on the INT8 back-end only");
+  if (M == 0 || N == 0) return OZII_OK;
+  if (!limbs_ok(C, M, N) || (K > 0 && (!limbs_ok(A, M, K) || !limbs_ok(B, K, N))))
+    return fail(h, OZII_EINVAL, "bad limb matrix descriptor");
+  hipStream_t s = h->stream;
+  hipError_t e;
+  if (K == 0) {
+    if (mode == 1) return OZII_OK;
+    e = ozl::launch_limb_zero(C->limb, C->exp, C->sign, C->ld, C->plane, nlimb, M, N, s);
+    return e == hipSuccess ? OZII_OK : hip_fail(h, e, "limb zero");
+  }
+  const int p = 64 * nlimb;
+  const HostPlan *hp;
+  const DevPlan *dp;
+  ozII_status st = get_plan(h, p, K, o, &hp, &dp, true);
+  if (st != OZII_OK) return st;
+  int nvw = 0, nwords = 0;
+  limb_words(*hp, &nvw, &nwords);
+  if (nvw > hp->nd / 2 + 1) return fail(h, OZII_EUNSUPPORTED, "group sum wider than its digits");
+  GemmLayout L = gemm_layout(*hp, M, N, K, o ? o->gemm_tile : 0);
+  // after the planes and t-planes: the group-sum columns (reused as the
+  // update's scratch), then the rounded product of mode 1
+  const int64_t MN = M * N;
+  const size_t cw_words = (size_t)std::max(nwords, 2 * nlimb + 2);
+  const size_t off_cw = (L.total + 255) / 256 * 256;
+  const size_t off_tl = off_cw + (cw_words * MN * 4 + 255) / 256 * 256;
+  const size_t off_te = off_tl + ((size_t)nlimb * MN * 8 + 255) / 256 * 256;
+  const size_t off_ts = off_te + ((size_t)MN * 4 + 255) / 256 * 256;
+  const size_t total = off_ts + ((size_t)MN + 255) / 256 * 256;
+  st = ensure_ws(h, mode ? total : off_tl);
+  if (st != OZII_OK) return st;
+  int32_t *ea = (int32_t *)(h->ws + L.off_ea);
+  int32_t *eb = (int32_t *)(h->ws + L.off_eb);
+  uint8_t *pa = (uint8_t *)(h->ws + L.off_pa);
+  uint8_t *pb = (uint8_t *)(h->ws + L.off_pb);
+  uint8_t *tpl = (uint8_t *)(h->ws + L.off_tpl);
+  uint32_t *cw = (uint32_t *)(h->ws + off_cw);
+  const int nwt = (hp->w + 2 + 31) / 32;
+  const double pairs = (double)hp->nmod * [&] {
+    int np = 0;
+    for (int g = hp->g0; g <= 2 * hp->S - 2; ++g)
+      for (int ta = 0; ta < hp->S; ++ta)
+        if (g - ta >= 0 && g - ta < hp->S) ++np;
+    return np;
+  }();
+  const double in_bytes = 8.0 * nlimb + 5.0;  // limbs, exponent and sign per element
+  const double res_bytes = (double)hp->S * hp->nmod, t_bytes = (double)hp->ng * hp->nmod;
+  {
+    ProfScope ps(h, OZ_STAGE_EXP, 12.0 * (double)(M * K + K * N), 0);
+    if ((e = ozl::launch_limb_exponents(A->limb, A->exp, A->ld, A->plane, nlimb, M, K, 1, ea, s)) != hipSuccess)
+      return hip_fail(h, e, "limb exponents(A)");
+    if ((e = ozl::launch_limb_exponents(B->limb, B->exp, B->ld, B->plane, nlimb, K, N, 0, eb, s)) != hipSuccess)
+      return hip_fail(h, e, "limb exponents(B)");
+  }
+  {
+    ProfScope ps(h, OZ_STAGE_PRODUCER, (double)(M + N) * K * (in_bytes + res_bytes), 0);
+    if ((e = ozl::launch_producer_limbs(A->limb, A->exp, A->sign, A->ld, A->plane, nlimb, 1, M,
+                                        L.Mp, K, L.Kp, ea, dp, nwt, pa, L.planeA, s)) != hipSuccess)
+      return hip_fail(h, e, "limb producer(A)");
+    if ((e = ozl::launch_producer_limbs(B->limb, B->exp, B->sign, B->ld, B->plane, nlimb, 0, N,
+                                        L.Np, K, L.Kp, eb, dp, nwt, pb, L.planeB, s)) != hipSuccess)
+      return hip_fail(h, e, "limb producer(B)");
+  }
+  {
+    ProfScope ps(h, OZ_STAGE_GEMM, res_bytes * (double)(M + N) * K + t_bytes * M * N,
+                 2.0 * (double)M * N * K * pairs);
+    if ((e = ozl::launch_gemm_i8((const int8_t *)pa, (const int8_t *)pb, tpl, dp, hp->ng, hp->nmod,
+                                 L.Mp, L.Np, L.Kp, L.planeA, L.planeB, o ? o->gemm_tile : 0, s)) != hipSuccess)
+      return hip_fail(h, e, "modular gemm");
+  }
+  {
+    // t-planes read once, each group's window of the sum read and written
+    ProfScope ps(h, OZ_STAGE_CONSUMER,
+                 (double)M * N * (t_bytes + 8.0 * nvw * hp->ng), 0);
+    if ((e = ozl::launch_consumer_limbs(tpl, L.Mp, L.Np, M, N, dp, hp->nd, nvw, cw, s)) != hipSuccess)
+      return hip_fail(h, e, "limb consumer");
+  }
+  {
+    ProfScope ps(h, OZ_STAGE_ROUND,
+                 (double)M * N * (4.0 * nwords + in_bytes * (mode ? 4 : 1)), 0);
+    if (mode == 0) {
+      if ((e = ozl::launch_limb_round(cw, nwords, M, N, ea, eb, hp->w, hp->g0, hp->Q, nlimb, C->limb,
+                                      C->exp, C->sign, C->ld, C->plane, s)) != hipSuccess)
+        return hip_fail(h, e, "limb round");
+    } else {
+      uint64_t *tl = (uint64_t *)(h->ws + off_tl);
+      int32_t *te = (int32_t *)(h->ws + off_te);
+      uint8_t *ts = (uint8_t *)(h->ws + off_ts);
+      if ((e = ozl::launch_limb_round(cw, nwords, M, N, ea, eb, hp->w, hp->g0, hp->Q, nlimb, tl, te,
+                                      ts, M, MN, s)) != hipSuccess)
+        return hip_fail(h, e, "limb round");
+      if ((e = ozl::launch_limb_sub(C->limb, C->exp, C->sign, C->ld, C->plane, tl, te, ts, nlimb, M,
+                                    N, cw, s)) != hipSuccess)
+        return hip_fail(h, e, "limb update");
+    }
+  }
+  return OZII_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+ozII_status ozII_gemm_limbs(ozII_handle h, int32_t mode, int32_t nlimb, int64_t M, int64_t N,
+                            int64_t K, const ozII_limbs *A, const ozII_limbs *B, ozII_limbs *C,
+                            const ozII_opts *o) {
+  return gemm_limbs_impl(h, mode, nlimb, M, N, K, A, B, C, o);
+}
 
 ozII_status ozII_create(ozII_handle *out, int device, void *stream) {
   if (!out) return OZII_EINVAL;

@@ -28,7 +28,7 @@ def test_exports_match_header():
 
 
 @pytest.mark.parametrize("p,K", [(106, 32), (212, 128), (212, 256), (159, 512), (1024, 1024),
-                                 (8192, 512), (212, 256)])
+                                 (8192, 512), (212, 256), (4096, 256), (256, 64)])
 def test_plan_matches_oracle(p, K):
     Z = _lib()
     import oracle as O
