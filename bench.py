@@ -77,20 +77,29 @@ def op_counts(n, b):
 
 
 PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
-KERNEL_FAMILY = {"producer": "k_producer", "consumer": "k_consumer"}
+# kernels behind each profiled stage (one stage launch = one kernel dispatch
+# for these stages)
+STAGE_KERNELS = {"producer": ("k_producer_b", "k_producer", "k_producer_limbs"),
+                 "gemm": ("k_gemm_i8_p", "k_gemm_i8", "k_gemm_f8", "k_gemm_f64"),
+                 "consumer": ("k_consumer_b", "k_consumer", "k_consumer_limbs"),
+                 "round": ("k_limb_round", "k_limb_sub")}
 
 
-def traffic_of(stage, profile_md, gemm_family="k_gemm_i8_p"):
-    """HBM bytes per launch of a stage's kernel from a committed rocprofv3
-    counter summary, or None when there is none or the kernel source has
-    changed since it was measured."""
+def traffic_of(stage, profile_md):
+    """HBM bytes per launch of a stage's kernels from a committed rocprofv3
+    counter summary (dispatch-weighted over the stage's kernels), or None
+    when there is none or the kernel sources changed since it was taken."""
     from paper_2609_29554_amd import pmc
     s = pmc.load(os.path.join(PROFILES, profile_md))
     if not s or s.get("kernel_source_sha256") != pmc.source_sha():
         return None
-    fam = gemm_family if stage == "gemm" else KERNEL_FAMILY.get(stage)
-    rec = s["kernels"].get(fam)
-    return rec.get("hbm_bytes_per_launch") if rec else None
+    tot, n = 0.0, 0
+    for fam in STAGE_KERNELS.get(stage, ()):
+        rec = s["kernels"].get(fam)
+        if rec and rec.get("hbm_bytes_per_launch") is not None:
+            tot += rec["hbm_bytes_per_launch"] * rec["dispatches"]
+            n += rec["dispatches"]
+    return tot / n if n else None
 
 
 def cpu_baseline(n_target, nc, b, n_sample):
@@ -133,10 +142,14 @@ def main():
     ap.add_argument("--no-native", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=2048)
-    ap.add_argument("--workload", choices=["lu", "gemm", "schur", "batch"], default="lu",
+    ap.add_argument("--workload", choices=["lu", "gemm", "schur", "batch", "limb-schur"],
+                    default="lu",
                     help="lu: QD Lotkin LU (default); gemm: standalone TD product m=n=k=4096; "
                          "schur: only the LU's Ozaki-II Schur-update products (for profiling); "
-                         "batch: 256 DD/QD systems n in [64, 512] in one persistent launch")
+                         "batch: 256 DD/QD systems n in [64, 512] in one persistent launch; "
+                         "limb-schur: the Schur-update products of the Lotkin LU n=2048, "
+                         "b=256 at p=4096 (64-limb numbers)")
+    ap.add_argument("--nlimb", type=int, default=64)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--gemm-n", type=int, default=4096)
     ap.add_argument("--gemm-backend", choices=["int8", "fp8", "f64"], default="int8")
@@ -175,6 +188,8 @@ def main():
         return bench_schur(args)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "limb-schur":
+        return bench_limb_schur(args)
 
     n, nc, b = args.n, args.nc, args.block
     log(f"generating Lotkin n={n} nc={nc}")
@@ -237,8 +252,8 @@ def main():
         if not launches or ms <= 0:
             return None
         per_launch_ms = ms / launches
-        traffic = (traffic_of(name, "pmc_traffic_lu_qd2048_lotkin.md")
-                   if update_name == "int8" and b == 256 else None)
+        traffic = (traffic_of(name, f"pmc_traffic_lu_qd{n}_lotkin_b{b}.md")
+                   if update_name == "int8" else None)
         if bound == "mfma":
             peak = PEAK_MFMA[update_name]
             achieved = ops / launches / (per_launch_ms * 1e-3) / 1e12
@@ -537,10 +552,9 @@ def bench_gemm(args):
     K = args.steps
     ms, launches, by, ops = prof["gemm"]
     ach = ops / launches / (ms / launches * 1e-3) / 1e12
-    fam = {"int8": "k_gemm_i8_p", "fp8": "k_gemm_f8", "f64": "k_gemm_f64"}[args.gemm_backend]
     prof_md = f"pmc_traffic_gemm_td{n}_{args.gemm_backend}.md"
     roof = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TOP/s",
-            "frac": ach / peak, "traffic": traffic_of("gemm", prof_md, fam), "kernel": "gemm",
+            "frac": ach / peak, "traffic": traffic_of("gemm", prof_md), "kernel": "gemm",
             "avg_launch_ms": ms / launches, "algorithmic_bytes_per_launch": by / launches}
     rooflines = {"gemm": roof}
     for k in ("producer", "consumer"):
@@ -559,6 +573,134 @@ def bench_gemm(args):
         "effective_gflops_td": 2.0 * n ** 3 / sec / 1e9,
         "stages": {k: {"ms_per_step": v[0] / K} for k, v in prof.items() if v[1]},
     }
+    print(json.dumps(out))
+
+
+def limb_cpu_baseline(nl, shapes, sample_mn=16):
+    """The limb oracle on one update of sample_mn x sample_mn x b, timed per
+    phase and scaled to the workload: residues by (M+N)K, modular products
+    by MNK, CRT and rounding by MN."""
+    import numpy as np
+
+    import oracle as O
+    import oracle.limbs as OL
+    import workloads as W
+
+    K = shapes[0][1]
+    rng = np.random.default_rng(20260933)
+    A = W.random_limbs(sample_mn, K, nl, rng, exp_sigma=2.0)
+    B = W.random_limbs(K, sample_mn, nl, rng, exp_sigma=2.0)
+    Cz = W.random_limbs(sample_mn, sample_mn, nl, rng, exp_sigma=2.0)
+    pl = O.make_plan(64 * nl, K)
+    t0 = time.perf_counter()
+    ea, eb = OL.exponents(A, True), OL.exponents(B, False)
+    pa = OL.residues(A, True, ea, pl)
+    pb = OL.residues(B, False, eb, pl)
+    t1 = time.perf_counter()
+    tpl = O.modgemm(pa, pb, pl)
+    t2 = time.perf_counter()
+    OL.ozgemm(1, A, B, Cz, pl)   # the whole product again: CRT and rounding are its remainder
+    t3 = time.perf_counter()
+    t_rest = max((t3 - t2) - (t2 - t0), 0.0)
+    s_mn = float(sample_mn * sample_mn)
+    res = sum(2.0 * m * kb for m, kb in shapes) / (2.0 * sample_mn * K)
+    mnk = sum(float(m) * m * kb for m, kb in shapes) / (s_mn * K)
+    mn = sum(float(m) * m for m, _ in shapes) / s_mn
+    est = (t1 - t0) * res + (t2 - t1) * mnk + t_rest * mn
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": est, "unit": "s", "cores": min(threads, os.cpu_count() or threads),
+            "kind": "oracle",
+            "sample": (f"limb oracle on one {sample_mn}x{sample_mn}x{K} update at p={64 * nl} "
+                       f"(residues {t1 - t0:.1f} s, modular products {t2 - t1:.1f} s, CRT and "
+                       f"rounding {t_rest:.1f} s), scaled to the seven updates by (M+N)K "
+                       f"({res:.0f}x), MNK ({mnk:.0f}x) and MN ({mn:.0f}x)")}
+
+
+def bench_limb_schur(args):
+    """The Ozaki-II Schur updates of a blocked LU of the Lotkin matrix at
+    p = 64 nlimb bits (n, b): for every step, C = RN_p(C - RN_p(A B)) with
+    A = A[k+b:, k:k+b], B = A[k:k+b, k+b:], C = A[k+b:, k+b:] of the Lotkin
+    matrix, updated in place through sub-block descriptors (no copies)."""
+    import ctypes
+    import numpy as np
+    import torch
+
+    import paper_2609_29554_amd as Z
+    import workloads as W
+
+    n, b, nl = args.n, args.block, args.nlimb
+    log(f"generating Lotkin limbs n={n} p={64 * nl}")
+    limb, ex, sg = W.lotkin_limbs(n, nl)
+    dl = torch.from_numpy(limb.view(np.int64)).cuda()
+    de = torch.from_numpy(ex).cuda()
+    ds = torch.from_numpy(sg).cuda()
+    del limb, ex, sg
+    ctx = Z.Context(0)
+    shapes = schur_shapes(n, b)
+
+    def desc(r0, c0):
+        off = r0 + c0 * n
+        return Z.Limbs(dl.data_ptr() + 8 * off, de.data_ptr() + 4 * off, ds.data_ptr() + off,
+                       n, n * n)
+
+    work = []
+    for k in range(0, n - b, b):
+        m = n - k - b
+        work.append((m, b, desc(k + b, k), desc(k, k + b), desc(k + b, k + b)))
+
+    def step():
+        for m, kb, A, B, Cd in work:
+            ctx._call(Z.lib().ozII_gemm_limbs(ctx._h, 1, nl, m, m, kb, ctypes.byref(A),
+                                              ctypes.byref(B), ctypes.byref(Cd), None))
+
+    ctx._bind()
+    for _ in range(max(args.warmup, 1)):
+        step()
+    ctx.sync_check()
+    ctx.set_profiling(True)
+    ctx.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.set_profiling(False)
+    ctx.sync_check()
+    sec = (t1 - t0) / args.steps
+    S, w, Q, nmod, _ = Z.plan_query(64 * nl, b)
+    ms, launches, by, ops = prof["gemm"]
+    ach = ops / launches / (ms / launches * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_MFMA["int8"], "unit": "TOP/s",
+            "frac": ach / PEAK_MFMA["int8"],
+            "traffic": traffic_of("gemm", f"pmc_traffic_limb_schur_p{64 * nl}.md"),
+            "kernel": "gemm", "avg_launch_ms": ms / launches, "launches": launches / args.steps,
+            "algorithmic_ops_per_launch": ops / launches}
+    rooflines = {"gemm": roof}
+    for k in ("producer", "consumer", "round"):
+        m2, l2, b2, _ = prof[k]
+        if not l2:
+            continue
+        a2 = b2 / l2 / (m2 / l2 * 1e-3) / 1e9
+        rooflines[k] = {"bound": "hbm", "achieved": a2, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": a2 / PEAK_HBM_GBS,
+                        "traffic": traffic_of(k, f"pmc_traffic_limb_schur_p{64 * nl}.md"),
+                        "kernel": k,
+                        "avg_launch_ms": m2 / l2, "algorithmic_bytes_per_launch": b2 / l2}
+    out = {"metric": METRIC, "value": sec, "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u64 limbs+i8", "data": "synthetic",
+           "config": {"workload": f"Ozaki-II Schur updates of the Lotkin LU n={n} b={b} at "
+                                  f"p={64 * nl} (limb format)", "S": S, "w": w, "nmod": nmod,
+                      "shapes": shapes},
+           "roofline": roof, "rooflines": rooflines,
+           "stages": {k: {"ms_per_step": v[0] / args.steps,
+                          "launches_per_step": v[1] / args.steps}
+                      for k, v in prof.items() if v[1]}}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (limb oracle sample)")
+        out["cpu_baseline"] = limb_cpu_baseline(nl, shapes)
     print(json.dumps(out))
 
 

@@ -536,10 +536,13 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
     if ((e = ozl::launch_exponents(nc, B, ldb, K, N, 0, eb, s)) != hipSuccess) return hip_fail(h, e, "exponents(B)");
   }
   {
-    ProfScope ps(h, OZ_STAGE_PRODUCER, (double)(M + N) * K * (8.0 * nc + res_bytes), 0);
+    ProfScope ps(h, OZ_STAGE_PRODUCER, (double)M * K * (8.0 * nc + res_bytes), 0);
     if ((e = ozl::launch_producer(nc, hp->nwx, hp->nh, (hp->w + 2 + 31) / 32, A, lda, 1, M, L.Mp, K, L.Kp, ea, dp,
                                   hp->planes_kind(), pa, L.planeA, s)) != hipSuccess)
       return hip_fail(h, e, "producer(A)");
+  }
+  {
+    ProfScope ps(h, OZ_STAGE_PRODUCER, (double)N * K * (8.0 * nc + res_bytes), 0);
     if ((e = ozl::launch_producer(nc, hp->nwx, hp->nh, (hp->w + 2 + 31) / 32, B, ldb, 0, N, L.Np, K, L.Kp, eb, dp,
                                   hp->planes_kind(), pb, L.planeB, s)) != hipSuccess)
       return hip_fail(h, e, "producer(B)");
@@ -664,10 +667,13 @@ ozII_status gemm_limbs_impl(ozII_ctx *h, int mode, int nlimb, int64_t M, int64_t
       return hip_fail(h, e, "limb exponents(B)");
   }
   {
-    ProfScope ps(h, OZ_STAGE_PRODUCER, (double)(M + N) * K * (in_bytes + res_bytes), 0);
+    ProfScope ps(h, OZ_STAGE_PRODUCER, (double)M * K * (in_bytes + res_bytes), 0);
     if ((e = ozl::launch_producer_limbs(A->limb, A->exp, A->sign, A->ld, A->plane, nlimb, 1, M,
                                         L.Mp, K, L.Kp, ea, dp, nwt, pa, L.planeA, s)) != hipSuccess)
       return hip_fail(h, e, "limb producer(A)");
+  }
+  {
+    ProfScope ps(h, OZ_STAGE_PRODUCER, (double)N * K * (in_bytes + res_bytes), 0);
     if ((e = ozl::launch_producer_limbs(B->limb, B->exp, B->sign, B->ld, B->plane, nlimb, 0, N,
                                         L.Np, K, L.Kp, eb, dp, nwt, pb, L.planeB, s)) != hipSuccess)
       return hip_fail(h, e, "limb producer(B)");
@@ -686,20 +692,26 @@ ozII_status gemm_limbs_impl(ozII_ctx *h, int mode, int nlimb, int64_t M, int64_t
     if ((e = ozl::launch_consumer_limbs(tpl, L.Mp, L.Np, M, N, dp, hp->nd, nvw, cw, s)) != hipSuccess)
       return hip_fail(h, e, "limb consumer");
   }
-  {
-    ProfScope ps(h, OZ_STAGE_ROUND,
-                 (double)M * N * (4.0 * nwords + in_bytes * (mode ? 4 : 1)), 0);
-    if (mode == 0) {
-      if ((e = ozl::launch_limb_round(cw, nwords, M, N, ea, eb, hp->w, hp->g0, hp->Q, nlimb, C->limb,
-                                      C->exp, C->sign, C->ld, C->plane, s)) != hipSuccess)
+  // rounding: the group-sum column read, the p-bit product written (to C, or
+  // to the temporary product of mode 1); update: C and the product read, the
+  // difference written and read back, C written
+  if (mode == 0) {
+    ProfScope ps(h, OZ_STAGE_ROUND, (double)M * N * (4.0 * nwords + in_bytes), 0);
+    if ((e = ozl::launch_limb_round(cw, nwords, M, N, ea, eb, hp->w, hp->g0, hp->Q, nlimb, C->limb,
+                                    C->exp, C->sign, C->ld, C->plane, s)) != hipSuccess)
+      return hip_fail(h, e, "limb round");
+  } else {
+    uint64_t *tl = (uint64_t *)(h->ws + off_tl);
+    int32_t *te = (int32_t *)(h->ws + off_te);
+    uint8_t *ts = (uint8_t *)(h->ws + off_ts);
+    {
+      ProfScope ps(h, OZ_STAGE_ROUND, (double)M * N * (4.0 * nwords + in_bytes), 0);
+      if ((e = ozl::launch_limb_round(cw, nwords, M, N, ea, eb, hp->w, hp->g0, hp->Q, nlimb, tl,
+                                      te, ts, M, MN, s)) != hipSuccess)
         return hip_fail(h, e, "limb round");
-    } else {
-      uint64_t *tl = (uint64_t *)(h->ws + off_tl);
-      int32_t *te = (int32_t *)(h->ws + off_te);
-      uint8_t *ts = (uint8_t *)(h->ws + off_ts);
-      if ((e = ozl::launch_limb_round(cw, nwords, M, N, ea, eb, hp->w, hp->g0, hp->Q, nlimb, tl, te,
-                                      ts, M, MN, s)) != hipSuccess)
-        return hip_fail(h, e, "limb round");
+    }
+    {
+      ProfScope ps(h, OZ_STAGE_ROUND, (double)M * N * (3.0 * in_bytes + 8.0 * (2 * nlimb + 2)), 0);
       if ((e = ozl::launch_limb_sub(C->limb, C->exp, C->sign, C->ld, C->plane, tl, te, ts, nlimb, M,
                                     N, cw, s)) != hipSuccess)
         return hip_fail(h, e, "limb update");

@@ -10,6 +10,9 @@ the kernel sources it was measured on.  bench.py uses the figures only while
 that source is unchanged.
 
     python -m paper_2609_29554_amd.pmc FETCH.csv WRITE.csv COPY_MIB OUT.md "command"
+
+It also writes the kernel-time summaries of ``rocprofv3 --kernel-trace
+--stats`` runs (``python -m paper_2609_29554_amd.pmc trace ...``).
 """
 from __future__ import annotations
 
@@ -17,6 +20,8 @@ import csv
 import hashlib
 import json
 import os
+import re
+import sqlite3
 import sys
 from collections import defaultdict
 
@@ -24,8 +29,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # the device code of the Ozaki-II kernels (a change to the host-side plane
 # padding in ozii.cpp also calls for new counter runs)
 KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in
-                  ("k_ozaki.hip", "ozii_elem.hpp", "expansion.hpp")]
-FAMILIES = ("k_producer", "k_gemm_i8_p", "k_gemm_i8", "k_gemm_f8", "k_gemm_f64", "k_consumer")
+                  ("k_ozaki.hip", "k_limbs.hip", "ozii_elem.hpp", "ozii_bytes.hpp",
+                   "expansion.hpp")]
+_KNAME = re.compile(r"(?:^|::|\s)(k_[A-Za-z0-9_]+)\s*(<[^()]*>)?\s*\(")
 
 
 def source_sha() -> str:
@@ -37,10 +43,17 @@ def source_sha() -> str:
 
 
 def _family(name: str):
-    for fam in FAMILIES:  # longer names first where one is a prefix of another
-        if fam + "<" in name or fam + "(" in name:
-            return fam
-    return None
+    """Base name of one of this library's kernels (k_...), else None."""
+    m = _KNAME.search(name)
+    return m.group(1) if m else None
+
+
+def short_name(name: str) -> str:
+    """Kernel name without namespace and argument list, template arguments kept."""
+    m = _KNAME.search(name)
+    if m:
+        return m.group(1) + (m.group(2) or "")
+    return name.split("(")[0].strip()
 
 
 def _read(path: str, counter: str):
@@ -96,6 +109,45 @@ def write_md(summary, path: str, command: str, title: str):
         f.write("\n".join(lines))
 
 
+def kernel_stats(path: str):
+    """Per kernel: (calls, total ms, average us) from a rocprofv3 run, either
+    its ``*_kernel_stats.csv`` (``--stats --output-format csv``) or its
+    ``*_results.db`` (the default output of ``--kernel-trace``)."""
+    rows = []
+    if path.endswith(".csv"):
+        for r in csv.DictReader(open(path)):
+            rows.append((r["Name"], int(r["Calls"]), float(r["TotalDurationNs"]) / 1e6,
+                         float(r["AverageNs"]) / 1e3))
+    else:
+        con = sqlite3.connect(path)
+        q = ("select s.display_name, count(*), sum(k.duration), avg(k.duration) from kernels k "
+             "join kernel_symbols s on k.kernel_id = s.kernel_id group by s.kernel_id")
+        for name, calls, tot, avg in con.execute(q):
+            rows.append((name, int(calls), tot / 1e6, avg / 1e3))
+    merged = defaultdict(lambda: [0, 0.0])
+    for name, calls, tot, _ in rows:
+        k = short_name(name)
+        merged[k][0] += calls
+        merged[k][1] += tot
+    out = [(k, c, t, t * 1e3 / c) for k, (c, t) in merged.items()]
+    out.sort(key=lambda r: -r[2])
+    return out
+
+
+def write_trace_md(stats, path: str, command: str, title: str, notes: str = ""):
+    total = sum(r[2] for r in stats) or 1.0
+    lines = [f"# {title}", "", "Command (run from /tmp on the MI355X box, repository at $R):",
+             "```", command, "```", ""]
+    if notes:
+        lines += [notes, ""]
+    lines += ["| kernel | calls | total ms | avg us | % |", "|---|---:|---:|---:|---:|"]
+    for k, c, t, a in stats:
+        lines.append(f"| `{k}` | {c} | {t:.3f} | {a:.1f} | {100.0 * t / total:.2f} |")
+    lines.append("")
+    with open(path, "w") as f:
+        f.write("\n".join(lines))
+
+
 def load(path: str):
     """The summary stored in a profiles/*.md file, or None."""
     if not os.path.exists(path):
@@ -109,6 +161,14 @@ def load(path: str):
 
 
 if __name__ == "__main__":
+    if sys.argv[1] == "trace":
+        # python -m paper_2609_29554_amd.pmc trace STATS OUT.md "command" "title" ["notes"]
+        st = kernel_stats(sys.argv[2])
+        write_trace_md(st, sys.argv[3], sys.argv[4], sys.argv[5],
+                       sys.argv[6] if len(sys.argv) > 6 else "")
+        for r in st[:12]:
+            print(r)
+        sys.exit(0)
     fetch_csv, write_csv, mib, out_md, cmd = sys.argv[1:6]
     title = sys.argv[6] if len(sys.argv) > 6 else "HBM traffic per kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE)"
     s = summarize(fetch_csv, write_csv, float(mib))

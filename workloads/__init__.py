@@ -198,17 +198,18 @@ def _limb_of_fraction(x: Fraction, p: int):
 
 def lotkin_limbs(n: int, nlimb: int):
     p = 64 * nlimb
-    limb = np.zeros((nlimb, n, n), dtype=np.uint64)
-    e = np.zeros((n, n), dtype=np.int32)
+    # one rounded reciprocal per denominator 1 .. 2n-1, then gathered
+    table = np.zeros((nlimb, 2 * n), dtype=np.uint64)
+    texp = np.zeros(2 * n, dtype=np.int32)
+    for d in range(1, 2 * n):
+        _, m, ex = _limb_of_fraction(Fraction(1, d), p)
+        for q in range(nlimb):
+            table[q, d] = (m >> (64 * q)) & ((1 << 64) - 1)
+        texp[d] = ex
+    ii = np.arange(n)[None, :]
+    jj = np.arange(n)[:, None]
+    dd = np.where(ii == 0, 1, ii + jj + 1)          # (cols, rows)
+    limb = table[:, dd]
+    e = texp[dd]
     sign = np.zeros((n, n), dtype=np.uint8)
-    cache = {}
-    for j in range(n):
-        for i in range(n):
-            d = 1 if i == 0 else i + j + 1
-            if d not in cache:
-                cache[d] = _limb_of_fraction(Fraction(1, d), p)
-            _, m, ex = cache[d]
-            for q in range(nlimb):
-                limb[q, j, i] = (m >> (64 * q)) & ((1 << 64) - 1)
-            e[j, i] = ex
     return limb, e, sign
