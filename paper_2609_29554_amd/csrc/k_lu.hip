@@ -100,7 +100,7 @@ __device__ __forceinline__ bool cand_better(const double (&kb_)[NC], int pb, int
   return pb < pa;
 }
 
-constexpr int PANEL_NT = 256;  // threads per panel workgroup
+constexpr int PANEL_NT = 512;  // threads per panel workgroup
 
 // ---------------------------------------------------------------------------
 // (P1) panel.  Panel rows [k, n), columns [k, k+kb).  Workgroup w owns the
@@ -224,16 +224,25 @@ __global__ __launch_bounds__(PANEL_NT) void k_panel(double *A, int64_t lda, int6
     // reduce it identically in every workgroup: four entries per lane of the
     // first wavefront, then a butterfly
     if (tid < G) {
+      // every device-coherent load first, then the LDS stores: the compiler
+      // keeps atomic loads in program order, so a store between two of them
+      // would make each load wait for the previous one's round trip
       const uint32_t *ln = LINE(buf, tid);
+      const double *kv = (const double *)(ln + CAND_KEY);
       const int ph = (int)ld_dev_u32(ln + 2);
-      tpos[tid] = (int)ld_dev_u32(ln + 1);
+      const int pos = (int)ld_dev_u32(ln + 1);
+      double kk[NC], kn[NC];
+#pragma unroll
+      for (int q = 0; q < NC; ++q) kk[q] = ld_dev_f64(kv + q);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) kn[q] = ld_dev_f64(kv + NC + q);
+      tpos[tid] = pos;
       tphys[tid] = ph;
       tidx[tid] = ph >= 0 ? tid : -1;
-      const double *kv = (const double *)(ln + CAND_KEY);
 #pragma unroll
       for (int q = 0; q < NC; ++q) {
-        tkey[tid][q] = ld_dev_f64(kv + q);
-        tnxt[tid][q] = ld_dev_f64(kv + NC + q);
+        tkey[tid][q] = kk[q];
+        tnxt[tid][q] = kn[q];
       }
     }
     __syncthreads();
@@ -321,10 +330,25 @@ __global__ __launch_bounds__(PANEL_NT) void k_panel(double *A, int64_t lda, int6
         }
       }
     } else {
-      // the other wavefronts: columns j+2 .. kb-1 of the pivot row
-      const double *cr = CROW(buf, wi);
-      for (int idx = tid - 64; idx < (kb - j - 2) * NC; idx += PANEL_NT - 64)
-        piv[(size_t)(j + 2) * NC + idx] = ld_dev_f64(cr + (size_t)(j + 2) * NC + idx);
+      // the other wavefronts: columns j+2 .. kb-1 of the pivot row, PF
+      // loads in flight per thread before their LDS stores (see above)
+      constexpr int PF = 8;
+      const double *cr = CROW(buf, wi) + (size_t)(j + 2) * NC;
+      double *pd = piv + (size_t)(j + 2) * NC;
+      const int total = (kb - j - 2) * NC;
+      for (int b0 = tid - 64; b0 < total; b0 += (PANEL_NT - 64) * PF) {
+        double v[PF];
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+          const int idx = b0 + u * (PANEL_NT - 64);
+          v[u] = idx < total ? ld_dev_f64(cr + idx) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+          const int idx = b0 + u * (PANEL_NT - 64);
+          if (idx < total) pd[idx] = v[u];
+        }
+      }
     }
     __syncthreads();
     if (last) break;

@@ -872,20 +872,34 @@ ozII_status ozII_getrf(ozII_handle h, int32_t nc, int64_t n, double *A, int64_t 
   for (int64_t k = 0; k < n; k += b) {
     const int kb = (int)std::min<int64_t>(b, n - k);
     const int64_t nr = n - k;
-    // panel geometry: G co-resident workgroups of R rows each
-    int G = 256, R = 0, maxb = 0;
-    for (;;) {
-      R = (int)((nr + G - 1) / G);
-      if (R > 32) return fail(h, OZII_EUNSUPPORTED, "panel too tall for the resident kernel");
-      if (ozl::panel_lds_bytes(nc, kb, R, nr) + 16384 > 160 * 1024) {
-        return fail(h, OZII_EUNSUPPORTED, "panel does not fit in LDS");
+    // panel geometry: G co-resident workgroups of R rows each.  Fewer,
+    // taller workgroups make the per-column exchange cheaper (every
+    // workgroup reads every candidate line), so 128 are tried first and 256
+    // when 128 would not hold the rows in LDS (static LDS of the kernel:
+    // about 20 KiB).
+    int G = 0, R = 0;
+    for (int G0 : {128, 256}) {
+      int g = G0, r = 0, maxb = 0;
+      bool ok = false;
+      for (;;) {
+        r = (int)((nr + g - 1) / g);
+        if (r > 32 || ozl::panel_lds_bytes(nc, kb, r, nr) + 20480 > 160 * 1024) break;
+        e = ozl::panel_max_blocks(nc, kb, r, nr, &maxb);
+        if (e != hipSuccess) return hip_fail(h, e, "panel occupancy");
+        if (maxb >= g) {
+          ok = true;
+          break;
+        }
+        g = maxb;
+        if (g <= 0) break;
       }
-      e = ozl::panel_max_blocks(nc, kb, R, nr, &maxb);
-      if (e != hipSuccess) return hip_fail(h, e, "panel occupancy");
-      if (maxb >= G) break;
-      G = maxb;
-      if (G <= 0) return fail(h, OZII_EUNSUPPORTED, "panel kernel cannot be resident");
+      if (ok) {
+        G = g;
+        R = r;
+        break;
+      }
     }
+    if (G <= 0) return fail(h, OZII_EUNSUPPORTED, "panel does not fit in LDS for a resident kernel");
     G = (int)std::min<int64_t>(G, (nr + R - 1) / R);
     if ((e = ozl::launch_fill_int((int *)h->flags, 0, 2 * 32 * 256, s)) != hipSuccess) return hip_fail(h, e, "fill lines");
     // a panel that stops early leaves no moved rows behind for laswp
