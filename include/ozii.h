@@ -61,7 +61,7 @@ typedef enum {
 } ozII_method;
 
 typedef enum {
-  OZII_TILE_AUTO = 0,    /* chosen from the product shape                     */
+  OZII_TILE_AUTO = 0,    /* 256x128 when it gives 2 workgroups per CU, else 128x128 */
   OZII_TILE_128x128 = 1, /* 4 wavefronts of 64x64, operands straight from L2  */
   OZII_TILE_256x128 = 2, /* 4 wavefronts of 128x64, operands staged in LDS    */
   OZII_TILE_256x256 = 3  /* 8 wavefronts of 128x64, operands staged in LDS    */

@@ -1052,12 +1052,12 @@ hipError_t launch_gemm_i8(const int8_t *pa, const int8_t *pb, uint8_t *tpl, cons
   const int64_t KB = Kp / 64;
   if (tile == GEMM_TILE_256x256) {
     const int tilesM = (int)(Mp / 256), tilesN = (int)(Np / 256);
-    hipLaunchKernelGGL((k_gemm_i8_p<2, 4, 4>), dim3((unsigned)(prods * tilesM * tilesN)),
+    hipLaunchKernelGGL((k_gemm_i8_p<2, 4, 3>), dim3((unsigned)(prods * tilesM * tilesN)),
                        dim3(512), 0, s, pa, pb, tpl, pl, Mp, Np, KB, planeA, planeB, tilesM,
                        tilesN);
   } else if (tile == GEMM_TILE_256x128) {
     const int tilesM = (int)(Mp / 256), tilesN = (int)(Np / 128);
-    hipLaunchKernelGGL((k_gemm_i8_p<2, 2, 5>), dim3((unsigned)(prods * tilesM * tilesN)),
+    hipLaunchKernelGGL((k_gemm_i8_p<2, 2, 3>), dim3((unsigned)(prods * tilesM * tilesN)),
                        dim3(256), 0, s, pa, pb, tpl, pl, Mp, Np, KB, planeA, planeB, tilesM,
                        tilesN);
   } else {

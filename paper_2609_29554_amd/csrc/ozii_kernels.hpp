@@ -25,11 +25,12 @@ inline bool gemm_tile_fits(int tile, int64_t Mp, int64_t Np) {
   }
 }
 
-// Largest tile that fits the padded shape and still gives every CU two
-// workgroups (prods = batched (group, modulus) products).
+// The 256x128 tile (three 24 KiB stages: two workgroups per CU overlap each
+// other's barriers) when it still gives every CU two workgroups (prods =
+// batched (group, modulus) products), else 128x128.  Measured on MI355X it
+// beats the 256x256 tile (one workgroup per CU) on both the TD 4096^3
+// product and the p = 4096 limb updates; 256x256 stays selectable.
 inline int gemm_tile_auto(int64_t prods, int64_t Mp, int64_t Np) {
-  if (gemm_tile_fits(GEMM_TILE_256x256, Mp, Np) && prods * (Mp / 256) * (Np / 256) >= 512)
-    return GEMM_TILE_256x256;
   if (gemm_tile_fits(GEMM_TILE_256x128, Mp, Np) && prods * (Mp / 256) * (Np / 128) >= 512)
     return GEMM_TILE_256x128;
   return GEMM_TILE_128x128;
