@@ -303,6 +303,7 @@ def main():
         native = {**nat, "best_s": best, "speedup_vs_native": best / sec}
 
     sweep = backend_sweep(ctx, args) if args.sweep_n > 0 else None
+    td_gemm = td_gemm_probe(args.gemm_n) if args.gemm_n > 0 else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -334,12 +335,51 @@ def main():
         "schur_update_ms": schur_ms,
         "gemm_gops": gops,
         "gemm_frac_peak": (gops / 1e3 / PEAK_MFMA.get(update_name, PEAK_INT8_TOPS)) if gops else None,
+        "gemm_td": td_gemm,
         "stages": stages,
         "info": info_v,
         "correct_bits": bits,
         "backend_sweep": sweep,
     }
     print(json.dumps(out))
+
+
+def td_gemm_probe(n, steps=3):
+    """The GEMM half of the headline metric on its own configuration: the
+    standalone triple-double Ozaki-II product m = n = k = n (INT8), modular
+    GEMM GOPS and fraction of the INT8 MFMA peak, timed with the library's
+    HIP events (same recipe as --workload gemm)."""
+    import numpy as np
+    import torch
+
+    import paper_2609_29554_amd as Z
+    import workloads as W
+
+    nc = 3
+    rng = np.random.default_rng(20260932)
+    dA = torch.from_numpy(W.random_expansions(n, n, nc, rng, exp_sigma=4.0)).cuda()
+    dB = torch.from_numpy(W.random_expansions(n, n, nc, rng, exp_sigma=4.0)).cuda()
+    dC = torch.zeros_like(dA)
+    ctx = Z.Context(0)
+    opts = Z.make_opts(backend=Z.BE_INT8)
+    ctx.gemm(0, dA, dB, dC, opts)
+    ctx.sync_check()
+    ctx.set_profiling(True)
+    ctx.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.gemm(0, dA, dB, dC, opts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.set_profiling(False)
+    ms, launches, _, ops = prof["gemm"]
+    gops = ops / (ms * 1e-3) / 1e9
+    ctx.close()
+    return {"workload": f"Ozaki-II product C=AB, triple-double, m=n=k={n}, INT8",
+            "product_ms": (t1 - t0) / steps * 1e3, "gemm_ms": ms / launches,
+            "gemm_gops": gops, "gemm_frac_int8_peak": gops / 1e3 / PEAK_INT8_TOPS}
 
 
 def backend_sweep(ctx, args):

@@ -507,6 +507,45 @@ __global__ __launch_bounds__(256) void k_trsm_lower_unit(const double *Lp, int64
   }
 }
 
+// U12 solve for kb <= ROWS: thread t owns row t % ROWS of column t / ROWS
+// of the workgroup's 256 / ROWS columns, so every lane holds an element
+// (one thread per row of two columns would leave half of them idle at
+// kb = 128).  Each element receives its multiply-subtracts in the order of
+// k_trsm_lower_unit.
+template <int NC, int ROWS>
+__global__ __launch_bounds__(256) void k_trsm_lower_unit_rc(const double *Lp, int64_t lda,
+                                                            double *Xp, int64_t ldx, int kb,
+                                                            int64_t ncols) {
+  constexpr int CPB = 256 / ROWS;
+  __shared__ double xs[2][CPB][NC];
+  const int tid = threadIdx.x, i = tid % ROWS, cc = tid / ROWS;
+  const int64_t c = (int64_t)blockIdx.x * CPB + cc;
+  const bool mine = i < kb && c < ncols;
+  double x[NC];
+  if (mine) ozx::load<NC>(Xp + (i + c * ldx) * NC, x);
+  else
+#pragma unroll
+    for (int q = 0; q < NC; ++q) x[q] = 0.0;
+  for (int h = 0; h < kb; ++h) {
+    const int b = h & 1;
+    if (i == h) {
+#pragma unroll
+      for (int q = 0; q < NC; ++q) xs[b][cc][q] = x[q];
+    }
+    __syncthreads();
+    if (mine && i > h) {
+      double l[NC], u[NC], o[NC];
+      ozx::load<NC>(Lp + (i + (int64_t)h * lda) * NC, l);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) u[q] = xs[b][cc][q];
+      ozx::fms<NC>(x, l, u, o);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) x[q] = o[q];
+    }
+  }
+  if (mine) ozx::store<NC>(Xp + (i + c * ldx) * NC, x);
+}
+
 // rinv[k] = 1 / u_kk (expansion division), one thread per diagonal entry.
 template <int NC>
 __global__ __launch_bounds__(256) void k_recip_diag(const double *LU, int64_t lda, int64_t n,
@@ -883,8 +922,17 @@ hipError_t launch_laswp(int nc, double *A, int64_t lda, int64_t k, int64_t c0, i
 template <int NC>
 static void trsm_l(int kb, dim3 g, hipStream_t s, const double *L, int64_t lda, double *X,
                    int64_t ldx, int64_t ncols) {
-  if (kb <= 256) hipLaunchKernelGGL((k_trsm_lower_unit<NC, 2, 1>), g, dim3(256), 0, s, L, lda, X, ldx, kb, ncols);
-  else hipLaunchKernelGGL((k_trsm_lower_unit<NC, 1, 2>), g, dim3(256), 0, s, L, lda, X, ldx, kb, ncols);
+  if (kb <= 64)
+    hipLaunchKernelGGL((k_trsm_lower_unit_rc<NC, 64>), dim3((unsigned)((ncols + 3) / 4)), dim3(256),
+                       0, s, L, lda, X, ldx, kb, ncols);
+  else if (kb <= 128)
+    hipLaunchKernelGGL((k_trsm_lower_unit_rc<NC, 128>), dim3((unsigned)((ncols + 1) / 2)),
+                       dim3(256), 0, s, L, lda, X, ldx, kb, ncols);
+  else if (kb <= 256)
+    hipLaunchKernelGGL((k_trsm_lower_unit_rc<NC, 256>), dim3((unsigned)ncols), dim3(256), 0, s, L,
+                       lda, X, ldx, kb, ncols);
+  else
+    hipLaunchKernelGGL((k_trsm_lower_unit<NC, 1, 2>), g, dim3(256), 0, s, L, lda, X, ldx, kb, ncols);
 }
 
 hipError_t launch_trsm_lower_unit(int nc, const double *L, int64_t lda, double *X, int64_t ldx,
