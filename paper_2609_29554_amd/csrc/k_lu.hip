@@ -310,24 +310,55 @@ __global__ __launch_bounds__(PANEL_NT) void k_panel(double *A, int64_t lda, int6
     __syncthreads();
     const bool last = j + 1 >= kb;
     if (tid < 64) {
-      // wavefront 0: l = a / pivot for the active rows, then column j+1
-      if (!zero) {
-        for (int r = tid; r < cnt; r += 64) {
-          if ((active >> r) & 1u) {
-            double a[NC], d[NC], l[NC];
-            ozx::load<NC>(RW(r, j), a);
-            ozx::load<NC>(piv + (size_t)j * NC, d);
-            ozx::div<NC>(a, d, l);
-            ozx::store<NC>(RW(r, j), l);
-            if (!last) {
-              double x[NC], u[NC], o[NC];
-              ozx::load<NC>(RW(r, j + 1), x);
-              ozx::load<NC>(piv + (size_t)(j + 1) * NC, u);
-              ozx::fms<NC>(x, l, u, o);
-              ozx::store<NC>(RW(r, j + 1), o);
-            }
+      // wavefront 0: l = a / pivot for the active rows (one per lane, R <=
+      // 32), then column j+1, whose values stay in the lanes: the local
+      // candidate for column j+1 is their butterfly maximum in the pivot
+      // order (the order of pick(), which any reduction tree respects)
+      double ck[NC];
+      int cpos = 0x7fffffff, cidx = -1;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) ck[q] = 0.0;
+      const int r = tid;
+      if (r < cnt && ((active >> r) & 1u)) {
+        double x[NC];
+        if (!last) ozx::load<NC>(RW(r, j + 1), x);
+        if (!zero) {
+          double a[NC], d[NC], l[NC];
+          ozx::load<NC>(RW(r, j), a);
+          ozx::load<NC>(piv + (size_t)j * NC, d);
+          ozx::div<NC>(a, d, l);
+          ozx::store<NC>(RW(r, j), l);
+          if (!last) {
+            double u[NC], o[NC];
+            ozx::load<NC>(piv + (size_t)(j + 1) * NC, u);
+            ozx::fms<NC>(x, l, u, o);
+            ozx::store<NC>(RW(r, j + 1), o);
+#pragma unroll
+            for (int q = 0; q < NC; ++q) x[q] = o[q];
           }
         }
+        if (!last) {
+#pragma unroll
+          for (int q = 0; q < NC; ++q) ck[q] = x[q];
+          cpos = sinv[r0 + r];
+          cidx = r;
+        }
+      }
+      if (!last) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          double ok[NC];
+#pragma unroll
+          for (int q = 0; q < NC; ++q) ok[q] = __shfl_xor(ck[q], off, 64);
+          const int op = __shfl_xor(cpos, off, 64), oi = __shfl_xor(cidx, off, 64);
+          if (cand_better<NC>(ok, op, oi, ck, cpos, cidx)) {
+#pragma unroll
+            for (int q = 0; q < NC; ++q) ck[q] = ok[q];
+            cpos = op;
+            cidx = oi;
+          }
+        }
+        if (tid == 0) s_best = cidx;
       }
     } else {
       // the other wavefronts: columns j+2 .. kb-1 of the pivot row, PF
@@ -352,8 +383,8 @@ __global__ __launch_bounds__(PANEL_NT) void k_panel(double *A, int64_t lda, int6
     }
     __syncthreads();
     if (last) break;
-    // candidate for column j+1: finish its row first, publish, arrive
-    pick(j + 1);
+    // candidate for column j+1 (s_best, from wavefront 0): finish its row
+    // first, publish, arrive
     const int best = s_best;
     const int width = kb - j - 2;
     if (!zero && best >= 0) {
