@@ -276,13 +276,31 @@ __global__ __launch_bounds__(PANEL_NT) void k_panel(double *A, int64_t lda, int6
         }
       }
       if (tid == 0) {
-        s_wi = bi;
-        s_ppos = bp;
-        s_pphys = bi >= 0 ? tphys[bi] : -1;
+        // the winner, and (for a consistent table) the bookkeeping of the
+        // interchange, before the single barrier below
+        const int wi0 = bi, pp0 = bp, ph0 = bi >= 0 ? tphys[bi] : -1;
         bool z = true;
 #pragma unroll
         for (int q = 0; q < NC; ++q) z = z && (bk[q] == 0.0);
+        s_wi = wi0;
+        s_ppos = pp0;
+        s_pphys = ph0;
         s_zero = z ? 1 : 0;
+        if (!(wi0 < 0 || pp0 < j || pp0 >= nr || ph0 < 0 || ph0 >= nr)) {
+#pragma unroll
+          for (int q = 0; q < NC; ++q) {
+            piv[(size_t)j * NC + q] = tkey[wi0][q];
+            if (j + 1 < kb) piv[(size_t)(j + 1) * NC + q] = tnxt[wi0][q];
+          }
+          const int q = sperm[j];
+          sperm[j] = ph0;
+          sperm[pp0] = q;
+          sinv[ph0] = j;
+          sinv[q] = pp0;
+          if (ph0 >= r0 && ph0 < r0 + cnt) active &= ~(1u << (ph0 - r0));
+          if (z && s_info == 0) s_info = (int)(k + j + 1);
+          if (wg == 0) ipiv[k + j] = k + pp0;
+        }
       }
     }
     __syncthreads();
@@ -292,22 +310,6 @@ __global__ __launch_bounds__(PANEL_NT) void k_panel(double *A, int64_t lda, int6
       if (tid == 0) __hip_atomic_store(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
-    if (tid == 0) {
-#pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        piv[(size_t)j * NC + q] = tkey[wi][q];
-        if (j + 1 < kb) piv[(size_t)(j + 1) * NC + q] = tnxt[wi][q];
-      }
-      const int q = sperm[j];
-      sperm[j] = pphys;
-      sperm[ppos] = q;
-      sinv[pphys] = j;
-      sinv[q] = ppos;
-      if (pphys >= r0 && pphys < r0 + cnt) active &= ~(1u << (pphys - r0));
-      if (zero && s_info == 0) s_info = (int)(k + j + 1);
-      if (wg == 0) ipiv[k + j] = k + ppos;
-    }
-    __syncthreads();
     const bool last = j + 1 >= kb;
     if (tid < 64) {
       // wavefront 0: l = a / pivot for the active rows (one per lane, R <=
