@@ -43,7 +43,8 @@ _i32 = C.c_int32
 EXPORTED = ["ozII_create", "ozII_destroy", "ozII_set_stream", "ozII_plan_query", "ozII_reserve",
             "ozII_gemm", "ozII_gemm_limbs", "ozII_gemm_stages", "ozII_gemm_stage_dims",
             "ozII_getrf", "ozII_getrs",
-            "ozII_batch_prepare", "ozII_batch_run", "ozII_tune", "ozII_stream_of",
+            "ozII_batch_prepare", "ozII_batch_prepare_ex", "ozII_batch_run", "ozII_tune",
+            "ozII_stream_of",
             "ozII_sync_check", "ozII_set_profiling",
             "ozII_profile_read", "ozII_status_string", "ozII_last_error"]
 
@@ -97,6 +98,7 @@ def lib():
         L.ozII_getrs.argtypes = [_p, _i32, _i64, _i64, _p, _i64, _p, _p, _i64]
         L.ozII_tune.argtypes = [_p, _i32, _i64, C.c_char_p, _i32, OP, C.POINTER(TuneReport)]
         L.ozII_batch_prepare.argtypes = [_p, _i32, C.POINTER(BatchItem)]
+        L.ozII_batch_prepare_ex.argtypes = [_p, _i32, C.POINTER(BatchItem), OP]
         L.ozII_batch_run.argtypes = [_p, _p]
         L.ozII_stream_of.argtypes = [_p, C.POINTER(_p)]
         L.ozII_sync_check.argtypes = [_p]
@@ -295,10 +297,13 @@ class Context:
                                     _ptr(B), max(n, 1)))
         return B
 
-    def batch_prepare(self, systems):
+    def batch_prepare(self, systems, opts: Optional[Opts] = None):
         """Upload a batch: systems = [(A, b or None, ipiv, info), ...] of CUDA
         tensors, A (n, n, nc) float64, b (1, n, nc) float64, ipiv int64[n],
-        info int32[1]; the tensors must stay alive while the batch is used."""
+        info int32[1]; the tensors must stay alive while the batch is used.
+        opts None: unblocked LU with the native update; opts with method
+        Ozaki-II: blocked LU (opts.block, default 32, at most 64) with the
+        Ozaki-II update on the INT8 back-end."""
         arr = (BatchItem * max(len(systems), 1))()
         for i, (A, b, ipiv, info) in enumerate(systems):
             _check_mat(A)
@@ -308,7 +313,10 @@ class Context:
                                _ptr(ipiv), _ptr(info))
         self._batch_refs = list(systems)
         self._bind()
-        self._call(lib().ozII_batch_prepare(self._h, len(systems), arr))
+        if opts is None:
+            self._call(lib().ozII_batch_prepare(self._h, len(systems), arr))
+        else:
+            self._call(lib().ozII_batch_prepare_ex(self._h, len(systems), arr, C.byref(opts)))
 
     def batch_run(self, times=None):
         """Factor and solve the prepared batch (graph-capturable); times: CUDA

@@ -14,10 +14,17 @@
 
 #include "../../include/ozii.h"
 #include "expansion.hpp"
+#include "ozii_elem.hpp"
+#include "ozii_stage.hpp"
+
+using namespace ozk;
+
+typedef int v4i __attribute__((ext_vector_type(4)));
 
 namespace {
 
 constexpr int BT = 1024;  // threads per workgroup (4 wavefronts per SIMD)
+constexpr int BTZ = 512;  // the same for the Ozaki-II update
 
 // largest |value| first, then the lower row index (a total order)
 template <int NC>
@@ -30,6 +37,87 @@ __device__ __forceinline__ bool piv_better(const double (&kb_)[NC], int64_t ib,
   return ib < ia;
 }
 
+// Column j of the LU: pivot search over rows j..n-1 (largest magnitude, then
+// the lower row index), ipiv and info, the whole-row interchange and the
+// division of the column below the pivot (nothing to divide after a zero
+// pivot: the column below it is zero).  Ends with the workgroup in step and
+// returns whether the pivot was exactly zero (the same in every thread).
+template <int NC, int NT>
+__device__ bool pivot_column(const ozII_batch_item &it, int64_t j, double (*rkey)[4],
+                             int64_t *ridx, int *s_info) {
+  const int tid = threadIdx.x;
+  const int64_t n = it.n;
+  double *A = it.A;
+  auto E = [&](int64_t i, int64_t c) { return A + (i + c * n) * NC; };
+  double bk[NC];
+  int64_t bi = -1;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) bk[q] = 0.0;
+  for (int64_t i = j + tid; i < n; i += NT) {
+    double x[NC];
+    ozx::load<NC>(E(i, j), x);
+    if (piv_better<NC>(x, i, bk, bi)) {
+#pragma unroll
+      for (int q = 0; q < NC; ++q) bk[q] = x[q];
+      bi = i;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NC; ++q) rkey[tid][q] = bk[q];
+  ridx[tid] = bi;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      double ka[NC], kv[NC];
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        ka[q] = rkey[tid][q];
+        kv[q] = rkey[tid + s][q];
+      }
+      if (piv_better<NC>(kv, ridx[tid + s], ka, ridx[tid])) {
+#pragma unroll
+        for (int q = 0; q < NC; ++q) rkey[tid][q] = kv[q];
+        ridx[tid] = ridx[tid + s];
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t p = ridx[0];
+  bool zero = true;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) zero = zero && (rkey[0][q] == 0.0);
+  __syncthreads();
+  if (tid == 0) {
+    it.ipiv[j] = p;
+    if (zero && *s_info == 0) *s_info = (int)(j + 1);
+  }
+  if (!zero) {
+    if (p != j) {  // whole-row interchange
+      for (int64_t c = tid; c < n; c += NT) {
+        double u[NC], v[NC];
+        ozx::load<NC>(E(j, c), u);
+        ozx::load<NC>(E(p, c), v);
+        ozx::store<NC>(E(j, c), v);
+        ozx::store<NC>(E(p, c), u);
+      }
+      __syncthreads();
+    }
+    double d[NC];
+    ozx::load<NC>(E(j, j), d);
+    for (int64_t i = j + 1 + tid; i < n; i += NT) {
+      double a[NC], l[NC];
+      ozx::load<NC>(E(i, j), a);
+      ozx::div<NC>(a, d, l);
+      ozx::store<NC>(E(i, j), l);
+    }
+    __syncthreads();
+  }
+  return zero;
+}
+
+template <int NC, int NT>
+__device__ void solve_one(const ozII_batch_item &it);
+
 template <int NC>
 __device__ void lu_solve_one(const ozII_batch_item &it, double (*rkey)[4], int64_t *ridx,
                              int *s_info) {
@@ -40,70 +128,7 @@ __device__ void lu_solve_one(const ozII_batch_item &it, double (*rkey)[4], int64
   if (tid == 0) *s_info = 0;
   __syncthreads();
   for (int64_t j = 0; j < n; ++j) {
-    // pivot search in column j, rows j..n-1
-    double bk[NC];
-    int64_t bi = -1;
-#pragma unroll
-    for (int q = 0; q < NC; ++q) bk[q] = 0.0;
-    for (int64_t i = j + tid; i < n; i += BT) {
-      double x[NC];
-      ozx::load<NC>(E(i, j), x);
-      if (piv_better<NC>(x, i, bk, bi)) {
-#pragma unroll
-        for (int q = 0; q < NC; ++q) bk[q] = x[q];
-        bi = i;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < NC; ++q) rkey[tid][q] = bk[q];
-    ridx[tid] = bi;
-    __syncthreads();
-    for (int s = BT / 2; s > 0; s >>= 1) {
-      if (tid < s) {
-        double ka[NC], kv[NC];
-#pragma unroll
-        for (int q = 0; q < NC; ++q) {
-          ka[q] = rkey[tid][q];
-          kv[q] = rkey[tid + s][q];
-        }
-        if (piv_better<NC>(kv, ridx[tid + s], ka, ridx[tid])) {
-#pragma unroll
-          for (int q = 0; q < NC; ++q) rkey[tid][q] = kv[q];
-          ridx[tid] = ridx[tid + s];
-        }
-      }
-      __syncthreads();
-    }
-    const int64_t p = ridx[0];
-    bool zero = true;
-#pragma unroll
-    for (int q = 0; q < NC; ++q) zero = zero && (rkey[0][q] == 0.0);
-    __syncthreads();
-    if (tid == 0) {
-      it.ipiv[j] = p;
-      if (zero && *s_info == 0) *s_info = (int)(j + 1);
-    }
-    if (!zero) {
-      if (p != j) {  // whole-row interchange
-        for (int64_t c = tid; c < n; c += BT) {
-          double u[NC], v[NC];
-          ozx::load<NC>(E(j, c), u);
-          ozx::load<NC>(E(p, c), v);
-          ozx::store<NC>(E(j, c), v);
-          ozx::store<NC>(E(p, c), u);
-        }
-        __syncthreads();
-      }
-      double d[NC];
-      ozx::load<NC>(E(j, j), d);
-      for (int64_t i = j + 1 + tid; i < n; i += BT) {
-        double a[NC], l[NC];
-        ozx::load<NC>(E(i, j), a);
-        ozx::div<NC>(a, d, l);
-        ozx::store<NC>(E(i, j), l);
-      }
-      __syncthreads();
-    }
+    pivot_column<NC, BT>(it, j, rkey, ridx, s_info);
     // rank-1 update of the trailing matrix (also after a zero pivot, with the
     // unscaled -- all-zero -- column, as the blocked LU with b = 1 does)
     const int64_t m = n - j - 1;
@@ -119,9 +144,19 @@ __device__ void lu_solve_one(const ozII_batch_item &it, double (*rkey)[4], int64
     __syncthreads();
   }
   if (tid == 0) *it.info = *s_info;
+  solve_one<NC, BT>(it);
+}
+
+// The solve with the factors: interchanges in ipiv order, forward (unit L,
+// ascending), backward with the reciprocals 1 / u_kk (descending), as
+// ozII_getrs does for one right-hand side.
+template <int NC, int NT>
+__device__ void solve_one(const ozII_batch_item &it) {
   if (!it.b) return;
-  // solve: interchanges in ipiv order, forward (unit L, ascending), backward
-  // with the reciprocals 1 / u_kk (descending)
+  const int tid = threadIdx.x;
+  const int64_t n = it.n;
+  double *A = it.A;
+  auto E = [&](int64_t i, int64_t c) { return A + (i + c * n) * NC; };
   double *x = it.b;
   if (tid == 0)
     for (int64_t j = 0; j < n; ++j) {
@@ -138,7 +173,7 @@ __device__ void lu_solve_one(const ozII_batch_item &it, double (*rkey)[4], int64
   for (int64_t k = 0; k < n; ++k) {
     double xk[NC];
     ozx::load<NC>(x + k * NC, xk);
-    for (int64_t i = k + 1 + tid; i < n; i += BT) {
+    for (int64_t i = k + 1 + tid; i < n; i += NT) {
       double a[NC], l[NC], o[NC];
       ozx::load<NC>(x + i * NC, a);
       ozx::load<NC>(E(i, k), l);
@@ -161,7 +196,7 @@ __device__ void lu_solve_one(const ozII_batch_item &it, double (*rkey)[4], int64
     __syncthreads();
     double xk[NC];
     ozx::load<NC>(x + k * NC, xk);
-    for (int64_t i = tid; i < k; i += BT) {
+    for (int64_t i = tid; i < k; i += NT) {
       double a[NC], u[NC], o[NC];
       ozx::load<NC>(x + i * NC, a);
       ozx::load<NC>(E(i, k), u);
@@ -169,6 +204,226 @@ __device__ void lu_solve_one(const ozII_batch_item &it, double (*rkey)[4], int64
       ozx::store<NC>(x + i * NC, o);
     }
     __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Blocked LU with the Ozaki-II Schur update, one system per workgroup
+// (Sec. 3.4, Eq. (schur), with the product of Sec. 3.1-3.3 at K = b).  Per
+// block of b columns: the panel (pivot_column and the rank-1 updates of the
+// panel's own columns, whole-row interchanges), U12 = L11^-1 A12 (for
+// k = k0 .. : a_ic -= l_ik u_kc over the rows below k of the block), then
+// A22 -= L21 U12 by the stages of ozII_gemm run inside the workgroup:
+//   (S1) row / column exponents into the scratch;
+//   (S2)+(S3) produce_block_b, the four 256-thread quarters taking 16-row
+//        blocks of L21 and U12 in turn (K <= 64: one block per 16 rows);
+//   (S4) every wavefront takes 64 x 64 tiles of the (group, modulus)
+//        products: 4 x 4 MFMA 16x16x64 fragments, operands straight from
+//        the scratch planes, the t-bytes stored as 4-byte column runs;
+//   (S5)+(S6) one element per thread: consume_element_b and the expansion
+//        subtraction.
+// Per element the operations are those of ozII_getrf with the same b and
+// method = Ozaki-II on the INT8 back-end, so the factors agree bit for bit.
+//
+// Scratch of one workgroup (Mp = m2 rounded up to 64, Kp = 64): ea, eb
+// (Mp int32 each), S nmod planes of L21 residues and S nmod planes of U12
+// residues (Mp x 64 bytes each), ng nmod t-planes (Mp x Mp bytes each).
+// ---------------------------------------------------------------------------
+template <int NC, int NWM, int NT>
+__device__ __forceinline__ void oz_update(double *A, int64_t n, int64_t k0, int64_t k1, const DevPlan *pl,
+                          uint8_t *ws, uint32_t *stage) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t K = k1 - k0, m2 = n - k1;
+  const int64_t Mp = (m2 + 63) & ~(int64_t)63;
+  const int S = pl->S, nmod = pl->nmod, ng = pl->ng, g0 = pl->g0, Q = pl->Q, w = pl->w;
+  int32_t *ea = (int32_t *)ws;
+  int32_t *eb = ea + Mp;
+  const int64_t plane = Mp * 64;
+  uint8_t *pa = (uint8_t *)(eb + Mp);
+  uint8_t *pb = pa + (int64_t)S * nmod * plane;
+  uint8_t *tpl = pb + (int64_t)S * nmod * plane;
+  const double *L21 = A + (k1 + k0 * n) * NC;  // m2 x K, leading dimension n
+  const double *U12 = A + (k0 + k1 * n) * NC;  // K x m2
+  double *A22 = A + (k1 + k1 * n) * NC;
+
+  // (S1)
+  for (int64_t i = tid; i < Mp; i += NT) {
+    int32_t be = EXP_ZERO, bf = EXP_ZERO;
+    if (i < m2)
+      for (int64_t h = 0; h < K; ++h) {
+        const int32_t u = exponent_of<NC>(L21 + (i + h * n) * NC);
+        const int32_t v = exponent_of<NC>(U12 + (h + i * n) * NC);
+        be = u > be ? u : be;
+        bf = v > bf ? v : bf;
+      }
+    ea[i] = be;
+    eb[i] = bf;
+  }
+  __syncthreads();
+
+  // (S2)+(S3)
+  {
+    const int T = tid & 255;
+    const int64_t OB = Mp / 16;
+    for (int64_t ob = tid >> 8; ob < 2 * OB; ob += NT / 256) {
+      const bool isA = ob < OB;
+      produce_block_b<NC, 8, NWM, PL_I8>(isA ? L21 : U12, n, isA ? 1 : 0, m2, K, 1, isA ? ea : eb,
+                                         pl, isA ? pa : pb, plane, 0, isA ? ob : ob - OB, T);
+    }
+  }
+  __syncthreads();
+
+  // (S4)
+  {
+    const int64_t TM = Mp / 64;
+    const int64_t items = (int64_t)ng * nmod * TM * TM;
+    for (int64_t q = wv; q < items; q += NT / 64) {
+      const int64_t tn = q % TM, tm = (q / TM) % TM;
+      const int gl = (int)(q / (TM * TM));
+      const int l = gl % nmod, g = g0 + gl / nmod;
+      const int ta0 = g - (S - 1) > 0 ? g - (S - 1) : 0;
+      const int ta1 = g < S - 1 ? g : S - 1;
+      v4i acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = v4i{0, 0, 0, 0};
+      for (int ta = ta0; ta <= ta1; ++ta) {
+        const uint8_t *A0 = pa + (int64_t)(ta * nmod + l) * plane + tm * 4 * 1024 + lane * 16;
+        const uint8_t *B0 = pb + (int64_t)((g - ta) * nmod + l) * plane + tn * 4 * 1024 + lane * 16;
+        v4i af[4], bf[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) af[a] = *(const v4i *)(A0 + a * 1024);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bf[b] = *(const v4i *)(B0 + b * 1024);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a][b], 0, 0, 0);
+      }
+      const uint32_t m = (uint32_t)pl->m[l];
+      const double md = (double)m, yd = (double)pl->y[l], im = pl->inv_m[l];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          uint32_t packed = 0;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) packed |= mod_times_y(acc[a][b][r], md, yd, im, m) << (8 * r);
+          const int64_t row = tm * 64 + 16 * a + 4 * (lane >> 4);
+          const int64_t col = tn * 64 + 16 * b + (lane & 15);
+          *(uint32_t *)(tpl + ((int64_t)gl * Mp + col) * Mp + row) = packed;
+        }
+    }
+  }
+  __syncthreads();
+
+  // (S5)+(S6) and A22 -= c
+  {
+    uint32_t *st = stage + tid * CST;
+    for (int64_t e = tid; e < m2 * m2; e += NT) {
+      const int64_t i = e % m2, j = e / m2;
+      const int32_t ei = ea[i], ej = eb[j];
+      const bool zero = ei == EXP_ZERO || ej == EXP_ZERO;
+      const int eps = zero ? 0 : w * g0 - (Q - 1 - ei) - (Q - 1 - ej);
+      double c[NC];
+      consume_element_b<NC, 12, 36>(tpl + j * Mp + i, Mp * Mp, pl, st, zero, eps, c);
+      double *dst = A22 + (i + j * n) * NC;
+      double a[NC], nc_[NC], r[NC];
+      ozx::load<NC>(dst, a);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) nc_[q] = -c[q];
+      ozx::add<NC>(a, nc_, r);
+      ozx::store<NC>(dst, r);
+    }
+  }
+  __syncthreads();
+}
+
+template <int NC, int NWM, int NT>
+__device__ __forceinline__ void lu_solve_oz(const ozII_batch_item &it, double (*rkey)[4], int64_t *ridx,
+                            int *s_info, const DevPlan *pl, uint8_t *ws, int b,
+                            uint32_t *stage) {
+  const int tid = threadIdx.x;
+  const int64_t n = it.n;
+  double *A = it.A;
+  auto E = [&](int64_t i, int64_t c) { return A + (i + c * n) * NC; };
+  if (tid == 0) *s_info = 0;
+  __syncthreads();
+  for (int64_t k0 = 0; k0 < n; k0 += b) {
+    const int64_t k1 = k0 + b < n ? k0 + b : n;
+    for (int64_t j = k0; j < k1; ++j) {
+      // rank-1 update of the panel's own columns j+1 .. k1-1; none after an
+      // exactly zero pivot (the column is left as it is, as in LAPACK's
+      // unblocked panel)
+      const bool zero = pivot_column<NC, NT>(it, j, rkey, ridx, s_info);
+      const int64_t mr = zero ? 0 : n - j - 1, mc = k1 - j - 1;
+      for (int64_t idx = tid; idx < mr * mc; idx += NT) {
+        const int64_t i = j + 1 + idx % mr, c = j + 1 + idx / mr;
+        double a[NC], l[NC], u[NC], o[NC];
+        ozx::load<NC>(E(i, c), a);
+        ozx::load<NC>(E(i, j), l);
+        ozx::load<NC>(E(j, c), u);
+        ozx::fms<NC>(a, l, u, o);
+        ozx::store<NC>(E(i, c), o);
+      }
+      __syncthreads();
+    }
+    if (k1 < n) {
+      // U12 = L11^-1 A12, forward in k
+      const int64_t ncol = n - k1;
+      for (int64_t k = k0; k + 1 < k1; ++k) {
+        const int64_t mr = k1 - k - 1;
+        for (int64_t idx = tid; idx < mr * ncol; idx += NT) {
+          const int64_t i = k + 1 + idx % mr, c = k1 + idx / mr;
+          double a[NC], l[NC], u[NC], o[NC];
+          ozx::load<NC>(E(i, c), a);
+          ozx::load<NC>(E(i, k), l);
+          ozx::load<NC>(E(k, c), u);
+          ozx::fms<NC>(a, l, u, o);
+          ozx::store<NC>(E(i, c), o);
+        }
+        __syncthreads();
+      }
+      oz_update<NC, NWM, NT>(A, n, k0, k1, pl, ws, stage);
+    }
+  }
+  if (tid == 0) *it.info = *s_info;
+  solve_one<NC, NT>(it);
+}
+
+// One workgroup of BTZ threads per CU (the update's stages need more than
+// the 128 registers a 1024-thread workgroup leaves per thread); the
+// consumer's per-thread staging shares the LDS with the pivot search (never
+// live at the same time).
+__global__ __launch_bounds__(BTZ) void k_batch_lu_oz(const ozII_batch_item *items, int count,
+                                                    int *queue, uint64_t *times,
+                                                    const DevPlan *pl2, const DevPlan *pl3,
+                                                    const DevPlan *pl4, uint8_t *ws, int64_t slot,
+                                                    int b) {
+  __shared__ __attribute__((aligned(16))) uint32_t lds[BTZ * CST];
+  static_assert(BTZ * CST * 4 >= BTZ * (32 + 8), "pivot search arrays fit the staging");
+  double(*rkey)[4] = (double(*)[4])lds;
+  int64_t *ridx = (int64_t *)(lds + BTZ * 8);
+  __shared__ int s_item, s_info;
+  uint8_t *myws = ws + (int64_t)blockIdx.x * slot;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
+    __syncthreads();
+    const int q = s_item;
+    __syncthreads();
+    if (q >= count) break;  // every workgroup leaves once the queue is empty
+    const ozII_batch_item it = items[q];
+    if (times && threadIdx.x == 0) times[2 * it.reserved] = __builtin_amdgcn_s_memrealtime();
+    if (it.nc == 2) lu_solve_oz<2, 6, BTZ>(it, rkey, ridx, &s_info, pl2, myws, b, lds);
+    else if (it.nc == 3) lu_solve_oz<3, 4, BTZ>(it, rkey, ridx, &s_info, pl3, myws, b, lds);
+    else lu_solve_oz<4, 4, BTZ>(it, rkey, ridx, &s_info, pl4, myws, b, lds);
+    __syncthreads();
+    if (times && threadIdx.x == 0) {
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+      times[2 * it.reserved + 1] = __builtin_amdgcn_s_memrealtime();
+    }
   }
 }
 
@@ -209,6 +464,16 @@ hipError_t launch_batch(const ozII_batch_item *items, int count, int *queue, uin
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_batch_clear, dim3(1), dim3(64), 0, s, queue);
   hipLaunchKernelGGL(k_batch_lu, dim3((unsigned)grid), dim3(BT), 0, s, items, count, queue, times);
+  return hipGetLastError();
+}
+hipError_t launch_batch_oz(const ozII_batch_item *items, int count, int *queue, uint64_t *times,
+                          int grid, const DevPlan *pl2, const DevPlan *pl3, const DevPlan *pl4,
+                          uint8_t *ws, int64_t slot, int b, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (b < 1 || b > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_batch_clear, dim3(1), dim3(64), 0, s, queue);
+  hipLaunchKernelGGL(k_batch_lu_oz, dim3((unsigned)grid), dim3(BTZ), 0, s, items, count, queue,
+                     times, pl2, pl3, pl4, ws, slot, b);
   return hipGetLastError();
 }
 }  // namespace ozl

@@ -19,6 +19,7 @@
 #include "ozii_elem.hpp"
 #include "ozii_bytes.hpp"
 #include "ozii_kernels.hpp"
+#include "ozii_stage.hpp"
 
 using namespace ozk;
 
@@ -74,8 +75,6 @@ __global__ __launch_bounds__(256) void k_col_exponents(const double *B, int64_t 
 // ---------------------------------------------------------------------------
 // (S2)+(S3) producer
 // ---------------------------------------------------------------------------
-// Plane encodings of the three back-ends of (S3)/(S4).
-enum { PL_I8 = 0, PL_F8 = 1, PL_F64 = 2 };
 
 // ---------------------------------------------------------------------------
 // Producer of the byte back-ends (INT8 residues, FP8 base-17 digits).  One
@@ -98,14 +97,6 @@ enum { PL_I8 = 0, PL_F8 = 1, PL_F64 = 2 };
 // floor(acc/m) is exact as the high word of (acc << k) * ceil(2^(32-k)/m):
 // acc < 2^(32-k)/m and (acc << k) < 2^24 hold for w <= 300.
 // ---------------------------------------------------------------------------
-template <int NWX>
-__device__ __forceinline__ uint32_t word_or_fill(const uint32_t (&X)[NWX], int k, uint32_t fill) {
-  uint32_t r = fill;
-#pragma unroll
-  for (int i = 0; i < NWX; ++i) r = k == i ? X[i] : r;
-  return r;
-}
-
 template <int NC, int NWX, int NWM, int PL>
 __global__ __launch_bounds__(256) void k_producer_b(const double *__restrict__ X, int64_t ld,
                                                     int rowwise, int64_t nout, int64_t K,
@@ -113,91 +104,8 @@ __global__ __launch_bounds__(256) void k_producer_b(const double *__restrict__ X
                                                     const DevPlan *__restrict__ pl,
                                                     uint8_t *__restrict__ planes,
                                                     int64_t plane_elems) {
-  const int T = threadIdx.x;
-  const int64_t kb = blockIdx.x, ob = blockIdx.y;
-  const int64_t o = ob * 16 + ((T >> 2) & 15);
-  const int64_t h0 = kb * 64 + 16 * (T >> 6) + 4 * (T & 3);
-  // dword index of this thread's four bytes in every plane (planes hold
-  // fewer than 2^31 elements)
-  const uint32_t offb = (uint32_t)((ob * KB + kb) * 1024 + 4 * T);  // < 2^31
-  const int S = pl->S, w = pl->w, nmod = pl->nmod, Q = pl->Q, nwt = pl->nwt;
-
-  uint32_t Xw[4][NWX];
-  int32_t ex = EXP_ZERO;
-  if (o < nout) ex = exps[o];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int64_t h = h0 + e;
-    const double *src = nullptr;
-    if (ex != EXP_ZERO && h < K) src = rowwise ? X + (o + h * ld) * NC : X + (h + o * ld) * NC;
-    if (src) {
-      to_fixed<NC, NWX>(src, Q - 1 - ex, Xw[e]);
-    } else {
-#pragma unroll
-      for (int k = 0; k < NWX; ++k) Xw[e][k] = 0u;
-    }
-  }
-  uint32_t cin[4] = {0u, 0u, 0u, 0u};
-  for (int t = 0; t < S; ++t) {
-    const bool top = t == S - 1;
-    const int bo = t * w, q = bo >> 5, b = bo & 31;
-    const int wq = w >> 5, wb = w & 31;
-    uint32_t F[4][NWM];
-    uint32_t sel[4];  // 1: add the (-2^W) mod m term (flag or sign)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const uint32_t fill = (Xw[e][NWX - 1] >> 31) ? 0xffffffffu : 0u;
-      uint32_t prev = word_or_fill<NWX>(Xw[e], q, fill);
-#pragma unroll
-      for (int j = 0; j < NWM; ++j) {
-        const uint32_t nxt = word_or_fill<NWX>(Xw[e], q + j + 1, fill);
-        F[e][j] = __builtin_amdgcn_alignbit(nxt, prev, b);
-        prev = nxt;
-      }
-      if (!top) {
-        // keep the w-bit field
-#pragma unroll
-        for (int j = 0; j < NWM; ++j)
-          F[e][j] = j < wq ? F[e][j] : (j == wq ? F[e][j] & ((1u << wb) - 1u) : 0u);
-      }
-      // add the incoming carry
-      uint32_t c = cin[e];
-#pragma unroll
-      for (int j = 0; j < NWM; ++j) {
-        const uint32_t sum = F[e][j] + c;
-        c = sum < c ? 1u : 0u;
-        F[e][j] = sum;
-      }
-      if (!top) {
-        // carry out of the field (bit w, inside the window since 32 nwt > w)
-        // and the centring flag (bit w-1)
-        uint32_t co = 0, fl = 0;
-        const int fq = (w - 1) >> 5, fb = (w - 1) & 31;
-#pragma unroll
-        for (int j = 0; j < NWM; ++j) {
-          if (j == wq) {
-            co = (F[e][j] >> wb) & 1u;
-            F[e][j] &= ~(1u << wb);
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < NWM; ++j)
-          if (j == fq) fl = (F[e][j] >> fb) & 1u;
-        sel[e] = fl;
-        cin[e] = co + fl;
-      } else {
-        uint32_t sg = 0;
-#pragma unroll
-        for (int j = 0; j < NWM; ++j)
-          if (j == nwt - 1) sg = F[e][j] >> 31;
-        sel[e] = sg;
-      }
-    }
-    const int pstep = PL == PL_F8 ? 2 : 1;
-    emit_byte_residues<NWM, PL == PL_F8>(F, sel, top ? REC_HT : REC_HW, pl, nmod,
-                                         planes + (int64_t)t * nmod * pstep * plane_elems,
-                                         plane_elems, offb);
-  }
+  produce_block_b<NC, NWX, NWM, PL>(X, ld, rowwise, nout, K, KB, exps, pl, planes, plane_elems,
+                                   blockIdx.x, blockIdx.y, threadIdx.x);
 }
 
 // Producer: one workgroup fills one 16-row x 64-k window of every plane.
@@ -255,21 +163,6 @@ __global__ __launch_bounds__(256) void k_producer(const double *X, int64_t ld, i
       }
     });
   }
-}
-
-// ---------------------------------------------------------------------------
-// (S4) epilogue: t = ((C mod m) y) mod m for |C| < 2^31, y < m <= 256.  x = C y is exact
-// in binary64 (< 2^39); floor(x * RN(1/m)) is floor(x/m) unless x/m is an
-// integer, when it may be one less (the rounding error, < 2^-17, is far
-// below the 1/m distance of any other quotient to an integer), so the
-// remainder is in [0, m] and the single wrap m -> 0 is an unsigned min.
-__device__ __forceinline__ uint32_t mod_times_y(int32_t c, double md, double yd, double im,
-                                                uint32_t m) {
-  const double x = (double)c * yd;
-  const double q = __builtin_floor(x * im);
-  const uint32_t r = (uint32_t)__builtin_fma(-q, md, x);
-  const uint32_t rm = r - m;
-  return r < rm ? r : rm;
 }
 
 // ---------------------------------------------------------------------------
@@ -846,34 +739,18 @@ __global__ __launch_bounds__(256) void k_consumer_b(const uint8_t *__restrict__ 
                                                     const int32_t *__restrict__ ea,
                                                     const int32_t *__restrict__ eb,
                                                     const DevPlan *__restrict__ pl, int mode) {
-  static_assert(NB % 4 == 0 && NB <= CRT4_NB, "byte columns");
-  constexpr int ND = NB / 2;
   __shared__ uint32_t stage[256 * CST];
   uint32_t *st = stage + threadIdx.x * CST;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t j = blockIdx.y;
   if (i >= M || j >= N) return;
-  const int nmod = pl->nmod, Q = pl->Q, w = pl->w, ng = pl->ng;
+  const int Q = pl->Q;
   const int32_t ei = ea[i], ej = eb[j];
   const bool zero = ei == EXP_ZERO || ej == EXP_ZERO;
-  const int eps = zero ? 0 : w * pl->g0 - (Q - 1 - ei) - (Q - 1 - ej);
-  const int64_t ps = Np * Mp;  // bytes between consecutive moduli
-  uint32_t cb[NWC];
-#pragma unroll
-  for (int k = 0; k < NWC; ++k) cb[k] = 0u;
-  for (int gi = 0; gi < ng; ++gi) {
-    const uint8_t *tp = tpl + ((int64_t)gi * nmod * Np + j) * Mp + i;
-    int32_t d[ND];
-    crt_group_bytes<NB>(tp, ps, nmod, pl, d);
-    add_shifted_digits<NWC, ND>(cb, d, w * gi, st);
-  }
+  const int eps = zero ? 0 : pl->w * pl->g0 - (Q - 1 - ei) - (Q - 1 - ej);
   double c[NC];
-  if (zero) {
-#pragma unroll
-    for (int qq = 0; qq < NC; ++qq) c[qq] = 0.0;
-  } else {
-    round_out<NWC, NC>(cb, eps, c);
-  }
+  // consecutive moduli Np Mp bytes apart
+  consume_element_b<NC, NWC, NB>(tpl + j * Mp + i, Np * Mp, pl, st, zero, eps, c);
   double *dst = C + (i + j * ldc) * NC;
   if (mode == 0) {
     ozx::store<NC>(dst, c);

@@ -326,6 +326,13 @@ struct ozII_ctx {
   ozII_batch_item *batch = nullptr;
   int batch_cap = 0, batch_count = 0, batch_grid = 1;
   int *batch_queue = nullptr;
+  // batched LU with the Ozaki-II update: panel width (0: native unblocked
+  // path), plans per nc = 2, 3, 4 and the per-workgroup scratch
+  int batch_b = 0;
+  const DevPlan *batch_pl[3] = {nullptr, nullptr, nullptr};
+  uint8_t *batch_ws = nullptr;
+  size_t batch_ws_bytes = 0;
+  int64_t batch_slot = 0;
   std::map<std::tuple<int, int64_t, int, int, int, int>, std::pair<HostPlan, DevPlan *>> plans;
   // per-stage profiling (HIP events on the handle's stream)
   struct ProfRec {
@@ -752,6 +759,7 @@ ozII_status ozII_destroy(ozII_handle h) {
   if (h->rinv) hipFree(h->rinv);
   if (h->batch) hipFree(h->batch);
   if (h->batch_queue) hipFree(h->batch_queue);
+  if (h->batch_ws) hipFree(h->batch_ws);
   if (h->bar) {
     hipFree(h->bar);
     hipFree(h->flags);
@@ -1008,13 +1016,53 @@ ozII_status ozII_getrs(ozII_handle h, int32_t nc, int64_t n, int64_t nrhs, const
 }
 
 ozII_status ozII_batch_prepare(ozII_handle h, int32_t count, const ozII_batch_item *items) {
+  return ozII_batch_prepare_ex(h, count, items, nullptr);
+}
+
+ozII_status ozII_batch_prepare_ex(ozII_handle h, int32_t count, const ozII_batch_item *items,
+                                  const ozII_opts *o) {
   if (!h || count < 0 || (count > 0 && !items)) return OZII_EINVAL;
+  const int method = o ? o->method : OZII_METHOD_NAIVE;
+  if (method != OZII_METHOD_OZAKI && method != OZII_METHOD_NAIVE) return fail(h, OZII_EINVAL, "bad method");
+  const bool oz = method == OZII_METHOD_OZAKI;
+  const int b = oz ? ((o && o->block > 0) ? o->block : 32) : 0;
+  if (oz && b > 64) return fail(h, OZII_EUNSUPPORTED, "batched Ozaki-II LU: panel width above 64");
+  if (oz && o->backend != OZII_BE_AUTO && o->backend != OZII_BE_INT8)
+    return fail(h, OZII_EUNSUPPORTED, "batched Ozaki-II LU: INT8 back-end only");
   std::vector<ozII_batch_item> v(items, items + count);
+  int64_t nmax[3] = {0, 0, 0};
   for (int i = 0; i < count; ++i) {
     const ozII_batch_item &it = v[i];
     if (it.nc < 2 || it.nc > 4 || it.n < 1 || it.n > 4096 || !it.A || !it.ipiv || !it.info)
       return fail(h, OZII_EINVAL, "batch item " + std::to_string(i) + " is invalid");
+    if (oz && it.n > 1024)
+      return fail(h, OZII_EUNSUPPORTED, "batched Ozaki-II LU: order above 1024");
     v[i].reserved = i;
+    nmax[it.nc - 2] = std::max(nmax[it.nc - 2], it.n);
+  }
+  // plans at K = b (those of ozII_getrf with the same block) and the scratch
+  // of one workgroup: exponents, residue planes of L21 and U12, t-planes
+  const DevPlan *pls[3] = {nullptr, nullptr, nullptr};
+  int64_t slot = 0;
+  if (oz) {
+    ozII_opts po = *o;
+    po.backend = OZII_BE_INT8;
+    for (int c = 0; c < 3; ++c) {
+      if (nmax[c] == 0) continue;
+      const int nc = c + 2;
+      const HostPlan *hp;
+      const DevPlan *dp;
+      ozII_status st = get_plan(h, 53 * nc, b, &po, &hp, &dp);
+      if (st != OZII_OK) return st;
+      const int nwt = (hp->w + 2 + 31) / 32;
+      if (hp->nwx > 8 || nwt > (nc == 2 ? 6 : 4) || hp->nwc > 12 || hp->nd > 18)
+        return fail(h, OZII_EUNSUPPORTED, "batched Ozaki-II LU: plan exceeds the compiled word sizes");
+      pls[c] = dp;
+      const int64_t Mp = roundup(std::max<int64_t>(nmax[c] - b, 1), 64);
+      const int64_t bytes = 8 * Mp + 2 * (int64_t)hp->S * hp->nmod * Mp * 64 +
+                            (int64_t)hp->ng * hp->nmod * Mp * Mp;
+      slot = std::max(slot, roundup(bytes, 256));
+    }
   }
   // longest processing time first: cost ~ nc n^3, ties in caller order
   std::stable_sort(v.begin(), v.end(), [](const ozII_batch_item &a, const ozII_batch_item &b) {
@@ -1037,21 +1085,38 @@ ozII_status ozII_batch_prepare(ozII_handle h, int32_t count, const ozII_batch_it
                           h->stream)) != hipSuccess)
     return hip_fail(h, e, "batch upload");
   if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
-  // persistent grid: one 1024-thread workgroup per CU, at most one per item
+  // persistent grid: one workgroup per CU, at most one per item
   int dev = 0, ncu = 0;
   if ((e = hipGetDevice(&dev)) != hipSuccess ||
       (e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
     return hip_fail(h, e, "device query");
+  const int grid = std::max(1, std::min(count, ncu));
+  if (oz && (size_t)(slot * grid) > h->batch_ws_bytes) {
+    if (h->batch_ws) hipFree(h->batch_ws);
+    h->batch_ws = nullptr;
+    h->batch_ws_bytes = 0;
+    if ((e = hipMalloc((void **)&h->batch_ws, (size_t)(slot * grid))) != hipSuccess)
+      return fail(h, OZII_ENOMEM, "batch scratch allocation failed");
+    h->batch_ws_bytes = (size_t)(slot * grid);
+  }
   h->batch_count = count;
-  h->batch_grid = std::max(1, std::min(count, ncu));
+  h->batch_grid = grid;
+  h->batch_b = b;
+  h->batch_slot = slot;
+  for (int c = 0; c < 3; ++c) h->batch_pl[c] = pls[c];
   return OZII_OK;
 }
 
 ozII_status ozII_batch_run(ozII_handle h, uint64_t *times) {
   if (!h) return OZII_EINVAL;
   if (h->batch_count == 0) return OZII_OK;
-  hipError_t e = ozl::launch_batch(h->batch, h->batch_count, h->batch_queue, times, h->batch_grid,
-                                   h->stream);
+  hipError_t e =
+      h->batch_b > 0
+          ? ozl::launch_batch_oz(h->batch, h->batch_count, h->batch_queue, times, h->batch_grid,
+                                 h->batch_pl[0], h->batch_pl[1], h->batch_pl[2], h->batch_ws,
+                                 h->batch_slot, h->batch_b, h->stream)
+          : ozl::launch_batch(h->batch, h->batch_count, h->batch_queue, times, h->batch_grid,
+                              h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "batched LU");
   return OZII_OK;
 }

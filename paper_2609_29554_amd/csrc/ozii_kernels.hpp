@@ -120,5 +120,12 @@ hipError_t launch_trsv(int nc, int fwd, const double *LU, int64_t lda, double *x
 // caller-order index in `reserved`
 hipError_t launch_batch(const ozII_batch_item *items, int count, int *queue, uint64_t *times,
                         int grid, hipStream_t s);
+// the same with the blocked LU and the in-workgroup Ozaki-II update (panel
+// width b <= 64); plans at K = b for nc = 2, 3, 4 (null for absent formats),
+// scratch of `slot` bytes per workgroup
+hipError_t launch_batch_oz(const ozII_batch_item *items, int count, int *queue, uint64_t *times,
+                           int grid, const ozk::DevPlan *pl2, const ozk::DevPlan *pl3,
+                           const ozk::DevPlan *pl4, uint8_t *ws, int64_t slot, int b,
+                           hipStream_t s);
 
 }  // namespace ozl

@@ -1,0 +1,171 @@
+// Per-element stages of the byte back-ends, shared by the grid kernels of
+// one Ozaki-II product and by the batched LU, which runs the same stages
+// inside one workgroup per system:
+//   produce_block_b   (S2)+(S3): one 16-row x 64-k block of every residue
+//                     plane, from expansions (Eq. direct, Sec. 3.2 slicing);
+//   mod_times_y       (S4) epilogue: t = ((C mod m) y) mod m, Eq. (crt);
+//   consume_element_b (S5)+(S6): CRT of every retained digit group, exact
+//                     group sum, one greedy rounding.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ozii_bytes.hpp"
+#include "ozii_elem.hpp"
+
+namespace ozk {
+
+// Plane encodings of the three back-ends of (S3)/(S4).
+enum { PL_I8 = 0, PL_F8 = 1, PL_F64 = 2 };
+
+// Producer of the byte back-ends (INT8 residues, FP8 base-17 digits): the
+// caller's 256 threads (T = 0..255) fill block (ob, kb) -- rows 16 ob ..
+// 16 ob + 15, inner indices 64 kb .. 64 kb + 63 -- of every plane; thread T
+// owns the four consecutive bytes 4T .. 4T+3 of the block, i.e. row
+// (T/4)%16 and inner indices 16(T/64) + 4(T%4) + e, e = 0..3, so each
+// residue plane receives one dword store per thread.  Rows at or past nout
+// and inner indices at or past K are zero.
+template <int NWX>
+__device__ __forceinline__ uint32_t word_or_fill(const uint32_t (&X)[NWX], int k, uint32_t fill) {
+  uint32_t r = fill;
+#pragma unroll
+  for (int i = 0; i < NWX; ++i) r = k == i ? X[i] : r;
+  return r;
+}
+
+template <int NC, int NWX, int NWM, int PL>
+__device__ __forceinline__ void produce_block_b(const double *__restrict__ X, int64_t ld,
+                                                int rowwise, int64_t nout, int64_t K, int64_t KB,
+                                                const int32_t *__restrict__ exps,
+                                                const DevPlan *__restrict__ pl,
+                                                uint8_t *__restrict__ planes,
+                                                int64_t plane_elems, int64_t kb, int64_t ob,
+                                                int T) {
+  const int64_t o = ob * 16 + ((T >> 2) & 15);
+  const int64_t h0 = kb * 64 + 16 * (T >> 6) + 4 * (T & 3);
+  // dword index of this thread's four bytes in every plane (planes hold
+  // fewer than 2^31 elements)
+  const uint32_t offb = (uint32_t)((ob * KB + kb) * 1024 + 4 * T);  // < 2^31
+  const int S = pl->S, w = pl->w, nmod = pl->nmod, Q = pl->Q, nwt = pl->nwt;
+
+  uint32_t Xw[4][NWX];
+  int32_t ex = EXP_ZERO;
+  if (o < nout) ex = exps[o];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t h = h0 + e;
+    const double *src = nullptr;
+    if (ex != EXP_ZERO && h < K) src = rowwise ? X + (o + h * ld) * NC : X + (h + o * ld) * NC;
+    if (src) {
+      to_fixed<NC, NWX>(src, Q - 1 - ex, Xw[e]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < NWX; ++k) Xw[e][k] = 0u;
+    }
+  }
+  uint32_t cin[4] = {0u, 0u, 0u, 0u};
+  for (int t = 0; t < S; ++t) {
+    const bool top = t == S - 1;
+    const int bo = t * w, q = bo >> 5, b = bo & 31;
+    const int wq = w >> 5, wb = w & 31;
+    uint32_t F[4][NWM];
+    uint32_t sel[4];  // 1: add the (-2^W) mod m term (flag or sign)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t fill = (Xw[e][NWX - 1] >> 31) ? 0xffffffffu : 0u;
+      uint32_t prev = word_or_fill<NWX>(Xw[e], q, fill);
+#pragma unroll
+      for (int j = 0; j < NWM; ++j) {
+        const uint32_t nxt = word_or_fill<NWX>(Xw[e], q + j + 1, fill);
+        F[e][j] = __builtin_amdgcn_alignbit(nxt, prev, b);
+        prev = nxt;
+      }
+      if (!top) {
+        // keep the w-bit field
+#pragma unroll
+        for (int j = 0; j < NWM; ++j)
+          F[e][j] = j < wq ? F[e][j] : (j == wq ? F[e][j] & ((1u << wb) - 1u) : 0u);
+      }
+      // add the incoming carry
+      uint32_t c = cin[e];
+#pragma unroll
+      for (int j = 0; j < NWM; ++j) {
+        const uint32_t sum = F[e][j] + c;
+        c = sum < c ? 1u : 0u;
+        F[e][j] = sum;
+      }
+      if (!top) {
+        // carry out of the field (bit w, inside the window since 32 nwt > w)
+        // and the centring flag (bit w-1)
+        uint32_t co = 0, fl = 0;
+        const int fq = (w - 1) >> 5, fb = (w - 1) & 31;
+#pragma unroll
+        for (int j = 0; j < NWM; ++j) {
+          if (j == wq) {
+            co = (F[e][j] >> wb) & 1u;
+            F[e][j] &= ~(1u << wb);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < NWM; ++j)
+          if (j == fq) fl = (F[e][j] >> fb) & 1u;
+        sel[e] = fl;
+        cin[e] = co + fl;
+      } else {
+        uint32_t sg = 0;
+#pragma unroll
+        for (int j = 0; j < NWM; ++j)
+          if (j == nwt - 1) sg = F[e][j] >> 31;
+        sel[e] = sg;
+      }
+    }
+    const int pstep = PL == PL_F8 ? 2 : 1;
+    emit_byte_residues<NWM, PL == PL_F8>(F, sel, top ? REC_HT : REC_HW, pl, nmod,
+                                         planes + (int64_t)t * nmod * pstep * plane_elems,
+                                         plane_elems, offb);
+  }
+}
+
+// (S4) epilogue: t = ((c mod m) y) mod m in [0, m) for any int32 c, y < m
+// <= 256.  x = c y is exact in binary64 (< 2^39); floor(x * RN(1/m)) is floor(x/m) unless x/m is an
+// integer, when it may be one less (the rounding error, < 2^-17, is far
+// below the 1/m distance of any other quotient to an integer), so the
+// remainder is in [0, m] and the single wrap m -> 0 is an unsigned min.
+__device__ __forceinline__ uint32_t mod_times_y(int32_t c, double md, double yd, double im,
+                                                uint32_t m) {
+  const double x = (double)c * yd;
+  const double q = __builtin_floor(x * im);
+  const uint32_t r = (uint32_t)__builtin_fma(-q, md, x);
+  const uint32_t rm = r - m;
+  return r < rm ? r : rm;
+}
+
+// Consumer of the byte back-ends, one element: per digit group gi the CRT of
+// crt_group_bytes over the t-bytes at tbase + (gi nmod + l) ps (modulus l),
+// the group added at bit w gi to the exact group sum, which is rounded once
+// to NC components of value sum 2^eps (zero: all components 0).  st: CST
+// words of thread-private scratch.
+template <int NC, int NWC, int NB>
+__device__ __forceinline__ void consume_element_b(const uint8_t *tbase, int64_t ps,
+                                                  const DevPlan *__restrict__ pl, uint32_t *st,
+                                                  bool zero, int eps, double (&c)[NC]) {
+  static_assert(NB % 4 == 0 && NB <= CRT4_NB, "byte columns");
+  constexpr int ND = NB / 2;
+  const int nmod = pl->nmod, w = pl->w, ng = pl->ng;
+  uint32_t cb[NWC];
+#pragma unroll
+  for (int k = 0; k < NWC; ++k) cb[k] = 0u;
+  for (int gi = 0; gi < ng; ++gi) {
+    int32_t d[ND];
+    crt_group_bytes<NB>(tbase + (int64_t)gi * nmod * ps, ps, nmod, pl, d);
+    add_shifted_digits<NWC, ND>(cb, d, w * gi, st);
+  }
+  if (zero) {
+#pragma unroll
+    for (int qq = 0; qq < NC; ++qq) c[qq] = 0.0;
+  } else {
+    round_out<NWC, NC>(cb, eps, c);
+  }
+}
+
+}  // namespace ozk
