@@ -158,6 +158,8 @@ def main():
     ap.add_argument("--sweep-block", type=int, default=128)
     ap.add_argument("--no-autotune", action="store_true",
                     help="use --block and the INT8 back-end instead of the autotuner's choice")
+    ap.add_argument("--batch-block", type=int, default=64,
+                    help="panel width of the batched Ozaki-II LU (at most 256)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -438,22 +440,12 @@ def backend_sweep(ctx, args):
     return out
 
 
-def bench_batch(args):
-    """The batched configuration: count independent systems (orders uniform in
-    [64, 512], half DD half QD, graded D R D) factored and solved in one
-    persistent launch captured in a hipGraph; a step restores the inputs and
-    replays the graph.  Reports the per-solve latency from device timestamps
-    (the 100 MHz real-time counter at each system's start and end)."""
+def _batch_run(ctx, systems, opts, args):
+    """Upload, capture and replay one batch; returns (seconds per step,
+    per-solve durations, completion times, info values)."""
     import numpy as np
     import torch
 
-    import paper_2609_29554_amd as Z
-    import workloads as W
-
-    rng = np.random.default_rng(20260934)
-    log(f"generating {args.batch_count} systems")
-    systems = W.batch_systems(args.batch_count, rng)
-    ctx = Z.Context(0)
     src, work = [], []
     for nc, A, b in systems:
         n = A.shape[0]
@@ -461,7 +453,7 @@ def bench_batch(args):
         work.append((torch.from_numpy(A).cuda(), torch.from_numpy(b).cuda(),
                      torch.zeros(n, dtype=torch.int64, device="cuda"),
                      torch.zeros(1, dtype=torch.int32, device="cuda")))
-    ctx.batch_prepare(work)
+    ctx.batch_prepare(work, opts)
     times = torch.zeros(2 * len(work), dtype=torch.int64, device="cuda")
     ctx.batch_run(times)          # eager warm-up
     ctx.sync_check()
@@ -485,27 +477,66 @@ def bench_batch(args):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.sync_check()
-    sec = (t1 - t0) / args.steps
     t = times.cpu().numpy().reshape(-1, 2).astype(np.float64) / 100e6   # seconds
     dur = t[:, 1] - t[:, 0]
     done = t[:, 1] - t[:, 0].min()
     infos = [int(w[3].cpu()[0]) for w in work]
+    return (t1 - t0) / args.steps, dur, done, infos
+
+
+def bench_batch(args):
+    """The batched configuration: count independent systems (orders uniform in
+    [64, 512], half DD half QD, graded D R D) factored and solved in one
+    persistent launch captured in a hipGraph; a step restores the inputs and
+    replays the graph.  Reports the per-solve latency from device timestamps
+    (the 100 MHz real-time counter at each system's start and end) for the
+    blocked LU with the in-workgroup Ozaki-II update (block --batch-block),
+    and beside it the unblocked LU with the native expansion update."""
+    import numpy as np
+
+    import paper_2609_29554_amd as Z
+    import workloads as W
+
+    rng = np.random.default_rng(20260934)
+    log(f"generating {args.batch_count} systems")
+    systems = W.batch_systems(args.batch_count, rng)
+    ctx = Z.Context(0)
     ns = [A.shape[0] for _, A, _ in systems]
+
+    ncs = np.array([nc for nc, _, _ in systems])
+
+    def stats(sec, dur, done, infos):
+        by_fmt = {{2: "DD", 3: "TD", 4: "QD"}[c]: {"p50": float(np.percentile(dur[ncs == c], 50)) * 1e3,
+                                                  "p99": float(np.percentile(dur[ncs == c], 99)) * 1e3}
+                  for c in sorted(set(ncs.tolist()))}
+        return {"ms_per_step": sec * 1e3, "latency_by_format_ms": by_fmt,
+                "latency_ms": {"p50": float(np.percentile(dur, 50)) * 1e3,
+                               "p99": float(np.percentile(dur, 99)) * 1e3,
+                               "max": float(dur.max()) * 1e3},
+                "completion_ms": {"p50": float(np.percentile(done, 50)) * 1e3,
+                                  "p99": float(np.percentile(done, 99)) * 1e3,
+                                  "makespan": float(done.max()) * 1e3},
+                "nonzero_info": int(sum(1 for v in infos if v != 0))}
+
+    log(f"Ozaki-II update, b = {args.batch_block}")
+    oz = stats(*_batch_run(ctx, systems, Z.make_opts(block=args.batch_block,
+                                                     method=Z.METHOD_OZAKI), args))
+    log("native update")
+    nat = stats(*_batch_run(ctx, systems, None, args))
     out = {"metric": "batched DD/QD LU + solve: per-solve latency p50/p99",
-           "value": float(np.percentile(dur, 99)) * 1e3, "unit": "ms (p99 per-solve latency)",
-           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
+           "value": oz["latency_ms"]["p99"], "unit": "ms (p99 per-solve latency)",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": oz["ms_per_step"],
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64x2/f64x4",
            "data": "synthetic",
            "config": {"workload": f"{len(systems)} independent systems, n in [64, 512] (mean "
                                   f"{np.mean(ns):.0f}), half DD half QD, graded D R D, one persistent "
-                                  f"launch in a captured hipGraph"},
-           "latency_ms": {"p50": float(np.percentile(dur, 50)) * 1e3,
-                          "p99": float(np.percentile(dur, 99)) * 1e3,
-                          "max": float(dur.max()) * 1e3},
-           "completion_ms": {"p50": float(np.percentile(done, 50)) * 1e3,
-                             "p99": float(np.percentile(done, 99)) * 1e3,
-                             "makespan": float(done.max()) * 1e3},
-           "nonzero_info": int(sum(1 for v in infos if v != 0))}
+                                  f"launch in a captured hipGraph; blocked LU b = {args.batch_block} "
+                                  f"with the Ozaki-II update (INT8) inside each workgroup"},
+           "latency_ms": oz["latency_ms"], "latency_by_format_ms": oz["latency_by_format_ms"],
+           "completion_ms": oz["completion_ms"],
+           "nonzero_info": oz["nonzero_info"],
+           "native_update": dict(nat, config="unblocked LU, native expansion update")}
     print(json.dumps(out))
 
 

@@ -220,7 +220,7 @@ ozII_status ozII_batch_prepare(ozII_handle h, int32_t count, const ozII_batch_it
 /* ozII_batch_prepare with options.  o == NULL or o->method ==
  * OZII_METHOD_NAIVE: as ozII_batch_prepare.  o->method == OZII_METHOD_OZAKI:
  * every item is factored by one workgroup with the blocked LU of ozII_getrf
- * (panel width b = o->block, default 32, at most 64) whose Schur updates run
+ * (panel width b = o->block, default 32, at most 256) whose Schur updates run
  * the Ozaki-II product of Sec. 3.1-3.3 inside the workgroup on the INT8
  * back-end (plans at K = b, honouring o->nslice / extra_groups / guard_ex):
  * per element the operations of ozII_getrf with the same o, so factors,
@@ -228,7 +228,7 @@ ozII_status ozII_batch_prepare(ozII_handle h, int32_t count, const ozII_batch_it
  * handle allocates one scratch slot per workgroup here (exponents, residue
  * planes of L21 and U12, t-planes: about ng nmod (n - b)^2 bytes for the
  * largest item), so ozII_batch_run still allocates nothing.
- * Errors: those of ozII_batch_prepare; OZII_EUNSUPPORTED for b > 64, an item
+ * Errors: those of ozII_batch_prepare; OZII_EUNSUPPORTED for b > 256, an item
  * of order above 1024, a back-end other than INT8 / AUTO, or a plan beyond
  * the compiled word sizes; OZII_ENOMEM when the scratch cannot be allocated. */
 ozII_status ozII_batch_prepare_ex(ozII_handle h, int32_t count, const ozII_batch_item *items,

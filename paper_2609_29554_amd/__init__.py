@@ -302,7 +302,7 @@ class Context:
         tensors, A (n, n, nc) float64, b (1, n, nc) float64, ipiv int64[n],
         info int32[1]; the tensors must stay alive while the batch is used.
         opts None: unblocked LU with the native update; opts with method
-        Ozaki-II: blocked LU (opts.block, default 32, at most 64) with the
+        Ozaki-II: blocked LU (opts.block, default 32, at most 256) with the
         Ozaki-II update on the INT8 back-end."""
         arr = (BatchItem * max(len(systems), 1))()
         for i, (A, b, ipiv, info) in enumerate(systems):

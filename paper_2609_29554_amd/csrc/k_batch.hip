@@ -25,6 +25,7 @@ namespace {
 
 constexpr int BT = 1024;  // threads per workgroup (4 wavefronts per SIMD)
 constexpr int BTZ = 512;  // the same for the Ozaki-II update
+constexpr int BZ_PRE = 10; // t-byte chunks requested at once by its CRT (nmod <= 40)
 
 // largest |value| first, then the lower row index (a total order)
 template <int NC>
@@ -215,8 +216,8 @@ __device__ void solve_one(const ozII_batch_item &it) {
 // k = k0 .. : a_ic -= l_ik u_kc over the rows below k of the block), then
 // A22 -= L21 U12 by the stages of ozII_gemm run inside the workgroup:
 //   (S1) row / column exponents into the scratch;
-//   (S2)+(S3) produce_block_b, the four 256-thread quarters taking 16-row
-//        blocks of L21 and U12 in turn (K <= 64: one block per 16 rows);
+//   (S2)+(S3) produce_block_b, the 256-thread quarters taking the 16-row x
+//        64-k blocks of L21 and U12 in turn;
 //   (S4) every wavefront takes 64 x 64 tiles of the (group, modulus)
 //        products: 4 x 4 MFMA 16x16x64 fragments, operands straight from
 //        the scratch planes, the t-bytes stored as 4-byte column runs;
@@ -225,20 +226,20 @@ __device__ void solve_one(const ozII_batch_item &it) {
 // Per element the operations are those of ozII_getrf with the same b and
 // method = Ozaki-II on the INT8 back-end, so the factors agree bit for bit.
 //
-// Scratch of one workgroup (Mp = m2 rounded up to 64, Kp = 64): ea, eb
+// Scratch of one workgroup (Mp = m2 and Kp = b rounded up to 64): ea, eb
 // (Mp int32 each), S nmod planes of L21 residues and S nmod planes of U12
-// residues (Mp x 64 bytes each), ng nmod t-planes (Mp x Mp bytes each).
+// residues (Mp x Kp bytes each), ng nmod t-planes (Mp x Mp bytes each).
 // ---------------------------------------------------------------------------
 template <int NC, int NWM, int NT>
 __device__ __forceinline__ void oz_update(double *A, int64_t n, int64_t k0, int64_t k1, const DevPlan *pl,
                           uint8_t *ws, uint32_t *stage) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t K = k1 - k0, m2 = n - k1;
-  const int64_t Mp = (m2 + 63) & ~(int64_t)63;
+  const int64_t Mp = (m2 + 63) & ~(int64_t)63, Kp = (K + 63) & ~(int64_t)63, KB = Kp / 64;
   const int S = pl->S, nmod = pl->nmod, ng = pl->ng, g0 = pl->g0, Q = pl->Q, w = pl->w;
   int32_t *ea = (int32_t *)ws;
   int32_t *eb = ea + Mp;
-  const int64_t plane = Mp * 64;
+  const int64_t plane = Mp * Kp;
   uint8_t *pa = (uint8_t *)(eb + Mp);
   uint8_t *pb = pa + (int64_t)S * nmod * plane;
   uint8_t *tpl = pb + (int64_t)S * nmod * plane;
@@ -264,11 +265,13 @@ __device__ __forceinline__ void oz_update(double *A, int64_t n, int64_t k0, int6
   // (S2)+(S3)
   {
     const int T = tid & 255;
-    const int64_t OB = Mp / 16;
-    for (int64_t ob = tid >> 8; ob < 2 * OB; ob += NT / 256) {
-      const bool isA = ob < OB;
-      produce_block_b<NC, 8, NWM, PL_I8>(isA ? L21 : U12, n, isA ? 1 : 0, m2, K, 1, isA ? ea : eb,
-                                         pl, isA ? pa : pb, plane, 0, isA ? ob : ob - OB, T);
+    const int64_t NBLK = Mp / 16 * KB;  // blocks per operand
+    for (int64_t q = tid >> 8; q < 2 * NBLK; q += NT / 256) {
+      const bool isA = q < NBLK;
+      const int64_t r = isA ? q : q - NBLK;
+      produce_block_b<NC, 8, NWM, PL_I8>(isA ? L21 : U12, n, isA ? 1 : 0, m2, K, KB,
+                                         isA ? ea : eb, pl, isA ? pa : pb, plane, r % KB, r / KB,
+                                         T);
     }
   }
   __syncthreads();
@@ -289,18 +292,21 @@ __device__ __forceinline__ void oz_update(double *A, int64_t n, int64_t k0, int6
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = v4i{0, 0, 0, 0};
       for (int ta = ta0; ta <= ta1; ++ta) {
-        const uint8_t *A0 = pa + (int64_t)(ta * nmod + l) * plane + tm * 4 * 1024 + lane * 16;
-        const uint8_t *B0 = pb + (int64_t)((g - ta) * nmod + l) * plane + tn * 4 * 1024 + lane * 16;
-        v4i af[4], bf[4];
+        const uint8_t *A0 = pa + (int64_t)(ta * nmod + l) * plane + tm * 4 * KB * 1024 + lane * 16;
+        const uint8_t *B0 =
+            pb + (int64_t)((g - ta) * nmod + l) * plane + tn * 4 * KB * 1024 + lane * 16;
+        for (int64_t kb = 0; kb < KB; ++kb) {
+          v4i af[4], bf[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) af[a] = *(const v4i *)(A0 + a * 1024);
+          for (int a = 0; a < 4; ++a) af[a] = *(const v4i *)(A0 + (a * KB + kb) * 1024);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) bf[b] = *(const v4i *)(B0 + b * 1024);
+          for (int b = 0; b < 4; ++b) bf[b] = *(const v4i *)(B0 + (b * KB + kb) * 1024);
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+          for (int a = 0; a < 4; ++a)
 #pragma unroll
-          for (int b = 0; b < 4; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a][b], 0, 0, 0);
+            for (int b = 0; b < 4; ++b)
+              acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[a][b], 0, 0, 0);
+        }
       }
       const uint32_t m = (uint32_t)pl->m[l];
       const double md = (double)m, yd = (double)pl->y[l], im = pl->inv_m[l];
@@ -328,7 +334,7 @@ __device__ __forceinline__ void oz_update(double *A, int64_t n, int64_t k0, int6
       const bool zero = ei == EXP_ZERO || ej == EXP_ZERO;
       const int eps = zero ? 0 : w * g0 - (Q - 1 - ei) - (Q - 1 - ej);
       double c[NC];
-      consume_element_b<NC, 12, 36>(tpl + j * Mp + i, Mp * Mp, pl, st, zero, eps, c);
+      consume_element_b<NC, 12, 36, BZ_PRE>(tpl + j * Mp + i, Mp * Mp, pl, st, zero, eps, c);
       double *dst = A22 + (i + j * n) * NC;
       double a[NC], nc_[NC], r[NC];
       ozx::load<NC>(dst, a);
@@ -470,7 +476,7 @@ hipError_t launch_batch_oz(const ozII_batch_item *items, int count, int *queue, 
                           int grid, const DevPlan *pl2, const DevPlan *pl3, const DevPlan *pl4,
                           uint8_t *ws, int64_t slot, int b, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  if (b < 1 || b > 64) return hipErrorInvalidValue;
+  if (b < 1 || b > 256) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_batch_clear, dim3(1), dim3(64), 0, s, queue);
   hipLaunchKernelGGL(k_batch_lu_oz, dim3((unsigned)grid), dim3(BTZ), 0, s, items, count, queue,
                      times, pl2, pl3, pl4, ws, slot, b);

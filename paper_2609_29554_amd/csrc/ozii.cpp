@@ -1026,7 +1026,7 @@ ozII_status ozII_batch_prepare_ex(ozII_handle h, int32_t count, const ozII_batch
   if (method != OZII_METHOD_OZAKI && method != OZII_METHOD_NAIVE) return fail(h, OZII_EINVAL, "bad method");
   const bool oz = method == OZII_METHOD_OZAKI;
   const int b = oz ? ((o && o->block > 0) ? o->block : 32) : 0;
-  if (oz && b > 64) return fail(h, OZII_EUNSUPPORTED, "batched Ozaki-II LU: panel width above 64");
+  if (oz && b > 256) return fail(h, OZII_EUNSUPPORTED, "batched Ozaki-II LU: panel width above 256");
   if (oz && o->backend != OZII_BE_AUTO && o->backend != OZII_BE_INT8)
     return fail(h, OZII_EUNSUPPORTED, "batched Ozaki-II LU: INT8 back-end only");
   std::vector<ozII_batch_item> v(items, items + count);
@@ -1055,11 +1055,11 @@ ozII_status ozII_batch_prepare_ex(ozII_handle h, int32_t count, const ozII_batch
       ozII_status st = get_plan(h, 53 * nc, b, &po, &hp, &dp);
       if (st != OZII_OK) return st;
       const int nwt = (hp->w + 2 + 31) / 32;
-      if (hp->nwx > 8 || nwt > (nc == 2 ? 6 : 4) || hp->nwc > 12 || hp->nd > 18)
+      if (hp->nwx > 8 || nwt > (nc == 2 ? 6 : 4) || hp->nwc > 12 || hp->nd > 18 || hp->nmod > 40)
         return fail(h, OZII_EUNSUPPORTED, "batched Ozaki-II LU: plan exceeds the compiled word sizes");
       pls[c] = dp;
-      const int64_t Mp = roundup(std::max<int64_t>(nmax[c] - b, 1), 64);
-      const int64_t bytes = 8 * Mp + 2 * (int64_t)hp->S * hp->nmod * Mp * 64 +
+      const int64_t Mp = roundup(std::max<int64_t>(nmax[c] - b, 1), 64), Kp = roundup(b, 64);
+      const int64_t bytes = 8 * Mp + 2 * (int64_t)hp->S * hp->nmod * Mp * Kp +
                             (int64_t)hp->ng * hp->nmod * Mp * Mp;
       slot = std::max(slot, roundup(bytes, 256));
     }

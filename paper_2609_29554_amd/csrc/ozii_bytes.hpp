@@ -91,7 +91,7 @@ __device__ __forceinline__ void emit_byte_residues(const uint32_t (&F)[4][NWM],
 // is below 54 * 255 / 2^17 < 0.11, and F lies within 2^-7 of an integer (the
 // plan keeps |Sbar| < P 2^-7), so round(F) is exact.  Then Sbar =
 // sum_k (col_k - round(F) P_k) 2^(8k), carried into 16-bit digits.
-template <int NB>
+template <int NB, int PRE = 0>
 __device__ __forceinline__ void crt_group_bytes(const uint8_t *tp, int64_t ps, int nmod,
                                                 const DevPlan *__restrict__ pl,
                                                 int32_t (&d)[NB / 2]) {
@@ -99,28 +99,47 @@ __device__ __forceinline__ void crt_group_bytes(const uint8_t *tp, int64_t ps, i
   constexpr int ND = NB / 2;
   const int nch = (nmod + 3) >> 2;
   // moduli past nmod read the last plane again: their table bytes are zero.
-  // The bytes of the next four moduli are loaded one chunk ahead and packed
-  // only when used.
-  uint32_t bt[4];
-  auto load4 = [&](int c) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int l = 4 * c + e < nmod ? 4 * c + e : nmod - 1;
-      bt[e] = tp[(int64_t)l * ps];
-    }
-  };
+  // PRE = 0: the bytes of the next four moduli are loaded one chunk ahead
+  // and packed only when used (enough with many wavefronts per CU to cover
+  // the latency); PRE > 0 (callers with few wavefronts per CU, nmod <= 4 PRE):
+  // the bytes of all PRE chunks are requested before the first product.
   uint32_t col[NB], F0 = 0, F1 = 0;
 #pragma unroll
   for (int k = 0; k < NB; ++k) col[k] = 0u;
-  load4(0);
-  for (int c = 0; c < nch; ++c) {
-    const uint32_t tw = bt[0] | (bt[1] << 8) | (bt[2] << 16) | (bt[3] << 24);
-    if (c + 1 < nch) load4(c + 1);
+  auto chunk = [&](int c, uint32_t tw) {
     const uint32_t *T = pl->crt4[c];
 #pragma unroll
     for (int k = 0; k < NB; ++k) col[k] = __builtin_amdgcn_udot4(tw, T[k], col[k], false);
     F0 = __builtin_amdgcn_udot4(tw, T[CRT4_NB], F0, false);
     F1 = __builtin_amdgcn_udot4(tw, T[CRT4_NB + 1], F1, false);
+  };
+  if constexpr (PRE > 0) {
+    uint32_t bt[PRE][4];
+#pragma unroll
+    for (int c = 0; c < PRE; ++c)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int l = 4 * c + e < nmod ? 4 * c + e : nmod - 1;
+        bt[c][e] = tp[(int64_t)l * ps];
+      }
+#pragma unroll
+    for (int c = 0; c < PRE; ++c)
+      if (c < nch) chunk(c, bt[c][0] | (bt[c][1] << 8) | (bt[c][2] << 16) | (bt[c][3] << 24));
+  } else {
+    uint32_t bt[4];
+    auto load4 = [&](int c) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int l = 4 * c + e < nmod ? 4 * c + e : nmod - 1;
+        bt[e] = tp[(int64_t)l * ps];
+      }
+    };
+    load4(0);
+    for (int c = 0; c < nch; ++c) {
+      const uint32_t tw = bt[0] | (bt[1] << 8) | (bt[2] << 16) | (bt[3] << 24);
+      if (c + 1 < nch) load4(c + 1);
+      chunk(c, tw);
+    }
   }
   const int32_t q = (int32_t)((F0 + (F1 << 8) + 32768u) >> 16);
   int32_t carry = 0;

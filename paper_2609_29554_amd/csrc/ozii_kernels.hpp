@@ -121,7 +121,7 @@ hipError_t launch_trsv(int nc, int fwd, const double *LU, int64_t lda, double *x
 hipError_t launch_batch(const ozII_batch_item *items, int count, int *queue, uint64_t *times,
                         int grid, hipStream_t s);
 // the same with the blocked LU and the in-workgroup Ozaki-II update (panel
-// width b <= 64); plans at K = b for nc = 2, 3, 4 (null for absent formats),
+// width b <= 256); plans at K = b for nc = 2, 3, 4 (null for absent formats),
 // scratch of `slot` bytes per workgroup
 hipError_t launch_batch_oz(const ozII_batch_item *items, int count, int *queue, uint64_t *times,
                            int grid, const ozk::DevPlan *pl2, const ozk::DevPlan *pl3,

@@ -144,8 +144,8 @@ __device__ __forceinline__ uint32_t mod_times_y(int32_t c, double md, double yd,
 // crt_group_bytes over the t-bytes at tbase + (gi nmod + l) ps (modulus l),
 // the group added at bit w gi to the exact group sum, which is rounded once
 // to NC components of value sum 2^eps (zero: all components 0).  st: CST
-// words of thread-private scratch.
-template <int NC, int NWC, int NB>
+// words of thread-private scratch; PRE: see crt_group_bytes.
+template <int NC, int NWC, int NB, int PRE = 0>
 __device__ __forceinline__ void consume_element_b(const uint8_t *tbase, int64_t ps,
                                                   const DevPlan *__restrict__ pl, uint32_t *st,
                                                   bool zero, int eps, double (&c)[NC]) {
@@ -157,7 +157,7 @@ __device__ __forceinline__ void consume_element_b(const uint8_t *tbase, int64_t 
   for (int k = 0; k < NWC; ++k) cb[k] = 0u;
   for (int gi = 0; gi < ng; ++gi) {
     int32_t d[ND];
-    crt_group_bytes<NB>(tbase + (int64_t)gi * nmod * ps, ps, nmod, pl, d);
+    crt_group_bytes<NB, PRE>(tbase + (int64_t)gi * nmod * ps, ps, nmod, pl, d);
     add_shifted_digits<NWC, ND>(cb, d, w * gi, st);
   }
   if (zero) {

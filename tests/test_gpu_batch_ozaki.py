@@ -4,7 +4,7 @@ blocked LU with the Ozaki-II update at the same block (INT8 plan at K = b)
 and its solve: factors, pivots, info and solutions bit for bit, for DD / TD
 / QD systems whose trailing blocks span several 64-wide tiles with ragged
 edges, systems no larger than one block, a singular system, b = 16 / 32 /
-64, eagerly and replayed from a captured hipGraph."""
+64 / 96 / 128 (one to two 64-wide inner blocks), eagerly and replayed from a captured hipGraph."""
 import numpy as np
 import pytest
 
@@ -54,7 +54,7 @@ def _check(dev, exp, systems):
             assert np.array_equal(to_host(db), X), tag
 
 
-@pytest.mark.parametrize("b", [32, 16, 64])
+@pytest.mark.parametrize("b", [32, 16, 64, 128, 96])
 def test_batch_ozaki_matches_oracle(b):
     import torch
     import paper_2609_29554_amd as Z
@@ -109,7 +109,7 @@ def test_batch_ozaki_rejects_unsupported():
     systems = _systems()[:2]
     dev = _device(systems)
     with pytest.raises(Z.OziiError):
-        ctx().batch_prepare(dev, Z.make_opts(block=128, method=Z.METHOD_OZAKI))
+        ctx().batch_prepare(dev, Z.make_opts(block=320, method=Z.METHOD_OZAKI))
     with pytest.raises(Z.OziiError):
         ctx().batch_prepare(dev, Z.make_opts(block=32, method=Z.METHOD_OZAKI, backend=Z.BE_FP8_B17))
     # the native path still works after a rejected call
