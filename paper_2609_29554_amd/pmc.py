@@ -30,7 +30,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # padding in ozii.cpp also calls for new counter runs)
 KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in
                   ("k_ozaki.hip", "k_limbs.hip", "ozii_elem.hpp", "ozii_bytes.hpp",
-                   "expansion.hpp")]
+                   "ozii_stage.hpp", "expansion.hpp")]
 _KNAME = re.compile(r"(?:^|::|\s)(k_[A-Za-z0-9_]+)\s*(<[^()]*>)?\s*\(")
 
 
