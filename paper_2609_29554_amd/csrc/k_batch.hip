@@ -63,26 +63,42 @@ __device__ bool pivot_column(const ozII_batch_item &it, int64_t j, double (*rkey
       bi = i;
     }
   }
+  // the order is total, so any reduction order gives the same winner: a
+  // butterfly inside each wavefront, then thread 0 over the wavefront winners
 #pragma unroll
-  for (int q = 0; q < NC; ++q) rkey[tid][q] = bk[q];
-  ridx[tid] = bi;
+  for (int off = 32; off > 0; off >>= 1) {
+    double kv[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) kv[q] = __shfl_xor(bk[q], off, 64);
+    const int64_t iv = __shfl_xor(bi, off, 64);
+    if (piv_better<NC>(kv, iv, bk, bi)) {
+#pragma unroll
+      for (int q = 0; q < NC; ++q) bk[q] = kv[q];
+      bi = iv;
+    }
+  }
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) rkey[tid >> 6][q] = bk[q];
+    ridx[tid >> 6] = bi;
+  }
   __syncthreads();
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (tid < s) {
+  if (tid == 0) {
+    for (int wv = 1; wv < NT / 64; ++wv) {
       double ka[NC], kv[NC];
 #pragma unroll
       for (int q = 0; q < NC; ++q) {
-        ka[q] = rkey[tid][q];
-        kv[q] = rkey[tid + s][q];
+        ka[q] = rkey[0][q];
+        kv[q] = rkey[wv][q];
       }
-      if (piv_better<NC>(kv, ridx[tid + s], ka, ridx[tid])) {
+      if (piv_better<NC>(kv, ridx[wv], ka, ridx[0])) {
 #pragma unroll
-        for (int q = 0; q < NC; ++q) rkey[tid][q] = kv[q];
-        ridx[tid] = ridx[tid + s];
+        for (int q = 0; q < NC; ++q) rkey[0][q] = kv[q];
+        ridx[0] = ridx[wv];
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
   const int64_t p = ridx[0];
   bool zero = true;
 #pragma unroll
@@ -117,7 +133,7 @@ __device__ bool pivot_column(const ozII_batch_item &it, int64_t j, double (*rkey
 }
 
 template <int NC, int NT>
-__device__ void solve_one(const ozII_batch_item &it);
+__device__ void solve_one(const ozII_batch_item &it, double (*rr)[4]);
 
 template <int NC>
 __device__ void lu_solve_one(const ozII_batch_item &it, double (*rkey)[4], int64_t *ridx,
@@ -145,14 +161,16 @@ __device__ void lu_solve_one(const ozII_batch_item &it, double (*rkey)[4], int64
     __syncthreads();
   }
   if (tid == 0) *it.info = *s_info;
-  solve_one<NC, BT>(it);
+  solve_one<NC, BT>(it, rkey);
 }
 
 // The solve with the factors: interchanges in ipiv order, forward (unit L,
 // ascending), backward with the reciprocals 1 / u_kk (descending), as
-// ozII_getrs does for one right-hand side.
+// ozII_getrs does for one right-hand side.  The reciprocals do not depend on
+// the right-hand side: they are formed NT at a time, in parallel, in rr
+// (NT x 4 doubles of LDS).
 template <int NC, int NT>
-__device__ void solve_one(const ozII_batch_item &it) {
+__device__ void solve_one(const ozII_batch_item &it, double (*rr)[4]) {
   if (!it.b) return;
   const int tid = threadIdx.x;
   const int64_t n = it.n;
@@ -184,12 +202,24 @@ __device__ void solve_one(const ozII_batch_item &it) {
     __syncthreads();
   }
   for (int64_t k = n - 1; k >= 0; --k) {
-    if (tid == 0) {
-      double one[NC], u[NC], r[NC], xk[NC], o[NC];
+    const int64_t top = k - (n - 1 - k) % NT;  // lowest row of k's chunk of reciprocals
+    const int64_t lo = top - NT + 1 > 0 ? top - NT + 1 : 0;
+    if ((n - 1 - k) % NT == 0) {
+      for (int64_t i = lo + tid; i <= k; i += NT) {
+        double one[NC], u[NC], r[NC];
 #pragma unroll
-      for (int q = 0; q < NC; ++q) one[q] = q == 0 ? 1.0 : 0.0;
-      ozx::load<NC>(E(k, k), u);
-      ozx::div<NC>(one, u, r);
+        for (int q = 0; q < NC; ++q) one[q] = q == 0 ? 1.0 : 0.0;
+        ozx::load<NC>(E(i, i), u);
+        ozx::div<NC>(one, u, r);
+#pragma unroll
+        for (int q = 0; q < NC; ++q) rr[i - lo][q] = r[q];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      double r[NC], xk[NC], o[NC];
+#pragma unroll
+      for (int q = 0; q < NC; ++q) r[q] = rr[k - lo][q];
       ozx::load<NC>(x + k * NC, xk);
       ozx::mul<NC>(xk, r, o);
       ozx::store<NC>(x + k * NC, o);
@@ -396,7 +426,7 @@ __device__ __forceinline__ void lu_solve_oz(const ozII_batch_item &it, double (*
     }
   }
   if (tid == 0) *it.info = *s_info;
-  solve_one<NC, NT>(it);
+  solve_one<NC, NT>(it, rkey);
 }
 
 // One workgroup of BTZ threads per CU (the update's stages need more than

@@ -116,3 +116,25 @@ def test_batch_ozaki_rejects_unsupported():
     ctx().batch_prepare(dev)
     ctx().batch_run()
     ctx().sync_check()
+
+
+def test_batch_ozaki_full_workload_sampled():
+    """The benchmarked workload itself -- 256 systems, n uniform in [64, 512],
+    half DD half QD, b = 64, one persistent launch -- with the largest QD and
+    DD systems and four others checked against the oracle bit for bit."""
+    import torch
+    import paper_2609_29554_amd as Z
+    note("batched Ozaki-II LU, 256 systems, sampled against the oracle")
+    rng = np.random.default_rng(20260934)
+    systems = W.batch_systems(256, rng)
+    dev = _device(systems)
+    ctx().batch_prepare(dev, Z.make_opts(block=64, method=Z.METHOD_OZAKI))
+    ctx().batch_run()
+    ctx().sync_check()
+    ns = [(i, nc, A.shape[0]) for i, (nc, A, _) in enumerate(systems)]
+    pick = {max((x for x in ns if x[1] == 4), key=lambda x: x[2])[0],
+            max((x for x in ns if x[1] == 2), key=lambda x: x[2])[0]}
+    pick |= set(np.random.default_rng(5).choice(len(systems), 4, replace=False).tolist())
+    sub = [systems[i] for i in sorted(pick)]
+    _check([dev[i] for i in sorted(pick)], _expected(sub, 64), sub)
+    assert all(int(to_host(d[3])[0]) == 0 for d in dev)
