@@ -787,8 +787,9 @@ __global__ __launch_bounds__(256) void k_apply_ipiv(double *B, int64_t ldb, int6
 // finished positions (agent release, then the counter).  Waits are bounded
 // like the panel's.
 // ---------------------------------------------------------------------------
-constexpr int TRSV_R = 16;  // rows per workgroup
-constexpr int TRSV_B = 32;  // solution values applied per batch
+constexpr int TRSV_R = 32;    // rows per workgroup
+constexpr int TRSV_B = 32;    // solution values applied per batch
+constexpr int TRSV_PUB = 4;   // rows of the diagonal block published at a time
 
 template <int NC, bool FWD>
 __global__ __launch_bounds__(256) void k_trsv(const double *LU, int64_t lda, double *x,
@@ -858,7 +859,9 @@ __global__ __launch_bounds__(256) void k_trsv(const double *LU, int64_t lda, dou
     }
     applied = avail;
   }
-  // the diagonal block
+  // the diagonal block; every TRSV_PUB rows the final values are published
+  // (stored, then the count raised after a release fence), so the next
+  // workgroup can apply them while this one continues
   for (int q = 0; q < cnt; ++q) {
     if (!FWD) {
       if (tid == 0) {
@@ -872,6 +875,8 @@ __global__ __launch_bounds__(256) void k_trsv(const double *LU, int64_t lda, dou
       }
       __syncthreads();
     }
+    // row q is final
+    if (tid < NC) x[row(p0 + q) * NC + tid] = xs[q][tid];
     const int r = q + 1 + tid;
     if (r < cnt) {
       double v[NC], a[NC], y[NC], o[NC];
@@ -885,14 +890,17 @@ __global__ __launch_bounds__(256) void k_trsv(const double *LU, int64_t lda, dou
 #pragma unroll
       for (int e = 0; e < NC; ++e) xs[r][e] = o[e];
     }
-    __syncthreads();
-  }
-  if (tid < cnt * NC) x[row(p0 + tid / NC) * NC + tid % NC] = (&xs[0][0])[tid];
-  __builtin_amdgcn_s_waitcnt(0x0F70);
-  __syncthreads();
-  if (tid == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_store(ready, (uint32_t)(p0 + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((q + 1) % TRSV_PUB == 0 || q + 1 == cnt) {
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // this thread's stores have completed
+      __syncthreads();
+      if (tid == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(ready, (uint32_t)(p0 + q + 1), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      }
+    } else {
+      __syncthreads();
+    }
   }
 }
 
