@@ -554,11 +554,14 @@ __global__ __launch_bounds__(256) void k_trsm_lower_unit_rc(const double *Lp, in
   const int tid = threadIdx.x, i = tid % ROWS, cc = tid / ROWS;
   const int64_t c = (int64_t)blockIdx.x * CPB + cc;
   const bool mine = i < kb && c < ncols;
-  double x[NC];
+  double x[NC], l[NC];
   if (mine) ozx::load<NC>(Xp + (i + c * ldx) * NC, x);
   else
 #pragma unroll
     for (int q = 0; q < NC; ++q) x[q] = 0.0;
+  // l_(i,h) of the next step is loaded while this step's multiply-subtract
+  // runs, so no load waits behind the barrier
+  if (mine && i > 0) ozx::load<NC>(Lp + i * NC, l);
   for (int h = 0; h < kb; ++h) {
     const int b = h & 1;
     if (i == h) {
@@ -567,13 +570,17 @@ __global__ __launch_bounds__(256) void k_trsm_lower_unit_rc(const double *Lp, in
     }
     __syncthreads();
     if (mine && i > h) {
-      double l[NC], u[NC], o[NC];
-      ozx::load<NC>(Lp + (i + (int64_t)h * lda) * NC, l);
+      double ln[NC], u[NC], o[NC];
+      const bool more = h + 1 < i;
+      if (more) ozx::load<NC>(Lp + (i + (int64_t)(h + 1) * lda) * NC, ln);
 #pragma unroll
       for (int q = 0; q < NC; ++q) u[q] = xs[b][cc][q];
       ozx::fms<NC>(x, l, u, o);
 #pragma unroll
       for (int q = 0; q < NC; ++q) x[q] = o[q];
+      if (more)
+#pragma unroll
+        for (int q = 0; q < NC; ++q) l[q] = ln[q];
     }
   }
   if (mine) ozx::store<NC>(Xp + (i + c * ldx) * NC, x);
