@@ -27,6 +27,24 @@ constexpr int BT = 1024;  // threads per workgroup (4 wavefronts per SIMD)
 constexpr int BTZ = 512;  // the same for the Ozaki-II update
 constexpr int BZ_PRE = 10; // t-byte chunks requested at once by its CRT (nmod <= 40)
 
+// The elements idx = t, t + NT, t + 2 NT, ... of a rectangle with mr > 0 rows
+// taken column by column, (i, c) = (idx % mr, idx / mr), with one division
+// per thread instead of one per element.
+template <int NT>
+struct ColWalk {
+  int32_t i, c, di, dc, mr;
+  __device__ ColWalk(int32_t rows, int32_t t)
+      : i(t % rows), c(t / rows), di(NT % rows), dc(NT / rows), mr(rows) {}
+  __device__ void next() {
+    i += di;
+    c += dc;
+    if (i >= mr) {
+      i -= mr;
+      ++c;
+    }
+  }
+};
+
 // largest |value| first, then the lower row index (a total order)
 template <int NC>
 __device__ __forceinline__ bool piv_better(const double (&kb_)[NC], int64_t ib,
@@ -149,8 +167,9 @@ __device__ void lu_solve_one(const ozII_batch_item &it, double (*rkey)[4], int64
     // rank-1 update of the trailing matrix (also after a zero pivot, with the
     // unscaled -- all-zero -- column, as the blocked LU with b = 1 does)
     const int64_t m = n - j - 1;
-    for (int64_t idx = tid; idx < m * m; idx += BT) {
-      const int64_t i = j + 1 + idx % m, c = j + 1 + idx / m;
+    ColWalk<BT> wk((int32_t)(m > 0 ? m : 1), tid);
+    for (int64_t idx = tid; idx < m * m; idx += BT, wk.next()) {
+      const int64_t i = j + 1 + wk.i, c = j + 1 + wk.c;
       double a[NC], l[NC], u[NC], o[NC];
       ozx::load<NC>(E(i, c), a);
       ozx::load<NC>(E(i, j), l);
