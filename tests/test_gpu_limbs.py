@@ -109,3 +109,46 @@ def test_gemm_limbs_k_zero_and_errors():
     assert not got[0].any() and (got[1] == OL.EXP_ZERO).all() and not got[2].any()
     with pytest.raises(Z.OziiError):
         ctx().gemm_limbs(0, _dev(A), _dev(B), _dev(C0), Z.make_opts(backend=Z.BE_FP8_B17))
+
+
+def test_limb_schur_first_update_p4096_full_size_sampled():
+    """The first Schur update of the limb benchmark in its launch
+    configuration -- the Lotkin matrix n = 2048 at p = 4096 (64 limbs),
+    C = RN_p(C - RN_p(A B)) with M = N = 1792, K = 256, on sub-block
+    descriptors of the whole matrix in device memory -- with 16 outputs
+    checked against the limb oracle, which needs only their rows of A and
+    columns of B (exponents are per row of A and per column of B)."""
+    import ctypes
+    import torch
+    import paper_2609_29554_amd as Z
+    n, b, nl = 2048, 256, 64
+    note("limb Schur update p=4096, 1792 x 1792 x 256, sampled")
+    limb, ex, sg = W.lotkin_limbs(n, nl)
+    dl = torch.from_numpy(limb.view(np.int64)).cuda()
+    de = torch.from_numpy(ex).cuda()
+    ds = torch.from_numpy(sg).cuda()
+
+    def desc(r0, c0):
+        off = r0 + c0 * n
+        return Z.Limbs(dl.data_ptr() + 8 * off, de.data_ptr() + 4 * off, ds.data_ptr() + off, n,
+                       n * n)
+
+    c = ctx()
+    c._bind()
+    A, B, Cd = desc(b, 0), desc(0, b), desc(b, b)
+    c._call(Z.lib().ozII_gemm_limbs(c._h, 1, nl, n - b, n - b, b, ctypes.byref(A), ctypes.byref(B),
+                                    ctypes.byref(Cd), None))
+    c.sync_check()
+    rows = np.array([0, 1, 900, n - b - 1])
+    cols = np.array([0, 2, 1000, n - b - 1])
+
+    def sub(r, cc):
+        return tuple(np.ascontiguousarray(x[..., cc, :][..., r]) for x in (limb, ex, sg))
+
+    want, _ = OL.ozgemm(1, sub(b + rows, np.arange(b)), sub(np.arange(b), b + cols),
+                        sub(b + rows, b + cols), O.make_plan(64 * nl, b))
+    ci, ri = torch.from_numpy(b + cols).cuda(), torch.from_numpy(b + rows).cuda()
+    got = (dl[:, ci][:, :, ri].cpu().numpy().view(np.uint64), de[ci][:, ri].cpu().numpy(),
+           ds[ci][:, ri].cpu().numpy())
+    for g, w_, name in zip(got, want, ("limbs", "exp", "sign")):
+        assert np.array_equal(g, w_), name

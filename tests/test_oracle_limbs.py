@@ -204,3 +204,16 @@ def test_rn_fraction_matches_correct_rounding_at_53_bits():
     for m in range(1 << 52, (1 << 52) + 64):
         x = Fraction(2 * m + 1, 2)
         assert frac_of(OL.rn_fraction(x, 53)) == Fraction(float(x))
+
+
+def test_limb_generators_return_the_device_layout():
+    """Limb matrices go to the device as flat copies addressed plane by plane
+    (limb q of element (i, j) at q rows cols + i + j rows), so the seeded
+    generators must hand out C-contiguous (nlimb, cols, rows) arrays."""
+    for L in (W.lotkin_limbs(9, 3), W.random_limbs(5, 7, 3, np.random.default_rng(1))):
+        limb, ex, sg = L
+        assert all(x.flags["C_CONTIGUOUS"] for x in L)
+        flat = limb.reshape(-1)
+        nl, cols, rows = limb.shape
+        for q, j, i in ((0, 0, 0), (nl - 1, cols - 1, rows - 1), (1, 2, 3)):
+            assert flat[q * rows * cols + i + j * rows] == limb[q, j, i]

@@ -209,7 +209,9 @@ def lotkin_limbs(n: int, nlimb: int):
     ii = np.arange(n)[None, :]
     jj = np.arange(n)[:, None]
     dd = np.where(ii == 0, 1, ii + jj + 1)          # (cols, rows)
-    limb = table[:, dd]
+    # plane-major and C-contiguous, as the device layout (fancy indexing alone
+    # would leave the limb index fastest in memory)
+    limb = np.ascontiguousarray(table[:, dd])
     e = texp[dd]
     sign = np.zeros((n, n), dtype=np.uint8)
     return limb, e, sign
