@@ -3,6 +3,10 @@
 * QD Lotkin LU, n = 2048, b = 256 (the bench workload): pivots, info and a
   SHA-256 of the whole factor array and of the solution must equal the values
   the oracle wrote into tests/golden/ (bit-exact for every element).
+* QD Lotkin LU, n = 1024, b = 128, on each Schur-update back-end (INT8,
+  FP8 base-17, binary64 moduli) and the native update: the whole factor
+  array, pivots, info and solution against the oracle LU with that
+  back-end's plan, bit for bit.
 * Standalone TD product, m = n = k = 4096 (the MFMA-bound workload): every
   output element depends only on its row of A and column of B (the shared
   exponents are per row / per column), so the oracle evaluates sampled rows
@@ -76,3 +80,29 @@ def test_gemm_td4096_sampled(mode):
     want, _ = O.ozgemm(mode, Asub, Bsub, Csub0, pl)
     got = C[cols][:, rows, :]
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("backend", ["int8", "fp8", "f64", "native"])
+def test_lu_lotkin_qd1024_backends_match_oracle(backend):
+    import paper_2609_29554_amd as Z
+    n, b, nc = 1024, 128, 4
+    note(f"full-size LU Lotkin n={n} b={b} nc={nc} update={backend}")
+    A = W.lotkin(n, nc)
+    rhs = W.rhs_ones(A)
+    if backend == "native":
+        LU, ipiv, info, _ = O.getrf(A, b, O.METHOD_NAIVE)
+        method, opts = Z.METHOD_NAIVE, None
+    else:
+        be = {"int8": O.BACKEND_INT8, "fp8": O.BACKEND_FP8_B17, "f64": O.BACKEND_F64MOD}[backend]
+        LU, ipiv, info, _ = O.getrf(A, b, O.METHOD_OZAKI, plan=O.make_plan(53 * nc, b, backend=be))
+        method, opts = Z.METHOD_OZAKI, Z.make_opts(backend=be)
+    X = O.getrs(LU, ipiv, rhs)
+    dA = to_dev(A)
+    dip, dinfo = ctx().getrf(dA, block=b, method=method, opts=opts)
+    dx = to_dev(rhs)
+    ctx().getrs(dA, dip, dx)
+    ctx().sync_check()
+    assert int(to_host(dinfo)[0]) == info
+    assert np.array_equal(to_host(dip), ipiv)
+    assert np.array_equal(to_host(dA), LU)
+    assert np.array_equal(to_host(dx), X)
