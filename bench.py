@@ -165,8 +165,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the LU would shard 2D block-cyclic; see DESIGN.md). Run with --gpus 1.",
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(the LU would shard 2D block-cyclic over a process grid). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 

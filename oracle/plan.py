@@ -9,7 +9,7 @@ width w, the fixed-point width Q = w*S and the number of moduli N_mod
 Prop. 2), and the CRT constants of Eq. (crt): P = prod m_l, M_l = P/m_l,
 y_l = M_l^{-1} mod m_l.
 
-Readings taken where the paper is terse (each is listed in the design doc):
+Readings taken where the paper is terse:
   * modulus set: the 54 largest prime powers not exceeding 256, in descending
     order (Sec. 3.2 says 54 moduli and 362.8 bits; only the set containing 256
     gives both, and it reproduces every printed GEMM/moduli count);
