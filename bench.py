@@ -343,6 +343,7 @@ def main():
         "correct_bits": bits,
         "backend_sweep": sweep,
     }
+    ctx.close()
     print(json.dumps(out))
 
 
@@ -537,6 +538,7 @@ def bench_batch(args):
            "completion_ms": oz["completion_ms"],
            "nonzero_info": oz["nonzero_info"],
            "native_update": dict(nat, config="unblocked LU, native expansion update")}
+    ctx.close()
     print(json.dumps(out))
 
 
@@ -580,6 +582,7 @@ def bench_schur(args):
                       "shapes": shapes},
            "stages": {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps}
                       for k, v in prof.items() if v[1]}}
+    ctx.close()
     print(json.dumps(out))
 
 
@@ -644,6 +647,7 @@ def bench_gemm(args):
         "effective_gflops_td": 2.0 * n ** 3 / sec / 1e9,
         "stages": {k: {"ms_per_step": v[0] / K} for k, v in prof.items() if v[1]},
     }
+    ctx.close()
     print(json.dumps(out))
 
 
@@ -769,6 +773,7 @@ def bench_limb_schur(args):
            "stages": {k: {"ms_per_step": v[0] / args.steps,
                           "launches_per_step": v[1] / args.steps}
                       for k, v in prof.items() if v[1]}}
+    ctx.close()
     if not args.no_cpu_baseline:
         log("cpu baseline (limb oracle sample)")
         out["cpu_baseline"] = limb_cpu_baseline(nl, shapes)

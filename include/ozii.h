@@ -145,6 +145,17 @@ ozII_status ozII_gemm_limbs(ozII_handle h, int32_t mode, int32_t nlimb, int64_t 
                             int64_t K, const ozII_limbs *A, const ozII_limbs *B, ozII_limbs *C,
                             const ozII_opts *o);
 
+/* ozII_gemm_limbs with the group sums of (S5) copied out (parity hook):
+ * sbar (device, may be null) receives, per retained digit group gi and
+ * element (i, j), Sbar_(g0+gi) of Eq. (crt) as nlimb_out (1..6) 64-bit
+ * two's-complement limbs, layout [ng][N][M][nlimb_out], computed by the CRT
+ * routine the limb consumer itself runs.  Errors: those of
+ * ozII_gemm_limbs; OZII_EINVAL for nlimb_out outside 1..6. */
+ozII_status ozII_gemm_limbs_stages(ozII_handle h, int32_t mode, int32_t nlimb, int64_t M,
+                                   int64_t N, int64_t K, const ozII_limbs *A,
+                                   const ozII_limbs *B, ozII_limbs *C, const ozII_opts *o,
+                                   uint64_t *sbar, int32_t nlimb_out);
+
 /* Same product with the intermediate stages copied out (parity hooks); any
  * output pointer may be null.  Sizes follow ozII_gemm_stage_dims:
  *   ea[M], eb[N]     (S1) row / column exponents (INT32_MIN for zero);
@@ -161,8 +172,11 @@ ozII_status ozII_gemm_limbs(ozII_handle h, int32_t mode, int32_t nlimb, int64_t 
  *                            spans 8 k (lane l: k l/16 and 4 + l/16);
  *   tpl              (S4) t-planes [ng][nmod][Np][Mp], uint8 (INT8, FP8) or
  *                    uint32 (F64);
- *   sbar             (S5) group sums, nlimb 64-bit two's-complement limbs per
- *                    element, layout [ng][N][M][nlimb]. */
+ *   sbar             (S5) group sums, nlimb (1..6) 64-bit two's-complement
+ *                    limbs per element, layout [ng][N][M][nlimb], computed by
+ *                    the CRT routine of the consumer that reads these
+ *                    t-planes (the byte-column CRT for INT8 and FP8, the
+ *                    binary64 CRT for binary64 moduli). */
 ozII_status ozII_gemm_stages(ozII_handle h, int32_t mode, int32_t nc, int64_t M, int64_t N,
                              int64_t K, const double *A, int64_t lda, const double *B,
                              int64_t ldb, double *C, int64_t ldc, const ozII_opts *o,
@@ -179,22 +193,35 @@ ozII_status ozII_gemm_stage_dims(int32_t nc, int64_t M, int64_t N, int64_t K, co
 ozII_status ozII_getrf(ozII_handle h, int32_t nc, int64_t n, double *A, int64_t lda,
                        int64_t *ipiv, int32_t *info, const ozII_opts *o);
 
-/* Solve A X = B from getrf's factors: interchanges in ipiv order, forward
- * substitution with unit L (ascending order per element), backward
- * substitution with U (descending order, then division by u_ii).  B is
- * n x nrhs (ldb >= n), overwritten by X. */
+/* Solve A X = B from getrf's factors by forward and backward substitution
+ * (Sec. 4.3, the solve of the Lotkin experiment; P A = L U of Sec. 3.4):
+ * the interchanges ipiv[0..n) applied to B in order (LAPACK's laswp), then
+ * forward substitution with the unit lower factor (element i takes
+ * x_i (+) -(l_ik (x) x_k) for k ascending) and backward substitution with the
+ * upper factor (element i takes x_i (+) -(u_ik (x) x_k) for k descending;
+ * x_k is divided by u_kk with the expansion division once all of its
+ * updates are in).  LU is the n x n output of ozII_getrf (lda >= n), ipiv
+ * its pivot vector (device int64, n entries, 0-based), B is n x nrhs
+ * (ldb >= n), overwritten by X; all device memory owned by the caller.  An
+ * exactly zero u_kk (info > 0 from getrf) gives non-finite components, as
+ * the division of the specification does.  Errors: OZII_EINVAL (null
+ * pointers, negative sizes, leading dimensions below n), OZII_EUNSUPPORTED
+ * (nc outside 2..4); OZII_EDEVICE is reported by ozII_sync_check if a
+ * bounded wait of the pipelined one-column solve timed out. */
 ozII_status ozII_getrs(ozII_handle h, int32_t nc, int64_t n, int64_t nrhs, const double *LU,
                        int64_t lda, const int64_t *ipiv, double *B, int64_t ldb);
 
 /* Batched LU + solve of many independent small systems in one persistent
- * launch.  Each item is an n x n matrix of nc-component expansions
- * (column-major, lda = n, device memory, factored in place), an optional
- * right-hand side b of n expansions (device; overwritten by the solution),
- * ipiv (device, n entries, 0-based LAPACK semantics) and info (device, one
- * int32).  Items may mix DD / TD / QD and orders.  Every item is factored by
- * one workgroup with the unblocked right-looking LU (partial pivoting) and
- * the native expansion update -- per element the operations of ozII_getrf
- * with block = 1, method = native -- then solved as ozII_getrs does.
+ * launch: per system the LU with partial pivoting of Sec. 3.4 and the solve
+ * by forward and backward substitution of Sec. 4.3.  Each item is an n x n
+ * matrix of nc-component expansions (column-major, lda = n, device memory,
+ * factored in place), an optional right-hand side b of n expansions
+ * (device; overwritten by the solution), ipiv (device, n entries, 0-based
+ * LAPACK semantics) and info (device, one int32).  Items may mix DD / TD /
+ * QD and orders.  Every item is factored by one workgroup with the
+ * unblocked right-looking LU (partial pivoting) and the native expansion
+ * update -- per element the operations of ozII_getrf with block = 1,
+ * method = native -- then solved as ozII_getrs does.
  *
  * ozII_batch_prepare (host, synchronous) validates the items, orders them by
  * decreasing cost nc n^3 (longest first) and uploads the table into
@@ -203,8 +230,9 @@ ozII_status ozII_getrs(ozII_handle h, int32_t nc, int64_t n, int64_t nrhs, const
  * allocates nothing and may be captured in a hipGraph.  times (device, may be
  * null) receives 2 per item in the caller's item order: the 100 MHz
  * real-time counter when its workgroup started and when it finished.
+ * The caller's buffers must stay allocated while the batch is in use.
  * Errors: OZII_EINVAL for a bad item (nc outside 2..4, n < 1 or > 4096, null
- * A/ipiv/info). */
+ * A/ipiv/info); OZII_ENOMEM when the table cannot be allocated. */
 typedef struct {
   int32_t nc;
   int32_t reserved;

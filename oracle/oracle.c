@@ -873,20 +873,15 @@ void orc_getrf(int nc, int64_t n, double *A, int64_t ld, int64_t b, int method,
     }
 }
 
-/* Solve A X = B from the factors: row interchanges in ipiv order, forward
- * substitution with unit L (element i updated for k ascending), backward
- * substitution with U (element i updated for k descending, then multiplied
- * by the expansion reciprocal 1/u_ii when its turn comes; the reciprocals
- * are independent of the right-hand side).  B is n x nrhs column-major. */
+/* Solve A X = B from the factors (Sec. 4.3: forward and backward
+ * substitution): row interchanges in ipiv order; forward substitution with
+ * unit L, element i updated for k ascending; backward substitution with U,
+ * element i updated for k descending, and x_k divided by u_kk (the expansion
+ * division of the specification) once all its updates are in.  B is
+ * n x nrhs column-major. */
 void orc_getrs(int nc, int64_t n, const double *LU, int64_t ld, const int64_t *ipiv,
                int64_t nrhs, double *B, int64_t ldb) {
     for (int64_t j = 0; j < n; ++j) swap_rows(nc, B, ldb, j, ipiv[j], 0, nrhs);
-    double *rinv = (double *)malloc(sizeof(double) * nc * (n > 0 ? n : 1));
-#pragma omp parallel for schedule(static)
-    for (int64_t k = 0; k < n; ++k) {
-        double one[MAXNC] = {1.0, 0.0, 0.0, 0.0};
-        orc_div(nc, one, LU + (k + k * ld) * nc, rinv + k * nc);
-    }
 #pragma omp parallel for schedule(static)
     for (int64_t r = 0; r < nrhs; ++r) {
         double *x = B + r * ldb * nc, t[MAXNC];
@@ -896,7 +891,7 @@ void orc_getrs(int nc, int64_t n, const double *LU, int64_t ld, const int64_t *i
                 for (int q = 0; q < nc; ++q) x[i * nc + q] = t[q];
             }
         for (int64_t k = n - 1; k >= 0; --k) {
-            orc_mul(nc, x + k * nc, rinv + k * nc, t);
+            orc_div(nc, x + k * nc, LU + (k + k * ld) * nc, t);
             for (int q = 0; q < nc; ++q) x[k * nc + q] = t[q];
             for (int64_t i = 0; i < k; ++i) {
                 orc_fms(nc, x + i * nc, LU + (i + k * ld) * nc, x + k * nc, t);
@@ -904,5 +899,4 @@ void orc_getrs(int nc, int64_t n, const double *LU, int64_t ld, const int64_t *i
             }
         }
     }
-    free(rinv);
 }

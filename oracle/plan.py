@@ -25,6 +25,17 @@ Readings taken where the paper is terse:
     factor 4 that centred residues would allow.  With at most 20 moduli this
     reproduces the printed DD/TD/QD GEMM counts 13/18/36 at K=512 (any cap
     from 18 to 21 does; the bound with the factor 4 gives 17 for TD).
+
+PARITY UNPINNED (binary64 modulus set): the cap of 20 is fitted to the three
+printed counts above, not taken from the paper, and the rule does not
+reproduce Table backend_hp (p = 1024 .. 16384 at K = 512), whose binary64
+column prints 15, 16, 16, 16, 16 moduli at the INT8 slice counts (this rule
+gives 18, 20, 20, 20, 20 at its own smaller slice counts).  Eq. fp64mod
+applied per pair (K (m/2)^2 < 2^53, the INT8 slice count) gives 14, 15, 16,
+16, 16: close but not equal either.  What is pinned is independent of the
+set: the binary64 back-end's products, group sums and factors equal the
+INT8 back-end's bit for bit at equal (S, w), because every group sum is an
+exact integer either way.
 """
 from __future__ import annotations
 

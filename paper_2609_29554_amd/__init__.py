@@ -10,8 +10,11 @@ column-major array of nc-component expansions that the C ABI expects
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
+import weakref
 from typing import Optional, Tuple
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -41,7 +44,8 @@ _i64 = C.c_int64
 _i32 = C.c_int32
 
 EXPORTED = ["ozII_create", "ozII_destroy", "ozII_set_stream", "ozII_plan_query", "ozII_reserve",
-            "ozII_gemm", "ozII_gemm_limbs", "ozII_gemm_stages", "ozII_gemm_stage_dims",
+            "ozII_gemm", "ozII_gemm_limbs", "ozII_gemm_limbs_stages", "ozII_gemm_stages",
+            "ozII_gemm_stage_dims",
             "ozII_getrf", "ozII_getrs",
             "ozII_batch_prepare", "ozII_batch_prepare_ex", "ozII_batch_run", "ozII_tune",
             "ozII_stream_of",
@@ -78,6 +82,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        # torch first: PyTorch ships its own HIP runtime under the same soname,
+        # and the library must bind to that one.  Loaded first, the library
+        # would pull in the system runtime and torch its own, and two HIP
+        # runtimes in one process do not share devices, memory or streams.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         OP = C.POINTER(Opts)
         L.ozII_create.argtypes = [C.POINTER(_p), C.c_int, _p]
@@ -89,6 +98,8 @@ def lib():
         L.ozII_gemm.argtypes = [_p, _i32, _i32, _i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, OP]
         LP = C.POINTER(Limbs)
         L.ozII_gemm_limbs.argtypes = [_p, _i32, _i32, _i64, _i64, _i64, LP, LP, LP, OP]
+        L.ozII_gemm_limbs_stages.argtypes = [_p, _i32, _i32, _i64, _i64, _i64, LP, LP, LP, OP,
+                                             _p, _i32]
         L.ozII_gemm_stages.argtypes = [_p, _i32, _i32, _i64, _i64, _i64, _p, _i64, _p, _i64, _p,
                                        _i64, OP, _p, _p, _p, _p, _p, _p, _i32]
         L.ozII_gemm_stage_dims.argtypes = [_i32, _i64, _i64, _i64, OP, C.POINTER(_i64),
@@ -139,13 +150,78 @@ def _check_mat(t, nc: Optional[int] = None):
     import torch
     if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.dim() == 3):
         raise ValueError("expected a contiguous float64 CUDA tensor of shape (cols, rows, nc)")
+    if t.shape[2] not in (2, 3, 4):
+        raise ValueError("expansions have 2, 3 or 4 components")
     if nc is not None and t.shape[2] != nc:
         raise ValueError("component count mismatch")
 
 
+def _check_vec(t, dtype, length: int, name: str):
+    """A contiguous CUDA vector of `dtype` with at least `length` entries."""
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous() and t.dim() == 1):
+        raise ValueError(f"{name}: expected a contiguous 1-D {dtype} CUDA tensor")
+    if t.numel() < length:
+        raise ValueError(f"{name}: needs at least {length} entries, has {t.numel()}")
+
+
+def _check_square(A, name: str):
+    _check_mat(A)
+    if A.shape[0] != A.shape[1]:
+        raise ValueError(f"{name} must be square: shape (n, n, nc)")
+
+
+def check_getrs_args(LU, ipiv, B):
+    """Validate the operands of a solve before they reach the C ABI (a
+    mismatched pivot vector or right-hand side would be read out of
+    bounds on the device)."""
+    import torch
+    _check_square(LU, "LU")
+    n, nc = LU.shape[0], LU.shape[2]
+    _check_mat(B, nc)
+    if B.shape[1] != n:
+        raise ValueError("B must have shape (nrhs, n, nc)")
+    _check_vec(ipiv, torch.int64, n, "ipiv")
+    if not (LU.device == B.device == ipiv.device):
+        raise ValueError("LU, ipiv and B must be on the same device")
+
+
+def check_batch_item(A, b, ipiv, info):
+    """Validate one system of a batch: A (n, n, nc) float64, b None or
+    (1, n, nc) float64, ipiv int64[n], info int32[1], all contiguous CUDA
+    tensors on one device."""
+    import torch
+    _check_square(A, "A")
+    n, nc = A.shape[0], A.shape[2]
+    if n < 1 or n > 4096:
+        raise ValueError("batched systems have 1 <= n <= 4096")
+    if b is not None:
+        _check_mat(b, nc)
+        if tuple(b.shape) != (1, n, nc):
+            raise ValueError("b must have shape (1, n, nc)")
+    _check_vec(ipiv, torch.int64, n, "ipiv")
+    _check_vec(info, torch.int32, 1, "info")
+    devs = {A.device, ipiv.device, info.device} | ({b.device} if b is not None else set())
+    if len(devs) != 1:
+        raise ValueError("the tensors of a system must be on one device")
+
+
+_LIVE = weakref.WeakSet()
+
+
+def close_all():
+    """Destroy every open handle (registered with atexit, so the library's
+    device memory is released while the HIP runtime is still fully up)."""
+    for c in list(_LIVE):
+        c.close()
+
+
+atexit.register(close_all)
+
+
 class Context:
     """A libozii handle bound to one device and (by default) torch's current
-    stream on it."""
+    stream on it.  Close it explicitly (or use it as a context manager); an
+    open handle is closed at interpreter exit by close_all()."""
 
     def __init__(self, device: int = 0):
         import torch
@@ -155,6 +231,14 @@ class Context:
         st = lib().ozII_create(C.byref(self._h), device, self._stream())
         if st != OK:
             raise OziiError(st, "ozII_create failed")
+        _LIVE.add(self)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
     @staticmethod
     def _stream():
@@ -173,8 +257,14 @@ class Context:
         if self._h:
             lib().ozII_destroy(self._h)
             self._h = _p()
+        _LIVE.discard(self)
 
     def __del__(self):
+        # no HIP calls while the interpreter shuts down: the runtime (and a
+        # profiler attached to it) may already be gone; close_all() has run
+        # by then for every handle that was still open
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -198,11 +288,8 @@ class Context:
                                    max(K, 1), _ptr(Cm), max(M, 1), C.byref(opts) if opts else None))
         return Cm
 
-    def gemm_limbs(self, mode: int, A, B, Cm, opts: Optional[Opts] = None):
-        """Limb-format product, mode 0: C = RN_p(A B); mode 1: C = RN_p(C - RN_p(A B)).
-        Each matrix is a tuple (limb, exp, sign) of contiguous CUDA tensors of
-        shapes (nlimb, cols, rows) int64 (the uint64 limbs), (cols, rows) int32
-        and (cols, rows) uint8."""
+    @staticmethod
+    def _limb_shapes(A, B, Cm):
         import torch
         nl = A[0].shape[0]
         for X in (A, B, Cm):
@@ -218,17 +305,43 @@ class Context:
         N = B[0].shape[1]
         if B[0].shape[2] != K or Cm[0].shape[1] != N or Cm[0].shape[2] != M:
             raise ValueError("shape mismatch")
+        return nl, M, N, K
 
-        def desc(X):
-            lb, ex, sg = X
-            rows, cols = lb.shape[2], lb.shape[1]
-            return Limbs(_ptr(lb), _ptr(ex), _ptr(sg), max(rows, 1), max(rows, 1) * cols)
+    @staticmethod
+    def _limb_desc(X):
+        lb, ex, sg = X
+        rows, cols = lb.shape[2], lb.shape[1]
+        return Limbs(_ptr(lb), _ptr(ex), _ptr(sg), max(rows, 1), max(rows, 1) * cols)
 
-        dA, dB, dC = desc(A), desc(B), desc(Cm)
+    def gemm_limbs(self, mode: int, A, B, Cm, opts: Optional[Opts] = None):
+        """Limb-format product, mode 0: C = RN_p(A B); mode 1: C = RN_p(C - RN_p(A B)).
+        Each matrix is a tuple (limb, exp, sign) of contiguous CUDA tensors of
+        shapes (nlimb, cols, rows) int64 (the uint64 limbs), (cols, rows) int32
+        and (cols, rows) uint8."""
+        nl, M, N, K = self._limb_shapes(A, B, Cm)
+        dA, dB, dC = (self._limb_desc(X) for X in (A, B, Cm))
         self._bind()
         self._call(lib().ozII_gemm_limbs(self._h, mode, nl, M, N, K, C.byref(dA), C.byref(dB),
                                          C.byref(dC), C.byref(opts) if opts else None))
         return Cm
+
+    def gemm_limbs_stages(self, mode: int, A, B, Cm, opts: Optional[Opts] = None,
+                          nlimb_out: int = 6):
+        """gemm_limbs with the (S5) group sums returned: int64 CUDA tensor of
+        shape (ng, N, M, nlimb_out), two's-complement 64-bit limbs."""
+        import torch
+        sh = self._limb_shapes(A, B, Cm)
+        nl, M, N, K = sh
+        S, w, Q, nmod, _ = plan_query(64 * nl, max(K, 1), opts)
+        ng = 2 * S - 1 - max(0, S - 1 - (opts.extra_groups if opts is not None else 0))
+        sbar = torch.zeros(ng * N * M * nlimb_out, dtype=torch.int64, device=A[0].device)
+        dA, dB, dC = (self._limb_desc(X) for X in (A, B, Cm))
+        self._bind()
+        self._call(lib().ozII_gemm_limbs_stages(self._h, mode, nl, M, N, K, C.byref(dA),
+                                                C.byref(dB), C.byref(dC),
+                                                C.byref(opts) if opts else None, _ptr(sbar),
+                                                nlimb_out))
+        return sbar.view(ng, N, M, nlimb_out)
 
     def gemm_stages(self, mode: int, A, B, Cm, opts: Optional[Opts] = None, nlimb: int = 6):
         """Product with every intermediate stage returned (parity hooks):
@@ -286,12 +399,9 @@ class Context:
 
     def getrs(self, LU, ipiv, B):
         """Solve in place: B (shape (nrhs, n, nc)) <- A^{-1} B."""
-        _check_mat(LU)
-        _check_mat(B, LU.shape[2])
+        check_getrs_args(LU, ipiv, B)
         n, nc = LU.shape[0], LU.shape[2]
         nrhs = B.shape[0]
-        if B.shape[1] != n:
-            raise ValueError("shape mismatch")
         self._bind()
         self._call(lib().ozII_getrs(self._h, nc, n, nrhs, _ptr(LU), max(n, 1), _ptr(ipiv),
                                     _ptr(B), max(n, 1)))
@@ -306,9 +416,7 @@ class Context:
         Ozaki-II update on the INT8 back-end."""
         arr = (BatchItem * max(len(systems), 1))()
         for i, (A, b, ipiv, info) in enumerate(systems):
-            _check_mat(A)
-            if b is not None:
-                _check_mat(b, A.shape[2])
+            check_batch_item(A, b, ipiv, info)
             arr[i] = BatchItem(A.shape[2], 0, A.shape[0], _ptr(A), _ptr(b) if b is not None else None,
                                _ptr(ipiv), _ptr(info))
         self._batch_refs = list(systems)

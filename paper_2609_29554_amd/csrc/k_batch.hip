@@ -151,7 +151,7 @@ __device__ bool pivot_column(const ozII_batch_item &it, int64_t j, double (*rkey
 }
 
 template <int NC, int NT>
-__device__ void solve_one(const ozII_batch_item &it, double (*rr)[4]);
+__device__ void solve_one(const ozII_batch_item &it);
 
 template <int NC>
 __device__ void lu_solve_one(const ozII_batch_item &it, double (*rkey)[4], int64_t *ridx,
@@ -180,16 +180,14 @@ __device__ void lu_solve_one(const ozII_batch_item &it, double (*rkey)[4], int64
     __syncthreads();
   }
   if (tid == 0) *it.info = *s_info;
-  solve_one<NC, BT>(it, rkey);
+  solve_one<NC, BT>(it);
 }
 
 // The solve with the factors: interchanges in ipiv order, forward (unit L,
-// ascending), backward with the reciprocals 1 / u_kk (descending), as
-// ozII_getrs does for one right-hand side.  The reciprocals do not depend on
-// the right-hand side: they are formed NT at a time, in parallel, in rr
-// (NT x 4 doubles of LDS).
+// ascending), backward (descending, each x_k divided by u_kk once its
+// updates are in), as ozII_getrs does for one right-hand side.
 template <int NC, int NT>
-__device__ void solve_one(const ozII_batch_item &it, double (*rr)[4]) {
+__device__ void solve_one(const ozII_batch_item &it) {
   if (!it.b) return;
   const int tid = threadIdx.x;
   const int64_t n = it.n;
@@ -221,26 +219,11 @@ __device__ void solve_one(const ozII_batch_item &it, double (*rr)[4]) {
     __syncthreads();
   }
   for (int64_t k = n - 1; k >= 0; --k) {
-    const int64_t top = k - (n - 1 - k) % NT;  // lowest row of k's chunk of reciprocals
-    const int64_t lo = top - NT + 1 > 0 ? top - NT + 1 : 0;
-    if ((n - 1 - k) % NT == 0) {
-      for (int64_t i = lo + tid; i <= k; i += NT) {
-        double one[NC], u[NC], r[NC];
-#pragma unroll
-        for (int q = 0; q < NC; ++q) one[q] = q == 0 ? 1.0 : 0.0;
-        ozx::load<NC>(E(i, i), u);
-        ozx::div<NC>(one, u, r);
-#pragma unroll
-        for (int q = 0; q < NC; ++q) rr[i - lo][q] = r[q];
-      }
-      __syncthreads();
-    }
     if (tid == 0) {
-      double r[NC], xk[NC], o[NC];
-#pragma unroll
-      for (int q = 0; q < NC; ++q) r[q] = rr[k - lo][q];
+      double u[NC], xk[NC], o[NC];
+      ozx::load<NC>(E(k, k), u);
       ozx::load<NC>(x + k * NC, xk);
-      ozx::mul<NC>(xk, r, o);
+      ozx::div<NC>(xk, u, o);
       ozx::store<NC>(x + k * NC, o);
     }
     __syncthreads();
@@ -445,7 +428,7 @@ __device__ __forceinline__ void lu_solve_oz(const ozII_batch_item &it, double (*
     }
   }
   if (tid == 0) *it.info = *s_info;
-  solve_one<NC, NT>(it, rkey);
+  solve_one<NC, NT>(it);
 }
 
 // One workgroup of BTZ threads per CU (the update's stages need more than

@@ -586,27 +586,12 @@ __global__ __launch_bounds__(256) void k_trsm_lower_unit_rc(const double *Lp, in
   if (mine) ozx::store<NC>(Xp + (i + c * ldx) * NC, x);
 }
 
-// rinv[k] = 1 / u_kk (expansion division), one thread per diagonal entry.
-template <int NC>
-__global__ __launch_bounds__(256) void k_recip_diag(const double *LU, int64_t lda, int64_t n,
-                                                    double *rinv) {
-  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (k >= n) return;
-  double one[NC], d[NC], r[NC];
-#pragma unroll
-  for (int q = 0; q < NC; ++q) one[q] = q == 0 ? 1.0 : 0.0;
-  ozx::load<NC>(LU + (k + k * lda) * NC, d);
-  ozx::div<NC>(one, d, r);
-  ozx::store<NC>(rinv + k * NC, r);
-}
-
 // X <- U^{-1} X for an upper-triangular kb x kb block: for h = kb-1 .. 0,
-// x_h <- x_h * rinv_h (rinv_h = 1/u_hh), then x_i -= u_ih x_h for i < h
+// x_h <- x_h / u_hh (expansion division), then x_i -= u_ih x_h for i < h
 // (descending order).
 template <int NC, int CPB, int RPT>
 __global__ __launch_bounds__(256) void k_trsm_upper(const double *Up, int64_t lda, double *Xp,
-                                                    int64_t ldx, int kb, int64_t ncols,
-                                                    const double *rinv) {
+                                                    int64_t ldx, int kb, int64_t ncols) {
   __shared__ double xs[2][CPB][NC];
   const int tid = threadIdx.x;
   const int64_t cbase = (int64_t)blockIdx.x * CPB;
@@ -630,11 +615,11 @@ __global__ __launch_bounds__(256) void k_trsm_upper(const double *Up, int64_t ld
       for (int rr = 0; rr < RPT; ++rr)
         if (rr == h / 256) {
           double d[NC];
-          ozx::load<NC>(rinv + (int64_t)h * NC, d);
+          ozx::load<NC>(Up + (h + (int64_t)h * lda) * NC, d);
 #pragma unroll
           for (int cc = 0; cc < CPB; ++cc) {
             double o[NC];
-            ozx::mul<NC>(x[rr][cc], d, o);
+            ozx::div<NC>(x[rr][cc], d, o);
 #pragma unroll
             for (int q = 0; q < NC; ++q) {
               x[rr][cc][q] = o[q];
@@ -782,32 +767,38 @@ __global__ __launch_bounds__(256) void k_apply_ipiv(double *B, int64_t ldb, int6
 
 // ---------------------------------------------------------------------------
 // Triangular solves of getrs for one right-hand side, pipelined over the
-// whole grid (one cooperative launch per direction).  Workgroup w owns the
-// rows at processing positions [w R, w R + R): rows 0.. in the forward
+// whole grid (one ordinary launch per direction).  A workgroup takes its
+// block of rows from an atomic ticket when it starts, so block t belongs to
+// the t-th workgroup to run: every block it waits for is owned by a
+// workgroup that is already running, whatever order the hardware dispatches
+// workgroups in and however few fit on the device at once.  Block t holds
+// the rows at processing positions [t R, t R + R): rows 0.. in the forward
 // solve with the unit lower factor, rows n-1.. in the backward solve with
 // the upper factor.  While earlier blocks are being finished it applies
 // their published solution values to its own rows -- the products l_ik x_k
 // in parallel, then the subtractions in the order the specification fixes
 // (ascending k forward, descending backward), so every element sees exactly
 // fms(x_i, l_ik, x_k) = x_i (+) (-(l_ik (x) x_k)) in that order -- then solves
-// its diagonal block, stores its R values and publishes the count of
-// finished positions (agent release, then the counter).  Waits are bounded
-// like the panel's.
-// ---------------------------------------------------------------------------
+// its diagonal block (backward: each x_k divided by u_kk once its updates
+// are in), stores its R values and publishes the count of finished
+// positions (agent release, then the counter).  Waits are bounded like the
+// panel's.
 constexpr int TRSV_R = 32;    // rows per workgroup
 constexpr int TRSV_B = 32;    // solution values applied per batch
 constexpr int TRSV_PUB = 4;   // rows of the diagonal block published at a time
 
 template <int NC, bool FWD>
 __global__ __launch_bounds__(256) void k_trsv(const double *LU, int64_t lda, double *x,
-                                              const double *rinv, int64_t n, uint32_t *ready,
+                                              int64_t n, uint32_t *ready, uint32_t *ticket,
                                               int *err) {
   __shared__ double xs[TRSV_R][NC];
   __shared__ double ys[TRSV_B][NC];
   __shared__ double pr[TRSV_R][TRSV_B][NC];
-  __shared__ int s_avail, s_fail;
+  __shared__ int s_avail, s_fail, s_blk;
   const int tid = threadIdx.x;
-  const int64_t p0 = (int64_t)blockIdx.x * TRSV_R;
+  if (tid == 0) s_blk = (int)atomicAdd(ticket, 1u);
+  __syncthreads();
+  const int64_t p0 = (int64_t)s_blk * TRSV_R;
   const int cnt = (int)(n - p0 < TRSV_R ? n - p0 : TRSV_R);
   auto row = [&](int64_t p) { return FWD ? p : n - 1 - p; };
   auto L = [&](int64_t i, int64_t k) { return LU + (i + k * lda) * NC; };
@@ -872,11 +863,11 @@ __global__ __launch_bounds__(256) void k_trsv(const double *LU, int64_t lda, dou
   for (int q = 0; q < cnt; ++q) {
     if (!FWD) {
       if (tid == 0) {
-        double v[NC], r[NC], o[NC];
+        double v[NC], u[NC], o[NC];
 #pragma unroll
         for (int e = 0; e < NC; ++e) v[e] = xs[q][e];
-        ozx::load<NC>(rinv + row(p0 + q) * NC, r);
-        ozx::mul<NC>(v, r, o);
+        ozx::load<NC>(L(row(p0 + q), row(p0 + q)), u);
+        ozx::div<NC>(v, u, o);
 #pragma unroll
         for (int e = 0; e < NC; ++e) xs[q][e] = o[e];
       }
@@ -997,29 +988,19 @@ hipError_t launch_trsm_lower_unit(int nc, const double *L, int64_t lda, double *
 
 template <int NC>
 static void trsm_u(int kb, dim3 g, hipStream_t s, const double *U, int64_t lda, double *X,
-                   int64_t ldx, int64_t ncols, const double *rinv) {
-  if (kb <= 256) hipLaunchKernelGGL((k_trsm_upper<NC, 1, 1>), g, dim3(256), 0, s, U, lda, X, ldx, kb, ncols, rinv);
-  else hipLaunchKernelGGL((k_trsm_upper<NC, 1, 2>), g, dim3(256), 0, s, U, lda, X, ldx, kb, ncols, rinv);
+                   int64_t ldx, int64_t ncols) {
+  if (kb <= 256) hipLaunchKernelGGL((k_trsm_upper<NC, 1, 1>), g, dim3(256), 0, s, U, lda, X, ldx, kb, ncols);
+  else hipLaunchKernelGGL((k_trsm_upper<NC, 1, 2>), g, dim3(256), 0, s, U, lda, X, ldx, kb, ncols);
 }
 
 hipError_t launch_trsm_upper(int nc, const double *U, int64_t lda, double *X, int64_t ldx, int kb,
-                             int64_t ncols, const double *rinv, hipStream_t s) {
+                             int64_t ncols, hipStream_t s) {
   if (ncols <= 0 || kb <= 0) return hipSuccess;
   if (kb > 512) return hipErrorInvalidValue;
   dim3 g((unsigned)ncols);
-  if (nc == 2) trsm_u<2>(kb, g, s, U, lda, X, ldx, ncols, rinv);
-  else if (nc == 3) trsm_u<3>(kb, g, s, U, lda, X, ldx, ncols, rinv);
-  else trsm_u<4>(kb, g, s, U, lda, X, ldx, ncols, rinv);
-  return hipGetLastError();
-}
-
-hipError_t launch_recip_diag(int nc, const double *LU, int64_t lda, int64_t n, double *rinv,
-                             hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  dim3 g((unsigned)((n + 255) / 256));
-  if (nc == 2) hipLaunchKernelGGL(k_recip_diag<2>, g, dim3(256), 0, s, LU, lda, n, rinv);
-  else if (nc == 3) hipLaunchKernelGGL(k_recip_diag<3>, g, dim3(256), 0, s, LU, lda, n, rinv);
-  else hipLaunchKernelGGL(k_recip_diag<4>, g, dim3(256), 0, s, LU, lda, n, rinv);
+  if (nc == 2) trsm_u<2>(kb, g, s, U, lda, X, ldx, ncols);
+  else if (nc == 3) trsm_u<3>(kb, g, s, U, lda, X, ldx, ncols);
+  else trsm_u<4>(kb, g, s, U, lda, X, ldx, ncols);
   return hipGetLastError();
 }
 
@@ -1064,13 +1045,15 @@ hipError_t launch_apply_ipiv(int nc, double *B, int64_t ldb, int64_t n, int64_t 
   return hipGetLastError();
 }
 
-hipError_t launch_trsv(int nc, int fwd, const double *LU, int64_t lda, double *x, const double *rinv,
-                       int64_t n, uint32_t *ready, int *err, hipStream_t s) {
+hipError_t launch_trsv(int nc, int fwd, const double *LU, int64_t lda, double *x, int64_t n,
+                       uint32_t *sync, int *err, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int G = (int)((n + TRSV_R - 1) / TRSV_R);
-  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(256), 0, s, (int *)ready, 0, (int64_t)1);
-#define OZ_TRSV(NC_, F_) \
-  hipLaunchKernelGGL((k_trsv<NC_, F_>), dim3((unsigned)G), dim3(256), 0, s, LU, lda, x, rinv, n, ready, err)
+  // sync[0]: finished positions, sync[1]: ticket of the next row block
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(256), 0, s, (int *)sync, 0, (int64_t)2);
+#define OZ_TRSV(NC_, F_)                                                                      \
+  hipLaunchKernelGGL((k_trsv<NC_, F_>), dim3((unsigned)G), dim3(256), 0, s, LU, lda, x, n, sync, \
+                     sync + 1, err)
   if (fwd) {
     if (nc == 2) OZ_TRSV(2, true); else if (nc == 3) OZ_TRSV(3, true); else OZ_TRSV(4, true);
   } else {

@@ -48,6 +48,17 @@ __global__ __launch_bounds__(256) void k_row_exponents(const double *A, int64_t 
   if (best != EXP_ZERO) atomicMax(e + i, best);
 }
 
+// C = 0 for an M x N matrix of nc-component expansions (leading dimension
+// ldc), one double per thread
+__global__ __launch_bounds__(256) void k_zero_expansions(double *C, int64_t ldc, int64_t rows,
+                                                         int64_t cols, int nc) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t per = rows * nc;
+  if (t >= per * cols) return;
+  const int64_t j = t / per, r = t - j * per;
+  C[j * ldc * nc + r] = 0.0;
+}
+
 __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t cnt) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t < cnt) p[t] = v;
@@ -764,8 +775,28 @@ __global__ __launch_bounds__(256) void k_consumer_b(const uint8_t *__restrict__ 
   }
 }
 
-// Debug export of the group sums: Sbar as 64-bit limbs (two's complement),
-// layout [gi][j][i][limb], nlimb limbs.
+// Export of the group sums (parity hook): Sbar as 64-bit limbs (two's
+// complement), layout [gi][j][i][limb], nlimb limbs, from the ND 16-bit
+// digits of a CRT routine.
+template <int ND>
+__device__ __forceinline__ void store_sbar_limbs(const int32_t (&d)[ND], uint64_t *o, int nlimb) {
+  const uint64_t fill = d[ND - 1] < 0 ? ~0ull : 0ull;
+  for (int q = 0; q < nlimb; ++q) {
+    uint64_t v = 0;
+    if (4 * q + 3 < ND) {
+      for (int k = 0; k < 4; ++k) v |= ((uint64_t)((uint32_t)d[4 * q + k] & 0xffffu)) << (16 * k);
+    } else {
+      for (int k = 0; k < 4; ++k) {
+        const uint64_t dig = 4 * q + k < ND ? (uint64_t)((uint32_t)d[4 * q + k] & 0xffffu)
+                                            : (fill & 0xffffu);
+        v |= dig << (16 * k);
+      }
+    }
+    o[q] = v;
+  }
+}
+
+// binary64 moduli: the group sums of crt_digits, the CRT of k_consumer
 template <class TT>
 __global__ __launch_bounds__(256) void k_crt_export(const TT *__restrict__ tpl, int64_t Mp,
                                                     int64_t Np, int64_t M, int64_t N,
@@ -777,17 +808,25 @@ __global__ __launch_bounds__(256) void k_crt_export(const TT *__restrict__ tpl, 
   for (int gi = 0; gi < pl->ng; ++gi) {
     int32_t d[NDCRT];
     crt_digits<NDCRT, TT>(tpl + ((int64_t)gi * nmod * Np + j) * Mp + i, Np * Mp, pl, d);
-    uint64_t *o = out + (((int64_t)gi * N + j) * M + i) * nlimb;
-    const uint64_t fill = d[NDCRT - 1] < 0 ? ~0ull : 0ull;
-    for (int q = 0; q < nlimb; ++q) {
-      uint64_t v = 0;
-      if (4 * q + 3 < NDCRT) {
-        for (int k = 0; k < 4; ++k) v |= ((uint64_t)((uint32_t)d[4 * q + k] & 0xffffu)) << (16 * k);
-      } else {
-        v = fill;
-      }
-      o[q] = v;
-    }
+    store_sbar_limbs<NDCRT>(d, out + (((int64_t)gi * N + j) * M + i) * nlimb, nlimb);
+  }
+}
+
+// byte back-ends (INT8, FP8): the group sums of crt_group_bytes<NB>, the
+// CRT that k_consumer_b and k_consumer_limbs run, with the same NB
+template <int NB>
+__global__ __launch_bounds__(256) void k_crt_export_b(const uint8_t *__restrict__ tpl, int64_t Mp,
+                                                      int64_t Np, int64_t M, int64_t N,
+                                                      const DevPlan *__restrict__ pl,
+                                                      uint64_t *out, int nlimb) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (i >= M || j >= N) return;
+  const int nmod = pl->nmod;
+  for (int gi = 0; gi < pl->ng; ++gi) {
+    int32_t d[NB / 2];
+    crt_group_bytes<NB>(tpl + ((int64_t)gi * nmod * Np + j) * Mp + i, Np * Mp, nmod, pl, d);
+    store_sbar_limbs<NB / 2>(d, out + (((int64_t)gi * N + j) * M + i) * nlimb, nlimb);
   }
 }
 
@@ -797,6 +836,15 @@ __global__ __launch_bounds__(256) void k_crt_export(const TT *__restrict__ tpl, 
 // host launchers
 // ---------------------------------------------------------------------------
 namespace ozl {
+
+hipError_t launch_zero_expansions(int nc, double *C, int64_t ldc, int64_t M, int64_t N,
+                                  hipStream_t s) {
+  const int64_t total = M * N * nc;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_expansions, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, C,
+                     ldc, M, N, nc);
+  return hipGetLastError();
+}
 
 hipError_t launch_exponents(int nc, const double *X, int64_t ld, int64_t rows, int64_t cols,
                             int rowwise, int32_t *e, hipStream_t s) {
@@ -977,17 +1025,25 @@ hipError_t launch_consumer(int nc, int nwc, int nd, const void *tpl, int tbytes,
   return hipGetLastError();
 }
 
-hipError_t launch_crt_export(const void *tpl, int tbytes, int64_t Mp, int64_t Np, int64_t M,
-                             int64_t N, const DevPlan *pl, uint64_t *out, int nlimb,
+hipError_t launch_crt_export(const void *tpl, int tbytes, int nd, int64_t Mp, int64_t Np,
+                             int64_t M, int64_t N, const DevPlan *pl, uint64_t *out, int nlimb,
                              hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
   dim3 g((unsigned)((M + 255) / 256), (unsigned)N);
-  if (tbytes == 1)
-    hipLaunchKernelGGL(k_crt_export<uint8_t>, g, dim3(256), 0, s, (const uint8_t *)tpl, Mp, Np, M,
-                       N, pl, out, nlimb);
-  else
+  if (tbytes == 1) {
+    // the byte-column count of the consumers (launch_consumer, the limb
+    // consumer): 36 up to 18 digits, else 48
+    if (nd > 24) return hipErrorInvalidValue;
+    if (nd <= 18)
+      hipLaunchKernelGGL(k_crt_export_b<36>, g, dim3(256), 0, s, (const uint8_t *)tpl, Mp, Np, M,
+                         N, pl, out, nlimb);
+    else
+      hipLaunchKernelGGL(k_crt_export_b<48>, g, dim3(256), 0, s, (const uint8_t *)tpl, Mp, Np, M,
+                         N, pl, out, nlimb);
+  } else {
     hipLaunchKernelGGL(k_crt_export<uint32_t>, g, dim3(256), 0, s, (const uint32_t *)tpl, Mp, Np,
                        M, N, pl, out, nlimb);
+  }
   return hipGetLastError();
 }
 

@@ -319,9 +319,6 @@ struct ozII_ctx {
   int *perm = nullptr, *moved = nullptr, *nmoved = nullptr;
   int64_t panel_n = 0;
   int panel_kb = 0;
-  // getrs: reciprocals of the diagonal of U
-  double *rinv = nullptr;
-  int64_t rinv_cap = 0;
   // batched LU: the uploaded item table (processing order) and its queue
   ozII_batch_item *batch = nullptr;
   int batch_cap = 0, batch_count = 0, batch_grid = 1;
@@ -509,9 +506,9 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
   if (!C || (K > 0 && (!A || !B))) return fail(h, OZII_EINVAL, "null matrix pointer");
   if (K == 0) {
     if (mode == 1) return OZII_OK;
-    // C = 0
-    hipError_t e = hipMemset2DAsync(C, ldc * nc * 8, 0, M * nc * 8, N, h->stream);
-    return e == hipSuccess ? OZII_OK : hip_fail(h, e, "hipMemset2DAsync");
+    // C = 0 (a fill kernel: stays correct inside a captured graph)
+    hipError_t e = ozl::launch_zero_expansions(nc, C, ldc, M, N, h->stream);
+    return e == hipSuccess ? OZII_OK : hip_fail(h, e, "zero C");
   }
   const HostPlan *hp;
   const DevPlan *dp;
@@ -520,11 +517,12 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
   GemmLayout L = gemm_layout(*hp, M, N, K, o ? o->gemm_tile : 0);
   st = ensure_ws(h, L.total);
   if (st != OZII_OK) return st;
-  int32_t *ea = (int32_t *)(h->ws + L.off_ea);
-  int32_t *eb = (int32_t *)(h->ws + L.off_eb);
-  void *pa = h->ws + L.off_pa;
-  void *pb = h->ws + L.off_pb;
-  void *tpl = h->ws + L.off_tpl;
+  char *ws = h->ws;
+  int32_t *ea = (int32_t *)(ws + L.off_ea);
+  int32_t *eb = (int32_t *)(ws + L.off_eb);
+  void *pa = ws + L.off_pa;
+  void *pb = ws + L.off_pb;
+  void *tpl = ws + L.off_tpl;
   hipStream_t s = h->stream;
   hipError_t e;
   const double pairs = (double)hp->nmod * [&] {
@@ -580,7 +578,7 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
     return hip_fail(h, e, "copy planesB");
   if (tpl_out && (e = hipMemcpyAsync(tpl_out, tpl, (size_t)L.tplBytes, hipMemcpyDeviceToDevice, s)) != hipSuccess)
     return hip_fail(h, e, "copy tpl");
-  if (sbar_out && (e = ozl::launch_crt_export(tpl, hp->t_bytes(), L.Mp, L.Np, M, N, dp, sbar_out, nlimb, s)) != hipSuccess)
+  if (sbar_out && (e = ozl::launch_crt_export(tpl, hp->t_bytes(), hp->nd, L.Mp, L.Np, M, N, dp, sbar_out, nlimb, s)) != hipSuccess)
     return hip_fail(h, e, "crt_export");
   {
     ProfScope ps(h, OZ_STAGE_CONSUMER, (double)M * N * (t_bytes + 8.0 * nc * (mode ? 2 : 1)), 0);
@@ -613,7 +611,8 @@ bool limbs_ok(const ozII_limbs *X, int64_t rows, int64_t cols) {
 
 ozII_status gemm_limbs_impl(ozII_ctx *h, int mode, int nlimb, int64_t M, int64_t N, int64_t K,
                             const ozII_limbs *A, const ozII_limbs *B, ozII_limbs *C,
-                            const ozII_opts *o) {
+                            const ozII_opts *o, uint64_t *sbar_out = nullptr,
+                            int nlimb_out = 0) {
   if (!h) return OZII_EINVAL;
   if (mode != 0 && mode != 1) return fail(h, OZII_EINVAL, "mode must be 0 or 1");
   if (nlimb < 1 || nlimb > 64) return fail(h, OZII_EINVAL, "nlimb must be 1..64");
@@ -692,6 +691,9 @@ ozII_status gemm_limbs_impl(ozII_ctx *h, int mode, int nlimb, int64_t M, int64_t
                                  L.Mp, L.Np, L.Kp, L.planeA, L.planeB, o ? o->gemm_tile : 0, s)) != hipSuccess)
       return hip_fail(h, e, "modular gemm");
   }
+  if (sbar_out && (e = ozl::launch_crt_export(tpl, 1, hp->nd, L.Mp, L.Np, M, N, dp, sbar_out,
+                                              nlimb_out, s)) != hipSuccess)
+    return hip_fail(h, e, "crt_export");
   {
     // t-planes read once, each group's window of the sum read and written
     ProfScope ps(h, OZ_STAGE_CONSUMER,
@@ -737,6 +739,15 @@ ozII_status ozII_gemm_limbs(ozII_handle h, int32_t mode, int32_t nlimb, int64_t 
   return gemm_limbs_impl(h, mode, nlimb, M, N, K, A, B, C, o);
 }
 
+ozII_status ozII_gemm_limbs_stages(ozII_handle h, int32_t mode, int32_t nlimb, int64_t M,
+                                   int64_t N, int64_t K, const ozII_limbs *A,
+                                   const ozII_limbs *B, ozII_limbs *C, const ozII_opts *o,
+                                   uint64_t *sbar, int32_t nlimb_out) {
+  if (!h) return OZII_EINVAL;
+  if (sbar && (nlimb_out < 1 || nlimb_out > 6)) return fail(h, OZII_EINVAL, "nlimb_out must be 1..6");
+  return gemm_limbs_impl(h, mode, nlimb, M, N, K, A, B, C, o, sbar, nlimb_out);
+}
+
 ozII_status ozII_create(ozII_handle *out, int device, void *stream) {
   if (!out) return OZII_EINVAL;
   *out = nullptr;
@@ -756,7 +767,6 @@ ozII_status ozII_destroy(ozII_handle h) {
   if (h->ws) hipFree(h->ws);
   for (auto &kv : h->plans) hipFree(kv.second.second);
   for (auto ev : h->pool) hipEventDestroy(ev);
-  if (h->rinv) hipFree(h->rinv);
   if (h->batch) hipFree(h->batch);
   if (h->batch_queue) hipFree(h->batch_queue);
   if (h->batch_ws) hipFree(h->batch_ws);
@@ -962,18 +972,6 @@ ozII_status ozII_getrs(ozII_handle h, int32_t nc, int64_t n, int64_t nrhs, const
   hipError_t e;
   ProfScope ps(h, OZ_STAGE_GETRS, 8.0 * nc * (double)n * n + 16.0 * nc * (double)n * nrhs,
                (double)n * n * nrhs);
-  if (h->rinv_cap < n * nc) {
-    if (h->rinv) {
-      if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
-      hipFree(h->rinv);
-      h->rinv = nullptr;
-      h->rinv_cap = 0;
-    }
-    if (hipMalloc((void **)&h->rinv, sizeof(double) * n * nc) != hipSuccess)
-      return fail(h, OZII_ENOMEM, "getrs scratch allocation failed");
-    h->rinv_cap = n * nc;
-  }
-  if ((e = ozl::launch_recip_diag(nc, LU, lda, n, h->rinv, s)) != hipSuccess) return hip_fail(h, e, "recip diag");
   if ((e = ozl::launch_apply_ipiv(nc, B, ldb, n, nrhs, ipiv, s)) != hipSuccess) return hip_fail(h, e, "apply ipiv");
   if (nrhs == 1) {
     // one right-hand side: the pipelined solves (same operations per element)
@@ -981,10 +979,10 @@ ozII_status ozII_getrs(ozII_handle h, int32_t nc, int64_t n, int64_t nrhs, const
       const ozII_status st = ensure_panel(h, 1, 1);
       if (st != OZII_OK) return st;
     }
-    uint32_t *ready = h->bar + 12;
-    if ((e = ozl::launch_trsv(nc, 1, LU, lda, B, nullptr, n, ready, h->err, s)) != hipSuccess)
+    uint32_t *sync = h->bar + 12;  // finished-position counter and row-block ticket
+    if ((e = ozl::launch_trsv(nc, 1, LU, lda, B, n, sync, h->err, s)) != hipSuccess)
       return hip_fail(h, e, "forward solve");
-    if ((e = ozl::launch_trsv(nc, 0, LU, lda, B, h->rinv, n, ready, h->err, s)) != hipSuccess)
+    if ((e = ozl::launch_trsv(nc, 0, LU, lda, B, n, sync, h->err, s)) != hipSuccess)
       return hip_fail(h, e, "backward solve");
     return OZII_OK;
   }
@@ -1004,7 +1002,7 @@ ozII_status ozII_getrs(ozII_handle h, int32_t nc, int64_t n, int64_t nrhs, const
     const int64_t j0 = bi * bs;
     const int ib = (int)std::min<int64_t>(bs, n - j0);
     if ((e = ozl::launch_trsm_upper(nc, LU + (j0 + j0 * lda) * nc, lda, B + j0 * nc, ldb, ib, nrhs,
-                                    h->rinv + j0 * nc, s)) != hipSuccess)
+                                    s)) != hipSuccess)
       return hip_fail(h, e, "backward block");
     if (j0 > 0) {
       if ((e = ozl::launch_naive_gemm(nc, LU + (j0 * lda) * nc, lda, B + j0 * nc, ldb, B, ldb, j0,

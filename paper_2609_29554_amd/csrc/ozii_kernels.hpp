@@ -36,6 +36,9 @@ inline int gemm_tile_auto(int64_t prods, int64_t Mp, int64_t Np) {
   return GEMM_TILE_128x128;
 }
 
+// C = 0 (M x N expansions of nc components, leading dimension ldc)
+hipError_t launch_zero_expansions(int nc, double *C, int64_t ldc, int64_t M, int64_t N,
+                                  hipStream_t s);
 // Ozaki-II product stages
 hipError_t launch_exponents(int nc, const double *X, int64_t ld, int64_t rows, int64_t cols,
                             int rowwise, int32_t *e, hipStream_t s);
@@ -58,8 +61,11 @@ hipError_t launch_consumer(int nc, int nwc, int nd, const void *tpl, int tbytes,
                            int64_t Np, double *C, int64_t ldc, int64_t M, int64_t N,
                            const int32_t *ea, const int32_t *eb, const DevPlan *pl, int mode,
                            hipStream_t s);
-hipError_t launch_crt_export(const void *tpl, int tbytes, int64_t Mp, int64_t Np, int64_t M,
-                             int64_t N, const DevPlan *pl, uint64_t *out, int nlimb,
+// group sums exported by the CRT routine of the consumer that reads these
+// t-planes (byte back-ends: crt_group_bytes with the consumer's byte-column
+// count for nd digits; binary64 moduli: crt_digits)
+hipError_t launch_crt_export(const void *tpl, int tbytes, int nd, int64_t Mp, int64_t Np,
+                             int64_t M, int64_t N, const DevPlan *pl, uint64_t *out, int nlimb,
                              hipStream_t s);
 
 // LU pieces
@@ -75,9 +81,7 @@ hipError_t launch_laswp(int nc, double *A, int64_t lda, int64_t k, int64_t c0, i
 hipError_t launch_trsm_lower_unit(int nc, const double *L, int64_t lda, double *X, int64_t ldx,
                                   int kb, int64_t ncols, hipStream_t s);
 hipError_t launch_trsm_upper(int nc, const double *U, int64_t lda, double *X, int64_t ldx, int kb,
-                             int64_t ncols, const double *rinv, hipStream_t s);
-hipError_t launch_recip_diag(int nc, const double *LU, int64_t lda, int64_t n, double *rinv,
-                             hipStream_t s);
+                             int64_t ncols, hipStream_t s);
 hipError_t launch_naive_gemm(int nc, const double *A, int64_t lda, const double *B, int64_t ldb,
                              double *C, int64_t ldc, int64_t M, int64_t N, int64_t K, int desc,
                              hipStream_t s);
@@ -111,10 +115,11 @@ hipError_t launch_limb_sub(uint64_t *climb, int32_t *cexp, uint8_t *csign, int64
 hipError_t launch_limb_zero(uint64_t *limb, int32_t *lexp, uint8_t *lsign, int64_t ld,
                             int64_t plane, int nlimb, int64_t M, int64_t N, hipStream_t s);
 // pipelined triangular solve of one right-hand side (fwd: unit lower,
-// ascending; else upper with the reciprocals rinv, descending); ready: one
-// device counter owned by the caller, reset by the launcher
-hipError_t launch_trsv(int nc, int fwd, const double *LU, int64_t lda, double *x, const double *rinv,
-                       int64_t n, uint32_t *ready, int *err, hipStream_t s);
+// ascending; else upper, descending, dividing by the diagonal); sync: two
+// device words owned by the caller (finished-position counter and row-block
+// ticket), reset by the launcher
+hipError_t launch_trsv(int nc, int fwd, const double *LU, int64_t lda, double *x, int64_t n,
+                       uint32_t *sync, int *err, hipStream_t s);
 
 // batched LU + solve (k_batch.hip); items in processing order, each with its
 // caller-order index in `reserved`

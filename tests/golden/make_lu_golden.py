@@ -1,10 +1,12 @@
-"""Write the expected values of the full-size QD Lotkin LU (n = 2048, b = 256,
-Ozaki-II INT8 Schur updates) from the CPU oracle only.
+"""Write the expected values of the full-size QD Lotkin LU (n = 2048, panel
+width b = 256 and b = 128, Ozaki-II INT8 Schur updates) from the CPU oracle
+only.
 
 Stores the pivot vector, info, SHA-256 digests of the factor array and of the
 solution of A x = A*ones (little-endian float64 bytes, shape (cols, rows, 4)),
-and a few hundred sampled factor entries.  Run: python tests/golden/make_lu_golden.py
-(about two minutes on 8 cores).
+and a few hundred sampled factor entries.  Run:
+python tests/golden/make_lu_golden.py [b ...]   (default: 256 128; about two
+minutes per panel width on 8 cores).
 """
 import hashlib
 import json
@@ -45,4 +47,5 @@ def main(n=2048, b=256, nc=4):
 
 
 if __name__ == "__main__":
-    main()
+    for blk in [int(a) for a in sys.argv[1:]] or [256, 128]:
+        main(b=blk)

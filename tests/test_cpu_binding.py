@@ -73,3 +73,75 @@ def test_status_strings():
     Z = _lib()
     for s in range(8):
         assert Z.lib().ozII_status_string(s)
+
+
+class _FakeCuda:
+    """Stands in for a CUDA tensor: the binding's checks read only shape,
+    dtype, device and layout, so they can be exercised without a GPU."""
+
+    def __init__(self, shape, dtype, contiguous=True, device="cuda:0"):
+        self.shape = tuple(shape)
+        self.dtype = dtype
+        self.is_cuda = True
+        self.device = device
+        self._c = contiguous
+
+    def is_contiguous(self):
+        return self._c
+
+    def dim(self):
+        return len(self.shape)
+
+    def numel(self):
+        n = 1
+        for s in self.shape:
+            n *= s
+        return n
+
+
+def test_getrs_arguments_are_validated():
+    Z = _lib()
+    import torch
+    f64, i64, i32 = torch.float64, torch.int64, torch.int32
+    n, nc = 6, 4
+    LU = _FakeCuda((n, n, nc), f64)
+    ok = dict(LU=LU, ipiv=_FakeCuda((n,), i64), B=_FakeCuda((2, n, nc), f64))
+    Z.check_getrs_args(**ok)
+    bad = [
+        dict(ok, LU=_FakeCuda((n, n + 1, nc), f64)),            # not square
+        dict(ok, ipiv=_FakeCuda((n,), i32)),                    # wrong pivot type
+        dict(ok, ipiv=_FakeCuda((n - 1,), i64)),                # too short
+        dict(ok, ipiv=_FakeCuda((n,), i64, device="cuda:1")),   # other device
+        dict(ok, B=_FakeCuda((2, n + 1, nc), f64)),             # wrong order
+        dict(ok, B=_FakeCuda((2, n, 2), f64)),                  # other format
+        dict(ok, B=_FakeCuda((2, n, nc), f64, contiguous=False)),
+        dict(ok, LU=_FakeCuda((n, n, 5), f64)),                 # 5 components
+    ]
+    for kw in bad:
+        with pytest.raises(ValueError):
+            Z.check_getrs_args(**kw)
+
+
+def test_batch_items_are_validated():
+    Z = _lib()
+    import torch
+    f64, i64, i32 = torch.float64, torch.int64, torch.int32
+    n, nc = 5, 2
+    ok = dict(A=_FakeCuda((n, n, nc), f64), b=_FakeCuda((1, n, nc), f64),
+              ipiv=_FakeCuda((n,), i64), info=_FakeCuda((1,), i32))
+    Z.check_batch_item(**ok)
+    Z.check_batch_item(**dict(ok, b=None))
+    bad = [
+        dict(ok, A=_FakeCuda((n, n - 1, nc), f64)),
+        dict(ok, b=_FakeCuda((2, n, nc), f64)),
+        dict(ok, b=_FakeCuda((1, n, 4), f64)),
+        dict(ok, ipiv=_FakeCuda((n,), i32)),
+        dict(ok, ipiv=_FakeCuda((n - 2,), i64)),
+        dict(ok, info=_FakeCuda((1,), i64)),
+        dict(ok, info=_FakeCuda((0,), i32)),
+        dict(ok, A=_FakeCuda((5000, 5000, nc), f64)),
+        dict(ok, info=_FakeCuda((1,), i32, device="cuda:1")),
+    ]
+    for kw in bad:
+        with pytest.raises(ValueError):
+            Z.check_batch_item(**kw)

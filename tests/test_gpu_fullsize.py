@@ -1,8 +1,9 @@
 """Parity at the benchmark sizes.
 
-* QD Lotkin LU, n = 2048, b = 256 (the bench workload): pivots, info and a
-  SHA-256 of the whole factor array and of the solution must equal the values
-  the oracle wrote into tests/golden/ (bit-exact for every element).
+* QD Lotkin LU, n = 2048, b = 256 and b = 128 (the bench workload; the
+  autotuner picks one of the two): pivots, info and a SHA-256 of the whole
+  factor array and of the solution must equal the values the oracle wrote
+  into tests/golden/ (bit-exact for every element).
 * QD Lotkin LU, n = 1024, b = 128, on each Schur-update back-end (INT8,
   FP8 base-17, binary64 moduli) and the native update: the whole factor
   array, pivots, info and solution against the oracle LU with that
@@ -24,15 +25,16 @@ import workloads as W
 from gpu_util import ctx, note, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
-GOLD = os.path.join(os.path.dirname(__file__), "golden", "lu_lotkin_qd2048_b256.json")
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "lu_lotkin_qd2048_b{}.json")
 
 
 def _sha(x):
     return hashlib.sha256(np.ascontiguousarray(x, dtype="<f8").tobytes()).hexdigest()
 
 
-def test_lu_lotkin_qd2048_matches_oracle_golden():
-    g = json.load(open(GOLD))
+@pytest.mark.parametrize("block", [256, 128])
+def test_lu_lotkin_qd2048_matches_oracle_golden(block):
+    g = json.load(open(GOLD.format(block)))
     n, b, nc = g["n"], g["b"], g["nc"]
     note(f"full-size LU Lotkin n={n} b={b} nc={nc}")
     A = W.lotkin(n, nc)

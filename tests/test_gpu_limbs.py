@@ -152,3 +152,32 @@ def test_limb_schur_first_update_p4096_full_size_sampled():
            ds[ci][:, ri].cpu().numpy())
     for g, w_, name in zip(got, want, ("limbs", "exp", "sign")):
         assert np.array_equal(g, w_), name
+
+
+@pytest.mark.parametrize("nl,M,N,K,E,seed", [
+    (4, 20, 17, 40, 0, 21),
+    (64, 9, 7, 20, 0, 22),      # p = 4096: 54 moduli, the 48-byte-column CRT
+    (64, 33, 5, 65, 1, 23),     # an extra digit group
+    (16, 40, 3, 130, 0, 24),
+])
+def test_gemm_limbs_group_sums_bit_exact(nl, M, N, K, E, seed):
+    """(S5) of the limb product: the group sums that the limb consumer's CRT
+    routine forms, exported by it, against the oracle's exact digit-group
+    sums (below the final rounding, which hides their low bits)."""
+    import paper_2609_29554_amd as Z
+    note(f"gemm_limbs group sums nl={nl} {M}x{N}x{K} E={E}")
+    A, B, C0 = _case(nl, M, N, K, 1, seed)
+    pl = O.make_plan(64 * nl, K, extra_groups=E)
+    _, _, sums = OL.group_sums(A, B, pl)
+    want, _ = OL.ozgemm(1, A, B, C0, pl)
+    dA, dB, dC = _dev(A), _dev(B), _dev(C0)
+    sb = ctx().gemm_limbs_stages(1, dA, dB, dC, Z.make_opts(extra_groups=E), nlimb_out=6)
+    ctx().sync_check()
+    got = to_host(sb).view(np.uint64)
+    assert got.shape == (len(pl.groups), N, M, 6)
+    for g in range(len(pl.groups)):
+        for j in range(N):
+            for i in range(M):
+                assert O.limbs_to_int(got[g, j, i]) == sums[g][j][i], (g, i, j)
+    for g_, w_ in zip(_host(dC), want):
+        assert np.array_equal(g_, w_)

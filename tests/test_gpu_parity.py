@@ -27,6 +27,7 @@ STAGE_CASES = [
     (4, 129, 257, 65, 2, 1),
     (2, 260, 140, 192, 1, 0),   # 3 inner steps per product (odd, below the stage count)
     (2, 300, 130, 448, 1, 0),   # 7 inner steps: loads issued inside the loop
+    (2, 40, 30, 1100, 1, 0),    # 39 moduli, 20 CRT digits: the 48-byte-column CRT
 ]
 
 
