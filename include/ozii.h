@@ -110,6 +110,31 @@ ozII_status ozII_gemm(ozII_handle h, int32_t mode, int32_t nc, int64_t M, int64_
                       const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
                       int64_t ldc, const ozII_opts *o);
 
+/* ozII_gemm for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid allocation).
+ * Same arguments, operations and results as ozII_gemm (bit for bit), but
+ * the plan tables and the workspace live in a static device array that the
+ * library reserves once per GPU it runs on and holds until the process ends
+ * (64 MiB: eight plan slots of 32 KiB, the rest workspace); the call makes
+ * no hipMalloc or hipFree and creates no event (profiling records nothing
+ * for it).  The first use of a plan (p, K, options) copies its tables into
+ * a slot on the handle's stream; a ninth distinct plan evicts the oldest.
+ * Limit: the product's workspace -- about 4 (M + N) + S N_mod b_r (Mp + Np)
+ * Kp + ng N_mod b_t Mp Np bytes, Mp, Np rounded up to 128 or 256, Kp to 64
+ * or 128, b_r / b_t the residue / t-value bytes of the back-end -- must fit
+ * ozII_gemm_noalloc_capacity() bytes (e.g. QD with M = N = K = 512, or
+ * M = N = 1024 with K = 64); larger products return OZII_EINVAL before
+ * anything is enqueued.  All calls on one GPU share its array, which keeps
+ * the last call's contents: calls that overlap on one GPU (other streams,
+ * other handles, other host threads) race and give undefined results.
+ * Errors: those of ozII_gemm; OZII_EINVAL for a product beyond the
+ * capacity; OZII_EHIP if the array could not be mapped on this device. */
+ozII_status ozII_gemm_noalloc(ozII_handle h, int32_t mode, int32_t nc, int64_t M, int64_t N,
+                              int64_t K, const double *A, int64_t lda, const double *B,
+                              int64_t ldb, double *C, int64_t ldc, const ozII_opts *o);
+/* Workspace bytes available to ozII_gemm_noalloc (host only). */
+ozII_status ozII_gemm_noalloc_capacity(int64_t *bytes);
+
 /* Arbitrary-precision limb matrices (the MPFR-like input of Sec. 3.3 and
  * the p-bit results of (S6)), p = 64 nlimb bits, 1 <= nlimb <= 64:
  *   x = (-1)^sign * (sum_q limb_q 2^(64 q)) * 2^(exp - p),

@@ -44,7 +44,8 @@ _i64 = C.c_int64
 _i32 = C.c_int32
 
 EXPORTED = ["ozII_create", "ozII_destroy", "ozII_set_stream", "ozII_plan_query", "ozII_reserve",
-            "ozII_gemm", "ozII_gemm_limbs", "ozII_gemm_limbs_stages", "ozII_gemm_stages",
+            "ozII_gemm", "ozII_gemm_noalloc", "ozII_gemm_noalloc_capacity",
+            "ozII_gemm_limbs", "ozII_gemm_limbs_stages", "ozII_gemm_stages",
             "ozII_gemm_stage_dims",
             "ozII_getrf", "ozII_getrs",
             "ozII_batch_prepare", "ozII_batch_prepare_ex", "ozII_batch_run", "ozII_tune",
@@ -96,6 +97,8 @@ def lib():
                                       C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]
         L.ozII_reserve.argtypes = [_p, _i32, _i64, _i64, _i64, _i64, OP]
         L.ozII_gemm.argtypes = [_p, _i32, _i32, _i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, OP]
+        L.ozII_gemm_noalloc.argtypes = L.ozII_gemm.argtypes
+        L.ozII_gemm_noalloc_capacity.argtypes = [C.POINTER(_i64)]
         LP = C.POINTER(Limbs)
         L.ozII_gemm_limbs.argtypes = [_p, _i32, _i32, _i64, _i64, _i64, LP, LP, LP, OP]
         L.ozII_gemm_limbs_stages.argtypes = [_p, _i32, _i32, _i64, _i64, _i64, LP, LP, LP, OP,
@@ -124,6 +127,15 @@ def lib():
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
+
+
+def noalloc_capacity() -> int:
+    """Workspace bytes of ozII_gemm_noalloc's static scratch."""
+    v = _i64()
+    st = lib().ozII_gemm_noalloc_capacity(C.byref(v))
+    if st != OK:
+        raise OziiError(st, "capacity")
+    return v.value
 
 
 def make_opts(backend: int = 0, nslice: int = 0, extra_groups: int = 0, guard_ex: int = 0,
@@ -323,6 +335,22 @@ class Context:
         self._bind()
         self._call(lib().ozII_gemm_limbs(self._h, mode, nl, M, N, K, C.byref(dA), C.byref(dB),
                                          C.byref(dC), C.byref(opts) if opts else None))
+        return Cm
+
+    def gemm_noalloc(self, mode: int, A, B, Cm, opts: Optional[Opts] = None):
+        """gemm() through ozII_gemm_noalloc: plan tables and workspace in the
+        library's static per-GPU scratch, no device allocation."""
+        nc = A.shape[2]
+        for t in (A, B, Cm):
+            _check_mat(t, nc)
+        K, M = A.shape[0], A.shape[1]
+        N = B.shape[0]
+        if B.shape[1] != K or Cm.shape[0] != N or Cm.shape[1] != M:
+            raise ValueError("shape mismatch")
+        self._bind()
+        self._call(lib().ozII_gemm_noalloc(self._h, mode, nc, M, N, K, _ptr(A), max(M, 1),
+                                           _ptr(B), max(K, 1), _ptr(Cm), max(M, 1),
+                                           C.byref(opts) if opts else None))
         return Cm
 
     def gemm_limbs_stages(self, mode: int, A, B, Cm, opts: Optional[Opts] = None,

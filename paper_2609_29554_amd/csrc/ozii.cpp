@@ -338,6 +338,7 @@ struct ozII_ctx {
     double bytes, ops;
   };
   bool profiling = false;
+  int prof_block = 0;  // > 0 inside ozII_gemm_noalloc: no events are created
   std::vector<ProfRec> prof;
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
@@ -368,7 +369,7 @@ struct ProfScope {
   ozII_ctx *h;
   int idx = -1;
   ProfScope(ozII_ctx *hh, int stage, double bytes, double ops) : h(hh) {
-    if (!h->profiling) return;
+    if (!h->profiling || h->prof_block) return;
     hipEvent_t a = prof_event(h), b = prof_event(h);
     if (!a || !b) return;
     hipEventRecord(a, h->stream);
@@ -407,6 +408,91 @@ ozII_status get_plan(ozII_ctx *h, int p, int64_t K, const ozII_opts *o, const Ho
   }
   *hp = &it->second.first;
   *dp = it->second.second;
+  return OZII_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch of ozII_gemm_noalloc, for callers that cannot allocate
+// device memory.  Each GPU the library runs on holds its own copy of the
+// array until the process ends.  Host code never passes the array's name to
+// a kernel or a copy: ozII_create maps it once per device with
+// hipGetSymbolAddress (device current) and every use goes through that
+// per-device address.  Layout: NOALLOC_SLOTS plan tables of
+// NOALLOC_SLOT_BYTES each, then the workspace of one product.
+// ---------------------------------------------------------------------------
+constexpr size_t NOALLOC_BYTES = (size_t)64 << 20;
+constexpr int NOALLOC_SLOTS = 8;
+constexpr size_t NOALLOC_SLOT_BYTES = 32 << 10;
+constexpr size_t NOALLOC_WS_OFF = NOALLOC_SLOTS * NOALLOC_SLOT_BYTES;
+static_assert(sizeof(DevPlan) <= NOALLOC_SLOT_BYTES, "plan slot too small");
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+struct NoallocDev {
+  char *base = nullptr;         // device address of `scratch` on this device
+  hipError_t map_err = hipSuccess;
+  bool used[NOALLOC_SLOTS] = {};
+  std::tuple<int, int64_t, int, int, int, int> key[NOALLOC_SLOTS];
+  HostPlan host_plan[NOALLOC_SLOTS];
+  DevPlan host_dev[NOALLOC_SLOTS];  // the uploaded tables (source of the copies)
+  int next = 0;
+};
+std::mutex g_noalloc_mu;
+std::map<int, NoallocDev> g_noalloc;
+
+// Map the static scratch on the current device (once per device).
+void noalloc_map(int device) {
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  NoallocDev &nd = g_noalloc[device];
+  if (nd.base || nd.map_err != hipSuccess) return;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    nd.map_err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+    return;
+  }
+  nd.base = (char *)ptr;
+}
+
+// The plan of (p, K, o) in one of the device's scratch slots: the tables are
+// built on the host and copied into a slot on the handle's stream the first
+// time a plan is used (or after it was evicted by NOALLOC_SLOTS others).
+ozII_status noalloc_plan(ozII_ctx *h, int p, int64_t K, const ozII_opts *o, const HostPlan **hp,
+                         const DevPlan **dp, char **ws) {
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  auto it = g_noalloc.find(h->device);
+  if (it == g_noalloc.end() || !it->second.base)
+    return fail(h, OZII_EHIP, std::string("static scratch not mapped: ") +
+                                  hipGetErrorString(it == g_noalloc.end() ? hipErrorInvalidSymbol
+                                                                          : it->second.map_err));
+  NoallocDev &nd = it->second;
+  const int backend = (o && o->backend) ? o->backend : OZII_BE_INT8;
+  const auto key = std::make_tuple(p, K, backend, o ? o->nslice : 0, o ? o->extra_groups : 0,
+                                   (o ? o->guard_ex : 0) * 2);
+  *ws = nd.base + NOALLOC_WS_OFF;
+  for (int sl = 0; sl < NOALLOC_SLOTS; ++sl)
+    if (nd.used[sl] && nd.key[sl] == key) {
+      *hp = &nd.host_plan[sl];
+      *dp = (const DevPlan *)(nd.base + sl * NOALLOC_SLOT_BYTES);
+      return OZII_OK;
+    }
+  HostPlan pl;
+  std::string why;
+  const ozII_status st = make_plan(p, K, o, pl, &why, true);
+  if (st != OZII_OK) return fail(h, st, "plan: " + why);
+  const int sl = nd.next;
+  nd.next = (nd.next + 1) % NOALLOC_SLOTS;
+  nd.used[sl] = false;
+  nd.host_plan[sl] = pl;
+  build_devplan(pl, nd.host_dev[sl]);
+  char *dst = nd.base + sl * NOALLOC_SLOT_BYTES;
+  const hipError_t e = hipMemcpyAsync(dst, &nd.host_dev[sl], sizeof(DevPlan),
+                                      hipMemcpyHostToDevice, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "plan upload");
+  nd.used[sl] = true;
+  nd.key[sl] = key;
+  *hp = &nd.host_plan[sl];
+  *dp = (const DevPlan *)dst;
   return OZII_OK;
 }
 
@@ -495,7 +581,7 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
                       const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
                       int64_t ldc, const ozII_opts *o, int32_t *ea_out, int32_t *eb_out,
                       void *pa_out, void *pb_out, void *tpl_out, uint64_t *sbar_out,
-                      int nlimb) {
+                      int nlimb, bool noalloc = false) {
   if (!h) return OZII_EINVAL;
   if (!valid_nc(nc)) return fail(h, OZII_EUNSUPPORTED, "nc must be 2, 3 or 4");
   if (mode != 0 && mode != 1) return fail(h, OZII_EINVAL, "mode must be 0 or 1");
@@ -512,12 +598,27 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
   }
   const HostPlan *hp;
   const DevPlan *dp;
-  ozII_status st = get_plan(h, 53 * nc, K, o, &hp, &dp);
-  if (st != OZII_OK) return st;
+  char *ws = nullptr;
+  ozII_status st;
+  if (noalloc) {
+    st = noalloc_plan(h, 53 * nc, K, o, &hp, &dp, &ws);
+    if (st != OZII_OK) return st;
+  } else {
+    st = get_plan(h, 53 * nc, K, o, &hp, &dp);
+    if (st != OZII_OK) return st;
+  }
   GemmLayout L = gemm_layout(*hp, M, N, K, o ? o->gemm_tile : 0);
-  st = ensure_ws(h, L.total);
-  if (st != OZII_OK) return st;
-  char *ws = h->ws;
+  if (noalloc) {
+    if (L.total > NOALLOC_BYTES - NOALLOC_WS_OFF)
+      return fail(h, OZII_EINVAL,
+                  "ozII_gemm_noalloc: the product needs " + std::to_string(L.total) +
+                      " bytes of workspace, the static scratch holds " +
+                      std::to_string(NOALLOC_BYTES - NOALLOC_WS_OFF));
+  } else {
+    st = ensure_ws(h, L.total);
+    if (st != OZII_OK) return st;
+    ws = h->ws;
+  }
   int32_t *ea = (int32_t *)(ws + L.off_ea);
   int32_t *eb = (int32_t *)(ws + L.off_eb);
   void *pa = ws + L.off_pa;
@@ -754,6 +855,9 @@ ozII_status ozII_create(ozII_handle *out, int device, void *stream) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return OZII_EINVAL;
   if (hipSetDevice(device) != hipSuccess) return OZII_EHIP;
+  // the static scratch of ozII_gemm_noalloc, mapped with this device
+  // current (a failure is reported by ozII_gemm_noalloc, not here)
+  noalloc_map(device);
   ozII_ctx *h = new ozII_ctx();
   h->device = device;
   h->stream = (hipStream_t)stream;
@@ -833,6 +937,23 @@ ozII_status ozII_gemm(ozII_handle h, int32_t mode, int32_t nc, int64_t M, int64_
                       int64_t ldc, const ozII_opts *o) {
   return gemm_impl(h, mode, nc, M, N, K, A, lda, B, ldb, C, ldc, o, nullptr, nullptr, nullptr,
                    nullptr, nullptr, nullptr, 0);
+}
+
+ozII_status ozII_gemm_noalloc(ozII_handle h, int32_t mode, int32_t nc, int64_t M, int64_t N,
+                              int64_t K, const double *A, int64_t lda, const double *B,
+                              int64_t ldb, double *C, int64_t ldc, const ozII_opts *o) {
+  if (!h) return OZII_EINVAL;
+  ++h->prof_block;
+  const ozII_status st = gemm_impl(h, mode, nc, M, N, K, A, lda, B, ldb, C, ldc, o, nullptr,
+                                   nullptr, nullptr, nullptr, nullptr, nullptr, 0, true);
+  --h->prof_block;
+  return st;
+}
+
+ozII_status ozII_gemm_noalloc_capacity(int64_t *bytes) {
+  if (!bytes) return OZII_EINVAL;
+  *bytes = (int64_t)(NOALLOC_BYTES - NOALLOC_WS_OFF);
+  return OZII_OK;
 }
 
 ozII_status ozII_gemm_stages(ozII_handle h, int32_t mode, int32_t nc, int64_t M, int64_t N,
