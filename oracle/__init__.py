@@ -10,7 +10,10 @@ expansion, Sec. 2 of the paper).  Element (i, j) component c is ``X[j, i, c]``,
 i.e. flat index ``(i + j*rows)*nc + c``.
 
 The heavy lifting is in ``oracle.c`` (plain C, its own big integers, built
-with ``-ffp-contract=off``); ``plan.py`` holds the plan rule.
+with ``-ffp-contract=off``) and ``lfloat.c`` (p-bit floating point with
+correct rounding and the LU on it, used at twice the working precision);
+``plan.py`` holds the plan rule, ``limbs.py`` the limb-format product and
+``lfloat.py`` the p-bit LU.
 """
 from __future__ import annotations
 
@@ -32,11 +35,11 @@ _lib = None
 def build(force: bool = True) -> str:
     """Compile oracle.c into liboracle.so (plain gcc, no GPU code)."""
     import subprocess
-    src = os.path.join(_HERE, "oracle.c")
+    srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "lfloat.c")]
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math",
-                               "-fopenmp", "-shared", "-fPIC", "-o", tmp, src])
+                               "-fopenmp", "-shared", "-fPIC", "-o", tmp] + srcs)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -82,6 +85,12 @@ def _declare(L):
     L.orc_getrf.argtypes = [_int, _i64, _dp, _i64, _i64, _int, _int, _int, _int, _i64p, _i32p,
                             _dp]
     L.orc_getrs.argtypes = [_int, _i64, _dp, _i64, _i64p, _i64, _dp, _i64]
+    L.orc_lf_vec.argtypes = [_int, _int, _i64, _u64p, _i64p, _u8p, _u64p, _i64p, _u8p, _u64p,
+                             _i64p, _u8p]
+    L.orc_lf_from_doubles.argtypes = [_int, _i64, _int, _dp, _u64p, _i64p, _u8p]
+    L.orc_lf_getrf.argtypes = [_int, _i64, _u64p, _i64p, _u8p, _i64, _i64p, _i32p]
+    L.orc_lf_getrs.argtypes = [_int, _i64, _u64p, _i64p, _u8p, _i64, _i64p, _i64, _u64p, _i64p,
+                               _u8p, _i64]
 
 
 def _p(a, t):
