@@ -75,11 +75,17 @@ typedef struct {
   int32_t guard_ex;     /* extra guard bits g_ex added to the slack (Sec. 3.2) */
   int32_t block;        /* getrf panel width b; 0 = 256                        */
   int32_t method;       /* getrf Schur update: ozII_method                     */
-  int32_t flags;        /* reserved, must be 0                                 */
+  int32_t flags;        /* OZII_F_* bits below; 0 = defaults                   */
   int32_t gemm_tile;    /* (S4) workgroup tile: ozII_gemm_tile; the residue   */
                         /* planes are padded to it.  Results do not depend on */
                         /* it (exact integer products).                       */
 } ozII_opts;
+
+/* ozII_opts.flags.  OZII_F_NO_LOOKAHEAD: getrf runs each Schur update as
+ * one product after its panel, instead of updating the next panel's columns
+ * first and the rest on a side stream while the next panel is factored
+ * (the default).  The results are the same bit for bit. */
+#define OZII_F_NO_LOOKAHEAD 1
 
 typedef struct ozII_ctx *ozII_handle;
 
@@ -289,23 +295,27 @@ ozII_status ozII_batch_prepare_ex(ozII_handle h, int32_t count, const ozII_batch
 ozII_status ozII_batch_run(ozII_handle h, uint64_t *times);
 
 /* Autotuner (the tuning step of Sec. 4.1, "only timing at the actual size is
- * trustworthy"): chooses the panel width b (64, 128, 256, 512 below n) and
- * the Schur update -- one of the three back-ends or the native expansion
- * update -- for nc-component expansions and order n.  Candidates are ordered
- * by a cost model (engine throughput x bits per modulus, plane and t-plane
- * traffic) and every one is timed with HIP events around ozII_getrf of a
- * synthetic diagonally dominant n x n matrix on the handle's stream; the
- * fastest is returned in *best (block, backend, method; other fields 0).
- * Candidates the library cannot run at this size (OZII_EUNSUPPORTED: a panel
- * that does not fit in LDS, a plan beyond the compiled word sizes) are
- * skipped; the report lists the timed ones.
+ * trustworthy"), for nc-component expansions and order n.  Stage 1 times the
+ * panel width b (64, 128, 256, 512 below n) x the Schur update -- one of the
+ * three back-ends or the native expansion update -- x the schedule (with or
+ * without OZII_F_NO_LOOKAHEAD); stage 2 times the winner (if Ozaki-II) with
+ * the slice count S one above the plan rule's minimum (Eq. Lhint trades
+ * slices against conversion cost) and, on the INT8 back-end, with each GEMM
+ * tile.  Candidates are ordered by a cost model (engine throughput x bits
+ * per modulus, plane and t-plane traffic, panel cost) and every one is timed
+ * with HIP events around ozII_getrf of a synthetic diagonally dominant n x n
+ * matrix on the handle's stream; the fastest is returned in *best (block,
+ * backend, method, nslice, gemm_tile, flags; other fields 0).  Candidates
+ * the library cannot run at this size (OZII_EUNSUPPORTED: a panel that does
+ * not fit in LDS, a plan beyond the compiled word sizes) are skipped; the
+ * report lists the timed ones.
  * With a cache path (host file, JSON array with one object per line, keyed by
  * the device's architecture name, nc and n) a cached choice is returned
  * without timing unless OZII_TUNE_RETUNE is set, and a new choice is stored.
  * Allocates a scratch matrix of n*n*nc doubles for the duration of the call
  * and synchronises the stream; rep may be null. */
 #define OZII_TUNE_RETUNE 1
-#define OZII_TUNE_MAXCAND 16
+#define OZII_TUNE_MAXCAND 40
 typedef struct {
   int32_t ncand;                         /* candidates timed (1 when cached)     */
   int32_t best;                          /* index of the choice                  */

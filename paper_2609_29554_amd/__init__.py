@@ -24,6 +24,7 @@ OK, EINVAL, ECAPACITY, EOVERFLOW, ENOMEM, EHIP, EUNSUPPORTED, EDEVICE = range(8)
 BE_AUTO, BE_INT8, BE_FP8_B17, BE_F64MOD = range(4)
 METHOD_OZAKI, METHOD_NAIVE = 0, 1
 TILE_AUTO, TILE_128x128, TILE_256x128, TILE_256x256 = range(4)
+F_NO_LOOKAHEAD = 1
 
 
 class OziiError(RuntimeError):
@@ -65,7 +66,7 @@ class BatchItem(C.Structure):
 
 
 TUNE_RETUNE = 1
-TUNE_MAXCAND = 16
+TUNE_MAXCAND = 40
 
 
 class TuneReport(C.Structure):
@@ -139,8 +140,8 @@ def noalloc_capacity() -> int:
 
 
 def make_opts(backend: int = 0, nslice: int = 0, extra_groups: int = 0, guard_ex: int = 0,
-              block: int = 0, method: int = 0, gemm_tile: int = 0) -> Opts:
-    return Opts(backend, nslice, extra_groups, guard_ex, block, method, 0, gemm_tile)
+              block: int = 0, method: int = 0, gemm_tile: int = 0, flags: int = 0) -> Opts:
+    return Opts(backend, nslice, extra_groups, guard_ex, block, method, flags, gemm_tile)
 
 
 def plan_query(p: int, K: int, opts: Optional[Opts] = None):
@@ -474,7 +475,8 @@ class Context:
             o = rep.cand[i]
             cands.append({"block": o.block,
                           "update": "native" if o.method == METHOD_NAIVE else names.get(o.backend, "?"),
-                          "ms": rep.ms[i], "model_ms": rep.model_ms[i]})
+                          "lookahead": not (o.flags & F_NO_LOOKAHEAD), "nslice": o.nslice,
+                          "gemm_tile": o.gemm_tile, "ms": rep.ms[i], "model_ms": rep.model_ms[i]})
         return best, {"from_cache": bool(rep.from_cache), "best": rep.best, "candidates": cands}
 
     def sync_check(self):

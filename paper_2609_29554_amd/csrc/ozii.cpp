@@ -319,6 +319,10 @@ struct ozII_ctx {
   int *perm = nullptr, *moved = nullptr, *nmoved = nullptr;
   int64_t panel_n = 0;
   int panel_kb = 0;
+  // getrf look-ahead: a side stream (default priority) for the rest of each
+  // Schur update while the next panel runs, and the fork / join events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // batched LU: the uploaded item table (processing order) and its queue
   ozII_batch_item *batch = nullptr;
   int batch_cap = 0, batch_count = 0, batch_grid = 1;
@@ -365,19 +369,23 @@ hipEvent_t prof_event(ozII_ctx *h) {
 }
 
 // Bracket one launch with events when profiling is on.
+// Bracket one launch with events when profiling is on, on the stream the
+// launch goes to (the handle's stream unless given).
 struct ProfScope {
   ozII_ctx *h;
+  hipStream_t s;
   int idx = -1;
-  ProfScope(ozII_ctx *hh, int stage, double bytes, double ops) : h(hh) {
+  ProfScope(ozII_ctx *hh, int stage, double bytes, double ops) : ProfScope(hh, stage, bytes, ops, hh->stream) {}
+  ProfScope(ozII_ctx *hh, int stage, double bytes, double ops, hipStream_t st) : h(hh), s(st) {
     if (!h->profiling || h->prof_block) return;
     hipEvent_t a = prof_event(h), b = prof_event(h);
     if (!a || !b) return;
-    hipEventRecord(a, h->stream);
+    hipEventRecord(a, s);
     h->prof.push_back({stage, a, b, bytes, ops});
     idx = (int)h->prof.size() - 1;
   }
   ~ProfScope() {
-    if (idx >= 0) hipEventRecord(h->prof[idx].b, h->stream);
+    if (idx >= 0) hipEventRecord(h->prof[idx].b, s);
   }
 };
 
@@ -581,8 +589,10 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
                       const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
                       int64_t ldc, const ozII_opts *o, int32_t *ea_out, int32_t *eb_out,
                       void *pa_out, void *pb_out, void *tpl_out, uint64_t *sbar_out,
-                      int nlimb, bool noalloc = false) {
+                      int nlimb, bool noalloc = false, hipStream_t stream = nullptr,
+                      char *ws_given = nullptr, size_t ws_cap = 0) {
   if (!h) return OZII_EINVAL;
+  hipStream_t s = ws_given ? stream : h->stream;
   if (!valid_nc(nc)) return fail(h, OZII_EUNSUPPORTED, "nc must be 2, 3 or 4");
   if (mode != 0 && mode != 1) return fail(h, OZII_EINVAL, "mode must be 0 or 1");
   if (M < 0 || N < 0 || K < 0) return fail(h, OZII_EINVAL, "negative size");
@@ -593,7 +603,7 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
   if (K == 0) {
     if (mode == 1) return OZII_OK;
     // C = 0 (a fill kernel: stays correct inside a captured graph)
-    hipError_t e = ozl::launch_zero_expansions(nc, C, ldc, M, N, h->stream);
+    hipError_t e = ozl::launch_zero_expansions(nc, C, ldc, M, N, s);
     return e == hipSuccess ? OZII_OK : hip_fail(h, e, "zero C");
   }
   const HostPlan *hp;
@@ -614,6 +624,9 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
                   "ozII_gemm_noalloc: the product needs " + std::to_string(L.total) +
                       " bytes of workspace, the static scratch holds " +
                       std::to_string(NOALLOC_BYTES - NOALLOC_WS_OFF));
+  } else if (ws_given) {
+    if (L.total > ws_cap) return fail(h, OZII_EINVAL, "internal: workspace region too small");
+    ws = ws_given;
   } else {
     st = ensure_ws(h, L.total);
     if (st != OZII_OK) return st;
@@ -624,7 +637,6 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
   void *pa = ws + L.off_pa;
   void *pb = ws + L.off_pb;
   void *tpl = ws + L.off_tpl;
-  hipStream_t s = h->stream;
   hipError_t e;
   const double pairs = (double)hp->nmod * [&] {
     int np = 0;
@@ -637,18 +649,18 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
   const double res_bytes = (double)hp->S * hp->nmod * hp->planes_per() * hp->el_bytes();
   const double t_bytes = (double)hp->ng * hp->nmod * hp->t_bytes();
   {
-    ProfScope ps(h, OZ_STAGE_EXP, 8.0 * nc * (double)(M * K + K * N), 0);
+    ProfScope ps(h, OZ_STAGE_EXP, 8.0 * nc * (double)(M * K + K * N), 0, s);
     if ((e = ozl::launch_exponents(nc, A, lda, M, K, 1, ea, s)) != hipSuccess) return hip_fail(h, e, "exponents(A)");
     if ((e = ozl::launch_exponents(nc, B, ldb, K, N, 0, eb, s)) != hipSuccess) return hip_fail(h, e, "exponents(B)");
   }
   {
-    ProfScope ps(h, OZ_STAGE_PRODUCER, (double)M * K * (8.0 * nc + res_bytes), 0);
+    ProfScope ps(h, OZ_STAGE_PRODUCER, (double)M * K * (8.0 * nc + res_bytes), 0, s);
     if ((e = ozl::launch_producer(nc, hp->nwx, hp->nh, (hp->w + 2 + 31) / 32, A, lda, 1, M, L.Mp, K, L.Kp, ea, dp,
                                   hp->planes_kind(), pa, L.planeA, s)) != hipSuccess)
       return hip_fail(h, e, "producer(A)");
   }
   {
-    ProfScope ps(h, OZ_STAGE_PRODUCER, (double)N * K * (8.0 * nc + res_bytes), 0);
+    ProfScope ps(h, OZ_STAGE_PRODUCER, (double)N * K * (8.0 * nc + res_bytes), 0, s);
     if ((e = ozl::launch_producer(nc, hp->nwx, hp->nh, (hp->w + 2 + 31) / 32, B, ldb, 0, N, L.Np, K, L.Kp, eb, dp,
                                   hp->planes_kind(), pb, L.planeB, s)) != hipSuccess)
       return hip_fail(h, e, "producer(B)");
@@ -656,7 +668,7 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
   {
     // issued operations: the FP8 back-end runs four sub-products per pair
     const double ops = 2.0 * (double)M * N * K * pairs * (hp->backend == OZII_BE_FP8_B17 ? 4.0 : 1.0);
-    ProfScope ps(h, OZ_STAGE_GEMM, res_bytes * (double)(M + N) * K + t_bytes * M * N, ops);
+    ProfScope ps(h, OZ_STAGE_GEMM, res_bytes * (double)(M + N) * K + t_bytes * M * N, ops, s);
     if (hp->backend == OZII_BE_FP8_B17)
       e = ozl::launch_gemm_f8((const uint8_t *)pa, (const uint8_t *)pb, (uint8_t *)tpl, dp, hp->ng,
                               hp->nmod, L.Mp, L.Np, L.Kp, L.planeA, L.planeB, s);
@@ -682,7 +694,7 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
   if (sbar_out && (e = ozl::launch_crt_export(tpl, hp->t_bytes(), hp->nd, L.Mp, L.Np, M, N, dp, sbar_out, nlimb, s)) != hipSuccess)
     return hip_fail(h, e, "crt_export");
   {
-    ProfScope ps(h, OZ_STAGE_CONSUMER, (double)M * N * (t_bytes + 8.0 * nc * (mode ? 2 : 1)), 0);
+    ProfScope ps(h, OZ_STAGE_CONSUMER, (double)M * N * (t_bytes + 8.0 * nc * (mode ? 2 : 1)), 0, s);
     if ((e = ozl::launch_consumer(nc, hp->nwc, hp->nd, tpl, hp->t_bytes(), L.Mp, L.Np, C, ldc, M, N,
                                   ea, eb, dp, mode, s)) != hipSuccess)
       return hip_fail(h, e, "consumer");
@@ -830,6 +842,38 @@ ozII_status gemm_limbs_impl(ozII_ctx *h, int mode, int nlimb, int64_t M, int64_t
   return OZII_OK;
 }
 
+// The side stream and the fork / join events of the look-ahead (created on
+// first use, on the handle's device, at the default priority).
+ozII_status ensure_side(ozII_ctx *h) {
+  if (h->side) return OZII_OK;
+  hipError_t e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming);
+  if (e != hipSuccess) return hip_fail(h, e, "look-ahead stream");
+  return OZII_OK;
+}
+
+// Workspace of getrf's Ozaki-II updates: one region for the look-ahead
+// columns (the next panel's, on the handle's stream) and one for the rest of
+// the update (on the side stream), which run concurrently.
+struct LuWs {
+  size_t la_off = 0, la_cap = 0, rest_off = 0, rest_cap = 0, total = 0;
+};
+
+LuWs lu_workspace(const HostPlan &hp, int64_t n, int b, int tile, bool lookahead) {
+  LuWs w;
+  if (n <= b) return w;
+  if (!lookahead) {  // one product per step over the whole trailing matrix
+    w.la_cap = w.total = gemm_layout(hp, n - b, n - b, b, tile).total;
+    return w;
+  }
+  w.la_cap = gemm_layout(hp, n - b, b, b, tile).total;
+  w.rest_off = (w.la_cap + 255) / 256 * 256;
+  w.rest_cap = n > 2 * b ? gemm_layout(hp, n - b, n - 2 * b, b, tile).total : 0;
+  w.total = w.rest_off + w.rest_cap;
+  return w;
+}
+
 }  // namespace
 
 extern "C" {
@@ -871,6 +915,12 @@ ozII_status ozII_destroy(ozII_handle h) {
   if (h->ws) hipFree(h->ws);
   for (auto &kv : h->plans) hipFree(kv.second.second);
   for (auto ev : h->pool) hipEventDestroy(ev);
+  if (h->side) {
+    hipStreamSynchronize(h->side);
+    hipStreamDestroy(h->side);
+  }
+  if (h->ev_fork) hipEventDestroy(h->ev_fork);
+  if (h->ev_join) hipEventDestroy(h->ev_join);
   if (h->batch) hipFree(h->batch);
   if (h->batch_queue) hipFree(h->batch_queue);
   if (h->batch_ws) hipFree(h->batch_ws);
@@ -925,8 +975,13 @@ ozII_status ozII_reserve(ozII_handle h, int32_t nc, int64_t M, int64_t N, int64_
       const DevPlan *dp;
       st = get_plan(h, 53 * nc, b, o, &hp, &dp);
       if (st != OZII_OK) return st;
-      st = ensure_ws(h, gemm_layout(*hp, n - b, n - b, b, o ? o->gemm_tile : 0).total);
+      const bool la = !(o && (o->flags & OZII_F_NO_LOOKAHEAD));
+      st = ensure_ws(h, lu_workspace(*hp, n, b, o ? o->gemm_tile : 0, la).total);
       if (st != OZII_OK) return st;
+      if (la) {
+        st = ensure_side(h);
+        if (st != OZII_OK) return st;
+      }
     }
   }
   return OZII_OK;
@@ -992,22 +1047,56 @@ ozII_status ozII_getrf(ozII_handle h, int32_t nc, int64_t n, double *A, int64_t 
   if (!A || !ipiv || !info) return fail(h, OZII_EINVAL, "null pointer");
   const int b = (o && o->block > 0) ? o->block : 256;
   const int method = o ? o->method : OZII_METHOD_OZAKI;
+  const int flags = o ? o->flags : 0;
   if (b > 512) return fail(h, OZII_EUNSUPPORTED, "panel width above 512");
   if (method != OZII_METHOD_OZAKI && method != OZII_METHOD_NAIVE) return fail(h, OZII_EINVAL, "bad method");
+  if (flags & ~OZII_F_NO_LOOKAHEAD) return fail(h, OZII_EINVAL, "unknown flags");
   if (n > (int64_t)1 << 20) return fail(h, OZII_EUNSUPPORTED, "n too large");
+  const bool lookahead = !(flags & OZII_F_NO_LOOKAHEAD);
   ozII_status st = ensure_panel(h, n, b);
   if (st != OZII_OK) return st;
+  LuWs W;
   if (method == OZII_METHOD_OZAKI && n > b) {
     const HostPlan *hp;
     const DevPlan *dp;
     st = get_plan(h, 53 * nc, b, o, &hp, &dp);
     if (st != OZII_OK) return st;
-    st = ensure_ws(h, gemm_layout(*hp, n - b, n - b, b, o ? o->gemm_tile : 0).total);
+    W = lu_workspace(*hp, n, b, o ? o->gemm_tile : 0, lookahead);
+    st = ensure_ws(h, W.total);
+    if (st != OZII_OK) return st;
+  }
+  if (lookahead && n > b) {
+    st = ensure_side(h);
     if (st != OZII_OK) return st;
   }
   hipStream_t s = h->stream;
   hipError_t e;
+  // C -= L21 U12 on columns [c0, c0 + nb) of the trailing matrix at step k,
+  // on stream st with workspace region (off, cap)
+  auto update = [&](int64_t k, int kb, int64_t c0, int64_t nb, hipStream_t st_, size_t off,
+                    size_t cap) -> ozII_status {
+    const int64_t m2 = n - k - kb;
+    const double *L21 = A + ((k + kb) + k * lda) * nc;
+    const double *U12 = A + (k + (k + kb + c0) * lda) * nc;
+    double *A22 = A + ((k + kb) + (k + kb + c0) * lda) * nc;
+    if (method == OZII_METHOD_OZAKI)
+      return gemm_impl(h, 1, nc, m2, nb, kb, L21, lda, U12, lda, A22, lda, o, nullptr, nullptr,
+                       nullptr, nullptr, nullptr, nullptr, 0, false, st_, h->ws + off, cap);
+    ProfScope ps(h, OZ_STAGE_NAIVE, 16.0 * nc * (double)m2 * nb + 16.0 * nc * (double)(m2 + nb) * kb,
+                 (double)m2 * nb * kb, st_);
+    const hipError_t ee = ozl::launch_naive_gemm(nc, L21, lda, U12, lda, A22, lda, m2, nb, kb, 0, st_);
+    return ee == hipSuccess ? OZII_OK : hip_fail(h, ee, "naive update");
+  };
+  auto trsm = [&](int64_t k, int kb, int64_t c0, int64_t nb, hipStream_t st_) -> ozII_status {
+    const double *L11 = A + (k + k * lda) * nc;
+    double *A12 = A + (k + (k + kb + c0) * lda) * nc;
+    ProfScope ps(h, OZ_STAGE_TRSM, 16.0 * nc * (double)kb * nb + 8.0 * nc * kb * kb / 2.0,
+                 (double)nb * kb * kb / 2.0, st_);
+    const hipError_t ee = ozl::launch_trsm_lower_unit(nc, L11, lda, A12, lda, kb, nb, st_);
+    return ee == hipSuccess ? OZII_OK : hip_fail(h, ee, "trsm");
+  };
   if ((e = ozl::launch_fill_int(info, 0, 1, s)) != hipSuccess) return hip_fail(h, e, "fill info");
+  bool side_busy = false;
   for (int64_t k = 0; k < n; k += b) {
     const int kb = (int)std::min<int64_t>(b, n - k);
     const int64_t nr = n - k;
@@ -1044,39 +1133,41 @@ ozII_status ozII_getrf(ozII_handle h, int32_t nc, int64_t n, double *A, int64_t 
     // a panel that stops early leaves no moved rows behind for laswp
     if ((e = ozl::launch_fill_int(h->nmoved, 0, 1, s)) != hipSuccess) return hip_fail(h, e, "fill nmoved");
     {
+      // (P1) panel k; with look-ahead it runs while the side stream finishes
+      // the previous step's update on the columns right of it
       ProfScope ps(h, OZ_STAGE_PANEL, 16.0 * nc * (double)nr * kb, (double)nr * kb * kb / 2.0);
       if ((e = ozl::launch_panel(nc, A, lda, n, k, kb, R, G, ipiv, info, h->flags, h->err, h->crow,
                                  h->perm, h->moved, h->nmoved, s)) != hipSuccess)
         return hip_fail(h, e, "panel");
+    }
+    if (side_busy) {
+      // join: the interchanges below touch the columns the side stream updates
+      if ((e = hipEventRecord(h->ev_join, h->side)) != hipSuccess) return hip_fail(h, e, "join record");
+      if ((e = hipStreamWaitEvent(s, h->ev_join, 0)) != hipSuccess) return hip_fail(h, e, "join wait");
+      side_busy = false;
     }
     {
       ProfScope ps(h, OZ_STAGE_LASWP, 32.0 * nc * (double)kb * n, 0);
       if ((e = ozl::launch_laswp(nc, A, lda, k, 0, n, h->perm, h->moved, h->nmoved, s)) != hipSuccess)
         return hip_fail(h, e, "laswp");
     }
-    if (k + kb < n) {
-      const int64_t m2 = n - k - kb;
-      const double *L11 = A + (k + k * lda) * nc;
-      double *A12 = A + (k + (k + kb) * lda) * nc;
-      {
-        ProfScope ps(h, OZ_STAGE_TRSM, 16.0 * nc * (double)kb * m2 + 8.0 * nc * kb * kb / 2.0,
-                     (double)m2 * kb * kb / 2.0);
-        if ((e = ozl::launch_trsm_lower_unit(nc, L11, lda, A12, lda, kb, m2, s)) != hipSuccess)
-          return hip_fail(h, e, "trsm");
-      }
-      const double *L21 = A + ((k + kb) + k * lda) * nc;
-      double *A22 = A + ((k + kb) + (k + kb) * lda) * nc;
-      if (method == OZII_METHOD_OZAKI) {
-        st = gemm_impl(h, 1, nc, m2, m2, kb, L21, lda, A12, lda, A22, lda, o, nullptr, nullptr,
-                       nullptr, nullptr, nullptr, nullptr, 0);
-        if (st != OZII_OK) return st;
-      } else {
-        ProfScope ps(h, OZ_STAGE_NAIVE, 16.0 * nc * (double)m2 * m2 + 16.0 * nc * (double)m2 * kb,
-                     (double)m2 * m2 * kb);
-        if ((e = ozl::launch_naive_gemm(nc, L21, lda, A12, lda, A22, lda, m2, m2, kb, 0, s)) != hipSuccess)
-          return hip_fail(h, e, "naive update");
-      }
+    if (k + kb >= n) break;
+    const int64_t m2 = n - k - kb;
+    // (P3) + (P4): the next panel's columns first (look-ahead), then the rest
+    const int64_t la = lookahead ? std::min<int64_t>(b, m2) : m2;
+    if ((st = trsm(k, kb, 0, la, s)) != OZII_OK) return st;
+    if ((st = update(k, kb, 0, la, s, 0, W.la_cap)) != OZII_OK) return st;
+    if (la < m2) {
+      if ((e = hipEventRecord(h->ev_fork, s)) != hipSuccess) return hip_fail(h, e, "fork record");
+      if ((e = hipStreamWaitEvent(h->side, h->ev_fork, 0)) != hipSuccess) return hip_fail(h, e, "fork wait");
+      if ((st = trsm(k, kb, la, m2 - la, h->side)) != OZII_OK) return st;
+      if ((st = update(k, kb, la, m2 - la, h->side, W.rest_off, W.rest_cap)) != OZII_OK) return st;
+      side_busy = true;
     }
+  }
+  if (side_busy) {
+    if ((e = hipEventRecord(h->ev_join, h->side)) != hipSuccess) return hip_fail(h, e, "join record");
+    if ((e = hipStreamWaitEvent(s, h->ev_join, 0)) != hipSuccess) return hip_fail(h, e, "join wait");
   }
   return OZII_OK;
 }

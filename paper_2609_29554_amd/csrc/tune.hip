@@ -1,13 +1,17 @@
-// Autotuner of the LU configuration (panel width b, Schur-update back-end or
-// the native update) for one precision and order n.
+// Autotuner of the LU configuration for one precision and order n: panel
+// width b, Schur-update back-end (or the native update), the schedule (with
+// or without look-ahead), then for the winner the slice count S and the
+// (S4) workgroup tile.
 //
 // The paper sizes the slices with a cost model (Eq. Lhint) and ranks the
 // engines by bits per modulus times throughput, but finds that only timing at
 // the actual size is trustworthy (Sec. 4.1).  Here the model only orders the
 // candidates; every feasible candidate is then timed with HIP events around
 // a full ozII_getrf of a synthetic diagonally dominant matrix of the
-// requested order, and the fastest wins.  Results are cached in a JSON file,
-// one object per line, keyed by device, component count and n.
+// requested order, and the fastest wins.  Stage 2 times the winner with S
+// one above the plan rule's minimum (Eq. Lhint trades slices against
+// conversion cost) and with each GEMM tile.  Results are cached in a JSON
+// file, one object per line, keyed by device, component count and n.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -72,7 +76,8 @@ double peak_ops(int backend) {
 // at ~20 us per column.
 double model_ms(int nc, int64_t n, const ozII_opts &o) {
   const int b = o.block;
-  double t = 20e-6 * (double)n;
+  const double panel = 20e-6 * (double)n;
+  double t = 0.0;
   for (int64_t k = 0; k + b < n; k += b) {
     const double m = (double)(n - k - b);
     if (o.method == OZII_METHOD_NAIVE) {
@@ -89,7 +94,9 @@ double model_ms(int nc, int64_t n, const ozII_opts &o) {
     const double bytes = 2.0 * m * b * (8.0 * nc + S * N * br) + 2.0 * ng * N * m * m * bt + 16.0 * nc * m * m;
     t += ops / (0.25 * peak_ops(o.backend)) + bytes / 4e12;
   }
-  return t * 1e3;
+  // look-ahead: the update runs beside the next panel on half the device
+  if (!(o.flags & OZII_F_NO_LOOKAHEAD)) t = std::max(0.0, 2.0 * t - panel) + 0.1 * t;
+  return (panel + t) * 1e3;
 }
 
 std::string device_key(int nc, int64_t n) {
@@ -109,14 +116,14 @@ bool cache_lookup(const char *path, const std::string &key, ozII_opts *o, double
   std::string line, want = "\"key\": \"" + key + "\"";
   while (std::getline(f, line)) {
     if (line.find(want) == std::string::npos) continue;
-    int be = 0, me = 0, b = 0, s = 0, t = 0;
+    int be = 0, me = 0, b = 0, s = 0, t = 0, fl = 0;
     double v = 0;
     const size_t p = line.find("\"backend\"");
     if (p == std::string::npos) return false;
     if (std::sscanf(line.c_str() + p,
                     "\"backend\": %d, \"method\": %d, \"block\": %d, \"nslice\": %d, "
-                    "\"gemm_tile\": %d, \"ms\": %lf",
-                    &be, &me, &b, &s, &t, &v) != 6)
+                    "\"gemm_tile\": %d, \"flags\": %d, \"ms\": %lf",
+                    &be, &me, &b, &s, &t, &fl, &v) != 7)
       return false;
     std::memset(o, 0, sizeof(*o));
     o->backend = be;
@@ -124,6 +131,7 @@ bool cache_lookup(const char *path, const std::string &key, ozII_opts *o, double
     o->block = b;
     o->nslice = s;
     o->gemm_tile = t;
+    o->flags = fl;
     *ms = v;
     return true;
   }
@@ -144,8 +152,8 @@ void cache_store(const char *path, const std::string &key, const ozII_opts &o, d
   char buf[512];
   std::snprintf(buf, sizeof(buf),
                 "{\"key\": \"%s\", \"backend\": %d, \"method\": %d, \"block\": %d, \"nslice\": %d, "
-                "\"gemm_tile\": %d, \"ms\": %.4f}",
-                key.c_str(), o.backend, o.method, o.block, o.nslice, o.gemm_tile, ms);
+                "\"gemm_tile\": %d, \"flags\": %d, \"ms\": %.4f}",
+                key.c_str(), o.backend, o.method, o.block, o.nslice, o.gemm_tile, o.flags, ms);
   keep.push_back(buf);
   const std::string tmp = std::string(path) + ".tmp";
   {
@@ -179,23 +187,27 @@ extern "C" ozII_status ozII_tune(ozII_handle h, int32_t nc, int64_t n, const cha
       return OZII_OK;
     }
   }
-  // candidates: panel width x (three back-ends + the native update)
+  // stage 1 candidates: panel width x (three back-ends + the native update)
+  // x schedule (look-ahead or not)
   std::vector<Cand> cands;
   for (int b : {64, 128, 256, 512}) {
     if (b >= n) continue;
     for (int be : {(int)OZII_BE_INT8, (int)OZII_BE_FP8_B17, (int)OZII_BE_F64MOD, 0}) {
-      Cand c;
-      std::memset(&c.o, 0, sizeof(c.o));
-      c.o.block = b;
-      c.o.backend = be ? be : OZII_BE_INT8;
-      c.o.method = be ? OZII_METHOD_OZAKI : OZII_METHOD_NAIVE;
-      if (be) {
-        int32_t S, w, Q, N;
-        if (ozII_plan_query(53 * nc, b, &c.o, &S, &w, &Q, &N, nullptr) != OZII_OK) continue;
+      for (int fl : {0, (int)OZII_F_NO_LOOKAHEAD}) {
+        Cand c;
+        std::memset(&c.o, 0, sizeof(c.o));
+        c.o.block = b;
+        c.o.backend = be ? be : OZII_BE_INT8;
+        c.o.method = be ? OZII_METHOD_OZAKI : OZII_METHOD_NAIVE;
+        c.o.flags = fl;
+        if (be) {
+          int32_t S, w, Q, N;
+          if (ozII_plan_query(53 * nc, b, &c.o, &S, &w, &Q, &N, nullptr) != OZII_OK) continue;
+        }
+        c.model_ms = model_ms(nc, n, c.o);
+        c.ms = 0;
+        cands.push_back(c);
       }
-      c.model_ms = model_ms(nc, n, c.o);
-      c.ms = 0;
-      cands.push_back(c);
     }
   }
   if (cands.empty()) {
@@ -206,7 +218,8 @@ extern "C" ozII_status ozII_tune(ozII_handle h, int32_t nc, int64_t n, const cha
     return OZII_OK;
   }
   std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.model_ms < b.model_ms; });
-  if ((int)cands.size() > OZII_TUNE_MAXCAND) cands.resize(OZII_TUNE_MAXCAND);
+  // room for stage 2 (up to 7 refinements of the winner)
+  if ((int)cands.size() > OZII_TUNE_MAXCAND - 7) cands.resize(OZII_TUNE_MAXCAND - 7);
 
   void *sv = nullptr;
   ozII_status st = ozII_stream_of(h, &sv);
@@ -244,27 +257,59 @@ extern "C" ozII_status ozII_tune(ozII_handle h, int32_t nc, int64_t n, const cha
   // OZII_EUNSUPPORTED before anything is enqueued and are skipped; any other
   // failure ends the tuning.
   std::vector<Cand> timed;
-  for (size_t ci = 0; ci < cands.size(); ++ci) {
-    Cand c = cands[ci];
-    st = ozII_reserve(h, nc, 0, 0, 0, n, &c.o);
-    float ms = 0;
-    for (int rep_i = 0; rep_i < 2 && st == OZII_OK; ++rep_i) {  // warm-up, then timed
-      if ((e = fill()) != hipSuccess) break;
-      if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
-      st = ozII_getrf(h, nc, n, A, n, ipiv, info, &c.o);
-      if (st != OZII_OK) break;
-      if ((e = hipEventRecord(e1, s)) != hipSuccess) break;
-      if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
-      if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+  auto time_all = [&](const std::vector<Cand> &list) {
+    for (size_t ci = 0; ci < list.size() && (int)timed.size() < OZII_TUNE_MAXCAND; ++ci) {
+      Cand c = list[ci];
+      st = ozII_reserve(h, nc, 0, 0, 0, n, &c.o);
+      float ms = 0;
+      for (int rep_i = 0; rep_i < 2 && st == OZII_OK; ++rep_i) {  // warm-up, then timed
+        if ((e = fill()) != hipSuccess) break;
+        if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
+        st = ozII_getrf(h, nc, n, A, n, ipiv, info, &c.o);
+        if (st != OZII_OK) break;
+        if ((e = hipEventRecord(e1, s)) != hipSuccess) break;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+      }
+      if (st == OZII_EUNSUPPORTED && e == hipSuccess) {
+        st = OZII_OK;
+        continue;
+      }
+      if (st == OZII_OK && e == hipSuccess) st = ozII_sync_check(h);
+      if (st != OZII_OK || e != hipSuccess) return;
+      c.ms = ms;
+      timed.push_back(c);
     }
-    if (st == OZII_EUNSUPPORTED && e == hipSuccess) {
-      st = OZII_OK;
-      continue;
+  };
+  time_all(cands);
+  // stage 2: the winner with one slice more and with every GEMM tile
+  if (st == OZII_OK && e == hipSuccess && !timed.empty()) {
+    int w0 = 0;
+    for (size_t ci = 1; ci < timed.size(); ++ci)
+      if (timed[ci].ms < timed[w0].ms) w0 = (int)ci;
+    const Cand win = timed[w0];
+    if (win.o.method == OZII_METHOD_OZAKI) {
+      std::vector<Cand> ref;
+      int32_t S = 0, w = 0, Q = 0, N = 0;
+      if (ozII_plan_query(53 * nc, win.o.block, &win.o, &S, &w, &Q, &N, nullptr) == OZII_OK) {
+        for (int ns : {0, S + 1})
+          for (int tile : {(int)OZII_TILE_AUTO, (int)OZII_TILE_128x128, (int)OZII_TILE_256x128,
+                           (int)OZII_TILE_256x256}) {
+            if (ns == 0 && tile == OZII_TILE_AUTO) continue;  // the winner itself
+            if (win.o.backend != OZII_BE_INT8 && tile != OZII_TILE_AUTO) continue;
+            Cand c = win;
+            c.o.nslice = ns;
+            c.o.gemm_tile = tile;
+            int32_t S2, w2, Q2, N2;
+            if (ozII_plan_query(53 * nc, c.o.block, &c.o, &S2, &w2, &Q2, &N2, nullptr) != OZII_OK)
+              continue;
+            c.model_ms = model_ms(nc, n, c.o);
+            c.ms = 0;
+            ref.push_back(c);
+          }
+      }
+      time_all(ref);
     }
-    if (st == OZII_OK && e == hipSuccess) st = ozII_sync_check(h);
-    if (st != OZII_OK || e != hipSuccess) break;
-    c.ms = ms;
-    timed.push_back(c);
   }
   cleanup();
   if (st != OZII_OK) return st;

@@ -228,6 +228,29 @@ def test_getrf_getrs_backends(case, backend):
     assert np.array_equal(to_host(dX), X)
 
 
+@pytest.mark.parametrize("method", [O.METHOD_OZAKI, O.METHOD_NAIVE], ids=["ozaki", "naive"])
+@pytest.mark.parametrize("case", [(4, 520, 256, "lotkin"), (2, 300, 64, "random"),
+                                  (3, 200, 96, "graded")],
+                         ids=lambda c: "nc{}-n{}-b{}-{}".format(*c))
+def test_getrf_with_and_without_lookahead(case, method):
+    """The default schedule updates the next panel's columns first and the
+    rest of each Schur update on a side stream while the next panel runs;
+    OZII_F_NO_LOOKAHEAD runs each update as one product.  Both equal the
+    oracle bit for bit."""
+    import paper_2609_29554_amd as Z
+    nc, n, b, kind = case
+    note(f"getrf lookahead on/off {case} method={method}")
+    A = _matrix(nc, n, kind, 11 + n)
+    LU, ipiv, info, _ = O.getrf(A, b, method)
+    for flags in (0, Z.F_NO_LOOKAHEAD):
+        dA = to_dev(A)
+        dip, dinfo = ctx().getrf(dA, block=b, method=method, opts=Z.make_opts(flags=flags))
+        ctx().sync_check()
+        assert int(to_host(dinfo)[0]) == info
+        assert np.array_equal(to_host(dip), ipiv)
+        assert np.array_equal(to_host(dA), LU)
+
+
 def test_getrs_several_rhs():
     """Three right-hand sides take the blocked solve (one takes the pipelined
     one); both against the oracle."""

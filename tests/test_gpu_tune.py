@@ -29,14 +29,17 @@ def test_tune_times_candidates_and_caches(tmp_path):
     assert len(data) == 1 and data[0]["block"] == opts.block
     opts2, rep2 = ctx().tune(nc, n, cache)
     assert rep2["from_cache"]
-    assert (opts2.block, opts2.backend, opts2.method) == (opts.block, opts.backend, opts.method)
+    fields = ("block", "backend", "method", "nslice", "gemm_tile", "flags")
+    assert all(getattr(opts2, f) == getattr(opts, f) for f in fields)
+    # stage 1 covers both schedules; stage 2 refines an Ozaki-II winner
+    assert {c["lookahead"] for c in cands} == {True, False}
 
     # the LU with the tuned configuration against the oracle with that plan
     A = W.graded(n, nc, 20.0, np.random.default_rng(31))
     if opts.method == Z.METHOD_NAIVE:
         LU, ipiv, info, _ = O.getrf(A, opts.block, O.METHOD_NAIVE)
     else:
-        plan = O.make_plan(53 * nc, opts.block, backend=opts.backend)
+        plan = O.make_plan(53 * nc, opts.block, backend=opts.backend, nslice=opts.nslice)
         LU, ipiv, info, _ = O.getrf(A, opts.block, O.METHOD_OZAKI, plan=plan)
     dA = to_dev(A)
     dip, dinfo = ctx().getrf(dA, block=opts.block, method=opts.method, opts=opts2)
