@@ -207,6 +207,10 @@ def main():
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--gemm-n", type=int, default=4096)
     ap.add_argument("--gemm-backend", choices=["int8", "fp8", "f64"], default="int8")
+    ap.add_argument("--gemm-plan", choices=["literal", "rule"], default="literal",
+                    help="standalone TD product: 'literal' = at 159-bit scaling as the workload "
+                         "states it (one slice, N_mod covering 2 k 2^318); 'rule' = the plan "
+                         "rule of Sec. 3.2")
     ap.add_argument("--sweep-n", type=int, default=1024,
                     help="order of the back-end comparison LU (0 = skip)")
     ap.add_argument("--sweep-block", type=int, default=128)
@@ -430,9 +434,11 @@ def main():
 
 def td_gemm_probe(n, steps=3):
     """The GEMM half of the headline metric on its own configuration: the
-    standalone triple-double Ozaki-II product m = n = k = n (INT8), modular
-    GEMM GOPS and fraction of the INT8 MFMA peak, timed with the library's
-    HIP events (same recipe as --workload gemm)."""
+    standalone triple-double Ozaki-II product m = n = k = n (INT8) at 159-bit
+    scaling as the workload states it (one slice, 48 moduli), and beside it
+    with the plan rule of Sec. 3.2; modular GEMM GOPS and fraction of the INT8
+    MFMA peak, timed with the library's HIP events (same recipe as
+    --workload gemm)."""
     import numpy as np
     import torch
 
@@ -445,25 +451,30 @@ def td_gemm_probe(n, steps=3):
     dB = torch.from_numpy(W.random_expansions(n, n, nc, rng, exp_sigma=4.0)).cuda()
     dC = torch.zeros_like(dA)
     ctx = Z.Context(0)
-    opts = Z.make_opts(backend=Z.BE_INT8)
-    ctx.gemm(0, dA, dB, dC, opts)
-    ctx.sync_check()
-    ctx.set_profiling(True)
-    ctx.profile_read()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
+    out = {"workload": f"Ozaki-II product C=AB, triple-double, m=n=k={n}, INT8"}
+    for plan, qb in (("literal", 159), ("rule", 0)):
+        opts = Z.make_opts(backend=Z.BE_INT8, qbits=qb)
+        S, w, Q, nmod, _ = Z.plan_query(53 * nc, n, opts)
         ctx.gemm(0, dA, dB, dC, opts)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = ctx.profile_read()
-    ctx.set_profiling(False)
-    ms, launches, _, ops = prof["gemm"]
-    gops = ops / (ms * 1e-3) / 1e9
+        ctx.sync_check()
+        ctx.set_profiling(True)
+        ctx.profile_read()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.gemm(0, dA, dB, dC, opts)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = ctx.profile_read()
+        ctx.set_profiling(False)
+        ms, launches, _, ops = prof["gemm"]
+        gops = ops / (ms * 1e-3) / 1e9
+        out[plan] = {"S": S, "w": w, "nmod": nmod, "product_ms": (t1 - t0) / steps * 1e3,
+                     "gemm_ms": ms / launches, "gemm_gops": gops,
+                     "gemm_frac_int8_peak": gops / 1e3 / PEAK_INT8_TOPS,
+                     "stages_ms": {k: v[0] / steps for k, v in prof.items() if v[1]}}
     ctx.close()
-    return {"workload": f"Ozaki-II product C=AB, triple-double, m=n=k={n}, INT8",
-            "product_ms": (t1 - t0) / steps * 1e3, "gemm_ms": ms / launches,
-            "gemm_gops": gops, "gemm_frac_int8_peak": gops / 1e3 / PEAK_INT8_TOPS}
+    return out
 
 
 def backend_sweep(ctx, args):
@@ -686,7 +697,7 @@ def bench_gemm(args):
     dB = torch.from_numpy(B).cuda()
     dC = torch.zeros_like(dA)
     be = {"int8": Z.BE_INT8, "fp8": Z.BE_FP8_B17, "f64": Z.BE_F64MOD}[args.gemm_backend]
-    opts = Z.make_opts(backend=be)
+    opts = Z.make_opts(backend=be, qbits=159 if args.gemm_plan == "literal" else 0)
     peak = PEAK_MFMA[args.gemm_backend]
     S, w, Q, nmod, _ = Z.plan_query(53 * nc, n, opts)
     ctx.reserve(nc, n, n, n, 0, opts)
@@ -707,7 +718,8 @@ def bench_gemm(args):
     K = args.steps
     ms, launches, by, ops = prof["gemm"]
     ach = ops / launches / (ms / launches * 1e-3) / 1e12
-    prof_md = f"pmc_traffic_gemm_td{n}_{args.gemm_backend}.md"
+    prof_md = (f"pmc_traffic_gemm_td{n}_{args.gemm_backend}"
+               f"{'_literal' if args.gemm_plan == 'literal' else ''}.md")
     roof = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TOP/s",
             "frac": ach / peak, "traffic": traffic_of("gemm", prof_md), "kernel": "gemm",
             "avg_launch_ms": ms / launches, "algorithmic_bytes_per_launch": by / launches}
@@ -722,8 +734,10 @@ def bench_gemm(args):
         "metric": METRIC, "value": sec, "unit": "s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64x3+i8", "data": "synthetic",
-        "config": {"workload": f"Ozaki-II product C=AB, triple-double, m=n=k={n}",
-                   "backend": args.gemm_backend, "S": S, "w": w, "nmod": nmod},
+        "config": {"workload": f"Ozaki-II product C=AB, triple-double, m=n=k={n}"
+                               f"{', 159-bit scaling' if args.gemm_plan == 'literal' else ', plan rule'}",
+                   "backend": args.gemm_backend, "plan": args.gemm_plan, "S": S, "w": w,
+                   "nmod": nmod},
         "roofline": roof, "rooflines": rooflines,
         "effective_gflops_td": 2.0 * n ** 3 / sec / 1e9,
         "stages": {k: {"ms_per_step": v[0] / K} for k, v in prof.items() if v[1]},

@@ -79,6 +79,11 @@ typedef struct {
   int32_t gemm_tile;    /* (S4) workgroup tile: ozII_gemm_tile; the residue   */
                         /* planes are padded to it.  Results do not depend on */
                         /* it (exact integer products).                       */
+  int32_t qbits;        /* > 0: the unsliced product of Sec. 3.1 at a stated  */
+                        /* scaling, |a_bar|, |b_bar| < 2^qbits (S = 1, Q =    */
+                        /* qbits + 1) with N_mod the fewest moduli covering   */
+                        /* the CRT range 2 K 2^(2 qbits); 0 = plan rule.      */
+                        /* Needs nslice <= 1 and no extra groups (EINVAL).    */
 } ozII_opts;
 
 /* ozII_opts.flags.  OZII_F_NO_LOOKAHEAD: getrf runs each Schur update as

@@ -133,17 +133,46 @@ def _accum_ok(backend: int, K: int, S: int) -> bool:
 
 
 def make_plan(p: int, K: int, backend: int = BACKEND_INT8, nslice: int = 0,
-              extra_groups: int = 0, guard_ex: int = 0) -> Plan:
+              extra_groups: int = 0, guard_ex: int = 0, qbits: int = 0) -> Plan:
     """Plan rule of Sec. 3.2 ("Determining w and N").
 
     slack = ceil(log2 2K) + 16 + g_ex;  for S = 1, 2, ...:
     w = ceil((p + slack)/S), need = 2w + log2 K + log2 S + 5, N = fewest
     leading moduli whose cumulative log2 exceeds need; accept the first S that
     fits the capacity and the accumulator bound.  ``nslice`` forces S.
+
+    ``qbits`` > 0 selects the unsliced product of Sec. 3.1 at a stated
+    scaling instead: |a_bar|, |b_bar| < 2^qbits, i.e. S = 1 and Q = w =
+    qbits + 1, with N the fewest moduli whose product exceeds the CRT range
+    2 K 2^(2 qbits) of the exact integer products.
     Raises ValueError when no S fits (or the forced one does not).
     """
     if p <= 0 or K <= 0:
         raise ValueError("p and K must be positive")
+    if qbits < 0 or (qbits > 0 and (nslice > 1 or extra_groups > 0)):
+        raise ValueError("qbits: a positive width, with one slice and no extra groups")
+    if qbits > 0:
+        if not _accum_ok(backend, K, 1):
+            raise ValueError("accumulator bound")
+        mods = f64_moduli(K, 1) if backend == BACKEND_F64MOD else int8_moduli()
+        need = 1 + math.log2(K) + 2 * qbits
+        cum, N = 0.0, None
+        for i, m in enumerate(mods, 1):
+            cum += math.log2(m)
+            if cum > need:
+                N = i
+                break
+        if N is None:
+            raise ValueError("need exceeds the CRT capacity of the modulus set")
+        used = mods[:N]
+        P = 1
+        for m in used:
+            P *= m
+        M = [P // m for m in used]
+        y = [pow(Mi % m, -1, m) for Mi, m in zip(M, used)]
+        return Plan(p=p, K=K, backend=backend, S=1, w=qbits + 1, Q=qbits + 1, nmod=N,
+                    moduli=list(used), extra_groups=0, guard_ex=guard_ex, need=need, P=P,
+                    M=M, y=y)
     slack = math.ceil(math.log2(2 * K)) + 16 + guard_ex
     s_range = [nslice] if nslice > 0 else range(1, 4097)
     for S in s_range:

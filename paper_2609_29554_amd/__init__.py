@@ -36,7 +36,7 @@ class OziiError(RuntimeError):
 class Opts(C.Structure):
     _fields_ = [("backend", C.c_int32), ("nslice", C.c_int32), ("extra_groups", C.c_int32),
                 ("guard_ex", C.c_int32), ("block", C.c_int32), ("method", C.c_int32),
-                ("flags", C.c_int32), ("gemm_tile", C.c_int32)]
+                ("flags", C.c_int32), ("gemm_tile", C.c_int32), ("qbits", C.c_int32)]
 
 
 _lib = None
@@ -140,8 +140,9 @@ def noalloc_capacity() -> int:
 
 
 def make_opts(backend: int = 0, nslice: int = 0, extra_groups: int = 0, guard_ex: int = 0,
-              block: int = 0, method: int = 0, gemm_tile: int = 0, flags: int = 0) -> Opts:
-    return Opts(backend, nslice, extra_groups, guard_ex, block, method, flags, gemm_tile)
+              block: int = 0, method: int = 0, gemm_tile: int = 0, flags: int = 0,
+              qbits: int = 0) -> Opts:
+    return Opts(backend, nslice, extra_groups, guard_ex, block, method, flags, gemm_tile, qbits)
 
 
 def plan_query(p: int, K: int, opts: Optional[Opts] = None):

@@ -122,7 +122,12 @@ ozII_status make_plan(int p, int64_t K, const ozII_opts *o, HostPlan &pl, std::s
   const int nslice = o ? o->nslice : 0;
   const int extra = o ? o->extra_groups : 0;
   const int gex = o ? o->guard_ex : 0;
-  if (p <= 0 || K <= 0 || nslice < 0 || extra < 0 || gex < 0) return OZII_EINVAL;
+  const int qbits = o ? o->qbits : 0;
+  if (p <= 0 || K <= 0 || nslice < 0 || extra < 0 || gex < 0 || qbits < 0) return OZII_EINVAL;
+  if (qbits > 0 && (nslice > 1 || extra > 0)) {
+    if (why) *why = "qbits: one slice and no extra groups";
+    return OZII_EINVAL;
+  }
   if (o && (o->gemm_tile < OZII_TILE_AUTO || o->gemm_tile > OZII_TILE_256x256)) {
     if (why) *why = "gemm_tile must be 0..3";
     return OZII_EINVAL;
@@ -133,15 +138,20 @@ ozII_status make_plan(int p, int64_t K, const ozII_opts *o, HostPlan &pl, std::s
   }
   const std::vector<int> mods8 = int8_moduli();
   const int slack = (int)std::ceil(std::log2(2.0 * (double)K)) + 16 + gex;
-  const int s_lo = nslice > 0 ? nslice : 1, s_hi = nslice > 0 ? nslice : 4096;
+  // qbits: the unsliced product of Sec. 3.1 at a stated scaling, |X| <
+  // 2^qbits: S = 1, Q = w = qbits + 1, and N covers the CRT range 2 K
+  // 2^(2 qbits) of the exact products (need = 1 + log2 K + 2 qbits)
+  const int s_lo = qbits > 0 ? 1 : (nslice > 0 ? nslice : 1);
+  const int s_hi = qbits > 0 ? 1 : (nslice > 0 ? nslice : 4096);
   bool any_acc = false;
   for (int S = s_lo; S <= s_hi; ++S) {
     if (!accum_ok(backend, K, S)) continue;
     const std::vector<int> mods = backend == OZII_BE_F64MOD ? f64_moduli(K, S) : mods8;
     if (mods.empty()) continue;
     any_acc = true;
-    const int w = (p + slack + S - 1) / S;
-    const double need = 2.0 * w + std::log2((double)K) + std::log2((double)S) + 5.0;
+    const int w = qbits > 0 ? qbits + 1 : (p + slack + S - 1) / S;
+    const double need = qbits > 0 ? 1.0 + std::log2((double)K) + 2.0 * qbits
+                                  : 2.0 * w + std::log2((double)K) + std::log2((double)S) + 5.0;
     double cum = 0.0;
     int N = 0;
     for (size_t i = 0; i < mods.size(); ++i) {
@@ -396,7 +406,7 @@ ozII_status get_plan(ozII_ctx *h, int p, int64_t K, const ozII_opts *o, const Ho
                      const DevPlan **dp, bool limbs = false) {
   const int backend = (o && o->backend) ? o->backend : OZII_BE_INT8;
   auto key = std::make_tuple(p, K, backend, o ? o->nslice : 0, o ? o->extra_groups : 0,
-                             (o ? o->guard_ex : 0) * 2 + (limbs ? 1 : 0));
+                             ((o ? o->guard_ex : 0) * 2 + (limbs ? 1 : 0)) * 4096 + (o ? o->qbits : 0));
   auto it = h->plans.find(key);
   if (it == h->plans.end()) {
     HostPlan pl;
@@ -476,7 +486,7 @@ ozII_status noalloc_plan(ozII_ctx *h, int p, int64_t K, const ozII_opts *o, cons
   NoallocDev &nd = it->second;
   const int backend = (o && o->backend) ? o->backend : OZII_BE_INT8;
   const auto key = std::make_tuple(p, K, backend, o ? o->nslice : 0, o ? o->extra_groups : 0,
-                                   (o ? o->guard_ex : 0) * 2);
+                                   (o ? o->guard_ex : 0) * 2 * 4096 + (o ? o->qbits : 0));
   *ws = nd.base + NOALLOC_WS_OFF;
   for (int sl = 0; sl < NOALLOC_SLOTS; ++sl)
     if (nd.used[sl] && nd.key[sl] == key) {

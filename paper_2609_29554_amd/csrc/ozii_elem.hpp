@@ -203,18 +203,8 @@ OZ_HD void crt_digits(const TT *t, int64_t stride, const DevPlan *pl, int32_t (&
 }
 
 // ---------------------------------------------------------------------------
-// Greedy round-to-nearest (ties to even) of an NW-word two's-complement
-// integer times 2^eps into NC doubles; a component below 2^-1022 is flushed
-// and ends the expansion.
+// Multiword helpers and the final rounding (S6)
 // ---------------------------------------------------------------------------
-template <int NW>
-OZ_HD bool is_zero_words(const uint32_t (&a)[NW]) {
-  uint32_t o = 0;
-#pragma unroll
-  for (int k = 0; k < NW; ++k) o |= a[k];
-  return o == 0;
-}
-
 template <int NW>
 OZ_HD void negate_words(uint32_t (&a)[NW]) {
   uint32_t carry = 1;
@@ -226,70 +216,89 @@ OZ_HD void negate_words(uint32_t (&a)[NW]) {
   }
 }
 
+// funnel shift: the 32 bits of (hi:lo) << s, 0 <= s < 32
+OZ_HD uint32_t shl_funnel(uint32_t hi, uint32_t lo, int s) {
+  return s ? (uint32_t)((((uint64_t)hi << 32) | lo) >> (32 - s)) : hi;
+}
+
+// Greedy round-to-nearest (ties to even) of the NW-word two's-complement
+// integer cb times 2^eps into NC doubles: x_0 = RN(c), x_k = RN(c - x_0 -
+// ... - x_(k-1)) with every remainder exact; a component below 2^-1022 is
+// flushed and ends the expansion.  Worked on sign and magnitude: every
+// component first normalises the remainder's magnitude so that its leading
+// bit is bit 32 NW - 1 (a shift by whole words through a fixed network of
+// selects, then one funnel shift), after which the 53-bit head, the
+// rounding bit and the sticky bits sit at fixed word positions.  The next
+// remainder is the magnitude below the head, negated (2^P - low, P the
+// head's lowest bit position) when the head was rounded up, which also
+// flips the sign.
 template <int NW, int NC>
-OZ_HD void round_out(uint32_t (&cb)[NW], int eps, double (&x)[NC]) {
+OZ_HD void round_out_n(const uint32_t (&cb)[NW], int eps, double (&x)[NC]) {
+  static_assert(NW >= 3 && NW <= 16, "word count");
+  uint32_t N[NW];
+  bool neg = (cb[NW - 1] >> 31) != 0;
+  {
+    uint32_t carry = 1;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const uint32_t v = neg ? ~cb[k] : cb[k];
+      const uint64_t t = (uint64_t)v + (neg ? carry : 0u);
+      N[k] = (uint32_t)t;
+      carry = (uint32_t)(t >> 32);
+    }
+  }
+  int sh = 0;  // N = |remainder| 2^sh
 #pragma unroll
   for (int c = 0; c < NC; ++c) x[c] = 0.0;
   bool done = false;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    if (!done && is_zero_words<NW>(cb)) done = true;
-    if (!done) {
-      const bool neg = (cb[NW - 1] >> 31) != 0;
-      uint32_t mag[NW];
+    int tw = -1;
 #pragma unroll
-      for (int k = 0; k < NW; ++k) mag[k] = cb[k];
-      if (neg) negate_words<NW>(mag);
-      // top non-zero word and the two below it
-      int tw = 0;
+    for (int k = 0; k < NW; ++k) tw = N[k] != 0u ? k : tw;
+    done = done || tw < 0;
+    // whole-word shift by NW - 1 - tw
+    const int sw = done ? 0 : NW - 1 - tw;
 #pragma unroll
-      for (int k = 0; k < NW; ++k)
-        if (mag[k] != 0u) tw = k;
-      uint32_t w0 = 0, w1 = 0, w2 = 0, below = 0;
+    for (int b = 8; b >= 1; b >>= 1) {
+      if (b < NW) {
+        const bool on = (sw & b) != 0;
 #pragma unroll
-      for (int k = 0; k < NW; ++k) {
-        if (k == tw) w0 = mag[k];
-        if (k == tw - 1) w1 = mag[k];
-        if (k == tw - 2) w2 = mag[k];
-        if (k < tw - 2) below |= mag[k];
-      }
-      const int lz = __builtin_clz(w0);
-      const int L = 32 * tw + 32 - lz;  // bit length
-      // 96-bit window normalised so that the leading one is bit 95
-      uint64_t hi = ((uint64_t)w0 << 32) | w1;
-      uint64_t lo = (uint64_t)w2 << 32;
-      if (lz) {
-        hi = (hi << lz) | (lo >> (64 - lz));
-        lo <<= lz;
-      }
-      uint64_t m = hi >> 11;                       // 53 bits
-      const uint32_t rb = (uint32_t)((hi >> 10) & 1u);
-      const bool sticky = ((hi & 0x3ffull) != 0) || (lo != 0) || (below != 0);
-      if (rb && (sticky || (m & 1ull))) m += 1;
-      const int ex = L - 53;                       // value = m * 2^ex
-      const int top = (63 - __builtin_clzll(m)) + ex + eps;
-      if (top < -1022) {
-        done = true;
-      } else {
-        double v = __builtin_ldexp((double)m, ex + eps);
-        x[c] = neg ? -v : v;
-        // cb -= sign * m * 2^ex  (for ex < 0 the bits below 2^0 are zero)
-        uint32_t borrow = 0, carry = 0;
-#pragma unroll
-        for (int k = 0; k < NW; ++k) {
-          uint32_t part = word_of_shifted(m, ex, k);
-          if (!neg) {
-            uint64_t t = (uint64_t)cb[k] - part - borrow;
-            cb[k] = (uint32_t)t;
-            borrow = (uint32_t)((t >> 63) & 1u);
-          } else {
-            uint64_t t = (uint64_t)cb[k] + part + carry;
-            cb[k] = (uint32_t)t;
-            carry = (uint32_t)(t >> 32);
-          }
-        }
+        for (int k = NW - 1; k >= 0; --k) N[k] = on ? (k >= b ? N[k - b] : 0u) : N[k];
       }
     }
+    const int lz = done ? 0 : __builtin_clz(N[NW - 1] | 1u);
+#pragma unroll
+    for (int k = NW - 1; k >= 1; --k) N[k] = shl_funnel(N[k], N[k - 1], lz);
+    N[0] = lz ? N[0] << lz : N[0];
+    sh += 32 * sw + lz;
+    const uint64_t hi = ((uint64_t)N[NW - 1] << 32) | N[NW - 2];
+    uint64_t m = hi >> 11;
+    const uint32_t rb = (uint32_t)((hi >> 10) & 1u);
+    uint32_t below = (uint32_t)(hi & 0x3ffu);
+#pragma unroll
+    for (int k = 0; k < NW - 2; ++k) below |= N[k];
+    const bool up = rb && (below != 0u || (m & 1ull));
+    m += up ? 1u : 0u;
+    const int ex = 32 * NW - sh - 53;  // value of the head: m 2^ex
+    const int top = (63 - __builtin_clzll(m | 1ull)) + ex + eps;
+    done = done || top < -1022;
+    if (!done) {
+      const double v = __builtin_ldexp((double)m, ex + eps);
+      x[c] = neg ? -v : v;
+    }
+    // the remainder below the head, P = 32 (NW - 2) + 11 bits
+    N[NW - 1] = 0u;
+    N[NW - 2] &= 0x7ffu;
+    uint32_t carry = 1;
+#pragma unroll
+    for (int k = 0; k < NW - 1; ++k) {
+      const uint64_t t = (uint64_t)(up ? ~N[k] : N[k]) + (up ? carry : 0u);
+      N[k] = (uint32_t)t;
+      carry = (uint32_t)(t >> 32);
+    }
+    N[NW - 2] &= 0x7ffu;
+    neg = neg != up;
   }
 }
 
@@ -425,7 +434,7 @@ OZ_HD void consume_element(TPtr tptr, int64_t pstride, const DevPlan *pl, uint32
 #pragma unroll
     for (int q = 0; q < NC; ++q) c[q] = 0.0;
   } else {
-    round_out<NWC, NC>(cb, eps, c);
+    round_out_n<NWC, NC>(cb, eps, c);
   }
 }
 

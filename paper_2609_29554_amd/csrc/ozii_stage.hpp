@@ -164,7 +164,7 @@ __device__ __forceinline__ void consume_element_b(const uint8_t *tbase, int64_t 
 #pragma unroll
     for (int qq = 0; qq < NC; ++qq) c[qq] = 0.0;
   } else {
-    round_out<NWC, NC>(cb, eps, c);
+    round_out_n<NWC, NC>(cb, eps, c);
   }
 }
 

@@ -12,7 +12,9 @@ that source is unchanged.
     python -m paper_2609_29554_amd.pmc FETCH.csv WRITE.csv COPY_MIB OUT.md "command"
 
 It also writes the kernel-time summaries of ``rocprofv3 --kernel-trace
---stats`` runs (``python -m paper_2609_29554_amd.pmc trace ...``).
+--stats`` runs (``python -m paper_2609_29554_amd.pmc trace ...``) and the
+VALU activity of a ``rocprofv3 --pmc VALUBusy SQ_INSTS_VALU SQ_WAVES`` run
+(``python -m paper_2609_29554_amd.pmc valu ...``).
 """
 from __future__ import annotations
 
@@ -148,6 +150,42 @@ def write_trace_md(stats, path: str, command: str, title: str, notes: str = ""):
         f.write("\n".join(lines))
 
 
+def valu_summary(path: str):
+    """Per kernel family from a counter CSV of VALUBusy, SQ_INSTS_VALU and
+    SQ_WAVES: dispatches, mean VALUBusy (percent of the time the CUs issue
+    VALU instructions, rocprofv3's derived metric), and VALU instructions
+    per wave (SQ_INSTS_VALU / SQ_WAVES summed over the dispatches)."""
+    vals = defaultdict(lambda: defaultdict(list))
+    for r in csv.DictReader(open(path)):
+        if not _family(r["Kernel_Name"]):
+            continue
+        vals[short_name(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    out = {}
+    for fam, c in vals.items():
+        busy = c.get("VALUBusy", [])
+        insts, waves = sum(c.get("SQ_INSTS_VALU", [])), sum(c.get("SQ_WAVES", []))
+        out[fam] = {"dispatches": max(len(v) for v in c.values()),
+                    "valu_busy_pct": sum(busy) / len(busy) if busy else None,
+                    "valu_insts_per_wave": insts / waves if waves else None}
+    return {"kernel_source_sha256": source_sha(), "kernels": out}
+
+
+def write_valu_md(summary, path: str, command: str, title: str, notes: str = ""):
+    lines = [f"# {title}", "", "Command (run from /tmp on the MI355X box, repository at $R):",
+             "```", command, "```", ""]
+    if notes:
+        lines += [notes, ""]
+    lines += ["| kernel | dispatches | VALUBusy % | VALU instructions per wave |",
+              "|---|---:|---:|---:|"]
+    for fam, r in sorted(summary["kernels"].items(), key=lambda kv: kv[0]):
+        b, i = r["valu_busy_pct"], r["valu_insts_per_wave"]
+        lines.append(f"| `{fam}` | {r['dispatches']} | {'' if b is None else f'{b:.1f}'} | "
+                     f"{'' if i is None else f'{i:.0f}'} |")
+    lines += ["", "Machine-readable:", "```json", json.dumps(summary), "```", ""]
+    with open(path, "w") as f:
+        f.write("\n".join(lines))
+
+
 def load(path: str):
     """The summary stored in a profiles/*.md file, or None."""
     if not os.path.exists(path):
@@ -161,6 +199,13 @@ def load(path: str):
 
 
 if __name__ == "__main__":
+    if sys.argv[1] == "valu":
+        # python -m paper_2609_29554_amd.pmc valu COUNTERS.csv OUT.md "command" "title" ["notes"]
+        sm = valu_summary(sys.argv[2])
+        write_valu_md(sm, sys.argv[3], sys.argv[4], sys.argv[5],
+                      sys.argv[6] if len(sys.argv) > 6 else "")
+        print(json.dumps(sm, indent=1))
+        sys.exit(0)
     if sys.argv[1] == "trace":
         # python -m paper_2609_29554_amd.pmc trace STATS OUT.md "command" "title" ["notes"]
         st = kernel_stats(sys.argv[2])

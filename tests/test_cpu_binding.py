@@ -145,3 +145,23 @@ def test_batch_items_are_validated():
     for kw in bad:
         with pytest.raises(ValueError):
             Z.check_batch_item(**kw)
+
+
+def test_literal_scaling_plan_matches_oracle():
+    # the standalone TD product "at 159-bit scaling": one slice, Q = 160,
+    # N_mod the fewest moduli with log2 P > 1 + log2 K + 2*159 = 331
+    Z = _lib()
+    import math
+    import oracle as O
+    for p, K, qb, be in ((159, 4096, 159, 1), (106, 512, 106, 1), (159, 4096, 159, 2),
+                         (212, 256, 160, 1), (159, 4096, 159, 3)):
+        got = Z.plan_query(p, K, Z.make_opts(backend=be, qbits=qb))
+        pl = O.make_plan(p, K, backend=be, qbits=qb)
+        assert got == (pl.S, pl.w, pl.Q, pl.nmod, pl.moduli)
+        assert pl.S == 1 and pl.Q == qb + 1
+        need = 1 + math.log2(K) + 2 * qb
+        assert math.log2(pl.P) > need
+        assert sum(math.log2(m) for m in pl.moduli[:-1]) <= need
+    assert O.make_plan(159, 4096, qbits=159).nmod == 48
+    with pytest.raises(Z.OziiError):
+        Z.plan_query(159, 4096, Z.make_opts(qbits=159, nslice=2))

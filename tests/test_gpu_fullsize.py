@@ -60,22 +60,27 @@ def td_operands(n, seed=20260932):
     return A, B
 
 
-@pytest.mark.parametrize("mode", [0, 1])
-def test_gemm_td4096_sampled(mode):
+@pytest.mark.parametrize("mode,plan", [(0, "rule"), (1, "rule"), (0, "literal"), (1, "literal")])
+def test_gemm_td4096_sampled(mode, plan):
+    """plan "rule": the plan rule of Sec. 3.2 (S = 2, 28 moduli); "literal":
+    the product at 159-bit scaling as the TD workload states it (one slice,
+    48 moduli covering 2 k 2^318)."""
+    import paper_2609_29554_amd as Z
     n = 4096
-    note(f"full-size TD product {n}^3 mode={mode}")
+    qb = 159 if plan == "literal" else 0
+    note(f"full-size TD product {n}^3 mode={mode} plan={plan}")
     A, B = td_operands(n)
     C0 = W.random_expansions(n, n, 3, np.random.default_rng(5), exp_sigma=4.0) if mode else \
         np.zeros((n, n, 3))
     dC = to_dev(C0)
-    ctx().gemm(mode, to_dev(A), to_dev(B), dC)
+    ctx().gemm(mode, to_dev(A), to_dev(B), dC, Z.make_opts(qbits=qb))
     ctx().sync_check()
     C = to_host(dC)
     rng = np.random.default_rng(11)
     rows = np.sort(rng.choice(n, 12, replace=False))
     cols = np.sort(rng.choice(n, 12, replace=False))
     rows[0], cols[-1] = 0, n - 1
-    pl = O.make_plan(159, n)
+    pl = O.make_plan(159, n, qbits=qb)
     Asub = np.ascontiguousarray(A[:, rows, :])      # (K, 12, nc): rows of A
     Bsub = np.ascontiguousarray(B[cols, :, :])      # (12, K, nc): columns of B
     Csub0 = np.ascontiguousarray(C0[cols][:, rows, :])

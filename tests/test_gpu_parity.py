@@ -92,6 +92,42 @@ def test_gemm_stages_bit_exact(case, tile):
     assert np.array_equal(to_host(dC1), C1ref)
 
 
+@pytest.mark.parametrize("case", [(3, 40, 33, 300, 159), (2, 130, 129, 64, 106),
+                                  (4, 17, 5, 520, 170)],
+                         ids=lambda c: "nc{}-{}x{}x{}-q{}".format(*c))
+def test_gemm_literal_scaling_bit_exact(case):
+    """The unsliced product at a stated scaling (ozII_opts.qbits): one slice,
+    |a_bar| < 2^qbits, N_mod covering 2 K 2^(2 qbits); residues, t-planes,
+    group sums and both product modes against the oracle with that plan."""
+    import paper_2609_29554_amd as Z
+    nc, M, N, K, qb = case
+    note(f"gemm literal scaling {case}")
+    A, B, C0 = _operands(nc, M, N, K, 300 + M + N + K)
+    pl = O.make_plan(53 * nc, K, qbits=qb)
+    opts = Z.make_opts(qbits=qb)
+    ea, eb = O.exponents(A, True), O.exponents(B, False)
+    ra, rb = O.residues(A, True, ea, pl), O.residues(B, False, eb, pl)
+    tpl = O.modgemm(ra, rb, pl)
+    Cref, sb = O.ozgemm(0, A, B, np.zeros((N, M, nc)), pl, want_sbar=True, nw_out=6)
+    C1ref, _ = O.ozgemm(1, A, B, C0, pl)
+    dA, dB = to_dev(A), to_dev(B)
+    dC = to_dev(np.zeros((N, M, nc)))
+    st = ctx().gemm_stages(0, dA, dB, dC, opts, nlimb=6)
+    d = st["dims"]
+    assert (d["S"], d["nmod"], d["ng"]) == (1, pl.nmod, 1)
+    P = pl.nmod
+    ga = Z.unfragment(to_host(st["planesA"]), P, d["Mp"], d["Kp"])
+    assert np.array_equal(ga[:, :M, :K], ra.reshape(P, M, K))
+    gt = to_host(st["tpl"]).reshape(1, pl.nmod, d["Np"], d["Mp"])
+    assert np.array_equal(gt[:, :, :N, :M], tpl)
+    gs = to_host(st["sbar"]).view(np.uint64).reshape(1, N, M, 6)
+    assert np.array_equal(gs, sb)
+    assert np.array_equal(to_host(dC), Cref)
+    dC1 = to_dev(C0)
+    ctx().gemm(1, dA, dB, dC1, opts)
+    assert np.array_equal(to_host(dC1), C1ref)
+
+
 def _e4m3_table():
     """Integer value of every E4M3 byte that encodes an integer in [-16, 16],
     from the OCP format definition (bias 7, 3 fraction bits)."""
