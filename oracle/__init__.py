@@ -91,6 +91,11 @@ def _declare(L):
     L.orc_lf_getrf.argtypes = [_int, _i64, _u64p, _i64p, _u8p, _i64, _i64p, _i32p]
     L.orc_lf_getrs.argtypes = [_int, _i64, _u64p, _i64p, _u8p, _i64, _i64p, _i64, _u64p, _i64p,
                                _u8p, _i64]
+    L.orc_lf_getf2.argtypes = [_int, _i64, _i64, _u64p, _i64p, _u8p, _i64, _i64p, _i32p]
+    L.orc_lf_trsm_lunit.argtypes = [_int, _i64, _i64, _u64p, _i64p, _u8p, _i64, _u64p, _i64p,
+                                    _u8p, _i64]
+    L.orc_lf_gemm_sub.argtypes = [_int, _i64, _i64, _i64, _u64p, _i64p, _u8p, _i64, _u64p,
+                                  _i64p, _u8p, _i64, _u64p, _i64p, _u8p, _i64]
 
 
 def _p(a, t):

@@ -404,24 +404,26 @@ void orc_lf_from_doubles(int nl, int64_t cnt, int nc, const double *x, uint64_t 
 /* ------------------------------------------------------------------ */
 /* LU with partial pivoting and the solve (Sec. 3.4, Sec. 4.3)          */
 /* ------------------------------------------------------------------ */
-/* Right-looking LU of the n x n matrix (element (i, j) at index i + j ld)
- * with partial pivoting: pivot = largest exact magnitude in the column,
- * ties to the lowest row; the whole row is interchanged; l = RN(a / pivot);
+/* Unblocked right-looking LU with partial pivoting of the m x nc block
+ * (m >= nc; element (i, j) at index i + j ld, i.e. the caller passes the
+ * block's first element): for each column j the pivot is the largest exact
+ * magnitude among rows j..m-1, ties to the lowest row; rows j and the pivot
+ * row are interchanged across the block's nc columns; l = RN(a / pivot);
  * then every a_ic (c > j) takes RN(a_ic - RN(l_ij a_jc)).  Per element the
- * updates come in ascending j, so the blocked variants with the same panel
- * and these updates give the same result.  ipiv 0-based (LAPACK), info =
- * first j+1 with an exactly zero pivot (that column is then skipped). */
-void orc_lf_getrf(int nl, int64_t n, uint64_t *m, int64_t *e, uint8_t *s, int64_t ld,
-                  int64_t *ipiv, int32_t *info) {
+ * updates come in ascending j.  ipiv[j] is the block-relative pivot row,
+ * info the first j+1 with an exactly zero pivot (that column is then
+ * skipped: no division, no update, as LAPACK's panel does). */
+void orc_lf_getf2(int nl, int64_t m_rows, int64_t nc, uint64_t *m, int64_t *e, uint8_t *s,
+                  int64_t ld, int64_t *ipiv, int32_t *info) {
     *info = 0;
 #define EL(i, j) ((i) + (j) * ld)
-    for (int64_t j = 0; j < n; ++j) {
+    for (int64_t j = 0; j < nc; ++j) {
         int64_t p = j;
-        for (int64_t i = j + 1; i < n; ++i)
+        for (int64_t i = j + 1; i < m_rows; ++i)
             if (abs_greater(nl, m + EL(i, j) * nl, e[EL(i, j)], m + EL(p, j) * nl, e[EL(p, j)])) p = i;
         ipiv[j] = p;
         if (p != j) {
-            for (int64_t c = 0; c < n; ++c) {
+            for (int64_t c = 0; c < nc; ++c) {
                 uint64_t t[LF_MAXL];
                 memcpy(t, m + EL(j, c) * nl, 8 * nl);
                 memcpy(m + EL(j, c) * nl, m + EL(p, c) * nl, 8 * nl);
@@ -442,7 +444,7 @@ void orc_lf_getrf(int nl, int64_t n, uint64_t *m, int64_t *e, uint8_t *s, int64_
         const int64_t pe = e[EL(j, j)];
         const int ps = s[EL(j, j)];
 #pragma omp parallel for schedule(dynamic, 4)
-        for (int64_t i = j + 1; i < n; ++i) {
+        for (int64_t i = j + 1; i < m_rows; ++i) {
             uint64_t lm[LF_MAXL], tm[LF_MAXL];
             int64_t le, te;
             uint8_t ls, ts;
@@ -450,7 +452,7 @@ void orc_lf_getrf(int nl, int64_t n, uint64_t *m, int64_t *e, uint8_t *s, int64_
             memcpy(m + EL(i, j) * nl, lm, 8 * nl);
             e[EL(i, j)] = le;
             s[EL(i, j)] = ls;
-            for (int64_t c = j + 1; c < n; ++c) {
+            for (int64_t c = j + 1; c < nc; ++c) {
                 lf_mul(nl, lm, le, ls, m + EL(j, c) * nl, e[EL(j, c)], s[EL(j, c)], tm, &te, &ts);
                 uint64_t *am = m + EL(i, c) * nl;
                 lf_add(nl, am, e[EL(i, c)], s[EL(i, c)], tm, te, ts, 1, am, e + EL(i, c),
@@ -459,6 +461,57 @@ void orc_lf_getrf(int nl, int64_t n, uint64_t *m, int64_t *e, uint8_t *s, int64_
         }
     }
 #undef EL
+}
+
+/* The LU of Sec. 3.4 on the whole n x n matrix, unblocked: the panel above
+ * with nc = m = n, so every interchange spans whole rows. */
+void orc_lf_getrf(int nl, int64_t n, uint64_t *m, int64_t *e, uint8_t *s, int64_t ld,
+                  int64_t *ipiv, int32_t *info) {
+    orc_lf_getf2(nl, n, n, m, e, s, ld, ipiv, info);
+}
+
+/* B <- L^-1 B for the unit lower triangle of the kb x kb block L (the U12
+ * block row of the blocked LU): per column, for k ascending, every row
+ * i > k takes RN(b_ik' - RN(l_ik b_kc)). */
+void orc_lf_trsm_lunit(int nl, int64_t kb, int64_t ncols, const uint64_t *lm, const int64_t *le,
+                       const uint8_t *ls, int64_t ldl, uint64_t *bm, int64_t *be, uint8_t *bs,
+                       int64_t ldb) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t c = 0; c < ncols; ++c) {
+        uint64_t tm[LF_MAXL];
+        int64_t te;
+        uint8_t ts;
+        for (int64_t k = 0; k < kb; ++k) {
+            const int64_t u = k + c * ldb;
+            for (int64_t i = k + 1; i < kb; ++i) {
+                const int64_t a = i + k * ldl, x = i + c * ldb;
+                lf_mul(nl, lm + a * nl, le[a], ls[a], bm + u * nl, be[u], bs[u], tm, &te, &ts);
+                lf_add(nl, bm + x * nl, be[x], bs[x], tm, te, ts, 1, bm + x * nl, be + x, bs + x);
+            }
+        }
+    }
+}
+
+/* C <- C - A B by multiply-subtracts: every c_ij takes RN(c_ij - RN(a_ik
+ * b_kj)) for k ascending (the native update; with the panel and the solve
+ * above it reproduces the unblocked LU element by element). */
+void orc_lf_gemm_sub(int nl, int64_t M, int64_t N, int64_t K, const uint64_t *am,
+                     const int64_t *ae, const uint8_t *as, int64_t lda, const uint64_t *bm,
+                     const int64_t *be, const uint8_t *bs, int64_t ldb, uint64_t *cm, int64_t *ce,
+                     uint8_t *cs, int64_t ldc) {
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < M * N; ++t) {
+        const int64_t i = t % M, j = t / M;
+        const int64_t x = i + j * ldc;
+        uint64_t tm[LF_MAXL];
+        int64_t te;
+        uint8_t ts;
+        for (int64_t k = 0; k < K; ++k) {
+            const int64_t a = i + k * lda, b = k + j * ldb;
+            lf_mul(nl, am + a * nl, ae[a], as[a], bm + b * nl, be[b], bs[b], tm, &te, &ts);
+            lf_add(nl, cm + x * nl, ce[x], cs[x], tm, te, ts, 1, cm + x * nl, ce + x, cs + x);
+        }
+    }
 }
 
 /* Solve A X = B from the factors: interchanges in ipiv order, forward
