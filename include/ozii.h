@@ -192,6 +192,48 @@ ozII_status ozII_gemm_limbs_stages(ozII_handle h, int32_t mode, int32_t nlimb, i
                                    const ozII_limbs *B, ozII_limbs *C, const ozII_opts *o,
                                    uint64_t *sbar, int32_t nlimb_out);
 
+/* Blocked right-looking LU with partial pivoting (Sec. 3.4) on an n x n limb
+ * matrix (the layout above), in place.  Per panel of b = o->block columns
+ * (0 = 256): the unblocked panel -- pivot = the entry of largest exact
+ * magnitude at or below the diagonal, ties to the lowest row; rows
+ * interchanged across the panel; l = RN_p(a / pivot); a = RN_p(a -
+ * RN_p(l u)) on the panel's remaining columns --, the panel's interchanges
+ * on the other columns, U12 = L11^-1 U12 by the same multiply-subtracts,
+ * then the Schur update A22 = RN_p(A22 - RN_p(L21 U12)) by the Ozaki-II
+ * product of ozII_gemm_limbs (o->method = OZII_METHOD_OZAKI, plan for
+ * K = b) or by multiply-subtracts RN_p(a - RN_p(l_ik u_kj)), k ascending
+ * (OZII_METHOD_NAIVE, which gives the unblocked LU bit for bit for any b).
+ * RN_p rounds to nearest, ties to even, like MPFR's RNDN (the number type
+ * of Sec. 2).  ipiv (device int64, n entries, 0-based, LAPACK semantics)
+ * and *info (device int32, first j+1 with an exactly zero pivot, else 0);
+ * a zero pivot skips its column's division and update.  Errors:
+ * OZII_EINVAL (bad sizes, null pointers, bad descriptor, nlimb outside
+ * 1..64, unknown method), OZII_EUNSUPPORTED (a back-end other than INT8,
+ * or a plan beyond the compiled sizes), OZII_ENOMEM, OZII_EHIP. */
+ozII_status ozII_getrf_limbs(ozII_handle h, int32_t nlimb, int64_t n, ozII_limbs *A,
+                             int64_t *ipiv, int32_t *info, const ozII_opts *o);
+
+/* Solve A X = B from ozII_getrf_limbs's factors by forward and backward
+ * substitution (Sec. 4.3): the interchanges ipiv[0..n) applied to B in
+ * order, then element i takes RN_p(x_i - RN_p(l_ik x_k)) for k ascending,
+ * and RN_p(x_i - RN_p(u_ik x_k)) for k descending with x_k = RN_p(x_k /
+ * u_kk) once its updates are in (an exactly zero u_kk gives x_k = 0).  LU
+ * is the n x n factor matrix, B an n x nrhs limb matrix (element (i, r) at
+ * index i + r ld), overwritten by X; device memory owned by the caller.
+ * Errors: OZII_EINVAL (bad sizes, null pointers, bad descriptors,
+ * nlimb outside 1..64), OZII_EHIP. */
+ozII_status ozII_getrs_limbs(ozII_handle h, int32_t nlimb, int64_t n, int64_t nrhs,
+                             const ozII_limbs *LU, const int64_t *ipiv, ozII_limbs *B);
+
+/* The p-bit arithmetic of the limb LU element by element (parity hook; the
+ * correctly rounded operations of the number type of Sec. 2): C_t =
+ * RN_p(A_t op B_t) for t < count, op 0 add, 1 subtract, 2 multiply,
+ * 3 divide (a zero divisor gives 0).  A, B, C are vectors: element t at
+ * index t of every plane.  Errors: OZII_EINVAL (bad op, sizes or
+ * descriptors), OZII_EHIP. */
+ozII_status ozII_limbs_arith(ozII_handle h, int32_t op, int32_t nlimb, int64_t count,
+                             const ozII_limbs *A, const ozII_limbs *B, ozII_limbs *C);
+
 /* Same product with the intermediate stages copied out (parity hooks); any
  * output pointer may be null.  Sizes follow ozII_gemm_stage_dims:
  *   ea[M], eb[N]     (S1) row / column exponents (INT32_MIN for zero);

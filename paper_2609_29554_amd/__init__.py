@@ -48,7 +48,8 @@ EXPORTED = ["ozII_create", "ozII_destroy", "ozII_set_stream", "ozII_plan_query",
             "ozII_gemm", "ozII_gemm_noalloc", "ozII_gemm_noalloc_capacity",
             "ozII_gemm_limbs", "ozII_gemm_limbs_stages", "ozII_gemm_stages",
             "ozII_gemm_stage_dims",
-            "ozII_getrf", "ozII_getrs",
+            "ozII_getrf", "ozII_getrs", "ozII_getrf_limbs", "ozII_getrs_limbs",
+            "ozII_limbs_arith",
             "ozII_batch_prepare", "ozII_batch_prepare_ex", "ozII_batch_run", "ozII_tune",
             "ozII_stream_of",
             "ozII_sync_check", "ozII_set_profiling",
@@ -111,6 +112,9 @@ def lib():
                                            C.POINTER(_i32), C.POINTER(_i32)]
         L.ozII_getrf.argtypes = [_p, _i32, _i64, _p, _i64, _p, _p, OP]
         L.ozII_getrs.argtypes = [_p, _i32, _i64, _i64, _p, _i64, _p, _p, _i64]
+        L.ozII_getrf_limbs.argtypes = [_p, _i32, _i64, LP, _p, _p, OP]
+        L.ozII_getrs_limbs.argtypes = [_p, _i32, _i64, _i64, LP, _p, LP]
+        L.ozII_limbs_arith.argtypes = [_p, _i32, _i32, _i64, LP, LP, LP]
         L.ozII_tune.argtypes = [_p, _i32, _i64, C.c_char_p, _i32, OP, C.POINTER(TuneReport)]
         L.ozII_batch_prepare.argtypes = [_p, _i32, C.POINTER(BatchItem)]
         L.ozII_batch_prepare_ex.argtypes = [_p, _i32, C.POINTER(BatchItem), OP]
@@ -176,6 +180,45 @@ def _check_vec(t, dtype, length: int, name: str):
         raise ValueError(f"{name}: expected a contiguous 1-D {dtype} CUDA tensor")
     if t.numel() < length:
         raise ValueError(f"{name}: needs at least {length} entries, has {t.numel()}")
+
+
+def check_limb_mat(X, nl=None, device=None):
+    """(nlimb, cols, rows) of a limb matrix (limb, exp, sign): contiguous
+    CUDA tensors of shapes (nlimb, cols, rows) int64, (cols, rows) int32 and
+    (cols, rows) uint8, nlimb in 1..64 (a mismatch would be read out of
+    bounds on the device)."""
+    import torch
+    if not (isinstance(X, (tuple, list)) and len(X) == 3):
+        raise ValueError("limb matrix: tuple (limb, exp, sign)")
+    lb, ex, sg = X
+    for t in (lb, ex, sg):
+        if not (getattr(t, "is_cuda", False) and t.is_contiguous()):
+            raise ValueError("limb matrix: contiguous CUDA tensors")
+        if device is not None and t.device != device:
+            raise ValueError("limb operands must be on one device")
+    if lb.dtype != torch.int64 or lb.dim() != 3 or not 1 <= lb.shape[0] <= 64:
+        raise ValueError("limbs: int64 tensor (nlimb, cols, rows), nlimb 1..64")
+    if nl is not None and lb.shape[0] != nl:
+        raise ValueError("limb count mismatch")
+    if ex.dtype != torch.int32 or sg.dtype != torch.uint8 or \
+            tuple(ex.shape) != tuple(lb.shape[1:]) or tuple(sg.shape) != tuple(lb.shape[1:]):
+        raise ValueError("exp int32 / sign uint8 of shape (cols, rows)")
+    return lb.shape[0], lb.shape[1], lb.shape[2]
+
+
+def check_getrs_limbs_args(LU, ipiv, B):
+    """Validate a limb solve's operands; returns (nlimb, n, nrhs)."""
+    import torch
+    nl, cols, n = check_limb_mat(LU)
+    if cols != n:
+        raise ValueError("LU must be square")
+    _, nrhs, rows = check_limb_mat(B, nl, LU[0].device)
+    if rows != n:
+        raise ValueError("B must have shape (nlimb, nrhs, n)")
+    _check_vec(ipiv, torch.int64, n, "ipiv")
+    if ipiv.device != LU[0].device:
+        raise ValueError("ipiv must be on the device of LU")
+    return nl, n, nrhs
 
 
 def _check_square(A, name: str):
@@ -436,6 +479,51 @@ class Context:
         self._call(lib().ozII_getrs(self._h, nc, n, nrhs, _ptr(LU), max(n, 1), _ptr(ipiv),
                                     _ptr(B), max(n, 1)))
         return B
+
+    def getrf_limbs(self, A, block: int = 256, method: int = METHOD_OZAKI,
+                    opts: Optional[Opts] = None):
+        """In-place LU of the n x n limb matrix A = (limb, exp, sign);
+        returns (ipiv int64[n] 0-based, info int32[1]) on the device."""
+        import torch
+        nl, cols, rows = check_limb_mat(A)
+        if cols != rows:
+            raise ValueError("A must be square")
+        n = rows
+        o = opts if opts is not None else Opts()
+        o.block = block
+        o.method = method
+        ipiv = torch.empty(max(n, 1), dtype=torch.int64, device=A[0].device)
+        info = torch.zeros(1, dtype=torch.int32, device=A[0].device)
+        d = self._limb_desc(A)
+        self._bind()
+        self._call(lib().ozII_getrf_limbs(self._h, nl, n, C.byref(d), _ptr(ipiv), _ptr(info),
+                                          C.byref(o)))
+        return ipiv, info
+
+    def getrs_limbs(self, LU, ipiv, B):
+        """Solve in place: B = (limb (nl, nrhs, n), exp, sign) <- A^{-1} B."""
+        nl, n, nrhs = check_getrs_limbs_args(LU, ipiv, B)
+        dL, dB = self._limb_desc(LU), self._limb_desc(B)
+        self._bind()
+        self._call(lib().ozII_getrs_limbs(self._h, nl, n, nrhs, C.byref(dL), _ptr(ipiv),
+                                          C.byref(dB)))
+        return B
+
+    def limbs_arith(self, op: str, A, B, Cm):
+        """Elementwise C = RN_p(A op B) on limb vectors (shape (nl, 1, count))."""
+        nl, c1, cnt = check_limb_mat(A)
+        dev = A[0].device
+        for X in (B, Cm):
+            if check_limb_mat(X, nl, dev)[1:] != (c1, cnt):
+                raise ValueError("shape mismatch")
+        if c1 != 1:
+            raise ValueError("vectors: shape (nlimb, 1, count)")
+        code = {"add": 0, "sub": 1, "mul": 2, "div": 3}[op]
+        dA, dB, dC = (self._limb_desc(X) for X in (A, B, Cm))
+        self._bind()
+        self._call(lib().ozII_limbs_arith(self._h, code, nl, cnt, C.byref(dA), C.byref(dB),
+                                          C.byref(dC)))
+        return Cm
 
     def batch_prepare(self, systems, opts: Optional[Opts] = None):
         """Upload a batch: systems = [(A, b or None, ipiv, info), ...] of CUDA

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libozii.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["k_ozaki.hip", "k_lu.hip", "k_batch.hip", "k_limbs.hip", "ozii.cpp", "tune.hip"]
+SOURCES = ["k_ozaki.hip", "k_lu.hip", "k_batch.hip", "k_limbs.hip", "k_limb_lu.hip", "ozii.cpp",
+           "tune.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]

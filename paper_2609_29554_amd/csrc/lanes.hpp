@@ -1,0 +1,31 @@
+// Cross-lane primitives of one 64-lane wavefront: the vocabulary of the
+// lane-distributed p-bit arithmetic in limbfp.hpp.  Every call must be made
+// by all 64 lanes of a converged wavefront.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define LFP_FN __device__ __forceinline__
+
+namespace lfp {
+
+LFP_FN int lane_id() { return (int)__lane_id(); }
+
+// bit l set when lane l's predicate holds
+LFP_FN uint64_t ballot(bool p) { return (uint64_t)__ballot(p ? 1 : 0); }
+
+// lane l's x, for a wave-uniform l
+LFP_FN uint64_t readlane64(uint64_t x, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// lane src's x (src in 0..63, any per-lane value)
+LFP_FN uint64_t shfl64(uint64_t x, int src) {
+  return (uint64_t)__shfl((unsigned long long)x, src, 64);
+}
+
+LFP_FN uint64_t umulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
+
+}  // namespace lfp

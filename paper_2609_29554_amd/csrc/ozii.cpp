@@ -329,6 +329,9 @@ struct ozII_ctx {
   int *perm = nullptr, *moved = nullptr, *nmoved = nullptr;
   int64_t panel_n = 0;
   int panel_kb = 0;
+  // limb LU: pivot candidates of one panel column and the zero-pivot word
+  int64_t *lcand = nullptr;
+  int32_t *lflag = nullptr;
   // getrf look-ahead: a side stream (default priority) for the rest of each
   // Schur update while the next panel runs, and the fork / join events
   hipStream_t side = nullptr;
@@ -852,6 +855,37 @@ ozII_status gemm_limbs_impl(ozII_ctx *h, int mode, int nlimb, int64_t M, int64_t
   return OZII_OK;
 }
 
+// Pivot-candidate and zero-pivot scratch of the limb LU (allocated once).
+ozII_status limb_scratch(ozII_ctx *h) {
+  if (h->lcand) return OZII_OK;
+  hipError_t e = hipMalloc((void **)&h->lcand, sizeof(int64_t) * ozl::LPIV_MAXGRID + 256);
+  if (e != hipSuccess) return hip_fail(h, e, "hipMalloc(limb pivot scratch)");
+  h->lflag = (int32_t *)(h->lcand + ozl::LPIV_MAXGRID);
+  return OZII_OK;
+}
+
+// the sub-matrix starting at element (i, j)
+ozII_limbs limbs_at(const ozII_limbs *A, int64_t i, int64_t j) {
+  const int64_t off = i + j * A->ld;
+  ozII_limbs r;
+  r.limb = A->limb + off;
+  r.exp = A->exp + off;
+  r.sign = A->sign + off;
+  r.ld = A->ld;
+  r.plane = A->plane;
+  return r;
+}
+
+ozl::LimbMat limb_mat(const ozII_limbs *A) {
+  ozl::LimbMat m;
+  m.limb = A->limb;
+  m.exp = A->exp;
+  m.sign = A->sign;
+  m.ld = A->ld;
+  m.plane = A->plane;
+  return m;
+}
+
 // The side stream and the fork / join events of the look-ahead (created on
 // first use, on the handle's device, at the default priority).
 ozII_status ensure_side(ozII_ctx *h) {
@@ -934,6 +968,7 @@ ozII_status ozII_destroy(ozII_handle h) {
   if (h->batch) hipFree(h->batch);
   if (h->batch_queue) hipFree(h->batch_queue);
   if (h->batch_ws) hipFree(h->batch_ws);
+  if (h->lcand) hipFree(h->lcand);
   if (h->bar) {
     hipFree(h->bar);
     hipFree(h->flags);
@@ -1233,6 +1268,94 @@ ozII_status ozII_getrs(ozII_handle h, int32_t nc, int64_t n, int64_t nrhs, const
     }
   }
   return OZII_OK;
+}
+
+ozII_status ozII_getrf_limbs(ozII_handle h, int32_t nlimb, int64_t n, ozII_limbs *A,
+                             int64_t *ipiv, int32_t *info, const ozII_opts *o) {
+  if (!h) return OZII_EINVAL;
+  if (nlimb < 1 || nlimb > 64) return fail(h, OZII_EINVAL, "nlimb must be 1..64");
+  if (n < 0) return fail(h, OZII_EINVAL, "negative size");
+  if (!ipiv || !info) return fail(h, OZII_EINVAL, "null pointer");
+  if (n > 0 && !limbs_ok(A, n, n)) return fail(h, OZII_EINVAL, "bad limb matrix descriptor");
+  if (o && o->backend && o->backend != OZII_BE_INT8)
+    return fail(h, OZII_EUNSUPPORTED, "the limb format runs on the INT8 back-end only");
+  const int method = o ? o->method : OZII_METHOD_OZAKI;
+  if (method != OZII_METHOD_OZAKI && method != OZII_METHOD_NAIVE)
+    return fail(h, OZII_EINVAL, "unknown method");
+  const int64_t b = (o && o->block > 0) ? o->block : 256;
+  ozII_status st = limb_scratch(h);
+  if (st != OZII_OK) return st;
+  if (method == OZII_METHOD_OZAKI && n > b) {
+    // every Schur update has K = b: check its plan before anything runs
+    const HostPlan *hp;
+    const DevPlan *dp;
+    if ((st = get_plan(h, 64 * nlimb, b, o, &hp, &dp, true)) != OZII_OK) return st;
+  }
+  hipStream_t s = h->stream;
+  hipError_t e;
+  if ((e = ozl::launch_lfill_i32(info, 0, 1, s)) != hipSuccess) return hip_fail(h, e, "info");
+  const ozl::LimbMat M = limb_mat(A);
+  const double el = 8.0 * nlimb + 5.0;
+  for (int64_t k0 = 0; k0 < n; k0 += b) {
+    const int64_t kb = std::min(b, n - k0);
+    {
+      ProfScope ps(h, OZ_STAGE_PANEL, el * (double)(n - k0) * kb, 0);
+      for (int64_t j = k0; j < k0 + kb; ++j)
+        if ((e = ozl::launch_lpanel_column(M, nlimb, j, n, k0, k0 + kb, h->lcand, ipiv, info,
+                                           h->lflag, s)) != hipSuccess)
+          return hip_fail(h, e, "limb panel");
+    }
+    {
+      ProfScope ps(h, OZ_STAGE_LASWP, 2.0 * el * kb * (double)(n - kb), 0);
+      if ((e = ozl::launch_llaswp(M, nlimb, ipiv, k0, kb, 0, k0, k0 + kb, n, s)) != hipSuccess)
+        return hip_fail(h, e, "limb laswp");
+    }
+    const int64_t rest = n - k0 - kb;
+    if (rest == 0) continue;
+    {
+      ProfScope ps(h, OZ_STAGE_TRSM, el * (double)kb * rest, 0);
+      if ((e = ozl::launch_ltrsm(M, nlimb, k0, kb, n, s)) != hipSuccess)
+        return hip_fail(h, e, "limb U12 solve");
+    }
+    if (method == OZII_METHOD_NAIVE) {
+      ProfScope ps(h, OZ_STAGE_NAIVE, el * (double)rest * rest, 0);
+      if ((e = ozl::launch_lschur_naive(M, nlimb, k0, kb, n, s)) != hipSuccess)
+        return hip_fail(h, e, "limb native update");
+    } else {
+      const ozII_limbs L21 = limbs_at(A, k0 + kb, k0), U12 = limbs_at(A, k0, k0 + kb);
+      ozII_limbs A22 = limbs_at(A, k0 + kb, k0 + kb);
+      if ((st = gemm_limbs_impl(h, 1, nlimb, rest, rest, kb, &L21, &U12, &A22, o)) != OZII_OK)
+        return st;
+    }
+  }
+  return OZII_OK;
+}
+
+ozII_status ozII_getrs_limbs(ozII_handle h, int32_t nlimb, int64_t n, int64_t nrhs,
+                             const ozII_limbs *LU, const int64_t *ipiv, ozII_limbs *B) {
+  if (!h) return OZII_EINVAL;
+  if (nlimb < 1 || nlimb > 64) return fail(h, OZII_EINVAL, "nlimb must be 1..64");
+  if (n < 0 || nrhs < 0) return fail(h, OZII_EINVAL, "negative size");
+  if (n == 0 || nrhs == 0) return OZII_OK;
+  if (!ipiv || !limbs_ok(LU, n, n) || !limbs_ok(B, n, nrhs))
+    return fail(h, OZII_EINVAL, "bad limb matrix descriptor or null pointer");
+  ProfScope ps(h, OZ_STAGE_GETRS, (8.0 * nlimb + 5.0) * ((double)n * n + 2.0 * n * nrhs), 0);
+  const hipError_t e = ozl::launch_lgetrs(limb_mat(LU), nlimb, n, ipiv, limb_mat(B), nrhs, h->stream);
+  return e == hipSuccess ? OZII_OK : hip_fail(h, e, "limb solve");
+}
+
+ozII_status ozII_limbs_arith(ozII_handle h, int32_t op, int32_t nlimb, int64_t count,
+                             const ozII_limbs *A, const ozII_limbs *B, ozII_limbs *C) {
+  if (!h) return OZII_EINVAL;
+  if (op < 0 || op > 3) return fail(h, OZII_EINVAL, "op must be 0..3");
+  if (nlimb < 1 || nlimb > 64) return fail(h, OZII_EINVAL, "nlimb must be 1..64");
+  if (count < 0) return fail(h, OZII_EINVAL, "negative size");
+  if (count == 0) return OZII_OK;
+  if (!limbs_ok(A, count, 1) || !limbs_ok(B, count, 1) || !limbs_ok(C, count, 1))
+    return fail(h, OZII_EINVAL, "bad limb vector descriptor");
+  const hipError_t e = ozl::launch_larith(op, nlimb, count, limb_mat(A), limb_mat(B), limb_mat(C),
+                                          h->stream);
+  return e == hipSuccess ? OZII_OK : hip_fail(h, e, "limb arithmetic");
 }
 
 ozII_status ozII_batch_prepare(ozII_handle h, int32_t count, const ozII_batch_item *items) {

@@ -133,4 +133,31 @@ hipError_t launch_batch_oz(const ozII_batch_item *items, int count, int *queue, 
                            const ozk::DevPlan *pl4, uint8_t *ws, int64_t slot, int b,
                            hipStream_t s);
 
+// LU on limb matrices outside the Ozaki-II product (k_limb_lu.hip): limb q
+// of element (i, j) at limb[q plane + i + j ld]
+struct LimbMat {
+  uint64_t *limb;
+  int32_t *exp;
+  uint8_t *sign;
+  int64_t ld, plane;
+};
+// pivot-candidate workgroups per panel column (the size of `cand`)
+constexpr int LPIV_MAXGRID = 64;
+// one panel column j of the panel [c0, c1): pivot search, ipiv[j], info,
+// interchange inside the panel, division, rank-1 update; zflag: one word
+hipError_t launch_lpanel_column(LimbMat A, int nl, int64_t j, int64_t n, int64_t c0, int64_t c1,
+                                int64_t *cand, int64_t *ipiv, int32_t *info, int32_t *zflag,
+                                hipStream_t s);
+// interchanges ipiv[k0 .. k0+kb) on columns [ca0, ca1) and [cb0, cb1)
+hipError_t launch_llaswp(LimbMat A, int nl, const int64_t *ipiv, int64_t k0, int64_t kb,
+                         int64_t ca0, int64_t ca1, int64_t cb0, int64_t cb1, hipStream_t s);
+hipError_t launch_ltrsm(LimbMat A, int nl, int64_t k0, int64_t kb, int64_t n, hipStream_t s);
+hipError_t launch_lschur_naive(LimbMat A, int nl, int64_t k0, int64_t kb, int64_t n,
+                               hipStream_t s);
+hipError_t launch_lgetrs(LimbMat LU, int nl, int64_t n, const int64_t *ipiv, LimbMat X,
+                         int64_t nrhs, hipStream_t s);
+hipError_t launch_larith(int op, int nl, int64_t cnt, LimbMat A, LimbMat B, LimbMat C,
+                         hipStream_t s);
+hipError_t launch_lfill_i32(int32_t *p, int32_t v, int count, hipStream_t s);
+
 }  // namespace ozl

@@ -122,6 +122,36 @@ def test_getrs_arguments_are_validated():
             Z.check_getrs_args(**kw)
 
 
+def test_limb_solve_arguments_are_validated():
+    Z = _lib()
+    import torch
+    i64, i32, u8 = torch.int64, torch.int32, torch.uint8
+    n, nl = 6, 3
+
+    def mat(cols, rows, nlimb=nl, **kw):
+        return (_FakeCuda((nlimb, cols, rows), i64, **kw), _FakeCuda((cols, rows), i32),
+                _FakeCuda((cols, rows), u8))
+
+    ok = dict(LU=mat(n, n), ipiv=_FakeCuda((n,), i64), B=mat(2, n))
+    assert Z.check_getrs_limbs_args(**ok) == (nl, n, 2)
+    bad = [
+        dict(ok, LU=mat(n + 1, n)),                              # not square
+        dict(ok, LU=mat(n, n, nlimb=65)),                        # too many limbs
+        dict(ok, B=mat(2, n, nlimb=2)),                          # other precision
+        dict(ok, B=mat(2, n + 1)),                               # wrong order
+        dict(ok, B=mat(2, n, contiguous=False)),
+        dict(ok, B=(ok["B"][0], _FakeCuda((2, n), i64), ok["B"][2])),   # exp dtype
+        dict(ok, B=(ok["B"][0], ok["B"][1], _FakeCuda((2, n - 1), u8))),  # sign shape
+        dict(ok, ipiv=_FakeCuda((n,), i32)),
+        dict(ok, ipiv=_FakeCuda((n - 1,), i64)),
+        dict(ok, ipiv=_FakeCuda((n,), i64, device="cuda:1")),
+        dict(ok, LU=ok["LU"][:2]),                               # not a triple
+    ]
+    for kw in bad:
+        with pytest.raises(ValueError):
+            Z.check_getrs_limbs_args(**kw)
+
+
 def test_batch_items_are_validated():
     Z = _lib()
     import torch
