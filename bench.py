@@ -196,13 +196,20 @@ def main():
     ap.add_argument("--no-native", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=2048)
-    ap.add_argument("--workload", choices=["lu", "gemm", "schur", "batch", "limb-schur"],
+    ap.add_argument("--workload", choices=["lu", "gemm", "schur", "batch", "limb-schur", "limb-lu"],
                     default="lu",
                     help="lu: QD Lotkin LU (default); gemm: standalone TD product m=n=k=4096; "
                          "schur: only the LU's Ozaki-II Schur-update products (for profiling); "
                          "batch: 256 DD/QD systems n in [64, 512] in one persistent launch; "
                          "limb-schur: the Schur-update products of the Lotkin LU n=2048, "
-                         "b=256 at p=4096 (64-limb numbers)")
+                         "b=256 at p=4096 (64-limb numbers); limb-lu: the whole Lotkin LU + "
+                         "solve on limb numbers (--limb-n, --limb-p, --limb-block; Table lotkin: "
+                         "n=512, p=3136, b=256)")
+    ap.add_argument("--limb-n", type=int, default=512)
+    ap.add_argument("--limb-p", type=int, default=3136)
+    ap.add_argument("--limb-block", type=int, default=256)
+    ap.add_argument("--limb-native", choices=["auto", "yes", "no"], default="auto",
+                    help="also time the native limb LU (blocked and unblocked); auto: n <= 1024")
     ap.add_argument("--nlimb", type=int, default=64)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--gemm-n", type=int, default=4096)
@@ -250,6 +257,8 @@ def main():
         return bench_batch(args)
     if args.workload == "limb-schur":
         return bench_limb_schur(args)
+    if args.workload == "limb-lu":
+        return bench_limb_lu(args)
 
     n, nc, b = args.n, args.nc, args.block
     log(f"generating Lotkin n={n} nc={nc}")
@@ -873,6 +882,149 @@ def bench_limb_schur(args):
         log("cpu baseline (limb oracle sample)")
         out["cpu_baseline"] = limb_cpu_baseline(nl, shapes)
     print(json.dumps(out))
+
+
+def host_limbs(X):
+    """A device limb matrix back on the host, limbs as uint64."""
+    import numpy as np
+    lb, ex, sg = (x.cpu().numpy() for x in X)
+    return lb.view(np.uint64), ex, sg
+
+
+def limb_correct_bits(limb, ex, sg):
+    """min_i floor(-log2 |x_i - 1|) of a limb vector, exactly (no binary64
+    conversion, which would underflow at these precisions)."""
+    from fractions import Fraction
+    nl, n = limb.shape[0], limb.shape[-1]
+    p = 64 * nl
+    worst = None
+    for i in range(n):
+        m = 0
+        for q in range(nl - 1, -1, -1):
+            m = (m << 64) | int(limb[q, 0, i])
+        v = Fraction(0) if m == 0 else Fraction(m) * Fraction(2) ** (int(ex[0, i]) - p)
+        if sg[0, i]:
+            v = -v
+        d = abs(v - 1)
+        if d == 0:
+            continue
+        bits = d.denominator.bit_length() - d.numerator.bit_length()
+        if Fraction(2) ** (-bits) < d:
+            bits -= 1
+        worst = bits if worst is None else min(worst, bits)
+    return worst if worst is not None else 1 << 30
+
+
+# Table lotkin, GPU rows (total time of getrf + getrs in seconds, correct bits)
+PAPER_LOTKIN = {(512, 3136): {"H100": {"naive_b1": 1.323, "naive_blk": 1.345, "ozaki": 1.308},
+                              "GB10": {"naive_b1": 2.171, "naive_blk": 2.08, "ozaki": 1.651},
+                              "bits": 545, "b": 256}}
+
+
+def bench_limb_lu(args):
+    """The Lotkin LU + solve on limb numbers (Sec. 4.3, Table lotkin): getrf
+    with the Ozaki-II Schur update at panel width b, then getrs, timed
+    together; the native variants (blocked naive at the same b, unblocked)
+    beside it, and the correct bits of x against the true solution 1."""
+    import numpy as np
+    import torch
+
+    import paper_2609_29554_amd as Z
+    import workloads as W
+
+    n, p, b = args.limb_n, args.limb_p, args.limb_block
+    if p % 64 or not 64 <= p <= 4096:
+        raise SystemExit("--limb-p must be a multiple of 64 in [64, 4096]")
+    nl = p // 64
+    log(f"generating Lotkin limbs n={n} p={p}")
+    A = W.lotkin_limbs(n, nl)
+    B = W.lotkin_rhs_limbs(n, nl)
+
+    def up(X):
+        return tuple(torch.from_numpy(np.ascontiguousarray(x).view(np.int64) if x.dtype == np.uint64
+                                      else np.ascontiguousarray(x)).cuda() for x in X)
+
+    dA0, dB0 = up(A), up(B)
+    ctx = Z.Context(0)
+
+    def run(method, blk):
+        dA = tuple(x.clone() for x in dA0)
+        dX = tuple(x.clone() for x in dB0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ipiv, info = ctx.getrf_limbs(dA, block=blk, method=method)
+        ctx.getrs_limbs(dA, ipiv, dX)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.sync_check()
+        return dt, dX, int(info.cpu()[0])
+
+    log("warmup")
+    for _ in range(max(args.warmup, 1)):
+        run(Z.METHOD_OZAKI, b)
+    ctx.set_profiling(True)
+    ctx.profile_read()
+    times = []
+    for _ in range(args.steps):
+        dt, dX, info = run(Z.METHOD_OZAKI, b)
+        times.append(dt)
+        log(f"ozaki step {dt:.3f} s")
+    prof = ctx.profile_read()
+    ctx.set_profiling(False)
+    sec = sorted(times)[len(times) // 2]
+    bits = limb_correct_bits(*host_limbs(dX))
+    native = None
+    if args.limb_native == "yes" or (args.limb_native == "auto" and n <= 1024):
+        native = {}
+        for name, blk in (("naive_blk", b), ("naive_b1", n)):
+            log(f"native {name}")
+            dt, dXn, _ = run(Z.METHOD_NAIVE, blk)
+            native[name] = {"s": dt, "block": blk,
+                            "correct_bits": limb_correct_bits(*host_limbs(dXn))}
+        best = min(v["s"] for v in native.values())
+        native["speedup_vs_best_native"] = best / sec
+    steps_p = args.steps
+    stages = {k: {"ms_per_step": v[0] / steps_p, "launches_per_step": v[1] / steps_p}
+              for k, v in prof.items() if v[1]}
+    roof = None
+    if prof.get("gemm") and prof["gemm"][1]:
+        ms, launches, _, ops = prof["gemm"]
+        ach = ops / launches / (ms / launches * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_MFMA["int8"], "unit": "TOP/s",
+                "frac": ach / PEAK_MFMA["int8"], "traffic": None, "kernel": "gemm",
+                "avg_launch_ms": ms / launches, "launches": launches / steps_p,
+                "algorithmic_ops_per_launch": ops / launches}
+    out = {"metric": METRIC, "value": sec, "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u64 limbs+i8", "data": "synthetic",
+           "config": {"workload": f"Lotkin LU + solve on limb numbers n={n} p={p} b={b} "
+                                  f"(getrf_limbs Ozaki-II INT8 + getrs_limbs)",
+                      "n": n, "p": p, "block": b},
+           "correct_bits": bits, "info": info, "native": native, "roofline": roof,
+           "stages": stages, "paper_context": PAPER_LOTKIN.get((n, p))}
+    ctx.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = limb_lu_cpu_baseline(n, nl)
+    print(json.dumps(out))
+
+
+def limb_lu_cpu_baseline(n, nl, n_sample=256):
+    """The p-bit oracle's LU + solve (unblocked, multiply-subtracts, as it
+    stands) on the Lotkin matrix of order min(n, n_sample) at the same p,
+    scaled by n^3 to the workload's order."""
+    import oracle.lfloat as LF
+    m = min(n, n_sample)
+    A = LF.lotkin(m, nl)
+    rhs = LF.rhs_times_ones(A)
+    t0 = time.perf_counter()
+    F, ip, _ = LF.getrf(A)
+    LF.getrs(F, ip, rhs)
+    t = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": t * (n / m) ** 3, "unit": "s", "cores": min(threads, os.cpu_count() or threads),
+            "kind": "oracle",
+            "sample": f"oracle getrf + getrs of the Lotkin matrix n={m} at p={64 * nl}: {t:.1f} s, "
+                      f"scaled by (n/{m})^3"}
 
 
 if __name__ == "__main__":

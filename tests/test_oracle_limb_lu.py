@@ -134,3 +134,11 @@ def test_factors_and_solution_against_exact_lu(nl, b):
     X = OLU.getrs(F, ip, B)
     xv = [v[0] for v in _vals(X)]
     assert all(abs(v - 1) <= Fraction(1, 2 ** (p - 30)) for v in xv)
+
+
+@pytest.mark.parametrize("n,nl", [(37, 1), (64, 3)])
+def test_lotkin_limb_generators_match_oracle(n, nl):
+    """The benchmark's Lotkin matrix and right-hand side (workloads) equal
+    the oracle's: RN_p of 1/(i+j+1), and RN_p of the exact row sums."""
+    assert _eq(W.lotkin_limbs(n, nl), OLU.from_lf(LF.lotkin(n, nl)))
+    assert _eq(W.lotkin_rhs_limbs(n, nl), OLU.from_lf(LF.rhs_times_ones(LF.lotkin(n, nl))))

@@ -215,3 +215,28 @@ def lotkin_limbs(n: int, nlimb: int):
     e = texp[dd]
     sign = np.zeros((n, n), dtype=np.uint8)
     return limb, e, sign
+
+
+def lotkin_rhs_limbs(n: int, nlimb: int):
+    """b = A 1 for the Lotkin limb matrix: every row of the stored (rounded)
+    entries summed exactly, then rounded to nearest-even at p bits (Sec. 4.3:
+    b formed at high precision and rounded to the target precision).
+    Layout of a one-column limb matrix: (nlimb, 1, n), (1, n), (1, n)."""
+    p = 64 * nlimb
+    # the stored entry 1/d (d = 1 for row 0) as an integer on the grid 2^(emin - p)
+    vals = {}
+    for d in range(1, 2 * n):
+        _, m, ex = _limb_of_fraction(Fraction(1, d), p)
+        vals[d] = (m, ex)
+    emin = min(ex for _, ex in vals.values())
+    grid = {d: m << (ex - emin) for d, (m, ex) in vals.items()}
+    limb_out = np.zeros((nlimb, 1, n), dtype=np.uint64)
+    e_out = np.zeros((1, n), dtype=np.int32)
+    s_out = np.zeros((1, n), dtype=np.uint8)
+    for i in range(n):
+        tot = n * grid[1] if i == 0 else sum(grid[i + j + 1] for j in range(n))
+        _, m, ex = _limb_of_fraction(Fraction(tot, 1 << (p - emin)), p)
+        for q in range(nlimb):
+            limb_out[q, 0, i] = (m >> (64 * q)) & ((1 << 64) - 1)
+        e_out[0, i] = ex
+    return limb_out, e_out, s_out
