@@ -208,6 +208,9 @@ def main():
     ap.add_argument("--limb-n", type=int, default=512)
     ap.add_argument("--limb-p", type=int, default=3136)
     ap.add_argument("--limb-block", type=int, default=256)
+    ap.add_argument("--limb-leaf", type=int, default=32,
+                    help="recursive panel / U12 solve down to this width, inner updates by "
+                         "Ozaki-II (0 = unblocked panel)")
     ap.add_argument("--limb-native", choices=["auto", "yes", "no"], default="auto",
                     help="also time the native limb LU (blocked and unblocked); auto: n <= 1024")
     ap.add_argument("--nlimb", type=int, default=64)
@@ -947,12 +950,14 @@ def bench_limb_lu(args):
     dA0, dB0 = up(A), up(B)
     ctx = Z.Context(0)
 
-    def run(method, blk):
+    leaf = args.limb_leaf
+
+    def run(method, blk, lf=0):
         dA = tuple(x.clone() for x in dA0)
         dX = tuple(x.clone() for x in dB0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ipiv, info = ctx.getrf_limbs(dA, block=blk, method=method)
+        ipiv, info = ctx.getrf_limbs(dA, block=blk, method=method, leaf=lf)
         ctx.getrs_limbs(dA, ipiv, dX)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -961,18 +966,23 @@ def bench_limb_lu(args):
 
     log("warmup")
     for _ in range(max(args.warmup, 1)):
-        run(Z.METHOD_OZAKI, b)
+        run(Z.METHOD_OZAKI, b, leaf)
     ctx.set_profiling(True)
     ctx.profile_read()
     times = []
     for _ in range(args.steps):
-        dt, dX, info = run(Z.METHOD_OZAKI, b)
+        dt, dX, info = run(Z.METHOD_OZAKI, b, leaf)
         times.append(dt)
         log(f"ozaki step {dt:.3f} s")
     prof = ctx.profile_read()
     ctx.set_profiling(False)
     sec = sorted(times)[len(times) // 2]
     bits = limb_correct_bits(*host_limbs(dX))
+    flat = None
+    if leaf:
+        dt, dXf, _ = run(Z.METHOD_OZAKI, b, 0)
+        flat = {"s": dt, "correct_bits": limb_correct_bits(*host_limbs(dXf))}
+        log(f"ozaki, unblocked panel {dt:.3f} s")
     native = None
     if args.limb_native == "yes" or (args.limb_native == "auto" and n <= 1024):
         native = {}
@@ -999,8 +1009,9 @@ def bench_limb_lu(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "u64 limbs+i8", "data": "synthetic",
            "config": {"workload": f"Lotkin LU + solve on limb numbers n={n} p={p} b={b} "
                                   f"(getrf_limbs Ozaki-II INT8 + getrs_limbs)",
-                      "n": n, "p": p, "block": b},
-           "correct_bits": bits, "info": info, "native": native, "roofline": roof,
+                      "n": n, "p": p, "block": b, "panel_leaf": leaf},
+           "correct_bits": bits, "info": info, "ozaki_unblocked_panel": flat, "native": native,
+           "roofline": roof,
            "stages": stages, "paper_context": PAPER_LOTKIN.get((n, p))}
     ctx.close()
     if not args.no_cpu_baseline:

@@ -84,6 +84,11 @@ typedef struct {
                         /* qbits + 1) with N_mod the fewest moduli covering   */
                         /* the CRT range 2 K 2^(2 qbits); 0 = plan rule.      */
                         /* Needs nslice <= 1 and no extra groups (EINVAL).    */
+  int32_t panel_leaf;   /* ozII_getrf_limbs: > 0 = recursive panel and U12    */
+                        /* solve down to this many columns / rows, their      */
+                        /* inner updates by the Schur update's method (the    */
+                        /* Ozaki-II panel of Sec. 5.2); 0 = unblocked panel   */
+                        /* and row-by-row solve.                              */
 } ozII_opts;
 
 /* ozII_opts.flags.  OZII_F_NO_LOOKAHEAD: getrf runs each Schur update as

@@ -24,6 +24,16 @@ The blocked right-looking LU of Sec. 3.4, for each panel of b columns:
 With the native update every element receives the operations of the
 unblocked LU in the same order, so the result equals ``orc_lf_getrf`` bit
 for bit for any b; with b >= n the Ozaki variant is the unblocked LU too.
+
+With leaf > 0 the panel and the U12 solve recurse (the acceleration of the
+panel by Ozaki-II that Sec. 5.2 proposes): a panel of w > leaf columns
+factors its left part (w1 = half its leaf-wide blocks), solves the rows
+above for its right part, updates the rows below it with the left part's
+L (K = w1) and factors the rest; a solve of h > leaf rows solves the top
+h1 rows, updates the rest, and solves them.  Leaves are the unblocked
+panel (interchanges across the whole panel) and the multiply-subtract
+solve.  With multiply-subtract updates the result is still the unblocked
+LU bit for bit.
 The solve is ``orc_lf_getrs`` (Sec. 4.3: forward and backward substitution,
 x_k divided by u_kk).
 """
@@ -78,55 +88,112 @@ def _swap_rows(X, r1, r2, cols):
         a[cols, r2] = t
 
 
-def getrf(A, b: int, method: str = "ozaki", extra_groups: int = 0):
-    """Blocked LU of the n x n limb matrix A with panel width b.  Returns
-    (LU in the limbs.py layout, ipiv (0-based rows, LAPACK semantics), info)."""
-    X = to_lf(A)
-    m, e, s = X
-    n = e.shape[0]
-    nl = m.shape[2]
-    ld = n
-    ipiv = np.zeros(n, dtype=np.int64)
-    info = 0
+def split(w: int, leaf: int) -> int:
+    """Left part of a recursive split of w > leaf columns: half of the
+    leaf-wide blocks, rounded up."""
+    blocks = -(-w // leaf)
+    return -(-blocks // 2) * leaf
+
+
+class _LU:
+    """The blocked LU's steps on the lfloat arrays X of an n x n matrix."""
+
+    def __init__(self, X, method, leaf, extra_groups):
+        self.X = X
+        self.m, self.e, self.s = X
+        self.n = self.e.shape[0]
+        self.nl = self.m.shape[2]
+        self.method = method
+        self.leaf = leaf
+        self.extra_groups = extra_groups
+        self.ipiv = np.zeros(self.n, dtype=np.int64)
+        self.info = 0
+
+    def update(self, i0, i1, c0, c1, k0, K):
+        """A[i0:i1, c0:c1] -= A[i0:i1, k0:k0+K] A[k0:k0+K, c0:c1]."""
+        n, nl, X = self.n, self.nl, self.X
+        if i1 <= i0 or c1 <= c0 or K == 0:
+            return
+        if self.method == "native":
+            lib().orc_lf_gemm_sub(nl, i1 - i0, c1 - c0, K, *_ptrs(X, i0, k0, n), n,
+                                  *_ptrs(X, k0, c0, n), n, *_ptrs(X, i0, c0, n), n)
+            return
+        m, e, s = self.m, self.e, self.s
+
+        def sub(r0, r1, cc0, cc1):
+            return from_lf((m[cc0:cc1, r0:r1], e[cc0:cc1, r0:r1], s[cc0:cc1, r0:r1]))
+        plan = make_plan(64 * nl, K, extra_groups=self.extra_groups)
+        out, _ = OL.ozgemm(1, sub(i0, i1, k0, k0 + K), sub(k0, k0 + K, c0, c1),
+                           sub(i0, i1, c0, c1), plan)
+        om, oe, os_ = to_lf(out)
+        m[c0:c1, i0:i1] = om
+        e[c0:c1, i0:i1] = oe
+        s[c0:c1, i0:i1] = os_
+
+    def trsm(self, r0, h, b0, b1):
+        """B = A[r0:r0+h, b0:b1] <- L^-1 B, L the unit lower triangle at
+        (r0, r0): multiply-subtracts in leaves, the rest by updates."""
+        if b1 <= b0 or h <= 1:
+            return
+        n, nl, X = self.n, self.nl, self.X
+        if not self.leaf or h <= self.leaf:
+            lib().orc_lf_trsm_lunit(nl, h, b1 - b0, *_ptrs(X, r0, r0, n), n,
+                                    *_ptrs(X, r0, b0, n), n)
+            return
+        h1 = split(h, self.leaf)
+        self.trsm(r0, h1, b0, b1)
+        self.update(r0 + h1, r0 + h, b0, b1, r0, h1)
+        self.trsm(r0 + h1, h - h1, b0, b1)
+
+    def panel(self, c0, w, P0, P1):
+        """Columns [c0, c0+w) over rows [c0, n); interchanges across the
+        whole panel [P0, P1)."""
+        n, nl, X = self.n, self.nl, self.X
+        if not self.leaf or w <= self.leaf:
+            piv = np.zeros(w, dtype=np.int64)
+            inf = np.zeros(1, dtype=np.int32)
+            lib().orc_lf_getf2(nl, n - c0, w, *_ptrs(X, c0, c0, n), n,
+                               piv.ctypes.data_as(_i64p), inf.ctypes.data_as(_i32p))
+            self.ipiv[c0:c0 + w] = piv + c0
+            if inf[0] and not self.info:
+                self.info = c0 + int(inf[0])
+            others = np.r_[P0:c0, c0 + w:P1]
+            for jj in range(c0, c0 + w):
+                r = int(self.ipiv[jj])
+                if r != jj and others.size:
+                    _swap_rows(X, jj, r, others)
+            return
+        w1 = split(w, self.leaf)
+        self.panel(c0, w1, P0, P1)
+        self.trsm(c0, w1, c0 + w1, c0 + w)
+        self.update(c0 + w1, n, c0 + w1, c0 + w, c0, w1)
+        self.panel(c0 + w1, w - w1, P0, P1)
+
+
+def getrf(A, b: int, method: str = "ozaki", extra_groups: int = 0, leaf: int = 0):
+    """Blocked LU of the n x n limb matrix A with panel width b.  leaf > 0:
+    the panel and the U12 solve recurse on halves down to leaf columns or
+    rows, the inner updates made like the Schur update (Ozaki-II or
+    multiply-subtracts).  Returns (LU in the limbs.py layout, ipiv (0-based
+    rows, LAPACK semantics), info)."""
+    if method not in ("ozaki", "native"):
+        raise ValueError(method)
+    L = _LU(to_lf(A), method, leaf, extra_groups)
+    n = L.n
     b = max(1, int(b))
     for k0 in range(0, n, b):
         kb = min(b, n - k0)
-        piv = np.zeros(kb, dtype=np.int64)
-        inf = np.zeros(1, dtype=np.int32)
-        lib().orc_lf_getf2(nl, n - k0, kb, *_ptrs(X, k0, k0, ld), ld, piv.ctypes.data_as(_i64p),
-                           inf.ctypes.data_as(_i32p))
-        ipiv[k0:k0 + kb] = piv + k0
-        if inf[0] and not info:
-            info = k0 + int(inf[0])
+        L.panel(k0, kb, k0, k0 + kb)
         others = np.r_[0:k0, k0 + kb:n]
         for jj in range(k0, k0 + kb):
-            r = int(ipiv[jj])
+            r = int(L.ipiv[jj])
             if r != jj and others.size:
-                _swap_rows(X, jj, r, others)
-        rest = n - k0 - kb
-        if rest == 0:
+                _swap_rows(L.X, jj, r, others)
+        if n - k0 - kb == 0:
             continue
-        lib().orc_lf_trsm_lunit(nl, kb, rest, *_ptrs(X, k0, k0, ld), ld,
-                                *_ptrs(X, k0, k0 + kb, ld), ld)
-        if method == "native":
-            lib().orc_lf_gemm_sub(nl, rest, rest, kb, *_ptrs(X, k0 + kb, k0, ld), ld,
-                                  *_ptrs(X, k0, k0 + kb, ld), ld, *_ptrs(X, k0 + kb, k0 + kb, ld),
-                                  ld)
-        elif method == "ozaki":
-            def sub(r0, r1, c0, c1):
-                return from_lf((m[c0:c1, r0:r1], e[c0:c1, r0:r1], s[c0:c1, r0:r1]))
-            L21 = sub(k0 + kb, n, k0, k0 + kb)
-            U12 = sub(k0, k0 + kb, k0 + kb, n)
-            A22 = sub(k0 + kb, n, k0 + kb, n)
-            plan = make_plan(64 * nl, kb, extra_groups=extra_groups)
-            out, _ = OL.ozgemm(1, L21, U12, A22, plan)
-            om, oe, os_ = to_lf(out)
-            m[k0 + kb:, k0 + kb:] = om
-            e[k0 + kb:, k0 + kb:] = oe
-            s[k0 + kb:, k0 + kb:] = os_
-        else:
-            raise ValueError(method)
-    return from_lf(X), ipiv, info
+        L.trsm(k0, kb, k0 + kb, n)
+        L.update(k0 + kb, n, k0 + kb, n, k0, kb)
+    return from_lf(L.X), L.ipiv, L.info
 
 
 def getrs(LU, ipiv, B):

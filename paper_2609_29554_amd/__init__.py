@@ -36,7 +36,8 @@ class OziiError(RuntimeError):
 class Opts(C.Structure):
     _fields_ = [("backend", C.c_int32), ("nslice", C.c_int32), ("extra_groups", C.c_int32),
                 ("guard_ex", C.c_int32), ("block", C.c_int32), ("method", C.c_int32),
-                ("flags", C.c_int32), ("gemm_tile", C.c_int32), ("qbits", C.c_int32)]
+                ("flags", C.c_int32), ("gemm_tile", C.c_int32), ("qbits", C.c_int32),
+                ("panel_leaf", C.c_int32)]
 
 
 _lib = None
@@ -145,8 +146,9 @@ def noalloc_capacity() -> int:
 
 def make_opts(backend: int = 0, nslice: int = 0, extra_groups: int = 0, guard_ex: int = 0,
               block: int = 0, method: int = 0, gemm_tile: int = 0, flags: int = 0,
-              qbits: int = 0) -> Opts:
-    return Opts(backend, nslice, extra_groups, guard_ex, block, method, flags, gemm_tile, qbits)
+              qbits: int = 0, panel_leaf: int = 0) -> Opts:
+    return Opts(backend, nslice, extra_groups, guard_ex, block, method, flags, gemm_tile, qbits,
+                panel_leaf)
 
 
 def plan_query(p: int, K: int, opts: Optional[Opts] = None):
@@ -481,9 +483,10 @@ class Context:
         return B
 
     def getrf_limbs(self, A, block: int = 256, method: int = METHOD_OZAKI,
-                    opts: Optional[Opts] = None):
+                    opts: Optional[Opts] = None, leaf: Optional[int] = None):
         """In-place LU of the n x n limb matrix A = (limb, exp, sign);
-        returns (ipiv int64[n] 0-based, info int32[1]) on the device."""
+        returns (ipiv int64[n] 0-based, info int32[1]) on the device.
+        leaf > 0: recursive panel and U12 solve down to leaf columns."""
         import torch
         nl, cols, rows = check_limb_mat(A)
         if cols != rows:
@@ -492,6 +495,8 @@ class Context:
         o = opts if opts is not None else Opts()
         o.block = block
         o.method = method
+        if leaf is not None:
+            o.panel_leaf = leaf
         ipiv = torch.empty(max(n, 1), dtype=torch.int64, device=A[0].device)
         info = torch.zeros(1, dtype=torch.int32, device=A[0].device)
         d = self._limb_desc(A)

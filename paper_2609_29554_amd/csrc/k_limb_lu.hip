@@ -7,8 +7,10 @@
 //     the interchange inside the panel) -> k_ldiv (l = RN(a / pivot)) ->
 //     k_lrank1 (RN(a - RN(l u)) on the panel's remaining columns);
 //   k_llaswp: the panel's interchanges on the other columns, in order;
-//   k_ltrsm:  U12 <- L11^-1 U12, one workgroup per column, k ascending;
-//   k_lschur_naive: the native update RN(a - RN(l_ik u_kj)), k ascending;
+//   k_ltrsm:  B <- L^-1 B for a unit lower triangle (the U12 solve and the
+//     leaves of its recursive form), one workgroup per column, k ascending;
+//   k_lschur_naive: the native update RN(a - RN(l_ik u_kj)), k ascending, on
+//     any block (the Schur update, or the inner updates of the recursion);
 //   getrs: the interchanges, then blocks of LBLK rows: the diagonal block
 //     by one workgroup per right-hand side, the rows below (forward) or
 //     above (backward) by one wavefront each, every element taking its
@@ -77,10 +79,11 @@ __device__ __forceinline__ void swap_el(const LimbMat &A, int64_t i1, int64_t i2
 }
 
 __device__ __forceinline__ int wave_in_block() { return (int)(threadIdx.x >> 6); }
+__device__ __forceinline__ int waves_in_block() { return (int)(blockDim.x >> 6); }
 __device__ __forceinline__ int64_t wave_global() {
-  return (int64_t)blockIdx.x * WPB + wave_in_block();
+  return (int64_t)blockIdx.x * waves_in_block() + wave_in_block();
 }
-__device__ __forceinline__ int64_t waves_total() { return (int64_t)gridDim.x * WPB; }
+__device__ __forceinline__ int64_t waves_total() { return (int64_t)gridDim.x * waves_in_block(); }
 
 // keep (r, x) when |x| is larger, or equal with a lower row
 __device__ __forceinline__ void take_max(int64_t &b, WF &v, int64_t r, const WF &x) {
@@ -111,40 +114,65 @@ __global__ __launch_bounds__(256) void k_lpiv(LimbMat A, int nl, int64_t j, int6
   }
 }
 
-__global__ __launch_bounds__(256) void k_lpiv_final(LimbMat A, int nl, int64_t j,
-                                                    const int64_t *cand, int ncand, int64_t c0,
-                                                    int64_t c1, int64_t *ipiv, int32_t *info,
-                                                    int32_t *zflag) {
-  __shared__ int64_t srow[WPB];
-  __shared__ int64_t spiv;
-  const int w = wave_in_block();
+// The pivot among the per-workgroup candidates: 16 wavefronts take up to
+// four candidates each, then a tournament through LDS (greatest |value|,
+// lowest row on ties); ipiv, info, the zero flag and the interchange across
+// the panel's columns [c0, c1).
+constexpr int FIN_WAVES = 16;
+__global__ __launch_bounds__(1024) void k_lpiv_final(LimbMat A, int nl, int64_t j,
+                                                     const int64_t *cand, int ncand, int64_t c0,
+                                                     int64_t c1, int64_t *ipiv, int32_t *info,
+                                                     int32_t *zflag) {
+  __shared__ uint64_t sm[FIN_WAVES][64];
+  __shared__ int64_t srow[FIN_WAVES];
+  __shared__ int32_t se[FIN_WAVES];
+  __shared__ uint32_t ss[FIN_WAVES];
+  const int w = wave_in_block(), l = lfp::lane_id();
   int64_t b = -1;
   WF v = lfp::wf_zero();
-  for (int k = w; k < ncand; k += WPB) {
+  for (int k = w; k < ncand; k += FIN_WAVES) {
     const int64_t r = cand[k];
     if (r >= 0) take_max(b, v, r, ld_el(A, r, j, nl));
   }
-  if (lfp::lane_id() == 0) srow[w] = b;
-  __syncthreads();
-  if (w == 0) {
-    int64_t bb = -1;
-    WF vv = lfp::wf_zero();
-    for (int k = 0; k < WPB; ++k) {
-      const int64_t r = srow[k];
-      if (r >= 0) take_max(bb, vv, r, ld_el(A, r, j, nl));
-    }
-    if (lfp::lane_id() == 0) {
-      spiv = bb;
-      ipiv[j] = bb;
-      const int32_t z = lfp::is_zero(vv) ? 1 : 0;
-      zflag[0] = z;
-      if (z && info[0] == 0) info[0] = (int32_t)(j + 1);
-    }
+  sm[w][l] = v.m;
+  if (l == 0) {
+    srow[w] = b;
+    se[w] = v.e;
+    ss[w] = v.s;
   }
   __syncthreads();
-  const int64_t r = spiv;
+  for (int step = 1; step < FIN_WAVES; step *= 2) {
+    if ((w & (2 * step - 1)) == 0) {
+      const int o = w + step;
+      const int64_t r = srow[o];
+      if (r >= 0) {
+        WF x;
+        x.m = sm[o][l];
+        x.e = se[o];
+        x.s = ss[o];
+        take_max(b, v, r, x);
+      }
+    }
+    __syncthreads();
+    if ((w & (2 * step - 1)) == 0) {
+      sm[w][l] = v.m;
+      if (l == 0) {
+        srow[w] = b;
+        se[w] = v.e;
+        ss[w] = v.s;
+      }
+    }
+    __syncthreads();
+  }
+  if (w == 0 && l == 0) {
+    ipiv[j] = b;
+    const int32_t z = lfp::is_zero(v) ? 1 : 0;
+    zflag[0] = z;
+    if (z && info[0] == 0) info[0] = (int32_t)(j + 1);
+  }
+  const int64_t r = srow[0];
   if (r != j)
-    for (int64_t c = c0 + w; c < c1; c += WPB) swap_el(A, j, r, c, nl);
+    for (int64_t c = c0 + w; c < c1; c += FIN_WAVES) swap_el(A, j, r, c, nl);
 }
 
 __global__ __launch_bounds__(256) void k_ldiv(LimbMat A, int nl, int64_t j, int64_t n,
@@ -181,41 +209,46 @@ __global__ __launch_bounds__(256) void k_llaswp(LimbMat A, int nl, const int64_t
   }
 }
 
-__global__ __launch_bounds__(256) void k_ltrsm(LimbMat A, int nl, int64_t k0, int64_t kb,
-                                               int64_t n) {
-  const int w = wave_in_block();
-  for (int64_t c = k0 + kb + blockIdx.x; c < n; c += gridDim.x) {
-    for (int64_t k = 0; k + 1 < kb; ++k) {
-      const WF u = ld_el(A, k0 + k, c, nl);
-      for (int64_t i = k + 1 + w; i < kb; i += WPB) {
-        const WF a = ld_el(A, k0 + i, c, nl), lv = ld_el(A, k0 + i, k0 + k, nl);
-        st_el(A, k0 + i, c, nl, lfp::fms(a, lv, u, nl));
+// B = A[r0:r0+h, b0:b1] <- L^-1 B for the unit lower triangle L at (r0, r0):
+// one workgroup per column, k ascending, the rows below k over its waves
+__global__ __launch_bounds__(1024) void k_ltrsm(LimbMat A, int nl, int64_t r0, int64_t h,
+                                                int64_t b0, int64_t b1) {
+  const int w = wave_in_block(), nw = waves_in_block();
+  for (int64_t c = b0 + blockIdx.x; c < b1; c += gridDim.x) {
+    for (int64_t k = 0; k + 1 < h; ++k) {
+      const WF u = ld_el(A, r0 + k, c, nl);
+      for (int64_t i = k + 1 + w; i < h; i += nw) {
+        const WF a = ld_el(A, r0 + i, c, nl), lv = ld_el(A, r0 + i, r0 + k, nl);
+        st_el(A, r0 + i, c, nl, lfp::fms(a, lv, u, nl));
       }
       __syncthreads();
     }
   }
 }
 
-__global__ __launch_bounds__(256) void k_lschur_naive(LimbMat A, int nl, int64_t k0, int64_t kb,
-                                                      int64_t n) {
-  const int64_t m = n - k0 - kb, cnt = m * m;
+// A[i0:i1, c0:c1] -= A[i0:i1, k0:k0+K] A[k0:k0+K, c0:c1] by multiply-subtracts,
+// k ascending; one wavefront per element
+__global__ __launch_bounds__(256) void k_lschur_naive(LimbMat A, int nl, int64_t i0, int64_t i1,
+                                                      int64_t c0, int64_t c1, int64_t k0,
+                                                      int64_t K) {
+  const int64_t m = i1 - i0, cnt = m * (c1 - c0);
   for (int64_t t = wave_global(); t < cnt; t += waves_total()) {
-    const int64_t i = k0 + kb + t % m, c = k0 + kb + t / m;
+    const int64_t i = i0 + t % m, c = c0 + t / m;
     WF a = ld_el(A, i, c, nl);
-    for (int64_t k = 0; k < kb; ++k)
-      a = lfp::fms(a, ld_el(A, i, k0 + k, nl), ld_el(A, k0 + k, c, nl), nl);
+    for (int64_t k = k0; k < k0 + K; ++k)
+      a = lfp::fms(a, ld_el(A, i, k, nl), ld_el(A, k, c, nl), nl);
     st_el(A, i, c, nl, a);
   }
 }
 
 // forward substitution, diagonal block [k0, k1); blockIdx.x = right-hand side
-__global__ __launch_bounds__(256) void k_lfwd_diag(LimbMat LU, LimbMat X, int nl, int64_t k0,
-                                                   int64_t k1) {
+__global__ __launch_bounds__(1024) void k_lfwd_diag(LimbMat LU, LimbMat X, int nl, int64_t k0,
+                                                    int64_t k1) {
   const int64_t r = blockIdx.x;
-  const int w = wave_in_block();
+  const int w = wave_in_block(), nw = waves_in_block();
   for (int64_t k = k0; k + 1 < k1; ++k) {
     const WF xk = ld_el(X, k, r, nl);
-    for (int64_t i = k + 1 + w; i < k1; i += WPB)
+    for (int64_t i = k + 1 + w; i < k1; i += nw)
       st_el(X, i, r, nl, lfp::fms(ld_el(X, i, r, nl), ld_el(LU, i, k, nl), xk, nl));
     __syncthreads();
   }
@@ -233,15 +266,15 @@ __global__ __launch_bounds__(256) void k_lfwd_rest(LimbMat LU, LimbMat X, int nl
 }
 
 // backward substitution, diagonal block [k0, k1), k descending
-__global__ __launch_bounds__(256) void k_lbwd_diag(LimbMat LU, LimbMat X, int nl, int64_t k0,
-                                                   int64_t k1) {
+__global__ __launch_bounds__(1024) void k_lbwd_diag(LimbMat LU, LimbMat X, int nl, int64_t k0,
+                                                    int64_t k1) {
   const int64_t r = blockIdx.x;
-  const int w = wave_in_block();
+  const int w = wave_in_block(), nw = waves_in_block();
   for (int64_t k = k1 - 1; k >= k0; --k) {
     if (w == 0) st_el(X, k, r, nl, lfp::div(ld_el(X, k, r, nl), ld_el(LU, k, k, nl), nl));
     __syncthreads();
     const WF xk = ld_el(X, k, r, nl);
-    for (int64_t i = k0 + w; i < k; i += WPB)
+    for (int64_t i = k0 + w; i < k; i += nw)
       st_el(X, i, r, nl, lfp::fms(ld_el(X, i, r, nl), ld_el(LU, i, k, nl), xk, nl));
     __syncthreads();
   }
@@ -290,18 +323,18 @@ int grid_for(int64_t waves, int64_t cap = 8192) {
 namespace ozl {
 
 int lpiv_grid(int64_t rows) {
-  int64_t g = (rows + 31) / 32;  // at least eight rows per wavefront
+  int64_t g = (rows + 7) / 8;  // at least two rows per wavefront
   if (g < 1) g = 1;
   return (int)(g < LPIV_MAXGRID ? g : LPIV_MAXGRID);
 }
 
-hipError_t launch_lpanel_column(LimbMat A, int nl, int64_t j, int64_t n, int64_t c0, int64_t c1,
-                                int64_t *cand, int64_t *ipiv, int32_t *info, int32_t *zflag,
-                                hipStream_t s) {
+hipError_t launch_lpanel_column(LimbMat A, int nl, int64_t j, int64_t n, int64_t s0, int64_t s1,
+                                int64_t c1, int64_t *cand, int64_t *ipiv, int32_t *info,
+                                int32_t *zflag, hipStream_t s) {
   const int g = lpiv_grid(n - j);
   hipLaunchKernelGGL(k_lpiv, dim3(g), dim3(256), 0, s, A, nl, j, n, cand);
-  hipLaunchKernelGGL(k_lpiv_final, dim3(1), dim3(256), 0, s, A, nl, j, (const int64_t *)cand, g,
-                     c0, c1, ipiv, info, zflag);
+  hipLaunchKernelGGL(k_lpiv_final, dim3(1), dim3(64 * FIN_WAVES), 0, s, A, nl, j,
+                     (const int64_t *)cand, g, s0, s1, ipiv, info, zflag);
   if (j + 1 < n) {
     hipLaunchKernelGGL(k_ldiv, dim3(grid_for(n - j - 1)), dim3(256), 0, s, A, nl, j, n,
                        (const int32_t *)zflag);
@@ -321,19 +354,21 @@ hipError_t launch_llaswp(LimbMat A, int nl, const int64_t *ipiv, int64_t k0, int
   return hipGetLastError();
 }
 
-hipError_t launch_ltrsm(LimbMat A, int nl, int64_t k0, int64_t kb, int64_t n, hipStream_t s) {
-  const int64_t cols = n - k0 - kb;
-  if (cols <= 0 || kb <= 1) return hipSuccess;
-  hipLaunchKernelGGL(k_ltrsm, dim3((unsigned)(cols < 65535 ? cols : 65535)), dim3(256), 0, s, A,
-                     nl, k0, kb, n);
+hipError_t launch_ltrsm(LimbMat A, int nl, int64_t r0, int64_t h, int64_t b0, int64_t b1,
+                        hipStream_t s) {
+  const int64_t cols = b1 - b0;
+  if (cols <= 0 || h <= 1) return hipSuccess;
+  hipLaunchKernelGGL(k_ltrsm, dim3((unsigned)(cols < 65535 ? cols : 65535)), dim3(1024), 0, s, A,
+                     nl, r0, h, b0, b1);
   return hipGetLastError();
 }
 
-hipError_t launch_lschur_naive(LimbMat A, int nl, int64_t k0, int64_t kb, int64_t n,
-                               hipStream_t s) {
-  const int64_t m = n - k0 - kb;
-  if (m <= 0 || kb <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lschur_naive, dim3(grid_for(m * m)), dim3(256), 0, s, A, nl, k0, kb, n);
+hipError_t launch_lschur_naive(LimbMat A, int nl, int64_t i0, int64_t i1, int64_t c0, int64_t c1,
+                               int64_t k0, int64_t K, hipStream_t s) {
+  const int64_t cnt = (i1 - i0) * (c1 - c0);
+  if (i1 <= i0 || c1 <= c0 || K <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lschur_naive, dim3(grid_for(cnt)), dim3(256), 0, s, A, nl, i0, i1, c0, c1,
+                     k0, K);
   return hipGetLastError();
 }
 
@@ -344,14 +379,14 @@ hipError_t launch_lgetrs(LimbMat LU, int nl, int64_t n, const int64_t *ipiv, Lim
                      (int64_t)0, nrhs, (int64_t)0, (int64_t)0);
   for (int64_t k0 = 0; k0 < n; k0 += LBLK) {
     const int64_t k1 = k0 + LBLK < n ? k0 + LBLK : n;
-    hipLaunchKernelGGL(k_lfwd_diag, dim3((unsigned)nrhs), dim3(256), 0, s, LU, X, nl, k0, k1);
+    hipLaunchKernelGGL(k_lfwd_diag, dim3((unsigned)nrhs), dim3(1024), 0, s, LU, X, nl, k0, k1);
     if (k1 < n)
       hipLaunchKernelGGL(k_lfwd_rest, dim3(grid_for(n - k1, 2048), (unsigned)nrhs), dim3(256), 0, s,
                          LU, X, nl, k0, k1, n);
   }
   for (int64_t k1 = n; k1 > 0;) {
     const int64_t k0 = k1 - LBLK > 0 ? k1 - LBLK : 0;
-    hipLaunchKernelGGL(k_lbwd_diag, dim3((unsigned)nrhs), dim3(256), 0, s, LU, X, nl, k0, k1);
+    hipLaunchKernelGGL(k_lbwd_diag, dim3((unsigned)nrhs), dim3(1024), 0, s, LU, X, nl, k0, k1);
     if (k0 > 0)
       hipLaunchKernelGGL(k_lbwd_rest, dim3(grid_for(k0, 2048), (unsigned)nrhs), dim3(256), 0, s, LU,
                          X, nl, k0, k1);

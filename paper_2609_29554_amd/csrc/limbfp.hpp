@@ -230,23 +230,30 @@ LFP_FN void mac(uint64_t &c0, uint64_t &c1, uint64_t &c2, uint64_t a, uint64_t b
 LFP_FN WF mul(const WF &a, const WF &b, int nl) {
   if (is_zero(a) || is_zero(b)) return wf_zero();
   const int l = lane_id();
-  // column l (and l + 64) of the schoolbook product, as c0 + c1 2^64 + c2 2^128
-  uint64_t c0l = 0, c1l = 0, c2l = 0, c0h = 0, c1h = 0, c2h = 0;
+  // Lane l sums column l of the schoolbook product (a_i b_(l-i), i <= l),
+  // then column l + 64 (a_i b_(l+64-i), i > l), as c0 + c1 2^64 + c2 2^128:
+  // one accumulator, the finished low column banked when i passes l.
+  uint64_t c0 = 0, c1 = 0, c2 = 0, k0 = 0, k1 = 0, k2 = 0;
   for (int i = 0; i < nl; ++i) {
     const uint64_t ai = readlane64(a.m, i);
-    // b_(l-i) for column l when l >= i, else b_(l+64-i) for column l + 64
     const uint64_t bv = shfl64(b.m, (l - i) & 63);
-    const bool lowcol = l >= i;
-    mac(c0l, c1l, c2l, ai, lowcol ? bv : 0ull);
-    mac(c0h, c1h, c2h, ai, lowcol ? 0ull : bv);
+    const bool sw = l + 1 == i;
+    k0 = sw ? c0 : k0;
+    k1 = sw ? c1 : k1;
+    k2 = sw ? c2 : k2;
+    c0 = sw ? 0ull : c0;
+    c1 = sw ? 0ull : c1;
+    c2 = sw ? 0ull : c2;
+    mac(c0, c1, c2, ai, bv);
   }
+  const bool banked = l + 1 < nl;  // lanes >= nl-1 never reach their high column
   W2 A, B, C;
-  A.lo = c0l;
-  A.hi = c0h;
-  B.lo = c1l;
-  B.hi = c1h;
-  C.lo = c2l;
-  C.hi = c2h;
+  A.lo = banked ? k0 : c0;
+  A.hi = banked ? c0 : 0ull;
+  B.lo = banked ? k1 : c1;
+  B.hi = banked ? c1 : 0ull;
+  C.lo = banked ? k2 : c2;
+  C.hi = banked ? c2 : 0ull;
   B = up_limb(B);
   C = up_limb(up_limb(C));  // column 2nl-2 holds one product: its c2 is 0
   uint32_t co;
@@ -322,6 +329,23 @@ LFP_FN WF add(const WF &a, const WF &b, uint32_t negb, int nl) {
   return r;
 }
 
+// min(floor(U / v), 2^32 - 1) for 2^31 <= v < 2^32 (rv = RN(1/v)): the
+// binary64 quotient is within 2^-17 of U / v (three roundings of relative
+// size 2^-53 on a value below 2^33), so its floor is off by at most one,
+// which the exact remainder U - q v decides.
+LFP_FN uint64_t digit_estimate(uint64_t U, uint64_t v, double rv) {
+  const double qf = (double)U * rv;
+  if (qf >= 4294967296.0) return 0xffffffffull;  // floor(U / v) >= 2^32 - 1
+  uint64_t q = (uint64_t)qf;                      // < 2^32: q v < 2^64
+  const uint64_t qv = q * v;
+  if (qv > U) {
+    q -= 1;
+  } else if (U - qv >= v) {
+    q += 1;
+  }
+  return q > 0xffffffffull ? 0xffffffffull : q;
+}
+
 // RN_p(a / b); b must be non-zero (a zero b gives zero)
 LFP_FN WF div(const WF &a, const WF &b, int nl) {
   if (is_zero(a) || is_zero(b)) return wf_zero();
@@ -329,6 +353,7 @@ LFP_FN WF div(const WF &a, const WF &b, int nl) {
   const bool act = l < nl;
   const uint64_t V = b.m;
   const uint64_t vt = readlane64(V, nl - 1) >> 32;  // top 32-bit digit, >= 2^31
+  const double rvt = 1.0 / (double)vt;
   // leading quotient digit d0 = floor(ma / mb) in {0, 1}
   const uint32_t d0 = cmp_mant(a.m, V) >= 0 ? 1u : 0u;
   uint64_t R = a.m;
@@ -344,8 +369,7 @@ LFP_FN WF div(const WF &a, const WF &b, int nl) {
     const uint64_t below = shfl64(R, (l + 63) & 63);
     R = act ? ((R << 32) | ((l ? below : 0ull) >> 32)) : 0ull;
     const uint64_t rt = U >> 32;  // the digit above limb nl-1
-    uint64_t qh = U / vt;
-    if (qh > 0xffffffffull) qh = 0xffffffffull;
+    uint64_t qh = digit_estimate(U, vt, rvt);
     // T = qh V: lane k's product lo + hi 2^64, hi moving to lane k+1
     const uint64_t p0 = qh * (V & 0xffffffffull), p1 = qh * (V >> 32);
     const uint64_t lo = p0 + (p1 << 32);

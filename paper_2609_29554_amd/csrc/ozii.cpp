@@ -886,6 +886,91 @@ ozl::LimbMat limb_mat(const ozII_limbs *A) {
   return m;
 }
 
+// Left part of a recursive split of w > leaf columns (or rows): half of the
+// leaf-wide blocks, rounded up.
+int64_t limb_split(int64_t w, int64_t leaf) {
+  const int64_t blocks = (w + leaf - 1) / leaf;
+  return (blocks + 1) / 2 * leaf;
+}
+
+// The steps of the LU on limb matrices (Sec. 3.4) on one n x n matrix:
+// panel, U12 solve and updates; with leaf > 0 the panel and the solve
+// recurse on halves down to leaf columns (rows) and their inner updates are
+// made like the Schur update -- the Ozaki-II product of the panel that
+// Sec. 5.2 proposes.
+struct LimbLU {
+  ozII_ctx *h;
+  const ozII_limbs *A;
+  ozl::LimbMat M;
+  int nl;
+  int64_t n;
+  int method;
+  int64_t leaf;
+  const ozII_opts *o;
+  int64_t *ipiv;
+  int32_t *info;
+
+  double el() const { return 8.0 * nl + 5.0; }
+
+  // the inner dimensions of the updates a panel (or, solve = true, a U12
+  // solve) of width w makes
+  void inner_dims(int64_t w, std::vector<int64_t> &ks, bool solve) const {
+    if (solve) ks.push_back(w);  // the Schur update after this panel
+    if (!leaf || w <= leaf) return;
+    const int64_t w1 = limb_split(w, leaf);
+    ks.push_back(w1);
+    inner_dims(w1, ks, false);
+    inner_dims(w - w1, ks, false);
+  }
+
+  // A[i0:i1, c0:c1] -= A[i0:i1, k0:k0+K] A[k0:k0+K, c0:c1]
+  ozII_status update(int64_t i0, int64_t i1, int64_t c0, int64_t c1, int64_t k0, int64_t K) {
+    if (i1 <= i0 || c1 <= c0 || K <= 0) return OZII_OK;
+    if (method == OZII_METHOD_NAIVE) {
+      ProfScope ps(h, OZ_STAGE_NAIVE, el() * (double)(i1 - i0) * (c1 - c0), 0);
+      const hipError_t e = ozl::launch_lschur_naive(M, nl, i0, i1, c0, c1, k0, K, h->stream);
+      return e == hipSuccess ? OZII_OK : hip_fail(h, e, "limb native update");
+    }
+    const ozII_limbs La = limbs_at(A, i0, k0), Lb = limbs_at(A, k0, c0);
+    ozII_limbs Lc = limbs_at(A, i0, c0);
+    return gemm_limbs_impl(h, 1, nl, i1 - i0, c1 - c0, K, &La, &Lb, &Lc, o);
+  }
+
+  // A[r0:r0+hh, b0:b1] <- L^-1 A[r0:r0+hh, b0:b1], L unit lower at (r0, r0)
+  ozII_status trsm(int64_t r0, int64_t hh, int64_t b0, int64_t b1) {
+    if (b1 <= b0 || hh <= 1) return OZII_OK;
+    if (!leaf || hh <= leaf) {
+      ProfScope ps(h, OZ_STAGE_TRSM, el() * (double)hh * (b1 - b0), 0);
+      const hipError_t e = ozl::launch_ltrsm(M, nl, r0, hh, b0, b1, h->stream);
+      return e == hipSuccess ? OZII_OK : hip_fail(h, e, "limb U12 solve");
+    }
+    const int64_t h1 = limb_split(hh, leaf);
+    ozII_status st;
+    if ((st = trsm(r0, h1, b0, b1)) != OZII_OK) return st;
+    if ((st = update(r0 + h1, r0 + hh, b0, b1, r0, h1)) != OZII_OK) return st;
+    return trsm(r0 + h1, hh - h1, b0, b1);
+  }
+
+  // columns [c0, c0+w) over rows [c0, n), interchanges across [P0, P1)
+  ozII_status panel(int64_t c0, int64_t w, int64_t P0, int64_t P1) {
+    if (!leaf || w <= leaf) {
+      ProfScope ps(h, OZ_STAGE_PANEL, el() * (double)(n - c0) * w, 0);
+      for (int64_t j = c0; j < c0 + w; ++j) {
+        const hipError_t e = ozl::launch_lpanel_column(M, nl, j, n, P0, P1, c0 + w, h->lcand,
+                                                       ipiv, info, h->lflag, h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "limb panel");
+      }
+      return OZII_OK;
+    }
+    const int64_t w1 = limb_split(w, leaf);
+    ozII_status st;
+    if ((st = panel(c0, w1, P0, P1)) != OZII_OK) return st;
+    if ((st = trsm(c0, w1, c0 + w1, c0 + w)) != OZII_OK) return st;
+    if ((st = update(c0 + w1, n, c0 + w1, c0 + w, c0, w1)) != OZII_OK) return st;
+    return panel(c0 + w1, w - w1, P0, P1);
+  }
+};
+
 // The side stream and the fork / join events of the look-ahead (created on
 // first use, on the handle's device, at the default priority).
 ozII_status ensure_side(ozII_ctx *h) {
@@ -1282,51 +1367,51 @@ ozII_status ozII_getrf_limbs(ozII_handle h, int32_t nlimb, int64_t n, ozII_limbs
   const int method = o ? o->method : OZII_METHOD_OZAKI;
   if (method != OZII_METHOD_OZAKI && method != OZII_METHOD_NAIVE)
     return fail(h, OZII_EINVAL, "unknown method");
+  if (o && o->panel_leaf < 0) return fail(h, OZII_EINVAL, "negative panel leaf");
+  LimbLU L;
+  L.h = h;
+  L.A = A;
+  L.M = limb_mat(A);
+  L.nl = nlimb;
+  L.n = n;
+  L.method = method;
+  L.leaf = o ? o->panel_leaf : 0;
+  L.o = o;
+  L.ipiv = ipiv;
+  L.info = info;
   const int64_t b = (o && o->block > 0) ? o->block : 256;
   ozII_status st = limb_scratch(h);
   if (st != OZII_OK) return st;
-  if (method == OZII_METHOD_OZAKI && n > b) {
-    // every Schur update has K = b: check its plan before anything runs
-    const HostPlan *hp;
-    const DevPlan *dp;
-    if ((st = get_plan(h, 64 * nlimb, b, o, &hp, &dp, true)) != OZII_OK) return st;
+  if (method == OZII_METHOD_OZAKI) {
+    // the plans of every inner dimension the updates use, before anything runs
+    std::vector<int64_t> ks;
+    for (int64_t k0 = 0; k0 < n; k0 += b) {
+      const int64_t kb = std::min(b, n - k0);
+      if (n - k0 - kb > 0) L.inner_dims(kb, ks, true);
+      L.inner_dims(kb, ks, false);
+    }
+    std::sort(ks.begin(), ks.end());
+    ks.erase(std::unique(ks.begin(), ks.end()), ks.end());
+    for (int64_t K : ks) {
+      const HostPlan *hp;
+      const DevPlan *dp;
+      if ((st = get_plan(h, 64 * nlimb, K, o, &hp, &dp, true)) != OZII_OK) return st;
+    }
   }
-  hipStream_t s = h->stream;
   hipError_t e;
-  if ((e = ozl::launch_lfill_i32(info, 0, 1, s)) != hipSuccess) return hip_fail(h, e, "info");
-  const ozl::LimbMat M = limb_mat(A);
+  if ((e = ozl::launch_lfill_i32(info, 0, 1, h->stream)) != hipSuccess) return hip_fail(h, e, "info");
   const double el = 8.0 * nlimb + 5.0;
   for (int64_t k0 = 0; k0 < n; k0 += b) {
     const int64_t kb = std::min(b, n - k0);
-    {
-      ProfScope ps(h, OZ_STAGE_PANEL, el * (double)(n - k0) * kb, 0);
-      for (int64_t j = k0; j < k0 + kb; ++j)
-        if ((e = ozl::launch_lpanel_column(M, nlimb, j, n, k0, k0 + kb, h->lcand, ipiv, info,
-                                           h->lflag, s)) != hipSuccess)
-          return hip_fail(h, e, "limb panel");
-    }
+    if ((st = L.panel(k0, kb, k0, k0 + kb)) != OZII_OK) return st;
     {
       ProfScope ps(h, OZ_STAGE_LASWP, 2.0 * el * kb * (double)(n - kb), 0);
-      if ((e = ozl::launch_llaswp(M, nlimb, ipiv, k0, kb, 0, k0, k0 + kb, n, s)) != hipSuccess)
+      if ((e = ozl::launch_llaswp(L.M, nlimb, ipiv, k0, kb, 0, k0, k0 + kb, n, h->stream)) != hipSuccess)
         return hip_fail(h, e, "limb laswp");
     }
-    const int64_t rest = n - k0 - kb;
-    if (rest == 0) continue;
-    {
-      ProfScope ps(h, OZ_STAGE_TRSM, el * (double)kb * rest, 0);
-      if ((e = ozl::launch_ltrsm(M, nlimb, k0, kb, n, s)) != hipSuccess)
-        return hip_fail(h, e, "limb U12 solve");
-    }
-    if (method == OZII_METHOD_NAIVE) {
-      ProfScope ps(h, OZ_STAGE_NAIVE, el * (double)rest * rest, 0);
-      if ((e = ozl::launch_lschur_naive(M, nlimb, k0, kb, n, s)) != hipSuccess)
-        return hip_fail(h, e, "limb native update");
-    } else {
-      const ozII_limbs L21 = limbs_at(A, k0 + kb, k0), U12 = limbs_at(A, k0, k0 + kb);
-      ozII_limbs A22 = limbs_at(A, k0 + kb, k0 + kb);
-      if ((st = gemm_limbs_impl(h, 1, nlimb, rest, rest, kb, &L21, &U12, &A22, o)) != OZII_OK)
-        return st;
-    }
+    if (n - k0 - kb == 0) continue;
+    if ((st = L.trsm(k0, kb, k0 + kb, n)) != OZII_OK) return st;
+    if ((st = L.update(k0 + kb, n, k0 + kb, n, k0, kb)) != OZII_OK) return st;
   }
   return OZII_OK;
 }

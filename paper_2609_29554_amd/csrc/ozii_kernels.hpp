@@ -143,17 +143,21 @@ struct LimbMat {
 };
 // pivot-candidate workgroups per panel column (the size of `cand`)
 constexpr int LPIV_MAXGRID = 64;
-// one panel column j of the panel [c0, c1): pivot search, ipiv[j], info,
-// interchange inside the panel, division, rank-1 update; zflag: one word
-hipError_t launch_lpanel_column(LimbMat A, int nl, int64_t j, int64_t n, int64_t c0, int64_t c1,
-                                int64_t *cand, int64_t *ipiv, int32_t *info, int32_t *zflag,
-                                hipStream_t s);
+// one panel column j: pivot search over rows [j, n), ipiv[j], info, the
+// interchange on columns [s0, s1), division, rank-1 update of columns
+// (j, c1); zflag: one word
+hipError_t launch_lpanel_column(LimbMat A, int nl, int64_t j, int64_t n, int64_t s0, int64_t s1,
+                                int64_t c1, int64_t *cand, int64_t *ipiv, int32_t *info,
+                                int32_t *zflag, hipStream_t s);
 // interchanges ipiv[k0 .. k0+kb) on columns [ca0, ca1) and [cb0, cb1)
 hipError_t launch_llaswp(LimbMat A, int nl, const int64_t *ipiv, int64_t k0, int64_t kb,
                          int64_t ca0, int64_t ca1, int64_t cb0, int64_t cb1, hipStream_t s);
-hipError_t launch_ltrsm(LimbMat A, int nl, int64_t k0, int64_t kb, int64_t n, hipStream_t s);
-hipError_t launch_lschur_naive(LimbMat A, int nl, int64_t k0, int64_t kb, int64_t n,
-                               hipStream_t s);
+// A[r0:r0+h, b0:b1] <- L^-1 A[r0:r0+h, b0:b1], L unit lower at (r0, r0)
+hipError_t launch_ltrsm(LimbMat A, int nl, int64_t r0, int64_t h, int64_t b0, int64_t b1,
+                        hipStream_t s);
+// A[i0:i1, c0:c1] -= A[i0:i1, k0:k0+K] A[k0:k0+K, c0:c1] by multiply-subtracts
+hipError_t launch_lschur_naive(LimbMat A, int nl, int64_t i0, int64_t i1, int64_t c0, int64_t c1,
+                               int64_t k0, int64_t K, hipStream_t s);
 hipError_t launch_lgetrs(LimbMat LU, int nl, int64_t n, const int64_t *ipiv, LimbMat X,
                          int64_t nrhs, hipStream_t s);
 hipError_t launch_larith(int op, int nl, int64_t cnt, LimbMat A, LimbMat B, LimbMat C,

@@ -125,11 +125,12 @@ def _matrix(nl, n, seed, kind="random"):
     return A
 
 
-def _lu(A, b, method):
+def _lu(A, b, method, leaf=0):
     import paper_2609_29554_amd as Z
     dA = _dev(A)
     ipiv, info = ctx().getrf_limbs(dA, block=b,
-                                   method=Z.METHOD_NAIVE if method == "native" else Z.METHOD_OZAKI)
+                                   method=Z.METHOD_NAIVE if method == "native" else Z.METHOD_OZAKI,
+                                   leaf=leaf)
     ctx().sync_check()
     return _host(dA), to_host(ipiv), int(to_host(info)[0])
 
@@ -153,6 +154,24 @@ def test_getrf_limbs_ozaki_bit_exact(nl, n, b):
     got, ipiv, info = _lu(A, b, "ozaki")
     want, ip, inf = OLU.getrf(A, b, "ozaki")
     _same(got, want)
+    assert np.array_equal(ipiv[:n], ip) and info == inf
+
+
+@pytest.mark.parametrize("nl,n,b,leaf", [(1, 40, 16, 4), (2, 70, 32, 8), (1, 33, 33, 5),
+                                         (4, 48, 24, 6)])
+def test_getrf_limbs_recursive_panel_bit_exact(nl, n, b, leaf):
+    """The recursive panel and U12 solve with Ozaki-II inner updates against
+    the oracle's same recursion; with multiply-subtract updates the result
+    is the unblocked LU."""
+    note(f"getrf_limbs recursive nl={nl} n={n} b={b} leaf={leaf}")
+    A = _matrix(nl, n, 19 * n + leaf)
+    got, ipiv, info = _lu(A, b, "ozaki", leaf)
+    want, ip, inf = OLU.getrf(A, b, "ozaki", leaf=leaf)
+    _same(got, want)
+    assert np.array_equal(ipiv[:n], ip) and info == inf
+    got, ipiv, info = _lu(A, b, "native", leaf)
+    F, ip, inf = LF.getrf(OLU.to_lf(A))
+    _same(got, OLU.from_lf(F))
     assert np.array_equal(ipiv[:n], ip) and info == inf
 
 
@@ -184,16 +203,17 @@ def test_getrs_limbs_bit_exact(nl, n, b, nrhs):
     _same(_host(dB), want)
 
 
-def test_lotkin_limb_lu_p3136_correct_bits():
+@pytest.mark.parametrize("leaf", [0, 32])
+def test_lotkin_limb_lu_p3136_correct_bits(leaf):
     """Table lotkin, n = 512 at p = 3136, b = 256: 545 correct bits on the
     GPU (546 on the CPU); the bound p - log2 cond is 525."""
     n, nl, b = 512, 49, 256
-    note("lotkin limb LU n=512 p=3136")
+    note(f"lotkin limb LU n=512 p=3136 leaf={leaf}")
     A = OLU.from_lf(LF.lotkin(n, nl))
     rhs = OLU.from_lf(LF.rhs_times_ones(LF.lotkin(n, nl)))
     import paper_2609_29554_amd as Z
     dA, dX = _dev(A), _dev(rhs)
-    ipiv, info = ctx().getrf_limbs(dA, block=b, method=Z.METHOD_OZAKI)
+    ipiv, info = ctx().getrf_limbs(dA, block=b, method=Z.METHOD_OZAKI, leaf=leaf)
     ctx().getrs_limbs(dA, ipiv, dX)
     ctx().sync_check()
     assert int(to_host(info)[0]) == 0

@@ -142,3 +142,42 @@ def test_lotkin_limb_generators_match_oracle(n, nl):
     the oracle's: RN_p of 1/(i+j+1), and RN_p of the exact row sums."""
     assert _eq(W.lotkin_limbs(n, nl), OLU.from_lf(LF.lotkin(n, nl)))
     assert _eq(W.lotkin_rhs_limbs(n, nl), OLU.from_lf(LF.rhs_times_ones(LF.lotkin(n, nl))))
+
+
+@pytest.mark.parametrize("nl,n,b,leaf", [(1, 24, 16, 4), (2, 30, 12, 3), (1, 37, 37, 8),
+                                         (3, 21, 9, 2)])
+@pytest.mark.parametrize("singular", [False, True])
+def test_recursive_native_panel_equals_unblocked(nl, n, b, leaf, singular):
+    A = _random(nl, n, 31 * n + leaf, singular)
+    F, ip, info = OLU.getrf(A, b, "native", leaf=leaf)
+    G, ip2, info2 = LF.getrf(OLU.to_lf(A))
+    assert _eq(F, OLU.from_lf(G))
+    assert np.array_equal(ip, ip2) and info == info2
+
+
+@pytest.mark.parametrize("nl,n,b", [(1, 20, 8), (2, 26, 12)])
+def test_recursive_ozaki_with_leaf_at_least_b_is_plain_blocked(nl, n, b):
+    A = _random(nl, n, 13 * n)
+    F, ip, info = OLU.getrf(A, b, "ozaki", leaf=b)
+    G, ip2, info2 = OLU.getrf(A, b, "ozaki")
+    assert _eq(F, G) and np.array_equal(ip, ip2)
+
+
+@pytest.mark.parametrize("nl,n,b,leaf", [(1, 32, 16, 4), (2, 24, 24, 6)])
+def test_recursive_ozaki_factors_close_to_unblocked(nl, n, b, leaf):
+    A = _random(nl, n, 17 * n)
+    F, ip, _ = OLU.getrf(A, b, "ozaki", leaf=leaf)
+    G, ip2, _ = LF.getrf(OLU.to_lf(A))
+    assert np.array_equal(ip, ip2)
+    p = 64 * nl
+    fv, gv = _vals(F), _vals(OLU.from_lf(G))
+    scale = max(abs(x) for row in gv for x in row)
+    worst = max(abs(fv[i][j] - gv[i][j]) for i in range(n) for j in range(n))
+    assert 0 < worst <= scale * Fraction(1, 2 ** (p - 24))
+    H, ip3, _ = OLU.getrf(A, b, "ozaki")
+    assert not _eq(F, H)          # the panel's updates did go through Ozaki-II
+
+
+def test_split_halves_leaf_blocks():
+    assert [OLU.split(w, 32) for w in (256, 96, 40, 64, 33)] == [128, 64, 32, 32, 32]
+    assert OLU.split(7, 2) == 4
