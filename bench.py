@@ -195,6 +195,8 @@ def main():
     ap.add_argument("--native-steps", type=int, default=1)
     ap.add_argument("--no-native", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probes", action="store_true",
+                    help="skip the batched-LU and limb-LU probes of the default line")
     ap.add_argument("--cpu-sample-n", type=int, default=2048)
     ap.add_argument("--workload", choices=["lu", "gemm", "schur", "batch", "limb-schur", "limb-lu"],
                     default="lu",
@@ -397,6 +399,12 @@ def main():
                                   "5.1 n, Sec. 4.3): no correct bit is expected"}
     sweep = backend_sweep(ctx, args) if args.sweep_n > 0 else None
     td_gemm = td_gemm_probe(args.gemm_n) if args.gemm_n > 0 else None
+    batch = limb = None
+    if not args.no_probes:
+        log("batch probe")
+        batch = batch_probe(args)
+        log("limb LU probe (Table lotkin point)")
+        limb = limb_lu_measure(512, 3136, 256, args.limb_leaf, 2, 1, "yes")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -439,6 +447,8 @@ def main():
         "correct_bits": bits,
         "accuracy": accuracy,
         "backend_sweep": sweep,
+        "batch256": batch,
+        "limb_lu_lotkin512_p3136": limb,
     }
     ctx.close()
     print(json.dumps(out))
@@ -924,18 +934,19 @@ PAPER_LOTKIN = {(512, 3136): {"H100": {"naive_b1": 1.323, "naive_blk": 1.345, "o
                               "bits": 545, "b": 256}}
 
 
-def bench_limb_lu(args):
+def limb_lu_measure(n, p, b, leaf, steps, warmup, native_mode="auto"):
     """The Lotkin LU + solve on limb numbers (Sec. 4.3, Table lotkin): getrf
-    with the Ozaki-II Schur update at panel width b, then getrs, timed
-    together; the native variants (blocked naive at the same b, unblocked)
-    beside it, and the correct bits of x against the true solution 1."""
+    with the Ozaki-II Schur update at panel width b (recursive panel down to
+    `leaf` columns when leaf > 0), then getrs, timed together (median of
+    `steps`); the same with the unblocked panel, the native variants
+    (blocked naive at the same b, unblocked) and the correct bits of x
+    against the true solution 1."""
     import numpy as np
     import torch
 
     import paper_2609_29554_amd as Z
     import workloads as W
 
-    n, p, b = args.limb_n, args.limb_p, args.limb_block
     if p % 64 or not 64 <= p <= 4096:
         raise SystemExit("--limb-p must be a multiple of 64 in [64, 4096]")
     nl = p // 64
@@ -950,8 +961,6 @@ def bench_limb_lu(args):
     dA0, dB0 = up(A), up(B)
     ctx = Z.Context(0)
 
-    leaf = args.limb_leaf
-
     def run(method, blk, lf=0):
         dA = tuple(x.clone() for x in dA0)
         dX = tuple(x.clone() for x in dB0)
@@ -965,12 +974,12 @@ def bench_limb_lu(args):
         return dt, dX, int(info.cpu()[0])
 
     log("warmup")
-    for _ in range(max(args.warmup, 1)):
+    for _ in range(max(warmup, 1)):
         run(Z.METHOD_OZAKI, b, leaf)
     ctx.set_profiling(True)
     ctx.profile_read()
     times = []
-    for _ in range(args.steps):
+    for _ in range(steps):
         dt, dX, info = run(Z.METHOD_OZAKI, b, leaf)
         times.append(dt)
         log(f"ozaki step {dt:.3f} s")
@@ -984,7 +993,7 @@ def bench_limb_lu(args):
         flat = {"s": dt, "correct_bits": limb_correct_bits(*host_limbs(dXf))}
         log(f"ozaki, unblocked panel {dt:.3f} s")
     native = None
-    if args.limb_native == "yes" or (args.limb_native == "auto" and n <= 1024):
+    if native_mode == "yes" or (native_mode == "auto" and n <= 1024):
         native = {}
         for name, blk in (("naive_blk", b), ("naive_b1", n)):
             log(f"native {name}")
@@ -993,8 +1002,7 @@ def bench_limb_lu(args):
                             "correct_bits": limb_correct_bits(*host_limbs(dXn))}
         best = min(v["s"] for v in native.values())
         native["speedup_vs_best_native"] = best / sec
-    steps_p = args.steps
-    stages = {k: {"ms_per_step": v[0] / steps_p, "launches_per_step": v[1] / steps_p}
+    stages = {k: {"ms_per_step": v[0] / steps, "launches_per_step": v[1] / steps}
               for k, v in prof.items() if v[1]}
     roof = None
     if prof.get("gemm") and prof["gemm"][1]:
@@ -1002,21 +1010,57 @@ def bench_limb_lu(args):
         ach = ops / launches / (ms / launches * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_MFMA["int8"], "unit": "TOP/s",
                 "frac": ach / PEAK_MFMA["int8"], "traffic": None, "kernel": "gemm",
-                "avg_launch_ms": ms / launches, "launches": launches / steps_p,
+                "avg_launch_ms": ms / launches, "launches": launches / steps,
                 "algorithmic_ops_per_launch": ops / launches}
+    ctx.close()
+    return {"s": sec, "steps_s": times, "n": n, "p": p, "block": b, "panel_leaf": leaf,
+            "correct_bits": bits, "info": info, "ozaki_unblocked_panel": flat, "native": native,
+            "roofline": roof, "stages": stages, "paper_context": PAPER_LOTKIN.get((n, p))}
+
+
+def bench_limb_lu(args):
+    """--workload limb-lu: limb_lu_measure at --limb-n / --limb-p /
+    --limb-block / --limb-leaf, with the oracle timed on the host."""
+    n, p, b = args.limb_n, args.limb_p, args.limb_block
+    r = limb_lu_measure(n, p, b, args.limb_leaf, args.steps, args.warmup, args.limb_native)
+    sec = r["s"]
     out = {"metric": METRIC, "value": sec, "unit": "s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": False,
            "scaling": "weak", "vs_baseline": None, "dtype": "u64 limbs+i8", "data": "synthetic",
            "config": {"workload": f"Lotkin LU + solve on limb numbers n={n} p={p} b={b} "
                                   f"(getrf_limbs Ozaki-II INT8 + getrs_limbs)",
-                      "n": n, "p": p, "block": b, "panel_leaf": leaf},
-           "correct_bits": bits, "info": info, "ozaki_unblocked_panel": flat, "native": native,
-           "roofline": roof,
-           "stages": stages, "paper_context": PAPER_LOTKIN.get((n, p))}
-    ctx.close()
+                      "n": n, "p": p, "block": b, "panel_leaf": args.limb_leaf},
+           **{k: r[k] for k in ("correct_bits", "info", "ozaki_unblocked_panel", "native",
+                                "roofline", "stages", "paper_context")}}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = limb_lu_cpu_baseline(n, nl)
+        out["cpu_baseline"] = limb_lu_cpu_baseline(n, p // 64)
     print(json.dumps(out))
+
+
+def batch_probe(args, steps=2):
+    """p50 / p99 per-solve latency and makespan of the batched configuration
+    (the --workload batch recipe, fewer replays) for the main bench line."""
+    import types
+
+    import numpy as np
+
+    import paper_2609_29554_amd as Z
+    import workloads as W
+
+    rng = np.random.default_rng(20260934)
+    systems = W.batch_systems(args.batch_count, rng)
+    ctx = Z.Context(0)
+    a = types.SimpleNamespace(steps=steps, warmup=1)
+    sec, dur, done, infos = _batch_run(ctx, systems, Z.make_opts(block=args.batch_block,
+                                                                 method=Z.METHOD_OZAKI), a)
+    ctx.close()
+    return {"workload": f"{len(systems)} systems n in [64, 512], half DD half QD, graded D R D, "
+                        f"one hipGraph-replayed persistent launch, Ozaki-II update b = "
+                        f"{args.batch_block} (see --workload batch)",
+            "latency_ms": {"p50": float(np.percentile(dur, 50)) * 1e3,
+                           "p99": float(np.percentile(dur, 99)) * 1e3},
+            "makespan_ms": float(done.max()) * 1e3,
+            "nonzero_info": int(sum(1 for v in infos if v != 0))}
 
 
 def limb_lu_cpu_baseline(n, nl, n_sample=256):

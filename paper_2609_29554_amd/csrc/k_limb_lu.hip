@@ -119,6 +119,7 @@ __global__ __launch_bounds__(256) void k_lpiv(LimbMat A, int nl, int64_t j, int6
 // lowest row on ties); ipiv, info, the zero flag and the interchange across
 // the panel's columns [c0, c1).
 constexpr int FIN_WAVES = 16;
+constexpr int FIN_PER = ozl::LPIV_MAXGRID / FIN_WAVES;  // candidates per wavefront
 __global__ __launch_bounds__(1024) void k_lpiv_final(LimbMat A, int nl, int64_t j,
                                                      const int64_t *cand, int ncand, int64_t c0,
                                                      int64_t c1, int64_t *ipiv, int32_t *info,
@@ -130,9 +131,27 @@ __global__ __launch_bounds__(1024) void k_lpiv_final(LimbMat A, int nl, int64_t 
   const int w = wave_in_block(), l = lfp::lane_id();
   int64_t b = -1;
   WF v = lfp::wf_zero();
-  for (int k = w; k < ncand; k += FIN_WAVES) {
-    const int64_t r = cand[k];
-    if (r >= 0) take_max(b, v, r, ld_el(A, r, j, nl));
+  // this wavefront's (up to FIN_PER) candidates: all loads issued first
+  int64_t rr[FIN_PER];
+  uint64_t mm[FIN_PER];
+#pragma unroll
+  for (int t = 0; t < FIN_PER; ++t) {
+    const int k = w + t * FIN_WAVES;
+    rr[t] = k < ncand ? cand[k] : -1;
+  }
+#pragma unroll
+  for (int t = 0; t < FIN_PER; ++t)
+    mm[t] = (rr[t] >= 0 && l < nl) ? A.limb[(int64_t)l * A.plane + rr[t] + j * A.ld] : 0ull;
+#pragma unroll
+  for (int t = 0; t < FIN_PER; ++t) {
+    if (rr[t] < 0) continue;
+    const int64_t idx = rr[t] + j * A.ld;
+    WF x;
+    x.m = mm[t];
+    const bool z = lfp::ballot(x.m != 0) == 0;
+    x.e = z ? lfp::EXP_ZERO : A.exp[idx];
+    x.s = z ? 0u : (uint32_t)(A.sign[idx] & 1u);
+    take_max(b, v, rr[t], x);
   }
   sm[w][l] = v.m;
   if (l == 0) {
@@ -173,6 +192,14 @@ __global__ __launch_bounds__(1024) void k_lpiv_final(LimbMat A, int nl, int64_t 
   const int64_t r = srow[0];
   if (r != j)
     for (int64_t c = c0 + w; c < c1; c += FIN_WAVES) swap_el(A, j, r, c, nl);
+}
+
+// rows j <-> ipiv[j] on columns [s0, s1), one wavefront per column
+__global__ __launch_bounds__(256) void k_lswap(LimbMat A, int nl, int64_t j, const int64_t *ipiv,
+                                               int64_t s0, int64_t s1) {
+  const int64_t r = ipiv[j];
+  if (r == j) return;
+  for (int64_t c = s0 + wave_global(); c < s1; c += waves_total()) swap_el(A, j, r, c, nl);
 }
 
 __global__ __launch_bounds__(256) void k_ldiv(LimbMat A, int nl, int64_t j, int64_t n,
@@ -333,8 +360,13 @@ hipError_t launch_lpanel_column(LimbMat A, int nl, int64_t j, int64_t n, int64_t
                                 int32_t *zflag, hipStream_t s) {
   const int g = lpiv_grid(n - j);
   hipLaunchKernelGGL(k_lpiv, dim3(g), dim3(256), 0, s, A, nl, j, n, cand);
+  // a wide interchange runs on one wavefront per column after the reduction
+  const bool wide = s1 - s0 > FIN_WAVES * 4;
   hipLaunchKernelGGL(k_lpiv_final, dim3(1), dim3(64 * FIN_WAVES), 0, s, A, nl, j,
-                     (const int64_t *)cand, g, s0, s1, ipiv, info, zflag);
+                     (const int64_t *)cand, g, s0, wide ? s0 : s1, ipiv, info, zflag);
+  if (wide)
+    hipLaunchKernelGGL(k_lswap, dim3(grid_for(s1 - s0)), dim3(256), 0, s, A, nl, j,
+                       (const int64_t *)ipiv, s0, s1);
   if (j + 1 < n) {
     hipLaunchKernelGGL(k_ldiv, dim3(grid_for(n - j - 1)), dim3(256), 0, s, A, nl, j, n,
                        (const int32_t *)zflag);

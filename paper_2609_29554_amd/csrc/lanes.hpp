@@ -28,4 +28,20 @@ LFP_FN uint64_t shfl64(uint64_t x, int src) {
 
 LFP_FN uint64_t umulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
 
+// lane l's result is lane l-1's x, lane 0's is 0 (DPP whole-wave shift)
+LFP_FN uint64_t up1_64(uint64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, 0x138, 0xf, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), 0x138, 0xf,
+                                                            0xf, false);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// lane l's result is lane (l-1) mod 64's x (DPP whole-wave rotation)
+LFP_FN uint64_t rot1_64(uint64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, 0x13C, 0xf, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), 0x13C, 0xf,
+                                                            0xf, false);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 }  // namespace lfp

@@ -20,7 +20,8 @@
 // top digit, at most two add-backs, Knuth's Theorem 4.3.1B).
 //
 // The includer provides LFP_FN and the cross-lane primitives lane_id,
-// ballot, readlane64 (wave-uniform lane), shfl64 (any lane) and umulhi64.
+// ballot, readlane64 (wave-uniform lane), shfl64 (any lane), up1_64 (from
+// lane l-1, 0 into lane 0), rot1_64 (from lane (l-1) mod 64) and umulhi64.
 // Every function must be called by all 64 lanes of a converged wavefront;
 // branches below depend on wave-uniform values only.
 #pragma once
@@ -207,7 +208,7 @@ LFP_FN int cmp_abs(const WF &a, const WF &b) {
 // limb j <- limb j-1 over the window (limb 0 <- 0)
 LFP_FN W2 up_limb(W2 w) {
   const int l = lane_id();
-  const uint64_t a = shfl64(w.lo, (l + 63) & 63), b = shfl64(w.hi, (l + 63) & 63);
+  const uint64_t a = rot1_64(w.lo), b = up1_64(w.hi);
   W2 r;
   r.lo = l ? a : 0ull;
   r.hi = l ? b : a;
@@ -234,9 +235,9 @@ LFP_FN WF mul(const WF &a, const WF &b, int nl) {
   // then column l + 64 (a_i b_(l+64-i), i > l), as c0 + c1 2^64 + c2 2^128:
   // one accumulator, the finished low column banked when i passes l.
   uint64_t c0 = 0, c1 = 0, c2 = 0, k0 = 0, k1 = 0, k2 = 0;
+  uint64_t bv = b.m;  // b_((l - i) mod 64) at step i: rotated by one lane per step
   for (int i = 0; i < nl; ++i) {
     const uint64_t ai = readlane64(a.m, i);
-    const uint64_t bv = shfl64(b.m, (l - i) & 63);
     const bool sw = l + 1 == i;
     k0 = sw ? c0 : k0;
     k1 = sw ? c1 : k1;
@@ -245,6 +246,7 @@ LFP_FN WF mul(const WF &a, const WF &b, int nl) {
     c1 = sw ? 0ull : c1;
     c2 = sw ? 0ull : c2;
     mac(c0, c1, c2, ai, bv);
+    bv = rot1_64(bv);
   }
   const bool banked = l + 1 < nl;  // lanes >= nl-1 never reach their high column
   W2 A, B, C;
@@ -366,16 +368,16 @@ LFP_FN WF div(const WF &a, const WF &b, int nl) {
   for (int i = 1; i <= K; ++i) {
     // R <- R 2^32 (R < V); U = the shifted remainder's top two digits
     const uint64_t U = readlane64(R, nl - 1);
-    const uint64_t below = shfl64(R, (l + 63) & 63);
-    R = act ? ((R << 32) | ((l ? below : 0ull) >> 32)) : 0ull;
+    const uint64_t below = up1_64(R);
+    R = act ? ((R << 32) | (below >> 32)) : 0ull;
     const uint64_t rt = U >> 32;  // the digit above limb nl-1
     uint64_t qh = digit_estimate(U, vt, rvt);
     // T = qh V: lane k's product lo + hi 2^64, hi moving to lane k+1
     const uint64_t p0 = qh * (V & 0xffffffffull), p1 = qh * (V >> 32);
     const uint64_t lo = p0 + (p1 << 32);
     const uint64_t hi = (p1 >> 32) + (lo < p0 ? 1ull : 0ull);
-    const uint64_t hin = shfl64(hi, (l + 63) & 63);
-    uint64_t T = lo + (l ? hin : 0ull);
+    const uint64_t hin = up1_64(hi);
+    uint64_t T = lo + hin;
     uint32_t c63;
     const uint64_t cm = chain(ballot(act && T < lo), ballot(act && T == ~0ull), 0u, c63);
     T = act ? T + bit_of(cm, l) : 0ull;

@@ -954,13 +954,16 @@ struct LimbLU {
   // columns [c0, c0+w) over rows [c0, n), interchanges across [P0, P1)
   ozII_status panel(int64_t c0, int64_t w, int64_t P0, int64_t P1) {
     if (!leaf || w <= leaf) {
+      // interchanges inside the leaf per column, then on the rest of the
+      // panel once per leaf (the same rows end up in the same places)
       ProfScope ps(h, OZ_STAGE_PANEL, el() * (double)(n - c0) * w, 0);
       for (int64_t j = c0; j < c0 + w; ++j) {
-        const hipError_t e = ozl::launch_lpanel_column(M, nl, j, n, P0, P1, c0 + w, h->lcand,
+        const hipError_t e = ozl::launch_lpanel_column(M, nl, j, n, c0, c0 + w, c0 + w, h->lcand,
                                                        ipiv, info, h->lflag, h->stream);
         if (e != hipSuccess) return hip_fail(h, e, "limb panel");
       }
-      return OZII_OK;
+      const hipError_t e = ozl::launch_llaswp(M, nl, ipiv, c0, w, P0, c0, c0 + w, P1, h->stream);
+      return e == hipSuccess ? OZII_OK : hip_fail(h, e, "limb panel interchanges");
     }
     const int64_t w1 = limb_split(w, leaf);
     ozII_status st;
