@@ -381,6 +381,23 @@ typedef struct {
 ozII_status ozII_tune(ozII_handle h, int32_t nc, int64_t n, const char *cache_path,
                       int32_t flags, ozII_opts *best, ozII_tune_report *rep);
 
+/* Autotuner of ozII_getrf_limbs (Sec. 4.1's timing at the actual size; the
+ * tuning of the limb format that Sec. 5.2 asks for) for nlimb-limb numbers
+ * and order n.  Stage 1 times the panel width b (64, 128, 256, 512 below n)
+ * x the panel leaf (0 = unblocked panel, 16, 32, 64 below b) with the
+ * Ozaki-II update, and the native update (unblocked panel) at each b while
+ * n <= 512; stage 2 times the winner with each GEMM tile and with S one
+ * above the plan rule's.  Each candidate is timed with HIP events around
+ * ozII_getrf_limbs of a synthetic random n x n limb matrix on the handle's
+ * stream (a warm-up run first); *best receives block, backend, method,
+ * panel_leaf, nslice and gemm_tile.  Cache and report as ozII_tune (key:
+ * architecture, nlimb, n).  Allocates n*n*(8 nlimb + 5) bytes for the
+ * duration of the call and synchronises the stream.  Errors: OZII_EINVAL
+ * (nlimb outside 1..64, n outside 2..32768, unknown flags),
+ * OZII_ENOMEM, OZII_EHIP, OZII_EUNSUPPORTED (no candidate runs). */
+ozII_status ozII_tune_limbs(ozII_handle h, int32_t nlimb, int64_t n, const char *cache_path,
+                            int32_t flags, ozII_opts *best, ozII_tune_report *rep);
+
 /* The HIP stream the handle enqueues on (as a void*). */
 ozII_status ozII_stream_of(ozII_handle h, void **stream);
 

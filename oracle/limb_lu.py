@@ -98,7 +98,7 @@ def split(w: int, leaf: int) -> int:
 class _LU:
     """The blocked LU's steps on the lfloat arrays X of an n x n matrix."""
 
-    def __init__(self, X, method, leaf, extra_groups):
+    def __init__(self, X, method, leaf, extra_groups, nslice=0):
         self.X = X
         self.m, self.e, self.s = X
         self.n = self.e.shape[0]
@@ -106,6 +106,7 @@ class _LU:
         self.method = method
         self.leaf = leaf
         self.extra_groups = extra_groups
+        self.nslice = nslice
         self.ipiv = np.zeros(self.n, dtype=np.int64)
         self.info = 0
 
@@ -122,7 +123,7 @@ class _LU:
 
         def sub(r0, r1, cc0, cc1):
             return from_lf((m[cc0:cc1, r0:r1], e[cc0:cc1, r0:r1], s[cc0:cc1, r0:r1]))
-        plan = make_plan(64 * nl, K, extra_groups=self.extra_groups)
+        plan = make_plan(64 * nl, K, nslice=self.nslice, extra_groups=self.extra_groups)
         out, _ = OL.ozgemm(1, sub(i0, i1, k0, k0 + K), sub(k0, k0 + K, c0, c1),
                            sub(i0, i1, c0, c1), plan)
         om, oe, os_ = to_lf(out)
@@ -170,7 +171,8 @@ class _LU:
         self.panel(c0 + w1, w - w1, P0, P1)
 
 
-def getrf(A, b: int, method: str = "ozaki", extra_groups: int = 0, leaf: int = 0):
+def getrf(A, b: int, method: str = "ozaki", extra_groups: int = 0, leaf: int = 0,
+          nslice: int = 0):
     """Blocked LU of the n x n limb matrix A with panel width b.  leaf > 0:
     the panel and the U12 solve recurse on halves down to leaf columns or
     rows, the inner updates made like the Schur update (Ozaki-II or
@@ -178,7 +180,7 @@ def getrf(A, b: int, method: str = "ozaki", extra_groups: int = 0, leaf: int = 0
     rows, LAPACK semantics), info)."""
     if method not in ("ozaki", "native"):
         raise ValueError(method)
-    L = _LU(to_lf(A), method, leaf, extra_groups)
+    L = _LU(to_lf(A), method, leaf, extra_groups, nslice)
     n = L.n
     b = max(1, int(b))
     for k0 in range(0, n, b):

@@ -52,6 +52,7 @@ EXPORTED = ["ozII_create", "ozII_destroy", "ozII_set_stream", "ozII_plan_query",
             "ozII_getrf", "ozII_getrs", "ozII_getrf_limbs", "ozII_getrs_limbs",
             "ozII_limbs_arith",
             "ozII_batch_prepare", "ozII_batch_prepare_ex", "ozII_batch_run", "ozII_tune",
+            "ozII_tune_limbs",
             "ozII_stream_of",
             "ozII_sync_check", "ozII_set_profiling",
             "ozII_profile_read", "ozII_status_string", "ozII_last_error"]
@@ -117,6 +118,8 @@ def lib():
         L.ozII_getrs_limbs.argtypes = [_p, _i32, _i64, _i64, LP, _p, LP]
         L.ozII_limbs_arith.argtypes = [_p, _i32, _i32, _i64, LP, LP, LP]
         L.ozII_tune.argtypes = [_p, _i32, _i64, C.c_char_p, _i32, OP, C.POINTER(TuneReport)]
+        L.ozII_tune_limbs.argtypes = [_p, _i32, _i64, C.c_char_p, _i32, OP,
+                                      C.POINTER(TuneReport)]
         L.ozII_batch_prepare.argtypes = [_p, _i32, C.POINTER(BatchItem)]
         L.ozII_batch_prepare_ex.argtypes = [_p, _i32, C.POINTER(BatchItem), OP]
         L.ozII_batch_run.argtypes = [_p, _p]
@@ -571,6 +574,26 @@ class Context:
                           "update": "native" if o.method == METHOD_NAIVE else names.get(o.backend, "?"),
                           "lookahead": not (o.flags & F_NO_LOOKAHEAD), "nslice": o.nslice,
                           "gemm_tile": o.gemm_tile, "ms": rep.ms[i], "model_ms": rep.model_ms[i]})
+        return best, {"from_cache": bool(rep.from_cache), "best": rep.best, "candidates": cands}
+
+    def tune_limbs(self, nlimb: int, n: int, cache_path: Optional[str] = None,
+                   retune: bool = False):
+        """Autotune the limb LU (block, panel leaf, native or Ozaki-II, then
+        S and the GEMM tile) for order n; returns (Opts, report dict)."""
+        best = Opts()
+        rep = TuneReport()
+        self._bind()
+        self._call(lib().ozII_tune_limbs(self._h, nlimb, n,
+                                         cache_path.encode() if cache_path else None,
+                                         TUNE_RETUNE if retune else 0, C.byref(best),
+                                         C.byref(rep)))
+        cands = []
+        for i in range(rep.ncand):
+            o = rep.cand[i]
+            cands.append({"block": o.block,
+                          "update": "native" if o.method == METHOD_NAIVE else "int8",
+                          "panel_leaf": o.panel_leaf, "nslice": o.nslice,
+                          "gemm_tile": o.gemm_tile, "ms": rep.ms[i]})
         return best, {"from_cache": bool(rep.from_cache), "best": rep.best, "candidates": cands}
 
     def sync_check(self):

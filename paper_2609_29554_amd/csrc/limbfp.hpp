@@ -15,9 +15,10 @@
 // lane is read off the 64-bit sum (g|p) + g + cin, whose bit k is
 // g_k ^ p_k ^ carry_k.  Products form each output column in its own lane
 // (columns 64..127 in a second register) and resolve the column sums the
-// same way; division is schoolbook long division on 32-bit digits (each
-// digit estimated from the remainder's top two digits over the divisor's
-// top digit, at most two add-backs, Knuth's Theorem 4.3.1B).
+// same way; division is schoolbook long division on 64-bit digits (each
+// digit from the remainder's top two digits over the divisor's top digit by
+// Moller and Granlund's two-by-one division, at most two add-backs, Knuth's
+// Theorem 4.3.1B).
 //
 // The includer provides LFP_FN and the cross-lane primitives lane_id,
 // ballot, readlane64 (wave-uniform lane), shfl64 (any lane), up1_64 (from
@@ -331,60 +332,77 @@ LFP_FN WF add(const WF &a, const WF &b, uint32_t negb, int nl) {
   return r;
 }
 
-// min(floor(U / v), 2^32 - 1) for 2^31 <= v < 2^32 (rv = RN(1/v)): the
-// binary64 quotient is within 2^-17 of U / v (three roundings of relative
-// size 2^-53 on a value below 2^33), so its floor is off by at most one,
-// which the exact remainder U - q v decides.
-LFP_FN uint64_t digit_estimate(uint64_t U, uint64_t v, double rv) {
-  const double qf = (double)U * rv;
-  if (qf >= 4294967296.0) return 0xffffffffull;  // floor(U / v) >= 2^32 - 1
-  uint64_t q = (uint64_t)qf;                      // < 2^32: q v < 2^64
-  const uint64_t qv = q * v;
-  if (qv > U) {
-    q -= 1;
-  } else if (U - qv >= v) {
-    q += 1;
+// floor((2^128 - 1) / v) - 2^64 for 2^63 <= v < 2^64: the reciprocal with
+// which Moller and Granlund divide two words by the invariant word v; by
+// binary long division of (2^64 - 1 - v) 2^64 + (2^64 - 1), whose high word
+// is below v.
+LFP_FN uint64_t recip64(uint64_t v) {
+  uint64_t r = ~v, q = 0;
+  for (int i = 0; i < 64; ++i) {
+    const uint64_t top = r >> 63;
+    r = (r << 1) | 1ull;
+    q <<= 1;
+    if (top || r >= v) {
+      r -= v;
+      q |= 1ull;
+    }
   }
-  return q > 0xffffffffull ? 0xffffffffull : q;
+  return q;
 }
 
-// RN_p(a / b); b must be non-zero (a zero b gives zero)
+// floor((u1 2^64 + u0) / v) for u1 < v, v >= 2^63, vinv = recip64(v)
+// (Moller and Granlund, "Improved division by invariant integers", 2011,
+// the two-by-one division with its two conditional corrections)
+LFP_FN uint64_t div2by1(uint64_t u1, uint64_t u0, uint64_t v, uint64_t vinv) {
+  const uint64_t p0 = vinv * u1, p1 = umulhi64(vinv, u1);
+  const uint64_t q0 = p0 + u0;
+  uint64_t q1 = p1 + u1 + (q0 < p0 ? 1ull : 0ull) + 1ull;
+  uint64_t r = u0 - q1 * v;
+  if (r > q0) {
+    q1 -= 1;
+    r += v;
+  }
+  if (r >= v) q1 += 1;
+  return q1;
+}
+
+// RN_p(a / b); b must be non-zero (a zero b gives zero).  Long division on
+// 64-bit digits: digit = min(floor(top two remainder digits / top divisor
+// digit), 2^64 - 1), at most two add-backs (Knuth, TAOCP 4.3.1, Theorem B).
 LFP_FN WF div(const WF &a, const WF &b, int nl) {
   if (is_zero(a) || is_zero(b)) return wf_zero();
   const int l = lane_id();
   const bool act = l < nl;
   const uint64_t V = b.m;
-  const uint64_t vt = readlane64(V, nl - 1) >> 32;  // top 32-bit digit, >= 2^31
-  const double rvt = 1.0 / (double)vt;
+  const uint64_t v1 = readlane64(V, nl - 1);  // top divisor digit, >= 2^63
+  const uint64_t vinv = recip64(v1);
   // leading quotient digit d0 = floor(ma / mb) in {0, 1}
   const uint32_t d0 = cmp_mant(a.m, V) >= 0 ? 1u : 0u;
   uint64_t R = a.m;
   uint32_t bo;
   if (d0) R = sub1(R, V, nl, 0u, bo);
-  // 2 nl + 1 further digits: Q collects the first 2 nl (limb q from digits
-  // 2nl - 2q - 1 (high half) and 2nl - 2q (low half)), dl is the last
-  const int K = 2 * nl + 1;
+  // nl + 1 further digits: limb nl - i of Q takes digit i (i <= nl), dl the last
+  const int K = nl + 1;
   uint64_t Q = 0, dl = 0;
   for (int i = 1; i <= K; ++i) {
-    // R <- R 2^32 (R < V); U = the shifted remainder's top two digits
-    const uint64_t U = readlane64(R, nl - 1);
-    const uint64_t below = up1_64(R);
-    R = act ? ((R << 32) | (below >> 32)) : 0ull;
-    const uint64_t rt = U >> 32;  // the digit above limb nl-1
-    uint64_t qh = digit_estimate(U, vt, rvt);
+    // R <- R 2^64 (R < V): its top limb becomes the digit above limb nl-1
+    const uint64_t ut = readlane64(R, nl - 1);
+    const uint64_t un = nl >= 2 ? readlane64(R, nl - 2) : 0ull;  // nl is uniform
+    const uint64_t Rs = up1_64(R);
+    R = act ? Rs : 0ull;
+    uint64_t qh = ut >= v1 ? ~0ull : div2by1(ut, un, v1, vinv);
     // T = qh V: lane k's product lo + hi 2^64, hi moving to lane k+1
-    const uint64_t p0 = qh * (V & 0xffffffffull), p1 = qh * (V >> 32);
-    const uint64_t lo = p0 + (p1 << 32);
-    const uint64_t hi = (p1 >> 32) + (lo < p0 ? 1ull : 0ull);
+    const uint64_t lo = qh * V, hi = umulhi64(qh, V);
     const uint64_t hin = up1_64(hi);
     uint64_t T = lo + hin;
     uint32_t c63;
     const uint64_t cm = chain(ballot(act && T < lo), ballot(act && T == ~0ull), 0u, c63);
     T = act ? T + bit_of(cm, l) : 0ull;
-    const uint64_t ttop = readlane64(hi, nl - 1) + out_at(cm, c63, nl);
+    const uint64_t ttop = readlane64(hi, nl - 1) + out_at(cm, c63, nl);  // <= 2^64 - 1
     uint32_t bt;
     R = sub1(R, T, nl, 0u, bt);
-    int64_t top = (int64_t)rt - (int64_t)ttop - (int64_t)bt;
+    // the remainder lies in [-2V, V): its top digit, signed, is -2, -1 or 0
+    int64_t top = (int64_t)(ut - ttop - bt);
     for (int k = 0; k < 2 && top < 0; ++k) {
       qh -= 1;
       uint32_t cy;
@@ -392,9 +410,7 @@ LFP_FN WF div(const WF &a, const WF &b, int nl) {
       top += cy;
     }
     if (i < K) {
-      const int t = 2 * nl - i;
-      const uint64_t dig = (t & 1) ? (qh << 32) : qh;
-      Q |= (l == (t >> 1)) ? dig : 0ull;
+      Q = (l == nl - i) ? qh : Q;
     } else {
       dl = qh;
     }
@@ -405,8 +421,8 @@ LFP_FN WF div(const WF &a, const WF &b, int nl) {
   if (!d0) {
     // quotient bits: Q (p bits), then the last digit
     m = Q;
-    rb = (uint32_t)(dl >> 31);
-    st = (uint32_t)((dl & 0x7fffffffull) != 0) | rem;
+    rb = (uint32_t)(dl >> 63);
+    st = (uint32_t)((dl << 1) != 0) | rem;
   } else {
     // a leading 1 before Q: shift right by one
     const uint64_t above = shfl64(Q, (l + 1) & 63);

@@ -219,3 +219,33 @@ def test_lotkin_limb_lu_p3136_correct_bits(leaf):
     assert int(to_host(info)[0]) == 0
     bits = LF.correct_bits(OLU.to_lf(_host(dX)))
     assert 542 <= bits <= 549, bits
+
+
+def test_tune_limbs_report_and_choice(tmp_path):
+    """The limb autotuner times its candidates, returns the fastest, caches
+    it, and its choice factors a matrix exactly like an explicit call."""
+    import paper_2609_29554_amd as Z
+    nl, n = 2, 160
+    note(f"tune_limbs nl={nl} n={n}")
+    cache = str(tmp_path / "tune.json")
+    best, rep = ctx().tune_limbs(nl, n, cache)
+    assert not rep["from_cache"] and len(rep["candidates"]) >= 4
+    ms = [c["ms"] for c in rep["candidates"]]
+    assert all(m > 0 for m in ms) and ms[rep["best"]] == min(ms)
+    chosen = rep["candidates"][rep["best"]]
+    assert best.block == chosen["block"] and best.panel_leaf == chosen["panel_leaf"]
+    assert {c["update"] for c in rep["candidates"]} == {"int8", "native"}
+    assert any(c["panel_leaf"] > 0 for c in rep["candidates"])
+    best2, rep2 = ctx().tune_limbs(nl, n, cache)
+    assert rep2["from_cache"] and (best2.block, best2.panel_leaf, best2.method, best2.gemm_tile,
+                                   best2.nslice) == (best.block, best.panel_leaf, best.method,
+                                                     best.gemm_tile, best.nslice)
+    A = _matrix(nl, 70, 3)
+    dA = _dev(A)
+    o = Z.make_opts(block=best.block, method=best.method, panel_leaf=best.panel_leaf,
+                    gemm_tile=best.gemm_tile)
+    ipiv, info = ctx().getrf_limbs(dA, block=best.block, method=best.method, opts=o)
+    ctx().sync_check()
+    meth = "native" if best.method == Z.METHOD_NAIVE else "ozaki"
+    want, ip, _ = OLU.getrf(A, best.block, meth, leaf=best.panel_leaf, nslice=best.nslice)
+    _same(_host(dA), want)
