@@ -12,7 +12,7 @@ namespace lfp {
 LFP_FN int lane_id() { return (int)__lane_id(); }
 
 // bit l set when lane l's predicate holds
-LFP_FN uint64_t ballot(bool p) { return (uint64_t)__ballot(p ? 1 : 0); }
+LFP_FN uint64_t ballot(bool p) { return (uint64_t)__builtin_amdgcn_ballot_w64(p); }
 
 // lane l's x, for a wave-uniform l
 LFP_FN uint64_t readlane64(uint64_t x, int l) {
@@ -26,7 +26,13 @@ LFP_FN uint64_t shfl64(uint64_t x, int src) {
   return (uint64_t)__shfl((unsigned long long)x, src, 64);
 }
 
-LFP_FN uint64_t umulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
+// a + b + cin (cin 0 or 1) on 32-bit words, the carry out in *cout
+LFP_FN uint32_t addc32(uint32_t a, uint32_t b, uint32_t cin, uint32_t *cout) {
+  unsigned c;
+  const uint32_t r = __builtin_addc(a, b, cin, &c);
+  *cout = c;
+  return r;
+}
 
 // lane l's result is lane l-1's x, lane 0's is 0 (DPP whole-wave shift)
 LFP_FN uint64_t up1_64(uint64_t x) {

@@ -22,7 +22,8 @@
 //
 // The includer provides LFP_FN and the cross-lane primitives lane_id,
 // ballot, readlane64 (wave-uniform lane), shfl64 (any lane), up1_64 (from
-// lane l-1, 0 into lane 0), rot1_64 (from lane (l-1) mod 64) and umulhi64.
+// lane l-1, 0 into lane 0), rot1_64 (from lane (l-1) mod 64) and addc32
+// (32-bit add with carry).
 // Every function must be called by all 64 lanes of a converged wavefront;
 // branches below depend on wave-uniform values only.
 #pragma once
@@ -216,16 +217,27 @@ LFP_FN W2 up_limb(W2 w) {
   return r;
 }
 
-LFP_FN void mac(uint64_t &c0, uint64_t &c1, uint64_t &c2, uint64_t a, uint64_t b) {
-  const uint64_t lo = a * b, hi = umulhi64(a, b);
-  c0 += lo;
-  const uint64_t k0 = c0 < lo ? 1ull : 0ull;
-  const uint64_t t = c1 + hi;
-  const uint64_t k1 = t < hi ? 1ull : 0ull;
-  const uint64_t u = t + k0;
-  const uint64_t k2 = u < k0 ? 1ull : 0ull;
-  c1 = u;
-  c2 += k1 + k2;
+// a b = lo + hi 2^64 from four 32 x 32 -> 64-bit multiply-adds
+LFP_FN void mul128(uint64_t a, uint64_t b, uint64_t &lo, uint64_t &hi) {
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  const uint64_t p00 = (uint64_t)a0 * b0;
+  const uint64_t p01 = (uint64_t)a0 * b1 + (p00 >> 32);
+  const uint64_t p10 = (uint64_t)a1 * b0 + (uint32_t)p01;
+  hi = (uint64_t)a1 * b1 + (p01 >> 32) + (p10 >> 32);
+  lo = (p10 << 32) | (uint32_t)p00;
+}
+
+// w (five 32-bit words, least significant first) += a b
+LFP_FN void mac5(uint32_t (&w)[5], uint64_t a, uint64_t b) {
+  uint64_t lo, hi;
+  mul128(a, b, lo, hi);
+  uint32_t c;
+  w[0] = addc32(w[0], (uint32_t)lo, 0u, &c);
+  w[1] = addc32(w[1], (uint32_t)(lo >> 32), c, &c);
+  w[2] = addc32(w[2], (uint32_t)hi, c, &c);
+  w[3] = addc32(w[3], (uint32_t)(hi >> 32), c, &c);
+  w[4] += c;
 }
 
 // RN_p(a b)
@@ -233,30 +245,35 @@ LFP_FN WF mul(const WF &a, const WF &b, int nl) {
   if (is_zero(a) || is_zero(b)) return wf_zero();
   const int l = lane_id();
   // Lane l sums column l of the schoolbook product (a_i b_(l-i), i <= l),
-  // then column l + 64 (a_i b_(l+64-i), i > l), as c0 + c1 2^64 + c2 2^128:
-  // one accumulator, the finished low column banked when i passes l.
-  uint64_t c0 = 0, c1 = 0, c2 = 0, k0 = 0, k1 = 0, k2 = 0;
+  // then column l + 64 (a_i b_(l+64-i), i > l), in one 160-bit accumulator
+  // (a column sum is below 64 2^128); the running sum is copied aside when
+  // i passes l, and the high column is the final sum minus that copy.
+  uint32_t w[5] = {0u, 0u, 0u, 0u, 0u}, k[5] = {0u, 0u, 0u, 0u, 0u};
   uint64_t bv = b.m;  // b_((l - i) mod 64) at step i: rotated by one lane per step
   for (int i = 0; i < nl; ++i) {
     const uint64_t ai = readlane64(a.m, i);
     const bool sw = l + 1 == i;
-    k0 = sw ? c0 : k0;
-    k1 = sw ? c1 : k1;
-    k2 = sw ? c2 : k2;
-    c0 = sw ? 0ull : c0;
-    c1 = sw ? 0ull : c1;
-    c2 = sw ? 0ull : c2;
-    mac(c0, c1, c2, ai, bv);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) k[q] = sw ? w[q] : k[q];
+    mac5(w, ai, bv);
     bv = rot1_64(bv);
   }
   const bool banked = l + 1 < nl;  // lanes >= nl-1 never reach their high column
+  uint32_t lw[5], hw[5], br = 0u;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    lw[q] = banked ? k[q] : w[q];
+    const uint32_t d = addc32(w[q], ~k[q], 1u - br, &br);  // w - k, br: borrow out
+    br = 1u - br;
+    hw[q] = banked ? d : 0u;
+  }
   W2 A, B, C;
-  A.lo = banked ? k0 : c0;
-  A.hi = banked ? c0 : 0ull;
-  B.lo = banked ? k1 : c1;
-  B.hi = banked ? c1 : 0ull;
-  C.lo = banked ? k2 : c2;
-  C.hi = banked ? c2 : 0ull;
+  A.lo = ((uint64_t)lw[1] << 32) | lw[0];
+  A.hi = ((uint64_t)hw[1] << 32) | hw[0];
+  B.lo = ((uint64_t)lw[3] << 32) | lw[2];
+  B.hi = ((uint64_t)hw[3] << 32) | hw[2];
+  C.lo = lw[4];
+  C.hi = hw[4];
   B = up_limb(B);
   C = up_limb(up_limb(C));  // column 2nl-2 holds one product: its c2 is 0
   uint32_t co;
@@ -354,7 +371,8 @@ LFP_FN uint64_t recip64(uint64_t v) {
 // (Moller and Granlund, "Improved division by invariant integers", 2011,
 // the two-by-one division with its two conditional corrections)
 LFP_FN uint64_t div2by1(uint64_t u1, uint64_t u0, uint64_t v, uint64_t vinv) {
-  const uint64_t p0 = vinv * u1, p1 = umulhi64(vinv, u1);
+  uint64_t p0, p1;
+  mul128(vinv, u1, p0, p1);
   const uint64_t q0 = p0 + u0;
   uint64_t q1 = p1 + u1 + (q0 < p0 ? 1ull : 0ull) + 1ull;
   uint64_t r = u0 - q1 * v;
@@ -392,7 +410,8 @@ LFP_FN WF div(const WF &a, const WF &b, int nl) {
     R = act ? Rs : 0ull;
     uint64_t qh = ut >= v1 ? ~0ull : div2by1(ut, un, v1, vinv);
     // T = qh V: lane k's product lo + hi 2^64, hi moving to lane k+1
-    const uint64_t lo = qh * V, hi = umulhi64(qh, V);
+    uint64_t lo, hi;
+    mul128(qh, V, lo, hi);
     const uint64_t hin = up1_64(hi);
     uint64_t T = lo + hin;
     uint32_t c63;
