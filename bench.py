@@ -33,7 +33,7 @@ METRIC = "QD LU n=2048 time vs native-QD GPU LU; Ozaki-II GEMM GOPS & % INT8 MFM
 PEAK_HBM_GBS = 8000.0
 PEAK_INT8_TOPS = 5000.0
 # dense MFMA peaks of MI355X per back-end of the modular GEMM [TOP/s]
-PEAK_MFMA = {"int8": 5000.0, "fp8": 5000.0, "f64": 78.6}
+PEAK_MFMA = {"int8": 5000.0, "fp8": 5000.0, "f64": 78.6, "fp16": 2500.0}
 
 
 def log(msg):
@@ -218,7 +218,7 @@ def main():
     ap.add_argument("--nlimb", type=int, default=64)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--gemm-n", type=int, default=4096)
-    ap.add_argument("--gemm-backend", choices=["int8", "fp8", "f64"], default="int8")
+    ap.add_argument("--gemm-backend", choices=["int8", "fp8", "f64", "fp16"], default="int8")
     ap.add_argument("--gemm-plan", choices=["literal", "rule"], default="literal",
                     help="standalone TD product: 'literal' = at 159-bit scaling as the workload "
                          "states it (one slice, N_mod covering 2 k 2^318); 'rule' = the plan "
@@ -275,7 +275,7 @@ def main():
     db0 = torch.from_numpy(rhs0).to(dev)
     dA = torch.empty_like(dA0)
     dx = torch.empty_like(db0)
-    names = {Z.BE_INT8: "int8", Z.BE_FP8_B17: "fp8", Z.BE_F64MOD: "f64"}
+    names = {Z.BE_INT8: "int8", Z.BE_FP8_B17: "fp8", Z.BE_F64MOD: "f64", Z.BE_FP16: "fp16"}
     tuning = None
     if args.no_autotune:
         run_opts = Z.make_opts(block=b, backend=Z.BE_INT8)
@@ -424,7 +424,8 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"int8": "f64x4+i8", "fp8": "f64x4+fp8", "f64": "f64x4", "native": "f64x4"}[update_name],
+        "dtype": {"int8": "f64x4+i8", "fp8": "f64x4+fp8", "f64": "f64x4", "fp16": "f64x4+f16",
+                  "native": "f64x4"}[update_name],
         "data": "synthetic",
         "config": {"workload": f"Lotkin quad-double LU n={n} (getrf+getrs), b={b}, Schur update "
                                f"{'Ozaki-II ' + update_name if update_name != 'native' else 'native'}"
@@ -502,7 +503,7 @@ def td_gemm_probe(n, steps=3):
 def backend_sweep(ctx, args):
     """Quad-double Lotkin LU + solve at n = sweep_n, b = sweep_block with the
     Schur update on each back-end of the modular GEMM (INT8, FP8 E4M3
-    base-17, binary64 moduli) and natively; one timed step each after a
+    base-17, binary64 moduli, FP16) and natively; one timed step each after a
     warm-up step.  Reports seconds, Schur-update time and the modular GEMM
     rate against that engine's MFMA peak."""
     import torch
@@ -516,7 +517,8 @@ def backend_sweep(ctx, args):
     dA, dx = torch.empty_like(A0), torch.empty_like(r0)
     out = {"workload": f"Lotkin quad-double LU n={n} b={b} (getrf+getrs)"}
     for name, be, method in (("int8", Z.BE_INT8, Z.METHOD_OZAKI), ("fp8", Z.BE_FP8_B17, Z.METHOD_OZAKI),
-                             ("f64", Z.BE_F64MOD, Z.METHOD_OZAKI), ("native", Z.BE_INT8, Z.METHOD_NAIVE)):
+                             ("f64", Z.BE_F64MOD, Z.METHOD_OZAKI), ("fp16", Z.BE_FP16, Z.METHOD_OZAKI),
+                             ("native", Z.BE_INT8, Z.METHOD_NAIVE)):
         opts = Z.make_opts(backend=be)
 
         def run():
@@ -718,7 +720,7 @@ def bench_gemm(args):
     dA = torch.from_numpy(A).cuda()
     dB = torch.from_numpy(B).cuda()
     dC = torch.zeros_like(dA)
-    be = {"int8": Z.BE_INT8, "fp8": Z.BE_FP8_B17, "f64": Z.BE_F64MOD}[args.gemm_backend]
+    be = {"int8": Z.BE_INT8, "fp8": Z.BE_FP8_B17, "f64": Z.BE_F64MOD, "fp16": Z.BE_FP16}[args.gemm_backend]
     opts = Z.make_opts(backend=be, qbits=159 if args.gemm_plan == "literal" else 0)
     peak = PEAK_MFMA[args.gemm_backend]
     S, w, Q, nmod, _ = Z.plan_query(53 * nc, n, opts)

@@ -46,13 +46,18 @@ typedef enum {
  *          (Eq. fp8digits) stored as E4M3, four sub-products per pair with
  *          exact FP32 accumulation;
  *   F64:   the 20 largest primes m with K S m^2 < 2^53 (Eq. fp64mod),
- *          residues in binary64, exact FP64 MFMA accumulation.
+ *          residues in binary64, exact FP64 MFMA accumulation;
+ *   FP16:  the INT8 moduli and residue planes, one product per modulus on
+ *          the FP16 engine (Sec. 4.1.3): residues converted to f16 in
+ *          registers, FP32 partial sums of at most 1024 products (exact,
+ *          Eq. fp16cond per chunk) folded into int32.
  * AUTO currently means INT8. */
 typedef enum {
   OZII_BE_AUTO = 0,
   OZII_BE_INT8 = 1,
   OZII_BE_FP8_B17 = 2,
-  OZII_BE_F64MOD = 3
+  OZII_BE_F64MOD = 3,
+  OZII_BE_FP16 = 4
 } ozII_backend;
 
 typedef enum {

@@ -23,7 +23,7 @@ from typing import Optional, Tuple
 
 import numpy as np
 
-from .plan import (BACKEND_F64MOD, BACKEND_FP8_B17, BACKEND_INT8, Plan,  # noqa: F401
+from .plan import (BACKEND_F64MOD, BACKEND_FP16, BACKEND_FP8_B17, BACKEND_INT8, Plan,  # noqa: F401
                    make_plan, int8_moduli, f64_moduli, lhint)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))

@@ -46,6 +46,7 @@ from typing import List, Optional
 BACKEND_INT8 = 1
 BACKEND_FP8_B17 = 2
 BACKEND_F64MOD = 3
+BACKEND_FP16 = 4   # the INT8 moduli and residues on the FP16 engine (Sec. 4.1.3)
 
 
 def _is_prime(n: int) -> bool:
@@ -125,7 +126,7 @@ class Plan:
 
 
 def _accum_ok(backend: int, K: int, S: int) -> bool:
-    if backend == BACKEND_INT8:
+    if backend in (BACKEND_INT8, BACKEND_FP16):
         return K * S * 128 * 128 < (1 << 31)
     if backend == BACKEND_FP8_B17:
         return K * S * 128 * 128 < (1 << 31) and K * S * 64 < (1 << 24)

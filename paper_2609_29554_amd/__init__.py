@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libozii.so")
 
 OK, EINVAL, ECAPACITY, EOVERFLOW, ENOMEM, EHIP, EUNSUPPORTED, EDEVICE = range(8)
-BE_AUTO, BE_INT8, BE_FP8_B17, BE_F64MOD = range(4)
+BE_AUTO, BE_INT8, BE_FP8_B17, BE_F64MOD, BE_FP16 = range(5)
 METHOD_OZAKI, METHOD_NAIVE = 0, 1
 TILE_AUTO, TILE_128x128, TILE_256x128, TILE_256x256 = range(4)
 F_NO_LOOKAHEAD = 1
@@ -440,7 +440,8 @@ class Context:
         # plane element type and planes per (slice, modulus); t-value type
         pdt, per, tdt = {BE_INT8: (torch.int8, 1, torch.uint8),
                          BE_FP8_B17: (torch.uint8, 2, torch.uint8),
-                         BE_F64MOD: (torch.float64, 1, torch.int32)}[backend]
+                         BE_F64MOD: (torch.float64, 1, torch.int32),
+                         BE_FP16: (torch.int8, 1, torch.uint8)}[backend]
         npl = S.value * nmod.value * per
         ea = torch.empty(M, dtype=torch.int32, device=dev)
         eb = torch.empty(N, dtype=torch.int32, device=dev)
@@ -566,7 +567,7 @@ class Context:
         self._bind()
         self._call(lib().ozII_tune(self._h, nc, n, cache_path.encode() if cache_path else None,
                                    TUNE_RETUNE if retune else 0, C.byref(best), C.byref(rep)))
-        names = {BE_INT8: "int8", BE_FP8_B17: "fp8", BE_F64MOD: "f64"}
+        names = {BE_INT8: "int8", BE_FP8_B17: "fp8", BE_F64MOD: "f64", BE_FP16: "fp16"}
         cands = []
         for i in range(rep.ncand):
             o = rep.cand[i]

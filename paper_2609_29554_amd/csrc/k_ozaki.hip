@@ -512,6 +512,132 @@ __device__ __forceinline__ uint32_t mod_times_y_d(double c, double md, double yd
 }
 }  // namespace
 
+// (S4) on the FP16 engine (the FP16 back-end: the INT8 moduli, one product
+// per modulus, FP32 accumulation).  The operands are the INT8 residue planes:
+// each lane's 16 residues of a 64-k block become two 8-element f16 vectors
+// in registers (byte u = r + 128 placed under the exponent of 1024, then
+// 1152 subtracted: exact), fed to v_mfma_f32_16x16x32_f16 -- the k order
+// inside a block only has to agree between A and B.  Every FP32 partial sum
+// covers at most 1024 products of residues |r| <= 128, so it stays within
+// 2^24 and exact; it is folded into int32 accumulators every 16 blocks and
+// at the end of each slice pair.  Tile and epilogue as k_gemm_i8.
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef _Float16 v2h __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t i8pair_to_f16(uint32_t u, uint32_t sel) {
+  v2h h = __builtin_bit_cast(v2h, __builtin_amdgcn_perm(0x64646464u, u, sel));
+  h = h - (v2h){(_Float16)1152.0f, (_Float16)1152.0f};
+  return __builtin_bit_cast(uint32_t, h);
+}
+
+__device__ __forceinline__ void i8_to_f16(v4i f, v8h &lo, v8h &hi) {
+  uint32_t o[8];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const uint32_t u = (uint32_t)f[d] ^ 0x80808080u;  // r + 128 per byte
+    o[2 * d] = i8pair_to_f16(u, 0x04010400u);         // bytes 0, 1 under 0x64
+    o[2 * d + 1] = i8pair_to_f16(u, 0x04030402u);     // bytes 2, 3
+  }
+  const v4i a = {(int)o[0], (int)o[1], (int)o[2], (int)o[3]};
+  const v4i b = {(int)o[4], (int)o[5], (int)o[6], (int)o[7]};
+  lo = __builtin_bit_cast(v8h, a);
+  hi = __builtin_bit_cast(v8h, b);
+}
+
+__global__ __launch_bounds__(256) void k_gemm_f16(const int8_t *__restrict__ pa,
+                                                  const int8_t *__restrict__ pb,
+                                                  uint8_t *__restrict__ tpl, const DevPlan *pl,
+                                                  int64_t Mp, int64_t Np, int64_t KB,
+                                                  int64_t planeA, int64_t planeB, int tilesM,
+                                                  int tilesN) {
+  constexpr int LDT = 144;
+  __shared__ __attribute__((aligned(16))) uint8_t tile[128 * LDT];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int nb = gridDim.x, pid = blockIdx.x;
+  const int xcd = pid & 7, loc = pid >> 3;
+  const int qd = nb >> 3, rm = nb & 7;
+  const int lt = (xcd < rm ? xcd * (qd + 1) : rm * (qd + 1) + (xcd - rm) * qd) + loc;
+  const int tn = lt % tilesN;
+  const int tm = (lt / tilesN) % tilesM;
+  const int gl = lt / (tilesN * tilesM);
+  const int nmod = pl->nmod;
+  const int l = gl % nmod, gi = gl / nmod;
+  const int S = pl->S, g = pl->g0 + gi;
+  const int ta0 = g - (S - 1) > 0 ? g - (S - 1) : 0;
+  const int ta1 = g < S - 1 ? g : S - 1;
+
+  v4i acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = v4i{0, 0, 0, 0};
+
+  for (int ta = ta0; ta <= ta1; ++ta) {
+    const int tb = g - ta;
+    const int8_t *A0 = pa + (int64_t)(ta * nmod + l) * planeA +
+                       ((int64_t)(tm * 8 + wm * 4) * KB) * 1024 + lane * 16;
+    const int8_t *B0 = pb + (int64_t)(tb * nmod + l) * planeB +
+                       ((int64_t)(tn * 8 + wn * 4) * KB) * 1024 + lane * 16;
+    v4f facc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) facc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int64_t kb = 0; kb < KB; ++kb) {
+      v8h al[4], ah[4], bl[4], bh[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        i8_to_f16(*(const v4i *)(A0 + ((int64_t)a * KB + kb) * 1024), al[a], ah[a]);
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        i8_to_f16(*(const v4i *)(B0 + ((int64_t)b * KB + kb) * 1024), bl[b], bh[b]);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          facc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[a], bl[b], facc[a][b], 0, 0, 0);
+          facc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[a], bh[b], facc[a][b], 0, 0, 0);
+        }
+      if ((kb & 15) == 15 || kb + 1 == KB) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[a][b][r] += (int)facc[a][b][r];
+            facc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+          }
+      }
+    }
+  }
+  const uint32_t m = (uint32_t)pl->m[l];
+  const double md = (double)m, yd = (double)pl->y[l], im = pl->inv_m[l];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      uint32_t packed = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) packed |= mod_times_y(acc[a][b][r], md, yd, im, m) << (8 * r);
+      const int row = wm * 64 + 16 * a + 4 * (lane >> 4);
+      const int col = wn * 64 + 16 * b + (lane & 15);
+      *(uint32_t *)(tile + col * LDT + row) = packed;
+    }
+  }
+  __syncthreads();
+  {
+    const int col = threadIdx.x >> 1, half = threadIdx.x & 1;
+    const uint4 *src = (const uint4 *)(tile + col * LDT + half * 64);
+    uint4 *dst = (uint4 *)(tpl + ((int64_t)gl * Np + (int64_t)tn * 128 + col) * Mp +
+                           (int64_t)tm * 128 + half * 64);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dst[k] = src[k];
+  }
+}
+
+
 __global__ __launch_bounds__(512) void k_gemm_f8(const uint8_t *__restrict__ pa,
                                                  const uint8_t *__restrict__ pb,
                                                  uint8_t *__restrict__ tpl, const DevPlan *pl,
@@ -951,6 +1077,18 @@ hipError_t launch_gemm_f8(const uint8_t *pa, const uint8_t *pb, uint8_t *tpl, co
   const int tilesM = (int)(Mp / 128), tilesN = (int)(Np / 128);
   hipLaunchKernelGGL(k_gemm_f8, dim3((unsigned)(prods * tilesM * tilesN)), dim3(512), 0, s, pa, pb,
                      tpl, pl, Mp, Np, Kp / 64, planeA, planeB, tilesM, tilesN);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_f16(const int8_t *pa, const int8_t *pb, uint8_t *tpl, const DevPlan *pl,
+                           int ng, int nmod, int64_t Mp, int64_t Np, int64_t Kp, int64_t planeA,
+                           int64_t planeB, hipStream_t s) {
+  const int64_t prods = (int64_t)ng * nmod;
+  if (prods <= 0 || Mp <= 0 || Np <= 0) return hipSuccess;
+  if (Mp % 128 || Np % 128 || Kp % 64) return hipErrorInvalidValue;
+  const int tilesM = (int)(Mp / 128), tilesN = (int)(Np / 128);
+  hipLaunchKernelGGL(k_gemm_f16, dim3((unsigned)(prods * tilesM * tilesN)), dim3(256), 0, s, pa,
+                     pb, tpl, pl, Mp, Np, Kp / 64, planeA, planeB, tilesM, tilesN);
   return hipGetLastError();
 }
 

@@ -111,7 +111,9 @@ struct HostPlan {
 // accumulators are exact); binary64 holds by the choice of the moduli.
 bool accum_ok(int backend, int64_t K, int S) {
   const double ks = (double)K * S;
-  if (backend == OZII_BE_INT8) return ks * 128.0 * 128.0 < 2147483648.0;
+  // FP16: FP32 partial sums of at most 1024 products (exact), folded into
+  // int32: the INT8 bound
+  if (backend == OZII_BE_INT8 || backend == OZII_BE_FP16) return ks * 128.0 * 128.0 < 2147483648.0;
   if (backend == OZII_BE_FP8_B17) return ks * 128.0 * 128.0 < 2147483648.0 && 2.0 * ks * 64.0 < 16777216.0;
   return true;
 }
@@ -132,7 +134,7 @@ ozII_status make_plan(int p, int64_t K, const ozII_opts *o, HostPlan &pl, std::s
     if (why) *why = "gemm_tile must be 0..3";
     return OZII_EINVAL;
   }
-  if (backend < OZII_BE_INT8 || backend > OZII_BE_F64MOD) {
+  if (backend < OZII_BE_INT8 || backend > OZII_BE_FP16) {
     if (why) *why = "unknown back-end";
     return OZII_EINVAL;
   }
@@ -687,6 +689,9 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
                               hp->nmod, L.Mp, L.Np, L.Kp, L.planeA, L.planeB, s);
     else if (hp->backend == OZII_BE_F64MOD)
       e = ozl::launch_gemm_f64((const double *)pa, (const double *)pb, (uint32_t *)tpl, dp, hp->ng,
+                               hp->nmod, L.Mp, L.Np, L.Kp, L.planeA, L.planeB, s);
+    else if (hp->backend == OZII_BE_FP16)
+      e = ozl::launch_gemm_f16((const int8_t *)pa, (const int8_t *)pb, (uint8_t *)tpl, dp, hp->ng,
                                hp->nmod, L.Mp, L.Np, L.Kp, L.planeA, L.planeB, s);
     else
       e = ozl::launch_gemm_i8((const int8_t *)pa, (const int8_t *)pb, (uint8_t *)tpl, dp, hp->ng,

@@ -54,6 +54,10 @@ hipError_t launch_gemm_i8(const int8_t *pa, const int8_t *pb, uint8_t *tpl, cons
 hipError_t launch_gemm_f8(const uint8_t *pa, const uint8_t *pb, uint8_t *tpl, const DevPlan *pl,
                           int ng, int nmod, int64_t Mp, int64_t Np, int64_t Kp, int64_t planeA,
                           int64_t planeB, hipStream_t s);
+// (S4) on the FP16 engine from the INT8 residue planes (Mp, Np multiples of 128)
+hipError_t launch_gemm_f16(const int8_t *pa, const int8_t *pb, uint8_t *tpl, const DevPlan *pl,
+                           int ng, int nmod, int64_t Mp, int64_t Np, int64_t Kp, int64_t planeA,
+                           int64_t planeB, hipStream_t s);
 hipError_t launch_gemm_f64(const double *pa, const double *pb, uint32_t *tpl, const DevPlan *pl,
                            int ng, int nmod, int64_t Mp, int64_t Np, int64_t Kp, int64_t planeA,
                            int64_t planeB, hipStream_t s);

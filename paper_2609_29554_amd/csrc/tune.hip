@@ -83,6 +83,7 @@ double peak_ops(int backend) {
   // dense MFMA peaks of MI355X [op/s] for the modular products
   if (backend == OZII_BE_F64MOD) return 78.6e12;
   if (backend == OZII_BE_FP8_B17) return 5.0e15;
+  if (backend == OZII_BE_FP16) return 2.5e15;
   return 5.0e15;
 }
 
@@ -214,7 +215,8 @@ extern "C" ozII_status ozII_tune(ozII_handle h, int32_t nc, int64_t n, const cha
   std::vector<Cand> cands;
   for (int b : {64, 128, 256, 512}) {
     if (b >= n) continue;
-    for (int be : {(int)OZII_BE_INT8, (int)OZII_BE_FP8_B17, (int)OZII_BE_F64MOD, 0}) {
+    for (int be : {(int)OZII_BE_INT8, (int)OZII_BE_FP8_B17, (int)OZII_BE_F64MOD, (int)OZII_BE_FP16,
+                   0}) {
       for (int fl : {0, (int)OZII_F_NO_LOOKAHEAD}) {
         Cand c;
         std::memset(&c.o, 0, sizeof(c.o));

@@ -59,7 +59,7 @@ def test_plan_options_and_errors():
     assert e.value.status == Z.EINVAL
 
 
-@pytest.mark.parametrize("be", [2, 3], ids=["fp8", "f64"])
+@pytest.mark.parametrize("be", [2, 3, 4], ids=["fp8", "f64", "fp16"])
 @pytest.mark.parametrize("p,K", [(106, 32), (159, 512), (212, 256), (212, 512), (212, 4096)])
 def test_backend_plans_match_oracle(be, p, K):
     Z = _lib()

@@ -89,7 +89,7 @@ def test_gemm_td4096_sampled(mode, plan):
     assert np.array_equal(got, want)
 
 
-@pytest.mark.parametrize("backend", ["int8", "fp8", "f64", "native"])
+@pytest.mark.parametrize("backend", ["int8", "fp8", "f64", "fp16", "native"])
 def test_lu_lotkin_qd1024_backends_match_oracle(backend):
     import paper_2609_29554_amd as Z
     n, b, nc = 1024, 128, 4
@@ -100,7 +100,8 @@ def test_lu_lotkin_qd1024_backends_match_oracle(backend):
         LU, ipiv, info, _ = O.getrf(A, b, O.METHOD_NAIVE)
         method, opts = Z.METHOD_NAIVE, None
     else:
-        be = {"int8": O.BACKEND_INT8, "fp8": O.BACKEND_FP8_B17, "f64": O.BACKEND_F64MOD}[backend]
+        be = {"int8": O.BACKEND_INT8, "fp8": O.BACKEND_FP8_B17, "f64": O.BACKEND_F64MOD,
+              "fp16": O.BACKEND_FP16}[backend]
         LU, ipiv, info, _ = O.getrf(A, b, O.METHOD_OZAKI, plan=O.make_plan(53 * nc, b, backend=be))
         method, opts = Z.METHOD_OZAKI, Z.make_opts(backend=be)
     X = O.getrs(LU, ipiv, rhs)

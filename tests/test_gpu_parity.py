@@ -147,11 +147,15 @@ def _e4m3_table():
 BACKEND_CASES = [c for c in STAGE_CASES if c[1] * c[2] > 1][:6] + [(2, 300, 130, 448, 1, 0)]
 
 
-@pytest.mark.parametrize("backend", [O.BACKEND_FP8_B17, O.BACKEND_F64MOD], ids=["fp8", "f64"])
-@pytest.mark.parametrize("case", BACKEND_CASES, ids=lambda c: "nc{}-{}x{}x{}-S{}-E{}".format(*c))
+@pytest.mark.parametrize("backend", [O.BACKEND_FP8_B17, O.BACKEND_F64MOD, O.BACKEND_FP16],
+                         ids=["fp8", "f64", "fp16"])
+@pytest.mark.parametrize("case", BACKEND_CASES + [(2, 40, 33, 1500, 2, 0)],
+                         ids=lambda c: "nc{}-{}x{}x{}-S{}-E{}".format(*c))
 def test_gemm_stages_backends(case, backend):
     """Residue (or digit) planes, t-planes, group sums and products of the
-    FP8 base-17 and binary64-moduli back-ends against the oracle."""
+    FP8 base-17, binary64-moduli and FP16 back-ends against the oracle (the
+    K = 1500 case spans more than 1024 inner terms per FP16 partial sum, so
+    the FP32 partial sums are folded into int32 mid-way)."""
     import paper_2609_29554_amd as Z
     nc, M, N, K, S_f, E = case
     note(f"gemm stages {case} backend {backend}")
@@ -237,7 +241,8 @@ def test_getrf_getrs_bit_exact(case, method):
     assert np.array_equal(to_host(dX), X)
 
 
-@pytest.mark.parametrize("backend", [O.BACKEND_FP8_B17, O.BACKEND_F64MOD], ids=["fp8", "f64"])
+@pytest.mark.parametrize("backend", [O.BACKEND_FP8_B17, O.BACKEND_F64MOD, O.BACKEND_FP16],
+                         ids=["fp8", "f64", "fp16"])
 @pytest.mark.parametrize("case", [(4, 100, 32, "lotkin"), (3, 129, 64, "graded"),
                                   (2, 300, 128, "lotkin")],
                          ids=lambda c: "nc{}-n{}-b{}-{}".format(*c))
