@@ -101,6 +101,12 @@ typedef struct {
  * first and the rest on a side stream while the next panel is factored
  * (the default).  The results are the same bit for bit. */
 #define OZII_F_NO_LOOKAHEAD 1
+/* OZII_F_FUSED: on the INT8 back-end, run (S4)-(S6) of each product as one
+ * kernel per 32 x 32 output tile that keeps the tile's t-values (Eq. crt)
+ * in LDS, instead of a batched GEMM writing t-planes to HBM and a separate
+ * consumer.  Plans of more than 120 (group, modulus) products, and the stage
+ * hooks, use the unfused kernels.  The results are the same bit for bit. */
+#define OZII_F_FUSED 2
 
 typedef struct ozII_ctx *ozII_handle;
 

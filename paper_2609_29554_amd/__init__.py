@@ -25,6 +25,7 @@ BE_AUTO, BE_INT8, BE_FP8_B17, BE_F64MOD, BE_FP16 = range(5)
 METHOD_OZAKI, METHOD_NAIVE = 0, 1
 TILE_AUTO, TILE_128x128, TILE_256x128, TILE_256x256 = range(4)
 F_NO_LOOKAHEAD = 1
+F_FUSED = 2
 
 
 class OziiError(RuntimeError):
@@ -78,7 +79,7 @@ class TuneReport(C.Structure):
                 ("ms", C.c_double * TUNE_MAXCAND), ("model_ms", C.c_double * TUNE_MAXCAND)]
 
 STAGES = ["exponents", "producer", "gemm", "consumer", "panel", "laswp", "trsm", "naive_update",
-          "getrs", "round"]
+          "getrs", "round", "fused"]
 
 
 def lib():

@@ -901,6 +901,105 @@ __global__ __launch_bounds__(256) void k_consumer_b(const uint8_t *__restrict__ 
   }
 }
 
+// Fused (S4)+(S5)+(S6) on the INT8 back-end: one workgroup per 32 x 32
+// output tile keeps every (digit group, modulus) t-value of its tile in LDS
+// instead of writing t-planes to HBM.  Eight wavefronts: wavefront w owns
+// the 16 x 16 block (w & 1, (w >> 1) & 1) of the tile and the products gl
+// of parity w >> 2, each the batched modular product of k_gemm_i8 on
+// fragments read straight from the residue planes (the next product's
+// fragments in flight while the current one multiplies), then the t
+// epilogue into LDS ([gl][column][row], 1 KiB per product).  After one
+// barrier every thread takes two elements through the consumer's CRT,
+// rounding and update (consume_element_b reading its bytes from LDS), so
+// the results equal those of k_gemm_i8 + k_consumer_b bit for bit.
+constexpr int FUSE_T = 32;        // tile edge
+constexpr int FUSE_MAXPROD = 120;  // (group, modulus) products whose t-bytes fit in LDS
+constexpr int FUSE_LDS_MAX = 160 * 1024;
+// per-thread staging words of the consumer phase (NB byte columns)
+template <int NB>
+constexpr int fuse_stage_words() { return stage_words<NB / 2>(); }
+static_assert(FUSE_MAXPROD * 1024 + 512 * fuse_stage_words<48>() * 4 <= FUSE_LDS_MAX,
+              "t-bytes and staging of the largest plan fit in LDS");
+template <int NC, int NWC, int NB>
+__global__ __launch_bounds__(512) void k_fused_b(const int8_t *__restrict__ pa,
+                                                 const int8_t *__restrict__ pb,
+                                                 const DevPlan *__restrict__ pl, int64_t KB,
+                                                 int64_t planeA, int64_t planeB, double *C,
+                                                 int64_t ldc, int64_t M, int64_t N,
+                                                 const int32_t *__restrict__ ea,
+                                                 const int32_t *__restrict__ eb, int mode,
+                                                 int tilesM) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t fsm[];
+  const int nmod = pl->nmod, ng = pl->ng, S = pl->S, g0 = pl->g0;
+  const int npr = ng * nmod;
+  uint8_t *tl = fsm;
+  uint32_t *stage = (uint32_t *)(fsm + (size_t)npr * 1024);
+  const int tm = (int)(blockIdx.x % (unsigned)tilesM), tn = (int)(blockIdx.x / (unsigned)tilesM);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int bm = wv & 1, bn = (wv >> 1) & 1, par = wv >> 2;
+  const int64_t arow = (int64_t)(tm * 2 + bm) * KB * 1024 + lane * 16;
+  const int64_t bcol = (int64_t)(tn * 2 + bn) * KB * 1024 + lane * 16;
+  // fragments of one product: (pairs <= S) x KB blocks of A and of B
+  auto pairs_of = [&](int gl, int &l, int &ta0, int &ta1, int &g) {
+    l = gl % nmod;
+    g = g0 + gl / nmod;
+    ta0 = g - (S - 1) > 0 ? g - (S - 1) : 0;
+    ta1 = g < S - 1 ? g : S - 1;
+  };
+  for (int gl = par; gl < npr; gl += 2) {
+    int l, ta0, ta1, g;
+    pairs_of(gl, l, ta0, ta1, g);
+    v4i acc = {0, 0, 0, 0};
+    for (int ta = ta0; ta <= ta1; ++ta) {
+      const int8_t *A0 = pa + (int64_t)(ta * nmod + l) * planeA + arow;
+      const int8_t *B0 = pb + (int64_t)((g - ta) * nmod + l) * planeB + bcol;
+      v4i af = *(const v4i *)A0, bf = *(const v4i *)B0;
+      for (int64_t kb = 0; kb < KB; ++kb) {
+        v4i an = af, bnx = bf;
+        if (kb + 1 < KB) {
+          an = *(const v4i *)(A0 + (kb + 1) * 1024);
+          bnx = *(const v4i *)(B0 + (kb + 1) * 1024);
+        }
+        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf, acc, 0, 0, 0);
+        af = an;
+        bf = bnx;
+      }
+    }
+    const uint32_t m = (uint32_t)pl->m[l];
+    const double md = (double)m, yd = (double)pl->y[l], im = pl->inv_m[l];
+    uint32_t packed = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) packed |= mod_times_y(acc[r], md, yd, im, m) << (8 * r);
+    const int row = bm * 16 + 4 * (lane >> 4), col = bn * 16 + (lane & 15);
+    *(uint32_t *)(tl + (size_t)gl * 1024 + col * FUSE_T + row) = packed;
+  }
+  __syncthreads();
+  constexpr int STG = fuse_stage_words<NB>();
+  uint32_t *st = stage + threadIdx.x * STG;
+  const int Q = pl->Q;
+  for (int e = threadIdx.x; e < FUSE_T * FUSE_T; e += 512) {
+    const int r = e & (FUSE_T - 1), cc = e / FUSE_T;
+    const int64_t i = (int64_t)tm * FUSE_T + r, j = (int64_t)tn * FUSE_T + cc;
+    if (i >= M || j >= N) continue;
+    const int32_t ei = ea[i], ej = eb[j];
+    const bool zero = ei == EXP_ZERO || ej == EXP_ZERO;
+    const int eps = zero ? 0 : pl->w * g0 - (Q - 1 - ei) - (Q - 1 - ej);
+    double c[NC];
+    consume_element_b<NC, NWC, NB, 0, STG>(tl + cc * FUSE_T + r, 1024, pl, st, zero, eps, c);
+    double *dst = C + (i + j * ldc) * NC;
+    if (mode == 0) {
+      ozx::store<NC>(dst, c);
+    } else {
+      double a[NC], nc_[NC], rr[NC];
+      ozx::load<NC>(dst, a);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) nc_[q] = -c[q];
+      ozx::add<NC>(a, nc_, rr);
+      ozx::store<NC>(dst, rr);
+    }
+  }
+}
+
 // Export of the group sums (parity hook): Sbar as 64-bit limbs (two's
 // complement), layout [gi][j][i][limb], nlimb limbs, from the ND 16-bit
 // digits of a CRT routine.
@@ -1160,6 +1259,39 @@ hipError_t launch_consumer(int nc, int nwc, int nd, const void *tpl, int tbytes,
 #undef OZ_CONS_ND
 #undef OZ_CONSB
 #undef OZ_CONS
+  return hipGetLastError();
+}
+
+int fused_max_products() { return FUSE_MAXPROD; }
+
+hipError_t launch_fused_b(int nc, int nwc, int nd, const int8_t *pa, const int8_t *pb,
+                          const DevPlan *pl, int ng, int nmod, int64_t Kp, int64_t planeA,
+                          int64_t planeB, double *C, int64_t ldc, int64_t M, int64_t N,
+                          const int32_t *ea, const int32_t *eb, int mode, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  if (ng * nmod > FUSE_MAXPROD || nd > 24) return hipErrorInvalidValue;
+  const int tilesM = (int)((M + FUSE_T - 1) / FUSE_T), tilesN = (int)((N + FUSE_T - 1) / FUSE_T);
+  hipError_t e = hipSuccess;
+#define OZ_FUSED(NC_, NWC_, NB_)                                                                  \
+  do {                                                                                            \
+    const size_t lds = (size_t)ng * nmod * 1024 + 512 * fuse_stage_words<NB_>() * 4;            \
+    e = hipFuncSetAttribute((const void *)k_fused_b<NC_, NWC_, NB_>,                             \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
+    if (e != hipSuccess) return e;                                                                \
+    hipLaunchKernelGGL((k_fused_b<NC_, NWC_, NB_>), dim3((unsigned)(tilesM * tilesN)), dim3(512), \
+                       lds, s, pa, pb, pl, Kp / 64, planeA, planeB, C, ldc, M, N, ea, eb, mode,    \
+                       tilesM);                                                                   \
+  } while (0)
+#define OZ_FUSED_ND(NC_, NWC_)              \
+  do {                                     \
+    if (nd <= 18) OZ_FUSED(NC_, NWC_, 36); \
+    else OZ_FUSED(NC_, NWC_, 48);          \
+  } while (0)
+  if (nc == 2) { if (nwc <= 12) OZ_FUSED_ND(2, 12); else OZ_FUSED_ND(2, 16); }
+  else if (nc == 3) { if (nwc <= 12) OZ_FUSED_ND(3, 12); else OZ_FUSED_ND(3, 16); }
+  else { if (nwc <= 12) OZ_FUSED_ND(4, 12); else OZ_FUSED_ND(4, 16); }
+#undef OZ_FUSED_ND
+#undef OZ_FUSED
   return hipGetLastError();
 }
 

@@ -31,7 +31,8 @@ enum {
   OZ_STAGE_NAIVE = 7,
   OZ_STAGE_GETRS = 8,
   OZ_STAGE_ROUND = 9,  // limb format: rounding of the group sums and the update
-  OZ_NSTAGES = 10
+  OZ_STAGE_FUSED = 10, // (S4)-(S6) in one kernel (OZII_F_FUSED)
+  OZ_NSTAGES = 11
 };
 
 // ---------------------------------------------------------------------------
@@ -680,6 +681,18 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
                                   hp->planes_kind(), pb, L.planeB, s)) != hipSuccess)
       return hip_fail(h, e, "producer(B)");
   }
+  // (S4)-(S6) fused: the t-values of a tile stay in LDS (INT8, no stage copies)
+  if (o && (o->flags & OZII_F_FUSED) && hp->backend == OZII_BE_INT8 && !ea_out && !eb_out &&
+      !pa_out && !pb_out && !tpl_out && !sbar_out && hp->ng * hp->nmod <= ozl::fused_max_products() &&
+      hp->nd <= 24) {
+    ProfScope ps(h, OZ_STAGE_FUSED, res_bytes * (double)(M + N) * K + 8.0 * nc * (mode ? 2 : 1) * M * N,
+                 2.0 * (double)M * N * K * pairs, s);
+    if ((e = ozl::launch_fused_b(nc, hp->nwc, hp->nd, (const int8_t *)pa, (const int8_t *)pb, dp,
+                                 hp->ng, hp->nmod, L.Kp, L.planeA, L.planeB, C, ldc, M, N, ea, eb,
+                                 mode, s)) != hipSuccess)
+      return hip_fail(h, e, "fused product");
+    return OZII_OK;
+  }
   {
     // issued operations: the FP8 back-end runs four sub-products per pair
     const double ops = 2.0 * (double)M * N * K * pairs * (hp->backend == OZII_BE_FP8_B17 ? 4.0 : 1.0);
@@ -1188,7 +1201,7 @@ ozII_status ozII_getrf(ozII_handle h, int32_t nc, int64_t n, double *A, int64_t 
   const int flags = o ? o->flags : 0;
   if (b > 512) return fail(h, OZII_EUNSUPPORTED, "panel width above 512");
   if (method != OZII_METHOD_OZAKI && method != OZII_METHOD_NAIVE) return fail(h, OZII_EINVAL, "bad method");
-  if (flags & ~OZII_F_NO_LOOKAHEAD) return fail(h, OZII_EINVAL, "unknown flags");
+  if (flags & ~(OZII_F_NO_LOOKAHEAD | OZII_F_FUSED)) return fail(h, OZII_EINVAL, "unknown flags");
   if (n > (int64_t)1 << 20) return fail(h, OZII_EUNSUPPORTED, "n too large");
   const bool lookahead = !(flags & OZII_F_NO_LOOKAHEAD);
   ozII_status st = ensure_panel(h, n, b);

@@ -385,25 +385,30 @@ OZ_HD void produce_element(const double *src, int mu, const DevPlan *pl, uint32_
 }
 
 // cb += Sbar 2^off (mod 2^(32 NWC)), Sbar given as ND two's-complement 16-bit
-// digits (the top one signed); st: CST words of thread-private scratch.
+// digits (the top one signed); st: STG words of thread-private scratch.  The
+// digits fill st[0, ND/2) and the sign fill the rest; a shifted read past the
+// end takes the last word, which is a fill word, so STG = ND/2 + 1 suffices.
+// An odd STG keeps the per-thread rows in distinct LDS banks.
 constexpr int CST = 33;
+template <int ND>
+constexpr int stage_words() { return (ND / 2 + 1) | 1; }
 
-template <int NWC, int ND>
+template <int NWC, int ND, int STG = CST>
 OZ_HD void add_shifted_digits(uint32_t (&cb)[NWC], const int32_t (&d)[ND], int off, uint32_t *st) {
-  static_assert(ND % 2 == 0 && ND / 2 + NWC + 1 <= CST, "staging too small");
+  static_assert(ND % 2 == 0 && ND / 2 + 1 <= STG, "staging too small");
   const uint32_t fill = d[ND - 1] < 0 ? 0xffffffffu : 0u;
 #pragma unroll
   for (int k = 0; k < ND / 2; ++k)
     st[k] = ((uint32_t)d[2 * k] & 0xffffu) | ((uint32_t)d[2 * k + 1] << 16);
 #pragma unroll
-  for (int k = ND / 2; k < CST; ++k) st[k] = fill;
+  for (int k = ND / 2; k < STG; ++k) st[k] = fill;
   const int q0 = off >> 5, b0 = off & 31;
   uint32_t carry = 0;
 #pragma unroll
   for (int k = 0; k < NWC; ++k) {
     const int s = k - q0;
-    uint32_t cur = s >= 0 ? st[s < CST ? s : CST - 1] : 0u;
-    uint32_t prv = s - 1 >= 0 ? st[s - 1 < CST ? s - 1 : CST - 1] : 0u;
+    uint32_t cur = s >= 0 ? st[s < STG ? s : STG - 1] : 0u;
+    uint32_t prv = s - 1 >= 0 ? st[s - 1 < STG ? s - 1 : STG - 1] : 0u;
     uint32_t v = b0 ? ((cur << b0) | (prv >> (32 - b0))) : cur;
     uint64_t tt = (uint64_t)cb[k] + v + carry;
     cb[k] = (uint32_t)tt;

@@ -58,6 +58,13 @@ hipError_t launch_gemm_f8(const uint8_t *pa, const uint8_t *pb, uint8_t *tpl, co
 hipError_t launch_gemm_f16(const int8_t *pa, const int8_t *pb, uint8_t *tpl, const DevPlan *pl,
                            int ng, int nmod, int64_t Mp, int64_t Np, int64_t Kp, int64_t planeA,
                            int64_t planeB, hipStream_t s);
+// fused (S4)+(S5)+(S6), INT8 planes: t-values of a 32 x 32 tile kept in LDS
+// (at most fused_max_products() (group, modulus) products)
+int fused_max_products();
+hipError_t launch_fused_b(int nc, int nwc, int nd, const int8_t *pa, const int8_t *pb,
+                          const DevPlan *pl, int ng, int nmod, int64_t Kp, int64_t planeA,
+                          int64_t planeB, double *C, int64_t ldc, int64_t M, int64_t N,
+                          const int32_t *ea, const int32_t *eb, int mode, hipStream_t s);
 hipError_t launch_gemm_f64(const double *pa, const double *pb, uint32_t *tpl, const DevPlan *pl,
                            int ng, int nmod, int64_t Mp, int64_t Np, int64_t Kp, int64_t planeA,
                            int64_t planeB, hipStream_t s);

@@ -143,9 +143,9 @@ __device__ __forceinline__ uint32_t mod_times_y(int32_t c, double md, double yd,
 // Consumer of the byte back-ends, one element: per digit group gi the CRT of
 // crt_group_bytes over the t-bytes at tbase + (gi nmod + l) ps (modulus l),
 // the group added at bit w gi to the exact group sum, which is rounded once
-// to NC components of value sum 2^eps (zero: all components 0).  st: CST
+// to NC components of value sum 2^eps (zero: all components 0).  st: STG
 // words of thread-private scratch; PRE: see crt_group_bytes.
-template <int NC, int NWC, int NB, int PRE = 0>
+template <int NC, int NWC, int NB, int PRE = 0, int STG = CST>
 __device__ __forceinline__ void consume_element_b(const uint8_t *tbase, int64_t ps,
                                                   const DevPlan *__restrict__ pl, uint32_t *st,
                                                   bool zero, int eps, double (&c)[NC]) {
@@ -158,7 +158,7 @@ __device__ __forceinline__ void consume_element_b(const uint8_t *tbase, int64_t 
   for (int gi = 0; gi < ng; ++gi) {
     int32_t d[ND];
     crt_group_bytes<NB, PRE>(tbase + (int64_t)gi * nmod * ps, ps, nmod, pl, d);
-    add_shifted_digits<NWC, ND>(cb, d, w * gi, st);
+    add_shifted_digits<NWC, ND, STG>(cb, d, w * gi, st);
   }
   if (zero) {
 #pragma unroll

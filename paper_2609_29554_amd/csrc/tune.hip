@@ -242,8 +242,8 @@ extern "C" ozII_status ozII_tune(ozII_handle h, int32_t nc, int64_t n, const cha
     return OZII_OK;
   }
   std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.model_ms < b.model_ms; });
-  // room for stage 2 (up to 7 refinements of the winner)
-  if ((int)cands.size() > OZII_TUNE_MAXCAND - 7) cands.resize(OZII_TUNE_MAXCAND - 7);
+  // room for stage 2 (up to 8 refinements of the winner)
+  if ((int)cands.size() > OZII_TUNE_MAXCAND - 8) cands.resize(OZII_TUNE_MAXCAND - 8);
 
   void *sv = nullptr;
   ozII_status st = ozII_stream_of(h, &sv);
@@ -331,6 +331,12 @@ extern "C" ozII_status ozII_tune(ozII_handle h, int32_t nc, int64_t n, const cha
             c.ms = 0;
             ref.push_back(c);
           }
+      }
+      if (win.o.backend == OZII_BE_INT8) {
+        // and with the fused (S4)-(S6) kernel
+        Cand c = win;
+        c.o.flags |= OZII_F_FUSED;
+        ref.push_back(c);
       }
       time_all(ref);
     }

@@ -338,3 +338,66 @@ def test_singular_info():
         ctx().sync_check()
         assert info > 0 and int(to_host(dinfo)[0]) == info
         assert np.array_equal(to_host(dA), LU)
+
+
+FUSED_CASES = [
+    # nc, M, N, K, forced S, extra groups
+    (4, 37, 29, 40, 0, 0),
+    (2, 70, 33, 130, 0, 1),
+    (3, 64, 64, 256, 2, 0),
+    (4, 130, 97, 128, 0, 0),
+    (2, 1, 1, 1, 0, 0),
+    (4, 300, 130, 448, 0, 0),
+    (3, 97, 150, 256, 3, 0),
+    (4, 64, 33, 64, 2, 1),      # 102 products
+    (4, 70, 40, 128, 3, 2),     # 115 products, near the LDS limit
+    (4, 50, 45, 128, 4, 3),     # 126 products: the three-kernel path
+]
+# (group, modulus) products whose t-bytes the fused kernel keeps in LDS
+FUSED_MAX_PRODUCTS = 120
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("case", FUSED_CASES, ids=lambda c: "nc{}-{}x{}x{}-S{}-E{}".format(*c))
+def test_gemm_fused_bit_exact(case, mode):
+    """The fused (S4)-(S6) kernel (t-values of a 32 x 32 tile kept in LDS)
+    against the oracle's product, ragged tiles included."""
+    import paper_2609_29554_amd as Z
+    nc, M, N, K, S_f, E = case
+    note(f"fused gemm {case} mode {mode}")
+    A, B, C0 = _operands(nc, M, N, K, 300 + M + N + K)
+    pl = O.make_plan(53 * nc, K, nslice=S_f, extra_groups=E)
+    start = C0 if mode else np.zeros((N, M, nc))
+    want, _ = O.ozgemm(mode, A, B, start, pl)
+    dA, dB, dC = to_dev(A), to_dev(B), to_dev(start)
+    c = ctx()
+    c.set_profiling(True)
+    try:
+        c.gemm(mode, dA, dB, dC, Z.make_opts(nslice=S_f, extra_groups=E, flags=Z.F_FUSED))
+        c.sync_check()
+        launches = c.profile_read()["fused"][1]
+    finally:
+        c.set_profiling(False)
+    assert np.array_equal(to_host(dC), want)
+    # the fused kernel runs whenever the plan's t-bytes fit its LDS tile,
+    # the three-kernel path otherwise
+    assert (launches > 0) == (len(pl.groups) * pl.nmod <= FUSED_MAX_PRODUCTS)
+
+
+@pytest.mark.parametrize("lookahead", [True, False])
+@pytest.mark.parametrize("case", [(4, 100, 32, "lotkin"), (2, 130, 64, "random"),
+                                  (4, 260, 128, "graded")],
+                         ids=lambda c: "nc{}-n{}-b{}-{}".format(*c))
+def test_getrf_fused_bit_exact(case, lookahead):
+    import paper_2609_29554_amd as Z
+    nc, n, b, kind = case
+    note(f"getrf fused {case} lookahead={lookahead}")
+    A = _matrix(nc, n, kind, 11 + n)
+    LU, ipiv, info, _ = O.getrf(A, b, O.METHOD_OZAKI)
+    flags = Z.F_FUSED | (0 if lookahead else Z.F_NO_LOOKAHEAD)
+    dA = to_dev(A)
+    dip, dinfo = ctx().getrf(dA, block=b, opts=Z.make_opts(flags=flags))
+    ctx().sync_check()
+    assert int(to_host(dinfo)[0]) == info
+    assert np.array_equal(to_host(dip), ipiv)
+    assert np.array_equal(to_host(dA), LU)
