@@ -196,9 +196,10 @@ def main():
     ap.add_argument("--no-native", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probes", action="store_true",
-                    help="skip the batched-LU and limb-LU probes of the default line")
+                    help="skip the batched-LU, limb-LU and limb back-end probes of the default line")
     ap.add_argument("--cpu-sample-n", type=int, default=2048)
-    ap.add_argument("--workload", choices=["lu", "gemm", "schur", "batch", "limb-schur", "limb-lu"],
+    ap.add_argument("--workload", choices=["lu", "gemm", "schur", "batch", "limb-schur", "limb-lu",
+                                           "limb-gemm"],
                     default="lu",
                     help="lu: QD Lotkin LU (default); gemm: standalone TD product m=n=k=4096; "
                          "schur: only the LU's Ozaki-II Schur-update products (for profiling); "
@@ -206,7 +207,8 @@ def main():
                          "limb-schur: the Schur-update products of the Lotkin LU n=2048, "
                          "b=256 at p=4096 (64-limb numbers); limb-lu: the whole Lotkin LU + "
                          "solve on limb numbers (--limb-n, --limb-p, --limb-block; Table lotkin: "
-                         "n=512, p=3136, b=256)")
+                         "n=512, p=3136, b=256); limb-gemm: the limb product n=512 on the INT8 "
+                         "and binary64 back-ends over p (--sweep-p; Table backend_hp)")
     ap.add_argument("--limb-n", type=int, default=512)
     ap.add_argument("--limb-p", type=int, default=3136)
     ap.add_argument("--limb-block", type=int, default=256)
@@ -216,6 +218,9 @@ def main():
     ap.add_argument("--limb-native", choices=["auto", "yes", "no"], default="auto",
                     help="also time the native limb LU (blocked and unblocked); auto: n <= 1024")
     ap.add_argument("--nlimb", type=int, default=64)
+    ap.add_argument("--sweep-p", default="1024,2048,4096,8192,16384",
+                    help="precisions of the limb-gemm back-end sweep")
+    ap.add_argument("--limb-gemm-n", type=int, default=512)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--gemm-n", type=int, default=4096)
     ap.add_argument("--gemm-backend", choices=["int8", "fp8", "f64", "fp16"], default="int8")
@@ -264,6 +269,8 @@ def main():
         return bench_limb_schur(args)
     if args.workload == "limb-lu":
         return bench_limb_lu(args)
+    if args.workload == "limb-gemm":
+        return bench_limb_gemm(args)
 
     n, nc, b = args.n, args.nc, args.block
     log(f"generating Lotkin n={n} nc={nc}")
@@ -399,12 +406,15 @@ def main():
                                   "5.1 n, Sec. 4.3): no correct bit is expected"}
     sweep = backend_sweep(ctx, args) if args.sweep_n > 0 else None
     td_gemm = td_gemm_probe(args.gemm_n) if args.gemm_n > 0 else None
-    batch = limb = None
+    batch = limb = limb_gemm = None
     if not args.no_probes:
         log("batch probe")
         batch = batch_probe(args)
         log("limb LU probe (Table lotkin point)")
         limb = limb_lu_measure(512, 3136, 256, args.limb_leaf, 2, 1, "yes")
+        log("limb product back-end sweep (Table backend_hp)")
+        limb_gemm = limb_gemm_sweep(ctx, args.limb_gemm_n,
+                                    [int(x) for x in args.sweep_p.split(",") if x], 2)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -450,6 +460,7 @@ def main():
         "backend_sweep": sweep,
         "batch256": batch,
         "limb_lu_lotkin512_p3136": limb,
+        "limb_gemm_backend_sweep": limb_gemm,
     }
     ctx.close()
     print(json.dumps(out))
@@ -896,6 +907,89 @@ def bench_limb_schur(args):
     if not args.no_cpu_baseline:
         log("cpu baseline (limb oracle sample)")
         out["cpu_baseline"] = limb_cpu_baseline(nl, shapes)
+    print(json.dumps(out))
+
+
+# Sec. 4.1.6, Table backend_hp, GPU block (H100): product of n = 512 limb
+# matrices, time [ms] on INT8 and on binary64 moduli, modulus counts
+PAPER_BACKEND_HP = {1024: (12.7, 7.4, 45, 15), 2048: (40.0, 22.6, 49, 16),
+                    4096: (132.8, 74.8, 54, 16), 8192: (511.5, 272.7, 53, 16),
+                    16384: (1900.8, 1046.5, 54, 16)}
+
+
+def limb_gemm_sweep(ctx, n, ps, steps):
+    """C = RN_p(A B) for random n x n limb matrices (exponents spread by
+    N(0, 4), 5 % zeros) at each p, on the INT8 and the binary64 back-ends:
+    HIP-event time per product, plan, modular-GEMM rate; returns a dict."""
+    import numpy as np
+    import torch
+
+    import paper_2609_29554_amd as Z
+    import workloads as W
+
+    rows = {}
+    for p in ps:
+        nl = p // 64
+        rng = np.random.default_rng(p)
+        dev = []
+        for _ in range(2):
+            limb, ex, sg = W.random_limbs(n, n, nl, rng, exp_sigma=4.0, zero_frac=0.05)
+            dev.append((torch.from_numpy(limb.view(np.int64)).cuda(), torch.from_numpy(ex).cuda(),
+                        torch.from_numpy(sg).cuda()))
+            del limb, ex, sg
+        dA, dB = dev
+        dC = tuple(torch.empty_like(x) for x in dA)
+        row = {"paper_h100_ms": {"int8": PAPER_BACKEND_HP.get(p, (None,) * 4)[0],
+                                 "f64": PAPER_BACKEND_HP.get(p, (None,) * 4)[1]},
+               "paper_moduli": {"int8": PAPER_BACKEND_HP.get(p, (None,) * 4)[2],
+                                "f64": PAPER_BACKEND_HP.get(p, (None,) * 4)[3]}}
+        for name, be in (("int8", Z.BE_INT8), ("f64", Z.BE_F64MOD)):
+            log(f"limb product n={n} p={p} {name}")
+            opts = Z.make_opts(backend=be)
+            ctx.gemm_limbs(0, dA, dB, dC, opts)       # warm: plan, workspace
+            ctx.sync_check()
+            ctx.set_profiling(True)
+            ctx.profile_read()
+            for _ in range(steps):
+                ctx.gemm_limbs(0, dA, dB, dC, opts)
+            ctx.sync_check()
+            prof = ctx.profile_read()
+            ctx.set_profiling(False)
+            total = sum(v[0] for v in prof.values()) / steps
+            gms, gl, _, gops = prof["gemm"]
+            S, w, Q, nmod, _ = Z.plan_query(p, n, opts)
+            ach = gops / (gms * 1e-3) / 1e12
+            row[name] = {"ms": total, "gemm_ms": gms / steps,
+                         "gemm_tops": ach, "gemm_frac": ach / PEAK_MFMA[name],
+                         "S": S, "w": w, "nmod": nmod,
+                         # (group, modulus) products: S (S + 1) / 2 slice pairs
+                         "products": nmod * S * (S + 1) // 2,
+                         "stages_ms": {k: v[0] / steps for k, v in prof.items() if v[1]}}
+        row["ratio_int8_over_f64"] = row["int8"]["ms"] / row["f64"]["ms"]
+        rows[p] = row
+        del dA, dB, dC, dev
+        torch.cuda.empty_cache()
+    return rows
+
+
+def bench_limb_gemm(args):
+    import torch
+
+    import paper_2609_29554_amd as Z
+
+    ps = [int(x) for x in args.sweep_p.split(",") if x]
+    ctx = Z.Context(0)
+    rows = limb_gemm_sweep(ctx, args.limb_gemm_n, ps, args.steps)
+    ctx.close()
+    top = rows[max(ps)]
+    best = min(top["int8"]["ms"], top["f64"]["ms"])
+    out = {"metric": "limb product n=512 on INT8 vs binary64 moduli over p (Table backend_hp)",
+           "value": best, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+           "ms_per_step": best, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u64 limbs+i8/f64", "data": "synthetic",
+           "config": {"workload": f"C = RN_p(A B), random n={args.limb_gemm_n} limb matrices, "
+                                  f"p = {ps}", "value_at_p": max(ps)},
+           "sweep": rows}
     print(json.dumps(out))
 
 

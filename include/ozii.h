@@ -163,7 +163,9 @@ ozII_status ozII_gemm_noalloc(ozII_handle h, int32_t mode, int32_t nc, int64_t M
 ozII_status ozII_gemm_noalloc_capacity(int64_t *bytes);
 
 /* Arbitrary-precision limb matrices (the MPFR-like input of Sec. 3.3 and
- * the p-bit results of (S6)), p = 64 nlimb bits, 1 <= nlimb <= 64:
+ * the p-bit results of (S6)), p = 64 nlimb bits, 1 <= nlimb <= 64 for the
+ * LU, its solve and the element arithmetic, up to OZII_GEMM_LIMBS_MAX for
+ * the product (p <= 16384, the range of Sec. 4.1.6's back-end comparison):
  *   x = (-1)^sign * (sum_q limb_q 2^(64 q)) * 2^(exp - p),
  * mantissa normalised (bit 63 of limb nlimb-1 set, i.e. x = 0.m 2^exp as
  * mpfr_get_exp reports it); zero has every limb 0 (on input exp and sign are
@@ -181,18 +183,22 @@ typedef struct {
   int64_t ld;
   int64_t plane;
 } ozII_limbs;
+#define OZII_GEMM_LIMBS_MAX 256
 
 /* Ozaki-II product on limb matrices, steps (S1)-(S6) of Sec. 3.1 with the
- * slices of Sec. 3.2 (the INT8 back-end only):
+ * slices of Sec. 3.2, on the INT8 back-end (default) or the binary64 moduli
+ * (o->backend = OZII_BE_F64MOD; Sec. 4.1.6 compares the two over p):
  *   mode 0: C = RN_p(A B),   mode 1: C = RN_p(C - RN_p(A B)),
  * RN_p: round to nearest, ties to even (MPFR's RNDN), applied once to the
  * exact integer result of (S5) and once to the update.  (S2) truncates:
  * X = sgn(x) trunc(|x| 2^mu) (mpfr_mul_2si then mpfr_get_z toward zero).
  * A is M x K, B is K x N, C is M x N; C must not overlap A or B.
- * Errors: OZII_EINVAL (bad sizes, null pointers, nlimb outside 1..64, ld or
- * plane too small), OZII_EUNSUPPORTED (a back-end other than INT8, or a plan
- * beyond the compiled sizes), OZII_ENOMEM.  Uses handle workspace of about
- * (M + N) K S N_mod + M N (ng N_mod + 4 * words) bytes. */
+ * Errors: OZII_EINVAL (bad sizes, null pointers, nlimb outside
+ * 1..OZII_GEMM_LIMBS_MAX, ld or plane too small), OZII_EUNSUPPORTED (a
+ * back-end other than INT8 or binary64 moduli, or a plan beyond the compiled
+ * sizes), OZII_ENOMEM.  Uses handle workspace of about (M + N) K S N_mod e +
+ * M N (ng N_mod t + 4 * words) bytes (e = 1, t = 1 on INT8; e = 8, t = 4 on
+ * the binary64 moduli). */
 ozII_status ozII_gemm_limbs(ozII_handle h, int32_t mode, int32_t nlimb, int64_t M, int64_t N,
                             int64_t K, const ozII_limbs *A, const ozII_limbs *B, ozII_limbs *C,
                             const ozII_opts *o);

@@ -322,11 +322,12 @@ class Context:
             self._h = _p()
         _LIVE.discard(self)
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # no HIP calls while the interpreter shuts down: the runtime (and a
         # profiler attached to it) may already be gone; close_all() has run
-        # by then for every handle that was still open
-        if sys.is_finalizing():
+        # by then for every handle that was still open.  The check is bound
+        # at definition time: module globals such as sys may already be None.
+        if _finalizing():
             return
         try:
             self.close()

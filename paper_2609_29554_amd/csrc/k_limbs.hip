@@ -86,7 +86,57 @@ __global__ __launch_bounds__(256) void k_limb_col_exp(const uint64_t *__restrict
 // (carry c_t, centring flag) is that of the expansion producer; a negative
 // X = ~|X| + 1 starts with c_0 = 1 and complemented windows.
 // ---------------------------------------------------------------------------
+// Binary64 moduli: the residues of slice t of the thread's four elements as
+// doubles, in the binary64 GEMM's fragment order (1 KiB blocks of 16 rows x
+// 8 k, lane l: row l%16, k l/16 and 4 + l/16; eight blocks per 64-k window;
+// off: each element's offset in a plane).  F and sel as for the byte
+// emitter: a lower slice has the value F - sel 2^w (F < 2^w), the top slice
+// is the nwt-word two's complement F with sign sel; its magnitude is reduced
+// and the residue negated.
 template <int NWM>
+__device__ __forceinline__ void emit_f64_residues(const uint32_t (&F)[4][NWM],
+                                                  const uint32_t (&sel)[4], bool top, int nwt,
+                                                  const DevPlan *__restrict__ pl, int nmod,
+                                                  double *pp, int64_t plane_elems,
+                                                  const int64_t (&off)[4]) {
+  constexpr int NH = 2 * NWM;
+  static_assert(NH <= NHMAX, "slice digits");
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    uint32_t mag[NWM];
+    const bool neg = top && sel[e] != 0;
+    uint32_t c = 1;
+#pragma unroll
+    for (int k = 0; k < NWM; ++k) {
+      if (top && k >= nwt) {
+        mag[k] = 0u;
+      } else if (neg) {
+        const uint32_t v = ~F[e][k];
+        mag[k] = v + c;
+        c = (c && mag[k] == 0u) ? 1u : 0u;
+      } else {
+        mag[k] = F[e][k];
+      }
+    }
+    uint32_t dig[NH];
+#pragma unroll
+    for (int k = 0; k < NH; ++k) dig[k] = (mag[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+    const bool flag = !top && sel[e] != 0;
+    for (int l = 0; l < nmod; ++l) {
+      const uint32_t m = (uint32_t)pl->m[l];
+      uint32_t r = digits_mod<NH, true>(dig, pl, l);
+      if (flag) {
+        r += m - pl->p2w[l];  // F - 2^w (mod m)
+        r = r >= m ? r - m : r;
+      } else if (neg) {
+        r = r == 0u ? 0u : m - r;
+      }
+      pp[(int64_t)l * plane_elems + off[e]] = (double)centre(r, (int32_t)m);
+    }
+  }
+}
+
+template <int NWM, bool F64>
 __global__ __launch_bounds__(256) void k_producer_limbs(
     const uint64_t *__restrict__ limb, const int32_t *__restrict__ lexp,
     const uint8_t *__restrict__ lsign, int64_t ld, int64_t plane, int nlimb, int rowwise,
@@ -194,8 +244,20 @@ __global__ __launch_bounds__(256) void k_producer_limbs(
         sel[e] = sg;
       }
     }
-    emit_byte_residues<NWM, false>(F, sel, top ? REC_HT : REC_HW, pl, nmod,
-                                   planes + (int64_t)t * nmod * plane_elems, plane_elems, offb);
+    if constexpr (F64) {
+      int64_t off[4];
+      const int r = (T >> 2) & 15;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int kk = 16 * (T >> 6) + 4 * (T & 3) + e, k8 = kk & 7;
+        off[e] = ((ob * KB + kb) * 8 + (kk >> 3)) * 128 + 2 * ((k8 & 3) * 16 + r) + (k8 >> 2);
+      }
+      emit_f64_residues<NWM>(F, sel, top, nwt, pl, nmod,
+                             (double *)planes + (int64_t)t * nmod * plane_elems, plane_elems, off);
+    } else {
+      emit_byte_residues<NWM, false>(F, sel, top ? REC_HT : REC_HW, pl, nmod,
+                                     planes + (int64_t)t * nmod * plane_elems, plane_elems, offb);
+    }
   }
 }
 
@@ -206,13 +268,13 @@ __global__ __launch_bounds__(256) void k_producer_limbs(
 // by fill) at word q0 = floor(w gi / 32).  After the last group the final
 // pend (0 or -1, the sign) is stored at word hw.
 // ---------------------------------------------------------------------------
-template <int NB>
-__global__ __launch_bounds__(256) void k_consumer_limbs(const uint8_t *__restrict__ tpl,
+template <int ND, class TT>
+__global__ __launch_bounds__(256) void k_consumer_limbs(const TT *__restrict__ tpl,
                                                         int64_t Mp, int64_t Np, int64_t M,
                                                         int64_t N, const DevPlan *__restrict__ pl,
                                                         int nvw, uint32_t *__restrict__ cw,
                                                         int64_t E) {
-  constexpr int ND = NB / 2, NV = ND / 2 + 1;
+  constexpr int NV = ND / 2 + 1;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t j = blockIdx.y;
   if (i >= M || j >= N) return;
@@ -225,7 +287,11 @@ __global__ __launch_bounds__(256) void k_consumer_limbs(const uint8_t *__restric
   int32_t pend = 0;
   for (int gi = 0; gi < ng; ++gi) {
     int32_t d[ND];
-    crt_group_bytes<NB>(tpl + ((int64_t)gi * nmod * Np + j) * Mp + i, ps, nmod, pl, d);
+    const TT *tg = tpl + ((int64_t)gi * nmod * Np + j) * Mp + i;
+    if constexpr (sizeof(TT) == 1)
+      crt_group_bytes<2 * ND>(tg, ps, nmod, pl, d);  // byte back-ends
+    else
+      crt_digits<ND, TT>(tg, ps, pl, d);              // binary64 moduli
     const uint32_t fill = d[ND - 1] < 0 ? 0xffffffffu : 0u;
     uint32_t st[ND / 2];
 #pragma unroll
@@ -509,43 +575,62 @@ hipError_t launch_limb_exponents(const uint64_t *limb, const int32_t *lexp, int6
   return hipGetLastError();
 }
 
+template <bool F64>
+static void producer_limbs_nw(int nwt, dim3 g, hipStream_t s, const uint64_t *limb,
+                              const int32_t *lexp, const uint8_t *lsign, int64_t ld,
+                              int64_t plane, int nlimb, int rowwise, int64_t nout, int64_t K,
+                              int64_t KB, const int32_t *exps, const DevPlan *pl, uint8_t *planes,
+                              int64_t plane_elems) {
+  if (nwt <= 4)
+    hipLaunchKernelGGL((k_producer_limbs<4, F64>), g, dim3(256), 0, s, limb, lexp, lsign, ld,
+                       plane, nlimb, rowwise, nout, K, KB, exps, pl, planes, plane_elems);
+  else if (nwt <= 6)
+    hipLaunchKernelGGL((k_producer_limbs<6, F64>), g, dim3(256), 0, s, limb, lexp, lsign, ld,
+                       plane, nlimb, rowwise, nout, K, KB, exps, pl, planes, plane_elems);
+  else
+    hipLaunchKernelGGL((k_producer_limbs<REC_PWMAX, F64>), g, dim3(256), 0, s, limb, lexp, lsign,
+                       ld, plane, nlimb, rowwise, nout, K, KB, exps, pl, planes, plane_elems);
+}
+
 hipError_t launch_producer_limbs(const uint64_t *limb, const int32_t *lexp, const uint8_t *lsign,
                                  int64_t ld, int64_t plane, int nlimb, int rowwise, int64_t nout,
                                  int64_t noutp, int64_t K, int64_t Kp, const int32_t *exps,
-                                 const DevPlan *pl, int nwt, uint8_t *planes, int64_t plane_elems,
-                                 hipStream_t s) {
+                                 const DevPlan *pl, int nwt, int kind, void *planes,
+                                 int64_t plane_elems, hipStream_t s) {
   const int64_t KB = Kp / 64, OB = noutp / 16;
   if (KB <= 0 || OB <= 0) return hipSuccess;
   if (plane_elems >= ((int64_t)1 << 31) || nwt > REC_PWMAX) return hipErrorInvalidValue;
+  if (kind != PLANES_I8 && kind != PLANES_F64) return hipErrorInvalidValue;
   dim3 g((unsigned)KB, (unsigned)OB);
-  if (nwt <= 4)
-    hipLaunchKernelGGL(k_producer_limbs<4>, g, dim3(256), 0, s, limb, lexp, lsign, ld, plane,
-                       nlimb, rowwise, nout, K, KB, exps, pl, planes, plane_elems);
-  else if (nwt <= 6)
-    hipLaunchKernelGGL(k_producer_limbs<6>, g, dim3(256), 0, s, limb, lexp, lsign, ld, plane,
-                       nlimb, rowwise, nout, K, KB, exps, pl, planes, plane_elems);
+  if (kind == PLANES_F64)
+    producer_limbs_nw<true>(nwt, g, s, limb, lexp, lsign, ld, plane, nlimb, rowwise, nout, K, KB,
+                            exps, pl, (uint8_t *)planes, plane_elems);
   else
-    hipLaunchKernelGGL(k_producer_limbs<REC_PWMAX>, g, dim3(256), 0, s, limb, lexp, lsign, ld,
-                       plane, nlimb, rowwise, nout, K, KB, exps, pl, planes, plane_elems);
+    producer_limbs_nw<false>(nwt, g, s, limb, lexp, lsign, ld, plane, nlimb, rowwise, nout, K, KB,
+                             exps, pl, (uint8_t *)planes, plane_elems);
   return hipGetLastError();
 }
 
-hipError_t launch_consumer_limbs(const uint8_t *tpl, int64_t Mp, int64_t Np, int64_t M, int64_t N,
-                                 const DevPlan *pl, int nd, int nvw, uint32_t *cw,
+hipError_t launch_consumer_limbs(const void *tpl, int tbytes, int64_t Mp, int64_t Np, int64_t M,
+                                 int64_t N, const DevPlan *pl, int nd, int nvw, uint32_t *cw,
                                  hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
   dim3 g((unsigned)((M + 255) / 256), (unsigned)N);
-  if (nd <= 18) {
-    if (nvw > 18 / 2 + 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_consumer_limbs<36>, g, dim3(256), 0, s, tpl, Mp, Np, M, N, pl, nvw, cw,
-                       M * N);
-  } else if (nd <= 24) {
-    if (nvw > 24 / 2 + 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_consumer_limbs<48>, g, dim3(256), 0, s, tpl, Mp, Np, M, N, pl, nvw, cw,
-                       M * N);
-  } else {
+  const int ndc = nd <= 18 ? 18 : (nd <= 24 ? 24 : 32);
+  if (nd > 32 || (tbytes == 1 && nd > 24) || (tbytes != 1 && tbytes != 4) ||
+      nvw > ndc / 2 + 1)
     return hipErrorInvalidValue;
+#define OZ_CONSL(ND_, TT_)                                                                       \
+  hipLaunchKernelGGL((k_consumer_limbs<ND_, TT_>), g, dim3(256), 0, s, (const TT_ *)tpl, Mp, Np, \
+                     M, N, pl, nvw, cw, M * N)
+  if (tbytes == 1) {
+    if (ndc == 18) OZ_CONSL(18, uint8_t);
+    else OZ_CONSL(24, uint8_t);
+  } else {
+    if (ndc == 18) OZ_CONSL(18, uint32_t);
+    else OZ_CONSL(32, uint32_t);
   }
+#undef OZ_CONSL
   return hipGetLastError();
 }
 

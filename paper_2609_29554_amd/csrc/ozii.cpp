@@ -419,7 +419,7 @@ ozII_status get_plan(ozII_ctx *h, int p, int64_t K, const ozII_opts *o, const Ho
     std::string why;
     ozII_status st = make_plan(p, K, o, pl, &why, !limbs);
     if (st != OZII_OK) return fail(h, st, "plan: " + why);
-    if (limbs && (pl.w > 300 || pl.nd > 24))
+    if (limbs && (pl.w > 300 || pl.nd > (pl.backend == OZII_BE_F64MOD ? ozk::NDCRT : 24)))
       return fail(h, OZII_EUNSUPPORTED, "plan: limb plan exceeds the compiled sizes");
     DevPlan host_dp;
     build_devplan(pl, host_dp);
@@ -759,10 +759,11 @@ ozII_status gemm_limbs_impl(ozII_ctx *h, int mode, int nlimb, int64_t M, int64_t
                             int nlimb_out = 0) {
   if (!h) return OZII_EINVAL;
   if (mode != 0 && mode != 1) return fail(h, OZII_EINVAL, "mode must be 0 or 1");
-  if (nlimb < 1 || nlimb > 64) return fail(h, OZII_EINVAL, "nlimb must be 1..64");
+  if (nlimb < 1 || nlimb > OZII_GEMM_LIMBS_MAX)
+    return fail(h, OZII_EINVAL, "nlimb must be 1..OZII_GEMM_LIMBS_MAX");
   if (M < 0 || N < 0 || K < 0) return fail(h, OZII_EINVAL, "negative size");
-  if (o && o->backend && o->backend != OZII_BE_INT8)
-    return fail(h, OZII_EUNSUPPORTED, "the limb format runs on the INT8 back-end only");
+  if (o && o->backend && o->backend != OZII_BE_INT8 && o->backend != OZII_BE_F64MOD)
+    return fail(h, OZII_EUNSUPPORTED, "the limb product runs on the INT8 or binary64 back-end");
   if (M == 0 || N == 0) return OZII_OK;
   if (!limbs_ok(C, M, N) || (K > 0 && (!limbs_ok(A, M, K) || !limbs_ok(B, K, N))))
     return fail(h, OZII_EINVAL, "bad limb matrix descriptor");
@@ -800,6 +801,7 @@ ozII_status gemm_limbs_impl(ozII_ctx *h, int mode, int nlimb, int64_t M, int64_t
   uint8_t *tpl = (uint8_t *)(h->ws + L.off_tpl);
   uint32_t *cw = (uint32_t *)(h->ws + off_cw);
   const int nwt = (hp->w + 2 + 31) / 32;
+  const bool f64 = hp->backend == OZII_BE_F64MOD;
   const double pairs = (double)hp->nmod * [&] {
     int np = 0;
     for (int g = hp->g0; g <= 2 * hp->S - 2; ++g)
@@ -808,7 +810,8 @@ ozII_status gemm_limbs_impl(ozII_ctx *h, int mode, int nlimb, int64_t M, int64_t
     return np;
   }();
   const double in_bytes = 8.0 * nlimb + 5.0;  // limbs, exponent and sign per element
-  const double res_bytes = (double)hp->S * hp->nmod, t_bytes = (double)hp->ng * hp->nmod;
+  const double res_bytes = (double)hp->S * hp->nmod * hp->el_bytes(),
+               t_bytes = (double)hp->ng * hp->nmod * hp->t_bytes();
   {
     ProfScope ps(h, OZ_STAGE_EXP, 12.0 * (double)(M * K + K * N), 0);
     if ((e = ozl::launch_limb_exponents(A->limb, A->exp, A->ld, A->plane, nlimb, M, K, 1, ea, s)) != hipSuccess)
@@ -819,30 +822,37 @@ ozII_status gemm_limbs_impl(ozII_ctx *h, int mode, int nlimb, int64_t M, int64_t
   {
     ProfScope ps(h, OZ_STAGE_PRODUCER, (double)M * K * (in_bytes + res_bytes), 0);
     if ((e = ozl::launch_producer_limbs(A->limb, A->exp, A->sign, A->ld, A->plane, nlimb, 1, M,
-                                        L.Mp, K, L.Kp, ea, dp, nwt, pa, L.planeA, s)) != hipSuccess)
+                                        L.Mp, K, L.Kp, ea, dp, nwt, hp->planes_kind(), pa,
+                                        L.planeA, s)) != hipSuccess)
       return hip_fail(h, e, "limb producer(A)");
   }
   {
     ProfScope ps(h, OZ_STAGE_PRODUCER, (double)N * K * (in_bytes + res_bytes), 0);
     if ((e = ozl::launch_producer_limbs(B->limb, B->exp, B->sign, B->ld, B->plane, nlimb, 0, N,
-                                        L.Np, K, L.Kp, eb, dp, nwt, pb, L.planeB, s)) != hipSuccess)
+                                        L.Np, K, L.Kp, eb, dp, nwt, hp->planes_kind(), pb,
+                                        L.planeB, s)) != hipSuccess)
       return hip_fail(h, e, "limb producer(B)");
   }
   {
     ProfScope ps(h, OZ_STAGE_GEMM, res_bytes * (double)(M + N) * K + t_bytes * M * N,
                  2.0 * (double)M * N * K * pairs);
-    if ((e = ozl::launch_gemm_i8((const int8_t *)pa, (const int8_t *)pb, tpl, dp, hp->ng, hp->nmod,
-                                 L.Mp, L.Np, L.Kp, L.planeA, L.planeB, o ? o->gemm_tile : 0, s)) != hipSuccess)
-      return hip_fail(h, e, "modular gemm");
+    if (f64)
+      e = ozl::launch_gemm_f64((const double *)pa, (const double *)pb, (uint32_t *)tpl, dp, hp->ng,
+                               hp->nmod, L.Mp, L.Np, L.Kp, L.planeA, L.planeB, s);
+    else
+      e = ozl::launch_gemm_i8((const int8_t *)pa, (const int8_t *)pb, tpl, dp, hp->ng, hp->nmod,
+                              L.Mp, L.Np, L.Kp, L.planeA, L.planeB, o ? o->gemm_tile : 0, s);
+    if (e != hipSuccess) return hip_fail(h, e, "modular gemm");
   }
-  if (sbar_out && (e = ozl::launch_crt_export(tpl, 1, hp->nd, L.Mp, L.Np, M, N, dp, sbar_out,
-                                              nlimb_out, s)) != hipSuccess)
+  if (sbar_out && (e = ozl::launch_crt_export(tpl, hp->t_bytes(), hp->nd, L.Mp, L.Np, M, N, dp,
+                                              sbar_out, nlimb_out, s)) != hipSuccess)
     return hip_fail(h, e, "crt_export");
   {
     // t-planes read once, each group's window of the sum read and written
     ProfScope ps(h, OZ_STAGE_CONSUMER,
                  (double)M * N * (t_bytes + 8.0 * nvw * hp->ng), 0);
-    if ((e = ozl::launch_consumer_limbs(tpl, L.Mp, L.Np, M, N, dp, hp->nd, nvw, cw, s)) != hipSuccess)
+    if ((e = ozl::launch_consumer_limbs(tpl, hp->t_bytes(), L.Mp, L.Np, M, N, dp, hp->nd, nvw, cw,
+                                        s)) != hipSuccess)
       return hip_fail(h, e, "limb consumer");
   }
   // rounding: the group-sum column read, the p-bit product written (to C, or

@@ -100,7 +100,7 @@ hipError_t launch_apply_ipiv(int nc, double *B, int64_t ldb, int64_t n, int64_t 
                              const int64_t *ipiv, hipStream_t s);
 hipError_t launch_fill_int(int *p, int v, int64_t cnt, hipStream_t s);
 
-// limb format (k_limbs.hip): exponents, producer (INT8 planes), consumer
+// limb format (k_limbs.hip): exponents, producer (INT8 or binary64 planes), consumer
 // (exact group sums as nwords-word columns, word k of element i + j M at
 // cw[k M N + i + j M]), the rounding of those sums into a limb matrix, the
 // update C = RN_p(C - T) (T: M x N limb matrix with ld M, plane M N; dw:
@@ -108,13 +108,16 @@ hipError_t launch_fill_int(int *p, int v, int64_t cnt, hipStream_t s);
 hipError_t launch_limb_exponents(const uint64_t *limb, const int32_t *lexp, int64_t ld,
                                  int64_t plane, int nlimb, int64_t rows, int64_t cols,
                                  int rowwise, int32_t *e, hipStream_t s);
+// kind: PLANES_I8 (byte residues) or PLANES_F64 (binary64 moduli);
+// tbytes: 1 (byte t-planes) or 4 (binary64 moduli)
 hipError_t launch_producer_limbs(const uint64_t *limb, const int32_t *lexp, const uint8_t *lsign,
                                  int64_t ld, int64_t plane, int nlimb, int rowwise, int64_t nout,
                                  int64_t noutp, int64_t K, int64_t Kp, const int32_t *exps,
-                                 const DevPlan *pl, int nwt, uint8_t *planes, int64_t plane_elems,
+                                 const DevPlan *pl, int nwt, int kind, void *planes,
+                                 int64_t plane_elems, hipStream_t s);
+hipError_t launch_consumer_limbs(const void *tpl, int tbytes, int64_t Mp, int64_t Np, int64_t M,
+                                 int64_t N, const DevPlan *pl, int nd, int nvw, uint32_t *cw,
                                  hipStream_t s);
-hipError_t launch_consumer_limbs(const uint8_t *tpl, int64_t Mp, int64_t Np, int64_t M, int64_t N,
-                                 const DevPlan *pl, int nd, int nvw, uint32_t *cw, hipStream_t s);
 hipError_t launch_limb_round(const uint32_t *cw, int nwords, int64_t M, int64_t N,
                              const int32_t *ea, const int32_t *eb, int w, int g0, int Q, int nlimb,
                              uint64_t *olimb, int32_t *oexp, uint8_t *osign, int64_t ldo,

@@ -181,3 +181,77 @@ def test_gemm_limbs_group_sums_bit_exact(nl, M, N, K, E, seed):
                 assert O.limbs_to_int(got[g, j, i]) == sums[g][j][i], (g, i, j)
     for g_, w_ in zip(_host(dC), want):
         assert np.array_equal(g_, w_)
+
+
+@pytest.mark.parametrize("nl,M,N,K,mode,seed", [
+    (1, 16, 16, 16, 0, 31),
+    (2, 37, 29, 40, 1, 32),
+    (2, 130, 3, 130, 0, 33),    # two 128-row GEMM tiles, a ragged tail
+    (8, 5, 9, 64, 1, 34),
+    (64, 9, 7, 20, 0, 35),      # p = 4096: 20 slices, 20 moduli
+    (64, 33, 5, 65, 1, 36),
+])
+def test_gemm_limbs_f64_bit_exact(nl, M, N, K, mode, seed):
+    """The limb product on the binary64 moduli (the back-end comparison of
+    Sec. 4.1.6): residues as doubles, FP64 MFMA, 32-bit t-values, the CRT of
+    the binary64 consumer, then the same group sums and RN_p as on INT8."""
+    import paper_2609_29554_amd as Z
+    note(f"gemm_limbs binary64 nl={nl} {M}x{N}x{K} mode={mode}")
+    A, B, C0 = _case(nl, M, N, K, mode, seed)
+    pl = O.make_plan(64 * nl, K, backend=O.BACKEND_F64MOD)
+    want, _ = OL.ozgemm(mode, A, B, C0, pl)
+    dA, dB, dC = _dev(A), _dev(B), _dev(C0)
+    ctx().gemm_limbs(mode, dA, dB, dC, Z.make_opts(backend=Z.BE_F64MOD))
+    ctx().sync_check()
+    got = _host(dC)
+    for g, w_, name in zip(got, want, ("limbs", "exp", "sign")):
+        assert np.array_equal(g, w_), name
+
+
+@pytest.mark.parametrize("nl,M,N,K,mode,backend,seed", [
+    (128, 5, 4, 9, 0, "int8", 41),      # p = 8192: 48 slices, 53 moduli
+    (128, 6, 3, 9, 1, "f64", 42),
+    (256, 4, 5, 9, 1, "int8", 43),      # p = 16384: 95 slices, 54 moduli
+    (256, 3, 4, 20, 0, "f64", 44),
+])
+def test_gemm_limbs_wide_precision_bit_exact(nl, M, N, K, mode, backend, seed):
+    """p = 8192 and 16384 (the top of Sec. 4.1.6's sweep) on both back-ends."""
+    import paper_2609_29554_amd as Z
+    note(f"gemm_limbs nl={nl} {M}x{N}x{K} mode={mode} {backend}")
+    A, B, C0 = _case(nl, M, N, K, mode, seed)
+    obe, zbe = (O.BACKEND_INT8, Z.BE_INT8) if backend == "int8" else (O.BACKEND_F64MOD, Z.BE_F64MOD)
+    pl = O.make_plan(64 * nl, K, backend=obe)
+    want, _ = OL.ozgemm(mode, A, B, C0, pl)
+    dA, dB, dC = _dev(A), _dev(B), _dev(C0)
+    ctx().gemm_limbs(mode, dA, dB, dC, Z.make_opts(backend=zbe))
+    ctx().sync_check()
+    got = _host(dC)
+    for g, w_, name in zip(got, want, ("limbs", "exp", "sign")):
+        assert np.array_equal(g, w_), name
+
+
+@pytest.mark.parametrize("nl,M,N,K,seed", [(4, 20, 17, 40, 51), (2, 130, 3, 70, 52)])
+def test_gemm_limbs_f64_group_sums_bit_exact(nl, M, N, K, seed):
+    """(S5) on the binary64 moduli: the group sums the limb consumer's CRT
+    forms from 32-bit t-values, exported, against the oracle's."""
+    import paper_2609_29554_amd as Z
+    note(f"gemm_limbs binary64 group sums nl={nl} {M}x{N}x{K}")
+    A, B, C0 = _case(nl, M, N, K, 1, seed)
+    pl = O.make_plan(64 * nl, K, backend=O.BACKEND_F64MOD)
+    assert pl.P.bit_length() < 6 * 64   # the exported limbs hold every sum
+    _, _, sums = OL.group_sums(A, B, pl)
+    dA, dB, dC = _dev(A), _dev(B), _dev(C0)
+    sb = ctx().gemm_limbs_stages(1, dA, dB, dC, Z.make_opts(backend=Z.BE_F64MOD), nlimb_out=6)
+    ctx().sync_check()
+    got = to_host(sb).view(np.uint64)
+    for g in range(len(pl.groups)):
+        for j in range(N):
+            for i in range(M):
+                assert O.limbs_to_int(got[g, j, i]) == sums[g][j][i], (g, i, j)
+
+
+def test_gemm_limbs_rejects_limb_counts_beyond_the_product_range():
+    import paper_2609_29554_amd as Z
+    A, B, C0 = _case(257, 2, 2, 2, 0, 61)
+    with pytest.raises(Z.OziiError):
+        ctx().gemm_limbs(0, _dev(A), _dev(B), _dev(C0))
