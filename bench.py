@@ -135,7 +135,7 @@ PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 # for these stages)
 STAGE_KERNELS = {"producer": ("k_producer_b", "k_producer", "k_producer_limbs"),
                  "gemm": ("k_gemm_i8_p", "k_gemm_i8", "k_gemm_f8", "k_gemm_f64"),
-                 "consumer": ("k_consumer_b", "k_consumer", "k_consumer_limbs"),
+                 "consumer": ("k_consumer_mx", "k_consumer_b", "k_consumer", "k_consumer_limbs"),
                  "round": ("k_limb_round", "k_limb_sub")}
 
 

@@ -865,29 +865,120 @@ __global__ __launch_bounds__(256) void k_consumer(const TT *__restrict__ tpl, in
 }
 
 // ---------------------------------------------------------------------------
-// (S5)+(S6) consumer of the byte back-ends (t-values < 256): per element
-// and digit group the CRT of crt_group_bytes, then the group is added at bit
-// w gi to the group sum, which is rounded once as in consume_element.
+// (S5)+(S6) consumer of the byte back-ends with the CRT's column sums on the
+// matrix cores.  One wavefront (a workgroup of its own) takes 64 consecutive
+// elements of a column.  Per digit group the t-bytes of its elements go to
+// LDS one element row at a time (t - 128 as signed bytes); four 16-element
+// blocks of them are the B operands of v_mfma_i32_16x16x64_i8 against the
+// plan's column table (DevPlan::crtm, three A operands held in registers:
+// f_l and the 46 bytes that M_l < 2^363 can have), which gives
+// sum_l (t_l - 128) b_jl for every table column j.  Through LDS, 32 elements
+// at a time, each lane collects its own element's columns, adds crtc, and
+// forms the 16-bit digits of Sbar as crt_group_bytes does (the same exact
+// integer, so the same digits).  The group shift, rounding and update are
+// those of consume_element_b.  6.5 KiB of LDS per wavefront.
 // ---------------------------------------------------------------------------
+constexpr int MX_TBS = 80;   // bytes per element row of the t-bytes (conflict-free reads)
+constexpr int MX_BLK = 3;    // 16-column blocks of the table: f_l, then bytes 0..45 of M_l
+constexpr int MX_CBS = 16 * MX_BLK + 4;  // ints per element row of the column sums
+static_assert(2 + 46 == 16 * MX_BLK, "table columns");
+
 template <int NC, int NWC, int NB>
-__global__ __launch_bounds__(256) void k_consumer_b(const uint8_t *__restrict__ tpl, int64_t Mp,
+__global__ __launch_bounds__(64) void k_consumer_mx(const uint8_t *__restrict__ tpl, int64_t Mp,
                                                     int64_t Np, double *__restrict__ C,
                                                     int64_t ldc, int64_t M, int64_t N,
                                                     const int32_t *__restrict__ ea,
                                                     const int32_t *__restrict__ eb,
                                                     const DevPlan *__restrict__ pl, int mode) {
-  __shared__ uint32_t stage[256 * CST];
-  uint32_t *st = stage + threadIdx.x * CST;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  constexpr int ND = NB / 2, STG = stage_words<ND>();
+  static_assert(64 * MX_TBS <= 32 * MX_CBS * 4 && 64 * STG <= 32 * MX_CBS, "LDS reuse");
+  // the t-byte rows, then the column sums of 32 elements, then the digit
+  // staging of add_shifted_digits share one buffer
+  __shared__ __attribute__((aligned(16))) int32_t buf[32 * MX_CBS];
+  uint8_t *tb = (uint8_t *)buf;
+  const int lane = (int)threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * 64, i = i0 + lane;
   const int64_t j = blockIdx.y;
-  if (i >= M || j >= N) return;
-  const int Q = pl->Q;
-  const int32_t ei = ea[i], ej = eb[j];
+  const int nmod = pl->nmod, w = pl->w, ng = pl->ng, Q = pl->Q;
+  v4i tab[MX_BLK];
+#pragma unroll
+  for (int b = 0; b < MX_BLK; ++b) tab[b] = *(const v4i *)&pl->crtm[b][lane][0];
+  const bool valid = i < M;
+  const int32_t ej = eb[j], ei = valid ? ea[i] : EXP_ZERO;
   const bool zero = ei == EXP_ZERO || ej == EXP_ZERO;
-  const int eps = zero ? 0 : pl->w * pl->g0 - (Q - 1 - ei) - (Q - 1 - ej);
+  const int eps = zero ? 0 : w * pl->g0 - (Q - 1 - ei) - (Q - 1 - ej);
+  const int64_t ps = Np * Mp;
+  const int nch = (nmod + 3) >> 2;
+  const int e4 = 4 * (lane & 15), lq = lane >> 4;
+  uint32_t *st = (uint32_t *)buf + lane * STG;
+  uint32_t cb[NWC];
+#pragma unroll
+  for (int k = 0; k < NWC; ++k) cb[k] = 0u;
+  for (int gi = 0; gi < ng; ++gi) {
+    // lane: moduli 4c + lq, elements e4 .. e4 + 3 (one dword of a plane);
+    // moduli past nmod read the last plane again, their table columns are 0
+    const uint8_t *tg = tpl + (int64_t)gi * nmod * ps + j * Mp + i0 + e4;
+    const uint8_t *src = tg + (int64_t)lq * ps, *last = tg + (int64_t)(nmod - 1) * ps;
+    for (int c = 0; c < nch; ++c, src += 4 * ps) {
+      const int l = 4 * c + lq;
+      const uint32_t v = *(const uint32_t *)(l < nmod ? src : last) ^ 0x80808080u;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) tb[(e4 + r) * MX_TBS + l] = (uint8_t)(v >> (8 * r));
+    }
+    __syncthreads();
+    v4i bf[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      bf[e] = *(const v4i *)(tb + (16 * e + (lane & 15)) * MX_TBS + 16 * lq);
+    __syncthreads();
+    int32_t col[52];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int e = 2 * h; e < 2 * h + 2; ++e)
+#pragma unroll
+        for (int b = 0; b < MX_BLK; ++b) {
+          const v4i acc =
+              __builtin_amdgcn_mfma_i32_16x16x64_i8(tab[b], bf[e], v4i{0, 0, 0, 0}, 0, 0, 0);
+          *(v4i *)(buf + (16 * (e - 2 * h) + (lane & 15)) * MX_CBS + 16 * b + 4 * lq) = acc;
+        }
+      __syncthreads();
+      if ((lane >> 5) == h) {
+#pragma unroll
+        for (int q = 0; q < 4 * MX_BLK; ++q) {
+          const v4i v = *(const v4i *)(buf + (lane & 31) * MX_CBS + 4 * q);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) col[4 * q + r] = v[r] + pl->crtc[4 * q + r];
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int k = 16 * MX_BLK; k < 52; ++k) col[k] = 0;  // bytes 46, 47 of every M_l are 0
+    // F = (sum_l t_l f_l) / 2^16 from columns 0, 1; then as crt_group_bytes
+    const int32_t qf = (col[0] + col[1] * 256 + 32768) >> 16;
+    int32_t d[ND];
+    int32_t carry = 0;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+      const int32_t lo = col[2 + 2 * k] - qf * (pl->pbyte[2 * k] & 0xff);
+      const int32_t hi = col[3 + 2 * k] - qf * (pl->pbyte[2 * k + 1] & 0xff);
+      const int32_t v = lo + (int32_t)((uint32_t)hi << 8) + carry;
+      d[k] = v & 0xffff;
+      carry = v >> 16;  // arithmetic
+    }
+    d[ND - 1] = (int32_t)(int16_t)(uint16_t)d[ND - 1];
+    add_shifted_digits<NWC, ND, STG>(cb, d, w * gi, st);
+    __syncthreads();  // the buffer takes the next group's t-bytes
+  }
+  if (!valid) return;
   double c[NC];
-  // consecutive moduli Np Mp bytes apart
-  consume_element_b<NC, NWC, NB>(tpl + j * Mp + i, Np * Mp, pl, st, zero, eps, c);
+  if (zero) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) c[q] = 0.0;
+  } else {
+    round_out_n<NWC, NC>(cb, eps, c);
+  }
   double *dst = C + (i + j * ldc) * NC;
   if (mode == 0) {
     ozx::store<NC>(dst, c);
@@ -911,7 +1002,7 @@ __global__ __launch_bounds__(256) void k_consumer_b(const uint8_t *__restrict__ 
 // epilogue into LDS ([gl][column][row], 1 KiB per product).  After one
 // barrier every thread takes two elements through the consumer's CRT,
 // rounding and update (consume_element_b reading its bytes from LDS), so
-// the results equal those of k_gemm_i8 + k_consumer_b bit for bit.
+// the results equal those of k_gemm_i8 + k_consumer_mx bit for bit.
 constexpr int FUSE_T = 32;        // tile edge
 constexpr int FUSE_MAXPROD = 120;  // (group, modulus) products whose t-bytes fit in LDS
 constexpr int FUSE_LDS_MAX = 160 * 1024;
@@ -1038,7 +1129,8 @@ __global__ __launch_bounds__(256) void k_crt_export(const TT *__restrict__ tpl, 
 }
 
 // byte back-ends (INT8, FP8): the group sums of crt_group_bytes<NB>, the
-// CRT that k_consumer_b and k_consumer_limbs run, with the same NB
+// CRT that k_consumer_limbs and the fused kernel run (k_consumer_mx forms
+// the same digits on the matrix cores), with the same NB
 template <int NB>
 __global__ __launch_bounds__(256) void k_crt_export_b(const uint8_t *__restrict__ tpl, int64_t Mp,
                                                       int64_t Np, int64_t M, int64_t N,
@@ -1239,25 +1331,35 @@ hipError_t launch_consumer(int nc, int nwc, int nd, const void *tpl, int tbytes,
 #define OZ_CONS(NC_, NWC_, ND_, TT_)                                                            \
   hipLaunchKernelGGL((k_consumer<NC_, NWC_, ND_, TT_>), g, dim3(256), 0, s, (const TT_ *)tpl, Mp, \
                      Np, C, ldc, M, N, ea, eb, pl, mode)
-#define OZ_CONSB(NC_, NWC_, NB_)                                                        \
-  hipLaunchKernelGGL((k_consumer_b<NC_, NWC_, NB_>), g, dim3(256), 0, s, (const uint8_t *)tpl, \
-                     Mp, Np, C, ldc, M, N, ea, eb, pl, mode)
-#define OZ_CONS_ND(NC_, NWC_)                                  \
-  do {                                                        \
-    if (tbytes == 1) {                                        \
-      if (nd <= 18) OZ_CONSB(NC_, NWC_, 36);                  \
-      else OZ_CONSB(NC_, NWC_, 48);                           \
-    } else {                                                  \
-      if (nd <= 18) OZ_CONS(NC_, NWC_, 18, uint32_t);         \
-      else OZ_CONS(NC_, NWC_, 32, uint32_t);                  \
-    }                                                         \
+#define OZ_CONS_ND(NC_, NWC_)                            \
+  do {                                                  \
+    if (nd <= 18) OZ_CONS(NC_, NWC_, 18, uint32_t);     \
+    else OZ_CONS(NC_, NWC_, 32, uint32_t);              \
   } while (0)
   if ((tbytes == 1 && nd > 24) || nd > 32) return hipErrorInvalidValue;
+  if (tbytes == 1) {
+    // the matrix-core CRT: 64-element wavefronts read whole plane rows
+    if ((M + 63) / 64 * 64 > Mp) return hipErrorInvalidValue;
+    dim3 gx((unsigned)((M + 63) / 64), (unsigned)N);
+#define OZ_CONSX(NC_, NWC_, NB_)                                                                \
+  hipLaunchKernelGGL((k_consumer_mx<NC_, NWC_, NB_>), gx, dim3(64), 0, s, (const uint8_t *)tpl, \
+                     Mp, Np, C, ldc, M, N, ea, eb, pl, mode)
+#define OZ_CONSX_ND(NC_, NWC_)                 \
+  do {                                        \
+    if (nd <= 18) OZ_CONSX(NC_, NWC_, 36);    \
+    else OZ_CONSX(NC_, NWC_, 48);             \
+  } while (0)
+    if (nc == 2) { if (nwc <= 12) OZ_CONSX_ND(2, 12); else OZ_CONSX_ND(2, 16); }
+    else if (nc == 3) { if (nwc <= 12) OZ_CONSX_ND(3, 12); else OZ_CONSX_ND(3, 16); }
+    else { if (nwc <= 12) OZ_CONSX_ND(4, 12); else OZ_CONSX_ND(4, 16); }
+#undef OZ_CONSX_ND
+#undef OZ_CONSX
+    return hipGetLastError();
+  }
   if (nc == 2) { if (nwc <= 12) OZ_CONS_ND(2, 12); else OZ_CONS_ND(2, 16); }
   else if (nc == 3) { if (nwc <= 12) OZ_CONS_ND(3, 12); else OZ_CONS_ND(3, 16); }
   else { if (nwc <= 12) OZ_CONS_ND(4, 12); else OZ_CONS_ND(4, 16); }
 #undef OZ_CONS_ND
-#undef OZ_CONSB
 #undef OZ_CONS
   return hipGetLastError();
 }

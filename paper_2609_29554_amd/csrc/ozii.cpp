@@ -307,6 +307,30 @@ void build_devplan(const HostPlan &hp, DevPlan &dp) {
     }
     for (int b = 0; b < ozk::CRT4_NB; ++b)
       dp.pbyte[b] = (int32_t)((big_digit16(P, b / 2) >> (8 * (b % 2))) & 0xffu);
+    // the matrix-core form of the same table (DevPlan::crtm, crtc): f_l and
+    // M_l in balanced bytes; M_l < P < 2^363 (at most 54 moduli <= 256)
+    // leaves bytes 46 and 47 zero
+    for (int l = 0; l < hp.nmod; ++l) {
+      const uint32_t m = (uint32_t)hp.mods[l];
+      Big Ml{1};
+      for (int k = 0; k < hp.nmod; ++k)
+        if (k != l) big_mul_small(Ml, (uint32_t)hp.mods[k]);
+      int32_t col[64] = {0};
+      const int32_t f = (int32_t)((65536u + m / 2) / m), fh = (f + 128) >> 8;
+      col[0] = f - 256 * fh;
+      col[1] = fh;
+      int32_t carry = 0;
+      for (int b = 0; b < ozk::CRT4_NB; ++b) {
+        int32_t v = (int32_t)((big_digit16(Ml, b / 2) >> (8 * (b % 2))) & 0xffu) + carry;
+        carry = v >= 128 ? 1 : 0;
+        col[2 + b] = v - 256 * carry;
+      }
+      // columns 48, 49 (bytes 46, 47) are 0 for every M_l < 2^363
+      for (int j = 0; j < 48; ++j) {
+        dp.crtm[j / 16][16 * (l / 16) + j % 16][l % 16] = (int8_t)col[j];
+        dp.crtc[j] += 128 * col[j];
+      }
+    }
   }
 }
 

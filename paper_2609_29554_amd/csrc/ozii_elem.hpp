@@ -42,6 +42,16 @@ struct DevPlan {
   // (zero for moduli beyond nmod).  pbyte: the bytes of P.
   uint32_t crt4[MAXMOD / 4][50];
   int32_t pbyte[48];
+  // The same CRT on the matrix cores: table column j of modulus l is f_l's
+  // low (j = 0) or high (j = 1) balanced byte, or balanced byte j - 2 of M_l
+  // (j < 48; balanced bytes lie in [-128, 127], so sum_j b_j 2^(8 (j-2))
+  // is M_l exactly: bytes 46, 47 of M_l < 2^363 are 0).  crtm holds the columns as the A operand of
+  // v_mfma_i32_16x16x64_i8, one 1 KiB block per 16 columns: lane L owns
+  // column 16 blk + L % 16 for moduli 16 (L / 16) .. + 15 (zero beyond
+  // nmod).  The t-values enter as t - 128; crtc[j] = 128 sum_l (column j of
+  // modulus l) restores sum_l t_l b_jl.
+  int8_t crtm[3][64][16];
+  int32_t crtc[48];
 };
 constexpr int CRT4_NB = 48, CRT4_W = 50;
 constexpr int REC_H = 10, REC_HW = 11, REC_HT = 12, REC_MAGIC = 13, REC_M = 14, REC_K = 15;

@@ -16,7 +16,9 @@ def test_traffic_summaries_parse_and_gate_on_source():
         assert s is not None and s["kernels"]
         assert 1.5 < s["fetch_factor"] < 2.5 and 0.5 < s["write_factor"] < 1.5
         stage = "consumer"
-        fam = "k_consumer_limbs" if "limb" in name else "k_consumer_b"
+        fams = [f for f in bench.STAGE_KERNELS[stage] if f in s["kernels"]]
+        assert fams, name
+        fam = fams[0]
         t = bench.traffic_of(stage, name)
         if s["kernel_source_sha256"] == pmc.source_sha():
             assert abs(t - s["kernels"][fam]["hbm_bytes_per_launch"]) <= 1e-9 * t and t > 0
