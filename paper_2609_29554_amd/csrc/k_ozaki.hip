@@ -200,9 +200,12 @@ __global__ __launch_bounds__(256) void k_gemm_i8(const int8_t *__restrict__ pa,
   const int lt = (xcd < rm ? xcd * (qd + 1) : rm * (qd + 1) + (xcd - rm) * qd) + loc;
   const int tn = lt % tilesN;
   const int tm = (lt / tilesN) % tilesM;
-  const int gl = lt / (tilesN * tilesM);
+  const int pr = lt / (tilesN * tilesM);
   const int nmod = pl->nmod;
-  const int l = gl % nmod, gi = gl / nmod;
+  // products in modulus-major order: neighbouring groups of one modulus share
+  // most of their slice planes; gl is the product's t-plane
+  const int gi = pr % pl->ng, l = pr / pl->ng;
+  const int gl = gi * nmod + l;
   const int S = pl->S, g = pl->g0 + gi;
   const int ta0 = g - (S - 1) > 0 ? g - (S - 1) : 0;
   const int ta1 = g < S - 1 ? g : S - 1;
@@ -348,13 +351,16 @@ __global__ __launch_bounds__(64 * WMW * WNW) void k_gemm_i8_p(
   const int qd = nb >> 3, rm = nb & 7;
   const int lt = (xcd < rm ? xcd * (qd + 1) : rm * (qd + 1) + (xcd - rm) * qd) + loc;
   const int per = tilesM * tilesN;
-  const int gl = lt / per, r = lt - gl * per;
+  const int pr = lt / per, r = lt - pr * per;
   const int grp = r / (GL_GM * tilesN), r2 = r - grp * (GL_GM * tilesN);
   const int tm0 = grp * GL_GM;
   const int gh = tilesM - tm0 < GL_GM ? tilesM - tm0 : GL_GM;
   const int tm = tm0 + r2 % gh, tn = r2 / gh;
   const int nmod = pl->nmod;
-  const int l = gl % nmod, gi = gl / nmod;
+  // products in modulus-major order: neighbouring groups of one modulus share
+  // most of their slice planes; gl is the product's t-plane
+  const int gi = pr % pl->ng, l = pr / pl->ng;
+  const int gl = gi * nmod + l;
   const int S = pl->S, g = pl->g0 + gi;
   const int ta0 = g - (S - 1) > 0 ? g - (S - 1) : 0;
   const int ta1 = g < S - 1 ? g : S - 1;
@@ -561,9 +567,12 @@ __global__ __launch_bounds__(256) void k_gemm_f16(const int8_t *__restrict__ pa,
   const int lt = (xcd < rm ? xcd * (qd + 1) : rm * (qd + 1) + (xcd - rm) * qd) + loc;
   const int tn = lt % tilesN;
   const int tm = (lt / tilesN) % tilesM;
-  const int gl = lt / (tilesN * tilesM);
+  const int pr = lt / (tilesN * tilesM);
   const int nmod = pl->nmod;
-  const int l = gl % nmod, gi = gl / nmod;
+  // products in modulus-major order: neighbouring groups of one modulus share
+  // most of their slice planes; gl is the product's t-plane
+  const int gi = pr % pl->ng, l = pr / pl->ng;
+  const int gl = gi * nmod + l;
   const int S = pl->S, g = pl->g0 + gi;
   const int ta0 = g - (S - 1) > 0 ? g - (S - 1) : 0;
   const int ta1 = g < S - 1 ? g : S - 1;
@@ -654,9 +663,12 @@ __global__ __launch_bounds__(512) void k_gemm_f8(const uint8_t *__restrict__ pa,
   const int lt = (xcd < rm ? xcd * (qd + 1) : rm * (qd + 1) + (xcd - rm) * qd) + loc;
   const int tn = lt % tilesN;
   const int tm = (lt / tilesN) % tilesM;
-  const int gl = lt / (tilesN * tilesM);
+  const int pr = lt / (tilesN * tilesM);
   const int nmod = pl->nmod;
-  const int l = gl % nmod, gi = gl / nmod;
+  // products in modulus-major order: neighbouring groups of one modulus share
+  // most of their slice planes; gl is the product's t-plane
+  const int gi = pr % pl->ng, l = pr / pl->ng;
+  const int gl = gi * nmod + l;
   const int S = pl->S, g = pl->g0 + gi;
   const int ta0 = g - (S - 1) > 0 ? g - (S - 1) : 0;
   const int ta1 = g < S - 1 ? g : S - 1;
@@ -756,9 +768,12 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double *__restrict__ pa,
   const int lt = (xcd < rm ? xcd * (qd + 1) : rm * (qd + 1) + (xcd - rm) * qd) + loc;
   const int tn = lt % tilesN;
   const int tm = (lt / tilesN) % tilesM;
-  const int gl = lt / (tilesN * tilesM);
+  const int pr = lt / (tilesN * tilesM);
   const int nmod = pl->nmod;
-  const int l = gl % nmod, gi = gl / nmod;
+  // products in modulus-major order: neighbouring groups of one modulus share
+  // most of their slice planes; gl is the product's t-plane
+  const int gi = pr % pl->ng, l = pr / pl->ng;
+  const int gl = gi * nmod + l;
   const int S = pl->S, g = pl->g0 + gi;
   const int ta0 = g - (S - 1) > 0 ? g - (S - 1) : 0;
   const int ta1 = g < S - 1 ? g : S - 1;
