@@ -359,10 +359,16 @@ def main():
     else:
         rooflines = {"gemm": roof("gemm", "mfma"), "producer": roof("producer", "hbm"),
                      "consumer": roof("consumer", "hbm")}
-        ozk_ms = {k: prof[k][0] for k in ("producer", "gemm", "consumer")}
+        ozk = ("producer", "gemm", "consumer")
+        if prof["fused"][1]:
+            # (S4)-(S6) in one kernel: priced on its modular GEMM operations
+            rooflines["fused"] = roof("fused", "mfma")
+            ozk = ozk + ("fused",)
+        ozk_ms = {k: prof[k][0] for k in ozk}
         dominant = max(ozk_ms, key=lambda k: ozk_ms[k])
-    schur_ms = sum(prof[k][0] for k in ("exponents", "producer", "gemm", "consumer")) / K
-    gemm_ms, gemm_ops = prof["gemm"][0], prof["gemm"][3]
+    schur_ms = sum(prof[k][0] for k in ("exponents", "producer", "gemm", "consumer", "fused")) / K
+    gemm_stage = "gemm" if prof["gemm"][1] or not prof["fused"][1] else "fused"
+    gemm_ms, gemm_ops = prof[gemm_stage][0], prof[gemm_stage][3]
     gops = gemm_ops / (gemm_ms * 1e-3) / 1e9 if gemm_ms > 0 else None
 
     native = None
@@ -440,10 +446,12 @@ def main():
         "config": {"workload": f"Lotkin quad-double LU n={n} (getrf+getrs), b={b}, Schur update "
                                f"{'Ozaki-II ' + update_name if update_name != 'native' else 'native'}"
                                f"{'' if run_opts.flags & Z.F_NO_LOOKAHEAD else ', look-ahead'}"
+                               f"{', fused (S4)-(S6)' if run_opts.flags & Z.F_FUSED else ''}"
                                f"{' (autotuned)' if tuning else ''}",
                    "n": n, "nc": nc, "block": b, "update": update_name,
                    "lookahead": not (run_opts.flags & Z.F_NO_LOOKAHEAD),
-                   "nslice": run_opts.nslice, "gemm_tile": run_opts.gemm_tile},
+                   "nslice": run_opts.nslice, "gemm_tile": run_opts.gemm_tile,
+                   "fused": bool(run_opts.flags & Z.F_FUSED)},
         "autotune": tuning,
         "roofline": rooflines[dominant] if dominant else None,
         "rooflines": rooflines,

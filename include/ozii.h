@@ -370,7 +370,8 @@ ozII_status ozII_batch_run(ozII_handle h, uint64_t *times);
  * without OZII_F_NO_LOOKAHEAD); stage 2 times the winner (if Ozaki-II) with
  * the slice count S one above the plan rule's minimum (Eq. Lhint trades
  * slices against conversion cost) and, on the INT8 back-end, with each GEMM
- * tile.  Candidates are ordered by a cost model (engine throughput x bits
+ * tile and with OZII_F_FUSED (taken only when at least 3 % faster than the
+ * best unfused candidate).  Candidates are ordered by a cost model (engine throughput x bits
  * per modulus, plane and t-plane traffic, panel cost) and every one is timed
  * with HIP events around ozII_getrf of a synthetic diagonally dominant n x n
  * matrix on the handle's stream; the fastest is returned in *best (block,

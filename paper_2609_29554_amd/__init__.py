@@ -576,7 +576,8 @@ class Context:
             cands.append({"block": o.block,
                           "update": "native" if o.method == METHOD_NAIVE else names.get(o.backend, "?"),
                           "lookahead": not (o.flags & F_NO_LOOKAHEAD), "nslice": o.nslice,
-                          "gemm_tile": o.gemm_tile, "ms": rep.ms[i], "model_ms": rep.model_ms[i]})
+                          "gemm_tile": o.gemm_tile, "fused": bool(o.flags & F_FUSED),
+                          "ms": rep.ms[i], "model_ms": rep.model_ms[i]})
         return best, {"from_cache": bool(rep.from_cache), "best": rep.best, "candidates": cands}
 
     def tune_limbs(self, nlimb: int, n: int, cache_path: Optional[str] = None,

@@ -345,9 +345,15 @@ extern "C" ozII_status ozII_tune(ozII_handle h, int32_t nc, int64_t n, const cha
   if (st != OZII_OK) return st;
   if (e != hipSuccess) return OZII_EHIP;
   if (timed.empty()) return OZII_EUNSUPPORTED;
-  int bi = 0;
-  for (size_t ci = 1; ci < timed.size(); ++ci)
-    if (timed[ci].ms < timed[bi].ms) bi = (int)ci;
+  // the fused (S4)-(S6) kernel only when it is clearly faster: stand-alone it
+  // is the slower product, inside the LU its time hides behind the panel and
+  // a tie is timing noise
+  int bi = -1, bf = -1;
+  for (size_t ci = 0; ci < timed.size(); ++ci) {
+    int &b = (timed[ci].o.flags & OZII_F_FUSED) ? bf : bi;
+    if (b < 0 || timed[ci].ms < timed[b].ms) b = (int)ci;
+  }
+  if (bi < 0 || (bf >= 0 && timed[bf].ms < 0.97 * timed[bi].ms)) bi = bf;
   *best = timed[bi].o;
   if (rep) {
     rep->ncand = (int32_t)timed.size();
