@@ -303,7 +303,7 @@ __device__ __forceinline__ void oz_update(double *A, int64_t n, int64_t k0, int6
       const int64_t r = isA ? q : q - NBLK;
       produce_block_b<NC, 8, NWM, PL_I8>(isA ? L21 : U12, n, isA ? 1 : 0, m2, K, KB,
                                          isA ? ea : eb, pl, isA ? pa : pb, plane, r % KB, r / KB,
-                                         T);
+                                         T, 0, pl->nmod);
     }
   }
   __syncthreads();

@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "ozii_bytes.hpp"
 #include "ozii_elem.hpp"
 #include "ozii_kernels.hpp"
@@ -87,16 +89,17 @@ __global__ __launch_bounds__(256) void k_limb_col_exp(const uint64_t *__restrict
 // X = ~|X| + 1 starts with c_0 = 1 and complemented windows.
 // ---------------------------------------------------------------------------
 // Binary64 moduli: the residues of slice t of the thread's four elements as
-// doubles, in the binary64 GEMM's fragment order (1 KiB blocks of 16 rows x
-// 8 k, lane l: row l%16, k l/16 and 4 + l/16; eight blocks per 64-k window;
-// off: each element's offset in a plane).  F and sel as for the byte
+// doubles for the moduli l0 .. l1-1 (pp at the plane of modulus l0), in the
+// binary64 GEMM's fragment order (1 KiB blocks of 16 rows x 8 k, lane l: row
+// l%16, k l/16 and 4 + l/16; eight blocks per 64-k window; off: each
+// element's offset in a plane).  F and sel as for the byte
 // emitter: a lower slice has the value F - sel 2^w (F < 2^w), the top slice
 // is the nwt-word two's complement F with sign sel; its magnitude is reduced
 // and the residue negated.
 template <int NWM>
 __device__ __forceinline__ void emit_f64_residues(const uint32_t (&F)[4][NWM],
                                                   const uint32_t (&sel)[4], bool top, int nwt,
-                                                  const DevPlan *__restrict__ pl, int nmod,
+                                                  const DevPlan *__restrict__ pl, int l0, int l1,
                                                   double *pp, int64_t plane_elems,
                                                   const int64_t (&off)[4]) {
   constexpr int NH = 2 * NWM;
@@ -122,7 +125,7 @@ __device__ __forceinline__ void emit_f64_residues(const uint32_t (&F)[4][NWM],
 #pragma unroll
     for (int k = 0; k < NH; ++k) dig[k] = (mag[k >> 1] >> (16 * (k & 1))) & 0xffffu;
     const bool flag = !top && sel[e] != 0;
-    for (int l = 0; l < nmod; ++l) {
+    for (int l = l0; l < l1; ++l) {
       const uint32_t m = (uint32_t)pl->m[l];
       uint32_t r = digits_mod<NH, true>(dig, pl, l);
       if (flag) {
@@ -131,7 +134,7 @@ __device__ __forceinline__ void emit_f64_residues(const uint32_t (&F)[4][NWM],
       } else if (neg) {
         r = r == 0u ? 0u : m - r;
       }
-      pp[(int64_t)l * plane_elems + off[e]] = (double)centre(r, (int32_t)m);
+      pp[(int64_t)(l - l0) * plane_elems + off[e]] = (double)centre(r, (int32_t)m);
     }
   }
 }
@@ -150,6 +153,9 @@ __global__ __launch_bounds__(256) void k_producer_limbs(
   const uint32_t offb = (uint32_t)((ob * KB + kb) * 1024 + 4 * T);  // < 2^31
   const int S = pl->S, w = pl->w, nmod = pl->nmod, Q = pl->Q, nwt = pl->nwt;
   const int p = 64 * nlimb;
+  // blockIdx.z: a part of the moduli (small products run several parts)
+  const int l0 = (int)blockIdx.z * nmod / (int)gridDim.z;
+  const int l1 = ((int)blockIdx.z + 1) * nmod / (int)gridDim.z;
 
   int32_t ex = EXP_ZERO;
   if (o < nout) ex = exps[o];
@@ -252,11 +258,13 @@ __global__ __launch_bounds__(256) void k_producer_limbs(
         const int kk = 16 * (T >> 6) + 4 * (T & 3) + e, k8 = kk & 7;
         off[e] = ((ob * KB + kb) * 8 + (kk >> 3)) * 128 + 2 * ((k8 & 3) * 16 + r) + (k8 >> 2);
       }
-      emit_f64_residues<NWM>(F, sel, top, nwt, pl, nmod,
-                             (double *)planes + (int64_t)t * nmod * plane_elems, plane_elems, off);
+      emit_f64_residues<NWM>(F, sel, top, nwt, pl, l0, l1,
+                             (double *)planes + ((int64_t)t * nmod + l0) * plane_elems,
+                             plane_elems, off);
     } else {
-      emit_byte_residues<NWM, false>(F, sel, top ? REC_HT : REC_HW, pl, nmod,
-                                     planes + (int64_t)t * nmod * plane_elems, plane_elems, offb);
+      emit_byte_residues<NWM, false>(F, sel, top ? REC_HT : REC_HW, pl, l0, l1,
+                                     planes + ((int64_t)t * nmod + l0) * plane_elems, plane_elems,
+                                     offb);
     }
   }
 }
@@ -595,13 +603,17 @@ static void producer_limbs_nw(int nwt, dim3 g, hipStream_t s, const uint64_t *li
 hipError_t launch_producer_limbs(const uint64_t *limb, const int32_t *lexp, const uint8_t *lsign,
                                  int64_t ld, int64_t plane, int nlimb, int rowwise, int64_t nout,
                                  int64_t noutp, int64_t K, int64_t Kp, const int32_t *exps,
-                                 const DevPlan *pl, int nwt, int kind, void *planes,
+                                 const DevPlan *pl, int nmod, int nwt, int kind, void *planes,
                                  int64_t plane_elems, hipStream_t s) {
   const int64_t KB = Kp / 64, OB = noutp / 16;
   if (KB <= 0 || OB <= 0) return hipSuccess;
   if (plane_elems >= ((int64_t)1 << 31) || nwt > REC_PWMAX) return hipErrorInvalidValue;
   if (kind != PLANES_I8 && kind != PLANES_F64) return hipErrorInvalidValue;
-  dim3 g((unsigned)KB, (unsigned)OB);
+  // split the moduli over up to 8 parts while the blocks alone give fewer
+  // than 4096 wavefronts (four per SIMD)
+  dim3 g((unsigned)KB, (unsigned)OB,
+         (unsigned)std::max<int64_t>(1, std::min<int64_t>({8, (int64_t)nmod,
+                                                            (4096 + 4 * KB * OB - 1) / (4 * KB * OB)})));
   if (kind == PLANES_F64)
     producer_limbs_nw<true>(nwt, g, s, limb, lexp, lsign, ld, plane, nlimb, rowwise, nout, K, KB,
                             exps, pl, (uint8_t *)planes, plane_elems);

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "expansion.hpp"
 #include "ozii_elem.hpp"
 #include "ozii_bytes.hpp"
@@ -108,15 +110,22 @@ __global__ __launch_bounds__(256) void k_col_exponents(const double *B, int64_t 
 // floor(acc/m) is exact as the high word of (acc << k) * ceil(2^(32-k)/m):
 // acc < 2^(32-k)/m and (acc << k) < 2^24 hold for w <= 300.
 // ---------------------------------------------------------------------------
-template <int NC, int NWX, int NWM, int PL>
+template <int NC, int NWX, int NWM, int PL, int EPT>
 __global__ __launch_bounds__(256) void k_producer_b(const double *__restrict__ X, int64_t ld,
                                                     int rowwise, int64_t nout, int64_t K,
                                                     int64_t KB, const int32_t *__restrict__ exps,
                                                     const DevPlan *__restrict__ pl,
                                                     uint8_t *__restrict__ planes,
                                                     int64_t plane_elems) {
-  produce_block_b<NC, NWX, NWM, PL>(X, ld, rowwise, nout, K, KB, exps, pl, planes, plane_elems,
-                                   blockIdx.x, blockIdx.y, threadIdx.x);
+  // blockIdx.z: a part of the moduli (small products run several parts to
+  // fill the chip; each part repeats the conversion and slicing).  EPT = 1:
+  // four workgroups per block, blockIdx.x = 4 kb + quarter.
+  const int nmod = pl->nmod, np = (int)gridDim.z, part = (int)blockIdx.z;
+  const int64_t kb = EPT == 4 ? (int64_t)blockIdx.x : (int64_t)(blockIdx.x >> 2);
+  const int T = EPT == 4 ? (int)threadIdx.x : (int)(((blockIdx.x & 3u) << 8) + threadIdx.x);
+  produce_block_b<NC, NWX, NWM, PL, EPT>(X, ld, rowwise, nout, K, KB, exps, pl, planes,
+                                         plane_elems, kb, blockIdx.y, T, part * nmod / np,
+                                         (part + 1) * nmod / np);
 }
 
 // Producer: one workgroup fills one 16-row x 64-k window of every plane.
@@ -1214,29 +1223,44 @@ static void producer_nh(int nh, dim3 g, hipStream_t s, const double *X, int64_t 
                        K, KB, exps, pl, planes, plane_elems);
 }
 
+template <int NC, int NWX, int PL, int EPT>
+static void producer_b_ept(int nwt, dim3 g, hipStream_t s, const double *X, int64_t ld,
+                           int rowwise, int64_t nout, int64_t K, int64_t KB, const int32_t *exps,
+                           const DevPlan *pl, uint8_t *P, int64_t plane_elems) {
+  if (nwt <= 4)
+    hipLaunchKernelGGL((k_producer_b<NC, NWX, 4, PL, EPT>), g, dim3(256), 0, s, X, ld, rowwise,
+                       nout, K, KB, exps, pl, P, plane_elems);
+  else if (nwt <= 6)
+    hipLaunchKernelGGL((k_producer_b<NC, NWX, 6, PL, EPT>), g, dim3(256), 0, s, X, ld, rowwise,
+                       nout, K, KB, exps, pl, P, plane_elems);
+  else
+    hipLaunchKernelGGL((k_producer_b<NC, NWX, REC_PWMAX, PL, EPT>), g, dim3(256), 0, s, X, ld,
+                       rowwise, nout, K, KB, exps, pl, P, plane_elems);
+}
+
+// g: (KB, OB, moduli parts); fine: one element per thread (four workgroups
+// per block) for products too small to fill the chip otherwise
 template <int NC, int NWX, int PL>
-static void producer_b_nw(int nwt, dim3 g, hipStream_t s, const double *X, int64_t ld,
+static void producer_b_nw(int nwt, bool fine, dim3 g, hipStream_t s, const double *X, int64_t ld,
                           int rowwise, int64_t nout, int64_t K, int64_t KB, const int32_t *exps,
                           const DevPlan *pl, void *planes, int64_t plane_elems) {
   uint8_t *P = (uint8_t *)planes;
-  if (nwt <= 4)
-    hipLaunchKernelGGL((k_producer_b<NC, NWX, 4, PL>), g, dim3(256), 0, s, X, ld, rowwise, nout,
-                       K, KB, exps, pl, P, plane_elems);
-  else if (nwt <= 6)
-    hipLaunchKernelGGL((k_producer_b<NC, NWX, 6, PL>), g, dim3(256), 0, s, X, ld, rowwise, nout,
-                       K, KB, exps, pl, P, plane_elems);
-  else
-    hipLaunchKernelGGL((k_producer_b<NC, NWX, REC_PWMAX, PL>), g, dim3(256), 0, s, X, ld, rowwise,
-                       nout, K, KB, exps, pl, P, plane_elems);
+  if (fine) {
+    g.x *= 4;
+    producer_b_ept<NC, NWX, PL, 1>(nwt, g, s, X, ld, rowwise, nout, K, KB, exps, pl, P, plane_elems);
+  } else {
+    producer_b_ept<NC, NWX, PL, 4>(nwt, g, s, X, ld, rowwise, nout, K, KB, exps, pl, P, plane_elems);
+  }
 }
 
 template <int PL>
-static void producer_b(int nc, int nwx, int nwt, dim3 g, hipStream_t s, const double *X,
+static void producer_b(int nc, int nwx, int nwt, bool fine, dim3 g, hipStream_t s, const double *X,
                        int64_t ld, int rowwise, int64_t nout, int64_t K, int64_t KB,
                        const int32_t *exps, const DevPlan *pl, void *planes,
                        int64_t plane_elems) {
-#define OZ_PRODB(NC_, NWX_) \
-  producer_b_nw<NC_, NWX_, PL>(nwt, g, s, X, ld, rowwise, nout, K, KB, exps, pl, planes, plane_elems)
+#define OZ_PRODB(NC_, NWX_)                                                                     \
+  producer_b_nw<NC_, NWX_, PL>(nwt, fine, g, s, X, ld, rowwise, nout, K, KB, exps, pl, planes, \
+                               plane_elems)
   if (nc == 2) { if (nwx <= 8) OZ_PRODB(2, 8); else OZ_PRODB(2, 12); }
   else if (nc == 3) { if (nwx <= 8) OZ_PRODB(3, 8); else OZ_PRODB(3, 12); }
   else { if (nwx <= 8) OZ_PRODB(4, 8); else OZ_PRODB(4, 12); }
@@ -1258,19 +1282,28 @@ static void producer_pl(int nc, int nwx, int nh, dim3 g, hipStream_t s, const do
 
 hipError_t launch_producer(int nc, int nwx, int nh, int nwt, const double *X, int64_t ld, int rowwise,
                            int64_t nout, int64_t noutp, int64_t K, int64_t Kp,
-                           const int32_t *exps, const DevPlan *pl, int backend, void *planes,
+                           const int32_t *exps, const DevPlan *pl, int nmod, int backend,
+                           void *planes,
                            int64_t plane_elems, hipStream_t s) {
   const int64_t KB = Kp / 64, OB = noutp / 16;
   if (KB <= 0 || OB <= 0) return hipSuccess;
   // the byte producer addresses a plane with 32-bit offsets
   if (backend != PLANES_F64 && plane_elems >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
   dim3 g((unsigned)KB, (unsigned)OB);
+  // byte back-ends on products too small to give 4096 wavefronts (four per
+  // SIMD): one element per thread, then the moduli split over up to 8 parts
+  const bool fine = KB * OB * 4 < 4096;
+  const int64_t waves = KB * OB * (fine ? 16 : 4);
+  dim3 gb = g;
+  gb.z = (unsigned)std::max<int64_t>(1, std::min<int64_t>({8, nmod, (4096 + waves - 1) / waves}));
   if (backend == PLANES_F8)
-    producer_b<PL_F8>(nc, nwx, nwt, g, s, X, ld, rowwise, nout, K, KB, exps, pl, planes, plane_elems);
+    producer_b<PL_F8>(nc, nwx, nwt, fine, gb, s, X, ld, rowwise, nout, K, KB, exps, pl, planes,
+                      plane_elems);
   else if (backend == PLANES_F64)
     producer_pl<PL_F64>(nc, nwx, nh, g, s, X, ld, rowwise, nout, K, KB, exps, pl, planes, plane_elems);
   else
-    producer_b<PL_I8>(nc, nwx, nwt, g, s, X, ld, rowwise, nout, K, KB, exps, pl, planes, plane_elems);
+    producer_b<PL_I8>(nc, nwx, nwt, fine, gb, s, X, ld, rowwise, nout, K, KB, exps, pl, planes,
+                      plane_elems);
   return hipGetLastError();
 }
 

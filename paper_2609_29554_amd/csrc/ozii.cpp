@@ -696,13 +696,13 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
   {
     ProfScope ps(h, OZ_STAGE_PRODUCER, (double)M * K * (8.0 * nc + res_bytes), 0, s);
     if ((e = ozl::launch_producer(nc, hp->nwx, hp->nh, (hp->w + 2 + 31) / 32, A, lda, 1, M, L.Mp, K, L.Kp, ea, dp,
-                                  hp->planes_kind(), pa, L.planeA, s)) != hipSuccess)
+                                  hp->nmod, hp->planes_kind(), pa, L.planeA, s)) != hipSuccess)
       return hip_fail(h, e, "producer(A)");
   }
   {
     ProfScope ps(h, OZ_STAGE_PRODUCER, (double)N * K * (8.0 * nc + res_bytes), 0, s);
     if ((e = ozl::launch_producer(nc, hp->nwx, hp->nh, (hp->w + 2 + 31) / 32, B, ldb, 0, N, L.Np, K, L.Kp, eb, dp,
-                                  hp->planes_kind(), pb, L.planeB, s)) != hipSuccess)
+                                  hp->nmod, hp->planes_kind(), pb, L.planeB, s)) != hipSuccess)
       return hip_fail(h, e, "producer(B)");
   }
   // (S4)-(S6) fused: the t-values of a tile stay in LDS (INT8, no stage copies)
@@ -846,14 +846,14 @@ ozII_status gemm_limbs_impl(ozII_ctx *h, int mode, int nlimb, int64_t M, int64_t
   {
     ProfScope ps(h, OZ_STAGE_PRODUCER, (double)M * K * (in_bytes + res_bytes), 0);
     if ((e = ozl::launch_producer_limbs(A->limb, A->exp, A->sign, A->ld, A->plane, nlimb, 1, M,
-                                        L.Mp, K, L.Kp, ea, dp, nwt, hp->planes_kind(), pa,
+                                        L.Mp, K, L.Kp, ea, dp, hp->nmod, nwt, hp->planes_kind(), pa,
                                         L.planeA, s)) != hipSuccess)
       return hip_fail(h, e, "limb producer(A)");
   }
   {
     ProfScope ps(h, OZ_STAGE_PRODUCER, (double)N * K * (in_bytes + res_bytes), 0);
     if ((e = ozl::launch_producer_limbs(B->limb, B->exp, B->sign, B->ld, B->plane, nlimb, 0, N,
-                                        L.Np, K, L.Kp, eb, dp, nwt, hp->planes_kind(), pb,
+                                        L.Np, K, L.Kp, eb, dp, hp->nmod, nwt, hp->planes_kind(), pb,
                                         L.planeB, s)) != hipSuccess)
       return hip_fail(h, e, "limb producer(B)");
   }

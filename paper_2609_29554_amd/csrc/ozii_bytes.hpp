@@ -28,8 +28,9 @@ __device__ __forceinline__ uint32_t mul_u24(uint32_t a, uint32_t b) {
   return r;
 }
 
-// Residues of slice t of four elements for every modulus, stored as one
-// dword (four consecutive bytes of a plane) per modulus.  F: the slice words
+// Residues of slice t of four elements (EPT = 4) for the moduli l0 .. l1-1
+// (pp at the plane of modulus l0), stored as one dword (four consecutive
+// bytes of a plane) per modulus; EPT = 1: one element, one byte.  F: the slice words
 // (NWM 32-bit words, zero above the slice), sel: whether the (-2^W) mod m
 // term applies (centring flag, or the sign of the top slice), base: REC_HW
 // or REC_HT.  The residue of modulus m is
@@ -40,19 +41,20 @@ __device__ __forceinline__ uint32_t mul_u24(uint32_t a, uint32_t b) {
 // (acc << k) * ceil(2^(32-k)/m): acc < 2^(32-k)/m and (acc << k) < 2^24 for
 // slices of at most 10 words.  FP8: the balanced base-17 digits of Eq.
 // (fp8digits) as E4M3 bytes, d0 then d1 plane.
-template <int NWM, bool FP8>
-__device__ __forceinline__ void emit_byte_residues(const uint32_t (&F)[4][NWM],
-                                                   const uint32_t (&sel)[4], int base,
-                                                   const DevPlan *__restrict__ pl, int nmod,
+template <int NWM, bool FP8, int EPT = 4>
+__device__ __forceinline__ void emit_byte_residues(const uint32_t (&F)[EPT][NWM],
+                                                   const uint32_t (&sel)[EPT], int base,
+                                                   const DevPlan *__restrict__ pl, int l0, int l1,
                                                    uint8_t *pp, int64_t plane_elems,
                                                    uint32_t offb) {
-  for (int l = 0; l < nmod; ++l, pp += (FP8 ? 2 : 1) * plane_elems) {
+  static_assert(EPT == 4 || EPT == 1, "four elements per dword, or one byte");
+  for (int l = l0; l < l1; ++l, pp += (FP8 ? 2 : 1) * plane_elems) {
     const uint32_t *R = pl->rec[l];
     const uint32_t m = R[REC_M], h = R[REC_H], magic = R[REC_MAGIC], ks = R[REC_K];
     const uint32_t hs = R[base];
-    int32_t c[4];
+    int32_t c[EPT];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < EPT; ++e) {
       uint32_t acc = sel[e] ? hs : h;
 #pragma unroll
       for (int j = 0; j < NWM; ++j) acc = __builtin_amdgcn_udot4(F[e][j], R[j], acc, false);
@@ -61,22 +63,31 @@ __device__ __forceinline__ void emit_byte_residues(const uint32_t (&F)[4][NWM],
       c[e] = (int32_t)(acc - mul_u24(qq, m) - h);
     }
     if (!FP8) {
-      const uint32_t word = (uint32_t)(c[0] & 0xff) | ((uint32_t)(c[1] & 0xff) << 8) |
-                            ((uint32_t)(c[2] & 0xff) << 16) | ((uint32_t)c[3] << 24);
-      *(uint32_t *)(pp + offb) = word;
+      if constexpr (EPT == 4) {
+        const uint32_t word = (uint32_t)(c[0] & 0xff) | ((uint32_t)(c[1] & 0xff) << 8) |
+                              ((uint32_t)(c[2] & 0xff) << 16) | ((uint32_t)c[3] << 24);
+        *(uint32_t *)(pp + offb) = word;
+      } else {
+        pp[offb] = (uint8_t)c[0];
+      }
     } else {
       // d1 = round(c/17) (never a tie), d0 = c - 17 d1; floor((c+144)/17)
       // as a multiply-high, exact for |c| <= 128
       uint32_t w0 = 0, w1 = 0;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < EPT; ++e) {
         const int32_t d1 = (int32_t)(((uint32_t)(c[e] + 144) * 3856u) >> 16) - 8;
         const int32_t d0 = c[e] - 17 * d1;
         w0 |= (uint32_t)e4m3_small(d0) << (8 * e);
         w1 |= (uint32_t)e4m3_small(d1) << (8 * e);
       }
-      *(uint32_t *)(pp + offb) = w0;
-      *(uint32_t *)(pp + plane_elems + offb) = w1;
+      if constexpr (EPT == 4) {
+        *(uint32_t *)(pp + offb) = w0;
+        *(uint32_t *)(pp + plane_elems + offb) = w1;
+      } else {
+        pp[offb] = (uint8_t)w0;
+        pp[plane_elems + offb] = (uint8_t)w1;
+      }
     }
   }
 }

@@ -46,8 +46,8 @@ hipError_t launch_exponents(int nc, const double *X, int64_t ld, int64_t rows, i
 enum { PLANES_I8 = 0, PLANES_F8 = 1, PLANES_F64 = 2 };
 hipError_t launch_producer(int nc, int nwx, int nh, int nwt, const double *X, int64_t ld, int rowwise,
                            int64_t nout, int64_t noutp, int64_t K, int64_t Kp,
-                           const int32_t *exps, const DevPlan *pl, int planes_kind, void *planes,
-                           int64_t plane_elems, hipStream_t s);
+                           const int32_t *exps, const DevPlan *pl, int nmod, int planes_kind,
+                           void *planes, int64_t plane_elems, hipStream_t s);
 hipError_t launch_gemm_i8(const int8_t *pa, const int8_t *pb, uint8_t *tpl, const DevPlan *pl,
                           int ng, int nmod, int64_t Mp, int64_t Np, int64_t Kp, int64_t planeA,
                           int64_t planeB, int tile, hipStream_t s);
@@ -113,7 +113,7 @@ hipError_t launch_limb_exponents(const uint64_t *limb, const int32_t *lexp, int6
 hipError_t launch_producer_limbs(const uint64_t *limb, const int32_t *lexp, const uint8_t *lsign,
                                  int64_t ld, int64_t plane, int nlimb, int rowwise, int64_t nout,
                                  int64_t noutp, int64_t K, int64_t Kp, const int32_t *exps,
-                                 const DevPlan *pl, int nwt, int kind, void *planes,
+                                 const DevPlan *pl, int nmod, int nwt, int kind, void *planes,
                                  int64_t plane_elems, hipStream_t s);
 hipError_t launch_consumer_limbs(const void *tpl, int tbytes, int64_t Mp, int64_t Np, int64_t M,
                                  int64_t N, const DevPlan *pl, int nd, int nvw, uint32_t *cw,

@@ -19,12 +19,15 @@ namespace ozk {
 enum { PL_I8 = 0, PL_F8 = 1, PL_F64 = 2 };
 
 // Producer of the byte back-ends (INT8 residues, FP8 base-17 digits): the
-// caller's 256 threads (T = 0..255) fill block (ob, kb) -- rows 16 ob ..
-// 16 ob + 15, inner indices 64 kb .. 64 kb + 63 -- of every plane; thread T
-// owns the four consecutive bytes 4T .. 4T+3 of the block, i.e. row
+// caller's threads fill block (ob, kb) -- rows 16 ob .. 16 ob + 15, inner
+// indices 64 kb .. 64 kb + 63 -- of every plane.  EPT = 4: 256 threads,
+// thread T owns the four consecutive bytes 4T .. 4T+3 of the block, i.e. row
 // (T/4)%16 and inner indices 16(T/64) + 4(T%4) + e, e = 0..3, so each
-// residue plane receives one dword store per thread.  Rows at or past nout
-// and inner indices at or past K are zero.
+// residue plane receives one dword store per thread; EPT = 1 (for small
+// products: a quarter of the conversion and slicing per thread): 1024
+// threads, thread T owns byte T (of the moduli l0 ..
+// l1-1: small products split the moduli over several workgroups).  Rows at
+// or past nout and inner indices at or past K are zero.
 template <int NWX>
 __device__ __forceinline__ uint32_t word_or_fill(const uint32_t (&X)[NWX], int k, uint32_t fill) {
   uint32_t r = fill;
@@ -33,26 +36,29 @@ __device__ __forceinline__ uint32_t word_or_fill(const uint32_t (&X)[NWX], int k
   return r;
 }
 
-template <int NC, int NWX, int NWM, int PL>
+template <int NC, int NWX, int NWM, int PL, int EPT = 4>
 __device__ __forceinline__ void produce_block_b(const double *__restrict__ X, int64_t ld,
                                                 int rowwise, int64_t nout, int64_t K, int64_t KB,
                                                 const int32_t *__restrict__ exps,
                                                 const DevPlan *__restrict__ pl,
                                                 uint8_t *__restrict__ planes,
                                                 int64_t plane_elems, int64_t kb, int64_t ob,
-                                                int T) {
-  const int64_t o = ob * 16 + ((T >> 2) & 15);
-  const int64_t h0 = kb * 64 + 16 * (T >> 6) + 4 * (T & 3);
-  // dword index of this thread's four bytes in every plane (planes hold
-  // fewer than 2^31 elements)
-  const uint32_t offb = (uint32_t)((ob * KB + kb) * 1024 + 4 * T);  // < 2^31
+                                                int T, int l0, int l1) {
+  // block byte E0 .. E0 + EPT - 1: byte E is row (E/16)%16, inner index
+  // 16(E/256) + 4((E/4)%4) + E%4 of the block
+  const int E0 = EPT * T;
+  const int64_t o = ob * 16 + ((E0 >> 4) & 15);
+  const int64_t h0 = kb * 64 + 16 * (E0 >> 8) + 4 * ((E0 >> 2) & 3) + (E0 & 3);
+  // index of this thread's bytes in every plane (planes hold fewer than
+  // 2^31 elements)
+  const uint32_t offb = (uint32_t)((ob * KB + kb) * 1024 + E0);  // < 2^31
   const int S = pl->S, w = pl->w, nmod = pl->nmod, Q = pl->Q, nwt = pl->nwt;
 
-  uint32_t Xw[4][NWX];
+  uint32_t Xw[EPT][NWX];
   int32_t ex = EXP_ZERO;
   if (o < nout) ex = exps[o];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
+  for (int e = 0; e < EPT; ++e) {
     const int64_t h = h0 + e;
     const double *src = nullptr;
     if (ex != EXP_ZERO && h < K) src = rowwise ? X + (o + h * ld) * NC : X + (h + o * ld) * NC;
@@ -63,15 +69,17 @@ __device__ __forceinline__ void produce_block_b(const double *__restrict__ X, in
       for (int k = 0; k < NWX; ++k) Xw[e][k] = 0u;
     }
   }
-  uint32_t cin[4] = {0u, 0u, 0u, 0u};
+  uint32_t cin[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) cin[e] = 0u;
   for (int t = 0; t < S; ++t) {
     const bool top = t == S - 1;
     const int bo = t * w, q = bo >> 5, b = bo & 31;
     const int wq = w >> 5, wb = w & 31;
-    uint32_t F[4][NWM];
-    uint32_t sel[4];  // 1: add the (-2^W) mod m term (flag or sign)
+    uint32_t F[EPT][NWM];
+    uint32_t sel[EPT];  // 1: add the (-2^W) mod m term (flag or sign)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < EPT; ++e) {
       const uint32_t fill = (Xw[e][NWX - 1] >> 31) ? 0xffffffffu : 0u;
       uint32_t prev = word_or_fill<NWX>(Xw[e], q, fill);
 #pragma unroll
@@ -120,8 +128,8 @@ __device__ __forceinline__ void produce_block_b(const double *__restrict__ X, in
       }
     }
     const int pstep = PL == PL_F8 ? 2 : 1;
-    emit_byte_residues<NWM, PL == PL_F8>(F, sel, top ? REC_HT : REC_HW, pl, nmod,
-                                         planes + (int64_t)t * nmod * pstep * plane_elems,
+    emit_byte_residues<NWM, PL == PL_F8, EPT>(F, sel, top ? REC_HT : REC_HW, pl, l0, l1,
+                                         planes + ((int64_t)t * nmod + l0) * pstep * plane_elems,
                                          plane_elems, offb);
   }
 }
