@@ -275,8 +275,9 @@ ozII_status ozII_limbs_arith(ozII_handle h, int32_t op, int32_t nlimb, int64_t c
  *   sbar             (S5) group sums, nlimb (1..6) 64-bit two's-complement
  *                    limbs per element, layout [ng][N][M][nlimb], computed by
  *                    the CRT routine of the consumer that reads these
- *                    t-planes (the byte-column CRT for INT8 and FP8, the
- *                    binary64 CRT for binary64 moduli). */
+ *                    t-planes (the byte-column CRT with its column sums on
+ *                    the matrix cores for INT8, FP8 and FP16, the binary64
+ *                    CRT for binary64 moduli). */
 ozII_status ozII_gemm_stages(ozII_handle h, int32_t mode, int32_t nc, int64_t M, int64_t N,
                              int64_t K, const double *A, int64_t lda, const double *B,
                              int64_t ldb, double *C, int64_t ldc, const ozII_opts *o,

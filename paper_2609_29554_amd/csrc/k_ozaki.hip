@@ -907,6 +907,73 @@ constexpr int MX_BLK = 3;    // 16-column blocks of the table: f_l, then bytes 0
 constexpr int MX_CBS = 16 * MX_BLK + 4;  // ints per element row of the column sums
 static_assert(2 + 46 == 16 * MX_BLK, "table columns");
 
+// The 16-bit digits of group gi's Sbar for the wavefront's 64 elements
+// (lane L: element i0 + L) by the matrix-core route; tg: t-value of modulus 0
+// of element i0 in group gi, moduli ps bytes apart.  Called by all 64 lanes
+// of a one-wavefront workgroup; buf (32 MX_CBS ints of LDS) is free again
+// when it returns.
+template <int NB>
+__device__ __forceinline__ void crt_group_mx(const uint8_t *tg, int64_t ps, int nmod,
+                                             const DevPlan *__restrict__ pl,
+                                             const v4i (&tab)[MX_BLK], int32_t *buf, int lane,
+                                             int32_t (&d)[NB / 2]) {
+  constexpr int ND = NB / 2;
+  uint8_t *tb = (uint8_t *)buf;
+  const int nch = (nmod + 3) >> 2;
+  const int e4 = 4 * (lane & 15), lq = lane >> 4;
+  // lane: moduli 4c + lq, elements e4 .. e4 + 3 (one dword of a plane);
+  // moduli past nmod read the last plane again, their table columns are 0
+  const uint8_t *src = tg + e4 + (int64_t)lq * ps, *last = tg + e4 + (int64_t)(nmod - 1) * ps;
+  for (int c = 0; c < nch; ++c, src += 4 * ps) {
+    const int l = 4 * c + lq;
+    const uint32_t v = *(const uint32_t *)(l < nmod ? src : last) ^ 0x80808080u;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) tb[(e4 + r) * MX_TBS + l] = (uint8_t)(v >> (8 * r));
+  }
+  __syncthreads();
+  v4i bf[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    bf[e] = *(const v4i *)(tb + (16 * e + (lane & 15)) * MX_TBS + 16 * lq);
+  __syncthreads();
+  int32_t col[52];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int e = 2 * h; e < 2 * h + 2; ++e)
+#pragma unroll
+      for (int b = 0; b < MX_BLK; ++b) {
+        const v4i acc =
+            __builtin_amdgcn_mfma_i32_16x16x64_i8(tab[b], bf[e], v4i{0, 0, 0, 0}, 0, 0, 0);
+        *(v4i *)(buf + (16 * (e - 2 * h) + (lane & 15)) * MX_CBS + 16 * b + 4 * lq) = acc;
+      }
+    __syncthreads();
+    if ((lane >> 5) == h) {
+#pragma unroll
+      for (int q = 0; q < 4 * MX_BLK; ++q) {
+        const v4i v = *(const v4i *)(buf + (lane & 31) * MX_CBS + 4 * q);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) col[4 * q + r] = v[r] + pl->crtc[4 * q + r];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 16 * MX_BLK; k < 52; ++k) col[k] = 0;  // bytes 46, 47 of every M_l are 0
+  // F = (sum_l t_l f_l) / 2^16 from columns 0, 1; then as crt_group_bytes
+  const int32_t qf = (col[0] + col[1] * 256 + 32768) >> 16;
+  int32_t carry = 0;
+#pragma unroll
+  for (int k = 0; k < ND; ++k) {
+    const int32_t lo = col[2 + 2 * k] - qf * (pl->pbyte[2 * k] & 0xff);
+    const int32_t hi = col[3 + 2 * k] - qf * (pl->pbyte[2 * k + 1] & 0xff);
+    const int32_t v = lo + (int32_t)((uint32_t)hi << 8) + carry;
+    d[k] = v & 0xffff;
+    carry = v >> 16;  // arithmetic
+  }
+  d[ND - 1] = (int32_t)(int16_t)(uint16_t)d[ND - 1];
+}
+
 template <int NC, int NWC, int NB>
 __global__ __launch_bounds__(64) void k_consumer_mx(const uint8_t *__restrict__ tpl, int64_t Mp,
                                                     int64_t Np, double *__restrict__ C,
@@ -919,7 +986,6 @@ __global__ __launch_bounds__(64) void k_consumer_mx(const uint8_t *__restrict__ 
   // the t-byte rows, then the column sums of 32 elements, then the digit
   // staging of add_shifted_digits share one buffer
   __shared__ __attribute__((aligned(16))) int32_t buf[32 * MX_CBS];
-  uint8_t *tb = (uint8_t *)buf;
   const int lane = (int)threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.x * 64, i = i0 + lane;
   const int64_t j = blockIdx.y;
@@ -932,66 +998,13 @@ __global__ __launch_bounds__(64) void k_consumer_mx(const uint8_t *__restrict__ 
   const bool zero = ei == EXP_ZERO || ej == EXP_ZERO;
   const int eps = zero ? 0 : w * pl->g0 - (Q - 1 - ei) - (Q - 1 - ej);
   const int64_t ps = Np * Mp;
-  const int nch = (nmod + 3) >> 2;
-  const int e4 = 4 * (lane & 15), lq = lane >> 4;
   uint32_t *st = (uint32_t *)buf + lane * STG;
   uint32_t cb[NWC];
 #pragma unroll
   for (int k = 0; k < NWC; ++k) cb[k] = 0u;
   for (int gi = 0; gi < ng; ++gi) {
-    // lane: moduli 4c + lq, elements e4 .. e4 + 3 (one dword of a plane);
-    // moduli past nmod read the last plane again, their table columns are 0
-    const uint8_t *tg = tpl + (int64_t)gi * nmod * ps + j * Mp + i0 + e4;
-    const uint8_t *src = tg + (int64_t)lq * ps, *last = tg + (int64_t)(nmod - 1) * ps;
-    for (int c = 0; c < nch; ++c, src += 4 * ps) {
-      const int l = 4 * c + lq;
-      const uint32_t v = *(const uint32_t *)(l < nmod ? src : last) ^ 0x80808080u;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) tb[(e4 + r) * MX_TBS + l] = (uint8_t)(v >> (8 * r));
-    }
-    __syncthreads();
-    v4i bf[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-      bf[e] = *(const v4i *)(tb + (16 * e + (lane & 15)) * MX_TBS + 16 * lq);
-    __syncthreads();
-    int32_t col[52];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-#pragma unroll
-      for (int e = 2 * h; e < 2 * h + 2; ++e)
-#pragma unroll
-        for (int b = 0; b < MX_BLK; ++b) {
-          const v4i acc =
-              __builtin_amdgcn_mfma_i32_16x16x64_i8(tab[b], bf[e], v4i{0, 0, 0, 0}, 0, 0, 0);
-          *(v4i *)(buf + (16 * (e - 2 * h) + (lane & 15)) * MX_CBS + 16 * b + 4 * lq) = acc;
-        }
-      __syncthreads();
-      if ((lane >> 5) == h) {
-#pragma unroll
-        for (int q = 0; q < 4 * MX_BLK; ++q) {
-          const v4i v = *(const v4i *)(buf + (lane & 31) * MX_CBS + 4 * q);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) col[4 * q + r] = v[r] + pl->crtc[4 * q + r];
-        }
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int k = 16 * MX_BLK; k < 52; ++k) col[k] = 0;  // bytes 46, 47 of every M_l are 0
-    // F = (sum_l t_l f_l) / 2^16 from columns 0, 1; then as crt_group_bytes
-    const int32_t qf = (col[0] + col[1] * 256 + 32768) >> 16;
     int32_t d[ND];
-    int32_t carry = 0;
-#pragma unroll
-    for (int k = 0; k < ND; ++k) {
-      const int32_t lo = col[2 + 2 * k] - qf * (pl->pbyte[2 * k] & 0xff);
-      const int32_t hi = col[3 + 2 * k] - qf * (pl->pbyte[2 * k + 1] & 0xff);
-      const int32_t v = lo + (int32_t)((uint32_t)hi << 8) + carry;
-      d[k] = v & 0xffff;
-      carry = v >> 16;  // arithmetic
-    }
-    d[ND - 1] = (int32_t)(int16_t)(uint16_t)d[ND - 1];
+    crt_group_mx<NB>(tpl + (int64_t)gi * nmod * ps + j * Mp + i0, ps, nmod, pl, tab, buf, lane, d);
     add_shifted_digits<NWC, ND, STG>(cb, d, w * gi, st);
     __syncthreads();  // the buffer takes the next group's t-bytes
   }
@@ -1168,6 +1181,28 @@ __global__ __launch_bounds__(256) void k_crt_export_b(const uint8_t *__restrict_
     int32_t d[NB / 2];
     crt_group_bytes<NB>(tpl + ((int64_t)gi * nmod * Np + j) * Mp + i, Np * Mp, nmod, pl, d);
     store_sbar_limbs<NB / 2>(d, out + (((int64_t)gi * N + j) * M + i) * nlimb, nlimb);
+  }
+}
+
+// The group sums of k_consumer_mx's own route, exported like k_crt_export_b.
+template <int NB>
+__global__ __launch_bounds__(64) void k_crt_export_mx(const uint8_t *__restrict__ tpl, int64_t Mp,
+                                                      int64_t Np, int64_t M, int64_t N,
+                                                      const DevPlan *__restrict__ pl,
+                                                      uint64_t *out, int nlimb) {
+  __shared__ __attribute__((aligned(16))) int32_t buf[32 * MX_CBS];
+  const int lane = (int)threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * 64, i = i0 + lane;
+  const int64_t j = blockIdx.y;
+  const int nmod = pl->nmod;
+  const int64_t ps = Np * Mp;
+  v4i tab[MX_BLK];
+#pragma unroll
+  for (int b = 0; b < MX_BLK; ++b) tab[b] = *(const v4i *)&pl->crtm[b][lane][0];
+  for (int gi = 0; gi < pl->ng; ++gi) {
+    int32_t d[NB / 2];
+    crt_group_mx<NB>(tpl + (int64_t)gi * nmod * ps + j * Mp + i0, ps, nmod, pl, tab, buf, lane, d);
+    if (i < M) store_sbar_limbs<NB / 2>(d, out + (((int64_t)gi * N + j) * M + i) * nlimb, nlimb);
   }
 }
 
@@ -1447,9 +1482,21 @@ hipError_t launch_fused_b(int nc, int nwc, int nd, const int8_t *pa, const int8_
 
 hipError_t launch_crt_export(const void *tpl, int tbytes, int nd, int64_t Mp, int64_t Np,
                              int64_t M, int64_t N, const DevPlan *pl, uint64_t *out, int nlimb,
-                             hipStream_t s) {
+                             int mx, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
   dim3 g((unsigned)((M + 255) / 256), (unsigned)N);
+  if (tbytes == 1 && mx) {
+    // the route of k_consumer_mx (expansion products)
+    if (nd > 24 || (M + 63) / 64 * 64 > Mp) return hipErrorInvalidValue;
+    dim3 gx((unsigned)((M + 63) / 64), (unsigned)N);
+    if (nd <= 18)
+      hipLaunchKernelGGL(k_crt_export_mx<36>, gx, dim3(64), 0, s, (const uint8_t *)tpl, Mp, Np, M,
+                         N, pl, out, nlimb);
+    else
+      hipLaunchKernelGGL(k_crt_export_mx<48>, gx, dim3(64), 0, s, (const uint8_t *)tpl, Mp, Np, M,
+                         N, pl, out, nlimb);
+    return hipGetLastError();
+  }
   if (tbytes == 1) {
     // the byte-column count of the consumers (launch_consumer, the limb
     // consumer): 36 up to 18 digits, else 48

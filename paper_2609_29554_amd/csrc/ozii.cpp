@@ -746,7 +746,7 @@ ozII_status gemm_impl(ozII_ctx *h, int mode, int nc, int64_t M, int64_t N, int64
     return hip_fail(h, e, "copy planesB");
   if (tpl_out && (e = hipMemcpyAsync(tpl_out, tpl, (size_t)L.tplBytes, hipMemcpyDeviceToDevice, s)) != hipSuccess)
     return hip_fail(h, e, "copy tpl");
-  if (sbar_out && (e = ozl::launch_crt_export(tpl, hp->t_bytes(), hp->nd, L.Mp, L.Np, M, N, dp, sbar_out, nlimb, s)) != hipSuccess)
+  if (sbar_out && (e = ozl::launch_crt_export(tpl, hp->t_bytes(), hp->nd, L.Mp, L.Np, M, N, dp, sbar_out, nlimb, 1, s)) != hipSuccess)
     return hip_fail(h, e, "crt_export");
   {
     ProfScope ps(h, OZ_STAGE_CONSUMER, (double)M * N * (t_bytes + 8.0 * nc * (mode ? 2 : 1)), 0, s);
@@ -869,7 +869,7 @@ ozII_status gemm_limbs_impl(ozII_ctx *h, int mode, int nlimb, int64_t M, int64_t
     if (e != hipSuccess) return hip_fail(h, e, "modular gemm");
   }
   if (sbar_out && (e = ozl::launch_crt_export(tpl, hp->t_bytes(), hp->nd, L.Mp, L.Np, M, N, dp,
-                                              sbar_out, nlimb_out, s)) != hipSuccess)
+                                              sbar_out, nlimb_out, 0, s)) != hipSuccess)
     return hip_fail(h, e, "crt_export");
   {
     // t-planes read once, each group's window of the sum read and written

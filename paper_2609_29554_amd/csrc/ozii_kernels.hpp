@@ -73,11 +73,12 @@ hipError_t launch_consumer(int nc, int nwc, int nd, const void *tpl, int tbytes,
                            const int32_t *ea, const int32_t *eb, const DevPlan *pl, int mode,
                            hipStream_t s);
 // group sums exported by the CRT routine of the consumer that reads these
-// t-planes (byte back-ends: crt_group_bytes with the consumer's byte-column
-// count for nd digits; binary64 moduli: crt_digits)
+// t-planes (byte back-ends: mx = 1 the matrix-core route of the expansion
+// consumer, mx = 0 crt_group_bytes of the limb consumer, with the consumer's
+// byte-column count for nd digits; binary64 moduli: crt_digits)
 hipError_t launch_crt_export(const void *tpl, int tbytes, int nd, int64_t Mp, int64_t Np,
                              int64_t M, int64_t N, const DevPlan *pl, uint64_t *out, int nlimb,
-                             hipStream_t s);
+                             int mx, hipStream_t s);
 
 // LU pieces
 size_t panel_lds_bytes(int nc, int kb, int R, int64_t nr);
