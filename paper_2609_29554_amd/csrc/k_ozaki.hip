@@ -974,6 +974,19 @@ __device__ __forceinline__ void crt_group_mx(const uint8_t *tg, int64_t ps, int 
   d[ND - 1] = (int32_t)(int16_t)(uint16_t)d[ND - 1];
 }
 
+// Block (x, y) of a 2-D grid in an XCD-aware order: workgroups are dispatched
+// to the 8 XCDs in turn, so each XCD is given a contiguous range of logical
+// blocks; neighbouring 64-element blocks of a column then share an L2 and
+// each 128-byte line of a t-plane row is fetched from HBM once.
+__device__ __forceinline__ void xcd_block(int64_t &bx, int64_t &by) {
+  const int64_t gx = gridDim.x, nb = gx * gridDim.y;
+  const int64_t pid = blockIdx.x + gx * blockIdx.y;
+  const int64_t xcd = pid & 7, loc = pid >> 3, qd = nb >> 3, rm = nb & 7;
+  const int64_t lt = (xcd < rm ? xcd * (qd + 1) : rm * (qd + 1) + (xcd - rm) * qd) + loc;
+  bx = lt % gx;
+  by = lt / gx;
+}
+
 template <int NC, int NWC, int NB>
 __global__ __launch_bounds__(64) void k_consumer_mx(const uint8_t *__restrict__ tpl, int64_t Mp,
                                                     int64_t Np, double *__restrict__ C,
@@ -987,8 +1000,9 @@ __global__ __launch_bounds__(64) void k_consumer_mx(const uint8_t *__restrict__ 
   // staging of add_shifted_digits share one buffer
   __shared__ __attribute__((aligned(16))) int32_t buf[32 * MX_CBS];
   const int lane = (int)threadIdx.x;
-  const int64_t i0 = (int64_t)blockIdx.x * 64, i = i0 + lane;
-  const int64_t j = blockIdx.y;
+  int64_t bx, j;
+  xcd_block(bx, j);
+  const int64_t i0 = bx * 64, i = i0 + lane;
   const int nmod = pl->nmod, w = pl->w, ng = pl->ng, Q = pl->Q;
   v4i tab[MX_BLK];
 #pragma unroll
@@ -1192,8 +1206,9 @@ __global__ __launch_bounds__(64) void k_crt_export_mx(const uint8_t *__restrict_
                                                       uint64_t *out, int nlimb) {
   __shared__ __attribute__((aligned(16))) int32_t buf[32 * MX_CBS];
   const int lane = (int)threadIdx.x;
-  const int64_t i0 = (int64_t)blockIdx.x * 64, i = i0 + lane;
-  const int64_t j = blockIdx.y;
+  int64_t bx, j;
+  xcd_block(bx, j);
+  const int64_t i0 = bx * 64, i = i0 + lane;
   const int nmod = pl->nmod;
   const int64_t ps = Np * Mp;
   v4i tab[MX_BLK];
