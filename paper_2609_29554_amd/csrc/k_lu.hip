@@ -100,6 +100,60 @@ __device__ __forceinline__ bool cand_better(const double (&kb_)[NC], int pb, int
   return pb < pa;
 }
 
+// Partner value of a 64-bit / 32-bit word under a DPP lane pattern (CTRL:
+// quad_perm or row mirror, never out of range); every lane of the
+// wavefront must call it.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  uint64_t u;
+  __builtin_memcpy(&u, &x, 8);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+  const uint64_t v = ((uint64_t)hi << 32) | lo;
+  double d;
+  __builtin_memcpy(&d, &v, 8);
+  return d;
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xf, 0xf, false);
+}
+
+// The best candidate of the wavefront in every lane (cand_better is a total
+// order, so any pairing network that meets every lane gives the same one):
+// lanes 32 and 16 apart through the LDS crossbar, then within each row of 16
+// by DPP (mirror, half mirror, quad swaps), which needs no LDS round trip.
+// All 64 lanes must call it.
+template <int NC>
+__device__ __forceinline__ void cand_allreduce(double (&k)[NC], int &pos, int &idx) {
+  auto take = [&](const double (&ok)[NC], int op, int oi) {
+    if (cand_better<NC>(ok, op, oi, k, pos, idx)) {
+#pragma unroll
+      for (int q = 0; q < NC; ++q) k[q] = ok[q];
+      pos = op;
+      idx = oi;
+    }
+  };
+#pragma unroll
+  for (int off = 32; off >= 16; off >>= 1) {
+    double ok[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) ok[q] = __shfl_xor(k[q], off, 64);
+    take(ok, __shfl_xor(pos, off, 64), __shfl_xor(idx, off, 64));
+  }
+#define OZ_DPP_STEP(CTRL)                                         \
+  do {                                                            \
+    double ok[NC];                                                \
+    _Pragma("unroll") for (int q = 0; q < NC; ++q) ok[q] = dpp_f64<CTRL>(k[q]); \
+    take(ok, dpp_i32<CTRL>(pos), dpp_i32<CTRL>(idx));              \
+  } while (0)
+  OZ_DPP_STEP(0x140);  // row_mirror: lane i <-> 15 - i of its row
+  OZ_DPP_STEP(0x141);  // row_half_mirror: i <-> 7 - i of its half row
+  OZ_DPP_STEP(0x4E);   // quad_perm [2, 3, 0, 1]
+  OZ_DPP_STEP(0xB1);   // quad_perm [1, 0, 3, 2]
+#undef OZ_DPP_STEP
+}
+
 constexpr int PANEL_NT = 512;  // threads per panel workgroup
 
 // ---------------------------------------------------------------------------
@@ -262,19 +316,7 @@ __global__ __launch_bounds__(PANEL_NT) void k_panel(double *A, int64_t lda, int6
           bi = tidx[gi];
         }
       }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        double ok[NC];
-#pragma unroll
-        for (int q = 0; q < NC; ++q) ok[q] = __shfl_xor(bk[q], off, 64);
-        const int op = __shfl_xor(bp, off, 64), oi = __shfl_xor(bi, off, 64);
-        if (cand_better<NC>(ok, op, oi, bk, bp, bi)) {
-#pragma unroll
-          for (int q = 0; q < NC; ++q) bk[q] = ok[q];
-          bp = op;
-          bi = oi;
-        }
-      }
+      cand_allreduce<NC>(bk, bp, bi);
       if (tid == 0) {
         // the winner, and (for a consistent table) the bookkeeping of the
         // interchange, before the single barrier below
@@ -347,19 +389,7 @@ __global__ __launch_bounds__(PANEL_NT) void k_panel(double *A, int64_t lda, int6
         }
       }
       if (!last) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          double ok[NC];
-#pragma unroll
-          for (int q = 0; q < NC; ++q) ok[q] = __shfl_xor(ck[q], off, 64);
-          const int op = __shfl_xor(cpos, off, 64), oi = __shfl_xor(cidx, off, 64);
-          if (cand_better<NC>(ok, op, oi, ck, cpos, cidx)) {
-#pragma unroll
-            for (int q = 0; q < NC; ++q) ck[q] = ok[q];
-            cpos = op;
-            cidx = oi;
-          }
-        }
+        cand_allreduce<NC>(ck, cpos, cidx);
         if (tid == 0) s_best = cidx;
       }
     } else {
