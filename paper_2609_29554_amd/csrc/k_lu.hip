@@ -804,27 +804,44 @@ __global__ __launch_bounds__(256) void k_apply_ipiv(double *B, int64_t ldb, int6
 // workgroups in and however few fit on the device at once.  Block t holds
 // the rows at processing positions [t R, t R + R): rows 0.. in the forward
 // solve with the unit lower factor, rows n-1.. in the backward solve with
-// the upper factor.  While earlier blocks are being finished it applies
-// their published solution values to its own rows -- the products l_ik x_k
-// in parallel, then the subtractions in the order the specification fixes
+// the upper factor.  Each row's value lives in one lane of wavefront 0.
+//
+// While earlier blocks are being finished the workgroup applies their
+// published solution values to its rows: the products l_ik x_k by all
+// wavefronts, then the subtractions in the order the specification fixes
 // (ascending k forward, descending backward), so every element sees exactly
-// fms(x_i, l_ik, x_k) = x_i (+) (-(l_ik (x) x_k)) in that order -- then solves
-// its diagonal block (backward: each x_k divided by u_kk once its updates
-// are in), stores its R values and publishes the count of finished
-// positions (agent release, then the counter).  Waits are bounded like the
-// panel's.
-constexpr int TRSV_R = 32;    // rows per workgroup
+// fms(x_i, l_ik, x_k) = x_i (+) (-(l_ik (x) x_k)) in that order.  Its
+// diagonal block, staged in LDS when the workgroup starts, is then solved by
+// wavefront 0 alone, with no barrier: row q's final value (backward: its
+// value divided by u_qq) is read from lane q into scalar registers and
+// applied to the later rows of the block.  Wavefront 1 publishes the final
+// values in groups of TRSV_PUB rows (stores, agent release, then the count
+// of finished positions), so the critical chain of the solve never waits
+// for a store.  Waits are bounded like the panel's.
+constexpr int TRSV_R = 32;    // rows per workgroup (lanes of wavefront 0)
 constexpr int TRSV_B = 32;    // solution values applied per batch
 constexpr int TRSV_PUB = 4;   // rows of the diagonal block published at a time
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  uint64_t u;
+  __builtin_memcpy(&u, &v, 8);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+  const uint64_t w = ((uint64_t)hi << 32) | lo;
+  double d;
+  __builtin_memcpy(&d, &w, 8);
+  return d;
+}
 
 template <int NC, bool FWD>
 __global__ __launch_bounds__(256) void k_trsv(const double *LU, int64_t lda, double *x,
                                               int64_t n, uint32_t *ready, uint32_t *ticket,
                                               int *err) {
-  __shared__ double xs[TRSV_R][NC];
-  __shared__ double ys[TRSV_B][NC];
-  __shared__ double pr[TRSV_R][TRSV_B][NC];
-  __shared__ int s_avail, s_fail, s_blk;
+  __shared__ double dg[TRSV_R][TRSV_R][NC];  // dg[q][r]: factor entry of row r, column q
+  __shared__ double pr[TRSV_B][TRSV_R][NC];  // negated products of one batch
+  __shared__ double ys[TRSV_B][NC];          // published values of one batch
+  __shared__ double xs[TRSV_R][NC];          // final values of the block
+  __shared__ int s_avail, s_fail, s_blk, s_done;
   const int tid = threadIdx.x;
   if (tid == 0) s_blk = (int)atomicAdd(ticket, 1u);
   __syncthreads();
@@ -832,15 +849,27 @@ __global__ __launch_bounds__(256) void k_trsv(const double *LU, int64_t lda, dou
   const int cnt = (int)(n - p0 < TRSV_R ? n - p0 : TRSV_R);
   auto row = [&](int64_t p) { return FWD ? p : n - 1 - p; };
   auto L = [&](int64_t i, int64_t k) { return LU + (i + k * lda) * NC; };
-  if (tid < cnt * NC) (&xs[0][0])[tid] = x[row(p0 + tid / NC) * NC + tid % NC];
-  if (tid == 0) s_fail = 0;
+  // the diagonal block (strict triangle, plus the diagonal backward); the
+  // row index runs fastest, so each column is one contiguous read
+  for (int e = tid; e < TRSV_R * TRSV_R * NC; e += 256) {
+    const int q = e / (TRSV_R * NC), r = (e / NC) % TRSV_R, c = e % NC;
+    if (q < cnt && r < cnt && (r > q || (!FWD && r == q)))
+      dg[q][r][c] = L(row(p0 + r), row(p0 + q))[c];
+  }
+  double v[NC];  // the row value of lane tid (wavefront 0, tid < cnt)
+#pragma unroll
+  for (int c = 0; c < NC; ++c) v[c] = tid < cnt ? x[row(p0 + tid) * NC + c] : 0.0;
+  if (tid == 0) {
+    s_fail = 0;
+    s_done = 0;
+  }
   __syncthreads();
   int64_t applied = 0;
   while (applied < p0) {
     if (tid == 0) {
       const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-      uint32_t spins = 0, v;
-      while ((int64_t)(v = ld_dev_u32(ready)) <= applied) {
+      uint32_t spins = 0, w;
+      while ((int64_t)(w = ld_dev_u32(ready)) <= applied) {
         if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { s_fail = 1; break; }
         if ((++spins & 63u) == 0 && __builtin_amdgcn_s_memrealtime() - t0 > 100000000ull) {
           __hip_atomic_store(err, 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -848,7 +877,7 @@ __global__ __launch_bounds__(256) void k_trsv(const double *LU, int64_t lda, dou
           break;
         }
       }
-      s_avail = (int)((int64_t)v < p0 ? (int64_t)v : p0);
+      s_avail = (int)((int64_t)w < p0 ? (int64_t)w : p0);
     }
     __syncthreads();
     if (s_fail) return;
@@ -863,71 +892,100 @@ __global__ __launch_bounds__(256) void k_trsv(const double *LU, int64_t lda, dou
         double a[NC], y[NC], o[NC];
         ozx::load<NC>(L(row(p0 + q), row(c0 + t)), a);
 #pragma unroll
-        for (int e = 0; e < NC; ++e) y[e] = ys[t][e];
+        for (int c = 0; c < NC; ++c) y[c] = ys[t][c];
         ozx::mul<NC>(a, y, o);
 #pragma unroll
-        for (int e = 0; e < NC; ++e) pr[q][t][e] = -o[e];
+        for (int c = 0; c < NC; ++c) pr[t][q][c] = -o[c];
       }
       __syncthreads();
+      // the subtractions, in order; the next batch's barrier waits for them
       if (tid < cnt) {
-        double v[NC], pv[NC], o[NC];
-#pragma unroll
-        for (int e = 0; e < NC; ++e) v[e] = xs[tid][e];
         for (int t = 0; t < nb; ++t) {
+          double pv[NC], o[NC];
 #pragma unroll
-          for (int e = 0; e < NC; ++e) pv[e] = pr[tid][t][e];
+          for (int c = 0; c < NC; ++c) pv[c] = pr[t][tid][c];
           ozx::add<NC>(v, pv, o);
 #pragma unroll
-          for (int e = 0; e < NC; ++e) v[e] = o[e];
+          for (int c = 0; c < NC; ++c) v[c] = o[c];
         }
-#pragma unroll
-        for (int e = 0; e < NC; ++e) xs[tid][e] = v[e];
       }
-      __syncthreads();
     }
     applied = avail;
   }
-  // the diagonal block; every TRSV_PUB rows the final values are published
-  // (stored, then the count raised after a release fence), so the next
-  // workgroup can apply them while this one continues
-  for (int q = 0; q < cnt; ++q) {
-    if (!FWD) {
-      if (tid == 0) {
-        double v[NC], u[NC], o[NC];
+  __syncthreads();
+  if (tid < 64) {
+    // wavefront 0: the diagonal block; the factor entries of the next step
+    // are read from LDS while this one computes
+    const int lane = tid;
+    double a[NC], u[NC];
 #pragma unroll
-        for (int e = 0; e < NC; ++e) v[e] = xs[q][e];
-        ozx::load<NC>(L(row(p0 + q), row(p0 + q)), u);
+    for (int c = 0; c < NC; ++c) {
+      a[c] = lane > 0 && lane < cnt ? dg[0][lane][c] : 0.0;
+      u[c] = FWD ? 0.0 : dg[0][0][c];
+    }
+    for (int q = 0; q < cnt; ++q) {
+      double an[NC], un[NC];
+      const int qn = q + 1 < cnt ? q + 1 : q;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        an[c] = lane > qn && lane < cnt ? dg[qn][lane][c] : 0.0;
+        un[c] = FWD ? 0.0 : dg[qn][qn][c];
+      }
+      if (!FWD && lane == q) {
+        double o[NC];
         ozx::div<NC>(v, u, o);
 #pragma unroll
-        for (int e = 0; e < NC; ++e) xs[q][e] = o[e];
+        for (int c = 0; c < NC; ++c) v[c] = o[c];
       }
-      __syncthreads();
-    }
-    // row q is final
-    if (tid < NC) x[row(p0 + q) * NC + tid] = xs[q][tid];
-    const int r = q + 1 + tid;
-    if (r < cnt) {
-      double v[NC], a[NC], y[NC], o[NC];
+      // row q is final
+      double y[NC];
 #pragma unroll
-      for (int e = 0; e < NC; ++e) {
-        v[e] = xs[r][e];
-        y[e] = xs[q][e];
-      }
-      ozx::load<NC>(L(row(p0 + r), row(p0 + q)), a);
-      ozx::fms<NC>(v, a, y, o);
+      for (int c = 0; c < NC; ++c) y[c] = readlane_f64(v[c], q);
+      if (lane == q) {
 #pragma unroll
-      for (int e = 0; e < NC; ++e) xs[r][e] = o[e];
-    }
-    if ((q + 1) % TRSV_PUB == 0 || q + 1 == cnt) {
-      __builtin_amdgcn_s_waitcnt(0x0F70);  // this thread's stores have completed
-      __syncthreads();
-      if (tid == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_store(ready, (uint32_t)(p0 + q + 1), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+        for (int c = 0; c < NC; ++c) xs[q][c] = v[c];
       }
-    } else {
-      __syncthreads();
+      if (lane > q && lane < cnt) {
+        double o[NC];
+        ozx::fms<NC>(v, a, y, o);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c] = o[c];
+      }
+      if ((q + 1) % TRSV_PUB == 0 || q + 1 == cnt) {
+        // the group's values are in LDS before the count is raised
+        if (lane == 0)
+          __hip_atomic_store(&s_done, q + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        a[c] = an[c];
+        u[c] = un[c];
+      }
+    }
+  } else if (tid < 128) {
+    // wavefront 1: publication of the finished rows
+    const int lane = tid - 64;
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    int done = 0;
+    while (done < cnt) {
+      const int d = __hip_atomic_load(&s_done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (d <= done) {
+        if (__builtin_amdgcn_s_memrealtime() - t0 > 100000000ull) {
+          if (lane == 0) __hip_atomic_store(err, 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          return;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      for (int e = lane; e < (d - done) * NC; e += 64) {
+        const int q = done + e / NC, c = e % NC;
+        x[row(p0 + q) * NC + c] = xs[q][c];
+      }
+      // this wavefront's stores complete before the count is raised
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if (lane == 0)
+        __hip_atomic_store(ready, (uint32_t)(p0 + d), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      done = d;
     }
   }
 }
