@@ -106,6 +106,31 @@ OZX_HD void renorm(double (&x)[K], double (&y)[NC]) {
     x[i + 1] = t;
   }
   x[0] = s;
+  // Top-down compression.  When the first S error terms are all non-zero
+  // every step emits its sum, the error carries on, and the components are
+  // those sums (plus the last error when fewer than NC steps exist); steps
+  // past the NC-th emit nothing.  Only lanes that met a zero error take the
+  // general form below, which gives the same result on the others.  This
+  // shortcut is taken for the renormalisations of products and quotients
+  // (K <= NC + 1), whose terms rarely meet a zero error; the merged sums of
+  // an addition often do (an exact step of the sweep above leaves a zero),
+  // so they go to the general form directly.
+  constexpr int S = K - 1 < NC ? K - 1 : NC;
+  bool zero = K > NC + 1;
+  if (!zero) {
+    double eps = x[0];
+#pragma unroll
+    for (int i = 1; i <= S; ++i) {
+      double r, e;
+      two_sum(eps, x[i], r, e);
+      y[i - 1] = r;
+      zero = zero || (e == 0.0);
+      eps = e;
+    }
+#pragma unroll
+    for (int q = S; q < NC; ++q) y[q] = q == S ? eps : 0.0;
+  }
+  if (!zero) return;
 #pragma unroll
   for (int i = 0; i < NC; ++i) y[i] = 0.0;
   int j = 0;
