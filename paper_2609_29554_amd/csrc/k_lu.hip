@@ -154,6 +154,47 @@ __device__ __forceinline__ void cand_allreduce(double (&k)[NC], int &pos, int &i
 #undef OZ_DPP_STEP
 }
 
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  uint64_t u;
+  __builtin_memcpy(&u, &v, 8);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+  const uint64_t w = ((uint64_t)hi << 32) | lo;
+  double d;
+  __builtin_memcpy(&d, &w, 8);
+  return d;
+}
+
+__device__ __forceinline__ double wave_max_f64(double v) {
+  v = fmax(v, __shfl_xor(v, 32, 64));
+  v = fmax(v, __shfl_xor(v, 16, 64));
+  v = fmax(v, dpp_f64<0x140>(v));
+  v = fmax(v, dpp_f64<0x141>(v));
+  v = fmax(v, dpp_f64<0x4E>(v));
+  v = fmax(v, dpp_f64<0xB1>(v));
+  return v;
+}
+
+// Leading-magnitude shortcut of the candidate order.  Each lane of a
+// wavefront has reduced its own candidates to lead = the largest |k[0]|
+// among them (-1 for none, NaN if one is NaN) and nlead = how many reach
+// it.  The order compares |k[0]| first, so when the largest leading
+// magnitude belongs to exactly one candidate, that one wins whatever its
+// other components and position: returns 1 and its lane in w.  Returns 0
+// when no lane has a candidate, 2 when the full order has to decide (equal
+// leading magnitudes, NaN).  All 64 lanes must call it; the result is
+// uniform.
+__device__ __forceinline__ int lead_winner(double lead, int nlead, int &w) {
+  const double M = wave_max_f64(lead);
+  const uint64_t hit = __ballot(lead == M);
+  const uint64_t odd = __ballot(lead != lead || (lead == M && nlead > 1));
+  if (odd != 0) return 2;
+  if (M < 0.0) return 0;
+  if (__popcll(hit) != 1) return 2;
+  w = __ffsll((unsigned long long)hit) - 1;
+  return 1;
+}
+
 constexpr int PANEL_NT = 512;  // threads per panel workgroup
 
 // ---------------------------------------------------------------------------
@@ -305,18 +346,38 @@ __global__ __launch_bounds__(PANEL_NT) void k_panel(double *A, int64_t lda, int6
       int bp = 0x7fffffff, bi = -1;
 #pragma unroll
       for (int q = 0; q < NC; ++q) bk[q] = 0.0;
+      // leading magnitudes of this lane's entries first; the full order
+      // only when they do not single out the winner
+      double lead = -1.0;
+      int nlead = 0, lb = 0;
       for (int gi = tid; gi < G; gi += 64) {
-        double kk[NC];
-#pragma unroll
-        for (int q = 0; q < NC; ++q) kk[q] = tkey[gi][q];
-        if (cand_better<NC>(kk, tpos[gi], tidx[gi], bk, bp, bi)) {
-#pragma unroll
-          for (int q = 0; q < NC; ++q) bk[q] = kk[q];
-          bp = tpos[gi];
-          bi = tidx[gi];
-        }
+        if (tidx[gi] < 0) continue;
+        const double m = fabs(tkey[gi][0]);
+        if (m != m) lead = m;
+        else if (m > lead) { lead = m; nlead = 1; lb = gi; }
+        else if (m == lead) ++nlead;
       }
-      cand_allreduce<NC>(bk, bp, bi);
+      int w = 0;
+      const int how = lead_winner(lead, nlead, w);
+      if (how == 1) {
+        bi = __builtin_amdgcn_readlane(lb, w);
+        bp = tpos[bi];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) bk[q] = tkey[bi][q];
+      } else if (how == 2) {
+        for (int gi = tid; gi < G; gi += 64) {
+          double kk[NC];
+#pragma unroll
+          for (int q = 0; q < NC; ++q) kk[q] = tkey[gi][q];
+          if (cand_better<NC>(kk, tpos[gi], tidx[gi], bk, bp, bi)) {
+#pragma unroll
+            for (int q = 0; q < NC; ++q) bk[q] = kk[q];
+            bp = tpos[gi];
+            bi = tidx[gi];
+          }
+        }
+        cand_allreduce<NC>(bk, bp, bi);
+      }
       if (tid == 0) {
         // the winner, and (for a consistent table) the bookkeeping of the
         // interchange, before the single barrier below
@@ -389,7 +450,10 @@ __global__ __launch_bounds__(PANEL_NT) void k_panel(double *A, int64_t lda, int6
         }
       }
       if (!last) {
-        cand_allreduce<NC>(ck, cpos, cidx);
+        int w = 0;
+        const int how = lead_winner(cidx >= 0 ? fabs(ck[0]) : -1.0, 1, w);
+        if (how == 1) cidx = __builtin_amdgcn_readlane(cidx, w);
+        else if (how == 2) cand_allreduce<NC>(ck, cpos, cidx);
         if (tid == 0) s_best = cidx;
       }
     } else {
@@ -822,16 +886,6 @@ constexpr int TRSV_R = 32;    // rows per workgroup (lanes of wavefront 0)
 constexpr int TRSV_B = 32;    // solution values applied per batch
 constexpr int TRSV_PUB = 4;   // rows of the diagonal block published at a time
 
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-  uint64_t u;
-  __builtin_memcpy(&u, &v, 8);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
-  const uint64_t w = ((uint64_t)hi << 32) | lo;
-  double d;
-  __builtin_memcpy(&d, &w, 8);
-  return d;
-}
 
 template <int NC, bool FWD>
 __global__ __launch_bounds__(256) void k_trsv(const double *LU, int64_t lda, double *x,
