@@ -222,6 +222,10 @@ __global__ __launch_bounds__(PANEL_NT) void k_panel(double *A, int64_t lda, int6
                                                     uint32_t *lines, int *err, double *crow,
                                                     int *perm_out, int *moved, int *nmoved) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  // the panel is the critical path of the factorisation, and with
+  // look-ahead the previous step's Schur update runs beside it on the same
+  // CUs: its wavefronts take the SIMDs' issue slots first
+  __builtin_amdgcn_s_setprio(3);
   const int nr = (int)(n - k);
   const int G = gridDim.x, wg = blockIdx.x, tid = threadIdx.x;
   double *rows = (double *)smem_raw;                 // R * kb * NC
