@@ -638,47 +638,78 @@ __global__ __launch_bounds__(256) void k_trsm_lower_unit(const double *Lp, int64
   }
 }
 
-// U12 solve for kb <= ROWS: thread t owns row t % ROWS of column t / ROWS
-// of the workgroup's 256 / ROWS columns, so every lane holds an element
-// (one thread per row of two columns would leave half of them idle at
-// kb = 128).  Each element receives its multiply-subtracts in the order of
+// U12 solve for kb <= 64 WPC: each column is held by WPC wavefronts, row
+// 64 p + l in lane l of the column's wavefront p (4 / WPC columns per
+// 256-thread workgroup).  Wavefront p first applies the values of rows
+// 0 .. 64 p - 1 as the wavefronts before it publish them (LDS, one counter
+// per column), then solves its own 64 rows with no barrier: row h's final
+// value is read from lane h - 64 p into scalar registers, published for
+// the wavefronts after it, and applied to the later rows.  Every element
+// receives its multiply-subtracts in ascending k, the order of
 // k_trsm_lower_unit.
-template <int NC, int ROWS>
-__global__ __launch_bounds__(256) void k_trsm_lower_unit_rc(const double *Lp, int64_t lda,
-                                                            double *Xp, int64_t ldx, int kb,
-                                                            int64_t ncols) {
-  constexpr int CPB = 256 / ROWS;
-  __shared__ double xs[2][CPB][NC];
-  const int tid = threadIdx.x, i = tid % ROWS, cc = tid / ROWS;
+template <int NC, int WPC>
+__global__ __launch_bounds__(256) void k_trsm_lower_unit_w(const double *Lp, int64_t lda,
+                                                           double *Xp, int64_t ldx, int kb,
+                                                           int64_t ncols) {
+  constexpr int CPB = 4 / WPC;
+  __shared__ double xs[CPB][WPC > 1 ? 64 * (WPC - 1) : 1][NC];
+  __shared__ int done[CPB];
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int cc = wv / WPC, part = wv % WPC;
   const int64_t c = (int64_t)blockIdx.x * CPB + cc;
-  const bool mine = i < kb && c < ncols;
+  if (tid < CPB) done[tid] = 0;
+  __syncthreads();
+  if (c >= ncols) return;  // whole wavefronts of a column past the end
+  const int i = 64 * part + lane;
+  const bool mine = i < kb;
+  auto L = [&](int r, int k) { return Lp + (r + (int64_t)k * lda) * NC; };
   double x[NC], l[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    x[q] = 0.0;
+    l[q] = 0.0;
+  }
   if (mine) ozx::load<NC>(Xp + (i + c * ldx) * NC, x);
-  else
+  const int h0 = 64 * part, h1 = kb < h0 + 64 ? kb : h0 + 64;
+  if (h0 >= kb) return;
+  // factor entry l_(i,h) of the next step is loaded while this one computes
+  if (mine && i > 0) ozx::load<NC>(L(i, 0), l);
+  for (int h = 0; h < h0; ++h) {
+    double ln[NC] = {}, y[NC], o[NC];
+    if (mine && h + 1 < i) ozx::load<NC>(L(i, h + 1), ln);
+    // the value of row h, published by an earlier wavefront of this column
+    // (it never waits itself before publishing, so this ends)
+    while (__hip_atomic_load(&done[cc], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) <= h)
+      __builtin_amdgcn_s_sleep(1);
 #pragma unroll
-    for (int q = 0; q < NC; ++q) x[q] = 0.0;
-  // l_(i,h) of the next step is loaded while this step's multiply-subtract
-  // runs, so no load waits behind the barrier
-  if (mine && i > 0) ozx::load<NC>(Lp + i * NC, l);
-  for (int h = 0; h < kb; ++h) {
-    const int b = h & 1;
-    if (i == h) {
+    for (int q = 0; q < NC; ++q) y[q] = xs[cc][h][q];
+    if (mine) {
+      ozx::fms<NC>(x, l, y, o);
 #pragma unroll
-      for (int q = 0; q < NC; ++q) xs[b][cc][q] = x[q];
+      for (int q = 0; q < NC; ++q) {
+        x[q] = o[q];
+        l[q] = ln[q];
+      }
     }
-    __syncthreads();
+  }
+  for (int h = h0; h < h1; ++h) {
+    double ln[NC] = {}, y[NC], o[NC];
+    if (mine && h + 1 < i) ozx::load<NC>(L(i, h + 1), ln);
+    // row h is final
+#pragma unroll
+    for (int q = 0; q < NC; ++q) y[q] = readlane_f64(x[q], h - h0);
+    if (part + 1 < WPC && lane == h - h0) {
+#pragma unroll
+      for (int q = 0; q < NC; ++q) xs[cc][h][q] = y[q];
+      __hip_atomic_store(&done[cc], h + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
     if (mine && i > h) {
-      double ln[NC], u[NC], o[NC];
-      const bool more = h + 1 < i;
-      if (more) ozx::load<NC>(Lp + (i + (int64_t)(h + 1) * lda) * NC, ln);
+      ozx::fms<NC>(x, l, y, o);
 #pragma unroll
-      for (int q = 0; q < NC; ++q) u[q] = xs[b][cc][q];
-      ozx::fms<NC>(x, l, u, o);
-#pragma unroll
-      for (int q = 0; q < NC; ++q) x[q] = o[q];
-      if (more)
-#pragma unroll
-        for (int q = 0; q < NC; ++q) l[q] = ln[q];
+      for (int q = 0; q < NC; ++q) {
+        x[q] = o[q];
+        l[q] = ln[q];
+      }
     }
   }
   if (mine) ozx::store<NC>(Xp + (i + c * ldx) * NC, x);
@@ -1108,13 +1139,13 @@ template <int NC>
 static void trsm_l(int kb, dim3 g, hipStream_t s, const double *L, int64_t lda, double *X,
                    int64_t ldx, int64_t ncols) {
   if (kb <= 64)
-    hipLaunchKernelGGL((k_trsm_lower_unit_rc<NC, 64>), dim3((unsigned)((ncols + 3) / 4)), dim3(256),
+    hipLaunchKernelGGL((k_trsm_lower_unit_w<NC, 1>), dim3((unsigned)((ncols + 3) / 4)), dim3(256),
                        0, s, L, lda, X, ldx, kb, ncols);
   else if (kb <= 128)
-    hipLaunchKernelGGL((k_trsm_lower_unit_rc<NC, 128>), dim3((unsigned)((ncols + 1) / 2)),
+    hipLaunchKernelGGL((k_trsm_lower_unit_w<NC, 2>), dim3((unsigned)((ncols + 1) / 2)),
                        dim3(256), 0, s, L, lda, X, ldx, kb, ncols);
   else if (kb <= 256)
-    hipLaunchKernelGGL((k_trsm_lower_unit_rc<NC, 256>), dim3((unsigned)ncols), dim3(256), 0, s, L,
+    hipLaunchKernelGGL((k_trsm_lower_unit_w<NC, 4>), dim3((unsigned)ncols), dim3(256), 0, s, L,
                        lda, X, ldx, kb, ncols);
   else
     hipLaunchKernelGGL((k_trsm_lower_unit<NC, 1, 2>), g, dim3(256), 0, s, L, lda, X, ldx, kb, ncols);
