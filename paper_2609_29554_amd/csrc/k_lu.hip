@@ -45,18 +45,25 @@ __device__ __forceinline__ double ld_dev_f64(const double *p) {
   return d;
 }
 
-// Make this workgroup's global writes visible at device scope, then store
-// the epoch in its candidate line.
+__device__ __forceinline__ void st_dev_u32(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev_f64(double *p, double v) {
+  uint64_t u;
+  __builtin_memcpy(&u, &v, 8);
+  __hip_atomic_store((uint64_t *)p, u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publish the epoch in this workgroup's candidate line.  Everything the
+// other workgroups read of it (the line's payload, the candidate row) is
+// written with device-coherent stores, so it only has to have completed
+// before the epoch is stored: every wave waits for its own stores
+// (s_waitcnt vmcnt(0)), then the workgroup barrier, then the epoch -- no
+// write-back of the XCD's L2, which a release fence would do every column.
 __device__ __forceinline__ void cand_arrive(uint32_t *line, uint32_t epoch) {
-  // every wave waits for its own global stores (s_waitcnt vmcnt(0)): the
-  // workgroup barrier alone does not, and the release below only covers the
-  // L2, so the data must have reached it before the epoch is written
   __builtin_amdgcn_s_waitcnt(0x0F70);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_store(line, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  if (threadIdx.x == 0) st_dev_u32(line, epoch);
 }
 
 // Wait until the lines of all G workgroups (buffer b) carry an epoch of at
@@ -293,22 +300,22 @@ __global__ __launch_bounds__(PANEL_NT) void k_panel(double *A, int64_t lda, int6
     if (tid == 0) {
       double *kv = (double *)(ln + CAND_KEY);
       if (best >= 0) {
-        ln[1] = (uint32_t)sinv[r0 + best];
-        ln[2] = (uint32_t)(r0 + best);
+        st_dev_u32(ln + 1, (uint32_t)sinv[r0 + best]);
+        st_dev_u32(ln + 2, (uint32_t)(r0 + best));
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
-          kv[q] = RW(best, c)[q];
-          kv[NC + q] = c + 1 < kb ? RW(best, c + 1)[q] : 0.0;
+          st_dev_f64(kv + q, RW(best, c)[q]);
+          st_dev_f64(kv + NC + q, c + 1 < kb ? RW(best, c + 1)[q] : 0.0);
         }
       } else {
-        ln[1] = 0x7fffffffu;
-        ln[2] = 0xffffffffu;
+        st_dev_u32(ln + 1, 0x7fffffffu);
+        st_dev_u32(ln + 2, 0xffffffffu);
       }
     }
     if (best >= 0) {
       double *cr = CROW(b, wg);
       for (int idx = tid; idx < (kb - c - 2) * NC; idx += PANEL_NT)
-        cr[(size_t)(c + 2) * NC + idx] = RW(best, c + 2)[idx];
+        st_dev_f64(cr + (size_t)(c + 2) * NC + idx, RW(best, c + 2)[idx]);
     }
   };
 
