@@ -23,9 +23,10 @@ namespace {
 // pivot column): word 0 holds an arrival epoch, the rest the workgroup's
 // pivot candidate for that column -- its row position and physical row, its
 // value in the pivot column and in the next column -- and a buffer crow holds
-// the rest of that row.  A workgroup writes the payload, makes it visible at
-// device scope (agent release: the dirty L2 lines are written back) and then
-// stores the epoch.  Readers poll the epochs and read every payload and crow
+// the rest of that row.  A workgroup writes the payload with device-coherent
+// stores, waits for them to complete and then stores the epoch (no release
+// fence, which would write back the whole L2 every column; see
+// cand_arrive).  Readers poll the epochs and read every payload and crow
 // with device-coherent loads, which go past the non-coherent caches, so no
 // cache invalidation is needed on the reading side; they are issued only
 // after the epochs were seen (the wait ends in a workgroup barrier).  Waits
