@@ -379,6 +379,38 @@ __device__ __forceinline__ void oz_update(double *A, int64_t n, int64_t k0, int6
   __syncthreads();
 }
 
+// a <- a - l u for the elements idx = 0 .. total-1 of one step (where(idx)
+// gives the three operands; a is updated in place), two elements per
+// thread in flight: both elements' loads are issued before the first
+// multiply-subtract, so one memory round trip serves two of them (the
+// Ozaki-II workgroup has half the wavefronts of the native one).  Each
+// element is updated once, so the order of its updates is the caller's.
+template <int NC, int NT, typename W>
+__device__ __forceinline__ void fms_sweep(int64_t total, W where) {
+  for (int64_t idx = threadIdx.x; idx < total; idx += 2 * NT) {
+    const bool two = idx + NT < total;
+    double *pa0, *pa1 = nullptr;
+    const double *pl0, *pu0, *pl1 = nullptr, *pu1 = nullptr;
+    where(idx, pa0, pl0, pu0);
+    if (two) where(idx + NT, pa1, pl1, pu1);
+    double a0[NC], l0[NC], u0[NC], a1[NC] = {}, l1[NC] = {}, u1[NC] = {}, o[NC];
+    ozx::load<NC>(pa0, a0);
+    ozx::load<NC>(pl0, l0);
+    ozx::load<NC>(pu0, u0);
+    if (two) {
+      ozx::load<NC>(pa1, a1);
+      ozx::load<NC>(pl1, l1);
+      ozx::load<NC>(pu1, u1);
+    }
+    ozx::fms<NC>(a0, l0, u0, o);
+    ozx::store<NC>(pa0, o);
+    if (two) {
+      ozx::fms<NC>(a1, l1, u1, o);
+      ozx::store<NC>(pa1, o);
+    }
+  }
+}
+
 template <int NC, int NWM, int NT>
 __device__ __forceinline__ void lu_solve_oz(const ozII_batch_item &it, double (*rkey)[4], int64_t *ridx,
                             int *s_info, const DevPlan *pl, uint8_t *ws, int b,
@@ -397,15 +429,13 @@ __device__ __forceinline__ void lu_solve_oz(const ozII_batch_item &it, double (*
       // unblocked panel)
       const bool zero = pivot_column<NC, NT>(it, j, rkey, ridx, s_info);
       const int64_t mr = zero ? 0 : n - j - 1, mc = k1 - j - 1;
-      for (int64_t idx = tid; idx < mr * mc; idx += NT) {
+      fms_sweep<NC, NT>(mr * mc, [&](int64_t idx, double *&pa, const double *&pl,
+                                     const double *&pu) {
         const int64_t i = j + 1 + idx % mr, c = j + 1 + idx / mr;
-        double a[NC], l[NC], u[NC], o[NC];
-        ozx::load<NC>(E(i, c), a);
-        ozx::load<NC>(E(i, j), l);
-        ozx::load<NC>(E(j, c), u);
-        ozx::fms<NC>(a, l, u, o);
-        ozx::store<NC>(E(i, c), o);
-      }
+        pa = E(i, c);
+        pl = E(i, j);
+        pu = E(j, c);
+      });
       __syncthreads();
     }
     if (k1 < n) {
@@ -413,15 +443,13 @@ __device__ __forceinline__ void lu_solve_oz(const ozII_batch_item &it, double (*
       const int64_t ncol = n - k1;
       for (int64_t k = k0; k + 1 < k1; ++k) {
         const int64_t mr = k1 - k - 1;
-        for (int64_t idx = tid; idx < mr * ncol; idx += NT) {
+        fms_sweep<NC, NT>(mr * ncol, [&](int64_t idx, double *&pa, const double *&pl,
+                                         const double *&pu) {
           const int64_t i = k + 1 + idx % mr, c = k1 + idx / mr;
-          double a[NC], l[NC], u[NC], o[NC];
-          ozx::load<NC>(E(i, c), a);
-          ozx::load<NC>(E(i, k), l);
-          ozx::load<NC>(E(k, c), u);
-          ozx::fms<NC>(a, l, u, o);
-          ozx::store<NC>(E(i, c), o);
-        }
+          pa = E(i, c);
+          pl = E(i, k);
+          pu = E(k, c);
+        });
         __syncthreads();
       }
       oz_update<NC, NWM, NT>(A, n, k0, k1, pl, ws, stage);
