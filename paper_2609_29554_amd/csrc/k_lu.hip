@@ -929,7 +929,6 @@ constexpr int TRSV_R = 32;    // rows per workgroup (lanes of wavefront 0)
 constexpr int TRSV_B = 32;    // solution values applied per batch
 constexpr int TRSV_PUB = 4;   // rows of the diagonal block published at a time
 
-
 template <int NC, bool FWD>
 __global__ __launch_bounds__(256) void k_trsv(const double *LU, int64_t lda, double *x,
                                               int64_t n, uint32_t *ready, uint32_t *ticket,
