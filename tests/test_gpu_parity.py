@@ -313,6 +313,27 @@ def test_getrs_several_rhs():
     assert np.array_equal(to_host(dX1), X[1:2])
 
 
+@pytest.mark.parametrize("nc,n", [(4, 200), (3, 356), (2, 65), (4, 129)],
+                         ids=lambda v: str(v))
+def test_getrs_blocked_ragged(nc, n):
+    """The blocked solve's unit-lower blocks of up to 256 rows run on one,
+    two or four chained wavefronts per column; orders whose last block
+    leaves a wavefront partly filled (200: 8 rows in the fourth, 356: a
+    100-row block, 65: one row in the second, 129: one row in the third,
+    none in the fourth) against the oracle."""
+    note(f"getrs nrhs=2 nc={nc} n={n}")
+    A = _matrix(nc, n, "graded", 23)
+    LU, ipiv, info, _ = O.getrf(A, 32, O.METHOD_NAIVE)
+    rng = np.random.default_rng(n)
+    R = W.random_expansions(n, 2, nc, rng, exp_sigma=2)          # (2, n, nc)
+    X = O.getrs(LU, ipiv, R)
+    dLU, dX = to_dev(LU), to_dev(R)
+    import torch
+    ctx().getrs(dLU, torch.from_numpy(ipiv).cuda(), dX)
+    ctx().sync_check()
+    assert np.array_equal(to_host(dX), X)
+
+
 def test_unblocked_equals_blocked_naive_on_gpu():
     nc, n = 4, 80
     note("unblocked vs blocked naive")
