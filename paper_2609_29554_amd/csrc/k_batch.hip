@@ -357,16 +357,43 @@ __device__ __forceinline__ void oz_update(double *A, int64_t n, int64_t k0, int6
   }
   __syncthreads();
 
-  // (S5)+(S6) and A22 -= c
+  // (S5)+(S6) and A22 -= c: each wavefront takes 64 consecutive elements of
+  // a column at a time through the matrix-core CRT, on its own slice of the
+  // staging LDS (the route and results of k_consumer_mx)
   {
-    uint32_t *st = stage + tid * CST;
-    for (int64_t e = tid; e < m2 * m2; e += NT) {
-      const int64_t i = e % m2, j = e / m2;
-      const int32_t ei = ea[i], ej = eb[j];
+    constexpr int NB = 36, NWC = 12, ND = NB / 2, STG = stage_words<ND>();
+    static_assert(64 * MX_TBS <= 32 * MX_CBS * 4 && 64 * STG <= 32 * MX_CBS, "LDS reuse");
+    static_assert(NT / 64 * 32 * MX_CBS <= NT * CST, "one column-sum buffer per wavefront");
+    int32_t *buf = (int32_t *)stage + wv * 32 * MX_CBS;
+    uint32_t *st = (uint32_t *)buf + lane * STG;
+    mxv4 tab[MX_BLK];
+#pragma unroll
+    for (int b = 0; b < MX_BLK; ++b) tab[b] = *(const mxv4 *)&pl->crtm[b][lane][0];
+    const int64_t TMB = Mp / 64, ps = Mp * Mp;
+    for (int64_t ch = wv; ch < m2 * TMB; ch += NT / 64) {
+      const int64_t j = ch / TMB, i0 = (ch % TMB) * 64, i = i0 + lane;
+      const bool valid = i < m2;
+      const int32_t ej = eb[j], ei = valid ? ea[i] : EXP_ZERO;
       const bool zero = ei == EXP_ZERO || ej == EXP_ZERO;
       const int eps = zero ? 0 : w * g0 - (Q - 1 - ei) - (Q - 1 - ej);
+      uint32_t cb[NWC];
+#pragma unroll
+      for (int k = 0; k < NWC; ++k) cb[k] = 0u;
+      for (int gi = 0; gi < ng; ++gi) {
+        int32_t d[ND];
+        crt_group_mx<NB, true>(tpl + (int64_t)gi * nmod * ps + j * Mp + i0, ps, nmod, pl, tab, buf,
+                               lane, d);
+        add_shifted_digits<NWC, ND, STG>(cb, d, w * gi, st);
+        mx_sync<true>();  // the buffer takes the next group's t-bytes
+      }
+      if (!valid) continue;
       double c[NC];
-      consume_element_b<NC, 12, 36, BZ_PRE>(tpl + j * Mp + i, Mp * Mp, pl, st, zero, eps, c);
+      if (zero) {
+#pragma unroll
+        for (int q = 0; q < NC; ++q) c[q] = 0.0;
+      } else {
+        round_out_n<NWC, NC>(cb, eps, c);
+      }
       double *dst = A22 + (i + j * n) * NC;
       double a[NC], nc_[NC], r[NC];
       ozx::load<NC>(dst, a);

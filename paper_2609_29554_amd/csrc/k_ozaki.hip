@@ -888,91 +888,6 @@ __global__ __launch_bounds__(256) void k_consumer(const TT *__restrict__ tpl, in
   }
 }
 
-// ---------------------------------------------------------------------------
-// (S5)+(S6) consumer of the byte back-ends with the CRT's column sums on the
-// matrix cores.  One wavefront (a workgroup of its own) takes 64 consecutive
-// elements of a column.  Per digit group the t-bytes of its elements go to
-// LDS one element row at a time (t - 128 as signed bytes); four 16-element
-// blocks of them are the B operands of v_mfma_i32_16x16x64_i8 against the
-// plan's column table (DevPlan::crtm, three A operands held in registers:
-// f_l and the 46 bytes that M_l < 2^363 can have), which gives
-// sum_l (t_l - 128) b_jl for every table column j.  Through LDS, 32 elements
-// at a time, each lane collects its own element's columns, adds crtc, and
-// forms the 16-bit digits of Sbar as crt_group_bytes does (the same exact
-// integer, so the same digits).  The group shift, rounding and update are
-// those of consume_element_b.  6.5 KiB of LDS per wavefront.
-// ---------------------------------------------------------------------------
-constexpr int MX_TBS = 80;   // bytes per element row of the t-bytes (conflict-free reads)
-constexpr int MX_BLK = 3;    // 16-column blocks of the table: f_l, then bytes 0..45 of M_l
-constexpr int MX_CBS = 16 * MX_BLK + 4;  // ints per element row of the column sums
-static_assert(2 + 46 == 16 * MX_BLK, "table columns");
-
-// The 16-bit digits of group gi's Sbar for the wavefront's 64 elements
-// (lane L: element i0 + L) by the matrix-core route; tg: t-value of modulus 0
-// of element i0 in group gi, moduli ps bytes apart.  Called by all 64 lanes
-// of a one-wavefront workgroup; buf (32 MX_CBS ints of LDS) is free again
-// when it returns.
-template <int NB>
-__device__ __forceinline__ void crt_group_mx(const uint8_t *tg, int64_t ps, int nmod,
-                                             const DevPlan *__restrict__ pl,
-                                             const v4i (&tab)[MX_BLK], int32_t *buf, int lane,
-                                             int32_t (&d)[NB / 2]) {
-  constexpr int ND = NB / 2;
-  uint8_t *tb = (uint8_t *)buf;
-  const int nch = (nmod + 3) >> 2;
-  const int e4 = 4 * (lane & 15), lq = lane >> 4;
-  // lane: moduli 4c + lq, elements e4 .. e4 + 3 (one dword of a plane);
-  // moduli past nmod read the last plane again, their table columns are 0
-  const uint8_t *src = tg + e4 + (int64_t)lq * ps, *last = tg + e4 + (int64_t)(nmod - 1) * ps;
-  for (int c = 0; c < nch; ++c, src += 4 * ps) {
-    const int l = 4 * c + lq;
-    const uint32_t v = *(const uint32_t *)(l < nmod ? src : last) ^ 0x80808080u;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) tb[(e4 + r) * MX_TBS + l] = (uint8_t)(v >> (8 * r));
-  }
-  __syncthreads();
-  v4i bf[4];
-#pragma unroll
-  for (int e = 0; e < 4; ++e)
-    bf[e] = *(const v4i *)(tb + (16 * e + (lane & 15)) * MX_TBS + 16 * lq);
-  __syncthreads();
-  int32_t col[52];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-#pragma unroll
-    for (int e = 2 * h; e < 2 * h + 2; ++e)
-#pragma unroll
-      for (int b = 0; b < MX_BLK; ++b) {
-        const v4i acc =
-            __builtin_amdgcn_mfma_i32_16x16x64_i8(tab[b], bf[e], v4i{0, 0, 0, 0}, 0, 0, 0);
-        *(v4i *)(buf + (16 * (e - 2 * h) + (lane & 15)) * MX_CBS + 16 * b + 4 * lq) = acc;
-      }
-    __syncthreads();
-    if ((lane >> 5) == h) {
-#pragma unroll
-      for (int q = 0; q < 4 * MX_BLK; ++q) {
-        const v4i v = *(const v4i *)(buf + (lane & 31) * MX_CBS + 4 * q);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) col[4 * q + r] = v[r] + pl->crtc[4 * q + r];
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int k = 16 * MX_BLK; k < 52; ++k) col[k] = 0;  // bytes 46, 47 of every M_l are 0
-  // F = (sum_l t_l f_l) / 2^16 from columns 0, 1; then as crt_group_bytes
-  const int32_t qf = (col[0] + col[1] * 256 + 32768) >> 16;
-  int32_t carry = 0;
-#pragma unroll
-  for (int k = 0; k < ND; ++k) {
-    const int32_t lo = col[2 + 2 * k] - qf * (pl->pbyte[2 * k] & 0xff);
-    const int32_t hi = col[3 + 2 * k] - qf * (pl->pbyte[2 * k + 1] & 0xff);
-    const int32_t v = lo + (int32_t)((uint32_t)hi << 8) + carry;
-    d[k] = v & 0xffff;
-    carry = v >> 16;  // arithmetic
-  }
-  d[ND - 1] = (int32_t)(int16_t)(uint16_t)d[ND - 1];
-}
 
 // Block (x, y) of a 2-D grid in an XCD-aware order: workgroups are dispatched
 // to the 8 XCDs in turn, so each XCD is given a contiguous range of logical
